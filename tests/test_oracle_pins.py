@@ -1,0 +1,520 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares the oracle with a
+closed form, a limit, a printed number from the paper, an independent
+library routine or a brute-force computation.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import gamma as Gamma, zeta
+
+from oracle import fermi, kernel, xc, ions
+from oracle.fft import fft3, ifft3, direct_dft3, dft1
+from oracle.functional import (Problem, TERM_TF, TERM_VW, TERM_NL0, TERM_NL1,
+                               TERM_HARTREE, TERM_LOCPP, TERM_XC)
+from paper_2601_23002_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HA_EV = 27.211386245988
+BOHR_CM = 0.529177210903e-8
+AMU_G = 1.66053906660e-24
+M_H_AMU = 1.00794
+MADELUNG_SC = -2.837297479480619   # simple-cubic Madelung constant with background
+
+
+# ----------------------------------------------------------------------------
+# FFT (C10 / P6)
+# ----------------------------------------------------------------------------
+
+def test_fft_matches_direct_dft_8cubed():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((8, 8, 8)) + 1j * rng.standard_normal((8, 8, 8))
+    ref = direct_dft3(x, -1) / x.size
+    assert np.max(np.abs(fft3(x) - ref)) < 1e-13
+    ref_inv = direct_dft3(x, +1)
+    assert np.max(np.abs(ifft3(x) - ref_inv)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [10, 12, 18, 30, 48, 50, 96, 150])
+def test_fft_1d_matches_library(N):
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    y = dft1(x, 1, -1)
+    ref = np.fft.fft(x, axis=1)
+    assert np.max(np.abs(y - ref)) < 1e-13 * N
+    z = dft1(y, 1, +1) / N
+    assert np.max(np.abs(z - x)) < 1e-14 * N
+
+
+def test_fft_rejects_non_smooth():
+    with pytest.raises(ValueError):
+        dft1(np.zeros(14), 0, -1)
+
+
+# ----------------------------------------------------------------------------
+# Fermi-Dirac integrals (C1 / P2)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nu", [-0.5, 0.5, 1.5])
+def test_fd_at_zero_closed_form(nu):
+    # I_nu(0) = Gamma(nu+1) (1 - 2^-nu) zeta(nu+1)
+    ref = Gamma(nu + 1) * (1 - 2.0 ** (-nu)) * zeta(nu + 1)
+    val = fermi.fd_integrals(np.array([0.0]), (nu,))[0][0]
+    assert abs(val / ref - 1) < 2e-15
+
+
+def test_fd_printed_values_at_zero():
+    v = fermi.fd_integrals(np.array([0.0]), (-0.5, 0.5, 1.5))
+    assert abs(v[0][0] - 1.072154929940191) < 3e-15
+    assert abs(v[1][0] - 0.678093895153101) < 3e-15
+    assert abs(v[2][0] - 1.152803837088362) < 3e-15
+
+
+@pytest.mark.parametrize("eta", [-40.0, -12.0, -3.0, -1.0])
+def test_fd_nondegenerate_series(eta):
+    for nu in (-0.5, 0.5, 1.5):
+        ref = Gamma(nu + 1) * sum((-1) ** (k + 1) * math.exp(k * eta) / k ** (nu + 1)
+                                  for k in range(1, 400))
+        val = fermi.fd_integrals(np.array([eta]), (nu,))[0][0]
+        assert abs(val / ref - 1) < 5e-15
+
+
+@pytest.mark.parametrize("eta", [300.0, 1000.0])
+def test_fd_sommerfeld_limit(eta):
+    # I_1/2 = (2/3) eta^1.5 [1 + pi^2/(8 eta^2) + 7 pi^4/(640 eta^4)
+    #                         + 31 pi^6/(3072 eta^6)] + O(eta^-6.5)
+    ref = 2 / 3 * eta ** 1.5 * (1 + math.pi ** 2 / (8 * eta ** 2) + 7 * math.pi ** 4 / (640 * eta ** 4)
+                                + 31 * math.pi ** 6 / (3072 * eta ** 6))
+    val = fermi.fd_integrals(np.array([eta]), (0.5,))[0][0]
+    assert abs(val / ref - 1) < 1e-14
+
+
+def test_fd_derivative_relation():
+    # d I_{1/2}/d eta = (1/2) I_{-1/2}: derivative quadrature vs a brute central difference
+    eta = np.array([-5.0, -0.3, 0.0, 2.0, 9.0])
+    d = fermi.fd_integrals(eta, (0.5,), derivative=True)[0]
+    h = 1e-4
+    fd = (fermi.fd_half(eta + h) - fermi.fd_half(eta - h)) / (2 * h)
+    assert np.max(np.abs(d / fd - 1)) < 1e-8
+    half_m = 0.5 * fermi.fd_integrals(eta, (-0.5,))[0]
+    assert np.max(np.abs(d / half_m - 1)) < 1e-13
+
+
+def test_fd_inversion_roundtrip():
+    u = np.exp(np.linspace(-35, 10, 301))
+    eta = fermi.eta_from_ratio(u)
+    assert np.max(np.abs(fermi.fd_half(eta) / u - 1)) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Paper's printed conditions (P1): rs <-> mass density <-> T_F
+# ----------------------------------------------------------------------------
+
+def test_paper_density_temperature_pairs():
+    data = json.load(open(os.path.join(HERE, "golden", "paper_conditions.json")))
+    for c in data["conditions"]:
+        rs = c["rs"]
+        n0 = 3.0 / (4.0 * math.pi * rs ** 3)
+        rho = n0 * M_H_AMU * AMU_G / BOHR_CM ** 3
+        digits = len(str(c["rho_g_cm3"]).split(".")[1])
+        assert abs(rho - c["rho_g_cm3"]) <= 0.5 * 10 ** -digits + 1e-12
+        # T_F from the oracle's finite-T Thomas-Fermi chemical potential at
+        # very low temperature: mu = T eta(n0 / n_T) -> E_F
+        T = 1e-4
+        mu = T * float(fermi.eta_from_ratio(np.array([n0 / fermi.density_scale(T)]))[0])
+        T_eV = c["theta"] * mu * HA_EV
+        tol = 0.05 + (0.13 if c["T_eV"] == 100.1 else 0.0)
+        assert abs(T_eV - c["T_eV"]) <= tol, (c, T_eV)
+
+
+# ----------------------------------------------------------------------------
+# Uniform electron gas (P3)
+# ----------------------------------------------------------------------------
+
+def _uniform_system(n0, T, n=8, L=6.0, terms=TERM_TF):
+    # one dummy ion carries the electron count; the local PP is switched off
+    ne = n0 * L ** 3
+    return W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([ne]),
+                    rc=np.array([0.5]), T=T, terms=terms)
+
+
+def test_uniform_gas_eta0_zero():
+    # T = 1, eta0 = 0: n0 = n_T I_1/2(0), f_TF = -(2/3) n_T T I_3/2(0)
+    T = 1.0
+    I12 = Gamma(1.5) * (1 - 2 ** -0.5) * zeta(1.5)
+    I32 = Gamma(2.5) * (1 - 2 ** -1.5) * zeta(2.5)
+    nT = math.sqrt(2) / math.pi ** 2 * T ** 1.5
+    n0 = nT * I12
+    assert abs(n0 - 0.09716393323546671) < 1e-16
+    s = _uniform_system(n0, T)
+    p = Problem(s, with_ewald=False)
+    e, g = p.evaluate(np.full(s.n, math.sqrt(n0)))
+    ref = -(2.0 / 3.0) * nT * T * I32
+    assert abs(ref - (-0.11012334807030762)) < 1e-15
+    assert abs(e["f_tf"] / p.V / ref - 1) < 1e-14
+    # potential: mu = T eta0 = 0
+    assert abs(e["mu"]) < 1e-13
+
+
+def test_uniform_gas_limits():
+    n0 = 0.05
+    # T -> 0: C_TF n^{5/3}, C_TF = (3/10)(3 pi^2)^{2/3}
+    C_TF = 0.3 * (3 * math.pi ** 2) ** (2 / 3)
+    assert abs(C_TF - 2.871234000188191) < 1e-14
+    T = 2e-4
+    _, f, _ = fermi.tf_terms(np.array([n0]), T)
+    EF = 0.5 * (3 * math.pi ** 2 * n0) ** (2 / 3)
+    # Sommerfeld: f = C_TF n^{5/3} (1 - (5 pi^2/12)(T/E_F)^2 + ...)
+    ref = C_TF * n0 ** (5 / 3) * (1 - 5 * math.pi ** 2 / 12 * (T / EF) ** 2)
+    assert abs(f[0] / ref - 1) < 1e-9
+    # T -> inf: n T [ln(n lambda^3 / 2) - 1], lambda = sqrt(2 pi / T)
+    T = 1e5
+    _, f, _ = fermi.tf_terms(np.array([n0]), T)
+    lam = math.sqrt(2 * math.pi / T)
+    x = n0 * lam ** 3 / 2
+    # next order of the quantum correction: + n T x / 2^{5/2}
+    ref = n0 * T * (math.log(x) - 1 + x / 2 ** 2.5)
+    assert abs(f[0] / ref - 1) < 1e-10
+
+
+def test_uniform_gas_nonlocal_terms_vanish():
+    n0, T = 0.03, 1.3
+    s = _uniform_system(n0, T, terms=TERM_TF | TERM_VW | TERM_NL0 | TERM_NL1 | TERM_HARTREE)
+    p = Problem(s, with_ewald=False)
+    e, g = p.evaluate(np.full(s.n, math.sqrt(n0)))
+    assert abs(e["e_vw"]) < 1e-25
+    assert abs(e["f_nl0"]) < 1e-30
+    assert abs(e["f_nl1"]) < 1e-30
+    assert abs(e["e_h"]) < 1e-30
+    # gradient is 2 phi mu everywhere (no residual)
+    r = g - 2 * e["mu"] * math.sqrt(n0)
+    assert np.max(np.abs(r)) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# von Weizsaecker (P4)
+# ----------------------------------------------------------------------------
+
+def test_vw_cosine_closed_form():
+    L, n = 7.0, 16
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([3.0]),
+                 rc=np.array([0.5]), T=1.0, terms=TERM_VW)
+    p = Problem(s, with_ewald=False)
+    x = np.arange(n)[:, None, None] * L / n * np.ones((1, n, n))
+    A, B, g = 0.3, 0.1, 3
+    G = 2 * math.pi * g / L
+    phi = A + B * np.cos(G * x)
+    e, _ = p.evaluate(phi, need_grad=False)
+    assert abs(e["e_vw"] / (p.V * B * B * G * G / 4) - 1) < 1e-13
+
+
+def test_vw_gaussian_orbital_single_orbital_limit():
+    # vW is exact for one orbital: a normalised Gaussian orbital
+    # phi = (2 pi s^2)^(-3/4) exp(-r^2/(4 s^2)) is the ground state of the
+    # harmonic oscillator with omega = 1/(2 s^2), whose kinetic energy is
+    # half of (3/2) omega, i.e. 3/(8 s^2)
+    L, n, sig = 16.0, 64, 0.9
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([1.0]),
+                 rc=np.array([0.5]), T=1.0, terms=TERM_VW)
+    p = Problem(s, with_ewald=False)
+    c = np.arange(n) * L / n - L / 2
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    phi = (2 * math.pi * sig ** 2) ** (-0.75) * np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (4 * sig ** 2))
+    e, _ = p.evaluate(phi, need_grad=False)
+    assert abs(e["e_vw"] - 3.0 / (8.0 * sig ** 2)) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Hartree of a Gaussian charge, Ewald (P5, P12)
+# ----------------------------------------------------------------------------
+
+def test_hartree_gaussian_charge():
+    L, n, sig, q = 10.0, 48, 0.7, 1.0
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([q]),
+                 rc=np.array([0.5]), T=1.0, terms=TERM_HARTREE)
+    p = Problem(s, with_ewald=False)
+    c = np.arange(n) * L / n
+    d = np.minimum(c, L - c)
+    X, Y, Z = np.meshgrid(d, d, d, indexing="ij")
+    rho = q * (2 * math.pi * sig ** 2) ** -1.5 * np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (2 * sig ** 2))
+    e, _ = p.evaluate(np.sqrt(rho), need_grad=False)
+    ref = q * q / 2 * (1 / (sig * math.sqrt(math.pi)) + MADELUNG_SC / L + 4 * math.pi * sig ** 2 / L ** 3)
+    assert abs(e["e_h"] - ref) < 1e-12
+
+
+def test_ewald_madelung_and_alpha_independence():
+    L, Z = 5.0, 2.0
+    e1 = ions.ewald(L, np.array([[0.3, 1.1, 2.0]]), np.array([Z]))
+    assert abs(e1 - Z * Z * MADELUNG_SC / (2 * L)) < 1e-13
+    rng = np.random.default_rng(4)
+    pos = rng.uniform(0, 7.0, (9, 3))
+    zv = rng.choice([1.0, 4.0], 9)
+    vals = [ions.ewald(7.0, pos, zv, alpha=a) for a in (0.35, 0.5, 0.8)]
+    assert max(vals) - min(vals) < 1e-11 * abs(vals[0])
+    # doubling the cell with copies of the ions doubles... 8x the energy
+    big = np.concatenate([pos + 7.0 * np.array(t) for t in np.ndindex(2, 2, 2)])
+    e8 = ions.ewald(14.0, big, np.tile(zv, 8))
+    assert abs(e8 / (8 * vals[0]) - 1) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# Local pseudopotential (C6)
+# ----------------------------------------------------------------------------
+
+def test_vloc_real_space_brute_force():
+    # the plane-wave sum of the erf potential equals the real-space lattice
+    # sum of -Z erf(r/rc)/r plus the neutralising background, up to the
+    # plane-wave truncation; compare on a fine grid at a few points
+    from scipy.special import erf
+    L, n = 6.0, 48
+    pos = np.array([[1.0, 2.0, 3.5], [4.2, 0.3, 5.9]])
+    zv = np.array([1.0, 4.0])
+    rc = np.array([0.9, 1.1])
+    VG = ions.vloc_spectrum(L, (n, n, n), pos, zv, rc)
+    Vr = np.real(ifft3(VG))
+    # brute force: Ewald-style split of -Z erf(r/rc)/r = -Z/r + Z erfc(r/rc)/r;
+    # the periodic -Z/r with background is the Ewald potential
+    alpha = 0.9
+    pts = [(3, 5, 7), (20, 33, 41), (0, 0, 0)]
+    for (i, j, k) in pts:
+        r0 = np.array([i, j, k]) * L / n
+        tot = 0.0
+        for R, Z, c in zip(pos, zv, rc):
+            img = np.array(list(np.ndindex(7, 7, 7))) - 3
+            d = np.linalg.norm(r0[None, :] - R[None, :] - img * L, axis=1)
+            # short-range pieces (erfc terms)
+            tot += np.sum(-Z * (erf(d / c) - erf(alpha * d)) / d)
+            # long-range Gaussian-smeared part in reciprocal space
+            m = np.arange(-12, 13)
+            g = np.stack(np.meshgrid(m, m, m, indexing="ij"), -1).reshape(-1, 3)
+            g = g[np.any(g != 0, 1)]
+            G = g * 2 * math.pi / L
+            G2 = np.sum(G * G, 1)
+            tot += np.sum(-4 * math.pi * Z / L ** 3 * np.exp(-G2 / (4 * alpha ** 2)) / G2
+                          * np.cos(G @ (r0 - R)))
+            # G = 0: the real-space image sum already carries the cell
+            # average pi Z (c^2 - 1/alpha^2)/V of the short-range piece; the
+            # plane-wave convention's average is pi Z c^2 / V
+            tot += math.pi * Z / (alpha ** 2 * L ** 3)
+        assert abs(Vr[i, j, k] - tot) < 1e-9, (Vr[i, j, k], tot)
+
+
+# ----------------------------------------------------------------------------
+# Kernel (P9 sum rule / T->0 limit, P14)
+# ----------------------------------------------------------------------------
+
+def _lindhard_T0(q, kf):
+    z = q / (2 * kf)
+    return -(kf / math.pi ** 2) * (0.5 + (1 - z * z) / (4 * z) * np.log(np.abs((1 + z) / (1 - z))))
+
+
+def test_chi0_zero_temperature_limit():
+    n0 = 0.1
+    kf = (3 * math.pi ** 2 * n0) ** (1 / 3)
+    EF = kf * kf / 2
+    q = np.array([0.1, 0.5, 1.0, 1.9, 2.8, 3.0, 4.0, 8.0]) * kf
+    devs = []
+    for t in (0.004, 0.002):
+        eta0, _ = kernel.uniform_gas(n0, t * EF)
+        c = kernel.chi0(q, t * EF, eta0)
+        devs.append(np.abs(c / _lindhard_T0(q, kf) - 1))
+    # finite-T correction is second order in T/E_F (Sommerfeld)
+    ratio = devs[0] / devs[1]
+    assert np.all(np.abs(ratio - 4.0) < 0.05), ratio
+    assert np.all(devs[1] < 4e-5)
+
+
+@pytest.mark.parametrize("T", [0.5, 1.0, 8.0])
+def test_chi0_compressibility_sum_rule(T):
+    n0 = 0.03
+    eta0, dmudn = kernel.uniform_gas(n0, T)
+    c = kernel.chi0(np.array([1e-5]), T, eta0)
+    assert abs(c[0] * dmudn + 1) < 1e-9
+    K = kernel.kernel_K(np.array([0.0, 1e-4, 1e-3]), n0, T)
+    assert K[0] == 0.0 and abs(K[1]) < 1e-6 and abs(K[2]) < 1e-4
+
+
+def test_chi0_quadrature_converged():
+    # halving the tanh-sinh step changes chi0 only at rounding level
+    n0, T = 0.03, 1.0
+    eta0, _ = kernel.uniform_gas(n0, T)
+    q = np.array([0.05, 0.7, 1.3, 2.9, 9.0])
+    c1 = kernel.chi0(q, T, eta0)
+    saved = (kernel._TS_H, kernel._TS_T, kernel._TS_U, kernel._TS_W, kernel._TS_FL, kernel._TS_FR)
+    try:
+        h = saved[0] / 2
+        t = np.arange(-400, 401) * h
+        u = 0.5 * math.pi * np.sinh(t)
+        kernel._TS_H, kernel._TS_T, kernel._TS_U = h, t, u
+        kernel._TS_W = 0.5 * math.pi * np.cosh(t) / np.cosh(u) ** 2
+        kernel._TS_FL = 1 / (1 + np.exp(-2 * u))
+        kernel._TS_FR = 1 / (1 + np.exp(2 * u))
+        c2 = kernel.chi0(q, T, eta0)
+    finally:
+        (kernel._TS_H, kernel._TS_T, kernel._TS_U, kernel._TS_W,
+         kernel._TS_FL, kernel._TS_FR) = saved
+    assert np.max(np.abs(c1 / c2 - 1)) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# XC (P16)
+# ----------------------------------------------------------------------------
+
+def test_exchange_closed_form_and_potential():
+    n = np.array([1e-4, 0.01, 0.3, 5.0])
+    eps_x_ref = -(3 / 4) * (3 / math.pi) ** (1 / 3) * n ** (1 / 3)
+    # exchange alone: subtract the correlation by evaluating at huge rs is not
+    # possible, so check the total potential against d(n eps)/dn instead and
+    # the exchange part through the rs scaling of the constant
+    assert abs(xc.CX - (3 / 4) * (3 / math.pi) ** (1 / 3) * (3 / (4 * math.pi)) ** (1 / 3)) < 1e-15
+    eps, v = xc.pz81(n)
+    h = 1e-6 * n
+    ep, _ = xc.pz81(n + h)
+    em, _ = xc.pz81(n - h)
+    dnde = ((n + h) * ep - (n - h) * em) / (2 * h)
+    assert np.max(np.abs(dnde / v - 1)) < 1e-8
+    assert np.all(eps < eps_x_ref)          # correlation energy is negative
+
+
+def test_pz81_continuity_at_rs_one():
+    n1 = 3 / (4 * math.pi)
+    e_lo, v_lo = xc.pz81(np.array([n1 * (1 + 1e-12)]))
+    e_hi, v_hi = xc.pz81(np.array([n1 * (1 - 1e-12)]))
+    # the published fit is continuous to about 1e-4 Ha at rs = 1
+    assert abs(e_lo[0] - e_hi[0]) < 2e-4
+
+
+# ----------------------------------------------------------------------------
+# Finite differences of every potential term (P7)
+# ----------------------------------------------------------------------------
+
+TERMS = [("TF", TERM_TF), ("VW", TERM_VW), ("NL0", TERM_NL0), ("NL1", TERM_NL1),
+         ("H", TERM_HARTREE), ("LOC", TERM_LOCPP), ("XC", TERM_XC),
+         ("ALL", 0x7F)]
+
+
+@pytest.mark.parametrize("name,mask", TERMS)
+def test_potential_matches_energy_finite_difference(name, mask):
+    base = W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 12, seed=21, beta=1.7, terms=mask)
+    p = Problem(base, with_ewald=False)
+    phi = W.random_phi(base, 5, amp=0.4)
+    e, g = p.evaluate(phi)
+    d = W.random_phi(base, 6, amp=0.5) - W.random_phi(base, 7, amp=0.5)
+    an = p.dot(g, d)
+    eps = 2e-4
+    E = lambda t: p.evaluate(phi + t * d, need_grad=False)[0]["free_energy"]
+    fd = (-E(2 * eps) + 8 * E(eps) - 8 * E(-eps) + E(-2 * eps)) / (12 * eps)
+    scale = max(abs(an), 1e-3 * abs(e["free_energy"]))
+    assert abs(fd - an) <= 1e-9 * scale + 1e-12, (name, fd, an)
+
+
+# ----------------------------------------------------------------------------
+# F0 / F1 closed forms at a = 1 (P10, P11)
+# ----------------------------------------------------------------------------
+
+def _cos_density(L, n, n0, parts):
+    x = np.arange(n)[:, None, None] * L / n * np.ones((1, n, n))
+    G = 2 * math.pi / L
+    dn = sum(eps * np.cos(k * G * x) for k, eps in parts)
+    return n0 + dn
+
+
+def test_f0_single_cosine_a1():
+    L, n, n0, T, g, eps = 6.0, 16, 0.04, 1.2, 2, 0.003
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([n0 * L ** 3]),
+                 rc=np.array([0.5]), T=T, alpha=1.0, terms=TERM_NL0)
+    p = Problem(s, with_ewald=False)
+    e, _ = p.evaluate(np.sqrt(_cos_density(L, n, n0, [(g, eps)])), need_grad=False)
+    assert abs(e["f_nl0"] / (p.V * p.w_shell[g * g] * eps ** 2 / 2) - 1) < 1e-12
+
+
+def test_f0_small_amplitude_any_a():
+    # F0 -> V K(G) eps^2 / 4 as eps -> 0 for any exponent a
+    L, n, n0, T, g = 6.0, 16, 0.04, 1.2, 3
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([n0 * L ** 3]),
+                 rc=np.array([0.5]), T=T, alpha=5 / 6, terms=TERM_NL0)
+    p = Problem(s, with_ewald=False)
+    K = kernel.kernel_K(np.array([2 * math.pi * g / L]), n0, T)[0]
+    r = []
+    for eps in (1e-3, 5e-4):
+        e, _ = p.evaluate(np.sqrt(_cos_density(L, n, n0, [(g, eps)])), need_grad=False)
+        r.append(e["f_nl0"] / (p.V * K * eps ** 2 / 4) - 1)
+    # deviation is O(eps^2) from the second-order expansion of n^a
+    assert abs(r[1]) < 1e-4 and abs(r[0] / r[1] - 4) < 0.05
+
+
+def test_f1_two_cosines_a1():
+    L, n, n0, T = 6.0, 16, 0.04, 1.2
+    e1, e2, g = 0.004, 0.003, 2
+    s = W.System(L=L, n=(n, n, n), pos=np.zeros((1, 3)), zval=np.array([n0 * L ** 3]),
+                 rc=np.array([0.5]), T=T, alpha=1.0, beta=1.0, terms=TERM_NL1)
+    p = Problem(s, with_ewald=False)
+    e, _ = p.evaluate(np.sqrt(_cos_density(L, n, n0, [(g, e1), (2 * g, e2)])), need_grad=False)
+    wp1, wp2 = p.wp_shell[g * g], p.wp_shell[4 * g * g]
+    ref = p.V / 12 * e1 ** 2 * e2 * (2 * wp1 + wp2)
+    assert abs(e["f_nl1"] / ref - 1) < 1e-11
+    e, _ = p.evaluate(np.sqrt(_cos_density(L, n, n0, [(g, e1)])), need_grad=False)
+    assert abs(e["f_nl1"]) < 1e-14 * abs(ref)
+
+
+def test_wprime_is_derivative_of_w():
+    # brute force: a plain (non-extrapolated) difference at a small step
+    L, n0, T, a = 6.0, 0.04, 1.2, 5 / 6
+    q = np.array([0.3, 1.0, 2.5, 6.0])
+    wp = kernel.kernel_wprime(q, n0, T, a)
+    h = 1e-5 * n0
+    fd = (kernel.kernel_w(q, n0 + h, T, a) - kernel.kernel_w(q, n0 - h, T, a)) / (2 * h)
+    assert np.max(np.abs(wp / fd - 1)) < 1e-6
+
+
+# ----------------------------------------------------------------------------
+# Symmetries and gauge (P13, P15)
+# ----------------------------------------------------------------------------
+
+def test_translation_permutation_rotation_invariance():
+    s = W.uniform_system(5, 1.0, 0.4, 2.0, 1.5, 12, seed=31)
+    p = Problem(s)
+    phi = W.random_phi(s, 8, amp=0.3)
+    e0, g0 = p.evaluate(phi)
+    h = s.L / 12
+    # translate ions by a grid vector and shift phi accordingly
+    shift = np.array([2, 5, 7])
+    s2 = W.System(L=s.L, n=s.n, pos=np.mod(s.pos + shift * h, s.L), zval=s.zval,
+                  rc=s.rc, T=s.T)
+    p2 = Problem(s2)
+    phi2 = np.roll(phi, tuple(shift), axis=(0, 1, 2))
+    e2, g2 = p2.evaluate(phi2)
+    assert abs(e2["total"] - e0["total"]) < 1e-12 * abs(e0["total"])
+    assert np.max(np.abs(g2 - np.roll(g0, tuple(shift), axis=(0, 1, 2)))) < 1e-11
+    # permutation
+    perm = np.random.default_rng(0).permutation(5)
+    s3 = W.System(L=s.L, n=s.n, pos=s.pos[perm], zval=s.zval[perm], rc=s.rc[perm], T=s.T)
+    e3, _ = Problem(s3).evaluate(phi)
+    assert abs(e3["total"] - e0["total"]) < 1e-12 * abs(e0["total"])
+    # 90 degree rotation about z: (x, y) -> (-y, x) on grid indices
+    pr = np.stack([np.mod(-s.pos[:, 1], s.L), s.pos[:, 0], s.pos[:, 2]], 1)
+    s4 = W.System(L=s.L, n=s.n, pos=pr, zval=s.zval, rc=s.rc, T=s.T)
+    idx = np.arange(12)
+    phi4 = np.transpose(phi[:, :, :], (1, 0, 2))[(-idx) % 12, :, :]
+    e4, _ = Problem(s4).evaluate(phi4)
+    assert abs(e4["total"] - e0["total"]) < 1e-12 * abs(e0["total"])
+
+
+def test_gauge_constant_shift():
+    s = W.uniform_system(5, 1.0, 0.4, 2.0, 1.5, 12, seed=32)
+    p = Problem(s, with_ewald=False)
+    phi = W.random_phi(s, 9)
+    e0, g0 = p.evaluate(phi)
+    c = 0.37
+    p.vloc = p.vloc.copy()
+    p.vloc[0, 0, 0] += c
+    e1, g1 = p.evaluate(phi)
+    assert abs(e1["free_energy"] - (e0["free_energy"] + c * p.ne)) < 1e-12 * p.ne
+    assert abs(e1["mu"] - (e0["mu"] + c)) < 1e-12
+    r0 = g0 - 2 * e0["mu"] * phi
+    r1 = g1 - 2 * e1["mu"] * phi
+    assert np.max(np.abs(r1 - r0)) < 1e-12
