@@ -1,0 +1,222 @@
+/*
+ * skx.h -- C ABI of libskx, a GPU (gfx950) implementation of the repeated
+ * evaluation of the finite-temperature orbital-free free energy and its
+ * potential on a periodic grid, and of the constrained density optimisation
+ * that drives it.
+ *
+ * Method (arXiv 2601.23002, "Unlocking the Power of Orbital-Free Density
+ * Functional Theory to Explore the Electronic Structure Under Extreme
+ * Conditions"):
+ *   F_s[n;T] = F_TF + F_vW + F_NL                       (Eq. (1))
+ *   F_NL     = F0 + beta F1, beta = 1 is XWMF           (Eq. (2) and text)
+ *   exchange-correlation: Perdew-Zunger LDA, adiabatic  (Methods)
+ *   local pseudopotential per ion                       (Methods)
+ * The paper prints no formula for the individual terms. This library uses
+ * the following readings (each is a choice where the paper is silent):
+ *   TF   exact uniform-gas free energy at T: f = n T eta - (2/3) n_T T I_3/2(eta),
+ *        n = n_T I_1/2(eta), n_T = sqrt(2)/pi^2 T^(3/2)
+ *   vW   (1/2) int |grad sqrt(n)|^2, temperature independent
+ *   F0   V sum_G w(G) |f~(G)|^2, f = n^a; w chosen so that TF + vW + F0
+ *        reproduce the finite-T Lindhard response at the mean density n0
+ *        (the kernel is the second functional derivative at the mean
+ *        valence density, Results section)
+ *   F1   (1/3) int dF dn (w' * dF), dF = n^a - n0^a, dn = n - n0,
+ *        w' = dw/dn0 at fixed T (first-order density dependence of the
+ *        kernel along n0 + t(n - n0), the "line integral" correction)
+ *   E_H  Hartree with the G = 0 term removed
+ *   V_loc erf-smeared Coulomb -Z erf(r/rc)/r per ion through the structure
+ *        factor, with its G = 0 (non-Coulomb) term; the real part of the
+ *        plane-wave sum on even grids
+ *   E_xc Perdew-Zunger 1981, unpolarised, temperature independent
+ *
+ * Units: Hartree atomic units. Energies are totals over the cell.
+ *
+ * Conventions for every entry point:
+ *   - Return codes only (no exceptions, no abort). SKX_OK = 0; a positive
+ *     value is a completed call with a warning; a negative value is an
+ *     error, described by skx_last_error(ctx) until the next call on ctx.
+ *   - The caller owns every pointer it passes; the library keeps no caller
+ *     pointer after a call returns (the serving engine copies its inputs).
+ *   - Device pointers must be on the context's device. Real grid fields are
+ *     C-order [n1][n2][n3] with n3 fastest, FP64 unless stated otherwise.
+ *   - Work is queued on the context's stream; calls that return host
+ *     scalars synchronise that stream. Calls on one context must not
+ *     overlap; distinct contexts are independent.
+ *   - State order: set_cell -> set_ions -> set_functional -> evaluate /
+ *     optimise. set_cell invalidates ions and kernel tables.
+ */
+#ifndef SKX_H
+#define SKX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SKX_OK = 0,
+  SKX_NOT_CONVERGED = 1,   /* optimisation stopped at max_iter or in the line search */
+  SKX_E_INVALID = -1,      /* bad size, lattice, parameter or pointer */
+  SKX_E_STATE = -2,        /* call out of order */
+  SKX_E_NOMEM = -3,        /* device allocation failed */
+  SKX_E_DEVICE = -4,       /* HIP runtime error */
+  SKX_E_NUMERIC = -5       /* non-finite input or numerical blow-up */
+};
+
+/* term mask bits of skx_functional.terms */
+enum {
+  SKX_TERM_TF = 1, SKX_TERM_VW = 2, SKX_TERM_NL0 = 4, SKX_TERM_NL1 = 8,
+  SKX_TERM_HARTREE = 16, SKX_TERM_LOCPP = 32, SKX_TERM_XC = 64, SKX_TERM_ALL = 127
+};
+
+enum { SKX_XC_NONE = 0, SKX_XC_PZ81 = 1 };
+enum { SKX_FP64 = 0, SKX_FP32 = 1, SKX_MIXED = 2 };
+enum { SKX_RHO = 0, SKX_SQRT_RHO = 1 };
+
+typedef struct skx_ctx skx_ctx;
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to
+ * queue work on, or NULL for a library-owned stream. Errors: SKX_E_DEVICE. */
+int skx_create(skx_ctx **out, int device, void *hip_stream);
+void skx_destroy(skx_ctx *ctx);
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char *skx_last_error(const skx_ctx *ctx);
+
+/* Periodic cell and grid. lattice: 9 doubles, rows a1, a2, a3 in bohr; this
+ * version accepts cubic cells only (a1 = L x, a2 = L y, a3 = L z). n1, n2, n3:
+ * even and 5-smooth, 8..512; the fused FP64 kernels need n <= 128 (FP32:
+ * n <= 192). Invalidates ions and tables. Errors: SKX_E_INVALID. */
+int skx_set_cell(skx_ctx *ctx, const double lattice[9], int n1, int n2, int n3);
+
+/* Ions: nions host positions [nions][3] (cartesian bohr, any image), a
+ * species index per ion, and per species the valence zval and erf width rc
+ * (bohr, > 0). Builds V_loc(G) through the ionic structure factor on the
+ * device and the Ewald ion-ion energy. Errors: SKX_E_INVALID, SKX_E_STATE
+ * (no cell), SKX_E_NOMEM. */
+int skx_set_ions(skx_ctx *ctx, int nions, const double *pos, const int *species, int nspecies,
+                 const double *zval, const double *rc);
+
+typedef struct {
+  double T;          /* electron temperature, Ha, > 0 */
+  double beta;       /* weight of F1 (Eq. (2)); 1 reproduces XWMF */
+  double alpha;      /* exponent a of f = n^a in F0/F1, in (0.5, 1.5]; default 5/6 */
+  unsigned terms;    /* SKX_TERM_* mask */
+  int xc;            /* SKX_XC_PZ81 or SKX_XC_NONE (clears SKX_TERM_XC) */
+  int precision;     /* SKX_FP64, SKX_FP32 or SKX_MIXED */
+} skx_functional;
+
+/* Store the functional; kernel tables are rebuilt lazily. Errors:
+ * SKX_E_INVALID, SKX_E_STATE. */
+int skx_set_functional(skx_ctx *ctx, const skx_functional *fn);
+
+typedef struct {
+  double f_tf, e_vw, f_nl0, f_nl1;  /* f_nl1 already carries the factor beta */
+  double e_h, e_loc, e_xc, e_ii;
+  double free_energy;               /* electronic: f_tf + ... + e_xc */
+  double total;                     /* free_energy + e_ii */
+  double mu;                        /* int phi dE/dphi / (2 N_e) */
+  double nelec;                     /* int n */
+} skx_energy;
+
+/* One evaluation of every energy term and of dE/dphi.
+ * in_dev: device field, n (SKX_RHO, phi = sqrt(n) is formed internally) or
+ *   phi = sqrt(n) (SKX_SQRT_RHO). FP64 for SKX_FP64/SKX_MIXED, FP32 for SKX_FP32.
+ * out_dev: NULL, or a device field of the same type receiving dE/dphi
+ *   (the unconstrained gradient with respect to phi).
+ * e: host struct receiving the energies. Synchronises the stream.
+ * Errors: SKX_E_STATE, SKX_E_INVALID, SKX_E_NUMERIC (non-finite field or a
+ * density beyond the Fermi-Dirac table). */
+int skx_evaluate_energy_potential(skx_ctx *ctx, const void *in_dev, int in_kind, void *out_dev,
+                                  skx_energy *e);
+
+typedef struct {
+  double gtol;              /* stop when ||r|| = (int r^2)^(1/2) < gtol, r = dE/dphi - 2 mu phi */
+  int max_iter;             /* iteration cap */
+  int lbfgs_m;              /* history length, 1..8 (5 by default) */
+  double fp32_switch_gtol;  /* SKX_MIXED: FP32 phase stops below this ||r|| */
+  int warm_start;           /* 1: rho_dev holds the starting density */
+} skx_opt_params;
+
+typedef struct {
+  skx_energy e;
+  int iters, evals, fp32_iters, fp32_evals;
+  double gnorm;
+  int status;               /* SKX_OK or SKX_NOT_CONVERGED (or a negative error) */
+  int resets;
+} skx_opt_result;
+
+/* Minimise the free energy over n = phi^2 at fixed electron number with
+ * limited-memory BFGS on phi (the minimisation the paper calls its SCF
+ * iterations). rho_dev: FP64 device field; input guess if warm_start,
+ * output density always. Returns SKX_OK, SKX_NOT_CONVERGED (best state
+ * returned) or an error. Synchronises the stream. */
+int skx_optimize_density(skx_ctx *ctx, void *rho_dev, const skx_opt_params *p,
+                         skx_opt_result *res);
+
+/* Solve nctx independent problems together: every kernel of the step
+ * sequence is one launch over all solves (uneven grids allowed, same
+ * precision mode required). rho_devs[i] as in skx_optimize_density.
+ * Each result equals that of solving alone (per-solve reductions are in a
+ * fixed order). Errors as skx_optimize_density; res[i].status per solve. */
+int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_params *p,
+                  skx_opt_result *res);
+
+/* ---- introspection (tests and tools) ---- */
+
+/* Copy the shell tables w[s], w'[s], s = g1^2+g2^2+g3^2 = 0..len-1, to host. */
+int skx_get_kernel_tables(skx_ctx *ctx, double *w_host, double *wp_host, int len);
+/* Copy V_loc(G) (half spectrum [n1][n2][n3/2+1] complex, FP64 pairs) to host. */
+int skx_get_vloc(skx_ctx *ctx, double *host);
+/* Number of shells (3 (n/2)^2 + 1 for cubic grids) of the current cell. */
+int skx_num_shells(const skx_ctx *ctx);
+/* Universal Fermi-Dirac table on `device`: for host ratios u = n / n_T > 0
+ * return eta with I_1/2(eta) = u and psi = eta - (2/3) I_3/2(eta) / u. */
+int skx_fd_eval(int device, const double *u_host, double *eta_host, double *psi_host, long long n);
+/* Forward then inverse transform of a host real field through the GPU FFT
+ * passes (spectral multipliers off); returns the round trip in out_host and
+ * the half spectrum [n1][n2][n3/2+1] complex (FP64 pairs, normalised 1/M)
+ * in spec_host (may be NULL). Cell must be set. */
+int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double *spec_host);
+
+/* ---- serving engine (continuous batching over requests) ---- */
+typedef struct {
+  double lattice[9];
+  int n1, n2, n3;
+  int nions;
+  const double *pos;         /* host [nions][3] */
+  const int *species;
+  int nspecies;
+  const double *zval, *rc;
+  skx_functional fn;
+  skx_opt_params opt;
+  double t_arrival;          /* caller's clock, seconds */
+} skx_request;
+
+typedef struct {
+  uint64_t ticket;
+  skx_opt_result r;
+  double t_admit, t_done;    /* engine clock, seconds since engine creation */
+  long long npoints;         /* n1*n2*n3 */
+} skx_result;
+
+typedef struct skx_engine skx_engine;
+/* hbm_budget_bytes bounds the device memory of resident solves;
+ * max_slots bounds how many solves are resident at once. */
+int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int max_slots);
+/* Copies the request; SKX_E_INVALID if it can never fit the budget. */
+int skx_engine_submit(skx_engine *eng, const skx_request *req, uint64_t *ticket);
+/* Admit queued requests into free slots, then run one optimiser step over
+ * every resident solve. Returns the number of resident solves (>= 0). */
+int skx_engine_step(skx_engine *eng);
+/* Collect finished results (up to max); the density of each is copied to
+ * rho_host[i] when rho_host is non-NULL and rho_host[i] is non-NULL. */
+int skx_engine_poll(skx_engine *eng, skx_result *out, double **rho_host, int max, int *n_out);
+int skx_engine_pending(const skx_engine *eng);
+void skx_engine_destroy(skx_engine *eng);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

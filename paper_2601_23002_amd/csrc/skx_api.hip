@@ -1,0 +1,1027 @@
+// Host runtime and C ABI of libskx: contexts, device buffers, plans, the
+// batched step sequence and the optimisation driver.
+#include "skx_internal.hpp"
+#include "skx_device.hpp"
+#include "../../include/skx.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace skx;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Per-device resources shared by all contexts: FFT twiddle bank and the
+// universal Fermi-Dirac Chebyshev table.
+// ---------------------------------------------------------------------------
+constexpr double FD_Y0 = -46.0, FD_DY = 0.5;
+constexpr int FD_NSEG = 124, FD_DEG = 20;     // covers ln(n/n_T) in [-46, 16)
+
+struct DeviceRes {
+  bool ready = false;
+  double *twbank = nullptr;
+  int tw_off[514];
+  double *fdcoef = nullptr;
+  FDTable fd{};
+};
+DeviceRes g_res[64];
+std::mutex g_mu;
+
+bool five_smooth_even(int n) {
+  if (n < 8 || n > 512 || (n & 1)) return false;
+  int m = n;
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+hipError_t init_device(int dev, std::string &err) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev < 0 || dev >= 64) { err = "device index out of range"; return hipErrorInvalidDevice; }
+  DeviceRes &r = g_res[dev];
+  if (r.ready) return hipSuccess;
+  hipError_t e = hipSetDevice(dev);
+  if (e != hipSuccess) { err = "hipSetDevice failed"; return e; }
+  std::vector<int> sizes, offs;
+  int off = 0;
+  for (int n = 2; n <= 512; ++n) {
+    r.tw_off[n] = -1;
+    int m = n;
+    for (int p : {2, 3, 5})
+      while (m % p == 0) m /= p;
+    if (m != 1) continue;
+    r.tw_off[n] = off;
+    sizes.push_back(n);
+    offs.push_back(off);
+    off += n;
+  }
+  e = hipMalloc((void **)&r.twbank, sizeof(double) * 2 * off);
+  if (e != hipSuccess) { err = "twiddle bank allocation failed"; return e; }
+  int *dsz = nullptr, *doff = nullptr;
+  hipMalloc((void **)&dsz, sizeof(int) * sizes.size());
+  hipMalloc((void **)&doff, sizeof(int) * offs.size());
+  hipMemcpy(dsz, sizes.data(), sizeof(int) * sizes.size(), hipMemcpyHostToDevice);
+  hipMemcpy(doff, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice);
+  e = build_twiddles(r.twbank, dsz, doff, (int)sizes.size(), 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipFree(dsz);
+  hipFree(doff);
+  if (e != hipSuccess) { err = "twiddle kernel failed"; return e; }
+  size_t nc = (size_t)FD_NSEG * 2 * (FD_DEG + 1);
+  e = hipMalloc((void **)&r.fdcoef, sizeof(double) * nc);
+  if (e != hipSuccess) { err = "FD table allocation failed"; return e; }
+  e = build_fd_table(r.fdcoef, FD_Y0, FD_DY, FD_NSEG, FD_DEG, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) { err = "FD table kernel failed"; return e; }
+  r.fd.y0 = FD_Y0;
+  r.fd.dy = FD_DY;
+  r.fd.inv_dy = 1.0 / FD_DY;
+  r.fd.nseg = FD_NSEG;
+  r.fd.deg = FD_DEG;
+  r.fd.coef = r.fdcoef;
+  r.ready = true;
+  return hipSuccess;
+}
+
+Plan make_plan(int n, int twoff) {
+  Plan p{};
+  p.n = n;
+  p.tw = twoff;
+  int m = n;
+  auto push = [&](unsigned r) { p.rad |= r << (4 * p.nst); p.nst++; m /= (int)r; };
+  while (m % 4 == 0 && p.nst < MAX_STAGES) push(4);
+  while (m % 2 == 0 && p.nst < MAX_STAGES) push(2);
+  while (m % 3 == 0 && p.nst < MAX_STAGES) push(3);
+  while (m % 5 == 0 && p.nst < MAX_STAGES) push(5);
+  return p;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// One solve instance in one precision: device buffers + descriptor.
+struct Instance {
+  int prec = -1;                 // 0 fp64, 1 fp32
+  size_t rsz = 0;
+  void *mem = nullptr;           // one arena for every field of the solve
+  size_t bytes = 0;
+  SolveDev h{};                  // host mirror of the descriptor
+  SolveDev *dptr = nullptr;      // device copy (batch of one)
+  OptState *st = nullptr;        // device
+  int *first = nullptr;          // device prefix sums for the batch of one [4][2]
+  BatchLaunch bl{};
+  bool vloc_ok = false;
+  int m_alloc = 0;
+};
+
+}  // namespace
+
+struct skx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  bool has_cell = false, has_ions = false, has_fn = false;
+  double L = 0;
+  int n1 = 0, n2 = 0, n3 = 0;
+  std::vector<double> pos, zsp, rcsp;
+  std::vector<int> species;
+  int nspecies = 0;
+  double ne = 0;
+  skx_functional fn{};
+  double *w = nullptr, *wp = nullptr;
+  int smax = 0;
+  bool tables_ok = false;
+  double e_ii = 0;
+  Instance inst[2];
+  double *ion_pos = nullptr, *ion_z = nullptr, *sp_z = nullptr, *sp_rc = nullptr;
+  int *ion_sp = nullptr;
+};
+
+namespace {
+
+int fail(skx_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(skx_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(c, SKX_E_NOMEM, m);
+  return fail(c, SKX_E_DEVICE, m);
+}
+
+void free_instance(Instance &I) {
+  if (I.mem) hipFree(I.mem);
+  if (I.dptr) hipFree(I.dptr);
+  if (I.st) hipFree(I.st);
+  if (I.first) hipFree(I.first);
+  I = Instance{};
+}
+
+int fields_mask(unsigned terms, double beta) {
+  int f = F_N;
+  if (terms & SKX_TERM_VW) f |= F_PHI;
+  if (terms & (SKX_TERM_NL0 | SKX_TERM_NL1)) f |= F_F;
+  if ((terms & SKX_TERM_NL1) && beta != 0.0) f |= F_H;
+  return f;
+}
+
+// LDS bytes of the three passes for one solve
+void lds_sizes(const SolveDev &h, int prec, size_t &a, size_t &b, size_t &c) {
+  size_t v = prec == 0 ? 16 : 8;
+  a = v * ((size_t)h.n2 * h.nh + h.n2 + h.n3);
+  b = v * ((size_t)h.n1 * h.nf * h.tk + h.n1);
+  c = a;
+  a = std::max(a, (size_t)1024);
+  b = std::max(b, (size_t)1024);
+  c = std::max(c, (size_t)1024);
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+// Allocate (or reuse) the buffers of one precision instance and fill the
+// descriptor's grid and buffer fields.
+int ensure_instance(skx_ctx *c, int prec, int m) {
+  Instance &I = c->inst[prec];
+  const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
+  const size_t rsz = prec == 0 ? 8 : 4;
+  const int tk = prec == 0 ? 8 : 16;
+  const int nh = n3 / 2 + 1;
+  const int pitch = (int)align_up(nh, tk);
+  const long long M = (long long)n1 * n2 * n3;
+  const long long H = (long long)n1 * n2 * pitch;
+  const int nkb = (nh + tk - 1) / tk;
+  const int nwg = (int)((M + CHUNK - 1) / CHUNK);
+  if (m < 1) m = 1;
+  if (I.mem && I.prec == prec && I.m_alloc >= m && I.h.n1 == n1 && I.h.n2 == n2 && I.h.n3 == n3)
+    return SKX_OK;
+  free_instance(I);
+  hipSetDevice(c->device);
+  // arena layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  size_t o_phi = take(rsz * M), o_phit = take(rsz * M), o_grad = take(rsz * M);
+  size_t o_r = take(rsz * M), o_d = take(rsz * M);
+  size_t o_S = take(rsz * M * m), o_Y = take(rsz * M * m);
+  size_t o_spec = take(2 * rsz * H * NFIELD), o_vloc = take(2 * rsz * H);
+  size_t o_pA = take(8 * (size_t)n1 * PART_A), o_pB = take(8 * (size_t)n2 * nkb * PART_B);
+  size_t o_pC = take(8 * (size_t)n1 * PART_C), o_pU = take(8 * (size_t)nwg * NDOT);
+  size_t o_pD = take(8 * (size_t)nwg * 2);
+  hipError_t e = hipMalloc(&I.mem, off);
+  if (e != hipSuccess) { I.mem = nullptr; return hip_fail(c, e, "device arena allocation"); }
+  hipMemsetAsync(I.mem, 0, off, c->stream);
+  e = hipMalloc((void **)&I.dptr, sizeof(SolveDev));
+  if (e == hipSuccess) e = hipMalloc((void **)&I.st, sizeof(OptState));
+  if (e == hipSuccess) e = hipMalloc((void **)&I.first, sizeof(int) * 8);
+  if (e != hipSuccess) { free_instance(I); return hip_fail(c, e, "descriptor allocation"); }
+  hipMemsetAsync(I.st, 0, sizeof(OptState), c->stream);
+  I.prec = prec;
+  I.rsz = rsz;
+  I.bytes = off;
+  I.m_alloc = m;
+  char *base = (char *)I.mem;
+  SolveDev &h = I.h;
+  h = SolveDev{};
+  h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = nh; h.pitch = pitch;
+  h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg;
+  h.M = M; h.H = H;
+  h.phi = base + o_phi; h.phit = base + o_phit; h.grad = base + o_grad;
+  h.r = base + o_r; h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
+  h.spec = base + o_spec; h.vloc = base + o_vloc;
+  h.partA = (double *)(base + o_pA); h.partB = (double *)(base + o_pB);
+  h.partC = (double *)(base + o_pC); h.partU = (double *)(base + o_pU);
+  h.partD = (double *)(base + o_pD);
+  h.st = I.st;
+  const DeviceRes &R = g_res[c->device];
+  h.p1 = make_plan(n1, R.tw_off[n1]);
+  h.p2 = make_plan(n2, R.tw_off[n2]);
+  h.p3 = make_plan(n3, R.tw_off[n3]);
+  I.vloc_ok = false;
+  return SKX_OK;
+}
+
+// Fill the physics fields of the descriptor from the context.
+void fill_physics(skx_ctx *c, SolveDev &h) {
+  const double PI = 3.14159265358979323846;
+  h.L = c->L;
+  h.V = c->L * c->L * c->L;
+  h.dV = h.V / (double)h.M;
+  h.ne = c->ne;
+  h.n0 = c->ne / h.V;
+  h.a = c->fn.alpha;
+  h.n0a = std::pow(h.n0, h.a);
+  h.T = c->fn.T;
+  h.beta = c->fn.beta;
+  h.kscale = (2.0 * PI / c->L) * (2.0 * PI / c->L);
+  h.lnnT = std::log(std::sqrt(2.0) / (PI * PI) * c->fn.T * std::sqrt(c->fn.T));
+  h.sqrt_ne = std::sqrt(c->ne);
+  h.inv_sqrt_ne = 1.0 / h.sqrt_ne;
+  h.terms = c->fn.terms;
+  h.fields = fields_mask(h.terms, h.beta);
+  int nf = 0;
+  for (int b = 0; b < NFIELD; ++b) h.slot[b] = (h.fields & (1 << b)) ? nf++ : -1;
+  h.nf = nf;
+  h.w = c->w;
+  h.wp = c->wp;
+}
+
+// Prefix sums and grids of a batch; writes `first` (device, 4*(n+1) ints).
+int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev *ddev,
+                int *dfirst, BatchLaunch &bl, hipStream_t s) {
+  const int n = (int)hs.size();
+  std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1);
+  fa[0] = fb[0] = fc[0] = fv[0] = 0;
+  size_t la = 0, lb = 0, lc = 0;
+  for (int i = 0; i < n; ++i) {
+    const SolveDev &h = hs[i];
+    fa[i + 1] = fa[i] + h.n1 * h.nf;
+    fb[i + 1] = fb[i] + h.n2 * h.nkb;
+    fc[i + 1] = fc[i] + h.n1;
+    fv[i + 1] = fv[i] + h.nwg_vec;
+    size_t a, b, cc;
+    lds_sizes(h, prec, a, b, cc);
+    la = std::max(la, a); lb = std::max(lb, b); lc = std::max(lc, cc);
+  }
+  if (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX)
+    return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
+  std::vector<int> all;
+  all.insert(all.end(), fa.begin(), fa.end());
+  all.insert(all.end(), fb.begin(), fb.end());
+  all.insert(all.end(), fc.begin(), fc.end());
+  all.insert(all.end(), fv.begin(), fv.end());
+  hipError_t e = hipMemcpyAsync(dfirst, all.data(), sizeof(int) * all.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ddev, hs.data(), sizeof(SolveDev) * n, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "descriptor upload");
+  const DeviceRes &R = g_res[c->device];
+  bl.dev = ddev;
+  bl.nsolve = n;
+  bl.prec = prec;
+  bl.twbank = R.twbank;
+  bl.fd = R.fd;
+  bl.gridA = fa[n]; bl.gridB = fb[n]; bl.gridC = fc[n]; bl.gridV = fv[n];
+  bl.firstA = dfirst;
+  bl.firstB = dfirst + (n + 1);
+  bl.firstC = dfirst + 2 * (n + 1);
+  bl.firstV = dfirst + 3 * (n + 1);
+  // pass C keeps dE/dphi beside the plane in LDS when every solve fits
+  size_t lc_acc = 0;
+  for (const SolveDev &h : hs)
+    lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
+                                  (prec == 0 ? 8 : 4) * (size_t)h.n2 * h.n3);
+  bl.accC_lds = lc_acc <= LDS_MAX ? 1 : 0;
+  if (bl.accC_lds) lc = std::max(lc, lc_acc);
+  bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
+  return SKX_OK;
+}
+
+int check_grid(skx_ctx *c, int prec) {
+  const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
+  SolveDev h{};
+  h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = n3 / 2 + 1; h.nf = NFIELD; h.tk = prec == 0 ? 8 : 16;
+  size_t a, b, cc;
+  lds_sizes(h, prec, a, b, cc);
+  if (a > LDS_MAX || b > LDS_MAX)
+    return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
+  return SKX_OK;
+}
+
+int ensure_tables(skx_ctx *c) {
+  if (c->tables_ok) return SKX_OK;
+  const int smax = (c->n1 / 2) * (c->n1 / 2) + (c->n2 / 2) * (c->n2 / 2) + (c->n3 / 2) * (c->n3 / 2);
+  if (c->w) { hipFree(c->w); c->w = nullptr; }
+  if (c->wp) { hipFree(c->wp); c->wp = nullptr; }
+  hipError_t e = hipMalloc((void **)&c->w, sizeof(double) * (smax + 1));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->wp, sizeof(double) * (smax + 1));
+  if (e != hipSuccess) return hip_fail(c, e, "kernel table allocation");
+  c->smax = smax;
+  const double V = c->L * c->L * c->L;
+  double eta0 = 0;
+  e = build_kernel_tables(c->w, c->wp, smax, c->L, c->ne / V, c->fn.T, c->fn.alpha,
+                          g_res[c->device].fd, &eta0, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel table build");
+  c->tables_ok = true;
+  return SKX_OK;
+}
+
+int ensure_vloc(skx_ctx *c, Instance &I) {
+  if (I.vloc_ok) return SKX_OK;
+  const int nions = (int)c->species.size();
+  const int nh = c->n3 / 2 + 1;
+  double2 *scr = nullptr;
+  size_t ns = (size_t)std::max(1, nions) * (c->n1 + c->n2 + nh);
+  hipError_t e = hipMallocAsync((void **)&scr, sizeof(double2) * ns, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "phase table allocation");
+  e = build_vloc(I.h.vloc, I.prec, c->n1, c->n2, c->n3, I.h.pitch, c->L, nions, c->ion_pos,
+                 c->ion_sp, c->nspecies, c->sp_z, c->sp_rc, scr, c->stream);
+  hipFreeAsync(scr, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "structure factor kernel");
+  I.vloc_ok = true;
+  return SKX_OK;
+}
+
+// Prepare instance `prec` of a context for a run: buffers, tables, V_loc,
+// descriptor upload for the batch of one.
+int prepare(skx_ctx *c, int prec, int m) {
+  if (!c->has_cell || !c->has_ions || !c->has_fn)
+    return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
+  int rc = check_grid(c, prec);
+  if (rc) return rc;
+  rc = ensure_instance(c, prec, m);
+  if (rc) return rc;
+  rc = ensure_tables(c);
+  if (rc) return rc;
+  Instance &I = c->inst[prec];
+  fill_physics(c, I.h);
+  rc = ensure_vloc(c, I);
+  if (rc) return rc;
+  return SKX_OK;
+}
+
+int upload_single(skx_ctx *c, Instance &I) {
+  std::vector<SolveDev> hs(1, I.h);
+  return build_batch(c, hs, I.prec, I.dptr, I.first, I.bl, c->stream);
+}
+
+__global__ void k_sqrt_field(const double *in, double *out, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) { double v = in[i]; out[i] = v > 0 ? sqrt(v) : 0.0; }
+}
+__global__ void k_sqrt_field_f(const float *in, float *out, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) { float v = in[i]; out[i] = v > 0 ? sqrtf(v) : 0.0f; }
+}
+template <typename R>
+__global__ void k_fill(R *p, R v, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+template <typename R>
+__global__ void k_square_out(const R *phi, double *rho, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) { double v = (double)phi[i]; rho[i] = v * v; }
+}
+template <typename R>
+__global__ void k_from_rho(const double *rho, R *phi, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) phi[i] = (R)rho[i];
+}
+__global__ void k_f2d(const float *a, double *b, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+unsigned blocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void energy_from(const double *e, double e_ii, skx_energy *out) {
+  out->f_tf = e[E_TF]; out->e_vw = e[E_VW]; out->f_nl0 = e[E_NL0]; out->f_nl1 = e[E_NL1];
+  out->e_h = e[E_H]; out->e_loc = e[E_LOC]; out->e_xc = e[E_XC]; out->e_ii = e_ii;
+  out->free_energy = e[E_FREE]; out->total = e[E_FREE] + e_ii; out->mu = e[E_MU];
+  out->nelec = e[E_NELEC];
+}
+
+// Initialise the optimiser state of one instance (host -> device).
+void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho) {
+  st = OptState{};
+  st.phase = PH_EVAL_INIT;
+  st.m = std::min(std::max(p.lbfgs_m, 1), MMAX);
+  st.max_iter = p.max_iter;
+  st.max_trials = 20;
+  st.gtol = gtol;
+  st.c1 = 1e-4;
+  st.theta_max = 0.5;
+  st.tolE_rel = 1e-12;
+  st.reset_pending = from_rho ? 2 : 0;
+}
+
+// The fixed step sequence: direction, trial evaluation, update.
+hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
+  hipError_t e = launch_opt_dir(bl, s);
+  if (e == hipSuccess) e = launch_eval(bl, s);
+  if (e == hipSuccess) e = launch_finalize_eval(bl, s);
+  if (e == hipSuccess) e = launch_opt_update(bl, s);
+  return e;
+}
+
+// Drive a batch until every solve is DONE or FAILED. States are polled
+// every `chunk` steps; the step sequence itself makes every decision.
+int drive(skx_ctx *c, const BatchLaunch &bl, const std::vector<OptState *> &states,
+          int max_steps, hipStream_t s) {
+  hipError_t e = launch_normalize(bl, s);
+  if (e != hipSuccess) return hip_fail(c, e, "normalisation kernels");
+  const int chunk = 8;
+  std::vector<int> ph(states.size());
+  int steps = 0;
+  while (steps < max_steps) {
+    for (int k = 0; k < chunk; ++k) {
+      e = step_sequence(bl, s);
+      if (e != hipSuccess) return hip_fail(c, e, "step kernels");
+    }
+    steps += chunk;
+    bool all = true;
+    for (size_t i = 0; i < states.size(); ++i) {
+      e = hipMemcpyAsync(&ph[i], &states[i]->phase, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return hip_fail(c, e, "state readback");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "step execution");
+    for (int p : ph)
+      if (p != PH_DONE && p != PH_FAILED) { all = false; break; }
+    if (all) break;
+  }
+  return SKX_OK;
+}
+
+int run_optimize(skx_ctx *c, Instance &I, void *rho_dev, const skx_opt_params &p, double gtol,
+                 int start_mode /* 0 uniform, 1 rho_dev (FP64 density), 2 keep I.phi */,
+                 OptState &out) {
+  const long long M = I.h.M;
+  hipStream_t s = c->stream;
+  if (start_mode == 0) {
+    const double v = std::sqrt(c->ne / (c->L * c->L * c->L));
+    if (I.prec == 0)
+      hipLaunchKernelGGL(k_fill<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                         (double *)I.h.phi, v, M);
+    else
+      hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                         (float *)I.h.phi, (float)v, M);
+  } else if (start_mode == 1) {
+    if (I.prec == 0)
+      hipLaunchKernelGGL(k_from_rho<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                         (const double *)rho_dev, (double *)I.h.phi, M);
+    else
+      hipLaunchKernelGGL(k_from_rho<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                         (const double *)rho_dev, (float *)I.h.phi, M);
+  }
+  OptState st;
+  init_state(st, p, gtol, start_mode == 1 ? 1 : 0);
+  hipError_t e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "state upload");
+  int rc = upload_single(c, I);
+  if (rc) return rc;
+  const int max_steps = (p.max_iter + 2) * 24 + 64;
+  std::vector<OptState *> states(1, I.st);
+  rc = drive(c, I.bl, states, max_steps, s);
+  if (rc) return rc;
+  e = hipMemcpyAsync(&out, I.st, sizeof(OptState), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "state readback");
+  return SKX_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int skx_create(skx_ctx **out, int device, void *hip_stream) {
+  if (!out) return SKX_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return SKX_E_DEVICE;
+  skx_ctx *c = new skx_ctx();
+  c->device = device;
+  std::string err;
+  if (init_device(device, err) != hipSuccess) { delete c; return SKX_E_DEVICE; }
+  hipSetDevice(device);
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return SKX_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return SKX_OK;
+}
+
+void skx_destroy(skx_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto &I : c->inst) free_instance(I);
+  hipFree(c->w); hipFree(c->wp);
+  hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *skx_last_error(const skx_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int skx_set_cell(skx_ctx *c, const double lattice[9], int n1, int n2, int n3) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!lattice) return fail(c, SKX_E_INVALID, "lattice is NULL");
+  const double L = lattice[0];
+  for (int i = 0; i < 9; ++i) {
+    const double want = (i % 4 == 0) ? L : 0.0;
+    if (!(std::isfinite(lattice[i])) || std::fabs(lattice[i] - want) > 1e-12 * std::fabs(L))
+      return fail(c, SKX_E_INVALID, "only cubic cells (L on the diagonal) are supported");
+  }
+  if (!(L > 0)) return fail(c, SKX_E_INVALID, "cell side must be positive");
+  if (!five_smooth_even(n1) || !five_smooth_even(n2) || !five_smooth_even(n3))
+    return fail(c, SKX_E_INVALID, "grid sizes must be even, 5-smooth and in [8, 512]");
+  c->L = L;
+  c->n1 = n1; c->n2 = n2; c->n3 = n3;
+  c->has_cell = true;
+  c->has_ions = false;
+  c->tables_ok = false;
+  for (auto &I : c->inst) I.vloc_ok = false;
+  return SKX_OK;
+}
+
+int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, int nspecies,
+                 const double *zval, const double *rc) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!c->has_cell) return fail(c, SKX_E_STATE, "set_cell first");
+  if (nions < 1 || nspecies < 1 || !pos || !species || !zval || !rc)
+    return fail(c, SKX_E_INVALID, "need at least one ion and one species");
+  double ne = 0;
+  for (int i = 0; i < nions; ++i) {
+    if (species[i] < 0 || species[i] >= nspecies)
+      return fail(c, SKX_E_INVALID, "species index out of range");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(pos[3 * i + a])) return fail(c, SKX_E_INVALID, "non-finite position");
+    ne += zval[species[i]];
+  }
+  for (int s = 0; s < nspecies; ++s)
+    if (!(zval[s] > 0) || !(rc[s] > 0)) return fail(c, SKX_E_INVALID, "zval and rc must be > 0");
+  hipSetDevice(c->device);
+  c->pos.assign(pos, pos + 3 * nions);
+  // wrap positions into the cell
+  for (auto &x : c->pos) x -= c->L * std::floor(x / c->L);
+  c->species.assign(species, species + nions);
+  c->zsp.assign(zval, zval + nspecies);
+  c->rcsp.assign(rc, rc + nspecies);
+  c->nspecies = nspecies;
+  c->ne = ne;
+  std::vector<double> zi(nions);
+  for (int i = 0; i < nions; ++i) zi[i] = zval[species[i]];
+  hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
+  c->ion_pos = c->ion_z = c->sp_z = c->sp_rc = nullptr;
+  c->ion_sp = nullptr;
+  hipError_t e = hipMalloc((void **)&c->ion_pos, sizeof(double) * 3 * nions);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->ion_z, sizeof(double) * nions);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->sp_z, sizeof(double) * nspecies);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->sp_rc, sizeof(double) * nspecies);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->ion_sp, sizeof(int) * nions);
+  if (e != hipSuccess) return hip_fail(c, e, "ion arrays");
+  hipStream_t s = c->stream;
+  hipMemcpyAsync(c->ion_pos, c->pos.data(), sizeof(double) * 3 * nions, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->ion_z, zi.data(), sizeof(double) * nions, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->sp_z, zval, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->sp_rc, rc, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->ion_sp, species, sizeof(int) * nions, hipMemcpyHostToDevice, s);
+  // Ewald energy on the device
+  {
+    const double L = c->L;
+    const double alpha = 3.2 / L;
+    const double gcut = 2.0 * alpha * std::sqrt(44.0);
+    const int mmax = (int)std::ceil(gcut * L / (2.0 * M_PI));
+    const long long side = 2 * mmax + 1;
+    const long long ng = side * side * side;
+    const long long npair = (long long)nions * (nions + 1) / 2;
+    const long long len = std::max(ng, npair);
+    double *scr = nullptr, *out = nullptr;
+    e = hipMallocAsync((void **)&scr, sizeof(double) * len, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&out, sizeof(double) * 2, s);
+    if (e != hipSuccess) return hip_fail(c, e, "Ewald scratch");
+    e = ewald_energy(L, nions, c->ion_pos, c->ion_z, scr, (int)len, out, s);
+    double parts[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(parts, out, sizeof(parts), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFreeAsync(scr, s);
+    hipFreeAsync(out, s);
+    if (e != hipSuccess) return hip_fail(c, e, "Ewald kernels");
+    double z2 = 0;
+    for (double z : zi) z2 += z * z;
+    const double V = L * L * L;
+    c->e_ii = parts[0] + parts[1] - alpha / std::sqrt(M_PI) * z2 - M_PI * ne * ne / (2.0 * V * alpha * alpha);
+  }
+  c->has_ions = true;
+  c->tables_ok = false;            // n0 changed
+  for (auto &I : c->inst) I.vloc_ok = false;
+  return SKX_OK;
+}
+
+int skx_set_functional(skx_ctx *c, const skx_functional *fn) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!fn) return fail(c, SKX_E_INVALID, "functional is NULL");
+  if (!(fn->T > 0) || !std::isfinite(fn->T)) return fail(c, SKX_E_INVALID, "T must be > 0");
+  if (!(fn->alpha > 0.5 && fn->alpha <= 1.5)) return fail(c, SKX_E_INVALID, "alpha must be in (0.5, 1.5]");
+  if (!std::isfinite(fn->beta)) return fail(c, SKX_E_INVALID, "beta must be finite");
+  if (fn->precision < SKX_FP64 || fn->precision > SKX_MIXED)
+    return fail(c, SKX_E_INVALID, "unknown precision");
+  if (fn->xc != SKX_XC_NONE && fn->xc != SKX_XC_PZ81) return fail(c, SKX_E_INVALID, "unknown xc");
+  if (fn->terms & ~127u) return fail(c, SKX_E_INVALID, "unknown term bits");
+  const bool tables_change = !c->has_fn || fn->T != c->fn.T || fn->alpha != c->fn.alpha;
+  c->fn = *fn;
+  if (fn->xc == SKX_XC_NONE) c->fn.terms &= ~(unsigned)SKX_TERM_XC;
+  c->has_fn = true;
+  if (tables_change) c->tables_ok = false;
+  return SKX_OK;
+}
+
+int skx_evaluate_energy_potential(skx_ctx *c, const void *in_dev, int in_kind, void *out_dev,
+                                  skx_energy *e) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!in_dev || !e) return fail(c, SKX_E_INVALID, "input field and energy struct are required");
+  if (in_kind != SKX_RHO && in_kind != SKX_SQRT_RHO) return fail(c, SKX_E_INVALID, "bad in_kind");
+  hipSetDevice(c->device);
+  const int prec = c->has_fn && c->fn.precision == SKX_FP32 ? 1 : 0;
+  int rc = prepare(c, prec, 1);
+  if (rc) return rc;
+  Instance &I = c->inst[prec];
+  SolveDev h = I.h;
+  const long long M = h.M;
+  if (in_kind == SKX_SQRT_RHO) {
+    h.phi = const_cast<void *>(in_dev);
+  } else {
+    if (prec == 0)
+      hipLaunchKernelGGL(k_sqrt_field, dim3(blocks(M, 256)), dim3(256), 0, c->stream,
+                         (const double *)in_dev, (double *)I.h.phi, M);
+    else
+      hipLaunchKernelGGL(k_sqrt_field_f, dim3(blocks(M, 256)), dim3(256), 0, c->stream,
+                         (const float *)in_dev, (float *)I.h.phi, M);
+  }
+  if (out_dev) h.grad = out_dev;
+  OptState st{};
+  st.phase = PH_EVAL_ONLY;
+  hipError_t he = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, c->stream);
+  if (he != hipSuccess) return hip_fail(c, he, "state upload");
+  std::vector<SolveDev> hs(1, h);
+  rc = build_batch(c, hs, prec, I.dptr, I.first, I.bl, c->stream);
+  if (rc) return rc;
+  he = launch_eval(I.bl, c->stream);
+  if (he == hipSuccess) he = launch_finalize_eval(I.bl, c->stream);
+  if (he != hipSuccess) return hip_fail(c, he, "evaluation kernels");
+  double ev[12];
+  he = hipMemcpyAsync(ev, I.st->e_trial, sizeof(ev), hipMemcpyDeviceToHost, c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return hip_fail(c, he, "evaluation");
+  energy_from(ev, c->e_ii, e);
+  if (ev[E_NONFINITE] != 0.0)
+    return fail(c, SKX_E_NUMERIC, "non-finite field or density outside the Fermi-Dirac table");
+  return SKX_OK;
+}
+
+int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx_opt_result *res) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!rho_dev || !p || !res) return fail(c, SKX_E_INVALID, "rho_dev, params and result are required");
+  if (p->lbfgs_m < 1 || p->lbfgs_m > MMAX) return fail(c, SKX_E_INVALID, "lbfgs_m must be in 1..8");
+  if (!(p->gtol > 0) || p->max_iter < 1) return fail(c, SKX_E_INVALID, "gtol > 0 and max_iter >= 1 required");
+  hipSetDevice(c->device);
+  std::memset(res, 0, sizeof(*res));
+  const int mode = c->has_fn ? c->fn.precision : SKX_FP64;
+  int rc;
+  OptState out{};
+  if (mode == SKX_FP64 || mode == SKX_FP32) {
+    const int prec = mode == SKX_FP64 ? 0 : 1;
+    rc = prepare(c, prec, p->lbfgs_m);
+    if (rc) return rc;
+    Instance &I = c->inst[prec];
+    rc = run_optimize(c, I, rho_dev, *p, p->gtol, p->warm_start ? 1 : 0, out);
+    if (rc) return rc;
+    if (prec == 0)
+      hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, c->stream,
+                         (const double *)I.h.phi, (double *)rho_dev, I.h.M);
+    else
+      hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, c->stream,
+                         (const float *)I.h.phi, (double *)rho_dev, I.h.M);
+    res->iters = out.iters;
+    res->evals = out.evals;
+    if (prec == 1) { res->fp32_iters = out.iters; res->fp32_evals = out.evals; }
+  } else {
+    // mixed: FP32 phase to fp32_switch_gtol, then FP64 refinement from there
+    rc = prepare(c, 1, p->lbfgs_m);
+    if (rc) return rc;
+    rc = prepare(c, 0, p->lbfgs_m);
+    if (rc) return rc;
+    Instance &I32 = c->inst[1];
+    Instance &I64 = c->inst[0];
+    const double sw = p->fp32_switch_gtol > 0 ? p->fp32_switch_gtol : 1e-5;
+    OptState o32{};
+    rc = run_optimize(c, I32, rho_dev, *p, std::max(sw, p->gtol), p->warm_start ? 1 : 0, o32);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_f2d, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
+                       (const float *)I32.h.phi, (double *)I64.h.phi, I64.h.M);
+    rc = run_optimize(c, I64, rho_dev, *p, p->gtol, 2, out);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
+                       (const double *)I64.h.phi, (double *)rho_dev, I64.h.M);
+    res->fp32_iters = o32.iters;
+    res->fp32_evals = o32.evals;
+    res->iters = o32.iters + out.iters;
+    res->evals = o32.evals + out.evals;
+  }
+  hipError_t he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return hip_fail(c, he, "optimisation");
+  energy_from(out.e_acc, c->e_ii, &res->e);
+  res->gnorm = out.rnorm;
+  res->resets = out.resets;
+  if (out.phase == PH_FAILED && out.status < 0) {
+    res->status = out.status;
+    return fail(c, out.status, "numerical failure in the optimisation");
+  }
+  res->status = (out.phase == PH_DONE && out.status == 0) ? SKX_OK : SKX_NOT_CONVERGED;
+  return res->status;
+}
+
+int skx_get_kernel_tables(skx_ctx *c, double *w_host, double *wp_host, int len) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!c->has_cell || !c->has_ions || !c->has_fn) return fail(c, SKX_E_STATE, "incomplete setup");
+  hipSetDevice(c->device);
+  int rc = ensure_tables(c);
+  if (rc) return rc;
+  if (len > c->smax + 1 || len < 0) return fail(c, SKX_E_INVALID, "len exceeds the shell count");
+  hipError_t e = hipSuccess;
+  if (w_host) e = hipMemcpyAsync(w_host, c->w, sizeof(double) * len, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && wp_host)
+    e = hipMemcpyAsync(wp_host, c->wp, sizeof(double) * len, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "table copy");
+  return SKX_OK;
+}
+
+int skx_num_shells(const skx_ctx *c) {
+  if (!c || !c->has_cell) return 0;
+  return (c->n1 / 2) * (c->n1 / 2) + (c->n2 / 2) * (c->n2 / 2) + (c->n3 / 2) * (c->n3 / 2) + 1;
+}
+
+int skx_get_vloc(skx_ctx *c, double *host) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!host) return fail(c, SKX_E_INVALID, "host buffer is NULL");
+  hipSetDevice(c->device);
+  int rc = prepare(c, 0, 1);
+  if (rc) return rc;
+  Instance &I = c->inst[0];
+  const int nh = c->n3 / 2 + 1;
+  hipError_t e = hipMemcpy2DAsync(host, sizeof(double) * 2 * nh, I.h.vloc,
+                                  sizeof(double) * 2 * I.h.pitch, sizeof(double) * 2 * nh,
+                                  (size_t)c->n1 * c->n2, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "V_loc copy");
+  return SKX_OK;
+}
+
+int skx_fd_eval(int device, const double *u_host, double *eta_host, double *psi_host, long long n) {
+  if (n < 0 || (n > 0 && (!u_host || !eta_host || !psi_host))) return SKX_E_INVALID;
+  for (long long i = 0; i < n; ++i)
+    if (!(u_host[i] > 0) || !std::isfinite(u_host[i])) return SKX_E_INVALID;
+  std::string err;
+  if (init_device(device, err) != hipSuccess) return SKX_E_DEVICE;
+  hipSetDevice(device);
+  if (n == 0) return SKX_OK;
+  double *d = nullptr;
+  if (hipMalloc((void **)&d, sizeof(double) * 3 * n) != hipSuccess) return SKX_E_NOMEM;
+  hipMemcpy(d, u_host, sizeof(double) * n, hipMemcpyHostToDevice);
+  hipError_t e = debug_fd_eval(d, d + n, d + 2 * n, n, g_res[device].fd, 0);
+  if (e == hipSuccess) e = hipMemcpy(eta_host, d + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(psi_host, d + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  hipFree(d);
+  return e == hipSuccess ? SKX_OK : SKX_E_DEVICE;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// FFT check and batched solves
+// ===========================================================================
+extern "C" {
+
+int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *spec_host) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!c->has_cell) return fail(c, SKX_E_STATE, "set_cell first");
+  if (!in_host || !out_host) return fail(c, SKX_E_INVALID, "host buffers are required");
+  hipSetDevice(c->device);
+  int rc = check_grid(c, 0);
+  if (rc) return rc;
+  rc = ensure_instance(c, 0, 1);
+  if (rc) return rc;
+  Instance &I = c->inst[0];
+  SolveDev h = I.h;
+  h.fields = F_PHI | F_N;
+  h.nf = 2;
+  h.slot[0] = 0; h.slot[1] = 1; h.slot[2] = -1; h.slot[3] = -1;
+  h.terms = 0;
+  h.L = c->L; h.V = c->L * c->L * c->L; h.dV = h.V / (double)h.M;
+  h.ne = 1.0; h.n0 = 1.0; h.a = 1.0; h.n0a = 1.0; h.T = 1.0; h.beta = 0.0;
+  h.debug = 1;
+  hipStream_t s = c->stream;
+  const long long M = h.M;
+  hipError_t e = hipMemcpyAsync(h.phi, in_host, sizeof(double) * M, hipMemcpyHostToDevice, s);
+  OptState st{};
+  st.phase = PH_EVAL_ONLY;
+  if (e == hipSuccess) e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "upload");
+  std::vector<SolveDev> hs(1, h);
+  rc = build_batch(c, hs, 0, I.dptr, I.first, I.bl, s);
+  if (rc) return rc;
+  e = launch_eval(I.bl, s, 3);
+  if (e != hipSuccess) return hip_fail(c, e, "forward passes");
+  const int nh = c->n3 / 2 + 1;
+  if (spec_host) {
+    e = hipMemcpy2DAsync(spec_host, sizeof(double) * 2 * nh, h.spec, sizeof(double) * 2 * h.pitch,
+                         sizeof(double) * 2 * nh, (size_t)c->n1 * c->n2, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(c, e, "spectrum copy");
+  }
+  hs[0].debug = 2;
+  e = hipMemcpyAsync(I.dptr, hs.data(), sizeof(SolveDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_eval(I.bl, s, 6);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out_host, h.grad, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "inverse passes");
+  return SKX_OK;
+}
+
+int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_params *p,
+                  skx_opt_result *res) {
+  if (!ctxs || nctx < 1 || !rho_devs || !p || !res) return SKX_E_INVALID;
+  skx_ctx *c0 = ctxs[0];
+  if (!c0) return SKX_E_INVALID;
+  c0->err.clear();
+  if (p->lbfgs_m < 1 || p->lbfgs_m > MMAX) return fail(c0, SKX_E_INVALID, "lbfgs_m must be in 1..8");
+  if (!(p->gtol > 0) || p->max_iter < 1) return fail(c0, SKX_E_INVALID, "gtol > 0 and max_iter >= 1 required");
+  for (int i = 0; i < nctx; ++i) {
+    if (!ctxs[i] || !rho_devs[i]) return fail(c0, SKX_E_INVALID, "null context or density");
+    if (ctxs[i]->device != c0->device) return fail(c0, SKX_E_INVALID, "all contexts must share a device");
+    if (!ctxs[i]->has_fn || ctxs[i]->fn.precision != c0->fn.precision)
+      return fail(c0, SKX_E_INVALID, "all contexts must use the same precision mode");
+  }
+  hipSetDevice(c0->device);
+  const int mode = c0->fn.precision;
+  std::vector<int> precs;
+  if (mode == SKX_FP64) precs = {0};
+  else if (mode == SKX_FP32) precs = {1};
+  else precs = {1, 0};
+  for (int i = 0; i < nctx; ++i) {
+    std::memset(&res[i], 0, sizeof(skx_opt_result));
+    for (int pr : precs) {
+      int rc = prepare(ctxs[i], pr, p->lbfgs_m);
+      if (rc) { c0->err = "solve " + std::to_string(i) + ": " + ctxs[i]->err; return rc; }
+    }
+    hipStreamSynchronize(ctxs[i]->stream);
+  }
+  hipStream_t s = c0->stream;
+  SolveDev *ddev = nullptr;
+  int *dfirst = nullptr;
+  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * 4 * (nctx + 1), s);
+  if (e != hipSuccess) return hip_fail(c0, e, "batch descriptors");
+  std::vector<OptState> outs(nctx), o32(nctx);
+  int rc = SKX_OK;
+  for (size_t ph = 0; ph < precs.size() && rc == SKX_OK; ++ph) {
+    const int pr = precs[ph];
+    const bool last = ph + 1 == precs.size();
+    const double gtol = last ? p->gtol
+                             : std::max(p->gtol, p->fp32_switch_gtol > 0 ? p->fp32_switch_gtol : 1e-5);
+    std::vector<SolveDev> hs;
+    std::vector<OptState *> states;
+    for (int i = 0; i < nctx; ++i) {
+      Instance &I = ctxs[i]->inst[pr];
+      const long long M = I.h.M;
+      int start = 0;
+      if (ph > 0) {
+        hipLaunchKernelGGL(k_f2d, dim3(blocks(M, 256)), dim3(256), 0, s,
+                           (const float *)ctxs[i]->inst[1].h.phi, (double *)I.h.phi, M);
+        start = 2;
+      } else if (p->warm_start) {
+        start = 1;
+        if (pr == 0)
+          hipLaunchKernelGGL(k_from_rho<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                             (const double *)rho_devs[i], (double *)I.h.phi, M);
+        else
+          hipLaunchKernelGGL(k_from_rho<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                             (const double *)rho_devs[i], (float *)I.h.phi, M);
+      } else {
+        const double v = std::sqrt(ctxs[i]->ne / (ctxs[i]->L * ctxs[i]->L * ctxs[i]->L));
+        if (pr == 0)
+          hipLaunchKernelGGL(k_fill<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                             (double *)I.h.phi, v, M);
+        else
+          hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                             (float *)I.h.phi, (float)v, M);
+      }
+      OptState st;
+      init_state(st, *p, gtol, start == 1 ? 1 : 0);
+      e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) { rc = hip_fail(c0, e, "state upload"); break; }
+      hs.push_back(I.h);
+      states.push_back(I.st);
+    }
+    if (rc) break;
+    BatchLaunch bl{};
+    rc = build_batch(c0, hs, pr, ddev, dfirst, bl, s);
+    if (rc) break;
+    rc = drive(c0, bl, states, (p->max_iter + 2) * 24 + 64, s);
+    if (rc) break;
+    for (int i = 0; i < nctx; ++i) {
+      OptState *dst = last ? &outs[i] : &o32[i];
+      e = hipMemcpyAsync(dst, states[i], sizeof(OptState), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) { rc = hip_fail(c0, e, "state readback"); break; }
+    }
+    if (rc) break;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rc = hip_fail(c0, e, "batch"); break; }
+  }
+  if (rc == SKX_OK) {
+    const int pr = precs.back();
+    for (int i = 0; i < nctx; ++i) {
+      Instance &I = ctxs[i]->inst[pr];
+      if (pr == 0)
+        hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                           (const double *)I.h.phi, (double *)rho_devs[i], I.h.M);
+      else
+        hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                           (const float *)I.h.phi, (double *)rho_devs[i], I.h.M);
+      const OptState &o = outs[i];
+      energy_from(o.e_acc, ctxs[i]->e_ii, &res[i].e);
+      res[i].gnorm = o.rnorm;
+      res[i].resets = o.resets;
+      if (precs.size() > 1) {
+        res[i].fp32_iters = o32[i].iters;
+        res[i].fp32_evals = o32[i].evals;
+        res[i].iters = o.iters + o32[i].iters;
+        res[i].evals = o.evals + o32[i].evals;
+      } else {
+        res[i].iters = o.iters;
+        res[i].evals = o.evals;
+        if (pr == 1) { res[i].fp32_iters = o.iters; res[i].fp32_evals = o.evals; }
+      }
+      if (o.phase == PH_FAILED && o.status < 0) res[i].status = o.status;
+      else res[i].status = (o.phase == PH_DONE && o.status == 0) ? SKX_OK : SKX_NOT_CONVERGED;
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(c0, e, "batch output");
+  }
+  hipFreeAsync(ddev, s);
+  hipFreeAsync(dfirst, s);
+  hipStreamSynchronize(s);
+  if (rc) return rc;
+  int worst = SKX_OK;
+  for (int i = 0; i < nctx; ++i)
+    if (res[i].status != SKX_OK) worst = (res[i].status < 0) ? res[i].status : (worst < 0 ? worst : SKX_NOT_CONVERGED);
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+// Device-side building blocks of libskx: complex arithmetic, the LDS
+// Stockham FFT, the Fermi-Dirac table lookup, Perdew-Zunger LDA, workgroup
+// reductions and the workgroup-to-work-item mapping.
+#pragma once
+
+#include "skx_internal.hpp"
+#include <type_traits>
+
+namespace skx {
+
+template <typename R> struct Vec2;
+template <> struct Vec2<double> { typedef double2 T; };
+template <> struct Vec2<float> { typedef float2 T; };
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+  V r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) {
+  V r; r.x = a.x * s; r.y = a.y * s; return r;
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V> __device__ __forceinline__ V cmul_mi(V a) {
+  V r;
+  if (INV) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers. Forward kernel exp(-2 pi i jk/R), inverse +.
+// ---------------------------------------------------------------------------
+template <int RAD, bool INV, typename V> struct Bfly;
+
+template <bool INV, typename V> struct Bfly<2, INV, V> {
+  __device__ __forceinline__ static void run(V *v) {
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b); v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename V> struct Bfly<3, INV, V> {
+  __device__ __forceinline__ static void run(V *v) {
+    typedef decltype(v[0].x) R;
+    const R S3 = (R)0.86602540378443864676;   // sin(2 pi / 3)
+    V a = v[0], b = v[1], c = v[2];
+    V t1 = cadd(b, c);
+    V t2; t2.x = a.x - (R)0.5 * t1.x; t2.y = a.y - (R)0.5 * t1.y;
+    V d = csub(b, c);
+    // forward: X1 = t2 - i s d, X2 = t2 + i s d
+    V sd = cmul_mi<INV>(cscale(d, S3));
+    v[0] = cadd(a, t1);
+    v[1] = cadd(t2, sd);
+    v[2] = csub(t2, sd);
+  }
+};
+
+template <bool INV, typename V> struct Bfly<4, INV, V> {
+  __device__ __forceinline__ static void run(V *v) {
+    V a = v[0], b = v[1], c = v[2], d = v[3];
+    V s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d);
+    V s3 = cmul_mi<INV>(csub(b, d));
+    v[0] = cadd(s0, s2);
+    v[1] = cadd(s1, s3);
+    v[2] = csub(s0, s2);
+    v[3] = csub(s1, s3);
+  }
+};
+
+template <bool INV, typename V> struct Bfly<5, INV, V> {
+  __device__ __forceinline__ static void run(V *v) {
+    typedef decltype(v[0].x) R;
+    const R C1 = (R)0.30901699437494742410;    // cos(2 pi/5)
+    const R C2 = (R)-0.80901699437494742410;   // cos(4 pi/5)
+    const R S1 = (R)0.95105651629515357212;    // sin(2 pi/5)
+    const R S2 = (R)0.58778525229247312917;    // sin(4 pi/5)
+    V x0 = v[0];
+    V t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    V t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    V a1; a1.x = x0.x + C1 * t1.x + C2 * t2.x; a1.y = x0.y + C1 * t1.y + C2 * t2.y;
+    V a2; a2.x = x0.x + C2 * t1.x + C1 * t2.x; a2.y = x0.y + C2 * t1.y + C1 * t2.y;
+    V b1; b1.x = S1 * t3.x + S2 * t4.x; b1.y = S1 * t3.y + S2 * t4.y;
+    V b2; b2.x = S2 * t3.x - S1 * t4.x; b2.y = S2 * t3.y - S1 * t4.y;
+    V m1 = cmul_mi<INV>(b1), m2 = cmul_mi<INV>(b2);
+    v[0] = cadd(x0, cadd(t1, t2));
+    v[1] = cadd(a1, m1);
+    v[4] = csub(a1, m1);
+    v[2] = cadd(a2, m2);
+    v[3] = csub(a2, m2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// One Stockham stage over `count` transforms of length N held in LDS.
+// Element e of transform t sits at buf[t*ts + e*es]. Butterflies are staged
+// in registers: every thread first reads all of its butterflies of a group
+// of whole transforms, the workgroup synchronises, then every thread writes
+// its results, so the stage runs in place. tw[k] = exp(-2 pi i k / N).
+// ---------------------------------------------------------------------------
+template <typename V, int RAD, int MAXB, bool INV>
+__device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int es, int ts,
+                                          const V *tw, int tid, int nthr) {
+  const int nb = N / RAD;
+  int per = (MAXB * nthr) / nb;
+  if (per < 1) per = 1;
+  const int twstep = N / (Ns * RAD);
+  for (int t0 = 0; t0 < count; t0 += per) {
+    const int t1 = (t0 + per < count) ? t0 + per : count;
+    const int gtot = (t1 - t0) * nb;
+    V v[MAXB][RAD];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int b = tid + i * nthr;
+      if (b < gtot) {
+        const int t = t0 + b / nb, j = b - (b / nb) * nb;
+        const V *base = buf + t * ts + j * es;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[i][r] = base[r * nb * es];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int b = tid + i * nthr;
+      if (b < gtot) {
+        const int t = t0 + b / nb, j = b - (b / nb) * nb;
+        const int k = j % Ns;
+        if (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < RAD; ++r) {
+            const V w = tw[k * r * twstep];
+            v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+          }
+        }
+        Bfly<RAD, INV, V>::run(v[i]);
+        V *out = buf + t * ts + ((j - k) * RAD + k) * es;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) out[r * Ns * es] = v[i][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename V, int MAXB, bool INV>
+__device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int es, int ts, const V *tw, int tid,
+                        int nthr) {
+  const int n = pl.n, nst = pl.nst;
+  const unsigned code = pl.rad;
+  int Ns = 1;
+  for (int s = 0; s < nst; ++s) {
+    const int rad = (code >> (4 * s)) & 15u;
+    switch (rad) {
+      case 4: fft_stage<V, 4, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
+      case 2: fft_stage<V, 2, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
+      case 3: fft_stage<V, 3, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
+      default: fft_stage<V, 5, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
+    }
+    Ns *= rad;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Universal Fermi-Dirac table: eta and psi = f_TF / (n T) as functions of
+// y = ln(n / n_T). Below the table the non-degenerate limit is exact to
+// double precision; above it the value is clamped and flagged.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fd_lookup(double y, const FDTable &fd, double &eta, double &psi) {
+  const double LN_G32 = -0.12078223763524522;    // ln Gamma(3/2)
+  double t = (y - fd.y0) * fd.inv_dy;
+  if (t < 0.0) { eta = y - LN_G32; psi = eta - 1.0; return 0; }
+  int sg = (int)t;
+  int bad = 0;
+  if (sg >= fd.nseg) { sg = fd.nseg - 1; bad = 1; }
+  double x = 2.0 * (t - sg) - 1.0;
+  const double *c0 = fd.coef + (size_t)sg * 2 * (fd.deg + 1);
+  const double *c1 = c0 + (fd.deg + 1);
+  double b1 = 0, b2 = 0, e1 = 0, e2 = 0;
+  for (int k = fd.deg; k >= 1; --k) {
+    double b0 = c0[k] + 2.0 * x * b1 - b2; b2 = b1; b1 = b0;
+    double a0 = c1[k] + 2.0 * x * e1 - e2; e2 = e1; e1 = a0;
+  }
+  eta = c0[0] + x * b1 - b2;
+  psi = c1[0] + x * e1 - e2;
+  return bad;
+}
+
+// Perdew-Zunger 1981 LDA (spin-unpolarised): energy per electron and
+// potential. The paper uses PZ LDA in the adiabatic approximation.
+__device__ __forceinline__ void pz81(double n, double &eps, double &v) {
+  if (!(n > 0.0)) { eps = 0.0; v = 0.0; return; }
+  const double PI = 3.14159265358979323846;
+  const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
+  double rs = cbrt(3.0 / (4.0 * PI * n));
+  double ex = -CX / rs;
+  double ec, vc;
+  if (rs >= 1.0) {
+    const double G = -0.1423, B1 = 1.0529, B2 = 0.3334;
+    double sq = sqrt(rs);
+    double den = 1.0 + B1 * sq + B2 * rs;
+    ec = G / den;
+    vc = G * (1.0 + (7.0 / 6.0) * B1 * sq + (4.0 / 3.0) * B2 * rs) / (den * den);
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    double lr = log(rs);
+    ec = A * lr + B + C * rs * lr + D * rs;
+    vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + (2.0 * D - C) * rs / 3.0;
+  }
+  eps = ex + ec;
+  v = (4.0 / 3.0) * ex + vc;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions and work mapping
+// ---------------------------------------------------------------------------
+// Workgroup sum of N values per thread: wavefront shuffles, then one lane
+// per wavefront through LDS, summed in a fixed order (deterministic).
+// sh must hold N * (nthr / 64) doubles. The totals land in out[0..N) of
+// thread 0 only.
+template <int N>
+__device__ __forceinline__ void block_reduce(double (&vals)[N], double *sh, int tid, int nthr,
+                                             double *out) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double v = vals[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    vals[q] = v;
+  }
+  const int lane = tid & 63, wid = tid >> 6, nw = nthr >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) sh[wid * N + q] = vals[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double acc = 0.0;
+      for (int w = 0; w < nw; ++w) acc += sh[w * N + q];
+      out[q] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give every XCD one contiguous range of work items so neighbouring
+// items (the fields of one plane, adjacent planes) share an L2. Blocks
+// b = x, x+8, x+16, ... land on XCD x; there are q + (x < r) of them for
+// grid = 8q + r, and they take the items [x q + min(x, r), ...): a bijection
+// of [0, grid).
+__device__ __forceinline__ int xcd_item(int b, int grid) {
+  const int NX = 8;
+  const int q = grid / NX, r = grid - q * NX;
+  const int x = b % NX;
+  return x * q + (x < r ? x : r) + b / NX;
+}
+
+__device__ __forceinline__ int find_solve(const int *first, int nsolve, int item) {
+  int lo = 0, hi = nsolve;     // first[lo] <= item < first[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (first[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int gidx(int m, int n) { return (2 * m < n) ? m : m - n; }
+
+}  // namespace skx

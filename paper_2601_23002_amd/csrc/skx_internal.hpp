@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP translation units of libskx.
+// Not part of the public C ABI (include/skx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace skx {
+
+constexpr int MMAX = 8;            // largest L-BFGS memory supported
+constexpr int NFIELD = 4;          // transformed fields: phi, n, f, h
+constexpr int MAX_STAGES = 8;      // FFT stages per axis
+constexpr int PART_A = 4;          // pass A partial sums: f_tf, e_xc, nelec, nonfinite
+constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinite
+constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
+constexpr int NDOT = 8 * MMAX + 8; // update-pass dot products
+constexpr int CHUNK = 4096;        // grid points per workgroup in the vector passes
+
+// Which transformed fields are present (slot order phi, n, f, h).
+enum FieldBits { F_PHI = 1, F_N = 2, F_F = 4, F_H = 8 };
+
+// Optimiser phases of one solve; every kernel of the fixed step sequence
+// checks the phase and skips solves it has nothing to do for.
+enum Phase { PH_IDLE = 0, PH_EVAL_INIT = 1, PH_TRIAL = 2, PH_UPDATE = 3,
+             PH_NEED_DIR = 4, PH_DONE = 5, PH_FAILED = 6, PH_EVAL_ONLY = 7 };
+
+struct Plan {                      // 1D FFT plan for one axis length
+  int n;
+  int nst;
+  unsigned rad;                    // radix of stage s in bits [4s, 4s+4)
+  int tw;                          // offset of exp(-2 pi i k / n) in the twiddle bank
+};
+
+// Control state of one solve (device resident, FP64).
+struct OptState {
+  int phase, iters, evals, trials, k, head, status, resets;
+  int m, max_iter, max_trials, reset_pending;
+  int pair_ok, nonfinite, pad0, pad1;
+  double gtol, c1, theta_max, tolE_rel;
+  double E, Et, mu, mut, rnorm, theta, g0, dnorm, rd;
+  double gamma, cr, cphi;
+  double cS[MMAX], cY[MMAX];
+  double SY[MMAX][MMAX], YY[MMAX][MMAX];
+  double Sr[MMAX], Yr[MMAX], Sphi[MMAX], Yphi[MMAX];
+  double rr, rphi;
+  int order[MMAX];                 // ring slot of the i-th oldest pair
+  double e_acc[12];                // energy terms at the accepted point
+  double e_trial[12];              // energy terms at the last evaluation
+};
+
+// Energy slots used in e_acc / e_trial
+enum ESlot { E_TF = 0, E_VW, E_NL0, E_NL1, E_H, E_LOC, E_XC, E_NELEC, E_FREE, E_MU, E_NONFINITE, E_SPARE };
+
+// Per-solve descriptor (device resident, POD).
+struct SolveDev {
+  int n1, n2, n3, nh, pitch;
+  int fields, nf;                  // FieldBits mask and count
+  int slot[NFIELD];                // spectrum slot of phi, n, f, h (-1 if absent)
+  int nkb, tk;                     // pass-B column blocks and their width
+  int nwg_vec;                     // workgroups of the vector passes
+  int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
+  unsigned terms;
+  long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
+  double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
+  Plan p1, p2, p3;
+  void *phi, *phit, *grad, *r, *d, *S, *Y;   // real fields (fp64 or fp32)
+  void *spec, *vloc;                         // complex spectra
+  const double *w, *wp;                      // shell tables
+  double *partA, *partB, *partC, *partU, *partD;
+  OptState *st;
+};
+
+struct FDTable {                   // Chebyshev segments of eta(y), psi(y), y = ln(n/n_T)
+  double y0, inv_dy, dy;
+  int nseg, deg;
+  const double *coef;              // [nseg][2][deg+1]
+};
+
+// ---- launch wrappers (defined in the .hip files) ----
+hipError_t build_twiddles(double *bank_dev, const int *sizes, const int *offsets, int nsizes,
+                          hipStream_t s);
+hipError_t build_fd_table(double *coef_dev, double y0, double dy, int nseg, int deg,
+                          hipStream_t s);
+hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double n0, double T,
+                               double a, const FDTable &fd, double *eta0_out, hipStream_t s);
+hipError_t build_vloc(void *vloc, int prec, int n1, int n2, int n3, int pitch, double L,
+                      int nions, const double *pos_dev, const int *species_dev,
+                      int nspecies, const double *zval_dev, const double *rc_dev,
+                      double2 *phase_scratch, hipStream_t s);
+hipError_t ewald_energy(double L, int nions, const double *pos_dev, const double *charge_dev,
+                        double *scratch_dev, int scratch_len, double *out_dev, hipStream_t s);
+hipError_t debug_fd_eval(const double *u_dev, double *eta_dev, double *psi_dev, long long n,
+                         const FDTable &fd, hipStream_t s);
+
+// The fixed step sequence over a batch of solves (defined in skx_passes.hip)
+struct BatchLaunch {
+  SolveDev *dev;                   // device array of descriptors
+  int nsolve;
+  int prec;                        // 0 fp64, 1 fp32
+  const double *twbank;
+  FDTable fd;
+  int gridA, gridB, gridC, gridV;  // total workgroups per kernel
+  const int *firstA, *firstB, *firstC, *firstV;  // device prefix sums (nsolve+1)
+  size_t ldsA, ldsB, ldsC;
+  int accC_lds;                    // pass C accumulates in LDS (else in the output)
+};
+hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);  // passes A|B|C
+hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_opt_update(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_opt_dir(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_normalize(const BatchLaunch &b, hipStream_t s);     // scale phi to N_e
+
+}  // namespace skx

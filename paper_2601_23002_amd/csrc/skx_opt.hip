@@ -1,0 +1,487 @@
+// Density optimisation of libskx: reductions that close each evaluation,
+// and the compact limited-memory BFGS on sqrt(n) with the electron-count
+// constraint, driven by a per-solve state machine so that a batch of solves
+// advances with one fixed kernel sequence (no host decision per step).
+//
+// The paper minimises the free energy at fixed electron number ("SCF
+// iterations", Methods, Table A caption) without naming the algorithm.
+// Reading used here: L-BFGS on the sphere int phi^2 = N_e,
+//   r = dE/dphi - 2 mu phi,  mu = int phi dE/dphi / (2 N_e),
+//   d = -H r (compact representation of the last m pairs, H0 = gamma I),
+//   d <- d + kappa phi with kappa making d tangent to the sphere,
+//   phi(t) = cos(t) phi + sin(t) sqrt(N_e) d/|d|,
+//   t0 = min(|d|/sqrt(N_e), t_max), backtracking Armijo with quadratic
+//   interpolation, rounding-level energy changes accepted.
+// The compact form H r = gamma r + S a - gamma Y p with p = R^-1 S^T r,
+// a = R^-T ((D + gamma Y^T Y) p - gamma Y^T r), R = upper(S^T Y),
+// D = diag(S^T Y), is the same operator as the two-loop recursion.
+#include "skx_device.hpp"
+#include <math.h>
+
+namespace skx {
+
+template <int N>
+__device__ void sum_parts(const double *part, int nrow, double *sh, int tid, int nthr,
+                          double *out) {
+  double v[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = 0.0;
+  for (int r = tid; r < nrow; r += nthr)
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += part[r * N + q];
+  block_reduce<N>(v, sh, tid, nthr, out);
+}
+
+__device__ void set_steepest(OptState *st) {
+  st->k = 0;
+  st->head = 0;
+  st->gamma = 1.0;
+  st->cr = -1.0;
+  for (int i = 0; i < MMAX; ++i) { st->cS[i] = 0.0; st->cY[i] = 0.0; }
+}
+
+// ---------------------------------------------------------------------------
+// Close an evaluation: energies, mu, and the line-search decision.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve) {
+  __shared__ double sh[4 * 16];
+  __shared__ double tA[PART_A], tB[PART_B], tC[PART_C];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  const int ph = st->phase;
+  if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
+  const int tid = threadIdx.x;
+  sum_parts<PART_A>(S.partA, S.n1, sh, tid, 256, tA);
+  sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
+  sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
+  if (tid != 0) return;
+  const double PI = 3.14159265358979323846;
+  double e[12];
+  e[E_TF] = S.dV * tA[0];
+  e[E_XC] = S.dV * tA[1];
+  e[E_NELEC] = S.dV * tA[2];
+  e[E_VW] = 0.5 * S.V * tB[0];
+  e[E_H] = 0.5 * S.V * 4.0 * PI * tB[1];
+  e[E_NL0] = S.V * tB[2];
+  e[E_NL1] = S.beta * S.V / 3.0 * tB[3];
+  e[E_LOC] = S.V * tB[4];
+  e[E_FREE] = e[E_TF] + e[E_VW] + e[E_NL0] + e[E_NL1] + e[E_H] + e[E_LOC] + e[E_XC];
+  e[E_MU] = S.dV * tC[0] / (2.0 * S.ne);
+  const double bad = tA[3] + tB[5] + tC[1];
+  const bool finite = (bad == 0.0) && (e[E_FREE] == e[E_FREE]) && fabs(e[E_FREE]) < 1e300;
+  e[E_NONFINITE] = finite ? 0.0 : 1.0;
+  e[E_SPARE] = 0.0;
+  for (int q = 0; q < 12; ++q) st->e_trial[q] = e[q];
+  st->evals += 1;
+  if (ph == PH_EVAL_ONLY) { st->phase = PH_IDLE; return; }
+  if (ph == PH_EVAL_INIT) {
+    if (!finite) { st->phase = PH_FAILED; st->status = -5; return; }
+    st->Et = e[E_FREE];
+    st->mut = e[E_MU];
+    st->phase = PH_UPDATE;
+    return;
+  }
+  // trial point of the line search
+  const double Et = e[E_FREE];
+  const double tolE = st->tolE_rel * fmax(1.0, fabs(st->E));
+  if (finite && Et <= st->E + st->c1 * st->theta * st->g0 + tolE) {
+    st->Et = Et;
+    st->mut = e[E_MU];
+    st->phase = PH_UPDATE;
+    return;
+  }
+  st->trials += 1;
+  if (!finite) {
+    st->theta *= 0.1;
+  } else {
+    const double den = 2.0 * (Et - st->E - st->g0 * st->theta);
+    double tn = (den > 0.0) ? -st->g0 * st->theta * st->theta / den : 0.5 * st->theta;
+    tn = fmin(fmax(tn, 0.1 * st->theta), 0.5 * st->theta);
+    st->theta = tn;
+  }
+  if (st->trials >= st->max_trials) {
+    if (st->k > 0) {
+      set_steepest(st);
+      st->cphi = st->rphi / S.ne;
+      st->resets += 1;
+      st->trials = 0;
+      st->phase = PH_NEED_DIR;
+    } else {
+      st->phase = PH_FAILED;
+      st->status = finite ? 1 : -5;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update pass: r_t, the new pair (s, y), and every inner product the compact
+// L-BFGS needs, in one sweep over the history.
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
+                                               int grid) {
+  __shared__ double sh[NDOT * (NT / 64)];
+  __shared__ double tot[NDOT];
+  const int item = blockIdx.x;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (st->phase != PH_UPDATE) return;
+  const int tid = threadIdx.x;
+  const int wl = item - first[s];
+  const long long g0 = (long long)wl * CHUNK;
+  const long long g1 = min((long long)S.M, g0 + CHUNK);
+  R *phi = reinterpret_cast<R *>(S.phi);
+  const R *phit = reinterpret_cast<const R *>(S.phit);
+  const R *grad = reinterpret_cast<const R *>(S.grad);
+  R *r = reinterpret_cast<R *>(S.r);
+  R *Sv = reinterpret_cast<R *>(S.S);
+  R *Yv = reinterpret_cast<R *>(S.Y);
+  const R mu2 = (R)(2.0 * st->mut);
+  double acc[NDOT];
+#pragma unroll
+  for (int q = 0; q < NDOT; ++q) acc[q] = 0.0;
+  // acc layout: [0..MMAX) sy_i, [MMAX..2MMAX) yy_i, sphi_i, yphi_i, sr_i, yr_i,
+  // then 6*MMAX + {0 sy, 1 yy, 2 sphi, 3 yphi, 4 sr, 5 yr, 6 rr, 7 rphi}
+  const int B = 6 * MMAX;
+  if (st->k == 0 && st->iters == 0 && st->reset_pending == 1) {
+    // first accepted point: residual only
+    for (long long g = g0 + tid; g < g1; g += NT) {
+      const R pt = phit[g];
+      const R rt = grad[g] - mu2 * pt;
+      r[g] = rt;
+      phi[g] = pt;
+      acc[B + 6] += (double)rt * rt;
+      acc[B + 7] += (double)rt * pt;
+    }
+  } else {
+    const int m = st->m, k = st->k, head = st->head;
+    const int kold = (k == m) ? m - 1 : k;
+    int slot[MMAX];
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) slot[i] = (i < kold) ? ((head - kold + i + 2 * m) % m) : 0;
+    R *Snew = Sv + (size_t)head * S.M;
+    R *Ynew = Yv + (size_t)head * S.M;
+    for (long long g = g0 + tid; g < g1; g += NT) {
+      const R pt = phit[g];
+      const R rt = grad[g] - mu2 * pt;
+      const R sv = pt - phi[g];
+      const R yv = rt - r[g];
+#pragma unroll
+      for (int i = 0; i < MMAX; ++i) {
+        if (i < kold) {
+          const double Si = (double)Sv[(size_t)slot[i] * S.M + g];
+          const double Yi = (double)Yv[(size_t)slot[i] * S.M + g];
+          acc[i] += Si * yv;
+          acc[MMAX + i] += Yi * yv;
+          acc[2 * MMAX + i] += Si * pt;
+          acc[3 * MMAX + i] += Yi * pt;
+          acc[4 * MMAX + i] += Si * rt;
+          acc[5 * MMAX + i] += Yi * rt;
+        }
+      }
+      acc[B + 0] += (double)sv * yv;
+      acc[B + 1] += (double)yv * yv;
+      acc[B + 2] += (double)sv * pt;
+      acc[B + 3] += (double)yv * pt;
+      acc[B + 4] += (double)sv * rt;
+      acc[B + 5] += (double)yv * rt;
+      acc[B + 6] += (double)rt * rt;
+      acc[B + 7] += (double)rt * pt;
+      Snew[g] = sv;
+      Ynew[g] = yv;
+      r[g] = rt;
+      phi[g] = pt;
+    }
+  }
+  block_reduce<NDOT>(acc, sh, tid, NT, tot);
+  if (tid == 0)
+    for (int q = 0; q < NDOT; ++q) S.partU[wl * NDOT + q] = tot[q];
+}
+
+__global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsolve) {
+  __shared__ double sh[NDOT * 4];
+  __shared__ double t[NDOT];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_UPDATE) return;
+  const int tid = threadIdx.x;
+  sum_parts<NDOT>(S.partU, S.nwg_vec, sh, tid, 256, t);
+  if (tid != 0) return;
+  const double dV = S.dV;
+  const int B = 6 * MMAX;
+  const int m = st->m;
+  for (int q = 0; q < NDOT; ++q) t[q] *= dV;
+  st->E = st->Et;
+  st->mu = st->mut;
+  for (int q = 0; q < 12; ++q) st->e_acc[q] = st->e_trial[q];
+  if (st->reset_pending == 1) {
+    st->reset_pending = 0;
+    set_steepest(st);
+  } else {
+    st->iters += 1;
+    int k = st->k;
+    if (k == m) {
+      // the oldest pair's memory now holds the new pair: drop it
+      for (int i = 0; i + 1 < k; ++i)
+        for (int j = 0; j + 1 < k; ++j) {
+          st->SY[i][j] = st->SY[i + 1][j + 1];
+          st->YY[i][j] = st->YY[i + 1][j + 1];
+        }
+      k = m - 1;
+    }
+    for (int i = 0; i < k; ++i) {
+      st->Sphi[i] = t[2 * MMAX + i];
+      st->Yphi[i] = t[3 * MMAX + i];
+      st->Sr[i] = t[4 * MMAX + i];
+      st->Yr[i] = t[5 * MMAX + i];
+    }
+    const double sy = t[B + 0], yy = t[B + 1];
+    const bool ok = (sy > 0.0) && (yy > 0.0) && (sy == sy) && (yy == yy);
+    if (ok) {
+      for (int i = 0; i < k; ++i) {
+        st->SY[i][k] = t[i];
+        st->SY[k][i] = 0.0;            // only the upper triangle is used
+        st->YY[i][k] = t[MMAX + i];
+        st->YY[k][i] = t[MMAX + i];
+      }
+      st->SY[k][k] = sy;
+      st->YY[k][k] = yy;
+      st->Sphi[k] = t[B + 2];
+      st->Yphi[k] = t[B + 3];
+      st->Sr[k] = t[B + 4];
+      st->Yr[k] = t[B + 5];
+      k += 1;
+      st->head = (st->head + 1) % m;
+    }
+    st->k = k;
+    st->pair_ok = ok ? 1 : 0;
+  }
+  st->rr = t[B + 6];
+  st->rphi = t[B + 7];
+  st->rnorm = sqrt(fmax(st->rr, 0.0));
+  if (!(st->rnorm == st->rnorm)) { st->phase = PH_FAILED; st->status = -5; return; }
+  if (st->rnorm < st->gtol) { st->phase = PH_DONE; st->status = 0; return; }
+  if (st->iters >= st->max_iter) { st->phase = PH_DONE; st->status = 1; return; }
+  // compact L-BFGS coefficients
+  const int k = st->k;
+  double gamma = 1.0;
+  if (k > 0) gamma = st->SY[k - 1][k - 1] / st->YY[k - 1][k - 1];
+  double p[MMAX], z[MMAX], a[MMAX];
+  for (int i = k - 1; i >= 0; --i) {
+    double v = st->Sr[i];
+    for (int j = i + 1; j < k; ++j) v -= st->SY[i][j] * p[j];
+    p[i] = v / st->SY[i][i];
+  }
+  for (int i = 0; i < k; ++i) {
+    double v = st->SY[i][i] * p[i] - gamma * st->Yr[i];
+    for (int j = 0; j < k; ++j) v += gamma * st->YY[i][j] * p[j];
+    z[i] = v;
+  }
+  for (int i = 0; i < k; ++i) {
+    double v = z[i];
+    for (int j = 0; j < i; ++j) v -= st->SY[j][i] * a[j];
+    a[i] = v / st->SY[i][i];
+  }
+  double dphi = -gamma * st->rphi;
+  double rd = -gamma * st->rr;
+  for (int i = 0; i < k; ++i) {
+    dphi += -a[i] * st->Sphi[i] + gamma * p[i] * st->Yphi[i];
+    rd += -a[i] * st->Sr[i] + gamma * p[i] * st->Yr[i];
+  }
+  const double kappa = -dphi / S.ne;
+  rd += kappa * st->rphi;
+  if (!(rd < 0.0)) {
+    set_steepest(st);
+    st->cphi = st->rphi / S.ne;
+    st->resets += (k > 0) ? 1 : 0;
+  } else {
+    st->gamma = gamma;
+    st->cr = -gamma;
+    for (int i = 0; i < MMAX; ++i) {
+      st->cS[i] = (i < k) ? -a[i] : 0.0;
+      st->cY[i] = (i < k) ? gamma * p[i] : 0.0;
+    }
+    st->cphi = kappa;
+  }
+  st->phase = PH_NEED_DIR;
+}
+
+// ---------------------------------------------------------------------------
+// Direction pass: d = cr r + sum cS_i s_i + sum cY_i y_i + cphi phi, |d|^2, r.d
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int nsolve, int grid) {
+  __shared__ double sh[2 * (NT / 64)];
+  __shared__ double tot[2];
+  const int item = blockIdx.x;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (st->phase != PH_NEED_DIR) return;
+  const int tid = threadIdx.x;
+  const int wl = item - first[s];
+  const long long g0 = (long long)wl * CHUNK;
+  const long long g1 = min((long long)S.M, g0 + CHUNK);
+  const R *phi = reinterpret_cast<const R *>(S.phi);
+  const R *r = reinterpret_cast<const R *>(S.r);
+  const R *Sv = reinterpret_cast<const R *>(S.S);
+  const R *Yv = reinterpret_cast<const R *>(S.Y);
+  R *d = reinterpret_cast<R *>(S.d);
+  const int m = st->m, k = st->k, head = st->head;
+  int slot[MMAX];
+  R cS[MMAX], cY[MMAX];
+#pragma unroll
+  for (int i = 0; i < MMAX; ++i) {
+    slot[i] = (i < k) ? ((head - k + i + 2 * m) % m) : 0;
+    cS[i] = (R)st->cS[i];
+    cY[i] = (R)st->cY[i];
+  }
+  const R cr = (R)st->cr, cphi = (R)st->cphi;
+  double dd = 0.0, rd = 0.0;
+  for (long long g = g0 + tid; g < g1; g += NT) {
+    const R rv = r[g];
+    R v = cr * rv + cphi * phi[g];
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+      if (i < k) v += cS[i] * Sv[(size_t)slot[i] * S.M + g] + cY[i] * Yv[(size_t)slot[i] * S.M + g];
+    }
+    d[g] = v;
+    dd += (double)v * v;
+    rd += (double)rv * v;
+  }
+  double acc[2] = {dd, rd};
+  block_reduce<2>(acc, sh, tid, NT, tot);
+  if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve) {
+  __shared__ double sh[2 * 4];
+  __shared__ double t[2];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_NEED_DIR) return;
+  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
+  if (threadIdx.x != 0) return;
+  const double dd = S.dV * t[0], rd = S.dV * t[1];
+  const double dn = sqrt(fmax(dd, 0.0));
+  if (!(rd < 0.0) || !(dn > 0.0)) {
+    if (st->k > 0) {
+      set_steepest(st);
+      st->cphi = st->rphi / S.ne;
+      st->resets += 1;
+      return;                       // stays in NEED_DIR: steepest descent next
+    }
+    st->phase = PH_FAILED;
+    st->status = 1;
+    return;
+  }
+  st->dnorm = dn;
+  st->rd = rd;
+  st->theta = fmin(dn * S.inv_sqrt_ne, st->theta_max);
+  st->g0 = rd / dn * S.sqrt_ne;
+  st->trials = 0;
+  st->phase = PH_TRIAL;
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation of the starting point: phi <- phi sqrt(N_e / int phi^2).
+// With from_rho, the input buffer holds a density and phi = sqrt(max(rho,0)).
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, int nsolve, int grid) {
+  __shared__ double sh[2 * (NT / 64)];
+  __shared__ double tot[2];
+  const int item = blockIdx.x;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (st->phase != PH_EVAL_INIT) return;
+  const int tid = threadIdx.x;
+  const int wl = item - first[s];
+  const long long g0 = (long long)wl * CHUNK;
+  const long long g1 = min((long long)S.M, g0 + CHUNK);
+  R *phi = reinterpret_cast<R *>(S.phi);
+  const bool from_rho = st->reset_pending == 2;
+  double ss = 0.0, bad = 0.0;
+  for (long long g = g0 + tid; g < g1; g += NT) {
+    R v = phi[g];
+    if (from_rho) {
+      v = v > (R)0 ? sqrt(v) : (R)0;
+      phi[g] = v;
+    }
+    if (!(v == v)) bad += 1.0;
+    ss += (double)v * v;
+  }
+  double acc[2] = {ss, bad};
+  block_reduce<2>(acc, sh, tid, NT, tot);
+  if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_norm(SolveDev *dev, int nsolve) {
+  __shared__ double sh[2 * 4];
+  __shared__ double t[2];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_EVAL_INIT) return;
+  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
+  if (threadIdx.x != 0) return;
+  const double nrm = S.dV * t[0];
+  if (t[1] != 0.0 || !(nrm > 0.0) || !(nrm < 1e300)) {
+    st->phase = PH_FAILED;
+    st->status = -5;
+    return;
+  }
+  st->theta = sqrt(S.ne / nrm);
+  st->reset_pending = 1;             // the first update only forms the residual
+}
+
+// ---------------------------------------------------------------------------
+template <typename R>
+static hipError_t launch_update_t(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<R, 256>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV,
+                     b.nsolve, b.gridV);
+  hipLaunchKernelGGL(k_finalize_update, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_dir_t(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL((k_dir<R, 256>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV, b.nsolve,
+                     b.gridV);
+  hipLaunchKernelGGL(k_finalize_dir, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_norm_t(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL((k_norm<R, 256>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV, b.nsolve,
+                     b.gridV);
+  hipLaunchKernelGGL(k_finalize_norm, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_eval, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  return hipGetLastError();
+}
+
+hipError_t launch_opt_update(const BatchLaunch &b, hipStream_t s) {
+  return b.prec == 0 ? launch_update_t<double>(b, s) : launch_update_t<float>(b, s);
+}
+hipError_t launch_opt_dir(const BatchLaunch &b, hipStream_t s) {
+  return b.prec == 0 ? launch_dir_t<double>(b, s) : launch_dir_t<float>(b, s);
+}
+hipError_t launch_normalize(const BatchLaunch &b, hipStream_t s) {
+  return b.prec == 0 ? launch_norm_t<double>(b, s) : launch_norm_t<float>(b, s);
+}
+
+}  // namespace skx

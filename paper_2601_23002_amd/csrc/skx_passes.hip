@@ -1,0 +1,496 @@
+// The functional evaluation of libskx as three fused passes over a batch of
+// solves, plus the reductions that close each pass.
+//
+//   pass A  real space, one workgroup per (solve, x-plane, field):
+//           trial point phi_t = cos(t) phi + sqrt(N_e) sin(t) d/|d|, the
+//           pointwise fields phi, n = phi^2, f = n^a, h = (f - n0^a)(n - n0),
+//           the local energy densities (finite-T TF through the Fermi-Dirac
+//           table, PZ LDA), then the real-to-complex z transform and the y
+//           transform of the plane in LDS.
+//   pass B  reciprocal space, one workgroup per (solve, y index, z block):
+//           x transform of the column block, every G-space energy term and
+//           the four reciprocal multipliers, inverse x transform.
+//   pass C  real space, one workgroup per (solve, x-plane): inverse y and
+//           complex-to-real z transforms of the four outputs, assembled with
+//           their pointwise coefficients into dE/dphi in registers.
+//
+// Energy terms (paper Eq. (1), Eq. (2); readings as stated in include/skx.h):
+//   F_TF = dV sum f_TF(n),   F_vW = (V/2) sum G^2 |phi~|^2,
+//   F0 = V sum w |f~|^2,     F1 = (V/3) sum w' Re(f~ h~*),
+//   E_H = (V/2) sum' 4 pi |n~|^2 / G^2,  E_loc = V sum Re(n~ V_loc*),
+//   E_xc = dV sum n eps_xc(n).
+// dE/dphi = A + 2 phi [B + T eta + v_xc] + c_P P + c_Q Q with
+//   A = G^2 phi~, B = 4 pi n~/G^2 + V_loc, P = 2 w f~ + (beta/3) w' h~,
+//   Q = (beta/3) w' f~, c_P = 2 a sign(phi)|phi|^(2a-1),
+//   c_Q = c_P (n - n0) + 2 phi (f - n0^a).
+#include "skx_device.hpp"
+#include <math.h>
+
+namespace skx {
+
+constexpr int MAXB_A = 2;
+constexpr int MAXB_C = 2;
+
+template <typename R> __device__ __forceinline__ R rpow(R x, R a);
+template <> __device__ __forceinline__ double rpow(double x, double a) { return pow(x, a); }
+template <> __device__ __forceinline__ float rpow(float x, float a) { return powf(x, a); }
+
+__device__ __forceinline__ int nth_field(int mask, int c) {
+  // bit index of the c-th set bit of mask (slot order phi, n, f, h)
+  for (int b = 0; b < NFIELD; ++b)
+    if (mask & (1 << b)) { if (c == 0) return b; --c; }
+  return -1;
+}
+
+template <typename V>
+__device__ __forceinline__ void load_twiddles(V *dst, const double *bank, int off, int n, int tid,
+                                              int nthr) {
+  const double2 *src = reinterpret_cast<const double2 *>(bank) + off;
+  for (int k = tid; k < n; k += nthr) {
+    double2 t = src[k];
+    V v; v.x = t.x; v.y = t.y;
+    dst[k] = v;
+  }
+}
+
+// Trial-point coefficients: phi_t = ca phi + cb d.
+__device__ __forceinline__ void trial_coef(const OptState *st, const SolveDev &S, double &ca,
+                                           double &cb, bool &use_d) {
+  int ph = st->phase;
+  if (ph == PH_TRIAL) {
+    double sn, cs;
+    sincos(st->theta, &sn, &cs);
+    ca = cs;
+    cb = S.sqrt_ne * sn / st->dnorm;
+    use_d = true;
+  } else {
+    ca = (ph == PH_EVAL_INIT) ? st->theta : 1.0;   // theta holds the normalising scale
+    cb = 0.0;
+    use_d = false;
+  }
+}
+
+__device__ __forceinline__ bool eval_phase(int ph) {
+  return ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY;
+}
+
+// ---------------------------------------------------------------------------
+// Pass A
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, int nsolve,
+                                              int grid, const double *twbank, FDTable fd) {
+  typedef typename Vec2<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (!eval_phase(st->phase)) return;
+  const int tid = threadIdx.x;
+  const int local = item - first[s];
+  const int plane = local / S.nf, c = local % S.nf;
+  const int fb = nth_field(S.fields, c);
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh;
+  const int pl = nh;                         // LDS row pitch (complex)
+  V *buf = reinterpret_cast<V *>(smem);
+  V *tw2 = buf + n2 * pl;
+  V *tw3 = tw2 + n2;
+  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
+
+  double ca, cb;
+  bool use_d;
+  trial_coef(st, S, ca, cb, use_d);
+  const R *phi = reinterpret_cast<const R *>(S.phi);
+  const R *dd = reinterpret_cast<const R *>(S.d);
+  R *phit = reinterpret_cast<R *>(S.phit);
+  const R invM = (R)(1.0 / (double)S.M);
+  const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
+  const bool energies = (c == 0);
+  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+  double e_tf = 0.0, e_xc = 0.0, nel = 0.0, bad = 0.0;
+  const size_t pbase = (size_t)plane * n2 * n3;
+  const int np = n2 * n3;
+  for (int e = tid; e < np; e += NT) {
+    const int j = e / n3, k = e - j * n3;
+    const size_t g = pbase + e;
+    R ph;
+    if (use_d) ph = (R)(ca * (double)phi[g] + cb * (double)dd[g]);
+    else ph = (R)(ca * (double)phi[g]);
+    if (c == 0) phit[g] = ph;
+    const R n = ph * ph;
+    R x;
+    if (fb == 0) x = ph;
+    else if (fb == 1) x = n;
+    else {
+      const R f = rpow(n, a);
+      x = (fb == 2) ? f : (f - n0a) * (n - n0);
+    }
+    if (energies) {
+      const double nd = (double)n;
+      if (!(nd == nd) || nd > 1e300) bad += 1.0;
+      if (nd > 0.0) {
+        nel += nd;
+        if (do_tf) {
+          double eta, psi;
+          bad += fd_lookup(log(nd) - S.lnnT, fd, eta, psi);
+          e_tf += S.T * nd * psi;
+        }
+        if (do_xc) {
+          double eps, v;
+          pz81(nd, eps, v);
+          e_xc += nd * eps;
+        }
+      }
+    }
+    R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
+    slot[j & 1] = x * invM;
+  }
+  __syncthreads();
+  // real-to-complex along z: pairs of rows as one complex row of length n3
+  fft_lds<V, MAXB_A, false>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
+  {
+    const int nk = n3 / 2 + 1;
+    int per = (MAXB_A * NT) / nk;
+    if (per < 1) per = 1;
+    for (int p0 = 0; p0 < n2 / 2; p0 += per) {
+      const int p1 = min(n2 / 2, p0 + per);
+      const int tot = (p1 - p0) * nk;
+      V A[MAXB_A], B[MAXB_A];
+#pragma unroll
+      for (int i = 0; i < MAXB_A; ++i) {
+        const int e = tid + i * NT;
+        if (e < tot) {
+          const int p = p0 + e / nk, k = e % nk;
+          const V X = buf[p * 2 * pl + k];
+          const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
+          A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
+          B[i].x = (R)0.5 * (X.y + Xm.y); B[i].y = (R)-0.5 * (X.x - Xm.x);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < MAXB_A; ++i) {
+        const int e = tid + i * NT;
+        if (e < tot) {
+          const int p = p0 + e / nk, k = e % nk;
+          buf[(2 * p) * pl + k] = A[i];
+          buf[(2 * p + 1) * pl + k] = B[i];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // complex transform along y for every z column
+  fft_lds<V, MAXB_A, false>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  V *spec = reinterpret_cast<V *>(S.spec) + (size_t)S.slot[fb] * S.H;
+  const size_t obase = (size_t)plane * n2 * S.pitch;
+  for (int e = tid; e < n2 * nh; e += NT) {
+    const int j = e / nh, k = e - j * nh;
+    spec[obase + (size_t)j * S.pitch + k] = buf[j * pl + k];
+  }
+  if (energies) {
+    double v[PART_A] = {e_tf, e_xc, nel, bad};
+    double tot[PART_A];
+    __syncthreads();
+    block_reduce<PART_A>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+    if (tid == 0)
+      for (int q = 0; q < PART_A; ++q) S.partA[plane * PART_A + q] = tot[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B
+// ---------------------------------------------------------------------------
+template <typename R, int NT, int TK>
+__global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, int nsolve,
+                                              int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (!eval_phase(st->phase)) return;
+  const int tid = threadIdx.x;
+  const int local = item - first[s];
+  const int j = local / S.nkb, kb = local % S.nkb;
+  const int k0 = kb * TK;
+  const int n1 = S.n1, nf = S.nf, W = nf * TK;
+  V *tile = reinterpret_cast<V *>(smem);
+  V *tw1 = tile + n1 * W;
+  load_twiddles(tw1, twbank, S.p1.tw, n1, tid, NT);
+  V *spec = reinterpret_cast<V *>(S.spec);
+  const size_t rowstride = (size_t)S.n2 * S.pitch;
+  for (int e = tid; e < n1 * W; e += NT) {
+    const int i = e / W, r = e - i * W;
+    const int cc = r / TK, kk = r - cc * TK;
+    tile[e] = spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk];
+  }
+  __syncthreads();
+  if (S.debug != 2) fft_lds<V, 4, false>(tile, S.p1, W, W, 1, tw1, tid, NT);
+  if (S.debug == 1) {
+    for (int e = tid; e < n1 * W; e += NT) {
+      const int i = e / W, r = e - i * W;
+      const int cc = r / TK, kk = r - cc * TK;
+      if (k0 + kk < S.nh)
+        spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] = tile[e];
+    }
+    return;
+  }
+
+  const unsigned terms = S.terms;
+  const bool do_vw = terms & 2u, do_nl0 = terms & 4u, do_nl1 = (terms & 8u) && S.beta != 0.0;
+  const bool do_h = terms & 16u, do_loc = terms & 32u;
+  const int sphi = S.slot[0], sn = S.slot[1], sf = S.slot[2], sh = S.slot[3];
+  const V *vloc = reinterpret_cast<const V *>(S.vloc);
+  const double kscale = S.kscale;
+  const R b3 = (R)(S.beta / 3.0);
+  const int g2 = gidx(j, S.n2);
+  double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
+  const double FOURPI = 12.566370614359172954;
+  for (int e = tid; e < n1 * TK; e += NT) {
+    const int i = e / TK, kk = e - i * TK;
+    const int k3 = k0 + kk;
+    if (k3 >= S.nh || S.debug) continue;
+    const int g1 = gidx(i, n1);
+    const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+    const double G2 = kscale * (double)sidx;
+    const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
+    V *row = tile + i * W;
+    if (sphi >= 0) {
+      V x = row[sphi * TK + kk];
+      if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
+      const R g2r = (R)G2;
+      x.x *= g2r; x.y *= g2r;
+      row[sphi * TK + kk] = x;
+    }
+    {
+      const V x = row[sn * TK + kk];
+      const size_t vi = ((size_t)i * S.n2 + j) * S.pitch + k3;
+      double bx = 0.0, by = 0.0;
+      if (do_h && sidx > 0) {
+        const double m2 = (double)x.x * x.x + (double)x.y * x.y;
+        eh += wgt * m2 / G2;
+        bx = FOURPI * x.x / G2;
+        by = FOURPI * x.y / G2;
+      }
+      if (do_loc) {
+        const V vl = vloc[vi];
+        eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
+        bx += vl.x;
+        by += vl.y;
+      }
+      if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
+      V o; o.x = (R)bx; o.y = (R)by;
+      row[sn * TK + kk] = o;
+    }
+    if (sf >= 0) {
+      const V f = row[sf * TK + kk];
+      const R w = (R)S.w[sidx];
+      const R wp = (R)S.wp[sidx];
+      V P; P.x = 0; P.y = 0;
+      if (do_nl0) {
+        ef0 += wgt * (double)w * ((double)f.x * f.x + (double)f.y * f.y);
+        P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
+      }
+      if (sh >= 0) {
+        const V h = row[sh * TK + kk];
+        ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
+        P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
+        V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
+        row[sh * TK + kk] = Q;
+      }
+      row[sf * TK + kk] = P;
+    }
+  }
+  (void)do_nl1;
+  __syncthreads();
+  fft_lds<V, 4, true>(tile, S.p1, W, W, 1, tw1, tid, NT);
+  for (int e = tid; e < n1 * W; e += NT) {
+    const int i = e / W, r = e - i * W;
+    const int cc = r / TK, kk = r - cc * TK;
+    if (k0 + kk < S.nh)
+      spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] = tile[e];
+  }
+  double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
+  double tot[PART_B];
+  __syncthreads();
+  block_reduce<PART_B>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+  if (tid == 0)
+    for (int q = 0; q < PART_B; ++q) S.partB[local * PART_B + q] = tot[q];
+}
+
+// ---------------------------------------------------------------------------
+// Pass C
+//
+// dE/dphi is accumulated field by field, either in LDS beside the plane
+// (ACC_LDS, when both fit) or in the output buffer itself, whose plane the
+// workgroup revisits while it is still in L2.
+// ---------------------------------------------------------------------------
+template <typename R, int NT, bool ACC_LDS>
+__global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, int nsolve,
+                                              int grid, const double *twbank, FDTable fd) {
+  typedef typename Vec2<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const OptState *st = S.st;
+  if (!eval_phase(st->phase)) return;
+  const int tid = threadIdx.x;
+  const int plane = item - first[s];
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh;
+  const int pl = nh;
+  V *buf = reinterpret_cast<V *>(smem);
+  V *tw2 = buf + n2 * pl;
+  V *tw3 = tw2 + n2;
+  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
+  const R *phit = reinterpret_cast<const R *>(S.phit);
+  R *grad = reinterpret_cast<R *>(S.grad);
+  const size_t pbase = (size_t)plane * n2 * n3;
+  const int np = n2 * n3;
+  R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : grad + pbase;
+  const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
+  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+  for (int e = tid; e < np; e += NT) {
+    R v0 = 0;
+    if (!S.debug) {
+      const R p = phit[pbase + e];
+      const double nd = (double)p * (double)p;
+      double v = 0.0;
+      if (nd > 0.0) {
+        if (do_tf) { double eta, psi; fd_lookup(log(nd) - S.lnnT, fd, eta, psi); v += S.T * eta; }
+        if (do_xc) { double eps, vx; pz81(nd, eps, vx); v += vx; }
+      }
+      v0 = (R)(2.0 * (double)p * v);
+    }
+    acc[e] = v0;
+  }
+  const V *spec = reinterpret_cast<const V *>(S.spec);
+  const size_t ibase = (size_t)plane * n2 * S.pitch;
+  for (int fb = 0; fb < NFIELD; ++fb) {
+    const int sl = S.slot[fb];
+    if (sl < 0 || (S.debug && fb != 0)) continue;
+    const V *src = spec + (size_t)sl * S.H + ibase;
+    __syncthreads();
+    for (int e = tid; e < n2 * nh; e += NT) {
+      const int j = e / nh, k = e - j * nh;
+      buf[j * pl + k] = src[(size_t)j * S.pitch + k];
+    }
+    __syncthreads();
+    fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+    // complex-to-real along z, two rows at a time: X = A + i B over the full
+    // row, A and B Hermitian-extended; the planes k = 0 and k = n3/2 keep
+    // only their real parts (real part of the plane-wave sum)
+    {
+      int per = (MAXB_C * 2 * NT) / n3;
+      if (per < 1) per = 1;
+      for (int p0 = 0; p0 < n2 / 2; p0 += per) {
+        const int p1 = min(n2 / 2, p0 + per);
+        const int tot = (p1 - p0) * n3;
+        V X[MAXB_C * 2];
+#pragma unroll
+        for (int i = 0; i < MAXB_C * 2; ++i) {
+          const int e = tid + i * NT;
+          if (e < tot) {
+            const int p = p0 + e / n3, k = e % n3;
+            V Av, Bv;
+            if (2 * k <= n3) {
+              Av = buf[(2 * p) * pl + k];
+              Bv = buf[(2 * p + 1) * pl + k];
+              if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
+            } else {
+              Av = buf[(2 * p) * pl + n3 - k];
+              Bv = buf[(2 * p + 1) * pl + n3 - k];
+              Av.y = -Av.y; Bv.y = -Bv.y;
+            }
+            X[i].x = Av.x - Bv.y;
+            X[i].y = Av.y + Bv.x;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXB_C * 2; ++i) {
+          const int e = tid + i * NT;
+          if (e < tot) {
+            const int p = p0 + e / n3, k = e % n3;
+            buf[p * 2 * pl + k] = X[i];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    fft_lds<V, MAXB_C, true>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
+    for (int e = tid; e < np; e += NT) {
+      const int j = e / n3, k = e - j * n3;
+      const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
+      const R val = cv[j & 1];
+      R coef;
+      if (fb == 0) {
+        coef = (R)1;
+      } else {
+        const R p = phit[pbase + e];
+        if (fb == 1) {
+          coef = (R)2 * p;
+        } else {
+          const R ap = p < 0 ? -p : p;
+          const R pw = (ap > 0) ? rpow(ap, (R)2 * a - (R)1) : (R)0;
+          const R cP = (R)2 * a * (p < 0 ? -pw : pw);
+          if (fb == 2) coef = cP;
+          else coef = cP * (p * p - n0) + (R)2 * p * (ap * pw - n0a);
+        }
+      }
+      acc[e] += coef * val;
+    }
+  }
+  __syncthreads();
+  double sphig = 0.0, bad = 0.0;
+  for (int e = tid; e < np; e += NT) {
+    const R g = acc[e];
+    if (ACC_LDS) grad[pbase + e] = g;
+    sphig += (double)phit[pbase + e] * (double)g;
+    if (!(g == g)) bad += 1.0;
+  }
+  double v[PART_C] = {sphig, bad};
+  double tot[PART_C];
+  __syncthreads();
+  block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+  if (tid == 0)
+    for (int q = 0; q < PART_C; ++q) S.partC[plane * PART_C + q] = tot[q];
+}
+
+// ---------------------------------------------------------------------------
+// Launch
+// ---------------------------------------------------------------------------
+template <typename R>
+static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
+  if (b.gridA > 0 && (mask & 1))
+    hipLaunchKernelGGL((k_passA<R, 256>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev, b.firstA,
+                       b.nsolve, b.gridA, b.twbank, b.fd);
+  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
+  constexpr int NTC = 512;
+  if (b.gridB > 0 && (mask & 2))
+    hipLaunchKernelGGL((k_passB<R, 256, TK>), dim3(b.gridB), dim3(256), b.ldsB, s, b.dev,
+                       b.firstB, b.nsolve, b.gridB, b.twbank);
+  if (b.gridC > 0 && (mask & 4)) {
+    if (b.accC_lds)
+      hipLaunchKernelGGL((k_passC<R, NTC, true>), dim3(b.gridC), dim3(NTC), b.ldsC, s, b.dev,
+                         b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+    else
+      hipLaunchKernelGGL((k_passC<R, NTC, false>), dim3(b.gridC), dim3(NTC), b.ldsC, s, b.dev,
+                         b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask) {
+  return b.prec == 0 ? launch_eval_t<double>(b, s, mask) : launch_eval_t<float>(b, s, mask);
+}
+
+}  // namespace skx

@@ -1,0 +1,283 @@
+"""Thin Python binding of libskx (include/skx.h) over ctypes.
+
+Argument marshalling only: every step of the evaluation and of the
+optimisation runs in the library's HIP kernels. PyTorch supplies device
+memory and the stream. If the shared library is missing, importing this
+module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+# torch first: its HIP runtime must be the one the library binds to (both
+# carry the soname libamdhip64.so.7), so device pointers and streams are
+# shared between the two
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libskx.so not built ({LIB_PATH}); run paper_2601_23002_amd/build.py")
+_lib = C.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC = -1, -2, -3, -4, -5
+TERM_TF, TERM_VW, TERM_NL0, TERM_NL1, TERM_HARTREE, TERM_LOCPP, TERM_XC = 1, 2, 4, 8, 16, 32, 64
+TERM_ALL = 127
+XC_NONE, XC_PZ81 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
+RHO, SQRT_RHO = 0, 1
+
+
+class SkxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"skx error {code}: {msg}")
+        self.code = code
+
+
+class Functional(C.Structure):
+    _fields_ = [("T", C.c_double), ("beta", C.c_double), ("alpha", C.c_double),
+                ("terms", C.c_uint), ("xc", C.c_int), ("precision", C.c_int)]
+
+
+class Energy(C.Structure):
+    _fields_ = [(k, C.c_double) for k in (
+        "f_tf", "e_vw", "f_nl0", "f_nl1", "e_h", "e_loc", "e_xc", "e_ii",
+        "free_energy", "total", "mu", "nelec")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class OptParams(C.Structure):
+    _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int), ("lbfgs_m", C.c_int),
+                ("fp32_switch_gtol", C.c_double), ("warm_start", C.c_int)]
+
+
+class OptResult(C.Structure):
+    _fields_ = [("e", Energy), ("iters", C.c_int), ("evals", C.c_int),
+                ("fp32_iters", C.c_int), ("fp32_evals", C.c_int), ("gnorm", C.c_double),
+                ("status", C.c_int), ("resets", C.c_int)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "e"}
+        d["energy"] = self.e.as_dict()
+        return d
+
+
+class Request(C.Structure):
+    _fields_ = [("lattice", C.c_double * 9), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
+                ("nions", C.c_int), ("pos", C.POINTER(C.c_double)),
+                ("species", C.POINTER(C.c_int)), ("nspecies", C.c_int),
+                ("zval", C.POINTER(C.c_double)), ("rc", C.POINTER(C.c_double)),
+                ("fn", Functional), ("opt", OptParams), ("t_arrival", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("r", OptResult), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("npoints", C.c_longlong)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_VP = C.c_void_p
+_sig("skx_create", C.c_int, [C.POINTER(_VP), C.c_int, _VP])
+_sig("skx_destroy", None, [_VP])
+_sig("skx_last_error", C.c_char_p, [_VP])
+_sig("skx_set_cell", C.c_int, [_VP, C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int])
+_sig("skx_set_ions", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)])
+_sig("skx_set_functional", C.c_int, [_VP, C.POINTER(Functional)])
+_sig("skx_evaluate_energy_potential", C.c_int, [_VP, _VP, C.c_int, _VP, C.POINTER(Energy)])
+_sig("skx_optimize_density", C.c_int, [_VP, _VP, C.POINTER(OptParams), C.POINTER(OptResult)])
+_sig("skx_run_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(OptParams),
+                                C.POINTER(OptResult)])
+_sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
+_sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
+_sig("skx_num_shells", C.c_int, [_VP])
+_sig("skx_fd_eval", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.c_longlong])
+_sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)])
+_sig("skx_engine_create", C.c_int, [C.POINTER(_VP), C.c_int, C.c_size_t, C.c_int])
+_sig("skx_engine_submit", C.c_int, [_VP, C.POINTER(Request), C.POINTER(C.c_uint64)])
+_sig("skx_engine_step", C.c_int, [_VP])
+_sig("skx_engine_poll", C.c_int, [_VP, C.POINTER(Result), C.POINTER(C.POINTER(C.c_double)),
+                                  C.c_int, C.POINTER(C.c_int)])
+_sig("skx_engine_pending", C.c_int, [_VP])
+_sig("skx_engine_destroy", None, [_VP])
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """One solve: cell, ions, functional and its device state."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libskx needs a GPU")
+        self.device = device
+        h = _VP()
+        s = stream if stream is not None else _stream_handle(device)
+        rc = _lib.skx_create(C.byref(h), device, _VP(s))
+        if rc != OK:
+            raise SkxError(rc, "skx_create failed")
+        self._h = h
+        self.n = None
+        self.L = None
+        self.precision = FP64
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.skx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise SkxError(rc, _lib.skx_last_error(self._h).decode())
+        return rc
+
+    def set_cell(self, L: float, n):
+        n = tuple(int(x) for x in (n if hasattr(n, "__len__") else (n, n, n)))
+        lat = (C.c_double * 9)(L, 0, 0, 0, L, 0, 0, 0, L)
+        self._check(_lib.skx_set_cell(self._h, lat, *n))
+        self.n, self.L = n, float(L)
+
+    def set_ions(self, pos, zval, rc, species=None):
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        zval = np.asarray(zval, dtype=np.float64).reshape(-1)
+        rc = np.asarray(rc, dtype=np.float64).reshape(-1)
+        if species is None:
+            # one species per distinct (Z, rc) pair
+            keys = list(zip(zval.tolist(), rc.tolist())) if zval.size == len(pos) else None
+            if keys is None:
+                raise ValueError("give species, or per-ion zval and rc")
+            uniq = sorted(set(keys))
+            species = np.array([uniq.index(k) for k in keys], dtype=np.int32)
+            zsp = np.array([u[0] for u in uniq])
+            rsp = np.array([u[1] for u in uniq])
+        else:
+            species = np.asarray(species, dtype=np.int32)
+            zsp, rsp = zval, rc
+        zsp = np.ascontiguousarray(zsp, dtype=np.float64)
+        rsp = np.ascontiguousarray(rsp, dtype=np.float64)
+        species = np.ascontiguousarray(species, dtype=np.int32)
+        self._check(_lib.skx_set_ions(self._h, len(pos), _dptr(pos),
+                                      species.ctypes.data_as(C.POINTER(C.c_int)), len(zsp),
+                                      _dptr(zsp), _dptr(rsp)))
+
+    def set_functional(self, T, beta=1.0, alpha=5.0 / 6.0, terms=TERM_ALL, xc=XC_PZ81,
+                       precision=FP64):
+        fn = Functional(T, beta, alpha, terms, xc, precision)
+        self._check(_lib.skx_set_functional(self._h, C.byref(fn)))
+        self.precision = precision
+
+    def setup(self, sys, precision=FP64):
+        """Configure from a workloads.System."""
+        self.set_cell(sys.L, sys.n)
+        self.set_ions(sys.pos, sys.zval, sys.rc)
+        self.set_functional(sys.T, sys.beta, sys.alpha, sys.terms, XC_PZ81, precision)
+        return self
+
+    def evaluate(self, field, kind=SQRT_RHO, want_grad=True):
+        """Energies (dict) and dE/dphi (tensor or None) for a device field."""
+        torch = _torch()
+        dt = torch.float32 if self.precision == FP32 else torch.float64
+        if field.dtype != dt or not field.is_cuda or not field.is_contiguous():
+            raise ValueError(f"field must be a contiguous {dt} CUDA tensor")
+        out = torch.empty_like(field) if want_grad else None
+        e = Energy()
+        self._check(_lib.skx_evaluate_energy_potential(
+            self._h, _VP(field.data_ptr()), kind, _VP(out.data_ptr()) if out is not None else None,
+            C.byref(e)))
+        return e.as_dict(), out
+
+    def optimize(self, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, rho0=None):
+        torch = _torch()
+        if rho0 is not None:
+            rho = rho0.to(dtype=torch.float64).contiguous().clone()
+            warm = 1
+        else:
+            rho = torch.empty(self.n, dtype=torch.float64, device=f"cuda:{self.device}")
+            warm = 0
+        p = OptParams(gtol, max_iter, m, fp32_switch_gtol, warm)
+        r = OptResult()
+        rc = _lib.skx_optimize_density(self._h, _VP(rho.data_ptr()), C.byref(p), C.byref(r))
+        self._check(rc)
+        return rho, r.as_dict()
+
+    def kernel_tables(self):
+        ns = _lib.skx_num_shells(self._h)
+        w = np.zeros(ns)
+        wp = np.zeros(ns)
+        self._check(_lib.skx_get_kernel_tables(self._h, _dptr(w), _dptr(wp), ns))
+        return w, wp
+
+    def vloc(self):
+        n1, n2, n3 = self.n
+        out = np.zeros((n1, n2, n3 // 2 + 1, 2))
+        self._check(_lib.skx_get_vloc(self._h, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def fft_check(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros_like(x)
+        n1, n2, n3 = x.shape
+        spec = np.zeros((n1, n2, n3 // 2 + 1, 2))
+        self._check(_lib.skx_fft_check(self._h, _dptr(x), _dptr(out), _dptr(spec)))
+        return out, spec[..., 0] + 1j * spec[..., 1]
+
+
+def fd_eval(u, device=0):
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    eta = np.zeros_like(u)
+    psi = np.zeros_like(u)
+    rc = _lib.skx_fd_eval(device, _dptr(u), _dptr(eta), _dptr(psi), u.size)
+    if rc != OK:
+        raise SkxError(rc, "skx_fd_eval failed")
+    return eta, psi
+
+
+def run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, warm=False):
+    n = len(ctxs)
+    hs = (_VP * n)(*[c._h for c in ctxs])
+    ptrs = (_VP * n)(*[r.data_ptr() for r in rhos])
+    p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1 if warm else 0)
+    res = (OptResult * n)()
+    rc = _lib.skx_run_batch(hs, n, ptrs, C.byref(p), res)
+    if rc < 0:
+        raise SkxError(rc, _lib.skx_last_error(ctxs[0]._h).decode())
+    return [r.as_dict() for r in res]
+
+
+def exported_symbols():
+    """Names of the functions this binding expects the library to export."""
+    return [n for n in dir(_lib) if n.startswith("skx_")]

@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Every GPU result is compared element by element with the oracle on the same
+seeded inputs. FP64 tolerance: 1e-10 relative on every energy term (the
+target stated for the FP64 path); potentials are compared against the
+largest magnitude of the field, for the same reason.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_23002_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("f_tf", "e_vw", "f_nl0", "f_nl1", "e_h", "e_loc", "e_xc")
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2601_23002_amd import skx
+    return skx, torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ----------------------------------------------------------------------------
+def test_fd_table_matches_oracle_inversion():
+    skx, _ = _lib()
+    from oracle import fermi
+    _say("case: fd table")
+    u = np.exp(np.linspace(-45.0, 15.5, 2001))
+    eta, psi = skx.fd_eval(u)
+    eta_ref = fermi.eta_from_ratio(u)
+    i32 = fermi.fd_integrals(eta_ref, (1.5,))[0]
+    psi_ref = eta_ref - (2.0 / 3.0) * i32 / u
+    assert np.max(np.abs(eta - eta_ref) / np.maximum(1.0, np.abs(eta_ref))) < 1e-13
+    assert np.max(np.abs(psi - psi_ref) / np.maximum(1.0, np.abs(psi_ref))) < 1e-13
+    # below the table: non-degenerate limit
+    u2 = np.array([1e-25, 1e-30])
+    e2, _ = skx.fd_eval(u2)
+    assert np.max(np.abs(e2 - fermi.eta_from_ratio(u2))) < 1e-12
+
+
+@pytest.mark.parametrize("n", [8, 12, 24, 30, 32, 48])
+def test_fft_matches_oracle(n):
+    skx, torch = _lib()
+    from oracle.fft import fft3
+    _say(f"case: fft n={n}")
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n, n, n))
+    c = skx.Context(0)
+    c.set_cell(7.0, (n, n, n))
+    out, spec = c.fft_check(x)
+    ref = fft3(x)[:, :, : n // 2 + 1]
+    assert np.max(np.abs(spec - ref)) < 1e-15 * max(1.0, np.max(np.abs(ref))) * 20
+    assert np.max(np.abs(out - x)) < 1e-13 * np.max(np.abs(x))
+
+
+def test_fft_nonsquare_grid():
+    skx, torch = _lib()
+    from oracle.fft import fft3
+    _say("case: fft 16x24x20")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((16, 24, 20))
+    c = skx.Context(0)
+    c.set_cell(7.0, (16, 24, 20))
+    out, spec = c.fft_check(x)
+    ref = fft3(x)[:, :, :11]
+    assert np.max(np.abs(spec - ref)) < 1e-14
+    assert np.max(np.abs(out - x)) < 1e-13 * np.max(np.abs(x))
+
+
+def _system(n, seed=3, nions=6, Z=1.0, rc=0.4, rs=2.0, T=1.0, beta=1.3, terms=W.TERM_ALL):
+    return W.uniform_system(nions, Z, rc, rs, T, n, seed=seed, beta=beta, terms=terms)
+
+
+def test_kernel_tables_match_oracle():
+    skx, torch = _lib()
+    from oracle import kernel
+    for (n, T, a) in ((16, 1.0, 5 / 6), (24, 0.5, 5 / 6), (16, 8.0, 1.0)):
+        _say(f"case: tables n={n} T={T}")
+        s = _system(n, T=T)
+        s.alpha = a
+        c = skx.Context(0).setup(s)
+        w, wp = c.kernel_tables()
+        n0 = s.nelec / s.volume
+        w_ref, wp_ref = kernel.shell_tables(s.L, s.n, n0, T, a)
+        assert np.max(np.abs(w - w_ref)) < 1e-11 * np.max(np.abs(w_ref))
+        assert np.max(np.abs(wp - wp_ref)) < 1e-9 * np.max(np.abs(wp_ref))
+
+
+def test_vloc_and_ewald_match_oracle():
+    skx, torch = _lib()
+    from oracle import ions
+    s = W.uniform_system(7, 1.0, 0.35, 1.5, 1.0, 24, seed=9)
+    # a second species
+    s.zval[2:4] = 4.0
+    s.rc[2:4] = 0.5
+    _say("case: vloc n=24")
+    c = skx.Context(0).setup(s)
+    v = c.vloc()
+    ref = ions.vloc_spectrum(s.L, s.n, s.pos, s.zval, s.rc)[:, :, :13]
+    assert np.max(np.abs(v - ref)) < 1e-14 * max(1.0, np.max(np.abs(ref))) * 10
+    e, _ = c.evaluate(torch.ones(s.n, dtype=torch.float64, device="cuda"), skx.SQRT_RHO, False)
+    assert abs(e["e_ii"] - ions.ewald(s.L, s.pos, s.zval)) < 1e-11 * abs(e["e_ii"])
+
+
+def _compare_eval(s, seed, tol=1e-10, prec=None):
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    p = Problem(s)
+    phi = W.random_phi(s, seed, amp=0.4)
+    e_ref, g_ref = p.evaluate(phi)
+    c = skx.Context(0).setup(s, precision=skx.FP64 if prec is None else prec)
+    dt = torch.float32 if prec == skx.FP32 else torch.float64
+    t = torch.tensor(phi, dtype=dt, device="cuda")
+    e, g = c.evaluate(t, skx.SQRT_RHO)
+    g = g.double().cpu().numpy()
+    scale = sum(abs(e_ref[k]) for k in TERMS)
+    for k in TERMS:
+        ref = e_ref[k]
+        assert abs(e[k] - ref) <= tol * max(abs(ref), 1e-3 * scale), (k, e[k], ref)
+    assert abs(e["free_energy"] - e_ref["free_energy"]) <= tol * scale
+    assert abs(e["mu"] - e_ref["mu"]) <= tol * max(1.0, abs(e_ref["mu"])) * 10
+    assert np.max(np.abs(g - g_ref)) <= tol * np.max(np.abs(g_ref)) * 10
+    return e, e_ref
+
+
+@pytest.mark.parametrize("n", [12, 16, 24, 30, 32])
+def test_evaluate_matches_oracle_fp64(n):
+    _say(f"case: evaluate fp64 n={n}")
+    _compare_eval(_system(n, seed=n), seed=n + 100)
+
+
+def test_evaluate_config_single_small_fp64():
+    _say("case: evaluate fp64 16 H rs=2 T=1 32^3")
+    _compare_eval(W.config_single_small(32), seed=7)
+
+
+@pytest.mark.parametrize("mask", [W.TERM_TF, W.TERM_VW, W.TERM_NL0, W.TERM_NL1,
+                                  W.TERM_HARTREE, W.TERM_LOCPP, W.TERM_XC,
+                                  W.TERM_TF | W.TERM_VW | W.TERM_NL0])
+def test_evaluate_single_terms(mask):
+    _say(f"case: evaluate terms={mask}")
+    _compare_eval(_system(16, seed=2, terms=mask), seed=4)
+
+
+def test_evaluate_beryllium_like_mixed_species():
+    s = W.uniform_system(8, 4.0, 0.5, 1.5, 4.0, 24, seed=11)
+    s.zval[:3] = 1.0
+    s.rc[:3] = 0.3
+    _say("case: evaluate mixed species")
+    _compare_eval(s, seed=12)
+
+
+def test_evaluate_fp32_within_single_precision():
+    skx, _ = _lib()
+    _say("case: evaluate fp32 n=24")
+    _compare_eval(_system(24, seed=5), seed=6, tol=2e-5, prec=skx.FP32)
+
+
+def test_evaluate_rejects_nonfinite():
+    skx, torch = _lib()
+    s = _system(16)
+    c = skx.Context(0).setup(s)
+    x = torch.ones(s.n, dtype=torch.float64, device="cuda")
+    x[3, 4, 5] = float("nan")
+    with pytest.raises(skx.SkxError) as ei:
+        c.evaluate(x, skx.SQRT_RHO)
+    assert ei.value.code == skx.E_NUMERIC
+
+
+def test_evaluate_rho_input_equals_sqrt_input():
+    skx, torch = _lib()
+    s = _system(16, seed=8)
+    c = skx.Context(0).setup(s)
+    phi = torch.tensor(W.random_phi(s, 3), dtype=torch.float64, device="cuda")
+    e1, g1 = c.evaluate(phi, skx.SQRT_RHO)
+    e2, g2 = c.evaluate(phi * phi, skx.RHO)
+    assert abs(e1["free_energy"] - e2["free_energy"]) < 1e-13 * abs(e1["free_energy"])
+
+
+def test_optimize_matches_oracle_small():
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    from oracle.optimize import optimize
+    s = _system(12, seed=41, beta=1.0)
+    _say("case: optimize fp64 n=12")
+    ref = optimize(Problem(s), gtol=1e-9, max_iter=400)
+    c = skx.Context(0).setup(s)
+    rho, r = c.optimize(gtol=1e-9, max_iter=400)
+    assert r["status"] == skx.OK, r
+    E, Eref = r["energy"]["free_energy"], ref["energy"]["free_energy"]
+    assert abs(E - Eref) < 1e-10 * abs(Eref)
+    n = rho.cpu().numpy()
+    dV = s.volume / s.M
+    assert dV * np.sum(np.abs(n - ref["n"])) / s.nelec < 1e-6
+    assert abs(dV * n.sum() - s.nelec) < 1e-12 * s.nelec
