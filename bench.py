@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the batched mixed-precision OFDFT solve on one MI355X.
+
+One step = one batched solve, through the C-ABI library, of the scan
+workload: 9 independent systems of 64 Z=1 ions (erf pseudopotential,
+rc = 0.3 bohr) at rs in {1,2,4} bohr x T in {0.5,2,8} Ha on 64^3 grids,
+uniform random positions (seeds 2..10). Every step runs every hot-path row:
+structure factor and kernel tables (set-up of each solve), then the
+optimiser with its fused FFT/functional evaluations, FP32 until
+||r|| < 1e-5 and FP64 refinement to ||r|| < 1e-8.
+
+Metric: grid-point functional evaluations per second,
+sum over solves of (evaluations x grid points) / wall time of the step.
+The plain FP64 GPU path is timed on the same workload for the speedup,
+and the mixed results are checked against it per solve (Ha/atom).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--gtol", type=float, default=1e-8)
+    return ap.parse_args()
+
+
+def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
+    """Algorithmic HBM bytes of one evaluation of passes A, B, C for one solve."""
+    n1, n2, n3 = sys_.n
+    M = n1 * n2 * n3
+    Hh = n1 * n2 * (n3 // 2 + 1)          # half-spectrum complex entries
+    b = prec_bytes
+    spec = 2 * b * Hh                     # one half spectrum
+    a = (2 if phase_trial else 1) * b * M + b * M + nf * spec
+    bb = 2 * nf * spec + (spec if with_loc else 0)
+    c = nf * spec + 2 * b * M
+    return a, bb, c
+
+
+def fields_count(sys_):
+    nf = 1                                # density always
+    if sys_.terms & 2:
+        nf += 1
+    if sys_.terms & (4 | 8):
+        nf += 1
+    if (sys_.terms & 8) and sys_.beta != 0:
+        nf += 1
+    return nf
+
+
+def cpu_baseline(sys_, seed=5):
+    """The oracle as it stands, one FP64 evaluation of one 64^3 system."""
+    from threadpoolctl import threadpool_limits
+    from paper_2601_23002_amd import workloads as W
+    from oracle.functional import Problem
+    with threadpool_limits(limits=1):
+        p = Problem(sys_)
+        phi = W.random_phi(sys_, seed)
+        t0 = time.perf_counter()
+        p.evaluate(phi)
+        dt = time.perf_counter() - t0
+    return dict(value=sys_.M / dt, unit="grid-pt evals/s", cores=1, kind="oracle",
+                sample=f"one FP64 evaluation (all terms, energy + dE/dphi) of one {sys_.n[0]}^3 "
+                       f"scan system, single thread, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2601_23002_amd import skx
+    from paper_2601_23002_amd import workloads as W
+
+    systems = W.config_scan(64)
+    dev = torch.device("cuda:0")
+
+    def make(prec):
+        ctxs = [skx.Context(0).setup(s, precision=prec) for s in systems]
+        rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
+        return ctxs, rhos
+
+    def step(ctxs, rhos):
+        return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=3000, m=5,
+                             fp32_switch_gtol=1e-5)
+
+    def work(res):
+        return sum(r["evals"] * s.M for r, s in zip(res, systems))
+
+    # ---- plain FP64 GPU path (speedup denominator and accuracy reference)
+    fp64 = None
+    if not args.no_fp64:
+        print("fp64 reference solves", file=sys.stderr, flush=True)
+        c64, r64 = make(skx.FP64)
+        step(c64, r64)                            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res64 = step(c64, r64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        fp64 = dict(value=work(res64) / t64, seconds=t64,
+                    E=[r["energy"]["free_energy"] for r in res64],
+                    rho=[r.cpu().numpy() for r in r64],
+                    iters=[r["iters"] for r in res64])
+        for c in c64:
+            c.close()
+
+    # ---- batched mixed precision (the headline)
+    ctxs, rhos = make(skx.MIXED)
+    for _ in range(args.warmup):
+        step(ctxs, rhos)
+    torch.cuda.synchronize()
+    skx.profile_reset()
+    skx.profile_enable(True)
+    total_work = 0
+    evals = {"fp32": 0, "fp64": 0}
+    bytes_pass = {"passA": 0.0, "passB": 0.0, "passC": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = None
+    for it in range(args.steps):
+        results = step(ctxs, rhos)
+        print(f"step {it}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+        total_work += work(results)
+        for r, s in zip(results, systems):
+            nf = fields_count(s)
+            e32, e64 = r["fp32_evals"], r["evals"] - r["fp32_evals"]
+            evals["fp32"] += e32
+            evals["fp64"] += e64
+            for (ne, b) in ((e32, 4), (e64, 8)):
+                if ne <= 0:
+                    continue
+                a1, b1, c1 = pass_bytes(s, b, nf, True, False)    # first evaluation
+                aT, bT, cT = pass_bytes(s, b, nf, True, True)     # trial evaluations
+                bytes_pass["passA"] += a1 + (ne - 1) * aT
+                bytes_pass["passB"] += b1 + (ne - 1) * bT
+                bytes_pass["passC"] += c1 + (ne - 1) * cT
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    skx.profile_enable(False)
+    prof = skx.profile_read()
+    value = total_work / wall
+
+    # roofline of the dominant evaluation kernel
+    dom = max(("passA", "passB", "passC"), key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    avg_s = ms / 1e3 / max(1, launches)
+    achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "bytes_per_launch": round(bytes_pass[dom] / max(1, launches))}
+
+    out = {
+        "metric": "grid-pt functional evals/s, batched+mixed vs plain FP64 @1e-6 Ha/atom; p99 lat",
+        "value": value,
+        "unit": "grid-pt evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "scan: 9 solves, 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha, "
+                               "64^3, batched, FP32 to |r|<1e-5 then FP64 to |r|<%g" % args.gtol,
+                   "global_batch": len(systems), "grid": 64, "parallelism": "batch"},
+        "roofline": roof,
+        "passes_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "evals": evals,
+    }
+    if fp64 is not None:
+        err = []
+        rerr = []
+        for i, (r, s) in enumerate(zip(results, systems)):
+            err.append(abs(r["energy"]["free_energy"] - fp64["E"][i]) / len(s.zval))
+            n_m = rhos[i].cpu().numpy()
+            rerr.append(float(np.sum(np.abs(n_m - fp64["rho"][i])) / np.sum(fp64["rho"][i])))
+        out["fp64_value"] = fp64["value"]
+        out["speedup_vs_fp64"] = value / fp64["value"]
+        out["max_err_ha_per_atom"] = max(err)
+        out["max_rel_density_err"] = max(rerr)
+        out["iters_fp64"] = fp64["iters"]
+    out["iters_mixed"] = [r["iters"] for r in results]
+    out["status"] = [r["status"] for r in results]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(systems[0])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -7,9 +7,13 @@ algorithm. Reading: limited-memory BFGS on the sphere int phi^2 = N_e.
 
   r      = dE/dphi - 2 mu phi,  mu = int phi dE/dphi / (2 N_e)
   d      = -H r by the two-loop recursion over the last m pairs (s, y),
-           H0 = gamma I with gamma = s.y / y.y of the newest pair
+           H0 = gamma P with P(G) = 1/(G^2 + kappa) applied through the
+           plane-wave expansion (kinetic preconditioner; kappa = 4 n0
+           dmu0/dn, the Thomas-Fermi curvature in phi of the uniform gas)
+           and gamma = s.y / y.P y of the newest pair (gamma = 1 without
+           history)
   d     <- d - (int d phi / N_e) phi        (tangent to the sphere)
-           reset to d = -r (and drop the history) if d is not descent
+           reset to d = -P r (and drop the history) if d is not descent
   phi(t) = phi cos t + sqrt(N_e) d^ sin t,  d^ = d / ||d||
   t0     = min(||d|| / sqrt(N_e), t_max); backtracking Armijo in t with
            quadratic interpolation, accepting rounding-level energy
@@ -25,14 +29,26 @@ import math
 
 import numpy as np
 
+from . import kernel
+from .fft import fft3, ifft3
+
 STATUS_OK, STATUS_NOT_CONVERGED = 0, 1
+
+
+def make_preconditioner(prob):
+    """P(G) = 1/(G^2 + kappa) as a function on grid fields."""
+    _, dmudn = kernel.uniform_gas(prob.n0, prob.T)
+    kappa = max(4.0 * prob.n0 * dmudn, 1e-3)
+    mult = 1.0 / (prob.G2 + kappa)
+    return lambda x: np.real(ifft3(mult * fft3(x)))
 
 
 def optimize(prob, phi0=None, gtol: float = 1e-8, max_iter: int = 1000,
              m: int = 5, c1: float = 1e-4, theta_max: float = 0.5,
-             max_trials: int = 20, verbose: bool = False):
+             max_trials: int = 20, precondition: bool = True, verbose: bool = False):
     ne = prob.ne
     dot = prob.dot
+    P = make_preconditioner(prob) if precondition else (lambda x: x)
     if phi0 is None:
         phi = np.full(prob.n, math.sqrt(prob.n0))
     else:
@@ -58,15 +74,16 @@ def optimize(prob, phi0=None, gtol: float = 1e-8, max_iter: int = 1000,
             a_ = rho * dot(s, q)
             q -= a_ * y
             al.append((a_, rho))
-        gamma = dot(S[-1], Y[-1]) / dot(Y[-1], Y[-1]) if S else 1.0
-        z = gamma * q
+        gamma = dot(S[-1], Y[-1]) / dot(Y[-1], P(Y[-1])) if S else 1.0
+        z = gamma * P(q)
         for (s, y), (a_, rho) in zip(zip(S, Y), reversed(al)):
             b = rho * dot(y, z)
             z += (a_ - b) * s
         d = -z
         d -= (dot(d, phi) / ne) * phi
         if dot(r, d) >= 0.0:
-            d = -r.copy()
+            d = -P(r)
+            d -= (dot(d, phi) / ne) * phi
             S, Y = [], []
         dnorm = math.sqrt(dot(d, d))
         dh = d / dnorm

@@ -137,6 +137,7 @@ struct skx_ctx {
   double *w = nullptr, *wp = nullptr;
   int smax = 0;
   bool tables_ok = false;
+  double kappa = 1.0;              // preconditioner shift (uniform-gas TF curvature)
   double e_ii = 0;
   Instance inst[2];
   double *ion_pos = nullptr, *ion_z = nullptr, *sp_z = nullptr, *sp_rc = nullptr;
@@ -207,7 +208,8 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   size_t o_phi = take(rsz * M), o_phit = take(rsz * M), o_grad = take(rsz * M);
-  size_t o_r = take(rsz * M), o_d = take(rsz * M);
+  size_t o_r = take(rsz * M), o_rt = take(rsz * M), o_pr = take(rsz * M), o_prt = take(rsz * M);
+  size_t o_d = take(rsz * M);
   size_t o_S = take(rsz * M * m), o_Y = take(rsz * M * m);
   size_t o_spec = take(2 * rsz * H * NFIELD), o_vloc = take(2 * rsz * H);
   size_t o_pA = take(8 * (size_t)n1 * PART_A), o_pB = take(8 * (size_t)n2 * nkb * PART_B);
@@ -231,8 +233,9 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = nh; h.pitch = pitch;
   h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg;
   h.M = M; h.H = H;
-  h.phi = base + o_phi; h.phit = base + o_phit; h.grad = base + o_grad;
-  h.r = base + o_r; h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
+  h.phi2[0] = base + o_phi; h.phi2[1] = base + o_phit; h.grad = base + o_grad;
+  h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
+  h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
   h.spec = base + o_spec; h.vloc = base + o_vloc;
   h.partA = (double *)(base + o_pA); h.partB = (double *)(base + o_pB);
   h.partC = (double *)(base + o_pC); h.partU = (double *)(base + o_pU);
@@ -269,6 +272,7 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
   h.nf = nf;
   h.w = c->w;
   h.wp = c->wp;
+  h.kappa = c->kappa;
 }
 
 // Prefix sums and grids of a batch; writes `first` (device, 4*(n+1) ints).
@@ -343,10 +347,14 @@ int ensure_tables(skx_ctx *c) {
   if (e != hipSuccess) return hip_fail(c, e, "kernel table allocation");
   c->smax = smax;
   const double V = c->L * c->L * c->L;
-  double eta0 = 0;
-  e = build_kernel_tables(c->w, c->wp, smax, c->L, c->ne / V, c->fn.T, c->fn.alpha,
-                          g_res[c->device].fd, &eta0, c->stream);
+  double gas[3] = {0, 1, 0};
+  const double n0 = c->ne / V;
+  e = build_kernel_tables(c->w, c->wp, smax, c->L, n0, c->fn.T, c->fn.alpha,
+                          g_res[c->device].fd, gas, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kernel table build");
+  // preconditioner shift: 4 n0 dmu0/dn, the curvature of the TF term in phi
+  const double dmudn = std::sqrt(2.0) * M_PI * M_PI / (std::sqrt(c->fn.T) * gas[1]);
+  c->kappa = std::isfinite(dmudn) && dmudn > 0 ? std::max(4.0 * n0 * dmudn, 1e-3) : 1.0;
   c->tables_ok = true;
   return SKX_OK;
 }
@@ -428,7 +436,7 @@ void energy_from(const double *e, double e_ii, skx_energy *out) {
 }
 
 // Initialise the optimiser state of one instance (host -> device).
-void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho) {
+void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho, int prec) {
   st = OptState{};
   st.phase = PH_EVAL_INIT;
   st.m = std::min(std::max(p.lbfgs_m, 1), MMAX);
@@ -437,16 +445,74 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
   st.gtol = gtol;
   st.c1 = 1e-4;
   st.theta_max = 0.5;
-  st.tolE_rel = 1e-12;
+  // energies carry the rounding of the field precision
+  st.tolE_rel = prec == 0 ? 1e-12 : 2e-6;
+  st.stall_limit = prec == 0 ? 0 : 12;
+  st.best_r = 1e300;
+  st.par = 0;
   st.reset_pending = from_rho ? 2 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Optional per-pass timing with HIP events on the launch stream.
+// ---------------------------------------------------------------------------
+enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_N };
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[PP_N] = {0};
+  long long count[PP_N] = {0};
+  std::mutex mu;
+} g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Launch `fn` between two recorded events when profiling is on.
+template <typename F>
+hipError_t timed(int which, hipStream_t s, F fn) {
+  if (!g_prof.on) return fn();
+  hipEvent_t a = prof_event(), b = prof_event();
+  hipEventRecord(a, s);
+  hipError_t e = fn();
+  hipEventRecord(b, s);
+  g_prof.pending.push_back({which, {a, b}});
+  return e;
+}
+
+// Fold finished event pairs into the totals (call after a stream sync).
+void prof_fold() {
+  if (g_prof.pending.empty()) return;
+  for (auto &p : g_prof.pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
+      g_prof.ms[p.first] += t;
+      g_prof.count[p.first] += 1;
+    }
+    g_prof.pool.push_back(p.second.first);
+    g_prof.pool.push_back(p.second.second);
+  }
+  g_prof.pending.clear();
 }
 
 // The fixed step sequence: direction, trial evaluation, update.
 hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
-  hipError_t e = launch_opt_dir(bl, s);
-  if (e == hipSuccess) e = launch_eval(bl, s);
-  if (e == hipSuccess) e = launch_finalize_eval(bl, s);
-  if (e == hipSuccess) e = launch_opt_update(bl, s);
+  hipError_t e = timed(PP_DIR, s, [&] { return launch_opt_dir(bl, s); });
+  if (e == hipSuccess) e = timed(PP_A, s, [&] { return launch_eval(bl, s, 1); });
+  if (e == hipSuccess) e = timed(PP_B, s, [&] { return launch_eval(bl, s, 2); });
+  if (e == hipSuccess) e = timed(PP_C, s, [&] { return launch_eval(bl, s, 4); });
+  if (e == hipSuccess) e = timed(PP_FIN, s, [&] { return launch_finalize_eval(bl, s); });
+  if (e == hipSuccess) e = timed(PP_PREC, s, [&] { return launch_prec(bl, s); });
+  if (e == hipSuccess) e = timed(PP_UPD, s, [&] { return launch_opt_update(bl, s); });
   return e;
 }
 
@@ -472,6 +538,7 @@ int drive(skx_ctx *c, const BatchLaunch &bl, const std::vector<OptState *> &stat
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "step execution");
+    prof_fold();
     for (int p : ph)
       if (p != PH_DONE && p != PH_FAILED) { all = false; break; }
     if (all) break;
@@ -488,20 +555,20 @@ int run_optimize(skx_ctx *c, Instance &I, void *rho_dev, const skx_opt_params &p
     const double v = std::sqrt(c->ne / (c->L * c->L * c->L));
     if (I.prec == 0)
       hipLaunchKernelGGL(k_fill<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                         (double *)I.h.phi, v, M);
+                         (double *)I.h.phi2[0], v, M);
     else
       hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                         (float *)I.h.phi, (float)v, M);
+                         (float *)I.h.phi2[0], (float)v, M);
   } else if (start_mode == 1) {
     if (I.prec == 0)
       hipLaunchKernelGGL(k_from_rho<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                         (const double *)rho_dev, (double *)I.h.phi, M);
+                         (const double *)rho_dev, (double *)I.h.phi2[0], M);
     else
       hipLaunchKernelGGL(k_from_rho<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                         (const double *)rho_dev, (float *)I.h.phi, M);
+                         (const double *)rho_dev, (float *)I.h.phi2[0], M);
   }
   OptState st;
-  init_state(st, p, gtol, start_mode == 1 ? 1 : 0);
+  init_state(st, p, gtol, start_mode == 1 ? 1 : 0, I.prec);
   hipError_t e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "state upload");
   int rc = upload_single(c, I);
@@ -690,14 +757,14 @@ int skx_evaluate_energy_potential(skx_ctx *c, const void *in_dev, int in_kind, v
   SolveDev h = I.h;
   const long long M = h.M;
   if (in_kind == SKX_SQRT_RHO) {
-    h.phi = const_cast<void *>(in_dev);
+    h.phi2[0] = const_cast<void *>(in_dev);
   } else {
     if (prec == 0)
       hipLaunchKernelGGL(k_sqrt_field, dim3(blocks(M, 256)), dim3(256), 0, c->stream,
-                         (const double *)in_dev, (double *)I.h.phi, M);
+                         (const double *)in_dev, (double *)I.h.phi2[0], M);
     else
       hipLaunchKernelGGL(k_sqrt_field_f, dim3(blocks(M, 256)), dim3(256), 0, c->stream,
-                         (const float *)in_dev, (float *)I.h.phi, M);
+                         (const float *)in_dev, (float *)I.h.phi2[0], M);
   }
   if (out_dev) h.grad = out_dev;
   OptState st{};
@@ -707,13 +774,20 @@ int skx_evaluate_energy_potential(skx_ctx *c, const void *in_dev, int in_kind, v
   std::vector<SolveDev> hs(1, h);
   rc = build_batch(c, hs, prec, I.dptr, I.first, I.bl, c->stream);
   if (rc) return rc;
-  he = launch_eval(I.bl, c->stream);
-  if (he == hipSuccess) he = launch_finalize_eval(I.bl, c->stream);
+  {
+    hipStream_t s = c->stream;
+    const BatchLaunch &bl = I.bl;
+    he = timed(PP_A, s, [&] { return launch_eval(bl, s, 1); });
+    if (he == hipSuccess) he = timed(PP_B, s, [&] { return launch_eval(bl, s, 2); });
+    if (he == hipSuccess) he = timed(PP_C, s, [&] { return launch_eval(bl, s, 4); });
+    if (he == hipSuccess) he = timed(PP_FIN, s, [&] { return launch_finalize_eval(bl, s); });
+  }
   if (he != hipSuccess) return hip_fail(c, he, "evaluation kernels");
   double ev[12];
   he = hipMemcpyAsync(ev, I.st->e_trial, sizeof(ev), hipMemcpyDeviceToHost, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   if (he != hipSuccess) return hip_fail(c, he, "evaluation");
+  prof_fold();
   energy_from(ev, c->e_ii, e);
   if (ev[E_NONFINITE] != 0.0)
     return fail(c, SKX_E_NUMERIC, "non-finite field or density outside the Fermi-Dirac table");
@@ -740,10 +814,10 @@ int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx
     if (rc) return rc;
     if (prec == 0)
       hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, c->stream,
-                         (const double *)I.h.phi, (double *)rho_dev, I.h.M);
+                         (const double *)I.h.phi2[out.par], (double *)rho_dev, I.h.M);
     else
       hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, c->stream,
-                         (const float *)I.h.phi, (double *)rho_dev, I.h.M);
+                         (const float *)I.h.phi2[out.par], (double *)rho_dev, I.h.M);
     res->iters = out.iters;
     res->evals = out.evals;
     if (prec == 1) { res->fp32_iters = out.iters; res->fp32_evals = out.evals; }
@@ -760,11 +834,11 @@ int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx
     rc = run_optimize(c, I32, rho_dev, *p, std::max(sw, p->gtol), p->warm_start ? 1 : 0, o32);
     if (rc) return rc;
     hipLaunchKernelGGL(k_f2d, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
-                       (const float *)I32.h.phi, (double *)I64.h.phi, I64.h.M);
+                       (const float *)I32.h.phi2[o32.par], (double *)I64.h.phi2[0], I64.h.M);
     rc = run_optimize(c, I64, rho_dev, *p, p->gtol, 2, out);
     if (rc) return rc;
     hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
-                       (const double *)I64.h.phi, (double *)rho_dev, I64.h.M);
+                       (const double *)I64.h.phi2[out.par], (double *)rho_dev, I64.h.M);
     res->fp32_iters = o32.iters;
     res->fp32_evals = o32.evals;
     res->iters = o32.iters + out.iters;
@@ -868,7 +942,7 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
   h.debug = 1;
   hipStream_t s = c->stream;
   const long long M = h.M;
-  hipError_t e = hipMemcpyAsync(h.phi, in_host, sizeof(double) * M, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(h.phi2[0], in_host, sizeof(double) * M, hipMemcpyHostToDevice, s);
   OptState st{};
   st.phase = PH_EVAL_ONLY;
   if (e == hipSuccess) e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
@@ -943,27 +1017,28 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
       int start = 0;
       if (ph > 0) {
         hipLaunchKernelGGL(k_f2d, dim3(blocks(M, 256)), dim3(256), 0, s,
-                           (const float *)ctxs[i]->inst[1].h.phi, (double *)I.h.phi, M);
+                           (const float *)ctxs[i]->inst[1].h.phi2[o32[i].par], (double *)I.h.phi2[0],
+                           M);
         start = 2;
       } else if (p->warm_start) {
         start = 1;
         if (pr == 0)
           hipLaunchKernelGGL(k_from_rho<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                             (const double *)rho_devs[i], (double *)I.h.phi, M);
+                             (const double *)rho_devs[i], (double *)I.h.phi2[0], M);
         else
           hipLaunchKernelGGL(k_from_rho<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                             (const double *)rho_devs[i], (float *)I.h.phi, M);
+                             (const double *)rho_devs[i], (float *)I.h.phi2[0], M);
       } else {
         const double v = std::sqrt(ctxs[i]->ne / (ctxs[i]->L * ctxs[i]->L * ctxs[i]->L));
         if (pr == 0)
           hipLaunchKernelGGL(k_fill<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                             (double *)I.h.phi, v, M);
+                             (double *)I.h.phi2[0], v, M);
         else
           hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
-                             (float *)I.h.phi, (float)v, M);
+                             (float *)I.h.phi2[0], (float)v, M);
       }
       OptState st;
-      init_state(st, *p, gtol, start == 1 ? 1 : 0);
+      init_state(st, *p, gtol, start == 1 ? 1 : 0, pr);
       e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
       if (e != hipSuccess) { rc = hip_fail(c0, e, "state upload"); break; }
       hs.push_back(I.h);
@@ -988,13 +1063,13 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
     const int pr = precs.back();
     for (int i = 0; i < nctx; ++i) {
       Instance &I = ctxs[i]->inst[pr];
+      const OptState &o = outs[i];
       if (pr == 0)
         hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
-                           (const double *)I.h.phi, (double *)rho_devs[i], I.h.M);
+                           (const double *)I.h.phi2[o.par], (double *)rho_devs[i], I.h.M);
       else
         hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
-                           (const float *)I.h.phi, (double *)rho_devs[i], I.h.M);
-      const OptState &o = outs[i];
+                           (const float *)I.h.phi2[o.par], (double *)rho_devs[i], I.h.M);
       energy_from(o.e_acc, ctxs[i]->e_ii, &res[i].e);
       res[i].gnorm = o.rnorm;
       res[i].resets = o.resets;
@@ -1022,6 +1097,36 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   for (int i = 0; i < nctx; ++i)
     if (res[i].status != SKX_OK) worst = (res[i].status < 0) ? res[i].status : (worst < 0 ? worst : SKX_NOT_CONVERGED);
   return worst;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Instrumentation
+// ===========================================================================
+extern "C" {
+
+int skx_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return SKX_OK;
+}
+
+int skx_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (int i = 0; i < PP_N; ++i) { g_prof.ms[i] = 0; g_prof.count[i] = 0; }
+  return SKX_OK;
+}
+
+int skx_profile_read(double *ms, long long *launches, int n) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (n < 0) return SKX_E_INVALID;
+  prof_fold();
+  for (int i = 0; i < n && i < PP_N; ++i) {
+    if (ms) ms[i] = g_prof.ms[i];
+    if (launches) launches[i] = g_prof.count[i];
+  }
+  return PP_N;
 }
 
 }  // extern "C"

@@ -14,8 +14,8 @@ constexpr int MAX_STAGES = 8;      // FFT stages per axis
 constexpr int PART_A = 4;          // pass A partial sums: f_tf, e_xc, nelec, nonfinite
 constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinite
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
-constexpr int NDOT = 8 * MMAX + 8; // update-pass dot products
-constexpr int CHUNK = 4096;        // grid points per workgroup in the vector passes
+constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
+constexpr int CHUNK = 1024;        // grid points per workgroup in the vector passes
 
 // Which transformed fields are present (slot order phi, n, f, h).
 enum FieldBits { F_PHI = 1, F_N = 2, F_F = 4, F_H = 8 };
@@ -33,18 +33,19 @@ struct Plan {                      // 1D FFT plan for one axis length
 };
 
 // Control state of one solve (device resident, FP64).
+// The current point lives in buffer `par` of each pair (phi, r, P r); the
+// trial point is written to buffer 1 - par and accepted by flipping par.
 struct OptState {
   int phase, iters, evals, trials, k, head, status, resets;
   int m, max_iter, max_trials, reset_pending;
-  int pair_ok, nonfinite, pad0, pad1;
+  int pair_ok, par, stall, stall_limit;
   double gtol, c1, theta_max, tolE_rel;
-  double E, Et, mu, mut, rnorm, theta, g0, dnorm, rd;
+  double E, Et, mu, mut, rnorm, theta, g0, dnorm, rd, best_r;
   double gamma, cr, cphi;
   double cS[MMAX], cY[MMAX];
-  double SY[MMAX][MMAX], YY[MMAX][MMAX];
-  double Sr[MMAX], Yr[MMAX], Sphi[MMAX], Yphi[MMAX];
-  double rr, rphi;
-  int order[MMAX];                 // ring slot of the i-th oldest pair
+  double SY[MMAX][MMAX], YPY[MMAX][MMAX];   // s_i.y_j (upper), y_i.P y_j
+  double Sr[MMAX], YPr[MMAX], Sphi[MMAX], PYphi[MMAX];
+  double rr, rphi, rPr, phiPr;
   double e_acc[12];                // energy terms at the accepted point
   double e_trial[12];              // energy terms at the last evaluation
 };
@@ -64,7 +65,9 @@ struct SolveDev {
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
   double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
   Plan p1, p2, p3;
-  void *phi, *phit, *grad, *r, *d, *S, *Y;   // real fields (fp64 or fp32)
+  double kappa;                    // preconditioner P(G) = 1 / (G^2 + kappa)
+  void *phi2[2], *r2[2], *pr2[2];  // current / trial point pairs (see OptState::par)
+  void *grad, *d, *S, *Y;          // real fields (fp64 or fp32); Y holds P y
   void *spec, *vloc;                         // complex spectra
   const double *w, *wp;                      // shell tables
   double *partA, *partB, *partC, *partU, *partD;
@@ -83,7 +86,8 @@ hipError_t build_twiddles(double *bank_dev, const int *sizes, const int *offsets
 hipError_t build_fd_table(double *coef_dev, double y0, double dy, int nseg, int deg,
                           hipStream_t s);
 hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double n0, double T,
-                               double a, const FDTable &fd, double *eta0_out, hipStream_t s);
+                               double a, const FDTable &fd, double *gas_out /* eta0, I_-1/2, dI_-1/2 */,
+                               hipStream_t s);
 hipError_t build_vloc(void *vloc, int prec, int n1, int n2, int n3, int pitch, double L,
                       int nions, const double *pos_dev, const int *species_dev,
                       int nspecies, const double *zval_dev, const double *rc_dev,
@@ -107,6 +111,7 @@ struct BatchLaunch {
 };
 hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);  // passes A|B|C
 hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_prec(const BatchLaunch &b, hipStream_t s, int mask = 7);  // P r_t, passes A|B|C
 hipError_t launch_opt_update(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_opt_dir(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_normalize(const BatchLaunch &b, hipStream_t s);     // scale phi to N_e

@@ -1,20 +1,27 @@
 // Density optimisation of libskx: reductions that close each evaluation,
-// and the compact limited-memory BFGS on sqrt(n) with the electron-count
-// constraint, driven by a per-solve state machine so that a batch of solves
-// advances with one fixed kernel sequence (no host decision per step).
+// and a preconditioned compact limited-memory BFGS on sqrt(n) with the
+// electron-count constraint, driven by a per-solve state machine so that a
+// batch of solves advances with one fixed kernel sequence (no host decision
+// per step).
 //
 // The paper minimises the free energy at fixed electron number ("SCF
 // iterations", Methods, Table A caption) without naming the algorithm.
 // Reading used here: L-BFGS on the sphere int phi^2 = N_e,
 //   r = dE/dphi - 2 mu phi,  mu = int phi dE/dphi / (2 N_e),
-//   d = -H r (compact representation of the last m pairs, H0 = gamma I),
-//   d <- d + kappa phi with kappa making d tangent to the sphere,
+//   d = -H r, H the L-BFGS inverse Hessian of the last m pairs with initial
+//       matrix H0 = gamma P, P(G) = 1/(G^2 + kappa) (kinetic preconditioner,
+//       kappa the Thomas-Fermi curvature 4 n0 dmu0/dn of the uniform gas)
+//       and gamma = s.y / y.P y of the newest pair,
+//   d <- d + kappa' phi, kappa' making d tangent to the sphere,
 //   phi(t) = cos(t) phi + sin(t) sqrt(N_e) d/|d|,
 //   t0 = min(|d|/sqrt(N_e), t_max), backtracking Armijo with quadratic
 //   interpolation, rounding-level energy changes accepted.
-// The compact form H r = gamma r + S a - gamma Y p with p = R^-1 S^T r,
-// a = R^-T ((D + gamma Y^T Y) p - gamma Y^T r), R = upper(S^T Y),
-// D = diag(S^T Y), is the same operator as the two-loop recursion.
+// Compact form (same operator as the two-loop recursion with H0 = gamma P):
+//   H r = gamma P r + S a - gamma (P Y) p,  p = R^-1 S^T r,
+//   a = R^-T ((D + gamma Y^T P Y) p - gamma (P Y)^T r),
+//   R = upper(S^T Y), D = diag(S^T Y).
+// Only S and P Y are stored; y = r_t - r and P y = P r_t - P r are formed
+// on the fly from the residual pair and its preconditioned pair.
 #include "skx_device.hpp"
 #include <math.h>
 
@@ -32,12 +39,14 @@ __device__ void sum_parts(const double *part, int nrow, double *sh, int tid, int
   block_reduce<N>(v, sh, tid, nthr, out);
 }
 
-__device__ void set_steepest(OptState *st) {
+// Direction d = -P r + kappa' phi (history dropped).
+__device__ void set_steepest(OptState *st, double ne) {
   st->k = 0;
   st->head = 0;
   st->gamma = 1.0;
   st->cr = -1.0;
   for (int i = 0; i < MMAX; ++i) { st->cS[i] = 0.0; st->cY[i] = 0.0; }
+  st->cphi = st->phiPr / ne;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,8 +112,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
   }
   if (st->trials >= st->max_trials) {
     if (st->k > 0) {
-      set_steepest(st);
-      st->cphi = st->rphi / S.ne;
+      set_steepest(st, S.ne);
       st->resets += 1;
       st->trials = 0;
       st->phase = PH_NEED_DIR;
@@ -116,8 +124,9 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
 }
 
 // ---------------------------------------------------------------------------
-// Update pass: r_t, the new pair (s, y), and every inner product the compact
-// L-BFGS needs, in one sweep over the history.
+// Update pass: the new pair (s, P y) and every inner product the compact
+// L-BFGS needs, in one sweep over the history. Reads the current point
+// (buffers par) and the accepted trial point (buffers 1 - par).
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
@@ -133,28 +142,31 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   const int wl = item - first[s];
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
-  R *phi = reinterpret_cast<R *>(S.phi);
-  const R *phit = reinterpret_cast<const R *>(S.phit);
-  const R *grad = reinterpret_cast<const R *>(S.grad);
-  R *r = reinterpret_cast<R *>(S.r);
+  const int par = st->par;
+  const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
+  const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
+  const R *r = reinterpret_cast<const R *>(S.r2[par]);
+  const R *rt = reinterpret_cast<const R *>(S.r2[1 - par]);
+  const R *pr = reinterpret_cast<const R *>(S.pr2[par]);
+  const R *prt = reinterpret_cast<const R *>(S.pr2[1 - par]);
   R *Sv = reinterpret_cast<R *>(S.S);
   R *Yv = reinterpret_cast<R *>(S.Y);
-  const R mu2 = (R)(2.0 * st->mut);
   double acc[NDOT];
 #pragma unroll
   for (int q = 0; q < NDOT; ++q) acc[q] = 0.0;
-  // acc layout: [0..MMAX) sy_i, [MMAX..2MMAX) yy_i, sphi_i, yphi_i, sr_i, yr_i,
-  // then 6*MMAX + {0 sy, 1 yy, 2 sphi, 3 yphi, 4 sr, 5 yr, 6 rr, 7 rphi}
+  // acc layout: [i] s_i.y, [M+i] Py_i.y, [2M+i] s_i.r_t, [3M+i] Py_i.r_t,
+  // [4M+i] s_i.phi_t, [5M+i] Py_i.phi_t (old pairs), then at B = 6M:
+  // s.y, y.Py, s.r_t, Py.r_t, s.phi_t, Py.phi_t, r_t.r_t, r_t.Pr_t,
+  // phi_t.Pr_t, r_t.phi_t
   const int B = 6 * MMAX;
-  if (st->k == 0 && st->iters == 0 && st->reset_pending == 1) {
-    // first accepted point: residual only
+  if (st->reset_pending == 1) {
+    // first accepted point: residual inner products only
     for (long long g = g0 + tid; g < g1; g += NT) {
-      const R pt = phit[g];
-      const R rt = grad[g] - mu2 * pt;
-      r[g] = rt;
-      phi[g] = pt;
-      acc[B + 6] += (double)rt * rt;
-      acc[B + 7] += (double)rt * pt;
+      const double a = rt[g], b = prt[g], f = phit[g];
+      acc[B + 6] += a * a;
+      acc[B + 7] += a * b;
+      acc[B + 8] += f * b;
+      acc[B + 9] += a * f;
     }
   } else {
     const int m = st->m, k = st->k, head = st->head;
@@ -165,10 +177,10 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
     R *Snew = Sv + (size_t)head * S.M;
     R *Ynew = Yv + (size_t)head * S.M;
     for (long long g = g0 + tid; g < g1; g += NT) {
-      const R pt = phit[g];
-      const R rt = grad[g] - mu2 * pt;
+      const R pt = phit[g], rtg = rt[g], prtg = prt[g];
       const R sv = pt - phi[g];
-      const R yv = rt - r[g];
+      const R yv = rtg - r[g];
+      const R pyv = prtg - pr[g];
 #pragma unroll
       for (int i = 0; i < MMAX; ++i) {
         if (i < kold) {
@@ -176,24 +188,24 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
           const double Yi = (double)Yv[(size_t)slot[i] * S.M + g];
           acc[i] += Si * yv;
           acc[MMAX + i] += Yi * yv;
-          acc[2 * MMAX + i] += Si * pt;
-          acc[3 * MMAX + i] += Yi * pt;
-          acc[4 * MMAX + i] += Si * rt;
-          acc[5 * MMAX + i] += Yi * rt;
+          acc[2 * MMAX + i] += Si * rtg;
+          acc[3 * MMAX + i] += Yi * rtg;
+          acc[4 * MMAX + i] += Si * pt;
+          acc[5 * MMAX + i] += Yi * pt;
         }
       }
       acc[B + 0] += (double)sv * yv;
-      acc[B + 1] += (double)yv * yv;
-      acc[B + 2] += (double)sv * pt;
-      acc[B + 3] += (double)yv * pt;
-      acc[B + 4] += (double)sv * rt;
-      acc[B + 5] += (double)yv * rt;
-      acc[B + 6] += (double)rt * rt;
-      acc[B + 7] += (double)rt * pt;
+      acc[B + 1] += (double)yv * pyv;
+      acc[B + 2] += (double)sv * rtg;
+      acc[B + 3] += (double)pyv * rtg;
+      acc[B + 4] += (double)sv * pt;
+      acc[B + 5] += (double)pyv * pt;
+      acc[B + 6] += (double)rtg * rtg;
+      acc[B + 7] += (double)rtg * prtg;
+      acc[B + 8] += (double)pt * prtg;
+      acc[B + 9] += (double)rtg * pt;
       Snew[g] = sv;
-      Ynew[g] = yv;
-      r[g] = rt;
-      phi[g] = pt;
+      Ynew[g] = pyv;
     }
   }
   block_reduce<NDOT>(acc, sh, tid, NT, tot);
@@ -219,9 +231,14 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
   st->E = st->Et;
   st->mu = st->mut;
   for (int q = 0; q < 12; ++q) st->e_acc[q] = st->e_trial[q];
+  st->par = 1 - st->par;            // the trial point becomes the current point
+  st->rr = t[B + 6];
+  st->rPr = t[B + 7];
+  st->phiPr = t[B + 8];
+  st->rphi = t[B + 9];
   if (st->reset_pending == 1) {
     st->reset_pending = 0;
-    set_steepest(st);
+    set_steepest(st, S.ne);
   } else {
     st->iters += 1;
     int k = st->k;
@@ -230,47 +247,54 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
       for (int i = 0; i + 1 < k; ++i)
         for (int j = 0; j + 1 < k; ++j) {
           st->SY[i][j] = st->SY[i + 1][j + 1];
-          st->YY[i][j] = st->YY[i + 1][j + 1];
+          st->YPY[i][j] = st->YPY[i + 1][j + 1];
         }
       k = m - 1;
     }
     for (int i = 0; i < k; ++i) {
-      st->Sphi[i] = t[2 * MMAX + i];
-      st->Yphi[i] = t[3 * MMAX + i];
-      st->Sr[i] = t[4 * MMAX + i];
-      st->Yr[i] = t[5 * MMAX + i];
+      st->Sr[i] = t[2 * MMAX + i];
+      st->YPr[i] = t[3 * MMAX + i];
+      st->Sphi[i] = t[4 * MMAX + i];
+      st->PYphi[i] = t[5 * MMAX + i];
     }
-    const double sy = t[B + 0], yy = t[B + 1];
-    const bool ok = (sy > 0.0) && (yy > 0.0) && (sy == sy) && (yy == yy);
+    const double sy = t[B + 0], ypy = t[B + 1];
+    const bool ok = (sy > 0.0) && (ypy > 0.0) && (sy == sy) && (ypy == ypy);
     if (ok) {
       for (int i = 0; i < k; ++i) {
         st->SY[i][k] = t[i];
         st->SY[k][i] = 0.0;            // only the upper triangle is used
-        st->YY[i][k] = t[MMAX + i];
-        st->YY[k][i] = t[MMAX + i];
+        st->YPY[i][k] = t[MMAX + i];
+        st->YPY[k][i] = t[MMAX + i];
       }
       st->SY[k][k] = sy;
-      st->YY[k][k] = yy;
-      st->Sphi[k] = t[B + 2];
-      st->Yphi[k] = t[B + 3];
-      st->Sr[k] = t[B + 4];
-      st->Yr[k] = t[B + 5];
+      st->YPY[k][k] = ypy;
+      st->Sr[k] = t[B + 2];
+      st->YPr[k] = t[B + 3];
+      st->Sphi[k] = t[B + 4];
+      st->PYphi[k] = t[B + 5];
       k += 1;
       st->head = (st->head + 1) % m;
     }
     st->k = k;
     st->pair_ok = ok ? 1 : 0;
   }
-  st->rr = t[B + 6];
-  st->rphi = t[B + 7];
   st->rnorm = sqrt(fmax(st->rr, 0.0));
   if (!(st->rnorm == st->rnorm)) { st->phase = PH_FAILED; st->status = -5; return; }
   if (st->rnorm < st->gtol) { st->phase = PH_DONE; st->status = 0; return; }
   if (st->iters >= st->max_iter) { st->phase = PH_DONE; st->status = 1; return; }
-  // compact L-BFGS coefficients
+  if (st->stall_limit > 0) {
+    // low-precision phase: stop once the residual no longer improves
+    if (st->rnorm < 0.9 * st->best_r) { st->best_r = st->rnorm; st->stall = 0; }
+    else if (++st->stall >= st->stall_limit) { st->phase = PH_DONE; st->status = 2; return; }
+  }
+  // compact L-BFGS coefficients, H0 = gamma P
   const int k = st->k;
-  double gamma = 1.0;
-  if (k > 0) gamma = st->SY[k - 1][k - 1] / st->YY[k - 1][k - 1];
+  if (k == 0) {
+    set_steepest(st, S.ne);
+    st->phase = PH_NEED_DIR;
+    return;
+  }
+  const double gamma = st->SY[k - 1][k - 1] / st->YPY[k - 1][k - 1];
   double p[MMAX], z[MMAX], a[MMAX];
   for (int i = k - 1; i >= 0; --i) {
     double v = st->Sr[i];
@@ -278,8 +302,8 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
     p[i] = v / st->SY[i][i];
   }
   for (int i = 0; i < k; ++i) {
-    double v = st->SY[i][i] * p[i] - gamma * st->Yr[i];
-    for (int j = 0; j < k; ++j) v += gamma * st->YY[i][j] * p[j];
+    double v = st->SY[i][i] * p[i] - gamma * st->YPr[i];
+    for (int j = 0; j < k; ++j) v += gamma * st->YPY[i][j] * p[j];
     z[i] = v;
   }
   for (int i = 0; i < k; ++i) {
@@ -287,18 +311,17 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
     for (int j = 0; j < i; ++j) v -= st->SY[j][i] * a[j];
     a[i] = v / st->SY[i][i];
   }
-  double dphi = -gamma * st->rphi;
-  double rd = -gamma * st->rr;
+  double dphi = -gamma * st->phiPr;
+  double rd = -gamma * st->rPr;
   for (int i = 0; i < k; ++i) {
-    dphi += -a[i] * st->Sphi[i] + gamma * p[i] * st->Yphi[i];
-    rd += -a[i] * st->Sr[i] + gamma * p[i] * st->Yr[i];
+    dphi += -a[i] * st->Sphi[i] + gamma * p[i] * st->PYphi[i];
+    rd += -a[i] * st->Sr[i] + gamma * p[i] * st->YPr[i];
   }
-  const double kappa = -dphi / S.ne;
-  rd += kappa * st->rphi;
+  const double kap = -dphi / S.ne;
+  rd += kap * st->rphi;
   if (!(rd < 0.0)) {
-    set_steepest(st);
-    st->cphi = st->rphi / S.ne;
-    st->resets += (k > 0) ? 1 : 0;
+    set_steepest(st, S.ne);
+    st->resets += 1;
   } else {
     st->gamma = gamma;
     st->cr = -gamma;
@@ -306,13 +329,14 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
       st->cS[i] = (i < k) ? -a[i] : 0.0;
       st->cY[i] = (i < k) ? gamma * p[i] : 0.0;
     }
-    st->cphi = kappa;
+    st->cphi = kap;
   }
   st->phase = PH_NEED_DIR;
 }
 
 // ---------------------------------------------------------------------------
-// Direction pass: d = cr r + sum cS_i s_i + sum cY_i y_i + cphi phi, |d|^2, r.d
+// Direction pass: d = cr P r + sum cS_i s_i + sum cY_i P y_i + cphi phi,
+// with |d|^2 and r.d.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int nsolve, int grid) {
@@ -327,8 +351,10 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   const int wl = item - first[s];
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
-  const R *phi = reinterpret_cast<const R *>(S.phi);
-  const R *r = reinterpret_cast<const R *>(S.r);
+  const int par = st->par;
+  const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
+  const R *r = reinterpret_cast<const R *>(S.r2[par]);
+  const R *pr = reinterpret_cast<const R *>(S.pr2[par]);
   const R *Sv = reinterpret_cast<const R *>(S.S);
   const R *Yv = reinterpret_cast<const R *>(S.Y);
   R *d = reinterpret_cast<R *>(S.d);
@@ -344,15 +370,14 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   const R cr = (R)st->cr, cphi = (R)st->cphi;
   double dd = 0.0, rd = 0.0;
   for (long long g = g0 + tid; g < g1; g += NT) {
-    const R rv = r[g];
-    R v = cr * rv + cphi * phi[g];
+    R v = cr * pr[g] + cphi * phi[g];
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) {
       if (i < k) v += cS[i] * Sv[(size_t)slot[i] * S.M + g] + cY[i] * Yv[(size_t)slot[i] * S.M + g];
     }
     d[g] = v;
     dd += (double)v * v;
-    rd += (double)rv * v;
+    rd += (double)r[g] * v;
   }
   double acc[2] = {dd, rd};
   block_reduce<2>(acc, sh, tid, NT, tot);
@@ -373,10 +398,9 @@ __global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve)
   const double dn = sqrt(fmax(dd, 0.0));
   if (!(rd < 0.0) || !(dn > 0.0)) {
     if (st->k > 0) {
-      set_steepest(st);
-      st->cphi = st->rphi / S.ne;
+      set_steepest(st, S.ne);
       st->resets += 1;
-      return;                       // stays in NEED_DIR: steepest descent next
+      return;                       // stays in NEED_DIR: preconditioned steepest descent next
     }
     st->phase = PH_FAILED;
     st->status = 1;
@@ -392,7 +416,7 @@ __global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve)
 
 // ---------------------------------------------------------------------------
 // Normalisation of the starting point: phi <- phi sqrt(N_e / int phi^2).
-// With from_rho, the input buffer holds a density and phi = sqrt(max(rho,0)).
+// With reset_pending == 2 the buffer holds a density and phi = sqrt(max(rho,0)).
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, int nsolve, int grid) {
@@ -407,7 +431,7 @@ __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, in
   const int wl = item - first[s];
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
-  R *phi = reinterpret_cast<R *>(S.phi);
+  R *phi = reinterpret_cast<R *>(S.phi2[st->par]);
   const bool from_rho = st->reset_pending == 2;
   double ss = 0.0, bad = 0.0;
   for (long long g = g0 + tid; g < g1; g += NT) {

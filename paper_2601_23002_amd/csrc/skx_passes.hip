@@ -1,6 +1,8 @@
 // The functional evaluation of libskx as three fused passes over a batch of
-// solves, plus the reductions that close each pass.
+// solves, and the same three passes reused to apply the optimiser's
+// preconditioner.
 //
+// Evaluation (MODE_EVAL):
 //   pass A  real space, one workgroup per (solve, x-plane, field):
 //           trial point phi_t = cos(t) phi + sqrt(N_e) sin(t) d/|d|, the
 //           pointwise fields phi, n = phi^2, f = n^a, h = (f - n0^a)(n - n0),
@@ -12,7 +14,7 @@
 //           the four reciprocal multipliers, inverse x transform.
 //   pass C  real space, one workgroup per (solve, x-plane): inverse y and
 //           complex-to-real z transforms of the four outputs, assembled with
-//           their pointwise coefficients into dE/dphi in registers.
+//           their pointwise coefficients into dE/dphi.
 //
 // Energy terms (paper Eq. (1), Eq. (2); readings as stated in include/skx.h):
 //   F_TF = dV sum f_TF(n),   F_vW = (V/2) sum G^2 |phi~|^2,
@@ -23,6 +25,11 @@
 //   A = G^2 phi~, B = 4 pi n~/G^2 + V_loc, P = 2 w f~ + (beta/3) w' h~,
 //   Q = (beta/3) w' f~, c_P = 2 a sign(phi)|phi|^(2a-1),
 //   c_Q = c_P (n - n0) + 2 phi (f - n0^a).
+//
+// Preconditioner (MODE_PREC), for solves whose trial point was accepted:
+//   pass A  r_t = dE/dphi - 2 mu_t phi_t (stored), transformed like phi;
+//   pass B  multiplied by 1 / (G^2 + kappa);
+//   pass C  transformed back into P r_t.
 #include "skx_device.hpp"
 #include <math.h>
 
@@ -30,6 +37,7 @@ namespace skx {
 
 constexpr int MAXB_A = 2;
 constexpr int MAXB_C = 2;
+constexpr int MODE_EVAL = 0, MODE_PREC = 1;
 
 template <typename R> __device__ __forceinline__ R rpow(R x, R a);
 template <> __device__ __forceinline__ double rpow(double x, double a) { return pow(x, a); }
@@ -70,14 +78,106 @@ __device__ __forceinline__ void trial_coef(const OptState *st, const SolveDev &S
   }
 }
 
-__device__ __forceinline__ bool eval_phase(int ph) {
+template <int MODE> __device__ __forceinline__ bool active_phase(int ph) {
+  if (MODE == MODE_PREC) return ph == PH_UPDATE;
   return ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY;
+}
+
+// Real-to-complex z transform of the rows held pairwise in LDS (pair p at
+// buf[2p pl ...] as x_{2p} + i x_{2p+1}), then the y transform of every
+// z column. On exit row j of the plane holds the half spectrum in [0, nh).
+template <typename V, typename R, int NT>
+__device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V *tw2,
+                                              const V *tw3, int tid) {
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh;
+  fft_lds<V, MAXB_A, false>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
+  const int nk = n3 / 2 + 1;
+  int per = (MAXB_A * NT) / nk;
+  if (per < 1) per = 1;
+  for (int p0 = 0; p0 < n2 / 2; p0 += per) {
+    const int p1 = min(n2 / 2, p0 + per);
+    const int tot = (p1 - p0) * nk;
+    V A[MAXB_A], B[MAXB_A];
+#pragma unroll
+    for (int i = 0; i < MAXB_A; ++i) {
+      const int e = tid + i * NT;
+      if (e < tot) {
+        const int p = p0 + e / nk, k = e % nk;
+        const V X = buf[p * 2 * pl + k];
+        const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
+        A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
+        B[i].x = (R)0.5 * (X.y + Xm.y); B[i].y = (R)-0.5 * (X.x - Xm.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB_A; ++i) {
+      const int e = tid + i * NT;
+      if (e < tot) {
+        const int p = p0 + e / nk, k = e % nk;
+        buf[(2 * p) * pl + k] = A[i];
+        buf[(2 * p + 1) * pl + k] = B[i];
+      }
+    }
+    __syncthreads();
+  }
+  fft_lds<V, MAXB_A, false>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+}
+
+// Inverse of plane_forward for one field loaded as a half spectrum in LDS:
+// inverse y transform, then complex-to-real along z, two rows at a time
+// (X = A + i B over the full row, A and B Hermitian-extended; the columns
+// k = 0 and k = n3/2 keep only their real parts, i.e. the real part of the
+// plane-wave sum). On exit row j's real values sit in component j&1 of
+// buf[(j>>1) 2 pl + k].
+template <typename V, typename R, int NT>
+__device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V *tw2,
+                                              const V *tw3, int tid) {
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh;
+  fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  int per = (MAXB_C * 2 * NT) / n3;
+  if (per < 1) per = 1;
+  for (int p0 = 0; p0 < n2 / 2; p0 += per) {
+    const int p1 = min(n2 / 2, p0 + per);
+    const int tot = (p1 - p0) * n3;
+    V X[MAXB_C * 2];
+#pragma unroll
+    for (int i = 0; i < MAXB_C * 2; ++i) {
+      const int e = tid + i * NT;
+      if (e < tot) {
+        const int p = p0 + e / n3, k = e % n3;
+        V Av, Bv;
+        if (2 * k <= n3) {
+          Av = buf[(2 * p) * pl + k];
+          Bv = buf[(2 * p + 1) * pl + k];
+          if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
+        } else {
+          Av = buf[(2 * p) * pl + n3 - k];
+          Bv = buf[(2 * p + 1) * pl + n3 - k];
+          Av.y = -Av.y; Bv.y = -Bv.y;
+        }
+        X[i].x = Av.x - Bv.y;
+        X[i].y = Av.y + Bv.x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB_C * 2; ++i) {
+      const int e = tid + i * NT;
+      if (e < tot) {
+        const int p = p0 + e / n3, k = e % n3;
+        buf[p * 2 * pl + k] = X[i];
+      }
+    }
+    __syncthreads();
+  }
+  fft_lds<V, MAXB_C, true>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
 }
 
 // ---------------------------------------------------------------------------
 // Pass A
 // ---------------------------------------------------------------------------
-template <typename R, int NT>
+template <typename R, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, int nsolve,
                                               int grid, const double *twbank, FDTable fd) {
   typedef typename Vec2<R>::T V;
@@ -87,11 +187,13 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
   const OptState *st = S.st;
-  if (!eval_phase(st->phase)) return;
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
   const int tid = threadIdx.x;
   const int local = item - first[s];
-  const int plane = local / S.nf, c = local % S.nf;
-  const int fb = nth_field(S.fields, c);
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const int plane = local / nf, c = local % nf;
+  const int fb = MODE == MODE_EVAL ? nth_field(S.fields, c) : 0;
   const int n2 = S.n2, n3 = S.n3, nh = S.nh;
   const int pl = nh;                         // LDS row pitch (complex)
   V *buf = reinterpret_cast<V *>(smem);
@@ -100,98 +202,80 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
   load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
 
-  double ca, cb;
-  bool use_d;
-  trial_coef(st, S, ca, cb, use_d);
-  const R *phi = reinterpret_cast<const R *>(S.phi);
-  const R *dd = reinterpret_cast<const R *>(S.d);
-  R *phit = reinterpret_cast<R *>(S.phit);
   const R invM = (R)(1.0 / (double)S.M);
-  const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
-  const bool energies = (c == 0);
-  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
-  double e_tf = 0.0, e_xc = 0.0, nel = 0.0, bad = 0.0;
   const size_t pbase = (size_t)plane * n2 * n3;
   const int np = n2 * n3;
-  for (int e = tid; e < np; e += NT) {
-    const int j = e / n3, k = e - j * n3;
-    const size_t g = pbase + e;
-    R ph;
-    if (use_d) ph = (R)(ca * (double)phi[g] + cb * (double)dd[g]);
-    else ph = (R)(ca * (double)phi[g]);
-    if (c == 0) phit[g] = ph;
-    const R n = ph * ph;
-    R x;
-    if (fb == 0) x = ph;
-    else if (fb == 1) x = n;
-    else {
-      const R f = rpow(n, a);
-      x = (fb == 2) ? f : (f - n0a) * (n - n0);
-    }
-    if (energies) {
-      const double nd = (double)n;
-      if (!(nd == nd) || nd > 1e300) bad += 1.0;
-      if (nd > 0.0) {
-        nel += nd;
-        if (do_tf) {
-          double eta, psi;
-          bad += fd_lookup(log(nd) - S.lnnT, fd, eta, psi);
-          e_tf += S.T * nd * psi;
-        }
-        if (do_xc) {
-          double eps, v;
-          pz81(nd, eps, v);
-          e_xc += nd * eps;
+  double e_tf = 0.0, e_xc = 0.0, nel = 0.0, bad = 0.0;
+  if (MODE == MODE_EVAL) {
+    double ca, cb;
+    bool use_d;
+    trial_coef(st, S, ca, cb, use_d);
+    const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
+    const R *dd = reinterpret_cast<const R *>(S.d);
+    R *phit = reinterpret_cast<R *>(S.phi2[1 - par]);
+    const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
+    const bool energies = (c == 0);
+    const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+    for (int e = tid; e < np; e += NT) {
+      const int j = e / n3, k = e - j * n3;
+      const size_t g = pbase + e;
+      R ph;
+      if (use_d) ph = (R)(ca * (double)phi[g] + cb * (double)dd[g]);
+      else ph = (R)(ca * (double)phi[g]);
+      if (c == 0) phit[g] = ph;
+      const R n = ph * ph;
+      R x;
+      if (fb == 0) x = ph;
+      else if (fb == 1) x = n;
+      else {
+        const R f = rpow(n, a);
+        x = (fb == 2) ? f : (f - n0a) * (n - n0);
+      }
+      if (energies) {
+        const double nd = (double)n;
+        if (!(nd == nd) || nd > 1e300) bad += 1.0;
+        if (nd > 0.0) {
+          nel += nd;
+          if (do_tf) {
+            double eta, psi;
+            bad += fd_lookup(log(nd) - S.lnnT, fd, eta, psi);
+            e_tf += S.T * nd * psi;
+          }
+          if (do_xc) {
+            double eps, v;
+            pz81(nd, eps, v);
+            e_xc += nd * eps;
+          }
         }
       }
+      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
+      slot[j & 1] = x * invM;
     }
-    R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
-    slot[j & 1] = x * invM;
+  } else {
+    // residual of the accepted trial point, stored for the update pass
+    const R *g = reinterpret_cast<const R *>(S.grad);
+    const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
+    R *rt = reinterpret_cast<R *>(S.r2[1 - par]);
+    const R mu2 = (R)(2.0 * st->mut);
+    for (int e = tid; e < np; e += NT) {
+      const int j = e / n3, k = e - j * n3;
+      const size_t gi = pbase + e;
+      const R x = g[gi] - mu2 * phit[gi];
+      rt[gi] = x;
+      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
+      slot[j & 1] = x * invM;
+    }
   }
   __syncthreads();
-  // real-to-complex along z: pairs of rows as one complex row of length n3
-  fft_lds<V, MAXB_A, false>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
-  {
-    const int nk = n3 / 2 + 1;
-    int per = (MAXB_A * NT) / nk;
-    if (per < 1) per = 1;
-    for (int p0 = 0; p0 < n2 / 2; p0 += per) {
-      const int p1 = min(n2 / 2, p0 + per);
-      const int tot = (p1 - p0) * nk;
-      V A[MAXB_A], B[MAXB_A];
-#pragma unroll
-      for (int i = 0; i < MAXB_A; ++i) {
-        const int e = tid + i * NT;
-        if (e < tot) {
-          const int p = p0 + e / nk, k = e % nk;
-          const V X = buf[p * 2 * pl + k];
-          const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
-          A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
-          B[i].x = (R)0.5 * (X.y + Xm.y); B[i].y = (R)-0.5 * (X.x - Xm.x);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < MAXB_A; ++i) {
-        const int e = tid + i * NT;
-        if (e < tot) {
-          const int p = p0 + e / nk, k = e % nk;
-          buf[(2 * p) * pl + k] = A[i];
-          buf[(2 * p + 1) * pl + k] = B[i];
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // complex transform along y for every z column
-  fft_lds<V, MAXB_A, false>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
-  V *spec = reinterpret_cast<V *>(S.spec) + (size_t)S.slot[fb] * S.H;
+  plane_forward<V, R, NT>(buf, S, tw2, tw3, tid);
+  V *spec = reinterpret_cast<V *>(S.spec) +
+            (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H;
   const size_t obase = (size_t)plane * n2 * S.pitch;
   for (int e = tid; e < n2 * nh; e += NT) {
     const int j = e / nh, k = e - j * nh;
     spec[obase + (size_t)j * S.pitch + k] = buf[j * pl + k];
   }
-  if (energies) {
+  if (MODE == MODE_EVAL && c == 0) {
     double v[PART_A] = {e_tf, e_xc, nel, bad};
     double tot[PART_A];
     __syncthreads();
@@ -204,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
 // ---------------------------------------------------------------------------
 // Pass B
 // ---------------------------------------------------------------------------
-template <typename R, int NT, int TK>
+template <typename R, int NT, int TK, int MODE>
 __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, int nsolve,
                                               int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
@@ -214,12 +298,12 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
   const OptState *st = S.st;
-  if (!eval_phase(st->phase)) return;
+  if (!active_phase<MODE>(st->phase)) return;
   const int tid = threadIdx.x;
   const int local = item - first[s];
   const int j = local / S.nkb, kb = local % S.nkb;
   const int k0 = kb * TK;
-  const int n1 = S.n1, nf = S.nf, W = nf * TK;
+  const int n1 = S.n1, nf = MODE == MODE_EVAL ? S.nf : 1, W = nf * TK;
   V *tile = reinterpret_cast<V *>(smem);
   V *tw1 = tile + n1 * W;
   load_twiddles(tw1, twbank, S.p1.tw, n1, tid, NT);
@@ -241,73 +325,85 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     }
     return;
   }
-
-  const unsigned terms = S.terms;
-  const bool do_vw = terms & 2u, do_nl0 = terms & 4u, do_nl1 = (terms & 8u) && S.beta != 0.0;
-  const bool do_h = terms & 16u, do_loc = terms & 32u;
-  const int sphi = S.slot[0], sn = S.slot[1], sf = S.slot[2], sh = S.slot[3];
-  const V *vloc = reinterpret_cast<const V *>(S.vloc);
   const double kscale = S.kscale;
-  const R b3 = (R)(S.beta / 3.0);
   const int g2 = gidx(j, S.n2);
   double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
-  const double FOURPI = 12.566370614359172954;
-  for (int e = tid; e < n1 * TK; e += NT) {
-    const int i = e / TK, kk = e - i * TK;
-    const int k3 = k0 + kk;
-    if (k3 >= S.nh || S.debug) continue;
-    const int g1 = gidx(i, n1);
-    const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
-    const double G2 = kscale * (double)sidx;
-    const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
-    V *row = tile + i * W;
-    if (sphi >= 0) {
-      V x = row[sphi * TK + kk];
-      if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
-      const R g2r = (R)G2;
-      x.x *= g2r; x.y *= g2r;
-      row[sphi * TK + kk] = x;
+  if (MODE == MODE_PREC) {
+    for (int e = tid; e < n1 * TK; e += NT) {
+      const int i = e / TK, kk = e - i * TK;
+      const int k3 = k0 + kk;
+      if (k3 >= S.nh) continue;
+      const int g1 = gidx(i, n1);
+      const double G2 = kscale * (double)(g1 * g1 + g2 * g2 + k3 * k3);
+      const R pg = (R)(1.0 / (G2 + S.kappa));
+      V x = tile[i * W + kk];
+      x.x *= pg; x.y *= pg;
+      tile[i * W + kk] = x;
     }
-    {
-      const V x = row[sn * TK + kk];
-      const size_t vi = ((size_t)i * S.n2 + j) * S.pitch + k3;
-      double bx = 0.0, by = 0.0;
-      if (do_h && sidx > 0) {
-        const double m2 = (double)x.x * x.x + (double)x.y * x.y;
-        eh += wgt * m2 / G2;
-        bx = FOURPI * x.x / G2;
-        by = FOURPI * x.y / G2;
+  } else {
+    const unsigned terms = S.terms;
+    const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
+    const bool do_h = terms & 16u, do_loc = terms & 32u;
+    const int sphi = S.slot[0], sn = S.slot[1], sf = S.slot[2], sh = S.slot[3];
+    const V *vloc = reinterpret_cast<const V *>(S.vloc);
+    const R b3 = (R)(S.beta / 3.0);
+    const double FOURPI = 12.566370614359172954;
+    for (int e = tid; e < n1 * TK; e += NT) {
+      const int i = e / TK, kk = e - i * TK;
+      const int k3 = k0 + kk;
+      if (k3 >= S.nh || S.debug) continue;
+      const int g1 = gidx(i, n1);
+      const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+      const double G2 = kscale * (double)sidx;
+      const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
+      V *row = tile + i * W;
+      if (sphi >= 0) {
+        V x = row[sphi * TK + kk];
+        if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
+        const R g2r = (R)G2;
+        x.x *= g2r; x.y *= g2r;
+        row[sphi * TK + kk] = x;
       }
-      if (do_loc) {
-        const V vl = vloc[vi];
-        eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
-        bx += vl.x;
-        by += vl.y;
+      {
+        const V x = row[sn * TK + kk];
+        const size_t vi = ((size_t)i * S.n2 + j) * S.pitch + k3;
+        double bx = 0.0, by = 0.0;
+        if (do_h && sidx > 0) {
+          const double m2 = (double)x.x * x.x + (double)x.y * x.y;
+          eh += wgt * m2 / G2;
+          bx = FOURPI * x.x / G2;
+          by = FOURPI * x.y / G2;
+        }
+        if (do_loc) {
+          const V vl = vloc[vi];
+          eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
+          bx += vl.x;
+          by += vl.y;
+        }
+        if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
+        V o; o.x = (R)bx; o.y = (R)by;
+        row[sn * TK + kk] = o;
       }
-      if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
-      V o; o.x = (R)bx; o.y = (R)by;
-      row[sn * TK + kk] = o;
-    }
-    if (sf >= 0) {
-      const V f = row[sf * TK + kk];
-      const R w = (R)S.w[sidx];
-      const R wp = (R)S.wp[sidx];
-      V P; P.x = 0; P.y = 0;
-      if (do_nl0) {
-        ef0 += wgt * (double)w * ((double)f.x * f.x + (double)f.y * f.y);
-        P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
+      if (sf >= 0) {
+        const V f = row[sf * TK + kk];
+        const R w = (R)S.w[sidx];
+        const R wp = (R)S.wp[sidx];
+        V P; P.x = 0; P.y = 0;
+        if (do_nl0) {
+          ef0 += wgt * (double)w * ((double)f.x * f.x + (double)f.y * f.y);
+          P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
+        }
+        if (sh >= 0) {
+          const V h = row[sh * TK + kk];
+          ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
+          P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
+          V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
+          row[sh * TK + kk] = Q;
+        }
+        row[sf * TK + kk] = P;
       }
-      if (sh >= 0) {
-        const V h = row[sh * TK + kk];
-        ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
-        P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
-        V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
-        row[sh * TK + kk] = Q;
-      }
-      row[sf * TK + kk] = P;
     }
   }
-  (void)do_nl1;
   __syncthreads();
   fft_lds<V, 4, true>(tile, S.p1, W, W, 1, tw1, tid, NT);
   for (int e = tid; e < n1 * W; e += NT) {
@@ -316,12 +412,14 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     if (k0 + kk < S.nh)
       spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] = tile[e];
   }
-  double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
-  double tot[PART_B];
-  __syncthreads();
-  block_reduce<PART_B>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
-  if (tid == 0)
-    for (int q = 0; q < PART_B; ++q) S.partB[local * PART_B + q] = tot[q];
+  if (MODE == MODE_EVAL) {
+    double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
+    double tot[PART_B];
+    __syncthreads();
+    block_reduce<PART_B>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+    if (tid == 0)
+      for (int q = 0; q < PART_B; ++q) S.partB[local * PART_B + q] = tot[q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
 // (ACC_LDS, when both fit) or in the output buffer itself, whose plane the
 // workgroup revisits while it is still in L2.
 // ---------------------------------------------------------------------------
-template <typename R, int NT, bool ACC_LDS>
+template <typename R, int NT, bool ACC_LDS, int MODE>
 __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, int nsolve,
                                               int grid, const double *twbank, FDTable fd) {
   typedef typename Vec2<R>::T V;
@@ -341,7 +439,8 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
   const OptState *st = S.st;
-  if (!eval_phase(st->phase)) return;
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
   const int tid = threadIdx.x;
   const int plane = item - first[s];
   const int n2 = S.n2, n3 = S.n3, nh = S.nh;
@@ -351,10 +450,29 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   V *tw3 = tw2 + n2;
   load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
-  const R *phit = reinterpret_cast<const R *>(S.phit);
-  R *grad = reinterpret_cast<R *>(S.grad);
   const size_t pbase = (size_t)plane * n2 * n3;
   const int np = n2 * n3;
+  const V *spec = reinterpret_cast<const V *>(S.spec);
+  const size_t ibase = (size_t)plane * n2 * S.pitch;
+
+  if (MODE == MODE_PREC) {
+    R *out = reinterpret_cast<R *>(S.pr2[1 - par]);
+    for (int e = tid; e < n2 * nh; e += NT) {
+      const int j = e / nh, k = e - j * nh;
+      buf[j * pl + k] = spec[ibase + (size_t)j * S.pitch + k];
+    }
+    __syncthreads();
+    plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
+    for (int e = tid; e < np; e += NT) {
+      const int j = e / n3, k = e - j * n3;
+      const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
+      out[pbase + e] = cv[j & 1];
+    }
+    return;
+  }
+
+  const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
+  R *grad = reinterpret_cast<R *>(S.grad);
   R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : grad + pbase;
   const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
   const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
@@ -372,8 +490,6 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
     }
     acc[e] = v0;
   }
-  const V *spec = reinterpret_cast<const V *>(S.spec);
-  const size_t ibase = (size_t)plane * n2 * S.pitch;
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0 || (S.debug && fb != 0)) continue;
@@ -384,49 +500,7 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
       buf[j * pl + k] = src[(size_t)j * S.pitch + k];
     }
     __syncthreads();
-    fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
-    // complex-to-real along z, two rows at a time: X = A + i B over the full
-    // row, A and B Hermitian-extended; the planes k = 0 and k = n3/2 keep
-    // only their real parts (real part of the plane-wave sum)
-    {
-      int per = (MAXB_C * 2 * NT) / n3;
-      if (per < 1) per = 1;
-      for (int p0 = 0; p0 < n2 / 2; p0 += per) {
-        const int p1 = min(n2 / 2, p0 + per);
-        const int tot = (p1 - p0) * n3;
-        V X[MAXB_C * 2];
-#pragma unroll
-        for (int i = 0; i < MAXB_C * 2; ++i) {
-          const int e = tid + i * NT;
-          if (e < tot) {
-            const int p = p0 + e / n3, k = e % n3;
-            V Av, Bv;
-            if (2 * k <= n3) {
-              Av = buf[(2 * p) * pl + k];
-              Bv = buf[(2 * p + 1) * pl + k];
-              if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
-            } else {
-              Av = buf[(2 * p) * pl + n3 - k];
-              Bv = buf[(2 * p + 1) * pl + n3 - k];
-              Av.y = -Av.y; Bv.y = -Bv.y;
-            }
-            X[i].x = Av.x - Bv.y;
-            X[i].y = Av.y + Bv.x;
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXB_C * 2; ++i) {
-          const int e = tid + i * NT;
-          if (e < tot) {
-            const int p = p0 + e / n3, k = e % n3;
-            buf[p * 2 * pl + k] = X[i];
-          }
-        }
-        __syncthreads();
-      }
-    }
-    fft_lds<V, MAXB_C, true>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
+    plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
     for (int e = tid; e < np; e += NT) {
       const int j = e / n3, k = e - j * n3;
       const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
@@ -470,27 +544,47 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
 // ---------------------------------------------------------------------------
 template <typename R>
 static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
-  if (b.gridA > 0 && (mask & 1))
-    hipLaunchKernelGGL((k_passA<R, 256>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev, b.firstA,
-                       b.nsolve, b.gridA, b.twbank, b.fd);
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   constexpr int NTC = 512;
+  if (b.gridA > 0 && (mask & 1))
+    hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
+                       b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
   if (b.gridB > 0 && (mask & 2))
-    hipLaunchKernelGGL((k_passB<R, 256, TK>), dim3(b.gridB), dim3(256), b.ldsB, s, b.dev,
-                       b.firstB, b.nsolve, b.gridB, b.twbank);
+    hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
+                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4)) {
     if (b.accC_lds)
-      hipLaunchKernelGGL((k_passC<R, NTC, true>), dim3(b.gridC), dim3(NTC), b.ldsC, s, b.dev,
-                         b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+      hipLaunchKernelGGL((k_passC<R, NTC, true, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC, s,
+                         b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     else
-      hipLaunchKernelGGL((k_passC<R, NTC, false>), dim3(b.gridC), dim3(NTC), b.ldsC, s, b.dev,
-                         b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+      hipLaunchKernelGGL((k_passC<R, NTC, false, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC,
+                         s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   }
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
+  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
+  // one field per solve: pass A has one workgroup per plane, like pass C
+  if (b.gridC > 0 && (mask & 1))
+    hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
+                       b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+  if (b.gridB > 0 && (mask & 2))
+    hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
+                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
+  if (b.gridC > 0 && (mask & 4))
+    hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
+                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   return hipGetLastError();
 }
 
 hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask) {
   return b.prec == 0 ? launch_eval_t<double>(b, s, mask) : launch_eval_t<float>(b, s, mask);
+}
+
+hipError_t launch_prec(const BatchLaunch &b, hipStream_t s, int mask) {
+  return b.prec == 0 ? launch_prec_t<double>(b, s, mask) : launch_prec_t<float>(b, s, mask);
 }
 
 }  // namespace skx

@@ -280,7 +280,7 @@ __global__ void k_uniform_gas(double *out, double n0, double T, FDTable fd) {
 }
 
 hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double n0, double T,
-                               double a, const FDTable &fd, double *eta0_out, hipStream_t s) {
+                               double a, const FDTable &fd, double *gas_out, hipStream_t s) {
   double *tmp = nullptr;
   hipError_t e = hipMallocAsync((void **)&tmp, 4 * sizeof(double), s);
   if (e != hipSuccess) return e;
@@ -290,7 +290,7 @@ hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFreeAsync(tmp, s);
   if (e != hipSuccess) return e;
-  if (eta0_out) *eta0_out = host[0];
+  if (gas_out) { gas_out[0] = host[0]; gas_out[1] = host[1]; gas_out[2] = host[2]; }
   hipLaunchKernelGGL(k_kernel_tables, dim3((smax + 1 + 63) / 64), dim3(64), 0, s, w, wp, smax, L,
                      n0, T, a, host[0], host[1], host[2]);
   return hipGetLastError();

@@ -108,6 +108,9 @@ _sig("skx_fd_eval", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_doub
                               C.POINTER(C.c_double), C.c_longlong])
 _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)])
+_sig("skx_profile_enable", C.c_int, [C.c_int])
+_sig("skx_profile_reset", C.c_int, [])
+_sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
 _sig("skx_engine_create", C.c_int, [C.POINTER(_VP), C.c_int, C.c_size_t, C.c_int])
 _sig("skx_engine_submit", C.c_int, [_VP, C.POINTER(Request), C.POINTER(C.c_uint64)])
 _sig("skx_engine_step", C.c_int, [_VP])
@@ -276,6 +279,25 @@ def run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, 
     if rc < 0:
         raise SkxError(rc, _lib.skx_last_error(ctxs[0]._h).decode())
     return [r.as_dict() for r in res]
+
+
+PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond")
+
+
+def profile_enable(on=True):
+    _lib.skx_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.skx_profile_reset()
+
+
+def profile_read():
+    """{pass name: (total ms, launches)} from the library's HIP-event timers."""
+    ms = (C.c_double * 8)()
+    cnt = (C.c_longlong * 8)()
+    n = _lib.skx_profile_read(ms, cnt, 8)
+    return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(min(n, len(PASS_NAMES)))}
 
 
 def exported_symbols():
