@@ -47,9 +47,11 @@ def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
     Hh = n1 * n2 * (n3 // 2 + 1)          # half-spectrum complex entries
     b = prec_bytes
     spec = 2 * b * Hh                     # one half spectrum
-    a = (2 if phase_trial else 1) * b * M + b * M + nf * spec
+    # A: phi (+ d) in; phi_t, local potential, n^a and nf half spectra out
+    a = (2 if phase_trial else 1) * b * M + 3 * b * M + nf * spec
     bb = 2 * nf * spec + (spec if with_loc else 0)
-    c = nf * spec + 2 * b * M
+    # C: nf half spectra, phi_t, local potential, n^a in; dE/dphi out
+    c = nf * spec + 4 * b * M
     return a, bb, c
 
 

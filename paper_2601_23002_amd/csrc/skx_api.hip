@@ -20,8 +20,8 @@ namespace {
 // Per-device resources shared by all contexts: FFT twiddle bank and the
 // universal Fermi-Dirac Chebyshev table.
 // ---------------------------------------------------------------------------
-constexpr double FD_Y0 = -46.0, FD_DY = 0.5;
-constexpr int FD_NSEG = 124, FD_DEG = 20;     // covers ln(n/n_T) in [-46, 16)
+constexpr double FD_Y0 = -46.0, FD_H = 1.0 / 64.0;
+constexpr int FD_N = 62 * 64;                 // covers ln(n/n_T) in [-46, 16)
 
 struct DeviceRes {
   bool ready = false;
@@ -73,18 +73,16 @@ hipError_t init_device(int dev, std::string &err) {
   hipFree(dsz);
   hipFree(doff);
   if (e != hipSuccess) { err = "twiddle kernel failed"; return e; }
-  size_t nc = (size_t)FD_NSEG * 2 * (FD_DEG + 1);
-  e = hipMalloc((void **)&r.fdcoef, sizeof(double) * nc);
+  e = hipMalloc((void **)&r.fdcoef, sizeof(double) * 4 * (FD_N + 1));
   if (e != hipSuccess) { err = "FD table allocation failed"; return e; }
-  e = build_fd_table(r.fdcoef, FD_Y0, FD_DY, FD_NSEG, FD_DEG, 0);
+  e = build_fd_table(r.fdcoef, FD_Y0, FD_H, FD_N, 0);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) { err = "FD table kernel failed"; return e; }
   r.fd.y0 = FD_Y0;
-  r.fd.dy = FD_DY;
-  r.fd.inv_dy = 1.0 / FD_DY;
-  r.fd.nseg = FD_NSEG;
-  r.fd.deg = FD_DEG;
-  r.fd.coef = r.fdcoef;
+  r.fd.h = FD_H;
+  r.fd.inv_h = 1.0 / FD_H;
+  r.fd.n = FD_N;
+  r.fd.node = r.fdcoef;
   r.ready = true;
   return hipSuccess;
 }
@@ -177,7 +175,7 @@ int fields_mask(unsigned terms, double beta) {
 void lds_sizes(const SolveDev &h, int prec, size_t &a, size_t &b, size_t &c) {
   size_t v = prec == 0 ? 16 : 8;
   a = v * ((size_t)h.n2 * h.nh + h.n2 + h.n3);
-  b = v * ((size_t)h.n1 * h.nf * h.tk + h.n1);
+  b = v * ((size_t)h.n1 * (h.nf * h.tk + 1) + h.n1);
   c = a;
   a = std::max(a, (size_t)1024);
   b = std::max(b, (size_t)1024);
@@ -209,10 +207,10 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   size_t o_phi = take(rsz * M), o_phit = take(rsz * M), o_grad = take(rsz * M);
   size_t o_r = take(rsz * M), o_rt = take(rsz * M), o_pr = take(rsz * M), o_prt = take(rsz * M);
-  size_t o_d = take(rsz * M);
+  size_t o_d = take(rsz * M), o_vpt = take(rsz * M), o_fpt = take(rsz * M);
   size_t o_S = take(rsz * M * m), o_Y = take(rsz * M * m);
   size_t o_spec = take(2 * rsz * H * NFIELD), o_vloc = take(2 * rsz * H);
-  size_t o_pA = take(8 * (size_t)n1 * PART_A), o_pB = take(8 * (size_t)n2 * nkb * PART_B);
+  size_t o_pA = take(8 * (size_t)n1 * NFIELD * PART_A), o_pB = take(8 * (size_t)n2 * nkb * PART_B);
   size_t o_pC = take(8 * (size_t)n1 * PART_C), o_pU = take(8 * (size_t)nwg * NDOT);
   size_t o_pD = take(8 * (size_t)nwg * 2);
   hipError_t e = hipMalloc(&I.mem, off);
@@ -236,6 +234,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.phi2[0] = base + o_phi; h.phi2[1] = base + o_phit; h.grad = base + o_grad;
   h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
   h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
+  h.vpt = base + o_vpt; h.fpt = base + o_fpt;
   h.spec = base + o_spec; h.vloc = base + o_vloc;
   h.partA = (double *)(base + o_pA); h.partB = (double *)(base + o_pB);
   h.partC = (double *)(base + o_pC); h.partU = (double *)(base + o_pU);

@@ -95,6 +95,25 @@ template <bool INV, typename V> struct Bfly<5, INV, V> {
 };
 
 // ---------------------------------------------------------------------------
+// Division by a workgroup-uniform divisor d <= 2^16 for x < 2^16:
+// q = floor(x * ceil(2^32/d) / 2^32) is exact in that range (the rounding
+// term is below 2^-16 <= 1/d), and costs one 32x64 multiply.
+// ---------------------------------------------------------------------------
+struct UDiv {
+  unsigned d;
+  unsigned long long m;
+};
+__device__ __forceinline__ UDiv make_udiv(unsigned d) {
+  UDiv r;
+  r.d = d;
+  r.m = ((1ull << 32) + d - 1) / d;
+  return r;
+}
+__device__ __forceinline__ unsigned udiv(unsigned x, const UDiv &v) {
+  return (unsigned)(((unsigned long long)x * v.m) >> 32);
+}
+
+// ---------------------------------------------------------------------------
 // One Stockham stage over `count` transforms of length N held in LDS.
 // Element e of transform t sits at buf[t*ts + e*es]. Butterflies are staged
 // in registers: every thread first reads all of its butterflies of a group
@@ -108,16 +127,20 @@ __device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int 
   int per = (MAXB * nthr) / nb;
   if (per < 1) per = 1;
   const int twstep = N / (Ns * RAD);
+  const UDiv dnb = make_udiv((unsigned)nb), dns = make_udiv((unsigned)Ns);
   for (int t0 = 0; t0 < count; t0 += per) {
     const int t1 = (t0 + per < count) ? t0 + per : count;
     const int gtot = (t1 - t0) * nb;
     V v[MAXB][RAD];
+    int tq[MAXB], jq[MAXB];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
       const int b = tid + i * nthr;
+      const int q = (int)udiv((unsigned)b, dnb);
+      tq[i] = t0 + q;
+      jq[i] = b - q * nb;
       if (b < gtot) {
-        const int t = t0 + b / nb, j = b - (b / nb) * nb;
-        const V *base = buf + t * ts + j * es;
+        const V *base = buf + tq[i] * ts + jq[i] * es;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) v[i][r] = base[r * nb * es];
       }
@@ -127,8 +150,8 @@ __device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int 
     for (int i = 0; i < MAXB; ++i) {
       const int b = tid + i * nthr;
       if (b < gtot) {
-        const int t = t0 + b / nb, j = b - (b / nb) * nb;
-        const int k = j % Ns;
+        const int j = jq[i];
+        const int k = j - (int)udiv((unsigned)j, dns) * Ns;
         if (Ns > 1) {
 #pragma unroll
           for (int r = 1; r < RAD; ++r) {
@@ -137,7 +160,7 @@ __device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int 
           }
         }
         Bfly<RAD, INV, V>::run(v[i]);
-        V *out = buf + t * ts + ((j - k) * RAD + k) * es;
+        V *out = buf + tq[i] * ts + ((j - k) * RAD + k) * es;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) out[r * Ns * es] = v[i][r];
       }
@@ -147,8 +170,8 @@ __device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int 
 }
 
 template <typename V, int MAXB, bool INV>
-__device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int es, int ts, const V *tw, int tid,
-                        int nthr) {
+__device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int es, int ts,
+                                        const V *tw, int tid, int nthr) {
   const int n = pl.n, nst = pl.nst;
   const unsigned code = pl.rad;
   int Ns = 1;
@@ -166,37 +189,46 @@ __device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int e
 
 // ---------------------------------------------------------------------------
 // Universal Fermi-Dirac table: eta and psi = f_TF / (n T) as functions of
-// y = ln(n / n_T). Below the table the non-degenerate limit is exact to
-// double precision; above it the value is clamped and flagged.
+// y = ln(n / n_T), by quintic Hermite interpolation between nodes that store
+// eta, eta', eta'' and psi (psi' = eta - psi and psi'' = eta' - eta + psi
+// follow from d(u psi)/du = eta). One lookup reads 64 contiguous bytes.
+// Below the table the non-degenerate limit is exact to double precision;
+// above it the value is clamped and flagged.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fd_lookup(double y, const FDTable &fd, double &eta, double &psi) {
   const double LN_G32 = -0.12078223763524522;    // ln Gamma(3/2)
-  double t = (y - fd.y0) * fd.inv_dy;
+  double t = (y - fd.y0) * fd.inv_h;
   if (t < 0.0) { eta = y - LN_G32; psi = eta - 1.0; return 0; }
-  int sg = (int)t;
+  int k = (int)t;
   int bad = 0;
-  if (sg >= fd.nseg) { sg = fd.nseg - 1; bad = 1; }
-  double x = 2.0 * (t - sg) - 1.0;
-  const double *c0 = fd.coef + (size_t)sg * 2 * (fd.deg + 1);
-  const double *c1 = c0 + (fd.deg + 1);
-  double b1 = 0, b2 = 0, e1 = 0, e2 = 0;
-  for (int k = fd.deg; k >= 1; --k) {
-    double b0 = c0[k] + 2.0 * x * b1 - b2; b2 = b1; b1 = b0;
-    double a0 = c1[k] + 2.0 * x * e1 - e2; e2 = e1; e1 = a0;
-  }
-  eta = c0[0] + x * b1 - b2;
-  psi = c1[0] + x * e1 - e2;
+  if (k >= fd.n) { k = fd.n - 1; bad = 1; }
+  const double s = t - k;
+  const double4 a = reinterpret_cast<const double4 *>(fd.node)[k];
+  const double4 b = reinterpret_cast<const double4 *>(fd.node)[k + 1];
+  const double h = fd.h;
+  const double s2 = s * s, s3 = s2 * s, s4 = s3 * s, s5 = s4 * s;
+  const double h0 = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
+  const double h1 = s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5;
+  const double h2 = 0.5 * s2 - 1.5 * s3 + 1.5 * s4 - 0.5 * s5;
+  const double h3 = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
+  const double h4 = -4.0 * s3 + 7.0 * s4 - 3.0 * s5;
+  const double h5 = 0.5 * s3 - s4 + 0.5 * s5;
+  eta = a.x * h0 + h * (a.y * h1 + h * a.z * h2) + b.x * h3 + h * (b.y * h4 + h * b.z * h5);
+  const double pa1 = a.x - a.w, pa2 = a.y - a.x + a.w;
+  const double pb1 = b.x - b.w, pb2 = b.y - b.x + b.w;
+  psi = a.w * h0 + h * (pa1 * h1 + h * pa2 * h2) + b.w * h3 + h * (pb1 * h4 + h * pb2 * h5);
   return bad;
 }
 
 // Perdew-Zunger 1981 LDA (spin-unpolarised): energy per electron and
-// potential. The paper uses PZ LDA in the adiabatic approximation.
-__device__ __forceinline__ void pz81(double n, double &eps, double &v) {
-  if (!(n > 0.0)) { eps = 0.0; v = 0.0; return; }
-  const double PI = 3.14159265358979323846;
+// potential, from x = ln n (rs = (3/(4 pi))^(1/3) exp(-x/3)). The paper uses
+// PZ LDA in the adiabatic approximation.
+__device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
+  const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
-  double rs = cbrt(3.0 / (4.0 * PI * n));
-  double ex = -CX / rs;
+  const double e3 = exp(x * (1.0 / 3.0));
+  double rs = RS1 / e3;
+  double ex = -CX / RS1 * e3;
   double ec, vc;
   if (rs >= 1.0) {
     const double G = -0.1423, B1 = 1.0529, B2 = 0.3334;
@@ -206,7 +238,7 @@ __device__ __forceinline__ void pz81(double n, double &eps, double &v) {
     vc = G * (1.0 + (7.0 / 6.0) * B1 * sq + (4.0 / 3.0) * B2 * rs) / (den * den);
   } else {
     const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
-    double lr = log(rs);
+    double lr = log(RS1) - x * (1.0 / 3.0);
     ec = A * lr + B + C * rs * lr + D * rs;
     vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + (2.0 * D - C) * rs / 3.0;
   }
@@ -243,6 +275,40 @@ __device__ __forceinline__ void block_reduce(double (&vals)[N], double *sh, int 
       for (int w = 0; w < nw; ++w) acc += sh[w * N + q];
       out[q] = acc;
     }
+  }
+  __syncthreads();
+}
+
+// Workgroup sums of up to 64 values per thread (N <= 64). Within a
+// wavefront a reduce-scatter butterfly halves the values per lane at every
+// exchange (63 shuffles in all instead of 6 N), after which lane q holds
+// the wavefront total of value q; the wavefront totals are then summed in a
+// fixed order (deterministic). sh must hold 64 * (nthr / 64) doubles; the
+// totals land in out[0..N) (written by threads 0..N-1).
+template <int N>
+__device__ __forceinline__ void block_reduce_many(const double (&vals)[N], double *sh, int tid,
+                                                  int nthr, double *out) {
+  static_assert(N <= 64, "at most 64 values");
+  double w[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q) w[q] = (q < N) ? vals[q] : 0.0;
+  const int lane = tid & 63, wid = tid >> 6, nw = nthr >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < off; ++i) {
+      const double send = up ? w[i] : w[off + i];
+      const double keep = up ? w[off + i] : w[i];
+      w[i] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  sh[wid * 64 + lane] = w[0];
+  __syncthreads();
+  if (tid < N) {
+    double acc = 0.0;
+    for (int v = 0; v < nw; ++v) acc += sh[v * 64 + tid];
+    out[tid] = acc;
   }
   __syncthreads();
 }

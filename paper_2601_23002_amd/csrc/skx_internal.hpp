@@ -68,23 +68,23 @@ struct SolveDev {
   double kappa;                    // preconditioner P(G) = 1 / (G^2 + kappa)
   void *phi2[2], *r2[2], *pr2[2];  // current / trial point pairs (see OptState::par)
   void *grad, *d, *S, *Y;          // real fields (fp64 or fp32); Y holds P y
+  void *vpt, *fpt;                 // T eta + v_xc and n^a at the trial point (pass A -> C)
   void *spec, *vloc;                         // complex spectra
   const double *w, *wp;                      // shell tables
   double *partA, *partB, *partC, *partU, *partD;
   OptState *st;
 };
 
-struct FDTable {                   // Chebyshev segments of eta(y), psi(y), y = ln(n/n_T)
-  double y0, inv_dy, dy;
-  int nseg, deg;
-  const double *coef;              // [nseg][2][deg+1]
+struct FDTable {                   // nodes of eta(y), psi(y) on y = y0 + k h, y = ln(n/n_T)
+  double y0, inv_h, h;
+  int n;                           // intervals; n + 1 nodes
+  const double *node;              // [n+1][4]: eta, d eta/dy, d2 eta/dy2, psi
 };
 
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t build_twiddles(double *bank_dev, const int *sizes, const int *offsets, int nsizes,
                           hipStream_t s);
-hipError_t build_fd_table(double *coef_dev, double y0, double dy, int nseg, int deg,
-                          hipStream_t s);
+hipError_t build_fd_table(double *node_dev, double y0, double h, int n, hipStream_t s);
 hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double n0, double T,
                                double a, const FDTable &fd, double *gas_out /* eta0, I_-1/2, dI_-1/2 */,
                                hipStream_t s);

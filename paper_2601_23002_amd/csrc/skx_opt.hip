@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
   const int ph = st->phase;
   if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
   const int tid = threadIdx.x;
-  sum_parts<PART_A>(S.partA, S.n1, sh, tid, 256, tA);
+  sum_parts<PART_A>(S.partA, S.n1 * S.nf, sh, tid, 256, tA);
   sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
   sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
   if (tid != 0) return;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
                                                int grid) {
-  __shared__ double sh[NDOT * (NT / 64)];
+  __shared__ double sh[64 * (NT / 64)];
   __shared__ double tot[NDOT];
   const int item = blockIdx.x;
   const int s = find_solve(first, nsolve, item);
@@ -208,13 +208,12 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
       Ynew[g] = pyv;
     }
   }
-  block_reduce<NDOT>(acc, sh, tid, NT, tot);
-  if (tid == 0)
-    for (int q = 0; q < NDOT; ++q) S.partU[wl * NDOT + q] = tot[q];
+  block_reduce_many<NDOT>(acc, sh, tid, NT, tot);
+  if (tid < NDOT) S.partU[wl * NDOT + tid] = tot[tid];
 }
 
 __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsolve) {
-  __shared__ double sh[NDOT * 4];
+  __shared__ double sh[64 * 4];
   __shared__ double t[NDOT];
   const int s = blockIdx.x;
   if (s >= nsolve) return;
@@ -222,7 +221,15 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
   OptState *st = S.st;
   if (st->phase != PH_UPDATE) return;
   const int tid = threadIdx.x;
-  sum_parts<NDOT>(S.partU, S.nwg_vec, sh, tid, 256, t);
+  {
+    double v[NDOT];
+#pragma unroll
+    for (int q = 0; q < NDOT; ++q) v[q] = 0.0;
+    for (int r = tid; r < S.nwg_vec; r += 256)
+#pragma unroll
+      for (int q = 0; q < NDOT; ++q) v[q] += S.partU[r * NDOT + q];
+    block_reduce_many<NDOT>(v, sh, tid, 256, t);
+  }
   if (tid != 0) return;
   const double dV = S.dV;
   const int B = 6 * MMAX;

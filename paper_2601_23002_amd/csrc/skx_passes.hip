@@ -94,6 +94,7 @@ __device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V
   const int nk = n3 / 2 + 1;
   int per = (MAXB_A * NT) / nk;
   if (per < 1) per = 1;
+  const UDiv dnk = make_udiv((unsigned)nk);
   for (int p0 = 0; p0 < n2 / 2; p0 += per) {
     const int p1 = min(n2 / 2, p0 + per);
     const int tot = (p1 - p0) * nk;
@@ -102,7 +103,8 @@ __device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V
     for (int i = 0; i < MAXB_A; ++i) {
       const int e = tid + i * NT;
       if (e < tot) {
-        const int p = p0 + e / nk, k = e % nk;
+        const int q = (int)udiv((unsigned)e, dnk);
+        const int p = p0 + q, k = e - q * nk;
         const V X = buf[p * 2 * pl + k];
         const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
         A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
@@ -114,7 +116,8 @@ __device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V
     for (int i = 0; i < MAXB_A; ++i) {
       const int e = tid + i * NT;
       if (e < tot) {
-        const int p = p0 + e / nk, k = e % nk;
+        const int q = (int)udiv((unsigned)e, dnk);
+        const int p = p0 + q, k = e - q * nk;
         buf[(2 * p) * pl + k] = A[i];
         buf[(2 * p + 1) * pl + k] = B[i];
       }
@@ -137,6 +140,7 @@ __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V
   fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
   int per = (MAXB_C * 2 * NT) / n3;
   if (per < 1) per = 1;
+  const UDiv dn3 = make_udiv((unsigned)n3);
   for (int p0 = 0; p0 < n2 / 2; p0 += per) {
     const int p1 = min(n2 / 2, p0 + per);
     const int tot = (p1 - p0) * n3;
@@ -145,7 +149,8 @@ __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V
     for (int i = 0; i < MAXB_C * 2; ++i) {
       const int e = tid + i * NT;
       if (e < tot) {
-        const int p = p0 + e / n3, k = e % n3;
+        const int q = (int)udiv((unsigned)e, dn3);
+        const int p = p0 + q, k = e - q * n3;
         V Av, Bv;
         if (2 * k <= n3) {
           Av = buf[(2 * p) * pl + k];
@@ -165,7 +170,8 @@ __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V
     for (int i = 0; i < MAXB_C * 2; ++i) {
       const int e = tid + i * NT;
       if (e < tot) {
-        const int p = p0 + e / n3, k = e % n3;
+        const int q = (int)udiv((unsigned)e, dn3);
+        const int p = p0 + q, k = e - q * n3;
         buf[p * 2 * pl + k] = X[i];
       }
     }
@@ -213,40 +219,52 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
     const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
     const R *dd = reinterpret_cast<const R *>(S.d);
     R *phit = reinterpret_cast<R *>(S.phi2[1 - par]);
+    R *v0 = reinterpret_cast<R *>(S.vpt);
+    R *fpw = reinterpret_cast<R *>(S.fpt);
     const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
-    const bool energies = (c == 0);
     const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+    const bool need_f = (S.fields & F_F) != 0;
+    const UDiv dn3 = make_udiv((unsigned)n3);
     for (int e = tid; e < np; e += NT) {
-      const int j = e / n3, k = e - j * n3;
+      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
       const size_t g = pbase + e;
       R ph;
       if (use_d) ph = (R)(ca * (double)phi[g] + cb * (double)dd[g]);
       else ph = (R)(ca * (double)phi[g]);
       if (c == 0) phit[g] = ph;
       const R n = ph * ph;
+      // the pointwise work of this plane is shared by its field workgroups:
+      // rows j = c (mod nf) get the local energy densities, the local
+      // potential T eta + v_xc and f = n^a stored for the assembly pass
+      const bool mine = (j % nf) == c;
+      R f = 0;
+      if (need_f && (fb >= 2 || mine)) f = rpow(n, a);
       R x;
       if (fb == 0) x = ph;
       else if (fb == 1) x = n;
-      else {
-        const R f = rpow(n, a);
-        x = (fb == 2) ? f : (f - n0a) * (n - n0);
-      }
-      if (energies) {
+      else x = (fb == 2) ? f : (f - n0a) * (n - n0);
+      if (mine) {
         const double nd = (double)n;
+        double v = 0.0;
         if (!(nd == nd) || nd > 1e300) bad += 1.0;
         if (nd > 0.0) {
           nel += nd;
+          const double x = log(nd);
           if (do_tf) {
             double eta, psi;
-            bad += fd_lookup(log(nd) - S.lnnT, fd, eta, psi);
+            bad += fd_lookup(x - S.lnnT, fd, eta, psi);
             e_tf += S.T * nd * psi;
+            v += S.T * eta;
           }
           if (do_xc) {
-            double eps, v;
-            pz81(nd, eps, v);
+            double eps, vx;
+            pz81_ln(x, eps, vx);
             e_xc += nd * eps;
+            v += vx;
           }
         }
+        v0[g] = (R)v;
+        if (need_f) fpw[g] = f;
       }
       R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
       slot[j & 1] = x * invM;
@@ -257,8 +275,9 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
     const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
     R *rt = reinterpret_cast<R *>(S.r2[1 - par]);
     const R mu2 = (R)(2.0 * st->mut);
+    const UDiv dn3 = make_udiv((unsigned)n3);
     for (int e = tid; e < np; e += NT) {
-      const int j = e / n3, k = e - j * n3;
+      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
       const size_t gi = pbase + e;
       const R x = g[gi] - mu2 * phit[gi];
       rt[gi] = x;
@@ -271,17 +290,18 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
   V *spec = reinterpret_cast<V *>(S.spec) +
             (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H;
   const size_t obase = (size_t)plane * n2 * S.pitch;
+  const UDiv dnh = make_udiv((unsigned)nh);
   for (int e = tid; e < n2 * nh; e += NT) {
-    const int j = e / nh, k = e - j * nh;
+    const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
     spec[obase + (size_t)j * S.pitch + k] = buf[j * pl + k];
   }
-  if (MODE == MODE_EVAL && c == 0) {
+  if (MODE == MODE_EVAL) {
     double v[PART_A] = {e_tf, e_xc, nel, bad};
     double tot[PART_A];
     __syncthreads();
     block_reduce<PART_A>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
     if (tid == 0)
-      for (int q = 0; q < PART_A; ++q) S.partA[plane * PART_A + q] = tot[q];
+      for (int q = 0; q < PART_A; ++q) S.partA[local * PART_A + q] = tot[q];
   }
 }
 
@@ -304,24 +324,29 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   const int j = local / S.nkb, kb = local % S.nkb;
   const int k0 = kb * TK;
   const int n1 = S.n1, nf = MODE == MODE_EVAL ? S.nf : 1, W = nf * TK;
+  // one padding element per tile row keeps the x transform (stride Wp)
+  // off a single LDS bank
+  const int Wp = W + 1;
   V *tile = reinterpret_cast<V *>(smem);
-  V *tw1 = tile + n1 * W;
+  V *tw1 = tile + n1 * Wp;
   load_twiddles(tw1, twbank, S.p1.tw, n1, tid, NT);
   V *spec = reinterpret_cast<V *>(S.spec);
   const size_t rowstride = (size_t)S.n2 * S.pitch;
+  const UDiv dW = make_udiv((unsigned)W);
   for (int e = tid; e < n1 * W; e += NT) {
-    const int i = e / W, r = e - i * W;
+    const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
-    tile[e] = spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk];
+    tile[i * Wp + r] = spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk];
   }
   __syncthreads();
-  if (S.debug != 2) fft_lds<V, 4, false>(tile, S.p1, W, W, 1, tw1, tid, NT);
+  if (S.debug != 2) fft_lds<V, 4, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
   if (S.debug == 1) {
     for (int e = tid; e < n1 * W; e += NT) {
-      const int i = e / W, r = e - i * W;
+      const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
       const int cc = r / TK, kk = r - cc * TK;
       if (k0 + kk < S.nh)
-        spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] = tile[e];
+        spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] =
+            tile[i * Wp + r];
     }
     return;
   }
@@ -336,9 +361,9 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       const int g1 = gidx(i, n1);
       const double G2 = kscale * (double)(g1 * g1 + g2 * g2 + k3 * k3);
       const R pg = (R)(1.0 / (G2 + S.kappa));
-      V x = tile[i * W + kk];
+      V x = tile[i * Wp + kk];
       x.x *= pg; x.y *= pg;
-      tile[i * W + kk] = x;
+      tile[i * Wp + kk] = x;
     }
   } else {
     const unsigned terms = S.terms;
@@ -356,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
       const double G2 = kscale * (double)sidx;
       const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
-      V *row = tile + i * W;
+      V *row = tile + i * Wp;
       if (sphi >= 0) {
         V x = row[sphi * TK + kk];
         if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
@@ -405,12 +430,13 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     }
   }
   __syncthreads();
-  fft_lds<V, 4, true>(tile, S.p1, W, W, 1, tw1, tid, NT);
+  fft_lds<V, 4, true>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
   for (int e = tid; e < n1 * W; e += NT) {
-    const int i = e / W, r = e - i * W;
+    const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
     if (k0 + kk < S.nh)
-      spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] = tile[e];
+      spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] =
+          tile[i * Wp + r];
   }
   if (MODE == MODE_EVAL) {
     double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
@@ -457,14 +483,15 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
 
   if (MODE == MODE_PREC) {
     R *out = reinterpret_cast<R *>(S.pr2[1 - par]);
+    const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
     for (int e = tid; e < n2 * nh; e += NT) {
-      const int j = e / nh, k = e - j * nh;
+      const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
       buf[j * pl + k] = spec[ibase + (size_t)j * S.pitch + k];
     }
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
     for (int e = tid; e < np; e += NT) {
-      const int j = e / n3, k = e - j * n3;
+      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
       const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
       out[pbase + e] = cv[j & 1];
     }
@@ -472,37 +499,27 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   }
 
   const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
+  const R *v0 = reinterpret_cast<const R *>(S.vpt);
+  const R *fpw = reinterpret_cast<const R *>(S.fpt);
   R *grad = reinterpret_cast<R *>(S.grad);
   R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : grad + pbase;
-  const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
-  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
-  for (int e = tid; e < np; e += NT) {
-    R v0 = 0;
-    if (!S.debug) {
-      const R p = phit[pbase + e];
-      const double nd = (double)p * (double)p;
-      double v = 0.0;
-      if (nd > 0.0) {
-        if (do_tf) { double eta, psi; fd_lookup(log(nd) - S.lnnT, fd, eta, psi); v += S.T * eta; }
-        if (do_xc) { double eps, vx; pz81(nd, eps, vx); v += vx; }
-      }
-      v0 = (R)(2.0 * (double)p * v);
-    }
-    acc[e] = v0;
-  }
+  const R a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
+  const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
+  for (int e = tid; e < np; e += NT)
+    acc[e] = S.debug ? (R)0 : (R)2 * phit[pbase + e] * v0[pbase + e];
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0 || (S.debug && fb != 0)) continue;
     const V *src = spec + (size_t)sl * S.H + ibase;
     __syncthreads();
     for (int e = tid; e < n2 * nh; e += NT) {
-      const int j = e / nh, k = e - j * nh;
+      const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
       buf[j * pl + k] = src[(size_t)j * S.pitch + k];
     }
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
     for (int e = tid; e < np; e += NT) {
-      const int j = e / n3, k = e - j * n3;
+      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
       const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
       const R val = cv[j & 1];
       R coef;
@@ -513,11 +530,10 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
         if (fb == 1) {
           coef = (R)2 * p;
         } else {
-          const R ap = p < 0 ? -p : p;
-          const R pw = (ap > 0) ? rpow(ap, (R)2 * a - (R)1) : (R)0;
-          const R cP = (R)2 * a * (p < 0 ? -pw : pw);
-          if (fb == 2) coef = cP;
-          else coef = cP * (p * p - n0) + (R)2 * p * (ap * pw - n0a);
+          // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
+          const R f = fpw[pbase + e];
+          const R cP = (p != (R)0) ? a2 * f / p : (R)0;
+          coef = (fb == 2) ? cP : cP * (p * p - n0) + (R)2 * p * (f - n0a);
         }
       }
       acc[e] += coef * val;

@@ -45,8 +45,38 @@ hipError_t build_twiddles(double *bank_dev, const int *sizes, const int *offsets
 // ---------------------------------------------------------------------------
 struct FDSums { double i_m12, i_12, i_32, di_m12; };
 
+// Degenerate limit: the Sommerfeld expansion
+//   I_nu(eta) = eta^(nu+1)/(nu+1) + sum_k 2 (1 - 2^(1-2k)) zeta(2k)
+//               nu (nu-1) ... (nu-2k+2) eta^(nu-2k+1),
+// whose neglected terms are below 1e-17 relative for eta > 300, with
+// exponentially small (exp(-eta)) corrections.
+__device__ void sommerfeld(double nu, double eta, double &val, double &deriv) {
+  const double PI2 = 9.8696044010893586188;
+  const double c[4] = {PI2 / 6.0, 7.0 * PI2 * PI2 / 360.0, 31.0 * PI2 * PI2 * PI2 / 15120.0,
+                       127.0 * PI2 * PI2 * PI2 * PI2 / 604800.0};
+  val = pow(eta, nu + 1.0) / (nu + 1.0);
+  deriv = pow(eta, nu);
+  double fall = nu;                  // nu (nu-1) ... (nu-2k+2)
+  double pw = pow(eta, nu - 1.0);    // eta^(nu-2k+1)
+  for (int k = 1; k <= 4; ++k) {
+    const double ex = nu - 2.0 * k + 1.0;
+    val += c[k - 1] * fall * pw;
+    deriv += c[k - 1] * fall * ex * pw / eta;
+    fall *= (nu - 2.0 * k + 1.0) * (nu - 2.0 * k);
+    pw /= eta * eta;
+  }
+}
+
 __device__ FDSums fd_trapezoid(double eta) {
   const double PI = 3.14159265358979323846;
+  if (eta > 300.0) {
+    FDSums r;
+    double dd;
+    sommerfeld(-0.5, eta, r.i_m12, r.di_m12);
+    sommerfeld(0.5, eta, r.i_12, dd);
+    sommerfeld(1.5, eta, r.i_32, dd);
+    return r;
+  }
   double mod = sqrt(eta * eta + PI * PI);
   double d = sqrt(0.5 * (mod - eta));
   double h = d / 7.0;
@@ -78,7 +108,7 @@ __device__ double fd_invert(double y, FDSums *out) {
   double u = exp(y);
   double eta = (y < 1.0) ? (y - LN_G32) : pow(1.5 * u, 2.0 / 3.0);
   FDSums s{};
-  for (int it = 0; it < 200; ++it) {
+  for (int it = 0; it < 100; ++it) {
     s = fd_trapezoid(eta);
     double g = log(s.i_12) - y;
     double step = g / (0.5 * s.i_m12 / s.i_12);
@@ -90,52 +120,27 @@ __device__ double fd_invert(double y, FDSums *out) {
   return eta;
 }
 
-// One thread per Chebyshev node: values of eta(y) and psi(y) =
-// eta - (2/3) I_3/2(eta) / exp(y), the TF free energy per electron over T.
-__global__ void k_fd_nodes(double *vals, double y0, double dy, int nseg, int deg) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  int nn = deg + 1;
-  if (idx >= nseg * nn) return;
-  int sg = idx / nn, j = idx % nn;
-  const double PI = 3.14159265358979323846;
-  double x = cos(PI * (j + 0.5) / nn);
-  double y = y0 + dy * (sg + 0.5 * (x + 1.0));
+// One thread per node y_k = y0 + k h: eta(y_k), its first two derivatives
+// and psi = eta - (2/3) I_3/2(eta) / u, u = exp(y). With dI_1/2/deta =
+// I_-1/2 / 2:  eta' = 2u / I_-1/2,  eta'' = eta' (1 - eta' I_-1/2' / I_-1/2).
+__global__ void k_fd_nodes(double *node, double y0, double h, int n) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > n) return;
+  double y = y0 + h * k;
   FDSums s;
   double eta = fd_invert(y, &s);
-  double psi = eta - (2.0 / 3.0) * s.i_32 / exp(y);
-  vals[(sg * 2 + 0) * nn + j] = eta;
-  vals[(sg * 2 + 1) * nn + j] = psi;
+  double u = exp(y);
+  double d1 = 2.0 * u / s.i_m12;
+  double d2 = d1 * (1.0 - d1 * s.di_m12 / s.i_m12);
+  node[4 * k + 0] = eta;
+  node[4 * k + 1] = d1;
+  node[4 * k + 2] = d2;
+  node[4 * k + 3] = eta - (2.0 / 3.0) * s.i_32 / u;
 }
 
-// Chebyshev coefficients (discrete cosine transform of the node values);
-// the k = 0 coefficient is stored halved so evaluation is a plain sum.
-__global__ void k_fd_coef(double *coef, const double *vals, int nseg, int deg) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  int nn = deg + 1;
-  if (idx >= nseg * 2 * nn) return;
-  int row = idx / nn, k = idx % nn;
-  const double PI = 3.14159265358979323846;
-  double acc = 0.0;
-  for (int j = 0; j < nn; ++j) acc += vals[row * nn + j] * cos(PI * k * (j + 0.5) / nn);
-  acc *= 2.0 / nn;
-  if (k == 0) acc *= 0.5;
-  coef[row * nn + k] = acc;
-}
-
-hipError_t build_fd_table(double *coef_dev, double y0, double dy, int nseg, int deg,
-                          hipStream_t s) {
-  double *vals = nullptr;
-  size_t bytes = sizeof(double) * nseg * 2 * (deg + 1);
-  hipError_t e = hipMallocAsync((void **)&vals, bytes, s);
-  if (e != hipSuccess) return e;
-  int tot = nseg * (deg + 1);
-  hipLaunchKernelGGL(k_fd_nodes, dim3((tot + 63) / 64), dim3(64), 0, s, vals, y0, dy, nseg, deg);
-  int tot2 = nseg * 2 * (deg + 1);
-  hipLaunchKernelGGL(k_fd_coef, dim3((tot2 + 127) / 128), dim3(128), 0, s, coef_dev, vals, nseg,
-                     deg);
-  e = hipGetLastError();
-  hipFreeAsync(vals, s);
-  return e;
+hipError_t build_fd_table(double *node_dev, double y0, double h, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fd_nodes, dim3((n + 1 + 63) / 64), dim3(64), 0, s, node_dev, y0, h, n);
+  return hipGetLastError();
 }
 
 __global__ void k_debug_fd(const double *u, double *eta, double *psi, long long n, FDTable fd) {
