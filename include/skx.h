@@ -190,6 +190,12 @@ int skx_profile_enable(int on);
 int skx_profile_reset(void);
 int skx_profile_read(double *ms, long long *launches, int n);
 
+/* Time the three evaluation passes over a batch of nctx configured contexts
+ * (uniform starting density, all in the precision of ctxs[0]): reps timed
+ * repetitions after one warm-up; ms_out[0..2] receive the mean milliseconds
+ * of passes A, B and C per launch. */
+int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out);
+
 /* ---- serving engine (continuous batching over requests) ---- */
 typedef struct {
   double lattice[9];

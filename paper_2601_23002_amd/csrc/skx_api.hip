@@ -1129,3 +1129,71 @@ int skx_profile_read(double *ms, long long *launches, int n) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Pass timing over a batch (used by the tile/launch autotuner and tools)
+// ===========================================================================
+extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out) {
+  if (!ctxs || nctx < 1 || reps < 1 || !ms_out) return SKX_E_INVALID;
+  skx_ctx *c0 = ctxs[0];
+  c0->err.clear();
+  hipSetDevice(c0->device);
+  const int prec = c0->fn.precision == SKX_FP32 ? 1 : 0;
+  for (int i = 0; i < nctx; ++i) {
+    if (!ctxs[i] || ctxs[i]->device != c0->device) return fail(c0, SKX_E_INVALID, "bad context");
+    int rc = prepare(ctxs[i], prec, 1);
+    if (rc) { c0->err = ctxs[i]->err; return rc; }
+    hipStreamSynchronize(ctxs[i]->stream);
+  }
+  hipStream_t s = c0->stream;
+  std::vector<SolveDev> hs;
+  for (int i = 0; i < nctx; ++i) {
+    Instance &I = ctxs[i]->inst[prec];
+    const double v = std::sqrt(ctxs[i]->ne / (ctxs[i]->L * ctxs[i]->L * ctxs[i]->L));
+    if (prec == 0)
+      hipLaunchKernelGGL(k_fill<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                         (double *)I.h.phi2[0], v, I.h.M);
+    else
+      hipLaunchKernelGGL(k_fill<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                         (float *)I.h.phi2[0], (float)v, I.h.M);
+    OptState st{};
+    st.phase = PH_EVAL_ONLY;
+    hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+    hs.push_back(I.h);
+  }
+  SolveDev *ddev = nullptr;
+  int *dfirst = nullptr;
+  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * 4 * (nctx + 1), s);
+  if (e != hipSuccess) return hip_fail(c0, e, "bench descriptors");
+  BatchLaunch bl{};
+  int rc = build_batch(c0, hs, prec, ddev, dfirst, bl, s);
+  if (rc == SKX_OK) {
+    hipEvent_t ev[4];
+    for (auto &x : ev) hipEventCreate(&x);
+    double tot[3] = {0, 0, 0};
+    for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+      hipEventRecord(ev[0], s);
+      e = launch_eval(bl, s, 1);
+      hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = launch_eval(bl, s, 2);
+      hipEventRecord(ev[2], s);
+      if (e == hipSuccess) e = launch_eval(bl, s, 4);
+      hipEventRecord(ev[3], s);
+      hipEventSynchronize(ev[3]);
+      if (r == 0) continue;            // first repetition warms caches
+      for (int q = 0; q < 3; ++q) {
+        float t = 0.f;
+        hipEventElapsedTime(&t, ev[q], ev[q + 1]);
+        tot[q] += t;
+      }
+    }
+    for (auto &x : ev) hipEventDestroy(x);
+    for (int q = 0; q < 3; ++q) ms_out[q] = tot[q] / reps;
+    if (e != hipSuccess) rc = hip_fail(c0, e, "bench passes");
+  }
+  hipFreeAsync(ddev, s);
+  hipFreeAsync(dfirst, s);
+  hipStreamSynchronize(s);
+  return rc;
+}

@@ -8,6 +8,35 @@
 
 namespace skx {
 
+// Pointers read from descriptors are generic (flat) pointers; the fields
+// they name live in global memory. Qualifying them lets the compiler issue
+// global loads that do not alias LDS, so loads can be batched ahead of LDS
+// stores.
+#define SKX_G __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ SKX_G T *gptr(const void *p) {
+  return (SKX_G T *)(void *)(p);
+}
+
+// HIP's vector structs cannot be copied through address-space-qualified
+// pointers; move them as clang native vectors instead.
+template <typename V> struct NativeOf;
+template <> struct NativeOf<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct NativeOf<float2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct NativeOf<double4> { typedef double T __attribute__((ext_vector_type(4))); };
+template <typename V> __device__ __forceinline__ V ldg(const SKX_G V *p) {
+  typedef typename NativeOf<V>::T N;
+  const N v = *reinterpret_cast<const SKX_G N *>(p);
+  V r;
+  __builtin_memcpy(&r, &v, sizeof(V));
+  return r;
+}
+template <typename V> __device__ __forceinline__ void stg(SKX_G V *p, const V &v) {
+  typedef typename NativeOf<V>::T N;
+  N w;
+  __builtin_memcpy(&w, &v, sizeof(V));
+  *reinterpret_cast<SKX_G N *>(p) = w;
+}
+
 template <typename R> struct Vec2;
 template <> struct Vec2<double> { typedef double2 T; };
 template <> struct Vec2<float> { typedef float2 T; };
@@ -203,8 +232,8 @@ __device__ __forceinline__ int fd_lookup(double y, const FDTable &fd, double &et
   int bad = 0;
   if (k >= fd.n) { k = fd.n - 1; bad = 1; }
   const double s = t - k;
-  const double4 a = reinterpret_cast<const double4 *>(fd.node)[k];
-  const double4 b = reinterpret_cast<const double4 *>(fd.node)[k + 1];
+  const double4 a = ldg(gptr<double4>(fd.node) + k);
+  const double4 b = ldg(gptr<double4>(fd.node) + k + 1);
   const double h = fd.h;
   const double s2 = s * s, s3 = s2 * s, s4 = s3 * s, s5 = s4 * s;
   const double h0 = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;

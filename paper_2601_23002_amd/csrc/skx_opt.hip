@@ -143,14 +143,14 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   const int par = st->par;
-  const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
-  const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
-  const R *r = reinterpret_cast<const R *>(S.r2[par]);
-  const R *rt = reinterpret_cast<const R *>(S.r2[1 - par]);
-  const R *pr = reinterpret_cast<const R *>(S.pr2[par]);
-  const R *prt = reinterpret_cast<const R *>(S.pr2[1 - par]);
-  R *Sv = reinterpret_cast<R *>(S.S);
-  R *Yv = reinterpret_cast<R *>(S.Y);
+  const SKX_G R *phi = gptr<R>(S.phi2[par]);
+  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
+  const SKX_G R *r = gptr<R>(S.r2[par]);
+  const SKX_G R *rt = gptr<R>(S.r2[1 - par]);
+  const SKX_G R *pr = gptr<R>(S.pr2[par]);
+  const SKX_G R *prt = gptr<R>(S.pr2[1 - par]);
+  SKX_G R *Sv = gptr<R>(S.S);
+  SKX_G R *Yv = gptr<R>(S.Y);
   double acc[NDOT];
 #pragma unroll
   for (int q = 0; q < NDOT; ++q) acc[q] = 0.0;
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
     int slot[MMAX];
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) slot[i] = (i < kold) ? ((head - kold + i + 2 * m) % m) : 0;
-    R *Snew = Sv + (size_t)head * S.M;
-    R *Ynew = Yv + (size_t)head * S.M;
+    SKX_G R *Snew = Sv + (size_t)head * S.M;
+    SKX_G R *Ynew = Yv + (size_t)head * S.M;
     for (long long g = g0 + tid; g < g1; g += NT) {
       const R pt = phit[g], rtg = rt[g], prtg = prt[g];
       const R sv = pt - phi[g];
@@ -359,12 +359,12 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   const int par = st->par;
-  const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
-  const R *r = reinterpret_cast<const R *>(S.r2[par]);
-  const R *pr = reinterpret_cast<const R *>(S.pr2[par]);
-  const R *Sv = reinterpret_cast<const R *>(S.S);
-  const R *Yv = reinterpret_cast<const R *>(S.Y);
-  R *d = reinterpret_cast<R *>(S.d);
+  const SKX_G R *phi = gptr<R>(S.phi2[par]);
+  const SKX_G R *r = gptr<R>(S.r2[par]);
+  const SKX_G R *pr = gptr<R>(S.pr2[par]);
+  const SKX_G R *Sv = gptr<R>(S.S);
+  const SKX_G R *Yv = gptr<R>(S.Y);
+  SKX_G R *d = gptr<R>(S.d);
   const int m = st->m, k = st->k, head = st->head;
   int slot[MMAX];
   R cS[MMAX], cY[MMAX];
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, in
   const int wl = item - first[s];
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
-  R *phi = reinterpret_cast<R *>(S.phi2[st->par]);
+  SKX_G R *phi = gptr<R>(S.phi2[st->par]);
   const bool from_rho = st->reset_pending == 2;
   double ss = 0.0, bad = 0.0;
   for (long long g = g0 + tid; g < g1; g += NT) {

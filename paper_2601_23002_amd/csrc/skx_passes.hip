@@ -216,11 +216,11 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
     double ca, cb;
     bool use_d;
     trial_coef(st, S, ca, cb, use_d);
-    const R *phi = reinterpret_cast<const R *>(S.phi2[par]);
-    const R *dd = reinterpret_cast<const R *>(S.d);
-    R *phit = reinterpret_cast<R *>(S.phi2[1 - par]);
-    R *v0 = reinterpret_cast<R *>(S.vpt);
-    R *fpw = reinterpret_cast<R *>(S.fpt);
+    const SKX_G R *phi = gptr<R>(S.phi2[par]);
+    const SKX_G R *dd = gptr<R>(S.d);
+    SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
+    SKX_G R *v0 = gptr<R>(S.vpt);
+    SKX_G R *fpw = gptr<R>(S.fpt);
     const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
     const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
     const bool need_f = (S.fields & F_F) != 0;
@@ -271,9 +271,9 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
     }
   } else {
     // residual of the accepted trial point, stored for the update pass
-    const R *g = reinterpret_cast<const R *>(S.grad);
-    const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
-    R *rt = reinterpret_cast<R *>(S.r2[1 - par]);
+    const SKX_G R *g = gptr<R>(S.grad);
+    const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
+    SKX_G R *rt = gptr<R>(S.r2[1 - par]);
     const R mu2 = (R)(2.0 * st->mut);
     const UDiv dn3 = make_udiv((unsigned)n3);
     for (int e = tid; e < np; e += NT) {
@@ -287,13 +287,13 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
   }
   __syncthreads();
   plane_forward<V, R, NT>(buf, S, tw2, tw3, tid);
-  V *spec = reinterpret_cast<V *>(S.spec) +
+  SKX_G V *spec = gptr<V>(S.spec) +
             (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H;
   const size_t obase = (size_t)plane * n2 * S.pitch;
   const UDiv dnh = make_udiv((unsigned)nh);
   for (int e = tid; e < n2 * nh; e += NT) {
     const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
-    spec[obase + (size_t)j * S.pitch + k] = buf[j * pl + k];
+    stg(spec + obase + (size_t)j * S.pitch + k, buf[j * pl + k]);
   }
   if (MODE == MODE_EVAL) {
     double v[PART_A] = {e_tf, e_xc, nel, bad};
@@ -330,13 +330,13 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   V *tile = reinterpret_cast<V *>(smem);
   V *tw1 = tile + n1 * Wp;
   load_twiddles(tw1, twbank, S.p1.tw, n1, tid, NT);
-  V *spec = reinterpret_cast<V *>(S.spec);
+  SKX_G V *spec = gptr<V>(S.spec);
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   const UDiv dW = make_udiv((unsigned)W);
   for (int e = tid; e < n1 * W; e += NT) {
     const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
-    tile[i * Wp + r] = spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk];
+    tile[i * Wp + r] = ldg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk);
   }
   __syncthreads();
   if (S.debug != 2) fft_lds<V, 4, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
@@ -345,8 +345,8 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
       const int cc = r / TK, kk = r - cc * TK;
       if (k0 + kk < S.nh)
-        spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] =
-            tile[i * Wp + r];
+        stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
+            tile[i * Wp + r]);
     }
     return;
   }
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
     const bool do_h = terms & 16u, do_loc = terms & 32u;
     const int sphi = S.slot[0], sn = S.slot[1], sf = S.slot[2], sh = S.slot[3];
-    const V *vloc = reinterpret_cast<const V *>(S.vloc);
+    const SKX_G V *vloc = gptr<V>(S.vloc);
     const R b3 = (R)(S.beta / 3.0);
     const double FOURPI = 12.566370614359172954;
     for (int e = tid; e < n1 * TK; e += NT) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
           by = FOURPI * x.y / G2;
         }
         if (do_loc) {
-          const V vl = vloc[vi];
+          const V vl = ldg(vloc + vi);
           eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
           bx += vl.x;
           by += vl.y;
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
     if (k0 + kk < S.nh)
-      spec[(size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk] =
-          tile[i * Wp + r];
+      stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
+          tile[i * Wp + r]);
   }
   if (MODE == MODE_EVAL) {
     double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
@@ -478,15 +478,15 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
   const size_t pbase = (size_t)plane * n2 * n3;
   const int np = n2 * n3;
-  const V *spec = reinterpret_cast<const V *>(S.spec);
+  const SKX_G V *spec = gptr<V>(S.spec);
   const size_t ibase = (size_t)plane * n2 * S.pitch;
 
   if (MODE == MODE_PREC) {
-    R *out = reinterpret_cast<R *>(S.pr2[1 - par]);
+    SKX_G R *out = gptr<R>(S.pr2[1 - par]);
     const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
     for (int e = tid; e < n2 * nh; e += NT) {
       const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
-      buf[j * pl + k] = spec[ibase + (size_t)j * S.pitch + k];
+      buf[j * pl + k] = ldg(spec + ibase + (size_t)j * S.pitch + k);
     }
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
@@ -498,11 +498,11 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
     return;
   }
 
-  const R *phit = reinterpret_cast<const R *>(S.phi2[1 - par]);
-  const R *v0 = reinterpret_cast<const R *>(S.vpt);
-  const R *fpw = reinterpret_cast<const R *>(S.fpt);
-  R *grad = reinterpret_cast<R *>(S.grad);
-  R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : grad + pbase;
+  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
+  const SKX_G R *v0 = gptr<R>(S.vpt);
+  const SKX_G R *fpw = gptr<R>(S.fpt);
+  SKX_G R *grad = gptr<R>(S.grad);
+  R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : (R *)(grad + pbase);
   const R a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
   const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
   for (int e = tid; e < np; e += NT)
@@ -510,11 +510,11 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0 || (S.debug && fb != 0)) continue;
-    const V *src = spec + (size_t)sl * S.H + ibase;
+    const SKX_G V *src = spec + (size_t)sl * S.H + ibase;
     __syncthreads();
     for (int e = tid; e < n2 * nh; e += NT) {
       const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
-      buf[j * pl + k] = src[(size_t)j * S.pitch + k];
+      buf[j * pl + k] = ldg(src + (size_t)j * S.pitch + k);
     }
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);

@@ -111,6 +111,7 @@ _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double
 _sig("skx_profile_enable", C.c_int, [C.c_int])
 _sig("skx_profile_reset", C.c_int, [])
 _sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
+_sig("skx_bench_eval", C.c_int, [C.POINTER(_VP), C.c_int, C.c_int, C.POINTER(C.c_double)])
 _sig("skx_engine_create", C.c_int, [C.POINTER(_VP), C.c_int, C.c_size_t, C.c_int])
 _sig("skx_engine_submit", C.c_int, [_VP, C.POINTER(Request), C.POINTER(C.c_uint64)])
 _sig("skx_engine_step", C.c_int, [_VP])
@@ -298,6 +299,17 @@ def profile_read():
     cnt = (C.c_longlong * 8)()
     n = _lib.skx_profile_read(ms, cnt, 8)
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(min(n, len(PASS_NAMES)))}
+
+
+def bench_eval(ctxs, reps=20):
+    """Mean per-launch milliseconds of passes A, B, C over a batch."""
+    n = len(ctxs)
+    hs = (_VP * n)(*[c._h for c in ctxs])
+    ms = (C.c_double * 3)()
+    rc = _lib.skx_bench_eval(hs, n, reps, ms)
+    if rc < 0:
+        raise SkxError(rc, _lib.skx_last_error(ctxs[0]._h).decode())
+    return {"passA": ms[0], "passB": ms[1], "passC": ms[2]}
 
 
 def exported_symbols():
