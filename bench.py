@@ -37,6 +37,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--gtol", type=float, default=1e-8)
+    ap.add_argument("--fp64-max-iter", type=int, default=500,
+                    help="iteration cap of the plain FP64 comparison solves")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
     return ap.parse_args()
 
 
@@ -53,6 +58,29 @@ def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
     # C: nf half spectra, phi_t, local potential, n^a in; dE/dphi out
     c = nf * spec + 4 * b * M
     return a, bb, c
+
+
+PASS_SOURCES = ("paper_2601_23002_amd/csrc/skx_passes.hip", "paper_2601_23002_amd/csrc/skx_device.hpp",
+                 "paper_2601_23002_amd/csrc/skx_internal.hpp")
+TRAFFIC_FILE = "profiles/traffic_scan64_mixed.md"
+
+
+def measured_traffic():
+    """Pass A HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when the pass sources changed since those counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            kv = dict(l.strip().split(": ", 1) for l in fh if l.startswith("    pass"))
+    except OSError:
+        return None
+    if kv.get("pass_sources_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(kv["passA_traffic_bytes_per_launch"])
 
 
 def fields_count(sys_):
@@ -89,6 +117,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
     from paper_2601_23002_amd import skx
     from paper_2601_23002_amd import workloads as W
 
@@ -100,8 +137,8 @@ def main():
         rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
         return ctxs, rhos
 
-    def step(ctxs, rhos):
-        return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=3000, m=5,
+    def step(ctxs, rhos, max_iter=3000):
+        return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=max_iter, m=5,
                              fp32_switch_gtol=1e-5)
 
     def work(res):
@@ -112,10 +149,10 @@ def main():
     if not args.no_fp64:
         print("fp64 reference solves", file=sys.stderr, flush=True)
         c64, r64 = make(skx.FP64)
-        step(c64, r64)                            # warm-up
+        step(c64, r64, args.fp64_max_iter)        # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res64 = step(c64, r64)
+        res64 = step(c64, r64, args.fp64_max_iter)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         fp64 = dict(value=work(res64) / t64, seconds=t64,
@@ -166,8 +203,10 @@ def main():
     ms, launches = prof[dom]
     avg_s = ms / 1e3 / max(1, launches)
     achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9
+    traffic = measured_traffic() if dom == "passA" else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
             "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
             "bytes_per_launch": round(bytes_pass[dom] / max(1, launches))}
 
@@ -203,6 +242,7 @@ def main():
         out["max_err_ha_per_atom"] = max(err)
         out["max_rel_density_err"] = max(rerr)
         out["iters_fp64"] = fp64["iters"]
+        out["fp64_max_iter"] = args.fp64_max_iter
     out["iters_mixed"] = [r["iters"] for r in results]
     out["status"] = [r["status"] for r in results]
     if not args.no_cpu_baseline:

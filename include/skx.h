@@ -207,7 +207,7 @@ typedef struct {
   const double *zval, *rc;
   skx_functional fn;
   skx_opt_params opt;
-  double t_arrival;          /* caller's clock, seconds */
+  double t_arrival;          /* seconds; callers use skx_engine_clock's clock */
 } skx_request;
 
 typedef struct {
@@ -223,13 +223,25 @@ typedef struct skx_engine skx_engine;
 int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int max_slots);
 /* Copies the request; SKX_E_INVALID if it can never fit the budget. */
 int skx_engine_submit(skx_engine *eng, const skx_request *req, uint64_t *ticket);
-/* Admit queued requests into free slots, then run one optimiser step over
- * every resident solve. Returns the number of resident solves (>= 0). */
+/* Admit queued requests (in arrival order) into free slots while their
+ * device footprint fits the budget, then advance every resident solve by
+ * four fused step sequences (one launch per kernel over all resident solves
+ * of a precision; a step sequence is one trial evaluation of the line search
+ * plus the history update when the trial is accepted). Mixed-precision
+ * solves move from the FP32 to the FP64 group at the switch; finished solves
+ * leave and free their slot. Returns the number of resident solves (>= 0) or
+ * an error. A request that fails set-up is reported by poll with its
+ * negative status. Results equal those of solving each request alone. */
 int skx_engine_step(skx_engine *eng);
 /* Collect finished results (up to max); the density of each is copied to
  * rho_host[i] when rho_host is non-NULL and rho_host[i] is non-NULL. */
 int skx_engine_poll(skx_engine *eng, skx_result *out, double **rho_host, int max, int *n_out);
+/* Queued + resident + finished-but-unpolled requests. */
 int skx_engine_pending(const skx_engine *eng);
+/* Seconds since engine creation (the clock of t_admit / t_done). */
+double skx_engine_clock(const skx_engine *eng);
+/* Text of the engine's last error. */
+const char *skx_engine_last_error(const skx_engine *eng);
 void skx_engine_destroy(skx_engine *eng);
 
 #ifdef __cplusplus

@@ -3,6 +3,7 @@
 #include "skx_internal.hpp"
 #include "skx_device.hpp"
 #include "../../include/skx.h"
+#include "skx_host.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -14,7 +15,8 @@
 
 using namespace skx;
 
-namespace {
+namespace skx {
+namespace host {
 
 // ---------------------------------------------------------------------------
 // Per-device resources shared by all contexts: FFT twiddle bank and the
@@ -102,47 +104,11 @@ Plan make_plan(int n, int twoff) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// One solve instance in one precision: device buffers + descriptor.
-struct Instance {
-  int prec = -1;                 // 0 fp64, 1 fp32
-  size_t rsz = 0;
-  void *mem = nullptr;           // one arena for every field of the solve
-  size_t bytes = 0;
-  SolveDev h{};                  // host mirror of the descriptor
-  SolveDev *dptr = nullptr;      // device copy (batch of one)
-  OptState *st = nullptr;        // device
-  int *first = nullptr;          // device prefix sums for the batch of one [4][2]
-  BatchLaunch bl{};
-  bool vloc_ok = false;
-  int m_alloc = 0;
-};
+}  // namespace host
+}  // namespace skx
 
-}  // namespace
-
-struct skx_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  bool has_cell = false, has_ions = false, has_fn = false;
-  double L = 0;
-  int n1 = 0, n2 = 0, n3 = 0;
-  std::vector<double> pos, zsp, rcsp;
-  std::vector<int> species;
-  int nspecies = 0;
-  double ne = 0;
-  skx_functional fn{};
-  double *w = nullptr, *wp = nullptr;
-  int smax = 0;
-  bool tables_ok = false;
-  double kappa = 1.0;              // preconditioner shift (uniform-gas TF curvature)
-  double e_ii = 0;
-  Instance inst[2];
-  double *ion_pos = nullptr, *ion_z = nullptr, *sp_z = nullptr, *sp_rc = nullptr;
-  int *ion_sp = nullptr;
-};
-
-namespace {
+namespace skx {
+namespace host {
 
 int fail(skx_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -186,6 +152,40 @@ constexpr size_t LDS_MAX = 160 * 1024;
 
 // Allocate (or reuse) the buffers of one precision instance and fill the
 // descriptor's grid and buffer fields.
+struct ArenaLayout {
+  size_t o_phi, o_phit, o_grad, o_r, o_rt, o_pr, o_prt, o_d, o_vpt, o_fpt, o_S, o_Y;
+  size_t o_spec, o_vloc, o_pA, o_pB, o_pC, o_pU, o_pD, total;
+};
+
+ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
+  const size_t rsz = prec == 0 ? 8 : 4;
+  const int tk = prec == 0 ? 8 : 16;
+  const int nh = n3 / 2 + 1;
+  const int pitch = (int)align_up(nh, tk);
+  const long long M = (long long)n1 * n2 * n3;
+  const long long H = (long long)n1 * n2 * pitch;
+  const int nkb = (nh + tk - 1) / tk;
+  const int nwg = (int)((M + CHUNK - 1) / CHUNK);
+  ArenaLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  L.o_phi = take(rsz * M); L.o_phit = take(rsz * M); L.o_grad = take(rsz * M);
+  L.o_r = take(rsz * M); L.o_rt = take(rsz * M); L.o_pr = take(rsz * M); L.o_prt = take(rsz * M);
+  L.o_d = take(rsz * M); L.o_vpt = take(rsz * M); L.o_fpt = take(rsz * M);
+  L.o_S = take(rsz * M * m); L.o_Y = take(rsz * M * m);
+  L.o_spec = take(2 * rsz * H * NFIELD); L.o_vloc = take(2 * rsz * H);
+  L.o_pA = take(8 * (size_t)n1 * NFIELD * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
+  L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwg * NDOT);
+  L.o_pD = take(8 * (size_t)nwg * 2);
+  L.total = off;
+  return L;
+}
+
+size_t instance_bytes(int n1, int n2, int n3, int prec, int m) {
+  return arena_layout(n1, n2, n3, prec, std::max(m, 1)).total + sizeof(SolveDev) +
+         sizeof(OptState) + 8 * sizeof(int);
+}
+
 int ensure_instance(skx_ctx *c, int prec, int m) {
   Instance &I = c->inst[prec];
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
@@ -202,17 +202,12 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
     return SKX_OK;
   free_instance(I);
   hipSetDevice(c->device);
-  // arena layout
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  size_t o_phi = take(rsz * M), o_phit = take(rsz * M), o_grad = take(rsz * M);
-  size_t o_r = take(rsz * M), o_rt = take(rsz * M), o_pr = take(rsz * M), o_prt = take(rsz * M);
-  size_t o_d = take(rsz * M), o_vpt = take(rsz * M), o_fpt = take(rsz * M);
-  size_t o_S = take(rsz * M * m), o_Y = take(rsz * M * m);
-  size_t o_spec = take(2 * rsz * H * NFIELD), o_vloc = take(2 * rsz * H);
-  size_t o_pA = take(8 * (size_t)n1 * NFIELD * PART_A), o_pB = take(8 * (size_t)n2 * nkb * PART_B);
-  size_t o_pC = take(8 * (size_t)n1 * PART_C), o_pU = take(8 * (size_t)nwg * NDOT);
-  size_t o_pD = take(8 * (size_t)nwg * 2);
+  const ArenaLayout A = arena_layout(n1, n2, n3, prec, m);
+  const size_t off = A.total;
+  const size_t o_phi = A.o_phi, o_phit = A.o_phit, o_grad = A.o_grad, o_r = A.o_r, o_rt = A.o_rt;
+  const size_t o_pr = A.o_pr, o_prt = A.o_prt, o_d = A.o_d, o_vpt = A.o_vpt, o_fpt = A.o_fpt;
+  const size_t o_S = A.o_S, o_Y = A.o_Y, o_spec = A.o_spec, o_vloc = A.o_vloc;
+  const size_t o_pA = A.o_pA, o_pB = A.o_pB, o_pC = A.o_pC, o_pU = A.o_pU, o_pD = A.o_pD;
   hipError_t e = hipMalloc(&I.mem, off);
   if (e != hipSuccess) { I.mem = nullptr; return hip_fail(c, e, "device arena allocation"); }
   hipMemsetAsync(I.mem, 0, off, c->stream);
@@ -427,6 +422,45 @@ __global__ void k_f2d(const float *a, double *b, long long n) {
 
 unsigned blocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+hipError_t start_uniform(skx_ctx *c, Instance &I, hipStream_t s) {
+  const long long M = I.h.M;
+  const double v = std::sqrt(c->ne / (c->L * c->L * c->L));
+  if (I.prec == 0)
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                       (double *)I.h.phi2[0], v, M);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
+                       (float *)I.h.phi2[0], (float)v, M);
+  return hipGetLastError();
+}
+
+hipError_t promote_phi(const Instance &I32, int par, Instance &I64, hipStream_t s) {
+  hipLaunchKernelGGL(k_f2d, dim3(blocks(I64.h.M, 256)), dim3(256), 0, s,
+                     (const float *)I32.h.phi2[par], (double *)I64.h.phi2[0], I64.h.M);
+  return hipGetLastError();
+}
+
+hipError_t square_out(const Instance &I, int par, double *rho, hipStream_t s) {
+  if (I.prec == 0)
+    hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                       (const double *)I.h.phi2[par], rho, I.h.M);
+  else
+    hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I.h.M, 256)), dim3(256), 0, s,
+                       (const float *)I.h.phi2[par], rho, I.h.M);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_phases(const SolveDev *dev, int n, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = dev[i].st->phase;
+}
+
+hipError_t gather_phases(const SolveDev *dev, int n, int *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_phases, dim3(blocks(n, 256)), dim3(256), 0, s, dev, n, out);
+  return hipGetLastError();
+}
+
 void energy_from(const double *e, double e_ii, skx_energy *out) {
   out->f_tf = e[E_TF]; out->e_vw = e[E_VW]; out->f_nl0 = e[E_NL0]; out->f_nl1 = e[E_NL1];
   out->e_h = e[E_H]; out->e_loc = e[E_LOC]; out->e_xc = e[E_XC]; out->e_ii = e_ii;
@@ -582,7 +616,10 @@ int run_optimize(skx_ctx *c, Instance &I, void *rho_dev, const skx_opt_params &p
   return SKX_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace skx
+
+using namespace skx::host;
 
 // ===========================================================================
 // C ABI

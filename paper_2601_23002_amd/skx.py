@@ -119,6 +119,8 @@ _sig("skx_engine_poll", C.c_int, [_VP, C.POINTER(Result), C.POINTER(C.POINTER(C.
                                   C.c_int, C.POINTER(C.c_int)])
 _sig("skx_engine_pending", C.c_int, [_VP])
 _sig("skx_engine_destroy", None, [_VP])
+_sig("skx_engine_clock", C.c_double, [_VP])
+_sig("skx_engine_last_error", C.c_char_p, [_VP])
 
 
 def _dptr(a):
@@ -133,6 +135,27 @@ def _torch():
 def _stream_handle(device):
     torch = _torch()
     return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ion_arrays(pos, zval, rc, species=None):
+    """Positions [N][3], species index per ion and per-species (Z, rc) arrays."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    zval = np.asarray(zval, dtype=np.float64).reshape(-1)
+    rc = np.asarray(rc, dtype=np.float64).reshape(-1)
+    if species is None:
+        # one species per distinct (Z, rc) pair
+        keys = list(zip(zval.tolist(), rc.tolist())) if zval.size == len(pos) else None
+        if keys is None:
+            raise ValueError("give species, or per-ion zval and rc")
+        uniq = sorted(set(keys))
+        species = np.array([uniq.index(k) for k in keys], dtype=np.int32)
+        zsp = np.array([u[0] for u in uniq])
+        rsp = np.array([u[1] for u in uniq])
+    else:
+        species = np.asarray(species, dtype=np.int32)
+        zsp, rsp = zval, rc
+    return (pos, np.ascontiguousarray(species, dtype=np.int32),
+            np.ascontiguousarray(zsp, dtype=np.float64), np.ascontiguousarray(rsp, dtype=np.float64))
 
 
 class Context:
@@ -176,24 +199,7 @@ class Context:
         self.n, self.L = n, float(L)
 
     def set_ions(self, pos, zval, rc, species=None):
-        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
-        zval = np.asarray(zval, dtype=np.float64).reshape(-1)
-        rc = np.asarray(rc, dtype=np.float64).reshape(-1)
-        if species is None:
-            # one species per distinct (Z, rc) pair
-            keys = list(zip(zval.tolist(), rc.tolist())) if zval.size == len(pos) else None
-            if keys is None:
-                raise ValueError("give species, or per-ion zval and rc")
-            uniq = sorted(set(keys))
-            species = np.array([uniq.index(k) for k in keys], dtype=np.int32)
-            zsp = np.array([u[0] for u in uniq])
-            rsp = np.array([u[1] for u in uniq])
-        else:
-            species = np.asarray(species, dtype=np.int32)
-            zsp, rsp = zval, rc
-        zsp = np.ascontiguousarray(zsp, dtype=np.float64)
-        rsp = np.ascontiguousarray(rsp, dtype=np.float64)
-        species = np.ascontiguousarray(species, dtype=np.int32)
+        pos, species, zsp, rsp = _ion_arrays(pos, zval, rc, species)
         self._check(_lib.skx_set_ions(self._h, len(pos), _dptr(pos),
                                       species.ctypes.data_as(C.POINTER(C.c_int)), len(zsp),
                                       _dptr(zsp), _dptr(rsp)))
@@ -310,6 +316,93 @@ def bench_eval(ctxs, reps=20):
     if rc < 0:
         raise SkxError(rc, _lib.skx_last_error(ctxs[0]._h).decode())
     return {"passA": ms[0], "passB": ms[1], "passC": ms[2]}
+
+
+class Engine:
+    """Serving engine (skx_engine_*): continuous batching of optimisations."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 64 << 30, max_slots: int = 64):
+        self._h = _VP()
+        rc = _lib.skx_engine_create(C.byref(self._h), device, hbm_budget, max_slots)
+        if rc != OK:
+            raise SkxError(rc, "skx_engine_create failed")
+        self._npts = {}
+
+    def close(self):
+        if self._h:
+            _lib.skx_engine_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        return _lib.skx_engine_clock(self._h)
+
+    def submit(self, sys, precision=MIXED, gtol=1e-8, max_iter=1000, m=5,
+               fp32_switch_gtol=1e-5, t_arrival=None) -> int:
+        """Queue one workloads.System; returns its ticket."""
+        pos, species, zsp, rsp = _ion_arrays(sys.pos, sys.zval, sys.rc)
+        req = Request()
+        L = float(sys.L)
+        for i, v in enumerate((L, 0, 0, 0, L, 0, 0, 0, L)):
+            req.lattice[i] = v
+        req.n1, req.n2, req.n3 = sys.n
+        req.nions = len(pos)
+        req.pos = _dptr(pos)
+        req.species = species.ctypes.data_as(C.POINTER(C.c_int))
+        req.nspecies = len(zsp)
+        req.zval = _dptr(zsp)
+        req.rc = _dptr(rsp)
+        req.fn = Functional(sys.T, sys.beta, sys.alpha, sys.terms, XC_PZ81, precision)
+        req.opt = OptParams(gtol, max_iter, m, fp32_switch_gtol, 0)
+        req.t_arrival = self.clock() if t_arrival is None else t_arrival
+        t = C.c_uint64()
+        rc = _lib.skx_engine_submit(self._h, C.byref(req), C.byref(t))
+        if rc != OK:
+            raise SkxError(rc, _lib.skx_engine_last_error(self._h).decode())
+        self._npts[t.value] = tuple(sys.n)
+        return t.value
+
+    def step(self) -> int:
+        rc = _lib.skx_engine_step(self._h)
+        if rc < 0:
+            raise SkxError(rc, _lib.skx_engine_last_error(self._h).decode())
+        return rc
+
+    def pending(self) -> int:
+        return _lib.skx_engine_pending(self._h)
+
+    def poll(self, want_density=False, max_results=256):
+        """Finished results: dicts with ticket, result, t_admit, t_done (engine clock)
+        and the density (numpy, FP64) when want_density."""
+        res = []
+        while len(res) < max_results:
+            k = 1 if want_density else max_results - len(res)
+            out = (Result * k)()
+            bufs, buf = None, None
+            if want_density:
+                biggest = max((int(np.prod(v)) for v in self._npts.values()), default=1)
+                buf = np.empty(biggest)
+                bufs = (C.POINTER(C.c_double) * 1)(_dptr(buf))
+            n = C.c_int()
+            rc = _lib.skx_engine_poll(self._h, out, bufs, k, C.byref(n))
+            if rc != OK:
+                raise SkxError(rc, _lib.skx_engine_last_error(self._h).decode())
+            for i in range(n.value):
+                r = out[i]
+                shape = self._npts.pop(r.ticket, None)
+                d = {"ticket": r.ticket, "result": r.r.as_dict(), "t_admit": r.t_admit,
+                     "t_done": r.t_done, "npoints": r.npoints}
+                if want_density and shape is not None and r.npoints > 0:
+                    d["rho"] = buf[:r.npoints].reshape(shape).copy()
+                res.append(d)
+            if n.value < k:
+                break
+        return res
 
 
 def exported_symbols():

@@ -1,0 +1,135 @@
+"""Batched solves and the serving engine (through the C ABI).
+
+A solve's arithmetic must not depend on which other solves share its
+launches: batched and engine results are compared bit for bit with the same
+solve run alone. Mixed-precision solves are compared with the FP64 oracle
+at the stated accuracy (1e-6 Ha/atom in energy, 1e-5 relative in density).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_23002_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2601_23002_amd import skx
+    return skx, torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _systems():
+    return [W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 12, seed=41),
+            W.uniform_system(8, 1.0, 0.3, 1.5, 4.0, 16, seed=42),
+            W.uniform_system(3, 4.0, 0.5, 1.5, 4.0, 20, seed=43),
+            W.uniform_system(10, 1.0, 0.3, 3.0, 0.5, 16, seed=44, beta=0.5)]
+
+
+def _alone(skx, s, precision, **kw):
+    c = skx.Context(0).setup(s, precision=precision)
+    rho, r = c.optimize(**kw)
+    return rho.cpu().numpy(), r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_run_batch_equals_alone(precision):
+    skx, torch = _lib()
+    prec = {"fp64": skx.FP64, "mixed": skx.MIXED}[precision]
+    systems = _systems()
+    _say(f"case: run_batch vs alone, {precision}, grids {[s.n[0] for s in systems]}")
+    kw = dict(gtol=1e-9, max_iter=400, m=5, fp32_switch_gtol=1e-5)
+    ctxs = [skx.Context(0).setup(s, precision=prec) for s in systems]
+    rhos = [torch.empty(s.n, dtype=torch.float64, device="cuda") for s in systems]
+    res = skx.run_batch(ctxs, rhos, **kw)
+    for s, r, rho in zip(systems, res, rhos):
+        n_a, r_a = _alone(skx, s, prec, **kw)
+        assert r["status"] == skx.OK, r
+        assert r["iters"] == r_a["iters"] and r["evals"] == r_a["evals"]
+        assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(rho.cpu().numpy(), n_a)
+
+
+def test_mixed_matches_oracle():
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    from oracle.optimize import optimize
+    for s in _systems()[:3]:
+        _say(f"case: mixed vs oracle, n={s.n[0]}, N={len(s.zval)}")
+        ref = optimize(Problem(s), gtol=1e-9, max_iter=600)
+        n, r = _alone(skx, s, skx.MIXED, gtol=1e-9, max_iter=600, fp32_switch_gtol=1e-5)
+        assert r["status"] == skx.OK, r
+        assert r["fp32_iters"] > 0
+        per_atom = abs(r["energy"]["free_energy"] - ref["energy"]["free_energy"]) / len(s.zval)
+        assert per_atom < 1e-6
+        assert np.sum(np.abs(n - ref["n"])) / np.sum(ref["n"]) < 1e-5
+
+
+def test_fp32_phase_alone_within_single_precision():
+    """An FP32-only solve already lands within the mixed-precision bar of the
+    FP64 minimum for a moderate gtol."""
+    skx, _ = _lib()
+    s = _systems()[1]
+    _say("case: fp32-only solve vs fp64 solve, n=16")
+    n64, r64 = _alone(skx, s, skx.FP64, gtol=1e-9, max_iter=600)
+    n32, r32 = _alone(skx, s, skx.FP32, gtol=1e-5, max_iter=600)
+    assert r32["status"] in (skx.OK, skx.NOT_CONVERGED)
+    assert abs(r32["energy"]["free_energy"] - r64["energy"]["free_energy"]) / len(s.zval) < 1e-6
+    assert np.sum(np.abs(n32 - n64)) / np.sum(n64) < 1e-4
+
+
+def test_engine_equals_alone_and_reports_latency():
+    skx, _ = _lib()
+    systems = _systems() + [W.uniform_system(5, 1.0, 0.3, 2.0, 2.0, 12, seed=45)]
+    kw = dict(gtol=1e-9, max_iter=400, m=5, fp32_switch_gtol=1e-5)
+    _say(f"case: engine, {len(systems)} requests, 2 slots")
+    eng = skx.Engine(0, hbm_budget=1 << 30, max_slots=2)
+    tickets = {}
+    for i, s in enumerate(systems):
+        prec = skx.FP64 if i == 2 else skx.MIXED
+        tickets[eng.submit(s, precision=prec, **kw)] = (s, prec)
+    done = []
+    steps = 0
+    while eng.pending() > 0 and steps < 5000:
+        resident = eng.step()
+        assert 0 <= resident <= 2
+        done += eng.poll(want_density=True)
+        steps += 1
+    assert len(done) == len(systems)
+    lat = []
+    for d in done:
+        s, prec = tickets[d["ticket"]]
+        n_a, r_a = _alone(skx, s, prec, **kw)
+        r = d["result"]
+        assert r["status"] == skx.OK, r
+        assert r["iters"] == r_a["iters"] and r["evals"] == r_a["evals"]
+        assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(d["rho"], n_a)
+        assert 0.0 <= d["t_admit"] <= d["t_done"]
+        lat.append(d["t_done"])
+    p50, p99 = np.percentile(lat, [50, 99])
+    assert 0 < p50 <= p99
+    eng.close()
+
+
+def test_engine_admission_limits():
+    skx, _ = _lib()
+    s = W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 32, seed=46)
+    _say("case: engine budget")
+    eng = skx.Engine(0, hbm_budget=1 << 20, max_slots=4)
+    with pytest.raises(skx.SkxError):
+        eng.submit(s)                       # 32^3 mixed needs far more than 1 MiB
+    bad = W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 14, seed=46)
+    with pytest.raises(skx.SkxError):
+        eng.submit(bad)                     # 14 is not 5-smooth
+    assert eng.pending() == 0
+    eng.close()
