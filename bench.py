@@ -13,6 +13,11 @@ Metric: grid-point functional evaluations per second,
 sum over solves of (evaluations x grid points) / wall time of the step.
 The plain FP64 GPU path is timed on the same workload for the speedup,
 and the mixed results are checked against it per solve (Ha/atom).
+
+The headline timed region records a HIP-event pair around every pass launch
+(the library then launches eagerly); the per-pass times and the roofline come
+from those events. The same steps are then timed again replayed from captured
+HIP graphs without events (value_graphs).
 """
 from __future__ import annotations
 
@@ -198,6 +203,16 @@ def main():
     prof = skx.profile_read()
     value = total_work / wall
 
+    # the same steps replayed from captured HIP graphs (no per-launch events)
+    graph_work = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.steps):
+        graph_work += work(step(ctxs, rhos))
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    print(f"graph steps: {wall_graph:.3f} s", file=sys.stderr, flush=True)
+
     # roofline of the dominant evaluation kernel
     dom = max(("passA", "passB", "passC"), key=lambda k: prof[k][0])
     ms, launches = prof[dom]
@@ -228,6 +243,8 @@ def main():
                    "global_batch": len(systems), "grid": 64, "parallelism": "batch"},
         "roofline": roof,
         "passes_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "value_graphs": graph_work / wall_graph,
+        "ms_per_step_graphs": wall_graph / args.steps * 1e3,
         "evals": evals,
     }
     if fp64 is not None:

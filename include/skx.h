@@ -190,6 +190,13 @@ int skx_profile_enable(int on);
 int skx_profile_reset(void);
 int skx_profile_read(double *ms, long long *launches, int n);
 
+/* Process-wide: capture the optimisation driver's fixed chunk of step
+ * sequences once per batch into a HIP graph and replay it (on = 1, the
+ * default), or launch every kernel eagerly (on = 0). Results are identical
+ * either way. While per-pass profiling is enabled the driver launches
+ * eagerly. Returns the previous setting. */
+int skx_set_graphs(int on);
+
 /* Time the three evaluation passes over a batch of nctx configured contexts
  * (uniform starting density, all in the precision of ctxs[0]): reps timed
  * repetitions after one warm-up; ms_out[0..2] receive the mean milliseconds

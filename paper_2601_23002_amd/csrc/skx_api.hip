@@ -499,6 +499,10 @@ struct Profiler {
   std::mutex mu;
 } g_prof;
 
+// Step sequences of the optimisation driver are captured into a HIP graph
+// and replayed (process-wide switch, on by default).
+bool g_graphs = true;
+
 hipEvent_t prof_event() {
   if (!g_prof.pool.empty()) {
     hipEvent_t e = g_prof.pool.back();
@@ -510,7 +514,8 @@ hipEvent_t prof_event() {
   return e;
 }
 
-// Launch `fn` between two recorded events when profiling is on.
+// Launch `fn` between two recorded events when profiling is on (the driver
+// launches eagerly then, so every launch has its own pair).
 template <typename F>
 hipError_t timed(int which, hipStream_t s, F fn) {
   if (!g_prof.on) return fn();
@@ -524,7 +529,6 @@ hipError_t timed(int which, hipStream_t s, F fn) {
 
 // Fold finished event pairs into the totals (call after a stream sync).
 void prof_fold() {
-  if (g_prof.pending.empty()) return;
   for (auto &p : g_prof.pending) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
@@ -550,33 +554,69 @@ hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
 }
 
 // Drive a batch until every solve is DONE or FAILED. States are polled
-// every `chunk` steps; the step sequence itself makes every decision.
+// every `chunk` steps; the step sequence itself makes every decision, so a
+// chunk is the same work every time and is captured once into a HIP graph
+// (eager launches when graphs are off or capture is refused).
 int drive(skx_ctx *c, const BatchLaunch &bl, const std::vector<OptState *> &states,
           int max_steps, hipStream_t s) {
+  (void)states;
   hipError_t e = launch_normalize(bl, s);
   if (e != hipSuccess) return hip_fail(c, e, "normalisation kernels");
   const int chunk = 8;
-  std::vector<int> ph(states.size());
+  const int n = bl.nsolve;
+  int *dph = nullptr;
+  e = hipMallocAsync((void **)&dph, sizeof(int) * n, s);
+  if (e != hipSuccess) return hip_fail(c, e, "phase buffer");
+  std::vector<int> ph(n);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // per-launch HIP-event timing needs the eager launches
+  if (g_graphs && !g_prof.on) {
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      hipError_t ec = hipSuccess;
+      for (int k = 0; k < chunk && ec == hipSuccess; ++k) ec = step_sequence(bl, s);
+      if (ec == hipSuccess) ec = gather_phases(bl.dev, n, dph, s);
+      e = hipStreamEndCapture(s, &graph);
+      if (ec == hipSuccess && e == hipSuccess)
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ec != hipSuccess || e != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        graph = nullptr;
+        exec = nullptr;
+        (void)hipGetLastError();
+        e = hipSuccess;
+      }
+    } else {
+      (void)hipGetLastError();
+      e = hipSuccess;
+    }
+  }
+  int rc = SKX_OK;
   int steps = 0;
   while (steps < max_steps) {
-    for (int k = 0; k < chunk; ++k) {
-      e = step_sequence(bl, s);
-      if (e != hipSuccess) return hip_fail(c, e, "step kernels");
+    if (exec) {
+      e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) { rc = hip_fail(c, e, "step graph"); break; }
+    } else {
+      for (int k = 0; k < chunk && e == hipSuccess; ++k) e = step_sequence(bl, s);
+      if (e == hipSuccess) e = gather_phases(bl.dev, n, dph, s);
+      if (e != hipSuccess) { rc = hip_fail(c, e, "step kernels"); break; }
     }
     steps += chunk;
-    bool all = true;
-    for (size_t i = 0; i < states.size(); ++i) {
-      e = hipMemcpyAsync(&ph[i], &states[i]->phase, sizeof(int), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return hip_fail(c, e, "state readback");
-    }
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(c, e, "step execution");
+    e = hipMemcpyAsync(ph.data(), dph, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rc = hip_fail(c, e, "step execution"); break; }
     prof_fold();
+    bool all = true;
     for (int p : ph)
       if (p != PH_DONE && p != PH_FAILED) { all = false; break; }
     if (all) break;
   }
-  return SKX_OK;
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  hipFreeAsync(dph, s);
+  return rc;
 }
 
 int run_optimize(skx_ctx *c, Instance &I, void *rho_dev, const skx_opt_params &p, double gtol,
@@ -1146,6 +1186,12 @@ int skx_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = on != 0;
   return SKX_OK;
+}
+
+int skx_set_graphs(int on) {
+  const int old = g_graphs ? 1 : 0;
+  g_graphs = on != 0;
+  return old;
 }
 
 int skx_profile_reset(void) {

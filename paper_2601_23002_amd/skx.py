@@ -109,6 +109,7 @@ _sig("skx_fd_eval", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_doub
 _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)])
 _sig("skx_profile_enable", C.c_int, [C.c_int])
+_sig("skx_set_graphs", C.c_int, [C.c_int])
 _sig("skx_profile_reset", C.c_int, [])
 _sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
 _sig("skx_bench_eval", C.c_int, [C.POINTER(_VP), C.c_int, C.c_int, C.POINTER(C.c_double)])
@@ -293,6 +294,12 @@ PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "preco
 
 def profile_enable(on=True):
     _lib.skx_profile_enable(1 if on else 0)
+
+
+def set_graphs(on=True):
+    """Replay the driver's step sequences from a captured HIP graph (default)
+    or launch them eagerly; returns the previous setting."""
+    return bool(_lib.skx_set_graphs(1 if on else 0))
 
 
 def profile_reset():

@@ -133,3 +133,28 @@ def test_engine_admission_limits():
         eng.submit(bad)                     # 14 is not 5-smooth
     assert eng.pending() == 0
     eng.close()
+
+
+def test_graph_replay_equals_eager():
+    """The driver replays one captured graph per chunk of step sequences, with
+    host polling and synchronisation between replays; every solve must end in
+    the state of the eager launches, on repeated calls."""
+    skx, torch = _lib()
+    systems = _systems()
+    kw = dict(gtol=1e-9, max_iter=400, m=5, fp32_switch_gtol=1e-5)
+    out = {}
+    for graphs in (False, True, True):
+        _say(f"case: run_batch mixed, graphs={graphs}")
+        skx.set_graphs(graphs)
+        ctxs = [skx.Context(0).setup(s, precision=skx.MIXED) for s in systems]
+        rhos = [torch.empty(s.n, dtype=torch.float64, device="cuda") for s in systems]
+        res = skx.run_batch(ctxs, rhos, **kw)
+        key = [(r["iters"], r["evals"], r["energy"]["free_energy"]) for r in res]
+        dens = [r.cpu().numpy() for r in rhos]
+        if "eager" not in out:
+            out["eager"] = (key, dens)
+        else:
+            assert key == out["eager"][0]
+            for a, b in zip(dens, out["eager"][1]):
+                assert np.array_equal(a, b)
+    skx.set_graphs(True)
