@@ -99,6 +99,15 @@ Plan make_plan(int n, int twoff) {
   while (m % 2 == 0 && p.nst < MAX_STAGES) push(2);
   while (m % 3 == 0 && p.nst < MAX_STAGES) push(3);
   while (m % 5 == 0 && p.nst < MAX_STAGES) push(5);
+  int Ns = 1;
+  for (int st = 0; st < p.nst; ++st) {
+    const int r = (p.rad >> (4 * st)) & 15u;
+    const unsigned nb = (unsigned)(n / r);
+    p.m_nb[st] = (0xFFFFFFFFull / nb) + 1ull;
+    p.m_ns[st] = (0xFFFFFFFFull / (unsigned)Ns) + 1ull;
+    p.twstep[st] = n / (Ns * r);
+    Ns *= r;
+  }
   return p;
 }
 

@@ -17,6 +17,14 @@ template <typename T> __device__ __forceinline__ SKX_G T *gptr(const void *p) {
   return (SKX_G T *)(void *)(p);
 }
 
+// Per-solve control state is read-only in the grid-wide kernels; reading it
+// through the constant address space turns every field into a scalar load,
+// and the branches on it into uniform branches.
+#define SKX_C __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ const SKX_C T *cptr(const void *p) {
+  return (const SKX_C T *)(p);
+}
+
 // HIP's vector structs cannot be copied through address-space-qualified
 // pointers; move them as clang native vectors instead.
 template <typename V> struct NativeOf;
@@ -36,6 +44,11 @@ template <typename V> __device__ __forceinline__ void stg(SKX_G V *p, const V &v
   __builtin_memcpy(&w, &v, sizeof(V));
   *reinterpret_cast<SKX_G N *>(p) = w;
 }
+
+// An empty asm that "redefines" a lane index: index arithmetic after it
+// cannot be hoisted out of enclosing loops, where it would stay live in
+// registers for the whole kernel and cut the occupancy.
+#define SKX_OPAQUE(x) asm volatile("" : "+v"(x))
 
 template <typename R> struct Vec2;
 template <> struct Vec2<double> { typedef double2 T; };
@@ -132,10 +145,12 @@ struct UDiv {
   unsigned d;
   unsigned long long m;
 };
+// ceil(2^32/d) = floor((2^32 - 1)/d) + 1 for d >= 1: one 32-bit division
+// (a 64-bit integer division would cost ~100 scalar instructions per call).
 __device__ __forceinline__ UDiv make_udiv(unsigned d) {
   UDiv r;
   r.d = d;
-  r.m = ((1ull << 32) + d - 1) / d;
+  r.m = (unsigned long long)(0xFFFFFFFFu / d) + 1ull;
   return r;
 }
 __device__ __forceinline__ unsigned udiv(unsigned x, const UDiv &v) {
@@ -150,13 +165,16 @@ __device__ __forceinline__ unsigned udiv(unsigned x, const UDiv &v) {
 // its results, so the stage runs in place. tw[k] = exp(-2 pi i k / N).
 // ---------------------------------------------------------------------------
 template <typename V, int RAD, int MAXB, bool INV>
-__device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int es, int ts,
-                                          const V *tw, int tid, int nthr) {
+__device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int twstep,
+                                          unsigned long long m_nb, unsigned long long m_ns,
+                                          int count, int es, int ts, const V *tw, int tid,
+                                          int nthr) {
   const int nb = N / RAD;
-  int per = (MAXB * nthr) / nb;
+  const UDiv dnb{(unsigned)nb, m_nb}, dns{(unsigned)Ns, m_ns};
+  SKX_OPAQUE(tid);
+  int per = (int)udiv((unsigned)(MAXB * nthr), dnb);
   if (per < 1) per = 1;
-  const int twstep = N / (Ns * RAD);
-  const UDiv dnb = make_udiv((unsigned)nb), dns = make_udiv((unsigned)Ns);
+#pragma unroll 1
   for (int t0 = 0; t0 < count; t0 += per) {
     const int t1 = (t0 + per < count) ? t0 + per : count;
     const int gtot = (t1 - t0) * nb;
@@ -198,19 +216,25 @@ __device__ __forceinline__ void fft_stage(V *buf, int N, int Ns, int count, int 
   }
 }
 
+// Full transform of `count` sequences of length pl.n (plan radices in
+// order; the per-stage division constants come precomputed in the plan).
 template <typename V, int MAXB, bool INV>
 __device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int es, int ts,
                                         const V *tw, int tid, int nthr) {
+  SKX_OPAQUE(tid);
   const int n = pl.n, nst = pl.nst;
   const unsigned code = pl.rad;
   int Ns = 1;
+#pragma unroll 1
   for (int s = 0; s < nst; ++s) {
     const int rad = (code >> (4 * s)) & 15u;
+    const int tws = pl.twstep[s];
+    const unsigned long long mb = pl.m_nb[s], ms = pl.m_ns[s];
     switch (rad) {
-      case 4: fft_stage<V, 4, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
-      case 2: fft_stage<V, 2, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
-      case 3: fft_stage<V, 3, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
-      default: fft_stage<V, 5, MAXB, INV>(buf, n, Ns, count, es, ts, tw, tid, nthr); break;
+      case 4: fft_stage<V, 4, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
+      case 2: fft_stage<V, 2, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
+      case 3: fft_stage<V, 3, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
+      default: fft_stage<V, 5, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
     }
     Ns *= rad;
   }
@@ -355,13 +379,21 @@ __device__ __forceinline__ int xcd_item(int b, int grid) {
   return x * q + (x < r ? x : r) + b / NX;
 }
 
+// Solve index of a work item (binary search of the batch prefix sums). The
+// result is workgroup-uniform; saying so lets every descriptor field live in
+// scalar registers instead of being loaded per lane.
 __device__ __forceinline__ int find_solve(const int *first, int nsolve, int item) {
   int lo = 0, hi = nsolve;     // first[lo] <= item < first[hi]
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
-    if (first[mid] <= item) lo = mid; else hi = mid;
+    if (__builtin_amdgcn_readfirstlane(first[mid]) <= item) lo = mid; else hi = mid;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// first[s] of the batch prefix sums as a workgroup-uniform value.
+__device__ __forceinline__ int first_of(const int *first, int s) {
+  return __builtin_amdgcn_readfirstlane(first[s]);
 }
 
 __device__ __forceinline__ int gidx(int m, int n) { return (2 * m < n) ? m : m - n; }

@@ -30,6 +30,11 @@ struct Plan {                      // 1D FFT plan for one axis length
   int nst;
   unsigned rad;                    // radix of stage s in bits [4s, 4s+4)
   int tw;                          // offset of exp(-2 pi i k / n) in the twiddle bank
+  // per stage s (Ns = product of the radices before s, RAD its radix):
+  // ceil(2^32 / (n / RAD)) and ceil(2^32 / Ns) for division by
+  // multiplication, and the twiddle stride n / (Ns RAD)
+  unsigned long long m_nb[MAX_STAGES], m_ns[MAX_STAGES];
+  int twstep[MAX_STAGES];
 };
 
 // Control state of one solve (device resident, FP64).

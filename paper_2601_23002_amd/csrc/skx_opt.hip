@@ -136,10 +136,10 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   const int item = blockIdx.x;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (st->phase != PH_UPDATE) return;
   const int tid = threadIdx.x;
-  const int wl = item - first[s];
+  const int wl = item - first_of(first, s);
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   const int par = st->par;
@@ -352,10 +352,10 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   const int item = blockIdx.x;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (st->phase != PH_NEED_DIR) return;
   const int tid = threadIdx.x;
-  const int wl = item - first[s];
+  const int wl = item - first_of(first, s);
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   const int par = st->par;
@@ -432,10 +432,10 @@ __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, in
   const int item = blockIdx.x;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (st->phase != PH_EVAL_INIT) return;
   const int tid = threadIdx.x;
-  const int wl = item - first[s];
+  const int wl = item - first_of(first, s);
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   SKX_G R *phi = gptr<R>(S.phi2[st->par]);

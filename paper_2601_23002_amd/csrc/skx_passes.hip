@@ -37,6 +37,12 @@ namespace skx {
 
 constexpr int MAXB_A = 2;
 constexpr int MAXB_C = 2;
+constexpr int MAXB_B = 2;
+// vector loads (pairs of grid values or complex values) each thread issues
+// before using any of them
+constexpr int LU_A = 4;
+constexpr int LU_L = 8;
+constexpr int LU_B = 4;
 constexpr int MODE_EVAL = 0, MODE_PREC = 1;
 
 template <typename R> __device__ __forceinline__ R rpow(R x, R a);
@@ -62,7 +68,7 @@ __device__ __forceinline__ void load_twiddles(V *dst, const double *bank, int of
 }
 
 // Trial-point coefficients: phi_t = ca phi + cb d.
-__device__ __forceinline__ void trial_coef(const OptState *st, const SolveDev &S, double &ca,
+__device__ __forceinline__ void trial_coef(const SKX_C OptState *st, const SolveDev &S, double &ca,
                                            double &cb, bool &use_d) {
   int ph = st->phase;
   if (ph == PH_TRIAL) {
@@ -136,6 +142,7 @@ __device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V
 template <typename V, typename R, int NT>
 __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V *tw2,
                                               const V *tw3, int tid) {
+  SKX_OPAQUE(tid);
   const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh;
   fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
   int per = (MAXB_C * 2 * NT) / n3;
@@ -180,6 +187,33 @@ __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V
   fft_lds<V, MAXB_C, true>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
 }
 
+// Copy one x-plane of a half spectrum ([n2][pitch] complex in HBM) into the
+// LDS plane [n2][pl], LU_L loads in flight per thread.
+template <typename V, int NT>
+__device__ __forceinline__ void load_plane(V *buf, const SKX_G V *src, int n2, int nh, int pitch,
+                                           int pl, int tid) {
+  SKX_OPAQUE(tid);
+  const UDiv dnh = make_udiv((unsigned)nh);
+  const int tot = n2 * nh;
+  for (int e0 = tid; e0 < tot; e0 += LU_L * NT) {
+    V t[LU_L];
+    int li[LU_L];
+#pragma unroll
+    for (int u = 0; u < LU_L; ++u) {
+      const int e = e0 + u * NT;
+      li[u] = -1;
+      if (e < tot) {
+        const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
+        li[u] = j * pl + k;
+        t[u] = ldg(src + (size_t)j * pitch + k);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LU_L; ++u)
+      if (li[u] >= 0) buf[li[u]] = t[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass A
 // ---------------------------------------------------------------------------
@@ -192,11 +226,11 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
   const int tid = threadIdx.x;
-  const int local = item - first[s];
+  const int local = item - first_of(first, s);
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   const int plane = local / nf, c = local % nf;
   const int fb = MODE == MODE_EVAL ? nth_field(S.fields, c) : 0;
@@ -216,73 +250,125 @@ __global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, i
     double ca, cb;
     bool use_d;
     trial_coef(st, S, ca, cb, use_d);
-    const SKX_G R *phi = gptr<R>(S.phi2[par]);
-    const SKX_G R *dd = gptr<R>(S.d);
-    SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
-    SKX_G R *v0 = gptr<R>(S.vpt);
-    SKX_G R *fpw = gptr<R>(S.fpt);
+    // fields are read and written as pairs of neighbours along z (n3 is
+    // even, so a pair never straddles a row). First phi_t for the whole
+    // plane, LU_A pair loads in flight per thread, parked in the LDS slots
+    // the transform will read; then, after a barrier, the pointwise work.
+    const size_t qbase = pbase >> 1;
+    const SKX_G V *phi = gptr<V>(S.phi2[par]) + qbase;
+    const SKX_G V *dd = gptr<V>(S.d) + qbase;
+    SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
     const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
     const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
     const bool need_f = (S.fields & F_F) != 0;
+    const int npair = np >> 1, h3 = n3 >> 1;
+    const UDiv dh3 = make_udiv((unsigned)h3), dnf = make_udiv((unsigned)nf);
+    for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
+      V pv[LU_A], dv[LU_A];
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) {
+          pv[u] = ldg(phi + q);
+          if (use_d) dv[u] = ldg(dd + q);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) {
+          const int j = (int)udiv((unsigned)q, dh3), k = 2 * (q - j * h3);
+          V o;
+          if (use_d) {
+            o.x = (R)(ca * (double)pv[u].x + cb * (double)dv[u].x);
+            o.y = (R)(ca * (double)pv[u].y + cb * (double)dv[u].y);
+          } else {
+            o.x = (R)(ca * (double)pv[u].x);
+            o.y = (R)(ca * (double)pv[u].y);
+          }
+          if (c == 0) stg(phit + q, o);
+          R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
+          slot[j & 1] = o.x;
+          slot[2 + (j & 1)] = o.y;
+        }
+      }
+    }
+    __syncthreads();
+    // per element from here (one element's FP64 work live at a time keeps
+    // the register count, and so the occupancy, in check)
+    SKX_G R *v0s = gptr<R>(S.vpt) + pbase;
+    SKX_G R *fps = gptr<R>(S.fpt) + pbase;
     const UDiv dn3 = make_udiv((unsigned)n3);
     for (int e = tid; e < np; e += NT) {
       const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
-      const size_t g = pbase + e;
-      R ph;
-      if (use_d) ph = (R)(ca * (double)phi[g] + cb * (double)dd[g]);
-      else ph = (R)(ca * (double)phi[g]);
-      if (c == 0) phit[g] = ph;
-      const R n = ph * ph;
       // the pointwise work of this plane is shared by its field workgroups:
       // rows j = c (mod nf) get the local energy densities, the local
       // potential T eta + v_xc and f = n^a stored for the assembly pass
-      const bool mine = (j % nf) == c;
+      const bool mine = (j - (int)udiv((unsigned)j, dnf) * nf) == c;
+      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]) + (j & 1);
+      const R ph = *slot;
+      const R n = ph * ph;
       R f = 0;
       if (need_f && (fb >= 2 || mine)) f = rpow(n, a);
       R x;
       if (fb == 0) x = ph;
       else if (fb == 1) x = n;
       else x = (fb == 2) ? f : (f - n0a) * (n - n0);
+      *slot = x * invM;
       if (mine) {
         const double nd = (double)n;
         double v = 0.0;
         if (!(nd == nd) || nd > 1e300) bad += 1.0;
         if (nd > 0.0) {
           nel += nd;
-          const double x = log(nd);
+          const double lx = log(nd);
           if (do_tf) {
             double eta, psi;
-            bad += fd_lookup(x - S.lnnT, fd, eta, psi);
+            bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
             e_tf += S.T * nd * psi;
             v += S.T * eta;
           }
           if (do_xc) {
             double eps, vx;
-            pz81_ln(x, eps, vx);
+            pz81_ln(lx, eps, vx);
             e_xc += nd * eps;
             v += vx;
           }
         }
-        v0[g] = (R)v;
-        if (need_f) fpw[g] = f;
+        v0s[e] = (R)v;
+        if (need_f) fps[e] = f;
       }
-      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
-      slot[j & 1] = x * invM;
     }
   } else {
     // residual of the accepted trial point, stored for the update pass
-    const SKX_G R *g = gptr<R>(S.grad);
-    const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
-    SKX_G R *rt = gptr<R>(S.r2[1 - par]);
+    const size_t qbase = pbase >> 1;
+    const SKX_G V *g = gptr<V>(S.grad) + qbase;
+    const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
+    SKX_G V *rt = gptr<V>(S.r2[1 - par]) + qbase;
     const R mu2 = (R)(2.0 * st->mut);
-    const UDiv dn3 = make_udiv((unsigned)n3);
-    for (int e = tid; e < np; e += NT) {
-      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
-      const size_t gi = pbase + e;
-      const R x = g[gi] - mu2 * phit[gi];
-      rt[gi] = x;
-      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
-      slot[j & 1] = x * invM;
+    const int npair = np >> 1, h3 = n3 >> 1;
+    const UDiv dh3 = make_udiv((unsigned)h3);
+    for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
+      V gv[LU_A], pv[LU_A];
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) { gv[u] = ldg(g + q); pv[u] = ldg(phit + q); }
+      }
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) {
+          const int j = (int)udiv((unsigned)q, dh3), k = 2 * (q - j * h3);
+          V x;
+          x.x = gv[u].x - mu2 * pv[u].x;
+          x.y = gv[u].y - mu2 * pv[u].y;
+          stg(rt + q, x);
+          R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
+          slot[j & 1] = x.x * invM;
+          slot[2 + (j & 1)] = x.y * invM;
+        }
+      }
     }
   }
   __syncthreads();
@@ -317,10 +403,10 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int tid = threadIdx.x;
-  const int local = item - first[s];
+  const int local = item - first_of(first, s);
   const int j = local / S.nkb, kb = local % S.nkb;
   const int k0 = kb * TK;
   const int n1 = S.n1, nf = MODE == MODE_EVAL ? S.nf : 1, W = nf * TK;
@@ -333,13 +419,26 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   SKX_G V *spec = gptr<V>(S.spec);
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   const UDiv dW = make_udiv((unsigned)W);
-  for (int e = tid; e < n1 * W; e += NT) {
-    const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
-    const int cc = r / TK, kk = r - cc * TK;
-    tile[i * Wp + r] = ldg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk);
+  for (int e0 = tid; e0 < n1 * W; e0 += LU_L * NT) {
+    V t[LU_L];
+    int li[LU_L];
+#pragma unroll
+    for (int u = 0; u < LU_L; ++u) {
+      const int e = e0 + u * NT;
+      li[u] = -1;
+      if (e < n1 * W) {
+        const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
+        const int cc = r / TK, kk = r - cc * TK;
+        li[u] = i * Wp + r;
+        t[u] = ldg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LU_L; ++u)
+      if (li[u] >= 0) tile[li[u]] = t[u];
   }
   __syncthreads();
-  if (S.debug != 2) fft_lds<V, 4, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+  if (S.debug != 2) fft_lds<V, MAXB_B, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
   if (S.debug == 1) {
     for (int e = tid; e < n1 * W; e += NT) {
       const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
@@ -373,10 +472,30 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     const SKX_G V *vloc = gptr<V>(S.vloc);
     const R b3 = (R)(S.beta / 3.0);
     const double FOURPI = 12.566370614359172954;
-    for (int e = tid; e < n1 * TK; e += NT) {
+    const SKX_G double *wt = gptr<double>(S.w);
+    const SKX_G double *wpt = gptr<double>(S.wp);
+    for (int e0 = tid; e0 < n1 * TK; e0 += LU_B * NT) {
+      // gathers of this batch first: V_loc(G) and the kernel tables
+      V vlb[LU_B];
+      double wb[LU_B], wpb[LU_B];
+#pragma unroll
+      for (int u = 0; u < LU_B; ++u) {
+        const int e = e0 + u * NT;
+        const int i = e / TK, kk = e - i * TK;
+        const int k3 = k0 + kk;
+        if (e < n1 * TK && k3 < S.nh) {
+          const int g1 = gidx(i, n1);
+          const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+          if (do_loc) vlb[u] = ldg(vloc + ((size_t)i * S.n2 + j) * S.pitch + k3);
+          if (sf >= 0) { wb[u] = wt[sidx]; wpb[u] = wpt[sidx]; }
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < LU_B; ++u) {
+      const int e = e0 + u * NT;
       const int i = e / TK, kk = e - i * TK;
       const int k3 = k0 + kk;
-      if (k3 >= S.nh || S.debug) continue;
+      if (e >= n1 * TK || k3 >= S.nh || S.debug) continue;
       const int g1 = gidx(i, n1);
       const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
       const double G2 = kscale * (double)sidx;
@@ -391,7 +510,6 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       }
       {
         const V x = row[sn * TK + kk];
-        const size_t vi = ((size_t)i * S.n2 + j) * S.pitch + k3;
         double bx = 0.0, by = 0.0;
         if (do_h && sidx > 0) {
           const double m2 = (double)x.x * x.x + (double)x.y * x.y;
@@ -400,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
           by = FOURPI * x.y / G2;
         }
         if (do_loc) {
-          const V vl = ldg(vloc + vi);
+          const V vl = vlb[u];
           eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
           bx += vl.x;
           by += vl.y;
@@ -411,8 +529,8 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       }
       if (sf >= 0) {
         const V f = row[sf * TK + kk];
-        const R w = (R)S.w[sidx];
-        const R wp = (R)S.wp[sidx];
+        const R w = (R)wb[u];
+        const R wp = (R)wpb[u];
         V P; P.x = 0; P.y = 0;
         if (do_nl0) {
           ef0 += wgt * (double)w * ((double)f.x * f.x + (double)f.y * f.y);
@@ -428,9 +546,10 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
         row[sf * TK + kk] = P;
       }
     }
+    }
   }
   __syncthreads();
-  fft_lds<V, 4, true>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+  fft_lds<V, MAXB_B, true>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
   for (int e = tid; e < n1 * W; e += NT) {
     const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
@@ -464,11 +583,11 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  const OptState *st = S.st;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
   const int tid = threadIdx.x;
-  const int plane = item - first[s];
+  const int plane = item - first_of(first, s);
   const int n2 = S.n2, n3 = S.n3, nh = S.nh;
   const int pl = nh;
   V *buf = reinterpret_cast<V *>(smem);
@@ -483,11 +602,8 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
 
   if (MODE == MODE_PREC) {
     SKX_G R *out = gptr<R>(S.pr2[1 - par]);
-    const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
-    for (int e = tid; e < n2 * nh; e += NT) {
-      const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
-      buf[j * pl + k] = ldg(spec + ibase + (size_t)j * S.pitch + k);
-    }
+    const UDiv dn3 = make_udiv((unsigned)n3);
+    load_plane<V, NT>(buf, spec + ibase, n2, nh, S.pitch, pl, tid);
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
     for (int e = tid; e < np; e += NT) {
@@ -498,54 +614,104 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
     return;
   }
 
-  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
-  const SKX_G R *v0 = gptr<R>(S.vpt);
-  const SKX_G R *fpw = gptr<R>(S.fpt);
+  // phi_t, the local potential and n^a are read as pairs along z, LU_A
+  // pairs per thread in flight
+  const size_t qbase = pbase >> 1;
+  const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
+  const SKX_G V *v0 = gptr<V>(S.vpt) + qbase;
+  const SKX_G V *fpw = gptr<V>(S.fpt) + qbase;
   SKX_G R *grad = gptr<R>(S.grad);
   R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : (R *)(grad + pbase);
   const R a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
-  const UDiv dn3 = make_udiv((unsigned)n3), dnh = make_udiv((unsigned)nh);
-  for (int e = tid; e < np; e += NT)
-    acc[e] = S.debug ? (R)0 : (R)2 * phit[pbase + e] * v0[pbase + e];
+  const int npair = np >> 1, h3 = n3 >> 1;
+  const UDiv dh3 = make_udiv((unsigned)h3);
+  for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
+    V pv[LU_A], vv[LU_A];
+#pragma unroll
+    for (int u = 0; u < LU_A; ++u) {
+      const int q = q0 + u * NT;
+      if (q < npair) { pv[u] = ldg(phit + q); vv[u] = ldg(v0 + q); }
+    }
+#pragma unroll
+    for (int u = 0; u < LU_A; ++u) {
+      const int q = q0 + u * NT;
+      if (q < npair) {
+        acc[2 * q] = S.debug ? (R)0 : (R)2 * pv[u].x * vv[u].x;
+        acc[2 * q + 1] = S.debug ? (R)0 : (R)2 * pv[u].y * vv[u].y;
+      }
+    }
+  }
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0 || (S.debug && fb != 0)) continue;
-    const SKX_G V *src = spec + (size_t)sl * S.H + ibase;
     __syncthreads();
-    for (int e = tid; e < n2 * nh; e += NT) {
-      const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
-      buf[j * pl + k] = ldg(src + (size_t)j * S.pitch + k);
-    }
+    load_plane<V, NT>(buf, spec + (size_t)sl * S.H + ibase, n2, nh, S.pitch, pl, tid);
     __syncthreads();
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
-    for (int e = tid; e < np; e += NT) {
-      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
-      const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
-      const R val = cv[j & 1];
-      R coef;
-      if (fb == 0) {
-        coef = (R)1;
-      } else {
-        const R p = phit[pbase + e];
-        if (fb == 1) {
-          coef = (R)2 * p;
-        } else {
-          // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
-          const R f = fpw[pbase + e];
-          const R cP = (p != (R)0) ? a2 * f / p : (R)0;
-          coef = (fb == 2) ? cP : cP * (p * p - n0) + (R)2 * p * (f - n0a);
+    int tq = tid;
+    SKX_OPAQUE(tq);
+    for (int q0 = tq; q0 < npair; q0 += LU_A * NT) {
+      V pv[LU_A], fv[LU_A];
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) {
+          if (fb >= 1) pv[u] = ldg(phit + q);
+          if (fb >= 2) fv[u] = ldg(fpw + q);
         }
       }
-      acc[e] += coef * val;
+#pragma unroll
+      for (int u = 0; u < LU_A; ++u) {
+        const int q = q0 + u * NT;
+        if (q < npair) {
+          const int j = (int)udiv((unsigned)q, dh3), k = 2 * (q - j * h3);
+          const R *cv = reinterpret_cast<const R *>(&buf[(j >> 1) * 2 * pl + k]);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const R val = cv[2 * h + (j & 1)];
+            R coef;
+            if (fb == 0) {
+              coef = (R)1;
+            } else {
+              const R p = h ? pv[u].y : pv[u].x;
+              if (fb == 1) {
+                coef = (R)2 * p;
+              } else {
+                // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
+                const R f = h ? fv[u].y : fv[u].x;
+                const R cP = (p != (R)0) ? a2 * f / p : (R)0;
+                coef = (fb == 2) ? cP : cP * (p * p - n0) + (R)2 * p * (f - n0a);
+              }
+            }
+            acc[2 * q + h] += coef * val;
+          }
+        }
+      }
     }
   }
   __syncthreads();
   double sphig = 0.0, bad = 0.0;
-  for (int e = tid; e < np; e += NT) {
-    const R g = acc[e];
-    if (ACC_LDS) grad[pbase + e] = g;
-    sphig += (double)phit[pbase + e] * (double)g;
-    if (!(g == g)) bad += 1.0;
+  SKX_G V *grad2 = gptr<V>(S.grad) + qbase;
+  for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
+    V pv[LU_A];
+#pragma unroll
+    for (int u = 0; u < LU_A; ++u) {
+      const int q = q0 + u * NT;
+      if (q < npair) pv[u] = ldg(phit + q);
+    }
+#pragma unroll
+    for (int u = 0; u < LU_A; ++u) {
+      const int q = q0 + u * NT;
+      if (q < npair) {
+        V g;
+        g.x = acc[2 * q];
+        g.y = acc[2 * q + 1];
+        if (ACC_LDS) stg(grad2 + q, g);
+        sphig += (double)pv[u].x * (double)g.x + (double)pv[u].y * (double)g.y;
+        if (!(g.x == g.x)) bad += 1.0;
+        if (!(g.y == g.y)) bad += 1.0;
+      }
+    }
   }
   double v[PART_C] = {sphig, bad};
   double tot[PART_C];
