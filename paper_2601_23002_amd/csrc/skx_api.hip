@@ -95,6 +95,7 @@ Plan make_plan(int n, int twoff) {
   p.tw = twoff;
   int m = n;
   auto push = [&](unsigned r) { p.rad |= r << (4 * p.nst); p.nst++; m /= (int)r; };
+  while (m % 8 == 0 && p.nst < MAX_STAGES) push(8);
   while (m % 4 == 0 && p.nst < MAX_STAGES) push(4);
   while (m % 2 == 0 && p.nst < MAX_STAGES) push(2);
   while (m % 3 == 0 && p.nst < MAX_STAGES) push(3);

@@ -113,6 +113,32 @@ template <bool INV, typename V> struct Bfly<4, INV, V> {
   }
 };
 
+// Radix 8 as two radix-4 DFTs of the even and odd points combined with the
+// eighth roots of unity (forward w = (1 - i)/sqrt2, inverse its conjugate).
+template <bool INV, typename V> struct Bfly<8, INV, V> {
+  __device__ __forceinline__ static void run(V *v) {
+    typedef decltype(v[0].x) R;
+    const R H = (R)0.70710678118654752440;     // 1/sqrt(2)
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<4, INV, V>::run(e);
+    Bfly<4, INV, V>::run(o);
+    V t1, t2, t3;
+    if (!INV) {
+      t1.x = H * (o[1].x + o[1].y); t1.y = H * (o[1].y - o[1].x);
+      t3.x = H * (o[3].y - o[3].x); t3.y = -H * (o[3].x + o[3].y);
+    } else {
+      t1.x = H * (o[1].x - o[1].y); t1.y = H * (o[1].x + o[1].y);
+      t3.x = -H * (o[3].x + o[3].y); t3.y = H * (o[3].x - o[3].y);
+    }
+    t2 = cmul_mi<INV>(o[2]);
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);   v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);   v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);   v[7] = csub(e[3], t3);
+  }
+};
+
 template <bool INV, typename V> struct Bfly<5, INV, V> {
   __device__ __forceinline__ static void run(V *v) {
     typedef decltype(v[0].x) R;
@@ -231,6 +257,7 @@ __device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int e
     const int tws = pl.twstep[s];
     const unsigned long long mb = pl.m_nb[s], ms = pl.m_ns[s];
     switch (rad) {
+      case 8: fft_stage<V, 8, (MAXB + 1) / 2, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
       case 4: fft_stage<V, 4, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
       case 2: fft_stage<V, 2, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
       case 3: fft_stage<V, 3, MAXB, INV>(buf, n, Ns, tws, mb, ms, count, es, ts, tw, tid, nthr); break;
