@@ -41,6 +41,7 @@ constexpr int MAXB_B = 2;
 // vector loads (pairs of grid values or complex values) each thread issues
 // before using any of them
 constexpr int LU_A = 4;
+constexpr int LU_C = 2;
 constexpr int LU_L = 8;
 constexpr int LU_B = 4;
 constexpr int MODE_EVAL = 0, MODE_PREC = 1;
@@ -218,7 +219,7 @@ __device__ __forceinline__ void load_plane(V *buf, const SKX_G V *src, int n2, i
 // Pass A
 // ---------------------------------------------------------------------------
 template <typename R, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_passA(SolveDev *dev, const int *first, int nsolve,
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *dev, const int *first, int nsolve,
                                               int grid, const double *twbank, FDTable fd) {
   typedef typename Vec2<R>::T V;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
 // workgroup revisits while it is still in L2.
 // ---------------------------------------------------------------------------
 template <typename R, int NT, bool ACC_LDS, int MODE>
-__global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, int nsolve,
+__global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first, int nsolve,
                                               int grid, const double *twbank, FDTable fd) {
   typedef typename Vec2<R>::T V;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
     return;
   }
 
-  // phi_t, the local potential and n^a are read as pairs along z, LU_A
+  // phi_t, the local potential and n^a are read as pairs along z, LU_C
   // pairs per thread in flight
   const size_t qbase = pbase >> 1;
   const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
@@ -625,15 +626,15 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   const R a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
   const int npair = np >> 1, h3 = n3 >> 1;
   const UDiv dh3 = make_udiv((unsigned)h3);
-  for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
-    V pv[LU_A], vv[LU_A];
+  for (int q0 = tid; q0 < npair; q0 += LU_C * NT) {
+    V pv[LU_C], vv[LU_C];
 #pragma unroll
-    for (int u = 0; u < LU_A; ++u) {
+    for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
       if (q < npair) { pv[u] = ldg(phit + q); vv[u] = ldg(v0 + q); }
     }
 #pragma unroll
-    for (int u = 0; u < LU_A; ++u) {
+    for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
       if (q < npair) {
         acc[2 * q] = S.debug ? (R)0 : (R)2 * pv[u].x * vv[u].x;
@@ -650,10 +651,10 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
     plane_inverse<V, R, NT>(buf, S, tw2, tw3, tid);
     int tq = tid;
     SKX_OPAQUE(tq);
-    for (int q0 = tq; q0 < npair; q0 += LU_A * NT) {
-      V pv[LU_A], fv[LU_A];
+    for (int q0 = tq; q0 < npair; q0 += LU_C * NT) {
+      V pv[LU_C], fv[LU_C];
 #pragma unroll
-      for (int u = 0; u < LU_A; ++u) {
+      for (int u = 0; u < LU_C; ++u) {
         const int q = q0 + u * NT;
         if (q < npair) {
           if (fb >= 1) pv[u] = ldg(phit + q);
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
         }
       }
 #pragma unroll
-      for (int u = 0; u < LU_A; ++u) {
+      for (int u = 0; u < LU_C; ++u) {
         const int q = q0 + u * NT;
         if (q < npair) {
           const int j = (int)udiv((unsigned)q, dh3), k = 2 * (q - j * h3);
@@ -692,15 +693,15 @@ __global__ __launch_bounds__(NT) void k_passC(SolveDev *dev, const int *first, i
   __syncthreads();
   double sphig = 0.0, bad = 0.0;
   SKX_G V *grad2 = gptr<V>(S.grad) + qbase;
-  for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
-    V pv[LU_A];
+  for (int q0 = tid; q0 < npair; q0 += LU_C * NT) {
+    V pv[LU_C];
 #pragma unroll
-    for (int u = 0; u < LU_A; ++u) {
+    for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
       if (q < npair) pv[u] = ldg(phit + q);
     }
 #pragma unroll
-    for (int u = 0; u < LU_A; ++u) {
+    for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
       if (q < npair) {
         V g;
