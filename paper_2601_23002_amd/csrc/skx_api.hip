@@ -234,7 +234,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   SolveDev &h = I.h;
   h = SolveDev{};
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = nh; h.pitch = pitch;
-  h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg;
+  h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg; h.mh = m;
   h.M = M; h.H = H;
   h.phi2[0] = base + o_phi; h.phi2[1] = base + o_phit; h.grad = base + o_grad;
   h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
@@ -327,6 +327,8 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
   bl.accC_lds = lc_acc <= LDS_MAX ? 1 : 0;
   if (bl.accC_lds) lc = std::max(lc, lc_acc);
   bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
+  bl.mh = 1;
+  for (const SolveDev &h : hs) bl.mh = std::max(bl.mh, std::min(h.mh, MMAX));
   return SKX_OK;
 }
 

@@ -65,6 +65,7 @@ struct SolveDev {
   int slot[NFIELD];                // spectrum slot of phi, n, f, h (-1 if absent)
   int nkb, tk;                     // pass-B column blocks and their width
   int nwg_vec;                     // workgroups of the vector passes
+  int mh;                          // history slots allocated (>= the solve's m)
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
   unsigned terms;
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
@@ -113,6 +114,7 @@ struct BatchLaunch {
   const int *firstA, *firstB, *firstC, *firstV;  // device prefix sums (nsolve+1)
   size_t ldsA, ldsB, ldsC;
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
+  int mh;                          // largest history length of the batch (1..MMAX)
 };
 hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);  // passes A|B|C
 hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s);

@@ -39,6 +39,17 @@ __device__ void sum_parts(const double *part, int nrow, double *sh, int tid, int
   block_reduce<N>(v, sh, tid, nthr, out);
 }
 
+// The control state of one solve is staged in LDS for the serial part of
+// each finalize kernel, so that thread 0 works at LDS latency instead of a
+// chain of dependent global-memory round trips; every thread copies a slice
+// in and out.
+__device__ __forceinline__ void stage_state(OptState *dst, const OptState *src, int tid) {
+  static_assert(sizeof(OptState) % 8 == 0, "OptState is copied as doubles");
+  const double *a = reinterpret_cast<const double *>(src);
+  double *b = reinterpret_cast<double *>(dst);
+  for (int i = tid; i < (int)(sizeof(OptState) / 8); i += 256) b[i] = a[i];
+}
+
 // Direction d = -P r + kappa' phi (history dropped).
 __device__ void set_steepest(OptState *st, double ne) {
   st->k = 0;
@@ -52,20 +63,8 @@ __device__ void set_steepest(OptState *st, double ne) {
 // ---------------------------------------------------------------------------
 // Close an evaluation: energies, mu, and the line-search decision.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve) {
-  __shared__ double sh[4 * 16];
-  __shared__ double tA[PART_A], tB[PART_B], tC[PART_C];
-  const int s = blockIdx.x;
-  if (s >= nsolve) return;
-  SolveDev &S = dev[s];
-  OptState *st = S.st;
-  const int ph = st->phase;
-  if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
-  const int tid = threadIdx.x;
-  sum_parts<PART_A>(S.partA, S.n1 * S.nf, sh, tid, 256, tA);
-  sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
-  sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
-  if (tid != 0) return;
+__device__ void finalize_eval_body(OptState *st, const SolveDev &S, const double *tA,
+                                   const double *tB, const double *tC, int ph) {
   const double PI = 3.14159265358979323846;
   double e[12];
   e[E_TF] = S.dV * tA[0];
@@ -123,12 +122,33 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
   }
 }
 
+__global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve) {
+  __shared__ double sh[4 * 16];
+  __shared__ double tA[PART_A], tB[PART_B], tC[PART_C];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  const int ph = st->phase;
+  if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
+  const int tid = threadIdx.x;
+  sum_parts<PART_A>(S.partA, S.n1 * S.nf, sh, tid, 256, tA);
+  sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
+  sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
+  __shared__ OptState lst;
+  stage_state(&lst, st, threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) finalize_eval_body(&lst, S, tA, tB, tC, ph);
+  __syncthreads();
+  stage_state(st, &lst, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Update pass: the new pair (s, P y) and every inner product the compact
 // L-BFGS needs, in one sweep over the history. Reads the current point
 // (buffers par) and the accepted trial point (buffers 1 - par).
 // ---------------------------------------------------------------------------
-template <typename R, int NT>
+template <typename R, int NT, int MM>
 __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
                                                int grid) {
   __shared__ double sh[64 * (NT / 64)];
@@ -151,14 +171,18 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   const SKX_G R *prt = gptr<R>(S.pr2[1 - par]);
   SKX_G R *Sv = gptr<R>(S.S);
   SKX_G R *Yv = gptr<R>(S.Y);
-  double acc[NDOT];
+  // MM = largest history length of the batch: at most KO = MM - 1 old pairs
+  // take part, so only NA sums are carried (laid out in blocks of KO, then
+  // the ten new-pair sums) and scattered to the MMAX layout at the end
+  constexpr int KO = MM - 1, NA = 6 * KO + 10;
+  double acc[NA];
 #pragma unroll
-  for (int q = 0; q < NDOT; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
   // acc layout: [i] s_i.y, [M+i] Py_i.y, [2M+i] s_i.r_t, [3M+i] Py_i.r_t,
   // [4M+i] s_i.phi_t, [5M+i] Py_i.phi_t (old pairs), then at B = 6M:
   // s.y, y.Py, s.r_t, Py.r_t, s.phi_t, Py.phi_t, r_t.r_t, r_t.Pr_t,
   // phi_t.Pr_t, r_t.phi_t
-  const int B = 6 * MMAX;
+  const int B = 6 * KO;
   if (st->reset_pending == 1) {
     // first accepted point: residual inner products only
     for (long long g = g0 + tid; g < g1; g += NT) {
@@ -171,9 +195,9 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   } else {
     const int m = st->m, k = st->k, head = st->head;
     const int kold = (k == m) ? m - 1 : k;
-    int slot[MMAX];
+    int slot[KO > 0 ? KO : 1];
 #pragma unroll
-    for (int i = 0; i < MMAX; ++i) slot[i] = (i < kold) ? ((head - kold + i + 2 * m) % m) : 0;
+    for (int i = 0; i < KO; ++i) slot[i] = (i < kold) ? ((head - kold + i + 2 * m) % m) : 0;
     SKX_G R *Snew = Sv + (size_t)head * S.M;
     SKX_G R *Ynew = Yv + (size_t)head * S.M;
     for (long long g = g0 + tid; g < g1; g += NT) {
@@ -182,16 +206,16 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
       const R yv = rtg - r[g];
       const R pyv = prtg - pr[g];
 #pragma unroll
-      for (int i = 0; i < MMAX; ++i) {
+      for (int i = 0; i < KO; ++i) {
         if (i < kold) {
           const double Si = (double)Sv[(size_t)slot[i] * S.M + g];
           const double Yi = (double)Yv[(size_t)slot[i] * S.M + g];
           acc[i] += Si * yv;
-          acc[MMAX + i] += Yi * yv;
-          acc[2 * MMAX + i] += Si * rtg;
-          acc[3 * MMAX + i] += Yi * rtg;
-          acc[4 * MMAX + i] += Si * pt;
-          acc[5 * MMAX + i] += Yi * pt;
+          acc[KO + i] += Yi * yv;
+          acc[2 * KO + i] += Si * rtg;
+          acc[3 * KO + i] += Yi * rtg;
+          acc[4 * KO + i] += Si * pt;
+          acc[5 * KO + i] += Yi * pt;
         }
       }
       acc[B + 0] += (double)sv * yv;
@@ -208,29 +232,20 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
       Ynew[g] = pyv;
     }
   }
-  block_reduce_many<NDOT>(acc, sh, tid, NT, tot);
-  if (tid < NDOT) S.partU[wl * NDOT + tid] = tot[tid];
+  block_reduce_many<NA>(acc, sh, tid, NT, tot);
+  if (tid < NDOT) {
+    double v;
+    if (tid < 6 * MMAX) {
+      const int blk = tid / MMAX, i = tid - blk * MMAX;
+      v = (i < KO) ? tot[blk * KO + i] : 0.0;
+    } else {
+      v = tot[6 * KO + tid - 6 * MMAX];
+    }
+    S.partU[wl * NDOT + tid] = v;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsolve) {
-  __shared__ double sh[64 * 4];
-  __shared__ double t[NDOT];
-  const int s = blockIdx.x;
-  if (s >= nsolve) return;
-  SolveDev &S = dev[s];
-  OptState *st = S.st;
-  if (st->phase != PH_UPDATE) return;
-  const int tid = threadIdx.x;
-  {
-    double v[NDOT];
-#pragma unroll
-    for (int q = 0; q < NDOT; ++q) v[q] = 0.0;
-    for (int r = tid; r < S.nwg_vec; r += 256)
-#pragma unroll
-      for (int q = 0; q < NDOT; ++q) v[q] += S.partU[r * NDOT + q];
-    block_reduce_many<NDOT>(v, sh, tid, 256, t);
-  }
-  if (tid != 0) return;
+__device__ void finalize_update_body(OptState *st, const SolveDev &S, double *t) {
   const double dV = S.dV;
   const int B = 6 * MMAX;
   const int m = st->m;
@@ -341,11 +356,37 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
   st->phase = PH_NEED_DIR;
 }
 
+__global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsolve) {
+  __shared__ double sh[64 * 4];
+  __shared__ double t[NDOT];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_UPDATE) return;
+  const int tid = threadIdx.x;
+  {
+    double v[NDOT];
+#pragma unroll
+    for (int q = 0; q < NDOT; ++q) v[q] = 0.0;
+    for (int r = tid; r < S.nwg_vec; r += 256)
+#pragma unroll
+      for (int q = 0; q < NDOT; ++q) v[q] += S.partU[r * NDOT + q];
+    block_reduce_many<NDOT>(v, sh, tid, 256, t);
+  }
+  __shared__ OptState lst;
+  stage_state(&lst, st, threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) finalize_update_body(&lst, S, t);
+  __syncthreads();
+  stage_state(st, &lst, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Direction pass: d = cr P r + sum cS_i s_i + sum cY_i P y_i + cphi phi,
 // with |d|^2 and r.d.
 // ---------------------------------------------------------------------------
-template <typename R, int NT>
+template <typename R, int NT, int MM>
 __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int nsolve, int grid) {
   __shared__ double sh[2 * (NT / 64)];
   __shared__ double tot[2];
@@ -366,10 +407,10 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   const SKX_G R *Yv = gptr<R>(S.Y);
   SKX_G R *d = gptr<R>(S.d);
   const int m = st->m, k = st->k, head = st->head;
-  int slot[MMAX];
-  R cS[MMAX], cY[MMAX];
+  int slot[MM];
+  R cS[MM], cY[MM];
 #pragma unroll
-  for (int i = 0; i < MMAX; ++i) {
+  for (int i = 0; i < MM; ++i) {
     slot[i] = (i < k) ? ((head - k + i + 2 * m) % m) : 0;
     cS[i] = (R)st->cS[i];
     cY[i] = (R)st->cY[i];
@@ -379,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   for (long long g = g0 + tid; g < g1; g += NT) {
     R v = cr * pr[g] + cphi * phi[g];
 #pragma unroll
-    for (int i = 0; i < MMAX; ++i) {
+    for (int i = 0; i < MM; ++i) {
       if (i < k) v += cS[i] * Sv[(size_t)slot[i] * S.M + g] + cY[i] * Yv[(size_t)slot[i] * S.M + g];
     }
     d[g] = v;
@@ -391,16 +432,7 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
 }
 
-__global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve) {
-  __shared__ double sh[2 * 4];
-  __shared__ double t[2];
-  const int s = blockIdx.x;
-  if (s >= nsolve) return;
-  SolveDev &S = dev[s];
-  OptState *st = S.st;
-  if (st->phase != PH_NEED_DIR) return;
-  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
-  if (threadIdx.x != 0) return;
+__device__ void finalize_dir_body(OptState *st, const SolveDev &S, const double *t) {
   const double dd = S.dV * t[0], rd = S.dV * t[1];
   const double dn = sqrt(fmax(dd, 0.0));
   if (!(rd < 0.0) || !(dn > 0.0)) {
@@ -419,6 +451,23 @@ __global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve)
   st->g0 = rd / dn * S.sqrt_ne;
   st->trials = 0;
   st->phase = PH_TRIAL;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve) {
+  __shared__ double sh[2 * 4];
+  __shared__ double t[2];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_NEED_DIR) return;
+  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
+  __shared__ OptState lst;
+  stage_state(&lst, st, threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) finalize_dir_body(&lst, S, t);
+  __syncthreads();
+  stage_state(st, &lst, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,16 +504,7 @@ __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, in
   if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
 }
 
-__global__ __launch_bounds__(256) void k_finalize_norm(SolveDev *dev, int nsolve) {
-  __shared__ double sh[2 * 4];
-  __shared__ double t[2];
-  const int s = blockIdx.x;
-  if (s >= nsolve) return;
-  SolveDev &S = dev[s];
-  OptState *st = S.st;
-  if (st->phase != PH_EVAL_INIT) return;
-  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
-  if (threadIdx.x != 0) return;
+__device__ void finalize_norm_body(OptState *st, const SolveDev &S, const double *t) {
   const double nrm = S.dV * t[0];
   if (t[1] != 0.0 || !(nrm > 0.0) || !(nrm < 1e300)) {
     st->phase = PH_FAILED;
@@ -475,19 +515,52 @@ __global__ __launch_bounds__(256) void k_finalize_norm(SolveDev *dev, int nsolve
   st->reset_pending = 1;             // the first update only forms the residual
 }
 
+__global__ __launch_bounds__(256) void k_finalize_norm(SolveDev *dev, int nsolve) {
+  __shared__ double sh[2 * 4];
+  __shared__ double t[2];
+  const int s = blockIdx.x;
+  if (s >= nsolve) return;
+  SolveDev &S = dev[s];
+  OptState *st = S.st;
+  if (st->phase != PH_EVAL_INIT) return;
+  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
+  __shared__ OptState lst;
+  stage_state(&lst, st, threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) finalize_norm_body(&lst, S, t);
+  __syncthreads();
+  stage_state(st, &lst, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 template <typename R>
 static hipError_t launch_update_t(const BatchLaunch &b, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<R, 256>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV,
-                     b.nsolve, b.gridV);
+  switch (b.mh) {
+#define SKX_UPD(MM)                                                                         \
+  case MM:                                                                                  \
+    hipLaunchKernelGGL((k_update<R, 256, MM>), dim3(b.gridV), dim3(256), 0, s, b.dev,         \
+                       b.firstV, b.nsolve, b.gridV);                                        \
+    break;
+    SKX_UPD(1) SKX_UPD(2) SKX_UPD(3) SKX_UPD(4) SKX_UPD(5) SKX_UPD(6) SKX_UPD(7)
+    default: SKX_UPD(8)
+#undef SKX_UPD
+  }
   hipLaunchKernelGGL(k_finalize_update, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
   return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t launch_dir_t(const BatchLaunch &b, hipStream_t s) {
-  hipLaunchKernelGGL((k_dir<R, 256>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV, b.nsolve,
-                     b.gridV);
+  switch (b.mh) {
+#define SKX_DIR(MM)                                                                         \
+  case MM:                                                                                  \
+    hipLaunchKernelGGL((k_dir<R, 256, MM>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV,  \
+                       b.nsolve, b.gridV);                                                  \
+    break;
+    SKX_DIR(1) SKX_DIR(2) SKX_DIR(3) SKX_DIR(4) SKX_DIR(5) SKX_DIR(6) SKX_DIR(7)
+    default: SKX_DIR(8)
+#undef SKX_DIR
+  }
   hipLaunchKernelGGL(k_finalize_dir, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
   return hipGetLastError();
 }
