@@ -57,7 +57,8 @@ extern "C" {
 
 enum {
   SKX_OK = 0,
-  SKX_NOT_CONVERGED = 1,   /* optimisation stopped at max_iter or in the line search */
+  SKX_NOT_CONVERGED = 1,   /* optimisation stopped at max_iter, in the line search, or after
+                              150 iterations without a 10% gain in ||r|| (best state kept) */
   SKX_E_INVALID = -1,      /* bad size, lattice, parameter or pointer */
   SKX_E_STATE = -2,        /* call out of order */
   SKX_E_NOMEM = -3,        /* device allocation failed */

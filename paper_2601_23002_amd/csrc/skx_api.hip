@@ -399,10 +399,6 @@ int prepare(skx_ctx *c, int prec, int m) {
   return SKX_OK;
 }
 
-int upload_single(skx_ctx *c, Instance &I) {
-  std::vector<SolveDev> hs(1, I.h);
-  return build_batch(c, hs, I.prec, I.dptr, I.first, I.bl, c->stream);
-}
 
 __global__ void k_sqrt_field(const double *in, double *out, long long n) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -492,7 +488,11 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
   st.theta_max = 0.5;
   // energies carry the rounding of the field precision
   st.tolE_rel = prec == 0 ? 1e-12 : 2e-6;
-  st.stall_limit = prec == 0 ? 0 : 12;
+  // a solve stops (SKX_NOT_CONVERGED in FP64, the switch in the FP32 phase)
+  // when its best ||r|| has not improved by 10% for this many iterations:
+  // FP32 rounding floors ||r|| near 1e-5; in FP64 a density straddling the
+  // PZ81 branch point rs = 1 floors it near 1e-4 (the potential jumps there)
+  st.stall_limit = prec == 0 ? 150 : 12;
   st.best_r = 1e300;
   st.par = 0;
   st.reset_pending = from_rho ? 2 : 0;
@@ -568,43 +568,47 @@ hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
 // Drive a batch until every solve is DONE or FAILED. States are polled
 // every `chunk` steps; the step sequence itself makes every decision, so a
 // chunk is the same work every time and is captured once into a HIP graph
-// (eager launches when graphs are off or capture is refused).
-int drive(skx_ctx *c, const BatchLaunch &bl, const std::vector<OptState *> &states,
+// (eager launches when graphs are off, while per-pass events are on, or when
+// capture is refused). When half of the solves have finished, the batch is
+// rebuilt from the unfinished ones (into the same descriptor buffers) so that
+// the launches stop covering finished solves; a solve's arithmetic does not
+// depend on the batch it is in.
+int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *dfirst,
           int max_steps, hipStream_t s) {
-  (void)states;
+  BatchLaunch bl{};
+  int rc = build_batch(c, hs, prec, ddev, dfirst, bl, s);
+  if (rc) return rc;
   hipError_t e = launch_normalize(bl, s);
   if (e != hipSuccess) return hip_fail(c, e, "normalisation kernels");
   const int chunk = 8;
-  const int n = bl.nsolve;
+  int n = bl.nsolve;
   int *dph = nullptr;
   e = hipMallocAsync((void **)&dph, sizeof(int) * n, s);
   if (e != hipSuccess) return hip_fail(c, e, "phase buffer");
   std::vector<int> ph(n);
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  // per-launch HIP-event timing needs the eager launches
-  if (g_graphs && !g_prof.on) {
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      hipError_t ec = hipSuccess;
-      for (int k = 0; k < chunk && ec == hipSuccess; ++k) ec = step_sequence(bl, s);
-      if (ec == hipSuccess) ec = gather_phases(bl.dev, n, dph, s);
-      e = hipStreamEndCapture(s, &graph);
-      if (ec == hipSuccess && e == hipSuccess)
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (ec != hipSuccess || e != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
-        graph = nullptr;
-        exec = nullptr;
-        (void)hipGetLastError();
-        e = hipSuccess;
-      }
-    } else {
+  auto drop_graph = [&]() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  auto capture = [&]() {
+    // per-launch HIP-event timing needs the eager launches
+    if (!g_graphs || g_prof.on) return;
+    hipError_t ec = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (ec != hipSuccess) { (void)hipGetLastError(); return; }
+    for (int k = 0; k < chunk && ec == hipSuccess; ++k) ec = step_sequence(bl, s);
+    if (ec == hipSuccess) ec = gather_phases(bl.dev, n, dph, s);
+    hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (ec == hipSuccess && ee == hipSuccess) ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ec != hipSuccess || ee != hipSuccess) {
+      drop_graph();
       (void)hipGetLastError();
-      e = hipSuccess;
     }
-  }
-  int rc = SKX_OK;
+  };
+  capture();
   int steps = 0;
   while (steps < max_steps) {
     if (exec) {
@@ -620,13 +624,25 @@ int drive(skx_ctx *c, const BatchLaunch &bl, const std::vector<OptState *> &stat
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { rc = hip_fail(c, e, "step execution"); break; }
     prof_fold();
-    bool all = true;
-    for (int p : ph)
-      if (p != PH_DONE && p != PH_FAILED) { all = false; break; }
-    if (all) break;
+    int active = 0;
+    for (int i = 0; i < n; ++i)
+      if (ph[i] != PH_DONE && ph[i] != PH_FAILED) ++active;
+    if (active == 0) break;
+    if (n > 1 && 2 * active <= n) {
+      std::vector<SolveDev> keep;
+      for (int i = 0; i < n; ++i)
+        if (ph[i] != PH_DONE && ph[i] != PH_FAILED) keep.push_back(hs[i]);
+      hs.swap(keep);
+      drop_graph();
+      rc = build_batch(c, hs, prec, ddev, dfirst, bl, s);
+      if (rc) break;
+      e = hipStreamSynchronize(s);          // hs is read from pageable memory
+      if (e != hipSuccess) { rc = hip_fail(c, e, "batch rebuild"); break; }
+      n = bl.nsolve;
+      capture();
+    }
   }
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
+  drop_graph();
   hipFreeAsync(dph, s);
   return rc;
 }
@@ -656,11 +672,8 @@ int run_optimize(skx_ctx *c, Instance &I, void *rho_dev, const skx_opt_params &p
   init_state(st, p, gtol, start_mode == 1 ? 1 : 0, I.prec);
   hipError_t e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "state upload");
-  int rc = upload_single(c, I);
-  if (rc) return rc;
   const int max_steps = (p.max_iter + 2) * 24 + 64;
-  std::vector<OptState *> states(1, I.st);
-  rc = drive(c, I.bl, states, max_steps, s);
+  int rc = drive(c, std::vector<SolveDev>(1, I.h), I.prec, I.dptr, I.first, max_steps, s);
   if (rc) return rc;
   e = hipMemcpyAsync(&out, I.st, sizeof(OptState), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1133,10 +1146,7 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
       states.push_back(I.st);
     }
     if (rc) break;
-    BatchLaunch bl{};
-    rc = build_batch(c0, hs, pr, ddev, dfirst, bl, s);
-    if (rc) break;
-    rc = drive(c0, bl, states, (p->max_iter + 2) * 24 + 64, s);
+    rc = drive(c0, hs, pr, ddev, dfirst, (p->max_iter + 2) * 24 + 64, s);
     if (rc) break;
     for (int i = 0; i < nctx; ++i) {
       OptState *dst = last ? &outs[i] : &o32[i];

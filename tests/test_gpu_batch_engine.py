@@ -158,3 +158,57 @@ def test_graph_replay_equals_eager():
             for a, b in zip(dens, out["eager"][1]):
                 assert np.array_equal(a, b)
     skx.set_graphs(True)
+
+
+def test_mixed_precision_96cubed_beryllium_like():
+    """128 Z=4 ions (rc 0.5 bohr), rs 1.5, T 4 Ha on 96^3: FP32 iterations then
+    FP64 refinement. Against the plain FP64 GPU solve: 1e-6 Ha/atom and 1e-5
+    relative density. Against the oracle, evaluated once at the mixed
+    solution (a full oracle solve at this size takes hours): the energy to
+    1e-10 relative, and the oracle's own constrained residual at that point
+    is at the convergence threshold."""
+    skx, _ = _lib()
+    from oracle.functional import Problem
+    s = W.config_mixed()
+    _say("case: mixed precision 96^3, 128 Z=4 ions")
+    gtol = 1e-8
+    n_mx, r_mx = _alone(skx, s, skx.MIXED, gtol=gtol, max_iter=2000, fp32_switch_gtol=1e-5)
+    assert r_mx["status"] == skx.OK, r_mx
+    assert r_mx["fp32_iters"] > 0
+    n_64, r_64 = _alone(skx, s, skx.FP64, gtol=gtol, max_iter=2000)
+    assert r_64["status"] == skx.OK, r_64
+    nat = len(s.zval)
+    d_e = abs(r_mx["energy"]["free_energy"] - r_64["energy"]["free_energy"]) / nat
+    d_n = np.sum(np.abs(n_mx - n_64)) / np.sum(n_64)
+    _say(f"  mixed vs fp64: {d_e:.3e} Ha/atom, density {d_n:.3e}; "
+         f"iters {r_mx['fp32_iters']}+{r_mx['iters'] - r_mx['fp32_iters']} vs {r_64['iters']}")
+    assert d_e < 1e-6 and d_n < 1e-5
+    p = Problem(s)
+    phi = np.sqrt(n_mx)
+    e, g = p.evaluate(phi)
+    rel = abs(e["free_energy"] - r_mx["energy"]["free_energy"]) / abs(e["free_energy"])
+    mu = p.dot(phi, g) / (2.0 * p.ne)
+    res = g - 2.0 * mu * phi
+    rn = np.sqrt(p.dot(res, res))
+    _say(f"  oracle at the mixed solution: energy rel {rel:.3e}, |r| {rn:.3e}")
+    assert rel < 1e-10
+    assert rn < 2.0 * gtol
+
+
+def test_thermal_ensemble_batch():
+    """Uneven thermal-like snapshots (Z=1 and Z=4, 16..256 ions, grids from
+    h = 0.25 bohr clamped to 16..48 here) solved in one batch; each equals
+    its solve alone."""
+    skx, torch = _lib()
+    systems = W.config_ensemble(count=12, nmin=16, nmax=48)
+    _say(f"case: ensemble batch, grids {[s.n[0] for s in systems]}")
+    kw = dict(gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5)
+    ctxs = [skx.Context(0).setup(s, precision=skx.MIXED) for s in systems]
+    rhos = [torch.empty(s.n, dtype=torch.float64, device="cuda") for s in systems]
+    res = skx.run_batch(ctxs, rhos, **kw)
+    for i in (0, 5, 11):
+        n_a, r_a = _alone(skx, systems[i], skx.MIXED, **kw)
+        assert res[i]["status"] == skx.OK, res[i]
+        assert res[i]["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(rhos[i].cpu().numpy(), n_a)
+    assert all(r["status"] == skx.OK for r in res)
