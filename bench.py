@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--count", type=int, default=0,
                     help="ensemble snapshots / served requests (0: the workload's default)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests per second")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default FFT radix orders instead of timing the candidates")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
@@ -268,6 +270,7 @@ def main():
         return
     from paper_2601_23002_amd import skx
     from paper_2601_23002_amd import workloads as W
+    skx.set_autotune(not args.no_autotune)
     if args.workload == "ensemble":
         return run_ensemble(args)
     if args.workload == "serve":
@@ -385,6 +388,7 @@ def main():
         "value_graphs": graph_work / wall_graph,
         "ms_per_step_graphs": wall_graph / args.steps * 1e3,
         "evals": evals,
+        "radix_order_64": {"fp32": skx.radix_order(64, skx.FP32), "fp64": skx.radix_order(64, skx.FP64)},
     }
     if fp64 is not None:
         err = []

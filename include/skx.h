@@ -198,6 +198,18 @@ int skx_profile_read(double *ms, long long *launches, int n);
  * eagerly. Returns the previous setting. */
 int skx_set_graphs(int on);
 
+/* Process-wide FFT autotuner (off by default). When on, the first set-up of
+ * an instance of a given transform length and precision times whole
+ * evaluations with each candidate radix order (radix 8 first; no radix 8;
+ * odd radices first; small radices first) and keeps the fastest for the rest
+ * of the process. Different orders round differently, so results are
+ * reproducible bit for bit only with the same choices. Returns the previous
+ * setting. */
+int skx_set_autotune(int on);
+/* Radix order in use for length n in `precision` (SKX_FP64 / SKX_FP32):
+ * writes up to max radices, returns their count or SKX_E_INVALID. */
+int skx_get_radix_order(int n, int precision, int *radices, int max);
+
 /* Time the three evaluation passes over a batch of nctx configured contexts
  * (uniform starting density, all in the precision of ctxs[0]): reps timed
  * repetitions after one warm-up; ms_out[0..2] receive the mean milliseconds

@@ -89,17 +89,38 @@ hipError_t init_device(int dev, std::string &err) {
   return hipSuccess;
 }
 
-Plan make_plan(int n, int twoff) {
+// Radix orders for a transform length: the default (radix 8 first, then 4,
+// 2, 3, 5) and the alternatives the autotuner times against it.
+std::vector<std::vector<int>> radix_candidates(int n) {
+  auto greedy = [n](std::initializer_list<int> order) {
+    std::vector<int> r;
+    int m = n;
+    for (int x : order)
+      while (m % x == 0 && (int)r.size() < MAX_STAGES) { r.push_back(x); m /= x; }
+    return r;
+  };
+  std::vector<std::vector<int>> c;
+  c.push_back(greedy({8, 4, 2, 3, 5}));
+  c.push_back(greedy({4, 2, 3, 5}));
+  c.push_back(greedy({5, 3, 8, 4, 2}));
+  std::vector<int> rev = c[0];
+  std::reverse(rev.begin(), rev.end());
+  c.push_back(rev);
+  std::vector<std::vector<int>> out;
+  for (auto &x : c)
+    if (std::find(out.begin(), out.end(), x) == out.end()) out.push_back(x);
+  return out;
+}
+
+// Radix order chosen by the autotuner per precision and length (empty: default).
+std::vector<int> g_tuned[2][513];
+bool g_autotune = false;
+
+Plan make_plan_from(int n, int twoff, const std::vector<int> &rads) {
   Plan p{};
   p.n = n;
   p.tw = twoff;
-  int m = n;
-  auto push = [&](unsigned r) { p.rad |= r << (4 * p.nst); p.nst++; m /= (int)r; };
-  while (m % 8 == 0 && p.nst < MAX_STAGES) push(8);
-  while (m % 4 == 0 && p.nst < MAX_STAGES) push(4);
-  while (m % 2 == 0 && p.nst < MAX_STAGES) push(2);
-  while (m % 3 == 0 && p.nst < MAX_STAGES) push(3);
-  while (m % 5 == 0 && p.nst < MAX_STAGES) push(5);
+  for (int r : rads) { p.rad |= (unsigned)r << (4 * p.nst); p.nst++; }
   int Ns = 1;
   for (int st = 0; st < p.nst; ++st) {
     const int r = (p.rad >> (4 * st)) & 15u;
@@ -110,6 +131,11 @@ Plan make_plan(int n, int twoff) {
     Ns *= r;
   }
   return p;
+}
+
+Plan make_plan(int n, int twoff, int prec) {
+  const std::vector<int> &t = g_tuned[prec][n];
+  return make_plan_from(n, twoff, t.empty() ? radix_candidates(n)[0] : t);
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -246,9 +272,9 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.partD = (double *)(base + o_pD);
   h.st = I.st;
   const DeviceRes &R = g_res[c->device];
-  h.p1 = make_plan(n1, R.tw_off[n1]);
-  h.p2 = make_plan(n2, R.tw_off[n2]);
-  h.p3 = make_plan(n3, R.tw_off[n3]);
+  h.p1 = make_plan(n1, R.tw_off[n1], prec);
+  h.p2 = make_plan(n2, R.tw_off[n2], prec);
+  h.p3 = make_plan(n3, R.tw_off[n3], prec);
   I.vloc_ok = false;
   return SKX_OK;
 }
@@ -381,6 +407,68 @@ int ensure_vloc(skx_ctx *c, Instance &I) {
   return SKX_OK;
 }
 
+// Time one evaluation (passes A, B, C) of instance I as a batch of one, in
+// milliseconds (mean of `reps` after a warm-up). Leaves phi uniform and the
+// state idle.
+double time_eval(skx_ctx *c, Instance &I, int reps) {
+  hipStream_t s = c->stream;
+  if (start_uniform(c, I, s) != hipSuccess) return -1.0;
+  OptState st{};
+  st.phase = PH_EVAL_ONLY;
+  BatchLaunch bl{};
+  std::vector<SolveDev> hs(1, I.h);
+  if (build_batch(c, hs, I.prec, I.dptr, I.first, bl, s)) return -1.0;
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  double best = -1.0;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+    hipEventRecord(a, s);
+    if (e == hipSuccess) e = launch_eval(bl, s, 7);
+    hipEventRecord(b, s);
+    hipEventSynchronize(b);
+    float t = 0.f;
+    hipEventElapsedTime(&t, a, b);
+    if (r > 0 && (best < 0 || t < best)) best = t;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  hipStreamSynchronize(s);
+  return e == hipSuccess ? best : -1.0;
+}
+
+// Pick, per transform length of this instance not tuned yet in this
+// precision, the fastest radix order among radix_candidates by timing whole
+// evaluations; the choice holds for the rest of the process.
+int autotune(skx_ctx *c, Instance &I) {
+  const int prec = I.prec;
+  const DeviceRes &R = g_res[c->device];
+  const int ns[3] = {I.h.n1, I.h.n2, I.h.n3};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = ns[ax];
+    if (!g_tuned[prec][n].empty()) continue;
+    const auto cands = radix_candidates(n);
+    std::vector<int> best = cands[0];
+    double tbest = -1.0;
+    for (const auto &cand : cands) {
+      g_tuned[prec][n] = cand;
+      I.h.p1 = make_plan(I.h.n1, R.tw_off[I.h.n1], prec);
+      I.h.p2 = make_plan(I.h.n2, R.tw_off[I.h.n2], prec);
+      I.h.p3 = make_plan(I.h.n3, R.tw_off[I.h.n3], prec);
+      const double t = time_eval(c, I, 3);
+      if (t < 0) return fail(c, SKX_E_DEVICE, "autotune timing failed");
+      if (tbest < 0 || t < tbest) { tbest = t; best = cand; }
+    }
+    g_tuned[prec][n] = best;
+  }
+  I.h.p1 = make_plan(I.h.n1, R.tw_off[I.h.n1], prec);
+  I.h.p2 = make_plan(I.h.n2, R.tw_off[I.h.n2], prec);
+  I.h.p3 = make_plan(I.h.n3, R.tw_off[I.h.n3], prec);
+  return SKX_OK;
+}
+
 // Prepare instance `prec` of a context for a run: buffers, tables, V_loc,
 // descriptor upload for the batch of one.
 int prepare(skx_ctx *c, int prec, int m) {
@@ -396,7 +484,8 @@ int prepare(skx_ctx *c, int prec, int m) {
   fill_physics(c, I.h);
   rc = ensure_vloc(c, I);
   if (rc) return rc;
-  return SKX_OK;
+  if (g_autotune) rc = autotune(c, I);
+  return rc;
 }
 
 
@@ -1208,6 +1297,21 @@ int skx_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = on != 0;
   return SKX_OK;
+}
+
+int skx_set_autotune(int on) {
+  const int old = g_autotune ? 1 : 0;
+  g_autotune = on != 0;
+  return old;
+}
+
+int skx_get_radix_order(int n, int precision, int *radices, int max) {
+  if (n < 2 || n > 512 || !radices || max < 1) return SKX_E_INVALID;
+  const int prec = precision == SKX_FP32 ? 1 : 0;
+  const std::vector<int> r = g_tuned[prec][n].empty() ? radix_candidates(n)[0] : g_tuned[prec][n];
+  const int k = std::min((int)r.size(), max);
+  for (int i = 0; i < k; ++i) radices[i] = r[i];
+  return (int)r.size();
 }
 
 int skx_set_graphs(int on) {

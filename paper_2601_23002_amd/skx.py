@@ -110,6 +110,8 @@ _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double
                                 C.POINTER(C.c_double)])
 _sig("skx_profile_enable", C.c_int, [C.c_int])
 _sig("skx_set_graphs", C.c_int, [C.c_int])
+_sig("skx_set_autotune", C.c_int, [C.c_int])
+_sig("skx_get_radix_order", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int])
 _sig("skx_profile_reset", C.c_int, [])
 _sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
 _sig("skx_bench_eval", C.c_int, [C.POINTER(_VP), C.c_int, C.c_int, C.POINTER(C.c_double)])
@@ -300,6 +302,20 @@ def set_graphs(on=True):
     """Replay the driver's step sequences from a captured HIP graph (default)
     or launch them eagerly; returns the previous setting."""
     return bool(_lib.skx_set_graphs(1 if on else 0))
+
+
+def set_autotune(on=True):
+    """Time candidate FFT radix orders at first set-up of each length and keep
+    the fastest (process-wide); returns the previous setting."""
+    return bool(_lib.skx_set_autotune(1 if on else 0))
+
+
+def radix_order(n, precision=FP64):
+    buf = (C.c_int * 16)()
+    k = _lib.skx_get_radix_order(n, precision, buf, 16)
+    if k < 0:
+        raise SkxError(k, "skx_get_radix_order failed")
+    return [buf[i] for i in range(k)]
 
 
 def profile_reset():

@@ -30,3 +30,19 @@ def test_library_exports_every_declared_symbol():
 def test_binding_imports_without_gpu():
     from paper_2601_23002_amd import skx
     assert skx.OK == 0 and skx.E_NUMERIC == -5
+
+
+def test_default_radix_orders_factor_the_length():
+    """Host-side plan logic (no device call): the default radix order of every
+    accepted length multiplies back to it and prefers radix 8."""
+    from paper_2601_23002_amd import skx
+    from paper_2601_23002_amd.workloads import ALLOWED_N
+    for n in ALLOWED_N:
+        r = skx.radix_order(n, skx.FP64)
+        assert all(x in (2, 3, 4, 5, 8) for x in r)
+        prod = 1
+        for x in r:
+            prod *= x
+        assert prod == n, (n, r)
+    assert skx.radix_order(64) == [8, 8]
+    assert skx.radix_order(96) == [8, 4, 3]

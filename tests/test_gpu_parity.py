@@ -204,3 +204,28 @@ def test_optimize_matches_oracle_small():
     dV = s.volume / s.M
     assert dV * np.sum(np.abs(n - ref["n"])) / s.nelec < 1e-6
     assert abs(dV * n.sum() - s.nelec) < 1e-12 * s.nelec
+
+
+def test_autotuned_plans_keep_parity():
+    """With the autotuner on, the radix order picked for 24 (timed among the
+    candidates) still gives an FP64 evaluation within 1e-10 of the oracle."""
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    old = skx.set_autotune(True)
+    try:
+        s = _system(24, seed=77, beta=1.0)
+        _say("case: autotuned plans n=24")
+        c = skx.Context(0).setup(s)
+        phi = W.random_phi(s, 5)
+        e, g = c.evaluate(torch.tensor(phi, dtype=torch.float64, device="cuda"), skx.SQRT_RHO)
+        r = skx.radix_order(24, skx.FP64)
+        prod = 1
+        for x in r:
+            prod *= x
+        assert prod == 24
+        e_ref, g_ref = Problem(s).evaluate(phi)
+        for k in TERMS + ("free_energy",):
+            assert abs(e[k] - e_ref[k]) <= 1e-10 * max(1.0, abs(e_ref[k])), k
+        assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= 1e-9 * np.max(np.abs(g_ref))
+    finally:
+        skx.set_autotune(old)
