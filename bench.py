@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--gtol", type=float, default=1e-8)
+    ap.add_argument("--switch-gtol", type=float, default=1e-5,
+                    help="||r|| at which the mixed solves leave FP32 for the FP64 refinement")
     ap.add_argument("--fp64-max-iter", type=int, default=500,
                     help="iteration cap of the plain FP64 comparison solves")
     ap.add_argument("--workload", choices=("scan", "ensemble", "serve"), default="scan",
@@ -286,7 +288,7 @@ def main():
 
     def step(ctxs, rhos, max_iter=3000):
         return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=max_iter, m=5,
-                             fp32_switch_gtol=1e-5)
+                             fp32_switch_gtol=args.switch_gtol)
 
     def work(res):
         return sum(r["evals"] * s.M for r, s in zip(res, systems))
@@ -381,7 +383,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "scan: 9 solves, 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha, "
-                               "64^3, batched, FP32 to |r|<1e-5 then FP64 to |r|<%g" % args.gtol,
+                               "64^3, batched, FP32 to |r|<%g then FP64 to |r|<%g" % (args.switch_gtol, args.gtol),
                    "global_batch": len(systems), "grid": 64, "parallelism": "batch"},
         "roofline": roof,
         "passes_ms": {k: round(v[0], 3) for k, v in prof.items()},
@@ -399,6 +401,7 @@ def main():
             rerr.append(float(np.sum(np.abs(n_m - fp64["rho"][i])) / np.sum(fp64["rho"][i])))
         out["fp64_value"] = fp64["value"]
         out["speedup_vs_fp64"] = value / fp64["value"]
+        out["time_speedup_vs_fp64"] = fp64["seconds"] / (wall_graph / args.steps)
         out["max_err_ha_per_atom"] = max(err)
         out["max_rel_density_err"] = max(rerr)
         out["iters_fp64"] = fp64["iters"]
