@@ -268,6 +268,107 @@ __device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int e
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront-owned transforms. When every transform of a call is read and
+// written by one wavefront only, a stage needs no workgroup barrier: the LDS
+// operations of a wavefront execute in order, so each lane's reads of a
+// stage precede every write of that stage (all butterflies of the stage are
+// held in registers first), and the next stage's reads follow them. The
+// compiler keeps that order through a wavefront-scope fence between the
+// halves (no instruction: a wavefront's LDS operations are already ordered).
+// ---------------------------------------------------------------------------
+#define SKX_WAVE_SYNC()                                   \
+  do {                                                    \
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                      \
+  } while (0)
+
+template <typename V, int RAD, int MB, bool INV>
+__device__ __forceinline__ void fft_stage_w(V *buf, int N, int Ns, int twstep,
+                                            unsigned long long m_nb, unsigned long long m_ns,
+                                            int t0, int ntr, int es, int ts, const V *tw,
+                                            int lane) {
+  const int nb = N / RAD;
+  const UDiv dnb{(unsigned)nb, m_nb}, dns{(unsigned)Ns, m_ns};
+  const int tot = ntr * nb;
+  V v[MB][RAD];
+  int tq[MB], jq[MB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = lane + 64 * i;
+    const int q = (int)udiv((unsigned)b, dnb);
+    tq[i] = t0 + q;
+    jq[i] = b - q * nb;
+    if (b < tot) {
+      const V *base = buf + tq[i] * ts + jq[i] * es;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[i][r] = base[r * nb * es];
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = lane + 64 * i;
+    if (b < tot) {
+      const int j = jq[i];
+      const int k = j - (int)udiv((unsigned)j, dns) * Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          const V w = tw[k * r * twstep];
+          v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+        }
+      }
+      Bfly<RAD, INV, V>::run(v[i]);
+      V *out = buf + tq[i] * ts + ((j - k) * RAD + k) * es;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) out[r * Ns * es] = v[i][r];
+    }
+  }
+  SKX_WAVE_SYNC();
+}
+
+// Can a wavefront hold ntr transforms of this plan in registers, at most
+// MAXV complex values per lane in every stage? (Workgroup-uniform.)
+template <int MAXV>
+__device__ __forceinline__ bool wave_fits(const Plan &pl, int ntr) {
+  for (int s = 0; s < pl.nst; ++s) {
+    const int rad = (pl.rad >> (4 * s)) & 15u;
+    if (ntr * (pl.n / rad) > 64 * (MAXV / rad)) return false;
+  }
+  return true;
+}
+
+// The transforms [t0, t0 + ntr) of this wavefront, every stage in place.
+template <typename V, int MAXV, bool INV>
+__device__ __forceinline__ void fft_lds_w(V *buf, const Plan &pl, int t0, int ntr, int es, int ts,
+                                          const V *tw, int lane) {
+  SKX_OPAQUE(lane);
+  const int n = pl.n, nst = pl.nst;
+  const unsigned code = pl.rad;
+  int Ns = 1;
+#pragma unroll 1
+  for (int s = 0; s < nst; ++s) {
+    const int rad = (code >> (4 * s)) & 15u;
+    const int tws = pl.twstep[s];
+    const unsigned long long mb = pl.m_nb[s], ms = pl.m_ns[s];
+    switch (rad) {
+      case 8: fft_stage_w<V, 8, MAXV / 8, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+      case 4: fft_stage_w<V, 4, MAXV / 4, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+      case 2: fft_stage_w<V, 2, MAXV / 2, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+      case 3: fft_stage_w<V, 3, MAXV / 3, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+      default: fft_stage_w<V, 5, MAXV / 5, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+    }
+    Ns *= rad;
+  }
+}
+
+// Transforms [lo, hi) of `count` owned by wavefront w of nw.
+__device__ __forceinline__ void wave_share(int count, int w, int nw, int &lo, int &hi) {
+  lo = (count * w) / nw;
+  hi = (count * (w + 1)) / nw;
+}
+
+// ---------------------------------------------------------------------------
 // Universal Fermi-Dirac table: eta and psi = f_TF / (n T) as functions of
 // y = ln(n / n_T), by quintic Hermite interpolation between nodes that store
 // eta, eta', eta'' and psi (psi' = eta - psi and psi'' = eta' - eta + psi
@@ -324,6 +425,34 @@ __device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
   }
   eps = ex + ec;
   v = (4.0 / 3.0) * ex + vc;
+}
+
+// Single-precision PZ81 for the FP32 evaluations (the exchange-correlation
+// potential then carries FP32 rounding like every other FP32 field; the
+// FP64 refinement uses pz81_ln). Hardware exp2 / reciprocal / square root.
+__device__ __forceinline__ void pz81_lnf(float x, float &eps, float &v) {
+  const float RS1 = 0.62035049089940001667f;   // (3/(4 pi))^(1/3)
+  const float LNRS1 = -0.47746482927568600731f;  // ln RS1
+  const float CX = 0.45816529328314287f;       // (3/(4 pi)) (9 pi / 4)^(1/3)
+  const float L2E3 = 0.48089834696298783f;     // log2(e) / 3
+  const float e3 = __builtin_amdgcn_exp2f(x * L2E3);
+  const float rs = RS1 * __builtin_amdgcn_rcpf(e3);
+  const float ex = -(CX / RS1) * e3;
+  float ec, vc;
+  if (rs >= 1.0f) {
+    const float G = -0.1423f, B1 = 1.0529f, B2 = 0.3334f;
+    const float sq = __builtin_amdgcn_sqrtf(rs);
+    const float iden = __builtin_amdgcn_rcpf(1.0f + B1 * sq + B2 * rs);
+    ec = G * iden;
+    vc = G * (1.0f + (7.0f / 6.0f) * B1 * sq + (4.0f / 3.0f) * B2 * rs) * iden * iden;
+  } else {
+    const float A = 0.0311f, B = -0.048f, C = 0.0020f, D = -0.0116f;
+    const float lr = LNRS1 - x * (1.0f / 3.0f);
+    ec = A * lr + B + C * rs * lr + D * rs;
+    vc = A * lr + (B - A / 3.0f) + (2.0f / 3.0f) * C * rs * lr + (2.0f * D - C) * rs / 3.0f;
+  }
+  eps = ex + ec;
+  v = (4.0f / 3.0f) * ex + vc;
 }
 
 // ---------------------------------------------------------------------------

@@ -46,9 +46,16 @@ constexpr int LU_L = 8;
 constexpr int LU_B = 4;
 constexpr int MODE_EVAL = 0, MODE_PREC = 1;
 
+// x^a for x >= 0 through exp(a ln x): in FP64 the error stays ~1e-15
+// relative; in FP32 the hardware log2/exp2 keep it ~1e-6, the rounding level
+// of the FP32 fields (a correctly rounded powf costs ~160 instructions).
 template <typename R> __device__ __forceinline__ R rpow(R x, R a);
-template <> __device__ __forceinline__ double rpow(double x, double a) { return pow(x, a); }
-template <> __device__ __forceinline__ float rpow(float x, float a) { return powf(x, a); }
+template <> __device__ __forceinline__ double rpow(double x, double a) {
+  return x > 0.0 ? exp(a * log(x)) : 0.0;
+}
+template <> __device__ __forceinline__ float rpow(float x, float a) {
+  return x > 1e-30f ? __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(x)) : 0.0f;
+}
 
 __device__ __forceinline__ int nth_field(int mask, int c) {
   // bit index of the c-th set bit of mask (slot order phi, n, f, h)
@@ -90,67 +97,180 @@ template <int MODE> __device__ __forceinline__ bool active_phase(int ph) {
   return ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY;
 }
 
+// Complex values per lane the wavefront-owned transforms may stage.
+template <typename R> struct WaveV { static constexpr int value = sizeof(R) == 4 ? 16 : 8; };
+
+// Real-to-complex split of the row pairs [lo, hi) after their z transform,
+// by the wavefront that owns them (X_k of the pair 2p + i 2p+1 becomes the
+// half spectra A_k of row 2p and B_k of row 2p+1, in place).
+template <typename V, typename R, int U>
+__device__ __forceinline__ void split_rows_w(V *buf, int lo, int hi, int n3, int nk, int pl,
+                                             int lane) {
+  const int tot = (hi - lo) * nk;
+  const UDiv dnk = make_udiv((unsigned)nk);
+  V A[U], B[U];
+  int ia[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = lane + 64 * u;
+    ia[u] = -1;
+    if (e < tot) {
+      const int q = (int)udiv((unsigned)e, dnk);
+      const int p = lo + q, k = e - q * nk;
+      const V X = buf[p * 2 * pl + k];
+      const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
+      A[u].x = (R)0.5 * (X.x + Xm.x); A[u].y = (R)0.5 * (X.y - Xm.y);
+      B[u].x = (R)0.5 * (X.y + Xm.y); B[u].y = (R)-0.5 * (X.x - Xm.x);
+      ia[u] = 2 * p * pl + k;
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (ia[u] >= 0) { buf[ia[u]] = A[u]; buf[ia[u] + pl] = B[u]; }
+  SKX_WAVE_SYNC();
+}
+
+// Complex-to-real merge of the row pairs [lo, hi) before their inverse z
+// transform (X = A + i B over the full row, Hermitian-extended; the columns
+// k = 0 and k = n3/2 keep only their real parts), by the owning wavefront.
+template <typename V, typename R, int U>
+__device__ __forceinline__ void merge_rows_w(V *buf, int lo, int hi, int n3, int pl, int lane) {
+  const int tot = (hi - lo) * n3;
+  const UDiv dn3 = make_udiv((unsigned)n3);
+  V X[U];
+  int ix[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = lane + 64 * u;
+    ix[u] = -1;
+    if (e < tot) {
+      const int q = (int)udiv((unsigned)e, dn3);
+      const int p = lo + q, k = e - q * n3;
+      V Av, Bv;
+      if (2 * k <= n3) {
+        Av = buf[(2 * p) * pl + k];
+        Bv = buf[(2 * p + 1) * pl + k];
+        if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
+      } else {
+        Av = buf[(2 * p) * pl + n3 - k];
+        Bv = buf[(2 * p + 1) * pl + n3 - k];
+        Av.y = -Av.y; Bv.y = -Bv.y;
+      }
+      X[u].x = Av.x - Bv.y;
+      X[u].y = Av.y + Bv.x;
+      ix[u] = p * 2 * pl + k;
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (ix[u] >= 0) buf[ix[u]] = X[u];
+  SKX_WAVE_SYNC();
+}
+
 // Real-to-complex z transform of the rows held pairwise in LDS (pair p at
 // buf[2p pl ...] as x_{2p} + i x_{2p+1}), then the y transform of every
-// z column. On exit row j of the plane holds the half spectrum in [0, nh).
+// z column. On exit (after a workgroup barrier) row j of the plane holds
+// the half spectrum in [0, nh). Each step runs on wavefront-owned
+// transforms when they fit in registers, else on the workgroup-wide stages.
 template <typename V, typename R, int NT>
 __device__ __forceinline__ void plane_forward(V *buf, const SolveDev &S, const V *tw2,
                                               const V *tw3, int tid) {
+  constexpr int NW = NT / 64, MAXV = WaveV<R>::value;
+  const int lane = tid & 63, wave = tid >> 6;
   const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh;
-  fft_lds<V, MAXB_A, false>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
-  const int nk = n3 / 2 + 1;
-  int per = (MAXB_A * NT) / nk;
-  if (per < 1) per = 1;
-  const UDiv dnk = make_udiv((unsigned)nk);
-  for (int p0 = 0; p0 < n2 / 2; p0 += per) {
-    const int p1 = min(n2 / 2, p0 + per);
-    const int tot = (p1 - p0) * nk;
-    V A[MAXB_A], B[MAXB_A];
-#pragma unroll
-    for (int i = 0; i < MAXB_A; ++i) {
-      const int e = tid + i * NT;
-      if (e < tot) {
-        const int q = (int)udiv((unsigned)e, dnk);
-        const int p = p0 + q, k = e - q * nk;
-        const V X = buf[p * 2 * pl + k];
-        const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
-        A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
-        B[i].x = (R)0.5 * (X.y + Xm.y); B[i].y = (R)-0.5 * (X.x - Xm.x);
-      }
-    }
+  const int nk = n3 / 2 + 1, cz = n2 / 2;
+  const int zmax = (cz + NW - 1) / NW;
+  if (wave_fits<MAXV>(S.p3, zmax) && zmax * nk <= 64 * (MAXV / 2)) {
+    int lo, hi;
+    wave_share(cz, wave, NW, lo, hi);
+    fft_lds_w<V, MAXV, false>(buf, S.p3, lo, hi - lo, 1, 2 * pl, tw3, lane);
+    split_rows_w<V, R, MAXV / 2>(buf, lo, hi, n3, nk, pl, lane);
     __syncthreads();
+  } else {
+    fft_lds<V, MAXB_A, false>(buf, S.p3, cz, 1, 2 * pl, tw3, tid, NT);
+    int per = (MAXB_A * NT) / nk;
+    if (per < 1) per = 1;
+    const UDiv dnk = make_udiv((unsigned)nk);
+    for (int p0 = 0; p0 < cz; p0 += per) {
+      const int p1 = min(cz, p0 + per);
+      const int tot = (p1 - p0) * nk;
+      V A[MAXB_A], B[MAXB_A];
 #pragma unroll
-    for (int i = 0; i < MAXB_A; ++i) {
-      const int e = tid + i * NT;
-      if (e < tot) {
-        const int q = (int)udiv((unsigned)e, dnk);
-        const int p = p0 + q, k = e - q * nk;
-        buf[(2 * p) * pl + k] = A[i];
-        buf[(2 * p + 1) * pl + k] = B[i];
+      for (int i = 0; i < MAXB_A; ++i) {
+        const int e = tid + i * NT;
+        if (e < tot) {
+          const int q = (int)udiv((unsigned)e, dnk);
+          const int p = p0 + q, k = e - q * nk;
+          const V X = buf[p * 2 * pl + k];
+          const V Xm = buf[p * 2 * pl + (k == 0 ? 0 : n3 - k)];
+          A[i].x = (R)0.5 * (X.x + Xm.x); A[i].y = (R)0.5 * (X.y - Xm.y);
+          B[i].x = (R)0.5 * (X.y + Xm.y); B[i].y = (R)-0.5 * (X.x - Xm.x);
+        }
       }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < MAXB_A; ++i) {
+        const int e = tid + i * NT;
+        if (e < tot) {
+          const int q = (int)udiv((unsigned)e, dnk);
+          const int p = p0 + q, k = e - q * nk;
+          buf[(2 * p) * pl + k] = A[i];
+          buf[(2 * p + 1) * pl + k] = B[i];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  fft_lds<V, MAXB_A, false>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  const int ymax = (nh + NW - 1) / NW;
+  if (wave_fits<MAXV>(S.p2, ymax)) {
+    int lo, hi;
+    wave_share(nh, wave, NW, lo, hi);
+    fft_lds_w<V, MAXV, false>(buf, S.p2, lo, hi - lo, pl, 1, tw2, lane);
+    __syncthreads();
+  } else {
+    fft_lds<V, MAXB_A, false>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  }
 }
 
 // Inverse of plane_forward for one field loaded as a half spectrum in LDS:
 // inverse y transform, then complex-to-real along z, two rows at a time
 // (X = A + i B over the full row, A and B Hermitian-extended; the columns
 // k = 0 and k = n3/2 keep only their real parts, i.e. the real part of the
-// plane-wave sum). On exit row j's real values sit in component j&1 of
-// buf[(j>>1) 2 pl + k].
+// plane-wave sum). On exit (after a workgroup barrier) row j's real values
+// sit in component j&1 of buf[(j>>1) 2 pl + k].
 template <typename V, typename R, int NT>
 __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V *tw2,
                                               const V *tw3, int tid) {
   SKX_OPAQUE(tid);
+  constexpr int NW = NT / 64, MAXV = WaveV<R>::value;
+  const int lane = tid & 63, wave = tid >> 6;
   const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh;
-  fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  const int cz = n2 / 2;
+  const int ymax = (nh + NW - 1) / NW;
+  if (wave_fits<MAXV>(S.p2, ymax)) {
+    int lo, hi;
+    wave_share(nh, wave, NW, lo, hi);
+    fft_lds_w<V, MAXV, true>(buf, S.p2, lo, hi - lo, pl, 1, tw2, lane);
+    __syncthreads();
+  } else {
+    fft_lds<V, MAXB_C, true>(buf, S.p2, nh, pl, 1, tw2, tid, NT);
+  }
+  const int zmax = (cz + NW - 1) / NW;
+  if (wave_fits<MAXV>(S.p3, zmax) && zmax * n3 <= 64 * MAXV) {
+    int lo, hi;
+    wave_share(cz, wave, NW, lo, hi);
+    merge_rows_w<V, R, MAXV>(buf, lo, hi, n3, pl, lane);
+    fft_lds_w<V, MAXV, true>(buf, S.p3, lo, hi - lo, 1, 2 * pl, tw3, lane);
+    __syncthreads();
+    return;
+  }
   int per = (MAXB_C * 2 * NT) / n3;
   if (per < 1) per = 1;
   const UDiv dn3 = make_udiv((unsigned)n3);
-  for (int p0 = 0; p0 < n2 / 2; p0 += per) {
-    const int p1 = min(n2 / 2, p0 + per);
+  for (int p0 = 0; p0 < cz; p0 += per) {
+    const int p1 = min(cz, p0 + per);
     const int tot = (p1 - p0) * n3;
     V X[MAXB_C * 2];
 #pragma unroll
@@ -185,7 +305,7 @@ __device__ __forceinline__ void plane_inverse(V *buf, const SolveDev &S, const V
     }
     __syncthreads();
   }
-  fft_lds<V, MAXB_C, true>(buf, S.p3, n2 / 2, 1, 2 * pl, tw3, tid, NT);
+  fft_lds<V, MAXB_C, true>(buf, S.p3, cz, 1, 2 * pl, tw3, tid, NT);
 }
 
 // Copy one x-plane of a half spectrum ([n2][pitch] complex in HBM) into the
@@ -331,7 +451,14 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
           }
           if (do_xc) {
             double eps, vx;
-            pz81_ln(lx, eps, vx);
+            if (sizeof(R) == 4) {
+              float ef, vf;
+              pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), ef, vf);
+              eps = ef;
+              vx = vf;
+            } else {
+              pz81_ln(lx, eps, vx);
+            }
             e_xc += nd * eps;
             v += vx;
           }
@@ -439,7 +566,20 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       if (li[u] >= 0) tile[li[u]] = t[u];
   }
   __syncthreads();
-  if (S.debug != 2) fft_lds<V, MAXB_B, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+  // x transforms of the tile columns, wavefront-owned when they fit
+  constexpr int NW = NT / 64, MAXV = WaveV<R>::value;
+  const int lane = tid & 63, wave = tid >> 6;
+  const bool xw = wave_fits<MAXV>(S.p1, (W + NW - 1) / NW);
+  int xlo, xhi;
+  wave_share(W, wave, NW, xlo, xhi);
+  if (S.debug != 2) {
+    if (xw) {
+      fft_lds_w<V, MAXV, false>(tile, S.p1, xlo, xhi - xlo, Wp, 1, tw1, lane);
+      __syncthreads();
+    } else {
+      fft_lds<V, MAXB_B, false>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+    }
+  }
   if (S.debug == 1) {
     for (int e = tid; e < n1 * W; e += NT) {
       const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
@@ -550,7 +690,12 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     }
   }
   __syncthreads();
-  fft_lds<V, MAXB_B, true>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+  if (xw) {
+    fft_lds_w<V, MAXV, true>(tile, S.p1, xlo, xhi - xlo, Wp, 1, tw1, lane);
+    __syncthreads();
+  } else {
+    fft_lds<V, MAXB_B, true>(tile, S.p1, W, Wp, 1, tw1, tid, NT);
+  }
   for (int e = tid; e < n1 * W; e += NT) {
     const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
     const int cc = r / TK, kk = r - cc * TK;
