@@ -881,12 +881,24 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4)) {
-    if (b.accC_lds)
+    // In FP32 two 512-thread groups share a CU; when the last round of
+    // those would be less than half full (e.g. 576 planes), 256-thread
+    // groups spread the planes more evenly over the CUs.
+    const int fill = b.gridC % (2 * 256);
+    if (sizeof(R) == 4 && fill > 0 && fill <= 256) {
+      if (b.accC_lds)
+        hipLaunchKernelGGL((k_passC<R, 256, true, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
+                           s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+      else
+        hipLaunchKernelGGL((k_passC<R, 256, false, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
+                           s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+    } else if (b.accC_lds) {
       hipLaunchKernelGGL((k_passC<R, NTC, true, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC, s,
                          b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-    else
+    } else {
       hipLaunchKernelGGL((k_passC<R, NTC, false, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC,
                          s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+    }
   }
   return hipGetLastError();
 }
