@@ -537,7 +537,11 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   const int local = item - first_of(first, s);
   const int j = local / S.nkb, kb = local % S.nkb;
   const int k0 = kb * TK;
-  const int n1 = S.n1, nf = MODE == MODE_EVAL ? S.nf : 1, W = nf * TK;
+  // columns of this block: TK, or fewer in the last block (the Nyquist
+  // column alone when n3/2 is a multiple of TK)
+  const int tkv = min(TK, S.nh - k0);
+  const UDiv dtk = make_udiv((unsigned)tkv);
+  const int n1 = S.n1, nf = MODE == MODE_EVAL ? S.nf : 1, W = nf * tkv;
   // one padding element per tile row keeps the x transform (stride Wp)
   // off a single LDS bank
   const int Wp = W + 1;
@@ -556,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
       li[u] = -1;
       if (e < n1 * W) {
         const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
-        const int cc = r / TK, kk = r - cc * TK;
+        const int cc = (int)udiv((unsigned)r, dtk), kk = r - cc * tkv;
         li[u] = i * Wp + r;
         t[u] = ldg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk);
       }
@@ -583,10 +587,9 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   if (S.debug == 1) {
     for (int e = tid; e < n1 * W; e += NT) {
       const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
-      const int cc = r / TK, kk = r - cc * TK;
-      if (k0 + kk < S.nh)
-        stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
-            tile[i * Wp + r]);
+      const int cc = (int)udiv((unsigned)r, dtk), kk = r - cc * tkv;
+      stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
+          tile[i * Wp + r]);
     }
     return;
   }
@@ -594,10 +597,9 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   const int g2 = gidx(j, S.n2);
   double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
   if (MODE == MODE_PREC) {
-    for (int e = tid; e < n1 * TK; e += NT) {
-      const int i = e / TK, kk = e - i * TK;
+    for (int e = tid; e < n1 * tkv; e += NT) {
+      const int i = (int)udiv((unsigned)e, dtk), kk = e - i * tkv;
       const int k3 = k0 + kk;
-      if (k3 >= S.nh) continue;
       const int g1 = gidx(i, n1);
       const double G2 = kscale * (double)(g1 * g1 + g2 * g2 + k3 * k3);
       const R pg = (R)(1.0 / (G2 + S.kappa));
@@ -615,16 +617,16 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
     const double FOURPI = 12.566370614359172954;
     const SKX_G double *wt = gptr<double>(S.w);
     const SKX_G double *wpt = gptr<double>(S.wp);
-    for (int e0 = tid; e0 < n1 * TK; e0 += LU_B * NT) {
+    for (int e0 = tid; e0 < n1 * tkv; e0 += LU_B * NT) {
       // gathers of this batch first: V_loc(G) and the kernel tables
       V vlb[LU_B];
       double wb[LU_B], wpb[LU_B];
 #pragma unroll
       for (int u = 0; u < LU_B; ++u) {
         const int e = e0 + u * NT;
-        const int i = e / TK, kk = e - i * TK;
+        const int i = (int)udiv((unsigned)e, dtk), kk = e - i * tkv;
         const int k3 = k0 + kk;
-        if (e < n1 * TK && k3 < S.nh) {
+        if (e < n1 * tkv) {
           const int g1 = gidx(i, n1);
           const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
           if (do_loc) vlb[u] = ldg(vloc + ((size_t)i * S.n2 + j) * S.pitch + k3);
@@ -634,23 +636,23 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
 #pragma unroll
     for (int u = 0; u < LU_B; ++u) {
       const int e = e0 + u * NT;
-      const int i = e / TK, kk = e - i * TK;
+      const int i = (int)udiv((unsigned)e, dtk), kk = e - i * tkv;
       const int k3 = k0 + kk;
-      if (e >= n1 * TK || k3 >= S.nh || S.debug) continue;
+      if (e >= n1 * tkv || S.debug) continue;
       const int g1 = gidx(i, n1);
       const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
       const double G2 = kscale * (double)sidx;
       const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
       V *row = tile + i * Wp;
       if (sphi >= 0) {
-        V x = row[sphi * TK + kk];
+        V x = row[sphi * tkv + kk];
         if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
         const R g2r = (R)G2;
         x.x *= g2r; x.y *= g2r;
-        row[sphi * TK + kk] = x;
+        row[sphi * tkv + kk] = x;
       }
       {
-        const V x = row[sn * TK + kk];
+        const V x = row[sn * tkv + kk];
         double bx = 0.0, by = 0.0;
         if (do_h && sidx > 0) {
           const double m2 = (double)x.x * x.x + (double)x.y * x.y;
@@ -666,10 +668,10 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
         }
         if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
         V o; o.x = (R)bx; o.y = (R)by;
-        row[sn * TK + kk] = o;
+        row[sn * tkv + kk] = o;
       }
       if (sf >= 0) {
-        const V f = row[sf * TK + kk];
+        const V f = row[sf * tkv + kk];
         const R w = (R)wb[u];
         const R wp = (R)wpb[u];
         V P; P.x = 0; P.y = 0;
@@ -678,13 +680,13 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
           P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
         }
         if (sh >= 0) {
-          const V h = row[sh * TK + kk];
+          const V h = row[sh * tkv + kk];
           ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
           P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
           V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
-          row[sh * TK + kk] = Q;
+          row[sh * tkv + kk] = Q;
         }
-        row[sf * TK + kk] = P;
+        row[sf * tkv + kk] = P;
       }
     }
     }
@@ -698,10 +700,9 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
   }
   for (int e = tid; e < n1 * W; e += NT) {
     const int i = (int)udiv((unsigned)e, dW), r = e - i * W;
-    const int cc = r / TK, kk = r - cc * TK;
-    if (k0 + kk < S.nh)
-      stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
-          tile[i * Wp + r]);
+    const int cc = (int)udiv((unsigned)r, dtk), kk = r - cc * tkv;
+    stg(spec + (size_t)cc * S.H + (size_t)i * rowstride + (size_t)j * S.pitch + k0 + kk,
+        tile[i * Wp + r]);
   }
   if (MODE == MODE_EVAL) {
     double v[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
