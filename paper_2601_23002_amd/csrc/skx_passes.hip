@@ -420,12 +420,14 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
     SKX_G R *v0s = gptr<R>(S.vpt) + pbase;
     SKX_G R *fps = gptr<R>(S.fpt) + pbase;
     const UDiv dn3 = make_udiv((unsigned)n3);
-    for (int e = tid; e < np; e += NT) {
+    for (int e = tid, it = 0; e < np; e += NT, ++it) {
       const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
       // the pointwise work of this plane is shared by its field workgroups:
-      // rows j = c (mod nf) get the local energy densities, the local
-      // potential T eta + v_xc and f = n^a stored for the assembly pass
-      const bool mine = (j - (int)udiv((unsigned)j, dnf) * nf) == c;
+      // the elements of sweeps it = c (mod nf) get the local energy
+      // densities, the local potential T eta + v_xc and f = n^a stored for
+      // the assembly pass. The choice is uniform over the workgroup, so every
+      // wavefront takes the FP64 branch in the same sweeps, with all lanes.
+      const bool mine = (it - (int)udiv((unsigned)it, dnf) * nf) == c;
       R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]) + (j & 1);
       const R ph = *slot;
       const R n = ph * ph;
