@@ -282,11 +282,15 @@ __device__ __forceinline__ void fft_lds(V *buf, const Plan &pl, int count, int e
     __builtin_amdgcn_wave_barrier();                      \
   } while (0)
 
+// tfast: consecutive lanes take consecutive transforms (for transforms that
+// are adjacent in memory, ts = 1: their elements then sit in consecutive
+// LDS words instead of one row pitch apart, which avoids bank conflicts);
+// otherwise consecutive butterflies of one transform.
 template <typename V, int RAD, int MB, bool INV>
 __device__ __forceinline__ void fft_stage_w(V *buf, int N, int Ns, int twstep,
                                             unsigned long long m_nb, unsigned long long m_ns,
-                                            int t0, int ntr, int es, int ts, const V *tw,
-                                            int lane) {
+                                            int t0, int ntr, const UDiv &dntr, bool tfast,
+                                            int es, int ts, const V *tw, int lane) {
   const int nb = N / RAD;
   const UDiv dnb{(unsigned)nb, m_nb}, dns{(unsigned)Ns, m_ns};
   const int tot = ntr * nb;
@@ -295,9 +299,15 @@ __device__ __forceinline__ void fft_stage_w(V *buf, int N, int Ns, int twstep,
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int b = lane + 64 * i;
-    const int q = (int)udiv((unsigned)b, dnb);
-    tq[i] = t0 + q;
-    jq[i] = b - q * nb;
+    if (tfast) {
+      const int q = (int)udiv((unsigned)b, dntr);
+      tq[i] = t0 + (b - q * ntr);
+      jq[i] = q;
+    } else {
+      const int q = (int)udiv((unsigned)b, dnb);
+      tq[i] = t0 + q;
+      jq[i] = b - q * nb;
+    }
     if (b < tot) {
       const V *base = buf + tq[i] * ts + jq[i] * es;
 #pragma unroll
@@ -345,6 +355,9 @@ __device__ __forceinline__ void fft_lds_w(V *buf, const Plan &pl, int t0, int nt
   SKX_OPAQUE(lane);
   const int n = pl.n, nst = pl.nst;
   const unsigned code = pl.rad;
+  if (ntr <= 0) return;
+  const UDiv dntr = make_udiv((unsigned)ntr);
+  const bool tf = ts == 1 && es != 1;
   int Ns = 1;
 #pragma unroll 1
   for (int s = 0; s < nst; ++s) {
@@ -352,11 +365,11 @@ __device__ __forceinline__ void fft_lds_w(V *buf, const Plan &pl, int t0, int nt
     const int tws = pl.twstep[s];
     const unsigned long long mb = pl.m_nb[s], ms = pl.m_ns[s];
     switch (rad) {
-      case 8: fft_stage_w<V, 8, MAXV / 8, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
-      case 4: fft_stage_w<V, 4, MAXV / 4, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
-      case 2: fft_stage_w<V, 2, MAXV / 2, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
-      case 3: fft_stage_w<V, 3, MAXV / 3, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
-      default: fft_stage_w<V, 5, MAXV / 5, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, es, ts, tw, lane); break;
+      case 8: fft_stage_w<V, 8, MAXV / 8, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, dntr, tf, es, ts, tw, lane); break;
+      case 4: fft_stage_w<V, 4, MAXV / 4, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, dntr, tf, es, ts, tw, lane); break;
+      case 2: fft_stage_w<V, 2, MAXV / 2, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, dntr, tf, es, ts, tw, lane); break;
+      case 3: fft_stage_w<V, 3, MAXV / 3, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, dntr, tf, es, ts, tw, lane); break;
+      default: fft_stage_w<V, 5, MAXV / 5, INV>(buf, n, Ns, tws, mb, ms, t0, ntr, dntr, tf, es, ts, tw, lane); break;
     }
     Ns *= rad;
   }
