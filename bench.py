@@ -80,9 +80,10 @@ PASS_SOURCES = ("paper_2601_23002_amd/csrc/skx_passes.hip", "paper_2601_23002_am
 TRAFFIC_FILE = "profiles/traffic_scan64_mixed.md"
 
 
-def measured_traffic():
-    """Pass A HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
-    or None when the pass sources changed since those counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of an evaluation pass from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None when the pass sources changed since
+    those counters were taken."""
     import hashlib
     h = hashlib.sha256()
     for f in PASS_SOURCES:
@@ -95,7 +96,8 @@ def measured_traffic():
         return None
     if kv.get("pass_sources_sha256_16") != h.hexdigest()[:16]:
         return None
-    return float(kv["passA_traffic_bytes_per_launch"])
+    v = kv.get(f"{kernel}_traffic_bytes_per_launch")
+    return None if v is None else float(v)
 
 
 def fields_count(sys_):
@@ -362,7 +364,7 @@ def main():
     ms, launches = prof[dom]
     avg_s = ms / 1e3 / max(1, launches)
     achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9
-    traffic = measured_traffic() if dom == "passA" else None
+    traffic = measured_traffic(dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
