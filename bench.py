@@ -67,11 +67,14 @@ def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
     Hh = n1 * n2 * (n3 // 2 + 1)          # half-spectrum complex entries
     b = prec_bytes
     spec = 2 * b * Hh                     # one half spectrum
-    # A: phi (+ d) in; phi_t, local potential, n^a and nf half spectra out
-    a = (2 if phase_trial else 1) * b * M + 3 * b * M + nf * spec
+    # per-point arrays pass A hands to pass C: phi_t, the local potential,
+    # and the coefficients c_P (with the f field) and c_Q (with the h field)
+    handed = 2 + (1 if nf >= 3 else 0) + (1 if nf >= 4 else 0)
+    # A: phi (+ d) in; the handed arrays and nf half spectra out
+    a = (2 if phase_trial else 1) * b * M + handed * b * M + nf * spec
     bb = 2 * nf * spec + (spec if with_loc else 0)
-    # C: nf half spectra, phi_t, local potential, n^a in; dE/dphi out
-    c = nf * spec + 4 * b * M
+    # C: nf half spectra and the handed arrays in; dE/dphi out
+    c = nf * spec + handed * b * M + b * M
     return a, bb, c
 
 

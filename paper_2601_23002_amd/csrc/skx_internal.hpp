@@ -74,7 +74,8 @@ struct SolveDev {
   double kappa;                    // preconditioner P(G) = 1 / (G^2 + kappa)
   void *phi2[2], *r2[2], *pr2[2];  // current / trial point pairs (see OptState::par)
   void *grad, *d, *S, *Y;          // real fields (fp64 or fp32); Y holds P y
-  void *vpt, *fpt;                 // T eta + v_xc and n^a at the trial point (pass A -> C)
+  void *vpt;                       // T eta + v_xc at the trial point (pass A -> C)
+  void *fpt, *qpt;                 // coefficients c_P, c_Q of the fields P, Q (pass A -> C)
   void *spec, *vloc;                         // complex spectra
   const double *w, *wp;                      // shell tables
   double *partA, *partB, *partC, *partU, *partD;

@@ -419,6 +419,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
     // the register count, and so the occupancy, in check)
     SKX_G R *v0s = gptr<R>(S.vpt) + pbase;
     SKX_G R *fps = gptr<R>(S.fpt) + pbase;
+    SKX_G R *qps = gptr<R>(S.qpt) + pbase;
+    const bool need_h = (S.fields & F_H) != 0;
+    const R a2 = (R)(2.0 * S.a);
     const UDiv dn3 = make_udiv((unsigned)n3);
     for (int e = tid, it = 0; e < np; e += NT, ++it) {
       const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
@@ -466,7 +469,13 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
           }
         }
         v0s[e] = (R)v;
-        if (need_f) fps[e] = f;
+        if (need_f) {
+          // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0),
+          // c_Q = c_P (n - n0) + 2 phi (f - n0^a)
+          const R cP = (ph != (R)0) ? a2 * f / ph : (R)0;
+          fps[e] = cP;
+          if (need_h) qps[e] = cP * (n - n0) + (R)2 * ph * (f - n0a);
+        }
       }
     }
   } else {
@@ -763,17 +772,20 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
     return;
   }
 
-  // phi_t, the local potential and n^a are read as pairs along z, LU_C
-  // pairs per thread in flight
+  // Per element the fields enter with the coefficients 1 (phi), 2 phi_t
+  // (n), c_P (f) and c_Q (h), stored by pass A; read as pairs along z, LU_C
+  // pairs per thread in flight. In FP32 phi_t is also kept in LDS beside
+  // dE/dphi, so that every array is read from HBM once.
+  constexpr bool PCACHE = ACC_LDS && sizeof(R) == 4;
   const size_t qbase = pbase >> 1;
   const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
   const SKX_G V *v0 = gptr<V>(S.vpt) + qbase;
-  const SKX_G V *fpw = gptr<V>(S.fpt) + qbase;
+  const SKX_G V *cpw = gptr<V>(S.fpt) + qbase;
+  const SKX_G V *cqw = gptr<V>(S.qpt) + qbase;
   SKX_G R *grad = gptr<R>(S.grad);
   R *acc = ACC_LDS ? reinterpret_cast<R *>(tw3 + n3) : (R *)(grad + pbase);
-  const R a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
-  const int npair = np >> 1, h3 = n3 >> 1;
-  const UDiv dh3 = make_udiv((unsigned)h3);
+  V *pc = reinterpret_cast<V *>(acc + np);        // phi_t pairs (PCACHE)
+  const int npair = np >> 1;
   for (int q0 = tid; q0 < npair; q0 += LU_C * NT) {
     V pv[LU_C], vv[LU_C];
 #pragma unroll
@@ -787,9 +799,12 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
       if (q < npair) {
         acc[2 * q] = S.debug ? (R)0 : (R)2 * pv[u].x * vv[u].x;
         acc[2 * q + 1] = S.debug ? (R)0 : (R)2 * pv[u].y * vv[u].y;
+        if (PCACHE) pc[q] = pv[u];
       }
     }
   }
+  const int h3 = n3 >> 1;
+  const UDiv dh3 = make_udiv((unsigned)h3);
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0 || (S.debug && fb != 0)) continue;
@@ -800,13 +815,14 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
     int tq = tid;
     SKX_OPAQUE(tq);
     for (int q0 = tq; q0 < npair; q0 += LU_C * NT) {
-      V pv[LU_C], fv[LU_C];
+      V cv2[LU_C];
 #pragma unroll
       for (int u = 0; u < LU_C; ++u) {
         const int q = q0 + u * NT;
         if (q < npair) {
-          if (fb >= 1) pv[u] = ldg(phit + q);
-          if (fb >= 2) fv[u] = ldg(fpw + q);
+          if (fb == 1) cv2[u] = PCACHE ? pc[q] : ldg(phit + q);
+          else if (fb == 2) cv2[u] = ldg(cpw + q);
+          else if (fb == 3) cv2[u] = ldg(cqw + q);
         }
       }
 #pragma unroll
@@ -818,20 +834,8 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const R val = cv[2 * h + (j & 1)];
-            R coef;
-            if (fb == 0) {
-              coef = (R)1;
-            } else {
-              const R p = h ? pv[u].y : pv[u].x;
-              if (fb == 1) {
-                coef = (R)2 * p;
-              } else {
-                // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
-                const R f = h ? fv[u].y : fv[u].x;
-                const R cP = (p != (R)0) ? a2 * f / p : (R)0;
-                coef = (fb == 2) ? cP : cP * (p * p - n0) + (R)2 * p * (f - n0a);
-              }
-            }
+            const R c = h ? cv2[u].y : cv2[u].x;
+            const R coef = fb == 0 ? (R)1 : (fb == 1 ? (R)2 * c : c);
             acc[2 * q + h] += coef * val;
           }
         }
@@ -846,7 +850,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 #pragma unroll
     for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
-      if (q < npair) pv[u] = ldg(phit + q);
+      if (q < npair) pv[u] = PCACHE ? pc[q] : ldg(phit + q);
     }
 #pragma unroll
     for (int u = 0; u < LU_C; ++u) {
