@@ -189,7 +189,7 @@ constexpr size_t LDS_MAX = 160 * 1024;
 // Allocate (or reuse) the buffers of one precision instance and fill the
 // descriptor's grid and buffer fields.
 struct ArenaLayout {
-  size_t o_phi, o_phit, o_grad, o_r, o_rt, o_pr, o_prt, o_d, o_vpt, o_fpt, o_qpt, o_S, o_Y;
+  size_t o_phi, o_phit, o_grad, o_r, o_rt, o_pr, o_prt, o_d, o_vpt, o_fpt, o_qpt, o_npa, o_S, o_Y;
   size_t o_spec, o_vloc, o_pA, o_pB, o_pC, o_pU, o_pD, total;
 };
 
@@ -208,10 +208,10 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   L.o_phi = take(rsz * M); L.o_phit = take(rsz * M); L.o_grad = take(rsz * M);
   L.o_r = take(rsz * M); L.o_rt = take(rsz * M); L.o_pr = take(rsz * M); L.o_prt = take(rsz * M);
   L.o_d = take(rsz * M); L.o_vpt = take(rsz * M); L.o_fpt = take(rsz * M);
-  L.o_qpt = take(rsz * M);
+  L.o_qpt = take(rsz * M); L.o_npa = take(rsz * M);
   L.o_S = take(rsz * M * m); L.o_Y = take(rsz * M * m);
   L.o_spec = take(2 * rsz * H * NFIELD); L.o_vloc = take(2 * rsz * H);
-  L.o_pA = take(8 * (size_t)n1 * NFIELD * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
+  L.o_pA = take(8 * (size_t)nwg * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
   L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwg * NDOT);
   L.o_pD = take(8 * (size_t)nwg * 2);
   L.total = off;
@@ -243,7 +243,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   const size_t off = A.total;
   const size_t o_phi = A.o_phi, o_phit = A.o_phit, o_grad = A.o_grad, o_r = A.o_r, o_rt = A.o_rt;
   const size_t o_pr = A.o_pr, o_prt = A.o_prt, o_d = A.o_d, o_vpt = A.o_vpt, o_fpt = A.o_fpt;
-  const size_t o_qpt = A.o_qpt;
+  const size_t o_qpt = A.o_qpt, o_npa = A.o_npa;
   const size_t o_S = A.o_S, o_Y = A.o_Y, o_spec = A.o_spec, o_vloc = A.o_vloc;
   const size_t o_pA = A.o_pA, o_pB = A.o_pB, o_pC = A.o_pC, o_pU = A.o_pU, o_pD = A.o_pD;
   hipError_t e = hipMalloc(&I.mem, off);
@@ -268,6 +268,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
   h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
   h.vpt = base + o_vpt; h.fpt = base + o_fpt; h.qpt = base + o_qpt;
+  h.npa = base + o_npa;
   h.spec = base + o_spec; h.vloc = base + o_vloc;
   h.partA = (double *)(base + o_pA); h.partB = (double *)(base + o_pB);
   h.partC = (double *)(base + o_pC); h.partU = (double *)(base + o_pU);

@@ -11,7 +11,7 @@ namespace skx {
 constexpr int MMAX = 8;            // largest L-BFGS memory supported
 constexpr int NFIELD = 4;          // transformed fields: phi, n, f, h
 constexpr int MAX_STAGES = 8;      // FFT stages per axis
-constexpr int PART_A = 4;          // pass A partial sums: f_tf, e_xc, nelec, nonfinite
+constexpr int PART_A = 4;          // pointwise-pass partial sums: f_tf, e_xc, nelec, nonfinite
 constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinite
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
 constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
@@ -76,6 +76,7 @@ struct SolveDev {
   void *grad, *d, *S, *Y;          // real fields (fp64 or fp32); Y holds P y
   void *vpt;                       // T eta + v_xc at the trial point (pass A -> C)
   void *fpt, *qpt;                 // coefficients c_P, c_Q of the fields P, Q (pass A -> C)
+  void *npa;                       // n^a at the trial point (pointwise kernel -> pass A)
   void *spec, *vloc;                         // complex spectra
   const double *w, *wp;                      // shell tables
   double *partA, *partB, *partC, *partU, *partD;

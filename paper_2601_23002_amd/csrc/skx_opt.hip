@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
   const int ph = st->phase;
   if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
   const int tid = threadIdx.x;
-  sum_parts<PART_A>(S.partA, S.n1 * S.nf, sh, tid, 256, tA);
+  sum_parts<PART_A>(S.partA, S.nwg_vec, sh, tid, 256, tA);
   sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
   sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
   __shared__ OptState lst;

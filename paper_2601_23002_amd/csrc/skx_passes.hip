@@ -336,6 +336,109 @@ __device__ __forceinline__ void load_plane(V *buf, const SKX_G V *src, int n2, i
 }
 
 // ---------------------------------------------------------------------------
+// Pointwise pass (first kernel of pass A), one workgroup per CHUNK points of
+// a solve: the trial point phi_t = ca phi + cb d, n = phi_t^2, f = n^a, the
+// local energy densities (finite-T TF through the Fermi-Dirac table, PZ LDA),
+// the local potential v0 = T eta + v_xc and the assembly coefficients
+// c_P = 2 a f / phi_t, c_Q = c_P (n - n0) + 2 phi_t (f - n0^a). Every point
+// is computed once; the transform kernel and pass C read the results.
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, int nsolve,
+                                              int grid, FDTable fd) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE_EVAL>(st->phase)) return;
+  const int par = st->par;
+  const int tid = threadIdx.x;
+  const int wl = item - first_of(first, s);
+  const long long g0 = (long long)wl * CHUNK;
+  const int cnt = (int)min((long long)CHUNK, S.M - g0);
+  double ca, cb;
+  bool use_d;
+  trial_coef(st, S, ca, cb, use_d);
+  const SKX_G R *phi = gptr<R>(S.phi2[par]) + g0;
+  const SKX_G R *dd = gptr<R>(S.d) + g0;
+  SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + g0;
+  SKX_G R *v0s = gptr<R>(S.vpt) + g0;
+  SKX_G R *fps = gptr<R>(S.fpt) + g0;
+  SKX_G R *qps = gptr<R>(S.qpt) + g0;
+  SKX_G R *nas = gptr<R>(S.npa) + g0;
+  const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
+  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+  const bool need_f = (S.fields & F_F) != 0, need_h = (S.fields & F_H) != 0;
+  constexpr int PER = CHUNK / NT;
+  R pv[PER], dv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT;
+    if (e < cnt) {
+      pv[u] = phi[e];
+      if (use_d) dv[u] = dd[e];
+    }
+  }
+  double e_tf = 0.0, e_xc = 0.0, nel = 0.0, bad = 0.0;
+#pragma unroll 1
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT;
+    if (e >= cnt) break;
+    // (the register arrays are read with a runtime index only through
+    // this select chain, which keeps them in registers)
+    R p0 = pv[0], d0 = use_d ? dv[0] : (R)0;
+#pragma unroll
+    for (int w = 1; w < PER; ++w)
+      if (u == w) { p0 = pv[w]; if (use_d) d0 = dv[w]; }
+    const R ph = use_d ? (R)(ca * (double)p0 + cb * (double)d0) : (R)(ca * (double)p0);
+    phit[e] = ph;
+    const R n = ph * ph;
+    const double nd = (double)n;
+    double v = 0.0;
+    if (!(nd == nd) || nd > 1e300) bad += 1.0;
+    if (nd > 0.0) {
+      nel += nd;
+      const double lx = log(nd);
+      if (do_tf) {
+        double eta, psi;
+        bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
+        e_tf += S.T * nd * psi;
+        v += S.T * eta;
+      }
+      if (do_xc) {
+        double eps, vx;
+        if (sizeof(R) == 4) {
+          float ef, vf;
+          pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), ef, vf);
+          eps = ef;
+          vx = vf;
+        } else {
+          pz81_ln(lx, eps, vx);
+        }
+        e_xc += nd * eps;
+        v += vx;
+      }
+    }
+    v0s[e] = (R)v;
+    if (need_f) {
+      const R f = rpow(n, a);
+      nas[e] = f;
+      // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
+      const R cP = (ph != (R)0) ? a2 * f / ph : (R)0;
+      fps[e] = cP;
+      if (need_h) qps[e] = cP * (n - n0) + (R)2 * ph * (f - n0a);
+    }
+  }
+  double vsum[PART_A] = {e_tf, e_xc, nel, bad};
+  double tot[PART_A];
+  block_reduce<PART_A>(vsum, reinterpret_cast<double *>(smem), tid, NT, tot);
+  if (tid == 0)
+    for (int q = 0; q < PART_A; ++q) S.partA[wl * PART_A + q] = tot[q];
+}
+
+// ---------------------------------------------------------------------------
 // Pass A
 // ---------------------------------------------------------------------------
 template <typename R, int NT, int MODE>
@@ -366,32 +469,25 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
   const R invM = (R)(1.0 / (double)S.M);
   const size_t pbase = (size_t)plane * n2 * n3;
   const int np = n2 * n3;
-  double e_tf = 0.0, e_xc = 0.0, nel = 0.0, bad = 0.0;
   if (MODE == MODE_EVAL) {
-    double ca, cb;
-    bool use_d;
-    trial_coef(st, S, ca, cb, use_d);
-    // fields are read and written as pairs of neighbours along z (n3 is
-    // even, so a pair never straddles a row). First phi_t for the whole
-    // plane, LU_A pair loads in flight per thread, parked in the LDS slots
-    // the transform will read; then, after a barrier, the pointwise work.
+    // the field of this workgroup from phi_t and f = n^a of the pointwise
+    // kernel, read as pairs of neighbours along z (n3 is even, so a pair
+    // never straddles a row), LU_A pairs per thread in flight
     const size_t qbase = pbase >> 1;
-    const SKX_G V *phi = gptr<V>(S.phi2[par]) + qbase;
-    const SKX_G V *dd = gptr<V>(S.d) + qbase;
-    SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
-    const R a = (R)S.a, n0 = (R)S.n0, n0a = (R)S.n0a;
-    const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
-    const bool need_f = (S.fields & F_F) != 0;
+    const SKX_G V *pt = gptr<V>(S.phi2[1 - par]) + qbase;
+    const SKX_G V *fa = gptr<V>(S.npa) + qbase;
+    const bool need_p = fb != 2, need_fa = fb >= 2;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a;
     const int npair = np >> 1, h3 = n3 >> 1;
-    const UDiv dh3 = make_udiv((unsigned)h3), dnf = make_udiv((unsigned)nf);
+    const UDiv dh3 = make_udiv((unsigned)h3);
     for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
-      V pv[LU_A], dv[LU_A];
+      V pv[LU_A], fv[LU_A];
 #pragma unroll
       for (int u = 0; u < LU_A; ++u) {
         const int q = q0 + u * NT;
         if (q < npair) {
-          pv[u] = ldg(phi + q);
-          if (use_d) dv[u] = ldg(dd + q);
+          if (need_p) pv[u] = ldg(pt + q);
+          if (need_fa) fv[u] = ldg(fa + q);
         }
       }
 #pragma unroll
@@ -399,82 +495,16 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
         const int q = q0 + u * NT;
         if (q < npair) {
           const int j = (int)udiv((unsigned)q, dh3), k = 2 * (q - j * h3);
-          V o;
-          if (use_d) {
-            o.x = (R)(ca * (double)pv[u].x + cb * (double)dv[u].x);
-            o.y = (R)(ca * (double)pv[u].y + cb * (double)dv[u].y);
-          } else {
-            o.x = (R)(ca * (double)pv[u].x);
-            o.y = (R)(ca * (double)pv[u].y);
+          R xv[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const R p = need_p ? (h ? pv[u].y : pv[u].x) : (R)0;
+            const R f = need_fa ? (h ? fv[u].y : fv[u].x) : (R)0;
+            xv[h] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
           }
-          if (c == 0) stg(phit + q, o);
           R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
-          slot[j & 1] = o.x;
-          slot[2 + (j & 1)] = o.y;
-        }
-      }
-    }
-    __syncthreads();
-    // per element from here (one element's FP64 work live at a time keeps
-    // the register count, and so the occupancy, in check)
-    SKX_G R *v0s = gptr<R>(S.vpt) + pbase;
-    SKX_G R *fps = gptr<R>(S.fpt) + pbase;
-    SKX_G R *qps = gptr<R>(S.qpt) + pbase;
-    const bool need_h = (S.fields & F_H) != 0;
-    const R a2 = (R)(2.0 * S.a);
-    const UDiv dn3 = make_udiv((unsigned)n3);
-    for (int e = tid, it = 0; e < np; e += NT, ++it) {
-      const int j = (int)udiv((unsigned)e, dn3), k = e - j * n3;
-      // the pointwise work of this plane is shared by its field workgroups:
-      // the elements of sweeps it = c (mod nf) get the local energy
-      // densities, the local potential T eta + v_xc and f = n^a stored for
-      // the assembly pass. The choice is uniform over the workgroup, so every
-      // wavefront takes the FP64 branch in the same sweeps, with all lanes.
-      const bool mine = (it - (int)udiv((unsigned)it, dnf) * nf) == c;
-      R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]) + (j & 1);
-      const R ph = *slot;
-      const R n = ph * ph;
-      R f = 0;
-      if (need_f && (fb >= 2 || mine)) f = rpow(n, a);
-      R x;
-      if (fb == 0) x = ph;
-      else if (fb == 1) x = n;
-      else x = (fb == 2) ? f : (f - n0a) * (n - n0);
-      *slot = x * invM;
-      if (mine) {
-        const double nd = (double)n;
-        double v = 0.0;
-        if (!(nd == nd) || nd > 1e300) bad += 1.0;
-        if (nd > 0.0) {
-          nel += nd;
-          const double lx = log(nd);
-          if (do_tf) {
-            double eta, psi;
-            bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
-            e_tf += S.T * nd * psi;
-            v += S.T * eta;
-          }
-          if (do_xc) {
-            double eps, vx;
-            if (sizeof(R) == 4) {
-              float ef, vf;
-              pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), ef, vf);
-              eps = ef;
-              vx = vf;
-            } else {
-              pz81_ln(lx, eps, vx);
-            }
-            e_xc += nd * eps;
-            v += vx;
-          }
-        }
-        v0s[e] = (R)v;
-        if (need_f) {
-          // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0),
-          // c_Q = c_P (n - n0) + 2 phi (f - n0^a)
-          const R cP = (ph != (R)0) ? a2 * f / ph : (R)0;
-          fps[e] = cP;
-          if (need_h) qps[e] = cP * (n - n0) + (R)2 * ph * (f - n0a);
+          slot[j & 1] = xv[0] * invM;
+          slot[2 + (j & 1)] = xv[1] * invM;
         }
       }
     }
@@ -519,14 +549,6 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
   for (int e = tid; e < n2 * nh; e += NT) {
     const int j = (int)udiv((unsigned)e, dnh), k = e - j * nh;
     stg(spec + obase + (size_t)j * S.pitch + k, buf[j * pl + k]);
-  }
-  if (MODE == MODE_EVAL) {
-    double v[PART_A] = {e_tf, e_xc, nel, bad};
-    double tot[PART_A];
-    __syncthreads();
-    block_reduce<PART_A>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
-    if (tid == 0)
-      for (int q = 0; q < PART_A; ++q) S.partA[local * PART_A + q] = tot[q];
   }
 }
 
@@ -881,9 +903,12 @@ template <typename R>
 static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   constexpr int NTC = 512;
-  if (b.gridA > 0 && (mask & 1))
+  if (b.gridA > 0 && (mask & 1)) {
+    hipLaunchKernelGGL((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
+                       b.firstV, b.nsolve, b.gridV, b.fd);
     hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                        b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
+  }
   if (b.gridB > 0 && (mask & 2))
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
