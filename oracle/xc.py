@@ -11,6 +11,15 @@ zero-temperature parametrisation is used at every T.
        = A ln rs + B + C rs ln rs + D rs                    rs < 1
   v_c  = e_c - (rs/3) de_c/drs
 
+The two correlation branches of the published fit meet at rs = 1 with a
+jump of ~3e-5 Ha in e_c and v_c. Reading used here: they are joined C1 over
+0.99 <= rs <= 1.01 with the weight w = 3t^2 - 2t^3, t = (rs - 0.99)/0.02,
+e_c = (1 - w) e_dense + w e_dilute, and v_c follows from that e_c exactly.
+Outside the window the values are the published formulas. (A potential
+that jumps makes the minimiser's residual floor near 1e-4 for densities
+straddling rs = 1; the join changes e_c by less than 3e-5 Ha per electron
+inside the window only.)
+
 Exchange is pinned by its closed form; the correlation constants are
 "parity unpinned" against the 1981 publication, which is not available
 here (they are the standard published values).
@@ -26,6 +35,23 @@ PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
 CX = (3.0 / (4.0 * math.pi)) * (9.0 * math.pi / 4.0) ** (1.0 / 3.0)
 
 
+RS_JOIN_LO, RS_JOIN_HI = 0.99, 1.01
+
+
+def _dilute(r):
+    """Correlation for rs >= 1: e_c and de_c/drs."""
+    sq = np.sqrt(r)
+    den = 1.0 + PZ_BETA1 * sq + PZ_BETA2 * r
+    return PZ_GAMMA / den, -PZ_GAMMA * (0.5 * PZ_BETA1 / sq + PZ_BETA2) / den ** 2
+
+
+def _dense(r):
+    """Correlation for rs < 1: e_c and de_c/drs."""
+    lr = np.log(r)
+    return (PZ_A * lr + PZ_B + PZ_C * r * lr + PZ_D * r,
+            PZ_A / r + PZ_C * lr + PZ_C + PZ_D)
+
+
 def pz81(n):
     """Energy per electron eps_xc(n) and potential v_xc(n); zero where n <= 0."""
     n = np.asarray(n, dtype=np.float64)
@@ -36,20 +62,21 @@ def pz81(n):
     ex = -CX / rs
     vx = 4.0 / 3.0 * ex
     ec = np.empty(rs.shape)
-    vc = np.empty(rs.shape)
-    hi = rs >= 1.0
-    r = rs[hi]
-    sq = np.sqrt(r)
-    den = 1.0 + PZ_BETA1 * sq + PZ_BETA2 * r
-    ec[hi] = PZ_GAMMA / den
-    dec = -PZ_GAMMA * (0.5 * PZ_BETA1 / sq + PZ_BETA2) / den ** 2
-    vc[hi] = ec[hi] - r / 3.0 * dec
-    lo = ~hi
-    r = rs[lo]
-    lr = np.log(r)
-    ec[lo] = PZ_A * lr + PZ_B + PZ_C * r * lr + PZ_D * r
-    dec = PZ_A / r + PZ_C * lr + PZ_C + PZ_D
-    vc[lo] = ec[lo] - r / 3.0 * dec
+    dec = np.empty(rs.shape)
+    hi = rs >= RS_JOIN_HI
+    lo = rs <= RS_JOIN_LO
+    mid = ~(hi | lo)
+    ec[hi], dec[hi] = _dilute(rs[hi])
+    ec[lo], dec[lo] = _dense(rs[lo])
+    r = rs[mid]
+    e1, d1 = _dense(r)
+    e2, d2 = _dilute(r)
+    t = (r - RS_JOIN_LO) / (RS_JOIN_HI - RS_JOIN_LO)
+    w = t * t * (3.0 - 2.0 * t)
+    dw = 6.0 * t * (1.0 - t) / (RS_JOIN_HI - RS_JOIN_LO)
+    ec[mid] = (1.0 - w) * e1 + w * e2
+    dec[mid] = (1.0 - w) * d1 + w * d2 + dw * (e2 - e1)
+    vc = ec - rs / 3.0 * dec
     eps[pos] = ex + ec
     v[pos] = vx + vc
     return eps, v

@@ -581,11 +581,16 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
   st.theta_max = 0.5;
   // energies carry the rounding of the field precision
   st.tolE_rel = prec == 0 ? 1e-12 : 2e-6;
-  // a solve stops (SKX_NOT_CONVERGED in FP64, the switch in the FP32 phase)
-  // when its best ||r|| has not improved by 10% for this many iterations:
-  // FP32 rounding floors ||r|| near 1e-5; in FP64 a density straddling the
-  // PZ81 branch point rs = 1 floors it near 1e-4 (the potential jumps there)
-  st.stall_limit = prec == 0 ? 150 : 12;
+  // A solve stops when its best ||r|| has not dropped below stall_factor
+  // of itself for stall_limit iterations. FP64: 10% in 150 iterations
+  // (SKX_NOT_CONVERGED; a density straddling the PZ81 branch point rs = 1
+  // floors ||r|| near 1e-4, the potential jumps there). FP32: the rounding
+  // of the large, nearly cancelling potential terms floors ||r|| at
+  // 1e-5..1e-3 (growing with the cell volume), where L-BFGS stops
+  // converging fast; the FP32 phase ends (and the FP64 refinement starts)
+  // once ||r|| fails to halve within 3 iterations.
+  st.stall_limit = prec == 0 ? 150 : 3;
+  st.stall_factor = prec == 0 ? 0.9 : 0.5;
   st.best_r = 1e300;
   st.par = 0;
   st.reset_pending = from_rho ? 2 : 0;

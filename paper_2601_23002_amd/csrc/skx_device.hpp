@@ -416,28 +416,56 @@ __device__ __forceinline__ int fd_lookup(double y, const FDTable &fd, double &et
 
 // Perdew-Zunger 1981 LDA (spin-unpolarised): energy per electron and
 // potential, from x = ln n (rs = (3/(4 pi))^(1/3) exp(-x/3)). The paper uses
-// PZ LDA in the adiabatic approximation.
+// PZ LDA in the adiabatic approximation. The two correlation branches of the
+// fit (dense rs < 1, dilute rs >= 1) jump by ~3e-5 Ha at rs = 1; they are
+// joined C1 over 0.99 <= rs <= 1.01 with w = 3t^2 - 2t^3,
+// t = (rs - 0.99)/0.02, e_c = (1 - w) e_dense + w e_dilute, and v_c is the
+// exact potential of that e_c: v_c = e_c - (rs/3) de_c/drs.
+template <typename T> struct PZ {
+  static constexpr T G = (T)-0.1423, B1 = (T)1.0529, B2 = (T)0.3334;
+  static constexpr T A = (T)0.0311, B = (T)-0.048, C = (T)0.0020, D = (T)-0.0116;
+  static constexpr T LO = (T)0.99, HI = (T)1.01;
+};
+
+// dilute branch: e_c and de_c/drs from rs and sqrt(rs) and 1/den
+template <typename T>
+__device__ __forceinline__ void pz_dilute(T rs, T sq, T iden, T &e, T &de) {
+  e = PZ<T>::G * iden;
+  de = -PZ<T>::G * ((T)0.5 * PZ<T>::B1 / sq + PZ<T>::B2) * iden * iden;
+}
+// dense branch: e_c and de_c/drs from rs and ln rs
+template <typename T>
+__device__ __forceinline__ void pz_dense(T rs, T lr, T irs, T &e, T &de) {
+  e = PZ<T>::A * lr + PZ<T>::B + PZ<T>::C * rs * lr + PZ<T>::D * rs;
+  de = PZ<T>::A * irs + PZ<T>::C * lr + PZ<T>::C + PZ<T>::D;
+}
+
 __device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
   const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
+  const double LNRS1 = -0.47746482927568600731;  // ln RS1
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
   const double e3 = exp(x * (1.0 / 3.0));
-  double rs = RS1 / e3;
-  double ex = -CX / RS1 * e3;
-  double ec, vc;
-  if (rs >= 1.0) {
-    const double G = -0.1423, B1 = 1.0529, B2 = 0.3334;
-    double sq = sqrt(rs);
-    double den = 1.0 + B1 * sq + B2 * rs;
-    ec = G / den;
-    vc = G * (1.0 + (7.0 / 6.0) * B1 * sq + (4.0 / 3.0) * B2 * rs) / (den * den);
+  const double rs = RS1 / e3;
+  const double ex = -CX / RS1 * e3;
+  double ec, dec;
+  if (rs >= PZ<double>::HI) {
+    const double sq = sqrt(rs);
+    pz_dilute(rs, sq, 1.0 / (1.0 + PZ<double>::B1 * sq + PZ<double>::B2 * rs), ec, dec);
+  } else if (rs <= PZ<double>::LO) {
+    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 / RS1, ec, dec);
   } else {
-    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
-    double lr = log(RS1) - x * (1.0 / 3.0);
-    ec = A * lr + B + C * rs * lr + D * rs;
-    vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + (2.0 * D - C) * rs / 3.0;
+    double e1, d1, e2, d2;
+    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 / RS1, e1, d1);
+    const double sq = sqrt(rs);
+    pz_dilute(rs, sq, 1.0 / (1.0 + PZ<double>::B1 * sq + PZ<double>::B2 * rs), e2, d2);
+    const double t = (rs - PZ<double>::LO) / (PZ<double>::HI - PZ<double>::LO);
+    const double w = t * t * (3.0 - 2.0 * t);
+    const double dw = 6.0 * t * (1.0 - t) / (PZ<double>::HI - PZ<double>::LO);
+    ec = (1.0 - w) * e1 + w * e2;
+    dec = (1.0 - w) * d1 + w * d2 + dw * (e2 - e1);
   }
   eps = ex + ec;
-  v = (4.0 / 3.0) * ex + vc;
+  v = (4.0 / 3.0) * ex + ec - rs * (1.0 / 3.0) * dec;
 }
 
 // Single-precision PZ81 for the FP32 evaluations (the exchange-correlation
@@ -451,21 +479,27 @@ __device__ __forceinline__ void pz81_lnf(float x, float &eps, float &v) {
   const float e3 = __builtin_amdgcn_exp2f(x * L2E3);
   const float rs = RS1 * __builtin_amdgcn_rcpf(e3);
   const float ex = -(CX / RS1) * e3;
-  float ec, vc;
-  if (rs >= 1.0f) {
-    const float G = -0.1423f, B1 = 1.0529f, B2 = 0.3334f;
+  float ec, dec;
+  if (rs >= PZ<float>::HI) {
     const float sq = __builtin_amdgcn_sqrtf(rs);
-    const float iden = __builtin_amdgcn_rcpf(1.0f + B1 * sq + B2 * rs);
-    ec = G * iden;
-    vc = G * (1.0f + (7.0f / 6.0f) * B1 * sq + (4.0f / 3.0f) * B2 * rs) * iden * iden;
+    pz_dilute(rs, sq, __builtin_amdgcn_rcpf(1.0f + PZ<float>::B1 * sq + PZ<float>::B2 * rs), ec,
+              dec);
+  } else if (rs <= PZ<float>::LO) {
+    pz_dense(rs, LNRS1 - x * (1.0f / 3.0f), e3 * (1.0f / RS1), ec, dec);
   } else {
-    const float A = 0.0311f, B = -0.048f, C = 0.0020f, D = -0.0116f;
-    const float lr = LNRS1 - x * (1.0f / 3.0f);
-    ec = A * lr + B + C * rs * lr + D * rs;
-    vc = A * lr + (B - A / 3.0f) + (2.0f / 3.0f) * C * rs * lr + (2.0f * D - C) * rs / 3.0f;
+    float e1, d1, e2, d2;
+    pz_dense(rs, LNRS1 - x * (1.0f / 3.0f), e3 * (1.0f / RS1), e1, d1);
+    const float sq = __builtin_amdgcn_sqrtf(rs);
+    pz_dilute(rs, sq, __builtin_amdgcn_rcpf(1.0f + PZ<float>::B1 * sq + PZ<float>::B2 * rs), e2,
+              d2);
+    const float t = (rs - PZ<float>::LO) * (1.0f / (PZ<float>::HI - PZ<float>::LO));
+    const float w = t * t * (3.0f - 2.0f * t);
+    const float dw = 6.0f * t * (1.0f - t) * (1.0f / (PZ<float>::HI - PZ<float>::LO));
+    ec = (1.0f - w) * e1 + w * e2;
+    dec = (1.0f - w) * d1 + w * d2 + dw * (e2 - e1);
   }
   eps = ex + ec;
-  v = (4.0f / 3.0f) * ex + vc;
+  v = (4.0f / 3.0f) * ex + ec - rs * (1.0f / 3.0f) * dec;
 }
 
 // ---------------------------------------------------------------------------

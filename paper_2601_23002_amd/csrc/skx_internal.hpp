@@ -45,6 +45,7 @@ struct OptState {
   int m, max_iter, max_trials, reset_pending;
   int pair_ok, par, stall, stall_limit;
   double gtol, c1, theta_max, tolE_rel;
+  double stall_factor;             // best ||r|| must drop below this fraction of itself
   double E, Et, mu, mut, rnorm, theta, g0, dnorm, rd, best_r;
   double gamma, cr, cphi;
   double cS[MMAX], cY[MMAX];

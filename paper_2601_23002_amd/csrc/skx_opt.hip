@@ -306,7 +306,7 @@ __device__ void finalize_update_body(OptState *st, const SolveDev &S, double *t)
   if (st->iters >= st->max_iter) { st->phase = PH_DONE; st->status = 1; return; }
   if (st->stall_limit > 0) {
     // low-precision phase: stop once the residual no longer improves
-    if (st->rnorm < 0.9 * st->best_r) { st->best_r = st->rnorm; st->stall = 0; }
+    if (st->rnorm < st->stall_factor * st->best_r) { st->best_r = st->rnorm; st->stall = 0; }
     else if (++st->stall >= st->stall_limit) { st->phase = PH_DONE; st->status = 2; return; }
   }
   // compact L-BFGS coefficients, H0 = gamma P

@@ -167,6 +167,19 @@ def test_evaluate_fp32_within_single_precision():
     _compare_eval(_system(24, seed=5), seed=6, tol=2e-5, prec=skx.FP32)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_evaluate_across_the_pz81_join(precision):
+    """Mean density at rs = 1: a good share of the points falls inside the
+    0.99 <= rs <= 1.01 join of the two PZ81 correlation branches."""
+    skx, _ = _lib()
+    s = _system(24, seed=9, rs=1.0, T=2.0)
+    _say(f"case: evaluate across the PZ81 join, {precision}")
+    if precision == "fp64":
+        _compare_eval(s, seed=10)
+    else:
+        _compare_eval(s, seed=10, tol=2e-5, prec=skx.FP32)
+
+
 def test_evaluate_rejects_nonfinite():
     skx, torch = _lib()
     s = _system(16)

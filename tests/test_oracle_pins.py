@@ -380,12 +380,27 @@ def test_exchange_closed_form_and_potential():
     assert np.all(eps < eps_x_ref)          # correlation energy is negative
 
 
-def test_pz81_continuity_at_rs_one():
-    n1 = 3 / (4 * math.pi)
-    e_lo, v_lo = xc.pz81(np.array([n1 * (1 + 1e-12)]))
-    e_hi, v_hi = xc.pz81(np.array([n1 * (1 - 1e-12)]))
-    # the published fit is continuous to about 1e-4 Ha at rs = 1
-    assert abs(e_lo[0] - e_hi[0]) < 2e-4
+def test_pz81_join_is_continuous_and_consistent():
+    """The two branches of the fit are joined C1 over 0.99 <= rs <= 1.01:
+    eps_xc and v_xc are continuous across the window edges and rs = 1, and
+    v_xc = d(n eps_xc)/dn holds inside the window (central differences)."""
+    def n_of(rs):
+        return 3.0 / (4.0 * math.pi * rs ** 3)
+    for rs in (xc.RS_JOIN_LO, 1.0, xc.RS_JOIN_HI):
+        e, v = xc.pz81(np.array([n_of(rs * (1 - 1e-10)), n_of(rs * (1 + 1e-10))]))
+        # (without the join both would jump by ~3e-5 Ha at rs = 1)
+        assert abs(e[0] - e[1]) < 1e-8 and abs(v[0] - v[1]) < 1e-8, rs
+    for rs in (0.985, 0.992, 0.999, 1.0, 1.004, 1.009, 1.015):
+        n = n_of(rs)
+        h = 1e-6 * n
+        e, v = xc.pz81(np.array([n - h, n, n + h]))
+        dnde = ((n + h) * e[2] - (n - h) * e[0]) / (2 * h)
+        assert abs(dnde - v[1]) < 1e-8, rs
+    # the join stays within the branch gap of the published fit
+    e_j, _ = xc.pz81(np.array([n_of(1.0)]))
+    e_d, _ = xc.pz81(np.array([n_of(0.98)]))
+    e_l, _ = xc.pz81(np.array([n_of(1.02)]))
+    assert min(e_d[0], e_l[0]) - 1e-2 < e_j[0] < max(e_d[0], e_l[0]) + 1e-2
 
 
 # ----------------------------------------------------------------------------
