@@ -442,7 +442,7 @@ __device__ __forceinline__ void pz_dense(T rs, T lr, T irs, T &e, T &de) {
 
 __device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
   const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
-  const double LNRS1 = -0.47746482927568600731;  // ln RS1
+  const double LNRS1 = -0.47747065276706024;  // ln RS1
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
   const double e3 = exp(x * (1.0 / 3.0));
   const double rs = RS1 / e3;
@@ -473,7 +473,7 @@ __device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
 // FP64 refinement uses pz81_ln). Hardware exp2 / reciprocal / square root.
 __device__ __forceinline__ void pz81_lnf(float x, float &eps, float &v) {
   const float RS1 = 0.62035049089940001667f;   // (3/(4 pi))^(1/3)
-  const float LNRS1 = -0.47746482927568600731f;  // ln RS1
+  const float LNRS1 = -0.47747065276706024f;  // ln RS1
   const float CX = 0.45816529328314287f;       // (3/(4 pi)) (9 pi / 4)^(1/3)
   const float L2E3 = 0.48089834696298783f;     // log2(e) / 3
   const float e3 = __builtin_amdgcn_exp2f(x * L2E3);
