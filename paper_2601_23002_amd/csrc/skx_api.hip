@@ -613,6 +613,8 @@ struct Profiler {
 // and replayed (process-wide switch, on by default).
 bool g_graphs = true;
 
+bool graphs_enabled() { return g_graphs && !g_prof.on; }
+
 hipEvent_t prof_event() {
   if (!g_prof.pool.empty()) {
     hipEvent_t e = g_prof.pool.back();

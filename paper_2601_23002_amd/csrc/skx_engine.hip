@@ -62,6 +62,16 @@ struct Group {
   int *dphase = nullptr;
   int cap = 0;
   BatchLaunch bl{};
+  // one engine step of this group (normalisation, the step sequences, the
+  // phase gather) captured for the current membership
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void drop_graph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
 };
 
 }  // namespace
@@ -163,9 +173,33 @@ int admit(skx_engine *e, Queued &q, Resident *&out) {
   return SKX_OK;
 }
 
+hipError_t group_step(skx_engine *e, Group &g) {
+  hipError_t he = launch_normalize(g.bl, e->stream);
+  for (int k = 0; k < ENGINE_CHUNK && he == hipSuccess; ++k) he = step_sequence(g.bl, e->stream);
+  if (he == hipSuccess) he = gather_phases(g.ddev, (int)g.members.size(), g.dphase, e->stream);
+  return he;
+}
+
+// Capture group_step into a graph (left without one if capture is refused).
+void capture_group(skx_engine *e, Group &g) {
+  if (!graphs_enabled() || g.members.empty()) return;
+  if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  const hipError_t ec = group_step(e, g);
+  hipError_t ee = hipStreamEndCapture(e->stream, &g.graph);
+  if (ec == hipSuccess && ee == hipSuccess) ee = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (ec != hipSuccess || ee != hipSuccess) {
+    g.drop_graph();
+    (void)hipGetLastError();
+  }
+}
+
 int rebuild(skx_engine *e, Group &g, int prec) {
   const int n = (int)g.members.size();
   g.dirty = false;
+  g.drop_graph();
   if (n == 0) return SKX_OK;
   if (n > g.cap) {
     hipStreamSynchronize(e->stream);
@@ -187,6 +221,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   if (rc) return eng_fail(e, rc, g.members[0]->ctx->err);
   // build_batch reads hs from pageable memory: finish before hs goes away
   hipStreamSynchronize(e->stream);
+  capture_group(e, g);
   return SKX_OK;
 }
 
@@ -316,9 +351,10 @@ int skx_engine_step(skx_engine *e) {
       if (rc) return rc;
     }
     if (g.members.empty()) continue;
-    hipError_t he = launch_normalize(g.bl, e->stream);
-    for (int k = 0; k < ENGINE_CHUNK && he == hipSuccess; ++k) he = step_sequence(g.bl, e->stream);
-    if (he == hipSuccess) he = gather_phases(g.ddev, (int)g.members.size(), g.dphase, e->stream);
+    // replay the captured step while the membership and the graph switch
+    // hold; launch eagerly otherwise
+    if (g.exec && !graphs_enabled()) g.drop_graph();
+    hipError_t he = g.exec ? hipGraphLaunch(g.exec, e->stream) : group_step(e, g);
     if (he != hipSuccess) return eng_fail(e, SKX_E_DEVICE, std::string("step kernels: ") + hipGetErrorString(he));
   }
   // collect phases, retire or promote finished solves
@@ -399,6 +435,7 @@ void skx_engine_destroy(skx_engine *e) {
   for (Finished &f : e->done)
     if (f.rho_dev) hipFree(f.rho_dev);
   for (Group &g : e->group) {
+    g.drop_graph();
     if (g.ddev) hipFree(g.ddev);
     if (g.dfirst) hipFree(g.dfirst);
     if (g.dphase) hipFree(g.dphase);

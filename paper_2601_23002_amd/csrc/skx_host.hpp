@@ -72,6 +72,9 @@ hipError_t start_uniform(skx_ctx *c, Instance &I, hipStream_t s);
 hipError_t promote_phi(const Instance &I32, int par, Instance &I64, hipStream_t s);
 // rho = phi^2 of parity `par` into an FP64 device field.
 hipError_t square_out(const Instance &I, int par, double *rho, hipStream_t s);
+// True when step sequences may be captured into HIP graphs (graphs on and
+// per-pass event timing off).
+bool graphs_enabled();
 // Gather states[i]->phase of a batch into out[i] (device).
 hipError_t gather_phases(const SolveDev *dev, int n, int *out, hipStream_t s);
 
