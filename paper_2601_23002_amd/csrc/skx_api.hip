@@ -188,6 +188,11 @@ constexpr size_t LDS_MAX = 160 * 1024;
 
 // Allocate (or reuse) the buffers of one precision instance and fill the
 // descriptor's grid and buffer fields.
+// Points per workgroup of the optimiser update: larger on large grids,
+// where the single-block finaliser would otherwise read thousands of rows of
+// partial sums.
+int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
+
 struct ArenaLayout {
   size_t o_phi, o_phit, o_grad, o_r, o_rt, o_pr, o_prt, o_d, o_vpt, o_fpt, o_qpt, o_npa, o_S, o_Y;
   size_t o_spec, o_vloc, o_pA, o_pB, o_pC, o_pU, o_pD, total;
@@ -202,6 +207,7 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   const long long H = (long long)n1 * n2 * pitch;
   const int nkb = (nh + tk - 1) / tk;
   const int nwg = (int)((M + CHUNK - 1) / CHUNK);
+  const int nwu = (int)((M + update_chunk(M) - 1) / update_chunk(M));
   ArenaLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -212,7 +218,7 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   L.o_S = take(rsz * M * m); L.o_Y = take(rsz * M * m);
   L.o_spec = take(2 * rsz * H * NFIELD); L.o_vloc = take(2 * rsz * H);
   L.o_pA = take(8 * (size_t)nwg * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
-  L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwg * NDOT);
+  L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwu * NDOT);
   L.o_pD = take(8 * (size_t)nwg * 2);
   L.total = off;
   return L;
@@ -220,7 +226,7 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
 
 size_t instance_bytes(int n1, int n2, int n3, int prec, int m) {
   return arena_layout(n1, n2, n3, prec, std::max(m, 1)).total + sizeof(SolveDev) +
-         sizeof(OptState) + 8 * sizeof(int);
+         sizeof(OptState) + 2 * NPREFIX * sizeof(int);
 }
 
 int ensure_instance(skx_ctx *c, int prec, int m) {
@@ -251,7 +257,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   hipMemsetAsync(I.mem, 0, off, c->stream);
   e = hipMalloc((void **)&I.dptr, sizeof(SolveDev));
   if (e == hipSuccess) e = hipMalloc((void **)&I.st, sizeof(OptState));
-  if (e == hipSuccess) e = hipMalloc((void **)&I.first, sizeof(int) * 8);
+  if (e == hipSuccess) e = hipMalloc((void **)&I.first, sizeof(int) * 2 * NPREFIX);
   if (e != hipSuccess) { free_instance(I); return hip_fail(c, e, "descriptor allocation"); }
   hipMemsetAsync(I.st, 0, sizeof(OptState), c->stream);
   I.prec = prec;
@@ -263,6 +269,8 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h = SolveDev{};
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = nh; h.pitch = pitch;
   h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg; h.mh = m;
+  h.uchunk = update_chunk(M);
+  h.nwg_upd = (int)((M + h.uchunk - 1) / h.uchunk);
   h.M = M; h.H = H;
   h.phi2[0] = base + o_phi; h.phi2[1] = base + o_phit; h.grad = base + o_grad;
   h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
@@ -312,8 +320,8 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
 int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s) {
   const int n = (int)hs.size();
-  std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1);
-  fa[0] = fb[0] = fc[0] = fv[0] = 0;
+  std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1), fu(n + 1);
+  fa[0] = fb[0] = fc[0] = fv[0] = fu[0] = 0;
   size_t la = 0, lb = 0, lc = 0;
   for (int i = 0; i < n; ++i) {
     const SolveDev &h = hs[i];
@@ -321,6 +329,7 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
     fb[i + 1] = fb[i] + h.n2 * h.nkb;
     fc[i + 1] = fc[i] + h.n1;
     fv[i + 1] = fv[i] + h.nwg_vec;
+    fu[i + 1] = fu[i] + h.nwg_upd;
     size_t a, b, cc;
     lds_sizes(h, prec, a, b, cc);
     la = std::max(la, a); lb = std::max(lb, b); lc = std::max(lc, cc);
@@ -332,6 +341,7 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
   all.insert(all.end(), fb.begin(), fb.end());
   all.insert(all.end(), fc.begin(), fc.end());
   all.insert(all.end(), fv.begin(), fv.end());
+  all.insert(all.end(), fu.begin(), fu.end());
   hipError_t e = hipMemcpyAsync(dfirst, all.data(), sizeof(int) * all.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -343,11 +353,12 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
   bl.prec = prec;
   bl.twbank = R.twbank;
   bl.fd = R.fd;
-  bl.gridA = fa[n]; bl.gridB = fb[n]; bl.gridC = fc[n]; bl.gridV = fv[n];
+  bl.gridA = fa[n]; bl.gridB = fb[n]; bl.gridC = fc[n]; bl.gridV = fv[n]; bl.gridU = fu[n];
   bl.firstA = dfirst;
   bl.firstB = dfirst + (n + 1);
   bl.firstC = dfirst + 2 * (n + 1);
   bl.firstV = dfirst + 3 * (n + 1);
+  bl.firstU = dfirst + 4 * (n + 1);
   // pass C keeps dE/dphi beside the plane in LDS when every solve fits
   size_t lc_acc = 0;
   // (FP64: the dE/dphi plane; FP32: that plane and a copy of phi_t)
@@ -1201,7 +1212,7 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   SolveDev *ddev = nullptr;
   int *dfirst = nullptr;
   hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * 4 * (nctx + 1), s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * NPREFIX * (nctx + 1), s);
   if (e != hipSuccess) return hip_fail(c0, e, "batch descriptors");
   std::vector<OptState> outs(nctx), o32(nctx);
   int rc = SKX_OK;
@@ -1384,7 +1395,7 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
   SolveDev *ddev = nullptr;
   int *dfirst = nullptr;
   hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * 4 * (nctx + 1), s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * NPREFIX * (nctx + 1), s);
   if (e != hipSuccess) return hip_fail(c0, e, "bench descriptors");
   BatchLaunch bl{};
   int rc = build_batch(c0, hs, prec, ddev, dfirst, bl, s);

@@ -209,7 +209,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
     g.ddev = nullptr; g.dfirst = nullptr; g.dphase = nullptr; g.cap = 0;
     const int cap = std::max(n, 2 * g.cap + 8);
     hipError_t he = hipMalloc((void **)&g.ddev, sizeof(SolveDev) * cap);
-    if (he == hipSuccess) he = hipMalloc((void **)&g.dfirst, sizeof(int) * 4 * (cap + 1));
+    if (he == hipSuccess) he = hipMalloc((void **)&g.dfirst, sizeof(int) * NPREFIX * (cap + 1));
     if (he == hipSuccess) he = hipMalloc((void **)&g.dphase, sizeof(int) * cap);
     if (he != hipSuccess) return eng_fail(e, SKX_E_NOMEM, "batch descriptor allocation");
     g.cap = cap;

@@ -16,6 +16,9 @@ constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinit
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
 constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
 constexpr int CHUNK = 1024;        // grid points per workgroup in the vector passes
+constexpr int UCHUNK = 4096;       // grid points per workgroup of the optimiser update on
+                                   // large grids (fewer rows of its 58 partial sums)
+constexpr int NPREFIX = 5;         // batch prefix-sum arrays: A, B, C, vector, update
 
 // Which transformed fields are present (slot order phi, n, f, h).
 enum FieldBits { F_PHI = 1, F_N = 2, F_F = 4, F_H = 8 };
@@ -66,6 +69,7 @@ struct SolveDev {
   int slot[NFIELD];                // spectrum slot of phi, n, f, h (-1 if absent)
   int nkb, tk;                     // pass-B column blocks and their width
   int nwg_vec;                     // workgroups of the vector passes
+  int nwg_upd, uchunk;             // workgroups of the optimiser update and their points
   int mh;                          // history slots allocated (>= the solve's m)
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
   unsigned terms;
@@ -113,8 +117,8 @@ struct BatchLaunch {
   int prec;                        // 0 fp64, 1 fp32
   const double *twbank;
   FDTable fd;
-  int gridA, gridB, gridC, gridV;  // total workgroups per kernel
-  const int *firstA, *firstB, *firstC, *firstV;  // device prefix sums (nsolve+1)
+  int gridA, gridB, gridC, gridV, gridU;  // total workgroups per kernel
+  const int *firstA, *firstB, *firstC, *firstV, *firstU;  // device prefix sums (nsolve+1)
   size_t ldsA, ldsB, ldsC;
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int mh;                          // largest history length of the batch (1..MMAX)

@@ -160,8 +160,8 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   if (st->phase != PH_UPDATE) return;
   const int tid = threadIdx.x;
   const int wl = item - first_of(first, s);
-  const long long g0 = (long long)wl * CHUNK;
-  const long long g1 = min((long long)S.M, g0 + CHUNK);
+  const long long g0 = (long long)wl * S.uchunk;
+  const long long g1 = min((long long)S.M, g0 + S.uchunk);
   const int par = st->par;
   const SKX_G R *phi = gptr<R>(S.phi2[par]);
   const SKX_G R *phit = gptr<R>(S.phi2[1 - par]);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
     double v[NDOT];
 #pragma unroll
     for (int q = 0; q < NDOT; ++q) v[q] = 0.0;
-    for (int r = tid; r < S.nwg_vec; r += 256)
+    for (int r = tid; r < S.nwg_upd; r += 256)
 #pragma unroll
       for (int q = 0; q < NDOT; ++q) v[q] += S.partU[r * NDOT + q];
     block_reduce_many<NDOT>(v, sh, tid, 256, t);
@@ -538,8 +538,8 @@ static hipError_t launch_update_t(const BatchLaunch &b, hipStream_t s) {
   switch (b.mh) {
 #define SKX_UPD(MM)                                                                         \
   case MM:                                                                                  \
-    hipLaunchKernelGGL((k_update<R, 256, MM>), dim3(b.gridV), dim3(256), 0, s, b.dev,         \
-                       b.firstV, b.nsolve, b.gridV);                                        \
+    hipLaunchKernelGGL((k_update<R, 256, MM>), dim3(b.gridU), dim3(256), 0, s, b.dev,         \
+                       b.firstU, b.nsolve, b.gridU);                                        \
     break;
     SKX_UPD(1) SKX_UPD(2) SKX_UPD(3) SKX_UPD(4) SKX_UPD(5) SKX_UPD(6) SKX_UPD(7)
     default: SKX_UPD(8)
