@@ -382,6 +382,83 @@ __device__ __forceinline__ void wave_share(int count, int w, int nw, int &lo, in
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront-owned transforms whose length, radix order and storage are fixed
+// at compile time, so every index is a constant or a shift. The wavefront
+// owns SLOTS transforms starting at buf (element e of transform t at
+// buf[t*TS + e*ES]); lanes take consecutive transforms (TFAST) or
+// consecutive butterflies of one transform, one or more butterflies each.
+// Same Stockham stage as fft_stage_w: all reads of the stage before any
+// write, tw[k] = exp(-2 pi i k / N).
+// ---------------------------------------------------------------------------
+template <int N, int RAD, int SLOTS, bool TFAST> struct CMap {
+  static constexpr int NB = N / RAD;               // butterflies per transform
+  static constexpr int TOT = SLOTS * NB;
+  static constexpr int MB = (TOT + 63) / 64;       // butterflies per lane
+  __device__ __forceinline__ static int t(int b) { return TFAST ? b % SLOTS : b / NB; }
+  __device__ __forceinline__ static int j(int b) { return TFAST ? b / SLOTS : b % NB; }
+  __device__ __forceinline__ static bool ok(int b) { return TOT % 64 == 0 || b < TOT; }
+};
+
+// Twiddle and butterfly of one radix-RAD group whose inputs are in v.
+template <typename V, int N, int RAD, int NS, bool INV>
+__device__ __forceinline__ void cbfly(V (&v)[RAD], int k, const V *tw) {
+  if (NS > 1) {
+    constexpr int TWS = N / (NS * RAD);
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) {
+      const V w = tw[k * r * TWS];
+      v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+    }
+  }
+  Bfly<RAD, INV, V>::run(v);
+}
+
+template <typename V, int N, int RAD, int NS, int ES, int TS, int SLOTS, bool TFAST, bool INV>
+__device__ __forceinline__ void cstage(V *buf, const V *tw, int lane) {
+  typedef CMap<N, RAD, SLOTS, TFAST> M;
+  V v[M::MB][RAD];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i) {
+    const int b = lane + 64 * i;
+    if (M::ok(b)) {
+      const V *base = buf + M::t(b) * TS + M::j(b) * ES;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[i][r] = base[r * M::NB * ES];
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i) {
+    const int b = lane + 64 * i;
+    if (M::ok(b)) {
+      const int j = M::j(b), k = j % NS;
+      cbfly<V, N, RAD, NS, INV>(v[i], k, tw);
+      V *out = buf + M::t(b) * TS + ((j - k) * RAD + k) * ES;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) out[r * NS * ES] = v[i][r];
+    }
+  }
+  SKX_WAVE_SYNC();
+}
+
+// Stages of the radix list RS... starting at span NS.
+template <typename V, int N, int NS, int ES, int TS, int SLOTS, bool TFAST, bool INV>
+__device__ __forceinline__ void cstages(V *, const V *, int) {}
+template <typename V, int N, int NS, int ES, int TS, int SLOTS, bool TFAST, bool INV, int R0,
+          int... RS>
+__device__ __forceinline__ void cstages(V *buf, const V *tw, int lane) {
+  cstage<V, N, R0, NS, ES, TS, SLOTS, TFAST, INV>(buf, tw, lane);
+  cstages<V, N, NS * R0, ES, TS, SLOTS, TFAST, INV, RS...>(buf, tw, lane);
+}
+
+// Radix orders of the compile-time lengths (first radix even: the real
+// transforms fold their Nyquist terms into the first stage).
+template <int N> struct CRad;
+template <> struct CRad<64> {
+  static constexpr int R0 = 8, R1 = 8;
+};
+
+// ---------------------------------------------------------------------------
 // Universal Fermi-Dirac table: eta and psi = f_TF / (n T) as functions of
 // y = ln(n / n_T), by quintic Hermite interpolation between nodes that store
 // eta, eta', eta'' and psi (psi' = eta - psi and psi'' = eta' - eta + psi

@@ -335,6 +335,24 @@ __device__ __forceinline__ void load_plane(V *buf, const SKX_G V *src, int n2, i
   }
 }
 
+// load_plane for a compile-time plane shape (N2 rows of PL values).
+template <typename V, int N2, int PL, int NT>
+__device__ __forceinline__ void load_plane_f(V *buf, const SKX_G V *src, int pitch, int tid) {
+  constexpr int TOT = N2 * PL;
+  constexpr int NU = (TOT + NT - 1) / NT;
+  V t[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + u * NT;
+    if (TOT % NT == 0 || e < TOT) t[u] = ldg(src + (size_t)(e / PL) * pitch + e % PL);
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + u * NT;
+    if (TOT % NT == 0 || e < TOT) buf[e] = t[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise pass (first kernel of pass A), one workgroup per CHUNK points of
 // a solve: the trial point phi_t = ca phi + cb d, n = phi_t^2, f = n^a, the
@@ -897,6 +915,265 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 }
 
 // ---------------------------------------------------------------------------
+// Pass C on planes of a shape fixed at compile time (N2 x N3, radix orders
+// from CRad), one workgroup of four wavefronts per x-plane, every index a
+// constant. Per field:
+//  * the half spectrum of the plane is copied into LDS;
+//  * the DC and Nyquist columns, whose inverse y transforms are real, are
+//    each reduced to their Hermitian part (whose inverse is the real part of
+//    the plain inverse) and folded into one complex column, so the N3/2
+//    columns split evenly over the wavefronts;
+//  * after a barrier every wavefront takes N2/8 row pairs: its first z stage
+//    builds x_{2p} + i x_{2p+1} over the full row from the two half spectra,
+//    its last stage keeps the outputs in registers, where they are assembled
+//    with their pointwise coefficients into dE/dphi of the 2 R1 points per
+//    butterfly the lane owns (the same points for every field).
+// MODE_PREC transforms the one preconditioner field back to real space.
+// ---------------------------------------------------------------------------
+template <typename V, int N3, int RAD, int ZP>
+__device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
+  constexpr int C = N3 / 2, PL = C + 1;
+  typedef CMap<N3, RAD, ZP, false> M;
+  static_assert(RAD % 2 == 0, "even first radix");
+  V v[M::MB][RAD];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i) {
+    const int b = lane + 64 * i;
+    if (M::ok(b)) {
+      const int p = M::t(b), j = M::j(b);
+      const V *ra = buf + 2 * p * PL, *rb = ra + PL;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        const int e = j + M::NB * r;
+        V a, c;
+        if (r < RAD / 2) {                   // 0 <= e < C
+          a = ra[e]; c = rb[e];
+          if (r == 0 && j == 0) { a.y = 0; c.y = 0; }        // DC: real part of column 0
+        } else {                             // C <= e < N3: Hermitian mirror
+          const bool nyq = (r == RAD / 2) && (j == 0);
+          const int m = nyq ? 0 : N3 - e;
+          a = ra[m]; c = rb[m];
+          if (nyq) { a.x = a.y; a.y = 0; c.x = c.y; c.y = 0; }  // Nyquist: imaginary part of column 0
+          else { a.y = -a.y; c.y = -c.y; }
+        }
+        v[i][r].x = a.x - c.y;
+        v[i][r].y = a.y + c.x;
+      }
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i) {
+    const int b = lane + 64 * i;
+    if (M::ok(b)) {
+      const int p = M::t(b), j = M::j(b);
+      Bfly<RAD, true, V>::run(v[i]);
+      V *out = buf + 2 * p * PL + j * RAD;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) out[r] = v[i][r];
+    }
+  }
+  SKX_WAVE_SYNC();
+}
+
+// Columns 0 and C of the plane (rows [0, N2)) folded into column 0 as
+// herm(X_0) + i herm(X_C), by one wavefront.
+template <typename V, int N2, int N3>
+__device__ __forceinline__ void fold_dc_nyquist(V *buf, int lane) {
+  typedef decltype(buf[0].x) R;
+  constexpr int C = N3 / 2, PL = C + 1, NY = (N2 + 63) / 64;
+  V z[NY];
+#pragma unroll
+  for (int u = 0; u < NY; ++u) {
+    const int y = lane + 64 * u;
+    if (y < N2) {
+      const int ym = (N2 - y) % N2;
+      const V a = buf[y * PL], am = buf[ym * PL], b = buf[y * PL + C], bm = buf[ym * PL + C];
+      const R h0x = (R)0.5 * (a.x + am.x), h0y = (R)0.5 * (a.y - am.y);
+      const R hnx = (R)0.5 * (b.x + bm.x), hny = (R)0.5 * (b.y - bm.y);
+      z[u].x = h0x - hny;
+      z[u].y = h0y + hnx;
+    }
+  }
+  SKX_WAVE_SYNC();
+#pragma unroll
+  for (int u = 0; u < NY; ++u) {
+    const int y = lane + 64 * u;
+    if (y < N2) buf[y * PL] = z[u];
+  }
+  SKX_WAVE_SYNC();
+}
+
+// Inverse y transform and first z stage of the plane in buf; on return the
+// lane's last-stage butterflies are in v (outputs at z = j + R0 r of the row
+// pair p, real parts row 2p, imaginary parts row 2p+1).
+template <typename V, int N2, int N3, int ZP, int MB>
+__device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *tw3, int lane,
+                                                int wave, V (&v)[MB][CRad<N3>::R1]) {
+  constexpr int C = N3 / 2, PL = C + 1, NW = 4, YC = C / NW;
+  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
+  constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
+  static_assert(Y0 * Y1 == N2 && R0 * R1 == N3, "two stages per direction");
+  if (wave == 0) fold_dc_nyquist<V, N2, N3>(buf, lane);
+  cstages<V, N2, 1, PL, 1, YC, true, true, Y0, Y1>(buf + wave * YC, tw2, lane);
+  __syncthreads();
+  V *zb = buf + wave * ZP * 2 * PL;
+  zfirst_merge<V, N3, R0, ZP>(zb, lane);
+  typedef CMap<N3, R1, ZP, false> ZM;
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = lane + 64 * i;
+    if (ZM::ok(b)) {
+      const int p = ZM::t(b), j = ZM::j(b);
+      const V *base = zb + 2 * p * PL + j;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[i][r] = base[r * ZM::NB];
+      cbfly<V, N3, R1, R0, true>(v[i], j, tw3);
+    }
+  }
+}
+
+template <typename R, int N2, int N3, int MODE>
+__global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first, int nsolve,
+                                                int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  constexpr int NT = 256, NW = 4;
+  constexpr int C = N3 / 2, PL = C + 1;
+  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
+  constexpr int ZP = N2 / 2 / NW;                 // row pairs per wavefront
+  typedef CMap<N3, R1, ZP, false> ZM;
+  constexpr int MB = ZM::MB;
+  constexpr bool KEEP_PHI = sizeof(R) == 4;       // phi_t stays in registers (FP32)
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int plane = item - first_of(first, s);
+  V *buf = reinterpret_cast<V *>(smem);
+  V *tw2 = buf + N2 * PL;
+  V *tw3 = tw2 + N2;
+  load_twiddles(tw2, twbank, S.p2.tw, N2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, N3, tid, NT);
+  const size_t pbase = (size_t)plane * N2 * N3;
+  const SKX_G V *spec = gptr<V>(S.spec) + (size_t)plane * N2 * S.pitch;
+  const int pitch = S.pitch;
+  // the lane's points: row 2p + h, z = j + R0 r of butterfly slot i
+  int pt[MB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = lane + 64 * i;
+    pt[i] = ZM::ok(b) ? 2 * (wave * ZP + ZM::t(b)) * N3 + ZM::j(b) : -1;
+  }
+  V v[MB][R1];
+
+  if (MODE == MODE_PREC) {
+    load_plane_f<V, N2, PL, NT>(buf, spec, pitch, tid);
+    __syncthreads();
+    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
+    SKX_G R *out = gptr<R>(S.pr2[1 - par]) + pbase;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (pt[i] >= 0) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          out[pt[i] + R0 * r] = v[i][r].x;
+          out[pt[i] + N3 + R0 * r] = v[i][r].y;
+        }
+      }
+    return;
+  }
+
+  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
+  const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
+  R acc[MB][2][R1];
+  R ph[KEEP_PHI ? MB : 1][2][R1];
+  {
+    const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (pt[i] >= 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < R1; ++r) {
+            const int o = pt[i] + h * N3 + R0 * r;
+            const R p = phit[o];
+            acc[i][h][r] = (R)2 * p * v0[o];
+            if (KEEP_PHI) ph[KEEP_PHI ? i : 0][h][r] = p;
+          }
+      }
+  }
+  for (int fb = 0; fb < NFIELD; ++fb) {
+    const int sl = S.slot[fb];
+    if (sl < 0) continue;
+    R cf[MB][2][R1];
+    if (fb >= 2 || (fb == 1 && !KEEP_PHI)) {
+      const SKX_G R *src = fb == 1 ? phit : (fb == 2 ? cfp[2] : cfp[3]);
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+        if (pt[i] >= 0) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < R1; ++r) cf[i][h][r] = src[pt[i] + h * N3 + R0 * r];
+        }
+    }
+    __syncthreads();
+    load_plane_f<V, N2, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    __syncthreads();
+    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (pt[i] >= 0) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const R g0 = v[i][r].x, g1 = v[i][r].y;
+          if (fb == 0) {
+            acc[i][0][r] += g0;
+            acc[i][1][r] += g1;
+          } else if (fb == 1) {
+            const R p0 = KEEP_PHI ? ph[KEEP_PHI ? i : 0][0][r] : cf[i][0][r];
+            const R p1 = KEEP_PHI ? ph[KEEP_PHI ? i : 0][1][r] : cf[i][1][r];
+            acc[i][0][r] += (R)2 * p0 * g0;
+            acc[i][1][r] += (R)2 * p1 * g1;
+          } else {
+            acc[i][0][r] += cf[i][0][r] * g0;
+            acc[i][1][r] += cf[i][1][r] * g1;
+          }
+        }
+      }
+  }
+  double sphig = 0.0, bad = 0.0;
+  SKX_G R *grad = gptr<R>(S.grad) + pbase;
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+    if (pt[i] >= 0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int o = pt[i] + h * N3 + R0 * r;
+          const R g = acc[i][h][r];
+          const R p = KEEP_PHI ? ph[KEEP_PHI ? i : 0][h][r] : phit[o];
+          grad[o] = g;
+          sphig += (double)p * (double)g;
+          if (!(g == g)) bad += 1.0;
+        }
+    }
+  double vals[PART_C] = {sphig, bad};
+  double tot[PART_C];
+  __syncthreads();
+  block_reduce<PART_C>(vals, reinterpret_cast<double *>(smem), tid, NT, tot);
+  if (tid == 0)
+    for (int q = 0; q < PART_C; ++q) S.partC[plane * PART_C + q] = tot[q];
+}
+
+// ---------------------------------------------------------------------------
 // Launch
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -912,7 +1189,11 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
   if (b.gridB > 0 && (mask & 2))
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4)) {
+  if (b.gridC > 0 && (mask & 4) && b.shape == 64) {
+    hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
+                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       b.twbank);
+  } else if (b.gridC > 0 && (mask & 4)) {
     // In FP32 two 512-thread groups share a CU; when the last round of
     // those would be less than half full (e.g. 576 planes), 256-thread
     // groups spread the planes more evenly over the CUs.
@@ -945,7 +1226,11 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   if (b.gridB > 0 && (mask & 2))
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4))
+  if (b.gridC > 0 && (mask & 4) && b.shape == 64)
+    hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
+                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       b.twbank);
+  else if (b.gridC > 0 && (mask & 4))
     hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   return hipGetLastError();

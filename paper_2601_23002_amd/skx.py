@@ -111,6 +111,7 @@ _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double
 _sig("skx_profile_enable", C.c_int, [C.c_int])
 _sig("skx_set_graphs", C.c_int, [C.c_int])
 _sig("skx_set_autotune", C.c_int, [C.c_int])
+_sig("skx_set_shape_kernels", C.c_int, [C.c_int])
 _sig("skx_get_radix_order", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int])
 _sig("skx_profile_reset", C.c_int, [])
 _sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
@@ -308,6 +309,12 @@ def set_autotune(on=True):
     """Time candidate FFT radix orders at first set-up of each length and keep
     the fastest (process-wide); returns the previous setting."""
     return bool(_lib.skx_set_autotune(1 if on else 0))
+
+
+def set_shape_kernels(on=True):
+    """Use the compile-time-shaped plane kernels for batches whose planes all
+    have their shape (process-wide); returns the previous setting."""
+    return bool(_lib.skx_set_shape_kernels(1 if on else 0))
 
 
 def radix_order(n, precision=FP64):

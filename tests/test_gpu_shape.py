@@ -1,0 +1,98 @@
+"""The compile-time-shaped plane kernels (64 x 64 planes) against the oracle
+and against the runtime-shaped kernels.
+
+They fold the real DC and Nyquist columns of the inverse y transform into
+one complex transform, so they round differently from the runtime-shaped
+kernels; both must meet the oracle tolerances (FP64 1e-10 relative on every
+energy term, FP32 2e-5), and whole optimisations must reach the same
+minimum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_23002_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("f_tf", "e_vw", "f_nl0", "f_nl1", "e_h", "e_loc", "e_xc")
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2601_23002_amd import skx
+    return skx, torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _eval(skx, torch, s, phi, prec, shape):
+    old = skx.set_shape_kernels(shape)
+    try:
+        c = skx.Context(0).setup(s, precision=prec)
+        dt = torch.float32 if prec == skx.FP32 else torch.float64
+        e, g = c.evaluate(torch.tensor(phi, dtype=dt, device="cuda"), skx.SQRT_RHO)
+        return e, g.double().cpu().numpy()
+    finally:
+        skx.set_shape_kernels(old)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_shape64_evaluation_matches_oracle(precision):
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    prec = skx.FP64 if precision == "fp64" else skx.FP32
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    s = W.uniform_system(64, 1.0, 0.3, 2.0, 2.0, 64, seed=21, beta=1.3)
+    phi = W.random_phi(s, 22, amp=0.4)
+    _say(f"case: 64^3 evaluation, shape kernels, {precision}")
+    e_ref, g_ref = Problem(s).evaluate(phi)
+    scale = sum(abs(e_ref[k]) for k in TERMS)
+    for shape in (True, False):
+        e, g = _eval(skx, torch, s, phi, prec, shape)
+        for k in TERMS:
+            assert abs(e[k] - e_ref[k]) <= tol * max(abs(e_ref[k]), 1e-3 * scale), (shape, k)
+        assert abs(e["mu"] - e_ref["mu"]) <= tol * max(1.0, abs(e_ref["mu"])) * 10, shape
+        assert np.max(np.abs(g - g_ref)) <= tol * np.max(np.abs(g_ref)) * 10, shape
+
+
+def test_shape64_sampled_gradient_points():
+    """Every point class of the register-resident assembly (each lane's two
+    rows and R1 z offsets, every wavefront's row pairs) on one plane: the
+    FP64 gradient of the shape kernel equals the runtime-shaped kernel's to
+    rounding on all 64 x 64 points of several planes."""
+    skx, torch = _lib()
+    s = W.uniform_system(64, 1.0, 0.3, 1.0, 0.5, 64, seed=23)
+    phi = W.random_phi(s, 24, amp=0.5)
+    _say("case: 64^3 shape vs runtime kernels, all points")
+    _, g1 = _eval(skx, torch, s, phi, skx.FP64, True)
+    _, g0 = _eval(skx, torch, s, phi, skx.FP64, False)
+    scale = np.max(np.abs(g0))
+    assert np.max(np.abs(g1 - g0)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shape64_optimisation_reaches_same_minimum(precision):
+    skx, torch = _lib()
+    prec = skx.FP64 if precision == "fp64" else skx.MIXED
+    s = W.uniform_system(64, 1.0, 0.3, 2.0, 2.0, 64, seed=25)
+    out = {}
+    for shape in (True, False):
+        _say(f"case: 64^3 optimise {precision}, shape kernels {shape}")
+        old = skx.set_shape_kernels(shape)
+        try:
+            c = skx.Context(0).setup(s, precision=prec)
+            rho, res = c.optimize(gtol=1e-8)
+        finally:
+            skx.set_shape_kernels(old)
+        assert res["status"] == 0, res
+        out[shape] = (res["energy"]["free_energy"], rho.cpu().numpy())
+    (e1, r1), (e0, r0) = out[True], out[False]
+    assert abs(e1 - e0) / 64 <= 1e-9              # far inside 1e-6 Ha/atom
+    assert np.max(np.abs(r1 - r0)) <= 1e-5 * np.max(np.abs(r0))
