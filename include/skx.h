@@ -206,13 +206,15 @@ int skx_set_graphs(int on);
  * reproducible bit for bit only with the same choices. Returns the previous
  * setting. */
 int skx_set_autotune(int on);
-/* Process-wide choice of the compile-time-shaped plane kernels (on by
- * default). When on, a batch whose planes all have the shape of such a
- * kernel (64 x 64) runs it in place of the runtime-shaped one; it folds the
- * real DC and Nyquist columns into one complex transform, so results differ
- * from the runtime-shaped kernels by rounding only. Applies to batches built
- * after the call. Returns the previous setting. */
-int skx_set_shape_kernels(int on);
+/* Process-wide choice of the compile-time-shaped pass kernels, a bit mask
+ * of the passes that use them: 1 pass A, 2 pass B, 4 pass C (default 7,
+ * all). A batch whose solves all have a 64 x 64 x 64 grid runs the selected
+ * passes with kernels built for that shape in place of the runtime-shaped
+ * ones; passes A and C fold the real DC and Nyquist columns of each plane
+ * into one complex y transform, so results differ from the runtime-shaped
+ * kernels by rounding only. Applies to batches built after the call.
+ * Returns the previous mask. */
+int skx_set_shape_kernels(int mask);
 
 /* Radix order in use for length n in `precision` (SKX_FP64 / SKX_FP32):
  * writes up to max radices, returns their count or SKX_E_INVALID. */

@@ -115,7 +115,7 @@ std::vector<std::vector<int>> radix_candidates(int n) {
 // Radix order chosen by the autotuner per precision and length (empty: default).
 std::vector<int> g_tuned[2][513];
 bool g_autotune = false;
-bool g_shape_kernels = true;
+int g_shape_kernels = 7;
 
 Plan make_plan_from(int n, int twoff, const std::vector<int> &rads) {
   Plan p{};
@@ -371,9 +371,9 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
   bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
   bl.mh = 1;
   for (const SolveDev &h : hs) bl.mh = std::max(bl.mh, std::min(h.mh, MMAX));
-  bl.shape = g_shape_kernels ? 64 : 0;
+  bl.shape = g_shape_kernels;
   for (const SolveDev &h : hs)
-    if (h.n2 != 64 || h.n3 != 64 || h.debug) bl.shape = 0;
+    if (h.n1 != 64 || h.n2 != 64 || h.n3 != 64 || h.debug) bl.shape = 0;
   return SKX_OK;
 }
 
@@ -1331,9 +1331,9 @@ int skx_set_autotune(int on) {
   return old;
 }
 
-int skx_set_shape_kernels(int on) {
-  const int old = g_shape_kernels ? 1 : 0;
-  g_shape_kernels = on != 0;
+int skx_set_shape_kernels(int mask) {
+  const int old = g_shape_kernels;
+  g_shape_kernels = mask & 7;
   return old;
 }
 

@@ -122,8 +122,8 @@ struct BatchLaunch {
   size_t ldsA, ldsB, ldsC;
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int mh;                          // largest history length of the batch (1..MMAX)
-  int shape;                       // N when every plane is N x N with a compile-time
-                                   // kernel for it (64), else 0 (runtime-shaped kernels)
+  int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
+                                   // 64 x 64 x 64 grids (every solve has that grid)
 };
 hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);  // passes A|B|C
 hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s);

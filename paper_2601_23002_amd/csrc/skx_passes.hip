@@ -915,6 +915,393 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 }
 
 // ---------------------------------------------------------------------------
+// Pass A on planes of a shape fixed at compile time (N2 x N3), one workgroup
+// of four wavefronts per (x-plane, field) (MODE_PREC: per x-plane, the
+// residual field). Every wavefront takes N2/8 row pairs: its first z stage
+// reads x_{2p} + i x_{2p+1} straight from the pointwise arrays, the last
+// one leaves the row pair's spectrum in LDS, which is then split into the
+// two half spectra with the real DC and Nyquist values of each row folded
+// into its column 0. After a barrier every wavefront takes N3/8 of the N3/2
+// columns for the y transform, whose outputs go from registers to HBM; the
+// folded column is unfolded into the DC and Nyquist columns on the way.
+// ---------------------------------------------------------------------------
+template <typename R, int N2, int N3, int MODE>
+__global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first, int nsolve,
+                                                int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  constexpr int NT = 256, NW = 4;
+  constexpr int C = N3 / 2, PL = C + 1, YC = C / NW, ZP = N2 / 2 / NW;
+  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
+  constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
+  static_assert(Y0 * Y1 == N2 && R0 * R1 == N3 && R0 % 2 == 0, "two stages per direction");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int local = item - first_of(first, s);
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const int plane = local / nf;
+  const int fb = MODE == MODE_EVAL ? nth_field(S.fields, local - plane * nf) : 0;
+  V *buf = reinterpret_cast<V *>(smem);
+  V *tw2 = buf + N2 * PL;
+  V *tw3 = tw2 + N2;
+  load_twiddles(tw2, twbank, S.p2.tw, N2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, N3, tid, NT);
+  __syncthreads();
+  const R invM = (R)(1.0 / (double)S.M);
+  const size_t pbase = (size_t)plane * N2 * N3;
+  V *zb = buf + wave * ZP * 2 * PL;
+  {
+    // first z stage, inputs from HBM: element e = j + NB r of pair p
+    typedef CMap<N3, R0, ZP, false> M;
+    V v[M::MB][R0];
+    const SKX_G R *pt = gptr<R>(S.phi2[1 - par]) + pbase;
+    const SKX_G R *fa = gptr<R>(S.npa) + pbase;
+    const SKX_G R *gr = gptr<R>(S.grad) + pbase;
+    SKX_G R *rt = gptr<R>(S.r2[1 - par]) + pbase;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a;
+    const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
+    const bool need_p = fb != 2, need_fa = fb >= 2;
+#pragma unroll
+    for (int i = 0; i < M::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (M::ok(b)) {
+        const int o = 2 * (wave * ZP + M::t(b)) * N3 + M::j(b);
+        R x[2][R0];
+        if (MODE == MODE_EVAL) {
+          R pv[2][R0], fv[2][R0];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const int q = o + h * N3 + M::NB * r;
+              if (need_p) pv[h][r] = pt[q];
+              if (need_fa) fv[h][r] = fa[q];
+            }
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const R p = need_p ? pv[h][r] : (R)0, f = need_fa ? fv[h][r] : (R)0;
+              x[h][r] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
+            }
+        } else {
+          R gv[2][R0], pv[2][R0];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const int q = o + h * N3 + M::NB * r;
+              gv[h][r] = gr[q];
+              pv[h][r] = pt[q];
+            }
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              x[h][r] = gv[h][r] - mu2 * pv[h][r];
+              rt[o + h * N3 + M::NB * r] = x[h][r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          v[i][r].x = x[0][r] * invM;
+          v[i][r].y = x[1][r] * invM;
+        }
+        Bfly<R0, false, V>::run(v[i]);
+        V *out = zb + 2 * M::t(b) * PL + M::j(b) * R0;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) out[r] = v[i][r];
+      }
+    }
+    SKX_WAVE_SYNC();
+  }
+  cstage<V, N3, R1, R0, 1, 2 * PL, ZP, false, false>(zb, tw3, lane);
+  {
+    // split X_k of the pair into the rows' half spectra; column 0 of each
+    // row takes (DC, Nyquist), both real
+    constexpr int TOT = ZP * C, NU = (TOT + 63) / 64;
+    V A[NU], B[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = lane + 64 * u;
+      if (TOT % 64 == 0 || e < TOT) {
+        const int p = e / C, k = e % C;
+        const V *row = zb + 2 * p * PL;
+        const V X = row[k];
+        const V Xm = row[k == 0 ? C : N3 - k];
+        if (k == 0) {
+          A[u].x = X.x; A[u].y = Xm.x;
+          B[u].x = X.y; B[u].y = Xm.y;
+        } else {
+          A[u].x = (R)0.5 * (X.x + Xm.x); A[u].y = (R)0.5 * (X.y - Xm.y);
+          B[u].x = (R)0.5 * (X.y + Xm.y); B[u].y = (R)-0.5 * (X.x - Xm.x);
+        }
+      }
+    }
+    SKX_WAVE_SYNC();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = lane + 64 * u;
+      if (TOT % 64 == 0 || e < TOT) {
+        const int p = e / C, k = e % C;
+        zb[2 * p * PL + k] = A[u];
+        zb[(2 * p + 1) * PL + k] = B[u];
+      }
+    }
+  }
+  __syncthreads();
+  SKX_G V *spec = gptr<V>(S.spec) + (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H +
+                  (size_t)plane * N2 * S.pitch;
+  const int pitch = S.pitch;
+  V *cb = buf + wave * YC;
+  cstage<V, N2, Y0, 1, PL, 1, YC, true, false>(cb, tw2, lane);
+  {
+    typedef CMap<N2, Y1, YC, true> M;
+#pragma unroll
+    for (int i = 0; i < M::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (M::ok(b)) {
+        const int t = M::t(b), j = M::j(b);
+        V v[Y1];
+#pragma unroll
+        for (int r = 0; r < Y1; ++r) v[r] = cb[t + (j + M::NB * r) * PL];
+        cbfly<V, N2, Y1, Y0, false>(v, j, tw2);
+        const int col = wave * YC + t;
+        if (col != 0) {
+#pragma unroll
+          for (int r = 0; r < Y1; ++r) stg(spec + (size_t)(j + Y0 * r) * pitch + col, v[r]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < Y1; ++r) buf[(j + Y0 * r) * PL] = v[r];
+        }
+      }
+    }
+  }
+  if (wave == 0) {
+    // unfold column 0: Z = F_DC + i F_Nyq of two real columns
+    SKX_WAVE_SYNC();
+    constexpr int NY = (N2 + 63) / 64;
+#pragma unroll
+    for (int u = 0; u < NY; ++u) {
+      const int y = lane + 64 * u;
+      if (y < N2) {
+        const V Z = buf[y * PL], Zm = buf[((N2 - y) % N2) * PL];
+        V F0, Fn;
+        F0.x = (R)0.5 * (Z.x + Zm.x); F0.y = (R)0.5 * (Z.y - Zm.y);
+        Fn.x = (R)0.5 * (Z.y + Zm.y); Fn.y = (R)-0.5 * (Z.x - Zm.x);
+        stg(spec + (size_t)y * pitch, F0);
+        stg(spec + (size_t)y * pitch + C, Fn);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B for x-transforms of a length fixed at compile time (N1), one
+// workgroup of four wavefronts per (y index, block of TK z columns). In
+// MODE_EVAL wavefront w owns the x transforms of field slot w (all TK
+// columns); in MODE_PREC the one field's columns are split over the four.
+// The first forward stage reads its inputs from HBM, the last inverse stage
+// writes its outputs there from registers; between the two directions the
+// multipliers and energy terms of every G point run over the LDS tiles.
+// ---------------------------------------------------------------------------
+template <typename R, int N1, int TK, int MODE>
+__global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first, int nsolve,
+                                                int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  constexpr int NT = 256, NW = 4;
+  constexpr int X0 = CRad<N1>::R0, X1 = CRad<N1>::R1;
+  static_assert(X0 * X1 == N1, "two x stages");
+  constexpr int TP = TK + 1;                       // LDS row pitch of a field tile
+  constexpr int SL = MODE == MODE_EVAL ? TK : TK / NW;   // columns per wavefront
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE>(st->phase)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int local = item - first_of(first, s);
+  const int jy = local / S.nkb, kb = local % S.nkb;
+  const int k0 = kb * TK;
+  const int tkv = min(TK, S.nh - k0);
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N1][TP]
+  V *tw1 = tile + NFIELD * N1 * TP;
+  load_twiddles(tw1, twbank, S.p1.tw, N1, tid, NT);
+  __syncthreads();
+  SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + k0;
+  const size_t rowstride = (size_t)S.n2 * S.pitch;
+  const int cc = MODE == MODE_EVAL ? wave : 0;       // field slot of this wavefront
+  const int c0 = MODE == MODE_EVAL ? 0 : wave * SL;  // its first column
+  const bool active = cc < nf;
+  V *tf = tile + cc * N1 * TP + c0;
+  SKX_G V *sf = spec + (size_t)cc * S.H + c0;
+  const int cv = tkv - c0;                           // valid columns from c0
+  if (active) {
+    typedef CMap<N1, X0, SL, true> M;
+    V v[M::MB][X0];
+#pragma unroll
+    for (int i = 0; i < M::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (M::ok(b)) {
+        const int t = M::t(b), jj = M::j(b);
+#pragma unroll
+        for (int r = 0; r < X0; ++r) {
+          if (t < cv) v[i][r] = ldg(sf + (size_t)(jj + M::NB * r) * rowstride + t);
+          else { v[i][r].x = 0; v[i][r].y = 0; }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (M::ok(b)) {
+        const int t = M::t(b), jj = M::j(b);
+        Bfly<X0, false, V>::run(v[i]);
+#pragma unroll
+        for (int r = 0; r < X0; ++r) tf[(jj * X0 + r) * TP + t] = v[i][r];
+      }
+    }
+    SKX_WAVE_SYNC();
+    cstage<V, N1, X1, X0, TP, 1, SL, true, false>(tf, tw1, lane);
+  }
+  __syncthreads();
+  const double kscale = S.kscale;
+  const int g2 = gidx(jy, S.n2);
+  double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
+  constexpr int NP = (N1 * TK + NT - 1) / NT;
+  if (MODE == MODE_PREC) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = tid + u * NT;
+      const int kx = e / TK, col = e % TK;
+      if ((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv) {
+        const int k3 = k0 + col, g1 = gidx(kx, N1);
+        const double G2 = kscale * (double)(g1 * g1 + g2 * g2 + k3 * k3);
+        const R pg = (R)(1.0 / (G2 + S.kappa));
+        V x = tile[kx * TP + col];
+        x.x *= pg; x.y *= pg;
+        tile[kx * TP + col] = x;
+      }
+    }
+  } else {
+    const unsigned terms = S.terms;
+    const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
+    const bool do_h = terms & 16u, do_loc = terms & 32u;
+    const int sphi = S.slot[0], sn = S.slot[1], sfl = S.slot[2], sh = S.slot[3];
+    const SKX_G V *vloc = gptr<V>(S.vloc);
+    const R b3 = (R)(S.beta / 3.0);
+    const double FOURPI = 12.566370614359172954;
+    const SKX_G double *wt = gptr<double>(S.w);
+    const SKX_G double *wpt = gptr<double>(S.wp);
+    V vlb[NP];
+    double wb[NP], wpb[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = tid + u * NT;
+      const int kx = e / TK, col = e % TK;
+      if ((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv) {
+        const int k3 = k0 + col, g1 = gidx(kx, N1);
+        const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+        if (do_loc) vlb[u] = ldg(vloc + ((size_t)kx * S.n2 + jy) * S.pitch + k3);
+        if (sfl >= 0) { wb[u] = wt[sidx]; wpb[u] = wpt[sidx]; }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = tid + u * NT;
+      const int kx = e / TK, col = e % TK;
+      if (!((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv)) continue;
+      const int k3 = k0 + col, g1 = gidx(kx, N1);
+      const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+      const double G2 = kscale * (double)sidx;
+      const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
+      V *pt = tile + kx * TP + col;                  // field slot c at pt[c N1 TP]
+      if (sphi >= 0) {
+        V x = pt[sphi * N1 * TP];
+        if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
+        const R g2r = (R)G2;
+        x.x *= g2r; x.y *= g2r;
+        pt[sphi * N1 * TP] = x;
+      }
+      {
+        const V x = pt[sn * N1 * TP];
+        double bx = 0.0, by = 0.0;
+        if (do_h && sidx > 0) {
+          const double m2 = (double)x.x * x.x + (double)x.y * x.y;
+          eh += wgt * m2 / G2;
+          bx = FOURPI * x.x / G2;
+          by = FOURPI * x.y / G2;
+        }
+        if (do_loc) {
+          const V vl = vlb[u];
+          eloc += wgt * ((double)x.x * vl.x + (double)x.y * vl.y);
+          bx += vl.x;
+          by += vl.y;
+        }
+        if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
+        V o; o.x = (R)bx; o.y = (R)by;
+        pt[sn * N1 * TP] = o;
+      }
+      if (sfl >= 0) {
+        const V f = pt[sfl * N1 * TP];
+        const R w = (R)wb[u];
+        const R wp = (R)wpb[u];
+        V P; P.x = 0; P.y = 0;
+        if (do_nl0) {
+          ef0 += wgt * (double)w * ((double)f.x * f.x + (double)f.y * f.y);
+          P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
+        }
+        if (sh >= 0) {
+          const V h = pt[sh * N1 * TP];
+          ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
+          P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
+          V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
+          pt[sh * N1 * TP] = Q;
+        }
+        pt[sfl * N1 * TP] = P;
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    cstage<V, N1, X0, 1, TP, 1, SL, true, true>(tf, tw1, lane);
+    typedef CMap<N1, X1, SL, true> M;
+#pragma unroll
+    for (int i = 0; i < M::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (M::ok(b)) {
+        const int t = M::t(b), jj = M::j(b);
+        V v[X1];
+#pragma unroll
+        for (int r = 0; r < X1; ++r) v[r] = tf[(jj + M::NB * r) * TP + t];
+        cbfly<V, N1, X1, X0, true>(v, jj, tw1);
+        if (t < cv) {
+#pragma unroll
+          for (int r = 0; r < X1; ++r) stg(sf + (size_t)(jj + X0 * r) * rowstride + t, v[r]);
+        }
+      }
+    }
+  }
+  if (MODE == MODE_EVAL) {
+    double vals[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
+    double tot[PART_B];
+    __syncthreads();
+    block_reduce<PART_B>(vals, reinterpret_cast<double *>(smem), tid, NT, tot);
+    if (tid == 0)
+      for (int q = 0; q < PART_B; ++q) S.partB[local * PART_B + q] = tot[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pass C on planes of a shape fixed at compile time (N2 x N3, radix orders
 // from CRad), one workgroup of four wavefronts per x-plane, every index a
 // constant. Per field:
@@ -1183,13 +1570,22 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
   if (b.gridA > 0 && (mask & 1)) {
     hipLaunchKernelGGL((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
                        b.firstV, b.nsolve, b.gridV, b.fd);
-    hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
-                       b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
+    if (b.shape & 1)
+      hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
+                         (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
+                         b.twbank);
+    else
+      hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
+                         b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
   }
-  if (b.gridB > 0 && (mask & 2))
+  if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
+    hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_EVAL>), dim3(b.gridB), dim3(256),
+                       (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
+                       b.nsolve, b.gridB, b.twbank);
+  else if (b.gridB > 0 && (mask & 2))
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4) && b.shape == 64) {
+  if (b.gridC > 0 && (mask & 4) && (b.shape & 4)) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
                        (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
@@ -1220,13 +1616,21 @@ template <typename R>
 static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   // one field per solve: pass A has one workgroup per plane, like pass C
-  if (b.gridC > 0 && (mask & 1))
+  if (b.gridC > 0 && (mask & 1) && (b.shape & 1))
+    hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
+                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       b.twbank);
+  else if (b.gridC > 0 && (mask & 1))
     hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  if (b.gridB > 0 && (mask & 2))
+  if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
+    hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(b.gridB), dim3(256),
+                       (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
+                       b.nsolve, b.gridB, b.twbank);
+  else if (b.gridB > 0 && (mask & 2))
     hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4) && b.shape == 64)
+  if (b.gridC > 0 && (mask & 4) && (b.shape & 4))
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);

@@ -311,10 +311,15 @@ def set_autotune(on=True):
     return bool(_lib.skx_set_autotune(1 if on else 0))
 
 
-def set_shape_kernels(on=True):
-    """Use the compile-time-shaped plane kernels for batches whose planes all
-    have their shape (process-wide); returns the previous setting."""
-    return bool(_lib.skx_set_shape_kernels(1 if on else 0))
+def set_shape_kernels(mask=7):
+    """Passes (bit mask: 1 A, 2 B, 4 C; True = all, False = none) that run
+    their compile-time-shaped kernels on batches of 64^3 grids
+    (process-wide); returns the previous mask."""
+    if mask is True:
+        mask = 7
+    elif mask is False:
+        mask = 0
+    return _lib.skx_set_shape_kernels(int(mask))
 
 
 def radix_order(n, precision=FP64):

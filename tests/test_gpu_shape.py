@@ -1,8 +1,8 @@
-"""The compile-time-shaped plane kernels (64 x 64 planes) against the oracle
-and against the runtime-shaped kernels.
+"""The compile-time-shaped pass kernels (64^3 grids) against the oracle and
+against the runtime-shaped kernels.
 
-They fold the real DC and Nyquist columns of the inverse y transform into
-one complex transform, so they round differently from the runtime-shaped
+Passes A and C fold the real DC and Nyquist columns of each plane into one
+complex y transform, so they round differently from the runtime-shaped
 kernels; both must meet the oracle tolerances (FP64 1e-10 relative on every
 energy term, FP32 2e-5), and whole optimisations must reach the same
 minimum.
@@ -54,7 +54,7 @@ def test_shape64_evaluation_matches_oracle(precision):
     _say(f"case: 64^3 evaluation, shape kernels, {precision}")
     e_ref, g_ref = Problem(s).evaluate(phi)
     scale = sum(abs(e_ref[k]) for k in TERMS)
-    for shape in (True, False):
+    for shape in (7, 1, 2, 4, 0):                 # all, each pass alone, none
         e, g = _eval(skx, torch, s, phi, prec, shape)
         for k in TERMS:
             assert abs(e[k] - e_ref[k]) <= tol * max(abs(e_ref[k]), 1e-3 * scale), (shape, k)
