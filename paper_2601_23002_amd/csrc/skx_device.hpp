@@ -456,6 +456,11 @@ __device__ __forceinline__ void cstages(V *buf, const V *tw, int lane) {
 template <int N> struct CRad;
 template <> struct CRad<64> {
   static constexpr int R0 = 8, R1 = 8;
+  // LDS row pitch (complex values) of a 64-column half-spectrum plane: 36
+  // spreads both the column transforms (8 adjacent columns of 8 rows) and
+  // the row-pair transforms (8 adjacent elements of 8 pairs) evenly over
+  // the LDS banks in FP32 and FP64.
+  static constexpr int PL = 36;
 };
 
 // ---------------------------------------------------------------------------

@@ -27,27 +27,31 @@
 
 namespace skx {
 
-template <int N>
-__device__ void sum_parts(const double *part, int nrow, double *sh, int tid, int nthr,
-                          double *out) {
-  double v[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = 0.0;
-  for (int r = tid; r < nrow; r += nthr)
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] += part[r * N + q];
-  block_reduce<N>(v, sh, tid, nthr, out);
-}
 
 // The control state of one solve is staged in LDS for the serial part of
 // each finalize kernel, so that thread 0 works at LDS latency instead of a
-// chain of dependent global-memory round trips; every thread copies a slice
-// in and out.
-__device__ __forceinline__ void stage_state(OptState *dst, const OptState *src, int tid) {
-  static_assert(sizeof(OptState) % 8 == 0, "OptState is copied as doubles");
-  const double *a = reinterpret_cast<const double *>(src);
-  double *b = reinterpret_cast<double *>(dst);
-  for (int i = tid; i < (int)(sizeof(OptState) / 8); i += 256) b[i] = a[i];
+// chain of dependent global-memory round trips; every thread copies one
+// slice in and out (the state is at most 256 doubles), its load in flight
+// together with the kernel's partial-sum loads.
+static_assert(sizeof(OptState) % 8 == 0, "OptState is copied as doubles");
+constexpr int NSTATE = (int)(sizeof(OptState) / 8);
+static_assert(NSTATE <= 256, "one state slice per thread");
+__device__ __forceinline__ double state_slice(const OptState *src, int tid) {
+  return tid < NSTATE ? reinterpret_cast<const double *>(src)[tid] : 0.0;
+}
+__device__ __forceinline__ void put_slice(OptState *dst, int tid, double v) {
+  if (tid < NSTATE) reinterpret_cast<double *>(dst)[tid] = v;
+}
+
+// Per-thread sums of the partial rows r = tid, tid + 256, ... (N values per
+// row); the workgroup sum follows in block_reduce.
+template <int N, int OFF, int TOT>
+__device__ __forceinline__ void row_sums(const double *part, int nrow, int tid, double (&v)[TOT]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[OFF + q] = 0.0;
+  for (int r = tid; r < nrow; r += 256)
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[OFF + q] += part[r * N + q];
 }
 
 // Direction d = -P r + kappa' phi (history dropped).
@@ -63,7 +67,7 @@ __device__ void set_steepest(OptState *st, double ne) {
 // ---------------------------------------------------------------------------
 // Close an evaluation: energies, mu, and the line-search decision.
 // ---------------------------------------------------------------------------
-__device__ void finalize_eval_body(OptState *st, const SolveDev &S, const double *tA,
+__device__ void finalize_eval_body(OptState *st, const SKX_C SolveDev &S, const double *tA,
                                    const double *tB, const double *tC, int ph) {
   const double PI = 3.14159265358979323846;
   double e[12];
@@ -123,24 +127,27 @@ __device__ void finalize_eval_body(OptState *st, const SolveDev &S, const double
 }
 
 __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve) {
-  __shared__ double sh[4 * 16];
-  __shared__ double tA[PART_A], tB[PART_B], tC[PART_C];
+  constexpr int NP = PART_A + PART_B + PART_C;
+  __shared__ double sh[4 * NP];
+  __shared__ double t[NP];
+  __shared__ OptState lst;
   const int s = blockIdx.x;
   if (s >= nsolve) return;
-  SolveDev &S = dev[s];
+  const SKX_C SolveDev &S = *cptr<SolveDev>(dev + s);
   OptState *st = S.st;
-  const int ph = st->phase;
+  const int ph = cptr<OptState>(st)->phase;
   if (!(ph == PH_EVAL_INIT || ph == PH_TRIAL || ph == PH_EVAL_ONLY)) return;
   const int tid = threadIdx.x;
-  sum_parts<PART_A>(S.partA, S.nwg_vec, sh, tid, 256, tA);
-  sum_parts<PART_B>(S.partB, S.n2 * S.nkb, sh, tid, 256, tB);
-  sum_parts<PART_C>(S.partC, S.n1, sh, tid, 256, tC);
-  __shared__ OptState lst;
-  stage_state(&lst, st, threadIdx.x);
+  const double sv = state_slice(st, tid);
+  double v[NP];
+  row_sums<PART_A, 0>(S.partA, S.nwg_vec, tid, v);
+  row_sums<PART_B, PART_A>(S.partB, S.n2 * S.nkb, tid, v);
+  row_sums<PART_C, PART_A + PART_B>(S.partC, S.n1, tid, v);
+  put_slice(&lst, tid, sv);
+  block_reduce<NP>(v, sh, tid, 256, t);
+  if (tid == 0) finalize_eval_body(&lst, S, t, t + PART_A, t + PART_A + PART_B, ph);
   __syncthreads();
-  if (threadIdx.x == 0) finalize_eval_body(&lst, S, tA, tB, tC, ph);
-  __syncthreads();
-  stage_state(st, &lst, threadIdx.x);
+  put_slice(st, tid, tid < NSTATE ? reinterpret_cast<const double *>(&lst)[tid] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,60 +252,99 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   }
 }
 
-__device__ void finalize_update_body(OptState *st, const SolveDev &S, double *t) {
-  const double dV = S.dV;
+// t holds the NDOT sums of the update pass, already scaled by dV; the
+// caller has copied e_trial to e_acc. The history blocks and vectors are
+// worked on as register copies whose every index is fixed at compile time
+// (loops to MM, the batch's largest history length, with guards), so no
+// step waits on a chain of LDS loads.
+template <int MM>
+__device__ void finalize_update_body(OptState *st, const SKX_C SolveDev &S, const double *t) {
   const int B = 6 * MMAX;
   const int m = st->m;
-  for (int q = 0; q < NDOT; ++q) t[q] *= dV;
   st->E = st->Et;
   st->mu = st->mut;
-  for (int q = 0; q < 12; ++q) st->e_acc[q] = st->e_trial[q];
   st->par = 1 - st->par;            // the trial point becomes the current point
   st->rr = t[B + 6];
   st->rPr = t[B + 7];
   st->phiPr = t[B + 8];
   st->rphi = t[B + 9];
+  // upper triangles only (SY is used there, YPY is symmetric); the
+  // vectors are refilled from t below the history length
+  double SY[MM][MM], YPY[MM][MM], Sr[MM], YPr[MM], Sphi[MM], PYphi[MM];
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    Sr[i] = 0.0;
+    YPr[i] = 0.0;
+    Sphi[i] = 0.0;
+    PYphi[i] = 0.0;
+#pragma unroll
+    for (int j = i; j < MM; ++j) {
+      SY[i][j] = st->SY[i][j];
+      YPY[i][j] = st->YPY[i][j];
+    }
+  }
+  int k = st->k;
   if (st->reset_pending == 1) {
     st->reset_pending = 0;
     set_steepest(st, S.ne);
+    k = 0;
   } else {
     st->iters += 1;
-    int k = st->k;
     if (k == m) {
       // the oldest pair's memory now holds the new pair: drop it
-      for (int i = 0; i + 1 < k; ++i)
-        for (int j = 0; j + 1 < k; ++j) {
-          st->SY[i][j] = st->SY[i + 1][j + 1];
-          st->YPY[i][j] = st->YPY[i + 1][j + 1];
+#pragma unroll
+      for (int i = 0; i + 1 < MM; ++i)
+#pragma unroll
+        for (int j = i; j + 1 < MM; ++j) {
+          SY[i][j] = SY[i + 1][j + 1];
+          YPY[i][j] = YPY[i + 1][j + 1];
         }
       k = m - 1;
     }
-    for (int i = 0; i < k; ++i) {
-      st->Sr[i] = t[2 * MMAX + i];
-      st->YPr[i] = t[3 * MMAX + i];
-      st->Sphi[i] = t[4 * MMAX + i];
-      st->PYphi[i] = t[5 * MMAX + i];
-    }
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+      if (i < k) {
+        Sr[i] = t[2 * MMAX + i];
+        YPr[i] = t[3 * MMAX + i];
+        Sphi[i] = t[4 * MMAX + i];
+        PYphi[i] = t[5 * MMAX + i];
+      }
     const double sy = t[B + 0], ypy = t[B + 1];
     const bool ok = (sy > 0.0) && (ypy > 0.0) && (sy == sy) && (ypy == ypy);
     if (ok) {
-      for (int i = 0; i < k; ++i) {
-        st->SY[i][k] = t[i];
-        st->SY[k][i] = 0.0;            // only the upper triangle is used
-        st->YPY[i][k] = t[MMAX + i];
-        st->YPY[k][i] = t[MMAX + i];
-      }
-      st->SY[k][k] = sy;
-      st->YPY[k][k] = ypy;
-      st->Sr[k] = t[B + 2];
-      st->YPr[k] = t[B + 3];
-      st->Sphi[k] = t[B + 4];
-      st->PYphi[k] = t[B + 5];
+#pragma unroll
+      for (int c = 0; c < MM; ++c)
+        if (c == k) {
+#pragma unroll
+          for (int i = 0; i < MM; ++i)
+            if (i < c) {
+              SY[i][c] = t[i];
+              YPY[i][c] = t[MMAX + i];
+            }
+          SY[c][c] = sy;
+          YPY[c][c] = ypy;
+          Sr[c] = t[B + 2];
+          YPr[c] = t[B + 3];
+          Sphi[c] = t[B + 4];
+          PYphi[c] = t[B + 5];
+        }
       k += 1;
       st->head = (st->head + 1) % m;
     }
     st->k = k;
     st->pair_ok = ok ? 1 : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    st->Sr[i] = Sr[i];
+    st->YPr[i] = YPr[i];
+    st->Sphi[i] = Sphi[i];
+    st->PYphi[i] = PYphi[i];
+#pragma unroll
+    for (int j = i; j < MM; ++j) {
+      st->SY[i][j] = SY[i][j];
+      st->YPY[i][j] = YPY[i][j];
+    }
   }
   st->rnorm = sqrt(fmax(st->rr, 0.0));
   if (!(st->rnorm == st->rnorm)) { st->phase = PH_FAILED; st->status = -5; return; }
@@ -310,35 +356,47 @@ __device__ void finalize_update_body(OptState *st, const SolveDev &S, double *t)
     else if (++st->stall >= st->stall_limit) { st->phase = PH_DONE; st->status = 2; return; }
   }
   // compact L-BFGS coefficients, H0 = gamma P
-  const int k = st->k;
   if (k == 0) {
     set_steepest(st, S.ne);
     st->phase = PH_NEED_DIR;
     return;
   }
-  const double gamma = st->SY[k - 1][k - 1] / st->YPY[k - 1][k - 1];
-  double p[MMAX], z[MMAX], a[MMAX];
-  for (int i = k - 1; i >= 0; --i) {
-    double v = st->Sr[i];
-    for (int j = i + 1; j < k; ++j) v -= st->SY[i][j] * p[j];
-    p[i] = v / st->SY[i][i];
+  double gamma = 1.0;
+#pragma unroll
+  for (int c = 0; c < MM; ++c)
+    if (c == k - 1) gamma = SY[c][c] / YPY[c][c];
+  double p[MM], z[MM], a[MM];
+#pragma unroll
+  for (int i = MM - 1; i >= 0; --i) {
+    double v = Sr[i];
+#pragma unroll
+    for (int j = i + 1; j < MM; ++j)
+      if (j < k) v -= SY[i][j] * p[j];
+    p[i] = i < k ? v / SY[i][i] : 0.0;
   }
-  for (int i = 0; i < k; ++i) {
-    double v = st->SY[i][i] * p[i] - gamma * st->YPr[i];
-    for (int j = 0; j < k; ++j) v += gamma * st->YPY[i][j] * p[j];
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    double v = SY[i][i] * p[i] - gamma * YPr[i];
+#pragma unroll
+    for (int j = 0; j < MM; ++j)
+      if (j < k) v += gamma * (i <= j ? YPY[i][j] : YPY[j][i]) * p[j];
     z[i] = v;
   }
-  for (int i = 0; i < k; ++i) {
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
     double v = z[i];
-    for (int j = 0; j < i; ++j) v -= st->SY[j][i] * a[j];
-    a[i] = v / st->SY[i][i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) v -= SY[j][i] * a[j];
+    a[i] = i < k ? v / SY[i][i] : 0.0;
   }
   double dphi = -gamma * st->phiPr;
   double rd = -gamma * st->rPr;
-  for (int i = 0; i < k; ++i) {
-    dphi += -a[i] * st->Sphi[i] + gamma * p[i] * st->PYphi[i];
-    rd += -a[i] * st->Sr[i] + gamma * p[i] * st->YPr[i];
-  }
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < k) {
+      dphi += -a[i] * Sphi[i] + gamma * p[i] * PYphi[i];
+      rd += -a[i] * Sr[i] + gamma * p[i] * YPr[i];
+    }
   const double kap = -dphi / S.ne;
   rd += kap * st->rphi;
   if (!(rd < 0.0)) {
@@ -347,39 +405,40 @@ __device__ void finalize_update_body(OptState *st, const SolveDev &S, double *t)
   } else {
     st->gamma = gamma;
     st->cr = -gamma;
+#pragma unroll
     for (int i = 0; i < MMAX; ++i) {
-      st->cS[i] = (i < k) ? -a[i] : 0.0;
-      st->cY[i] = (i < k) ? gamma * p[i] : 0.0;
+      st->cS[i] = (i < k && i < MM) ? -a[i < MM ? i : 0] : 0.0;
+      st->cY[i] = (i < k && i < MM) ? gamma * p[i < MM ? i : 0] : 0.0;
     }
     st->cphi = kap;
   }
   st->phase = PH_NEED_DIR;
 }
 
+template <int MM>
 __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsolve) {
   __shared__ double sh[64 * 4];
   __shared__ double t[NDOT];
+  __shared__ OptState lst;
   const int s = blockIdx.x;
   if (s >= nsolve) return;
-  SolveDev &S = dev[s];
+  const SKX_C SolveDev &S = *cptr<SolveDev>(dev + s);
   OptState *st = S.st;
-  if (st->phase != PH_UPDATE) return;
+  if (cptr<OptState>(st)->phase != PH_UPDATE) return;
   const int tid = threadIdx.x;
+  const double sv = state_slice(st, tid);
   {
     double v[NDOT];
-#pragma unroll
-    for (int q = 0; q < NDOT; ++q) v[q] = 0.0;
-    for (int r = tid; r < S.nwg_upd; r += 256)
-#pragma unroll
-      for (int q = 0; q < NDOT; ++q) v[q] += S.partU[r * NDOT + q];
+    row_sums<NDOT, 0>(S.partU, S.nwg_upd, tid, v);
+    put_slice(&lst, tid, sv);
     block_reduce_many<NDOT>(v, sh, tid, 256, t);
   }
-  __shared__ OptState lst;
-  stage_state(&lst, st, threadIdx.x);
+  if (tid < NDOT) t[tid] *= S.dV;
+  if (tid < 12) lst.e_acc[tid] = lst.e_trial[tid];
   __syncthreads();
-  if (threadIdx.x == 0) finalize_update_body(&lst, S, t);
+  if (tid == 0) finalize_update_body<MM>(&lst, S, t);
   __syncthreads();
-  stage_state(st, &lst, threadIdx.x);
+  put_slice(st, tid, tid < NSTATE ? reinterpret_cast<const double *>(&lst)[tid] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
 }
 
-__device__ void finalize_dir_body(OptState *st, const SolveDev &S, const double *t) {
+__device__ void finalize_dir_body(OptState *st, const SKX_C SolveDev &S, const double *t) {
   const double dd = S.dV * t[0], rd = S.dV * t[1];
   const double dn = sqrt(fmax(dd, 0.0));
   if (!(rd < 0.0) || !(dn > 0.0)) {
@@ -456,18 +515,21 @@ __device__ void finalize_dir_body(OptState *st, const SolveDev &S, const double 
 __global__ __launch_bounds__(256) void k_finalize_dir(SolveDev *dev, int nsolve) {
   __shared__ double sh[2 * 4];
   __shared__ double t[2];
+  __shared__ OptState lst;
   const int s = blockIdx.x;
   if (s >= nsolve) return;
-  SolveDev &S = dev[s];
+  const SKX_C SolveDev &S = *cptr<SolveDev>(dev + s);
   OptState *st = S.st;
-  if (st->phase != PH_NEED_DIR) return;
-  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
-  __shared__ OptState lst;
-  stage_state(&lst, st, threadIdx.x);
+  if (cptr<OptState>(st)->phase != PH_NEED_DIR) return;
+  const int tid = threadIdx.x;
+  const double sv = state_slice(st, tid);
+  double v[2];
+  row_sums<2, 0>(S.partD, S.nwg_vec, tid, v);
+  put_slice(&lst, tid, sv);
+  block_reduce<2>(v, sh, tid, 256, t);
+  if (tid == 0) finalize_dir_body(&lst, S, t);
   __syncthreads();
-  if (threadIdx.x == 0) finalize_dir_body(&lst, S, t);
-  __syncthreads();
-  stage_state(st, &lst, threadIdx.x);
+  put_slice(st, tid, tid < NSTATE ? reinterpret_cast<const double *>(&lst)[tid] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,7 +566,7 @@ __global__ __launch_bounds__(NT) void k_norm(SolveDev *dev, const int *first, in
   if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
 }
 
-__device__ void finalize_norm_body(OptState *st, const SolveDev &S, const double *t) {
+__device__ void finalize_norm_body(OptState *st, const SKX_C SolveDev &S, const double *t) {
   const double nrm = S.dV * t[0];
   if (t[1] != 0.0 || !(nrm > 0.0) || !(nrm < 1e300)) {
     st->phase = PH_FAILED;
@@ -518,18 +580,21 @@ __device__ void finalize_norm_body(OptState *st, const SolveDev &S, const double
 __global__ __launch_bounds__(256) void k_finalize_norm(SolveDev *dev, int nsolve) {
   __shared__ double sh[2 * 4];
   __shared__ double t[2];
+  __shared__ OptState lst;
   const int s = blockIdx.x;
   if (s >= nsolve) return;
-  SolveDev &S = dev[s];
+  const SKX_C SolveDev &S = *cptr<SolveDev>(dev + s);
   OptState *st = S.st;
-  if (st->phase != PH_EVAL_INIT) return;
-  sum_parts<2>(S.partD, S.nwg_vec, sh, threadIdx.x, 256, t);
-  __shared__ OptState lst;
-  stage_state(&lst, st, threadIdx.x);
+  if (cptr<OptState>(st)->phase != PH_EVAL_INIT) return;
+  const int tid = threadIdx.x;
+  const double sv = state_slice(st, tid);
+  double v[2];
+  row_sums<2, 0>(S.partD, S.nwg_vec, tid, v);
+  put_slice(&lst, tid, sv);
+  block_reduce<2>(v, sh, tid, 256, t);
+  if (tid == 0) finalize_norm_body(&lst, S, t);
   __syncthreads();
-  if (threadIdx.x == 0) finalize_norm_body(&lst, S, t);
-  __syncthreads();
-  stage_state(st, &lst, threadIdx.x);
+  put_slice(st, tid, tid < NSTATE ? reinterpret_cast<const double *>(&lst)[tid] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,12 +605,13 @@ static hipError_t launch_update_t(const BatchLaunch &b, hipStream_t s) {
   case MM:                                                                                  \
     hipLaunchKernelGGL((k_update<R, 256, MM>), dim3(b.gridU), dim3(256), 0, s, b.dev,         \
                        b.firstU, b.nsolve, b.gridU);                                        \
+    hipLaunchKernelGGL(k_finalize_update<MM>, dim3(b.nsolve), dim3(256), 0, s, b.dev,        \
+                       b.nsolve);                                                           \
     break;
     SKX_UPD(1) SKX_UPD(2) SKX_UPD(3) SKX_UPD(4) SKX_UPD(5) SKX_UPD(6) SKX_UPD(7)
     default: SKX_UPD(8)
 #undef SKX_UPD
   }
-  hipLaunchKernelGGL(k_finalize_update, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
   return hipGetLastError();
 }
 

@@ -335,21 +335,22 @@ __device__ __forceinline__ void load_plane(V *buf, const SKX_G V *src, int n2, i
   }
 }
 
-// load_plane for a compile-time plane shape (N2 rows of PL values).
-template <typename V, int N2, int PL, int NT>
+// load_plane for a compile-time plane shape: N2 rows of NH values, stored
+// at LDS row pitch PL.
+template <typename V, int N2, int NH, int PL, int NT>
 __device__ __forceinline__ void load_plane_f(V *buf, const SKX_G V *src, int pitch, int tid) {
-  constexpr int TOT = N2 * PL;
+  constexpr int TOT = N2 * NH;
   constexpr int NU = (TOT + NT - 1) / NT;
   V t[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
     const int e = tid + u * NT;
-    if (TOT % NT == 0 || e < TOT) t[u] = ldg(src + (size_t)(e / PL) * pitch + e % PL);
+    if (TOT % NT == 0 || e < TOT) t[u] = ldg(src + (size_t)(e / NH) * pitch + e % NH);
   }
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
     const int e = tid + u * NT;
-    if (TOT % NT == 0 || e < TOT) buf[e] = t[u];
+    if (TOT % NT == 0 || e < TOT) buf[(e / NH) * PL + e % NH] = t[u];
   }
 }
 
@@ -414,11 +415,11 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     phit[e] = ph;
     const R n = ph * ph;
     const double nd = (double)n;
-    double v = 0.0;
+    double v = 0.0, lx = 0.0;
     if (!(nd == nd) || nd > 1e300) bad += 1.0;
     if (nd > 0.0) {
       nel += nd;
-      const double lx = log(nd);
+      lx = log(nd);
       if (do_tf) {
         double eta, psi;
         bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
@@ -441,7 +442,8 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     }
     v0s[e] = (R)v;
     if (need_f) {
-      const R f = rpow(n, a);
+      // FP64: n^a = exp(a ln n) with the logarithm taken above
+      const R f = sizeof(R) == 8 ? (nd > 0.0 ? (R)exp((double)a * lx) : (R)0) : rpow(n, a);
       nas[e] = f;
       // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
       const R cP = (ph != (R)0) ? a2 * f / ph : (R)0;
@@ -930,7 +932,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
                                                 int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
   constexpr int NT = 256, NW = 4;
-  constexpr int C = N3 / 2, PL = C + 1, YC = C / NW, ZP = N2 / 2 / NW;
+  constexpr int C = N3 / 2, PL = CRad<N3>::PL, YC = C / NW, ZP = N2 / 2 / NW;
   constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
   constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
   static_assert(Y0 * Y1 == N2 && R0 * R1 == N3 && R0 % 2 == 0, "two stages per direction");
@@ -1319,7 +1321,7 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
 // ---------------------------------------------------------------------------
 template <typename V, int N3, int RAD, int ZP>
 __device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
-  constexpr int C = N3 / 2, PL = C + 1;
+  constexpr int C = N3 / 2, PL = CRad<N3>::PL;
   typedef CMap<N3, RAD, ZP, false> M;
   static_assert(RAD % 2 == 0, "even first radix");
   V v[M::MB][RAD];
@@ -1368,7 +1370,7 @@ __device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
 template <typename V, int N2, int N3>
 __device__ __forceinline__ void fold_dc_nyquist(V *buf, int lane) {
   typedef decltype(buf[0].x) R;
-  constexpr int C = N3 / 2, PL = C + 1, NY = (N2 + 63) / 64;
+  constexpr int C = N3 / 2, PL = CRad<N3>::PL, NY = (N2 + 63) / 64;
   V z[NY];
 #pragma unroll
   for (int u = 0; u < NY; ++u) {
@@ -1397,7 +1399,7 @@ __device__ __forceinline__ void fold_dc_nyquist(V *buf, int lane) {
 template <typename V, int N2, int N3, int ZP, int MB>
 __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *tw3, int lane,
                                                 int wave, V (&v)[MB][CRad<N3>::R1]) {
-  constexpr int C = N3 / 2, PL = C + 1, NW = 4, YC = C / NW;
+  constexpr int C = N3 / 2, PL = CRad<N3>::PL, NW = 4, YC = C / NW;
   constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
   constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
   static_assert(Y0 * Y1 == N2 && R0 * R1 == N3, "two stages per direction");
@@ -1425,7 +1427,7 @@ __global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first,
                                                 int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
   constexpr int NT = 256, NW = 4;
-  constexpr int C = N3 / 2, PL = C + 1;
+  constexpr int C = N3 / 2, PL = CRad<N3>::PL;
   constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
   constexpr int ZP = N2 / 2 / NW;                 // row pairs per wavefront
   typedef CMap<N3, R1, ZP, false> ZM;
@@ -1459,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first,
   V v[MB][R1];
 
   if (MODE == MODE_PREC) {
-    load_plane_f<V, N2, PL, NT>(buf, spec, pitch, tid);
+    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec, pitch, tid);
     __syncthreads();
     plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
     SKX_G R *out = gptr<R>(S.pr2[1 - par]) + pbase;
@@ -1511,7 +1513,7 @@ __global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first,
         }
     }
     __syncthreads();
-    load_plane_f<V, N2, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
     __syncthreads();
     plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
 #pragma unroll
@@ -1572,7 +1574,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
                        b.firstV, b.nsolve, b.gridV, b.fd);
     if (b.shape & 1)
       hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
-                         (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
+                         (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
                          b.twbank);
     else
       hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
@@ -1587,7 +1589,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4) && (b.shape & 4)) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
-                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   } else if (b.gridC > 0 && (mask & 4)) {
     // In FP32 two 512-thread groups share a CU; when the last round of
@@ -1618,7 +1620,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   // one field per solve: pass A has one workgroup per plane, like pass C
   if (b.gridC > 0 && (mask & 1) && (b.shape & 1))
     hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
-                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   else if (b.gridC > 0 && (mask & 1))
     hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
@@ -1632,7 +1634,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4) && (b.shape & 4))
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
-                       (64 * 33 + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
+                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   else if (b.gridC > 0 && (mask & 4))
     hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
