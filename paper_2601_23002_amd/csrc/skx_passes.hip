@@ -1423,7 +1423,8 @@ __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *t
 }
 
 template <typename R, int N2, int N3, int MODE>
-__global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first, int nsolve,
+// (three workgroups per CU: caps FP64 at 168 VGPRs, FP32 needs fewer)
+__global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *first, int nsolve,
                                                 int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
   constexpr int NT = 256, NW = 4;
@@ -1501,6 +1502,10 @@ __global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first,
     const int sl = S.slot[fb];
     if (sl < 0) continue;
     R cf[MB][2][R1];
+    __syncthreads();
+    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    __syncthreads();
+    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
     if (fb >= 2 || (fb == 1 && !KEEP_PHI)) {
       const SKX_G R *src = fb == 1 ? phit : (fb == 2 ? cfp[2] : cfp[3]);
 #pragma unroll
@@ -1512,10 +1517,6 @@ __global__ __launch_bounds__(256) void k_passCf(SolveDev *dev, const int *first,
             for (int r = 0; r < R1; ++r) cf[i][h][r] = src[pt[i] + h * N3 + R0 * r];
         }
     }
-    __syncthreads();
-    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
-    __syncthreads();
-    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
 #pragma unroll
     for (int i = 0; i < MB; ++i)
       if (pt[i] >= 0) {
