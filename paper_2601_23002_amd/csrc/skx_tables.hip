@@ -176,7 +176,9 @@ hipError_t debug_fd_eval(const double *u_dev, double *eta_dev, double *psi_dev, 
 // ---------------------------------------------------------------------------
 struct Chi { double chi, dchi; };
 
-__device__ Chi chi0_byparts(double q, double T, double eta0) {
+// One wavefront per shell: lane l takes the nodes k = -K + l, -K + l + 64,
+// ... of every interval, the lane sums are added across the wavefront.
+__device__ Chi chi0_byparts(double q, double T, double eta0, int lane) {
   const double PI = 3.14159265358979323846;
   double kmax = sqrt(2.0 * T * (fmax(eta0, 0.0) + 55.0));
   double pts[6];
@@ -212,7 +214,7 @@ __device__ Chi chi0_byparts(double q, double T, double eta0) {
     bool lsing = (a == half) && (half == 0.5 * q);
     bool rsing = (b == half) && (half == 0.5 * q);
     double sum = 0.0, dsum = 0.0;
-    for (int k = -K; k <= K; ++k) {
+    for (int k = -K + lane; k <= K; k += 64) {
       double t = k * h;
       double u = 0.5 * PI * sinh(t);
       double ch = cosh(u);
@@ -240,6 +242,10 @@ __device__ Chi chi0_byparts(double q, double T, double eta0) {
     acc += 0.5 * L * h * sum;
     dacc += 0.5 * L * h * dsum;
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc += __shfl_down(acc, off, 64);
+    dacc += __shfl_down(dacc, off, 64);
+  }
   Chi r;
   r.chi = -acc / (PI * PI * q * T);
   r.dchi = -dacc / (PI * PI * q * T);
@@ -252,15 +258,20 @@ __device__ double fd_table_eta(double y, const FDTable &fd) {
   return e;
 }
 
-__global__ void k_kernel_tables(double *w, double *wp, int smax, double L, double n0, double T,
-                                double a, double eta0, double im12, double dim12) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_kernel_tables(double *w, double *wp, int smax, double L,
+                                                       double n0, double T, double a, double eta0,
+                                                       double im12, double dim12) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (s > smax) return;
-  if (s == 0) { w[0] = 0.0; wp[0] = 0.0; return; }
+  if (s == 0) {
+    if (lane == 0) { w[0] = 0.0; wp[0] = 0.0; }
+    return;
+  }
   const double PI = 3.14159265358979323846;
   const double SQ2 = 1.41421356237309504880;
   double q = (2.0 * PI / L) * sqrt((double)s);
-  Chi c = chi0_byparts(q, T, eta0);
+  Chi c = chi0_byparts(q, T, eta0, lane);
+  if (lane != 0) return;
   double dmudn = SQ2 * PI * PI / (sqrt(T) * im12);
   double K = -1.0 / c.chi - dmudn - q * q / (4.0 * n0);
   double pref = pow(n0, 2.0 - 2.0 * a) / (2.0 * a * a);
@@ -296,7 +307,7 @@ hipError_t build_kernel_tables(double *w, double *wp, int smax, double L, double
   hipFreeAsync(tmp, s);
   if (e != hipSuccess) return e;
   if (gas_out) { gas_out[0] = host[0]; gas_out[1] = host[1]; gas_out[2] = host[2]; }
-  hipLaunchKernelGGL(k_kernel_tables, dim3((smax + 1 + 63) / 64), dim3(64), 0, s, w, wp, smax, L,
+  hipLaunchKernelGGL(k_kernel_tables, dim3((smax + 1 + 3) / 4), dim3(256), 0, s, w, wp, smax, L,
                      n0, T, a, host[0], host[1], host[2]);
   return hipGetLastError();
 }
@@ -417,30 +428,31 @@ hipError_t build_vloc(void *vloc, int prec, int n1, int n2, int n3, int pitch, d
 // reciprocal part: one thread per G vector. Partial sums are reduced in a
 // fixed order by a single workgroup (deterministic).
 // ---------------------------------------------------------------------------
-__global__ void k_ewald_real(double *part, int nions, const double *pos, const double *Z, double L,
-                             double alpha, int nimg, double rcut) {
-  long long npair = (long long)nions * (nions + 1) / 2;
-  long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+// One wavefront per ion pair i <= j: the lanes share the periodic images.
+__global__ __launch_bounds__(256) void k_ewald_real(double *part, int nions, const double *pos,
+                                                    const double *Z, double L, double alpha,
+                                                    int nimg, double rcut) {
+  const long long npair = (long long)nions * (nions + 1) / 2;
+  const long long idx = blockIdx.x * 4LL + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= npair) return;
+  // decode (i, j) with i <= j
+  long long rem = idx;
+  int i = 0;
+  while (rem >= nions - i) { rem -= nions - i; ++i; }
+  const int j = i + (int)rem;
+  const double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
+               dz = pos[3 * i + 2] - pos[3 * j + 2];
+  const int side = 2 * nimg + 1, nimgs = side * side * side;
   double acc = 0.0;
-  if (idx < npair) {
-    // decode (i, j) with i <= j
-    long long rem = idx;
-    int i = 0;
-    while (rem >= nions - i) { rem -= nions - i; ++i; }
-    int j = i + (int)rem;
-    double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
-           dz = pos[3 * i + 2] - pos[3 * j + 2];
-    double fac = (i == j) ? 0.5 : 1.0;
-    for (int a = -nimg; a <= nimg; ++a)
-      for (int b = -nimg; b <= nimg; ++b)
-        for (int c = -nimg; c <= nimg; ++c) {
-          double x = dx + a * L, y = dy + b * L, z = dz + c * L;
-          double r = sqrt(x * x + y * y + z * z);
-          if (r > 0.0 && r < rcut) acc += erfc(alpha * r) / r;
-        }
-    acc *= fac * Z[i] * Z[j];
-    part[idx] = acc;
+  for (int m = lane; m < nimgs; m += 64) {
+    const int a = m / (side * side) - nimg, b = (m / side) % side - nimg, c = m % side - nimg;
+    const double x = dx + a * L, y = dy + b * L, z = dz + c * L;
+    const double r = sqrt(x * x + y * y + z * z);
+    if (r > 0.0 && r < rcut) acc += erfc(alpha * r) / r;
   }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) part[idx] = acc * ((i == j) ? 0.5 : 1.0) * Z[i] * Z[j];
 }
 
 __global__ void k_ewald_recip(double *part, int nions, const double *pos, const double *Z, double L,
@@ -498,7 +510,7 @@ hipError_t ewald_energy(double L, int nions, const double *pos_dev, const double
   long long side = 2 * mmax + 1;
   long long ng = side * side * side;
   if (npair > scratch_len || ng > scratch_len) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ewald_real, dim3((unsigned)((npair + 127) / 128)), dim3(128), 0, s,
+  hipLaunchKernelGGL(k_ewald_real, dim3((unsigned)((npair + 3) / 4)), dim3(256), 0, s,
                      scratch_dev, nions, pos_dev, charge_dev, L, alpha, nimg, rcut);
   hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, scratch_dev, npair, out_dev, 0);
   hipLaunchKernelGGL(k_ewald_recip, dim3((unsigned)((ng + 127) / 128)), dim3(128), 0, s,
