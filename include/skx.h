@@ -216,6 +216,15 @@ int skx_set_autotune(int on);
  * Returns the previous mask. */
 int skx_set_shape_kernels(int mask);
 
+/* Planes (y-z slices) whose half spectrum does not fit in LDS (FP64
+ * beyond 128 x 128, FP32 beyond 192 x 192) run passes A and C in chunks of
+ * row pairs and columns, the half spectrum staying in HBM between the z and
+ * y transforms. force = 1 makes every plane take that path (for checking it
+ * against the in-LDS kernels on small grids); 0 (default) uses it only where
+ * needed. Results differ from the in-LDS kernels by rounding only. Applies
+ * to batches built after the call. Returns the previous setting. */
+int skx_set_plane_chunking(int force);
+
 /* Radix order in use for length n in `precision` (SKX_FP64 / SKX_FP32):
  * writes up to max radices, returns their count or SKX_E_INVALID. */
 int skx_get_radix_order(int n, int precision, int *radices, int max);

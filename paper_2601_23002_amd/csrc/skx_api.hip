@@ -116,6 +116,7 @@ std::vector<std::vector<int>> radix_candidates(int n) {
 std::vector<int> g_tuned[2][513];
 bool g_autotune = false;
 int g_shape_kernels = 7;
+bool g_chunk_planes = false;
 
 Plan make_plan_from(int n, int twoff, const std::vector<int> &rads) {
   Plan p{};
@@ -318,9 +319,17 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
 }
 
 // Prefix sums and grids of a batch; writes `first` (device, 4*(n+1) ints).
-int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev *ddev,
+int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s) {
-  const int n = (int)hs.size();
+  const int n = (int)hs_in.size();
+  // planes beyond LDS (or every plane, when chunking is forced) take the
+  // chunked pass A and C kernels
+  std::vector<SolveDev> hs(hs_in);
+  for (SolveDev &h : hs) {
+    size_t a, b, cc;
+    lds_sizes(h, prec, a, b, cc);
+    h.big = (a > LDS_MAX || (g_chunk_planes && !h.debug)) ? 1 : 0;
+  }
   std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1), fu(n + 1);
   fa[0] = fb[0] = fc[0] = fv[0] = fu[0] = 0;
   size_t la = 0, lb = 0, lc = 0;
@@ -333,7 +342,8 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
     fu[i + 1] = fu[i] + h.nwg_upd;
     size_t a, b, cc;
     lds_sizes(h, prec, a, b, cc);
-    la = std::max(la, a); lb = std::max(lb, b); lc = std::max(lc, cc);
+    lb = std::max(lb, b);
+    if (!h.big) { la = std::max(la, a); lc = std::max(lc, cc); }
   }
   if (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX)
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
@@ -364,16 +374,19 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev 
   size_t lc_acc = 0;
   // (FP64: the dE/dphi plane; FP32: that plane and a copy of phi_t)
   for (const SolveDev &h : hs)
-    lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
-                                  8 * (size_t)h.n2 * h.n3);
+    if (!h.big)
+      lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
+                                    8 * (size_t)h.n2 * h.n3);
   bl.accC_lds = lc_acc <= LDS_MAX ? 1 : 0;
   if (bl.accC_lds) lc = std::max(lc, lc_acc);
   bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
   bl.mh = 1;
   for (const SolveDev &h : hs) bl.mh = std::max(bl.mh, std::min(h.mh, MMAX));
+  bl.has_big = bl.has_small = 0;
+  for (const SolveDev &h : hs) (h.big ? bl.has_big : bl.has_small) = 1;
   bl.shape = g_shape_kernels;
   for (const SolveDev &h : hs)
-    if (h.n1 != 64 || h.n2 != 64 || h.n3 != 64 || h.debug) bl.shape = 0;
+    if (h.n1 != 64 || h.n2 != 64 || h.n3 != 64 || h.debug || h.big) bl.shape = 0;
   return SKX_OK;
 }
 
@@ -383,8 +396,13 @@ int check_grid(skx_ctx *c, int prec) {
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = n3 / 2 + 1; h.nf = NFIELD; h.tk = prec == 0 ? 8 : 16;
   size_t a, b, cc;
   lds_sizes(h, prec, a, b, cc);
-  if (a > LDS_MAX || b > LDS_MAX)
+  // planes beyond LDS run the chunked kernels, which need room for one row
+  // pair and two columns; pass B's x tile must fit as it is
+  const size_t v = prec == 0 ? 16 : 8;
+  const size_t cap = BIG_LDS / v - n2 - n3;
+  if (b > LDS_MAX || cap < 2 * (size_t)h.nh || cap < 2 * (size_t)n2)
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
+  (void)a;
   return SKX_OK;
 }
 
@@ -1328,6 +1346,12 @@ int skx_profile_enable(int on) {
 int skx_set_autotune(int on) {
   const int old = g_autotune ? 1 : 0;
   g_autotune = on != 0;
+  return old;
+}
+
+int skx_set_plane_chunking(int force) {
+  const int old = g_chunk_planes ? 1 : 0;
+  g_chunk_planes = force != 0;
   return old;
 }
 

@@ -16,6 +16,7 @@ constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinit
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
 constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
 constexpr int CHUNK = 1024;        // grid points per workgroup in the vector passes
+constexpr size_t BIG_LDS = 96 * 1024;   // LDS of the chunked plane kernels (bytes)
 constexpr int UCHUNK = 4096;       // grid points per workgroup of the optimiser update on
                                    // large grids (fewer rows of its 58 partial sums)
 constexpr int NPREFIX = 5;         // batch prefix-sum arrays: A, B, C, vector, update
@@ -72,6 +73,7 @@ struct SolveDev {
   int nwg_upd, uchunk;             // workgroups of the optimiser update and their points
   int mh;                          // history slots allocated (>= the solve's m)
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
+  int big;                         // plane too large for LDS: chunked passes A and C
   unsigned terms;
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
   double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
@@ -122,6 +124,7 @@ struct BatchLaunch {
   size_t ldsA, ldsB, ldsC;
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int mh;                          // largest history length of the batch (1..MMAX)
+  int has_big, has_small;          // solves on the chunked / the in-LDS plane kernels
   int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
                                    // 64 x 64 x 64 grids (every solve has that grid)
 };

@@ -470,6 +470,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
+  if (S.big) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -783,6 +784,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
+  if (S.big) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -914,6 +916,237 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
   block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
   if (tid == 0)
     for (int q = 0; q < PART_C; ++q) S.partC[plane * PART_C + q] = tot[q];
+}
+
+// ---------------------------------------------------------------------------
+// Passes A and C for planes whose half spectrum does not fit in LDS (FP64
+// beyond 128 x 128, FP32 beyond 192 x 192): one workgroup per plane (and
+// field, in pass A's evaluation) works through the plane in chunks of row
+// pairs for the z transforms and chunks of columns for the y transforms,
+// the half spectrum staying in the plane's HBM slot in between. The
+// workgroup reads back only what it wrote itself, after a barrier (the plane
+// stays in L2 meanwhile).
+// ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ int big_cap(int n2, int n3) {
+  return (int)(BIG_LDS / sizeof(V)) - n2 - n3;     // complex values of LDS work space
+}
+
+// y transforms of every column of the plane's half spectrum, in place in HBM.
+template <typename V, bool INV, int NT>
+__device__ void big_columns(V *buf, SKX_G V *spec, const SolveDev &S, const V *tw2, int tid) {
+  const int n2 = S.n2, nh = S.nh, pitch = S.pitch;
+  const int cap = big_cap<V>(n2, S.n3);
+  const int cc = max(1, min(nh, cap / n2 - 1)), ccp = cc + 1;
+  for (int k0 = 0; k0 < nh; k0 += cc) {
+    const int kc = min(cc, nh - k0);
+    const UDiv dkc = make_udiv((unsigned)kc);
+    for (int e = tid; e < n2 * kc; e += NT) {
+      const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+      buf[y * ccp + kk] = ldg(spec + (size_t)y * pitch + k0 + kk);
+    }
+    __syncthreads();
+    fft_lds<V, MAXB_A, INV>(buf, S.p2, kc, ccp, 1, tw2, tid, NT);
+    for (int e = tid; e < n2 * kc; e += NT) {
+      const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+      stg(spec + (size_t)y * pitch + k0 + kk, buf[y * ccp + kk]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *first, int nsolve,
+                                                  int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  if (!S.big) return;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
+  const int tid = threadIdx.x;
+  const int local = item - first_of(first, s);
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const int plane = local / nf;
+  const int fb = MODE == MODE_EVAL ? nth_field(S.fields, local - plane * nf) : 0;
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh, pitch = S.pitch;
+  V *tw2 = reinterpret_cast<V *>(smem);
+  V *tw3 = tw2 + n2;
+  V *buf = tw3 + n3;
+  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
+  __syncthreads();
+  const R invM = (R)(1.0 / (double)S.M);
+  const size_t pbase = (size_t)plane * n2 * n3;
+  SKX_G V *spec = gptr<V>(S.spec) + (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H +
+                  (size_t)plane * n2 * pitch;
+  const SKX_G R *pt = gptr<R>(S.phi2[1 - par]) + pbase;
+  const SKX_G R *fa = gptr<R>(S.npa) + pbase;
+  const SKX_G R *gr = gptr<R>(S.grad) + pbase;
+  SKX_G R *rt = gptr<R>(S.r2[1 - par]) + pbase;
+  const R n0 = (R)S.n0, n0a = (R)S.n0a;
+  const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
+  const int cz = n2 / 2, nk = n3 / 2 + 1;
+  const int rc = max(1, min(cz, big_cap<V>(n2, n3) / (2 * pl)));
+  const UDiv dn3 = make_udiv((unsigned)n3), dnk = make_udiv((unsigned)nk);
+  for (int p0 = 0; p0 < cz; p0 += rc) {
+    const int np = min(cz, p0 + rc) - p0;
+    // rows 2p and 2p+1 of the pair as one complex row
+    for (int e = tid; e < np * n3; e += NT) {
+      const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+      const int o = 2 * (p0 + q) * n3 + z;
+      R x[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (MODE == MODE_EVAL) {
+          const R p = fb != 2 ? pt[o + h * n3] : (R)0;
+          const R f = fb >= 2 ? fa[o + h * n3] : (R)0;
+          x[h] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
+        } else {
+          x[h] = gr[o + h * n3] - mu2 * pt[o + h * n3];
+          rt[o + h * n3] = x[h];
+        }
+      }
+      V v;
+      v.x = x[0] * invM;
+      v.y = x[1] * invM;
+      buf[q * 2 * pl + z] = v;
+    }
+    __syncthreads();
+    fft_lds<V, MAXB_A, false>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
+    // split into the two rows' half spectra, straight to HBM
+    for (int e = tid; e < np * nk; e += NT) {
+      const int q = (int)udiv((unsigned)e, dnk), k = e - q * nk;
+      const V X = buf[q * 2 * pl + k];
+      const V Xm = buf[q * 2 * pl + (k == 0 ? 0 : n3 - k)];
+      V A, B;
+      A.x = (R)0.5 * (X.x + Xm.x); A.y = (R)0.5 * (X.y - Xm.y);
+      B.x = (R)0.5 * (X.y + Xm.y); B.y = (R)-0.5 * (X.x - Xm.x);
+      const int y = 2 * (p0 + q);
+      stg(spec + (size_t)y * pitch + k, A);
+      stg(spec + (size_t)(y + 1) * pitch + k, B);
+    }
+    __syncthreads();
+  }
+  big_columns<V, false, NT>(buf, spec, S, tw2, tid);
+}
+
+template <typename R, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *first, int nsolve,
+                                                  int grid, const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  if (!S.big) return;
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (!active_phase<MODE>(st->phase)) return;
+  const int par = st->par;
+  const int tid = threadIdx.x;
+  const int plane = item - first_of(first, s);
+  const int n2 = S.n2, n3 = S.n3, pl = S.nh, pitch = S.pitch;
+  V *tw2 = reinterpret_cast<V *>(smem);
+  V *tw3 = tw2 + n2;
+  V *buf = tw3 + n3;
+  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
+  __syncthreads();
+  const size_t pbase = (size_t)plane * n2 * n3;
+  SKX_G V *spec0 = gptr<V>(S.spec) + (size_t)plane * n2 * pitch;
+  const int nfl = MODE == MODE_EVAL ? NFIELD : 1;
+  for (int fb = 0; fb < nfl; ++fb) {
+    const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
+    if (sl < 0) continue;
+    big_columns<V, true, NT>(buf, spec0 + (size_t)sl * S.H, S, tw2, tid);
+  }
+  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
+  const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
+  const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
+  SKX_G R *out = MODE == MODE_EVAL ? gptr<R>(S.grad) + pbase : gptr<R>(S.pr2[1 - par]) + pbase;
+  const int cz = n2 / 2;
+  const int rc = max(1, min(cz, big_cap<V>(n2, n3) / (2 * pl)));
+  const UDiv dn3 = make_udiv((unsigned)n3);
+  double sphig = 0.0, bad = 0.0;
+  for (int p0 = 0; p0 < cz; p0 += rc) {
+    const int np = min(cz, p0 + rc) - p0;
+    if (MODE == MODE_EVAL) {
+      for (int e = tid; e < np * n3; e += NT) {
+        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+        const int o = 2 * (p0 + q) * n3 + z;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) out[o + h * n3] = (R)2 * phit[o + h * n3] * v0[o + h * n3];
+      }
+    }
+    for (int fb = 0; fb < nfl; ++fb) {
+      const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
+      if (sl < 0) continue;
+      const SKX_G V *spec = spec0 + (size_t)sl * S.H;
+      // x_{2p} + i x_{2p+1} over the full row from the two half spectra
+      for (int e = tid; e < np * n3; e += NT) {
+        const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
+        const int y = 2 * (p0 + q);
+        V Av, Bv;
+        if (2 * k <= n3) {
+          Av = ldg(spec + (size_t)y * pitch + k);
+          Bv = ldg(spec + (size_t)(y + 1) * pitch + k);
+          if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
+        } else {
+          Av = ldg(spec + (size_t)y * pitch + n3 - k);
+          Bv = ldg(spec + (size_t)(y + 1) * pitch + n3 - k);
+          Av.y = -Av.y; Bv.y = -Bv.y;
+        }
+        V X;
+        X.x = Av.x - Bv.y;
+        X.y = Av.y + Bv.x;
+        buf[q * 2 * pl + k] = X;
+      }
+      __syncthreads();
+      fft_lds<V, MAXB_C, true>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
+      for (int e = tid; e < np * n3; e += NT) {
+        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+        const int o = 2 * (p0 + q) * n3 + z;
+        const V X = buf[q * 2 * pl + z];
+        if (MODE == MODE_PREC) {
+          out[o] = X.x;
+          out[o + n3] = X.y;
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const R val = h ? X.y : X.x;
+            const R coef = fb == 0 ? (R)1 : fb == 1 ? (R)2 * cfp[1][o + h * n3] : cfp[fb][o + h * n3];
+            out[o + h * n3] += coef * val;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (MODE == MODE_EVAL) {
+      for (int e = tid; e < np * n3; e += NT) {
+        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+        const int o = 2 * (p0 + q) * n3 + z;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const R g = out[o + h * n3];
+          sphig += (double)phit[o + h * n3] * (double)g;
+          if (!(g == g)) bad += 1.0;
+        }
+      }
+    }
+  }
+  if (MODE == MODE_EVAL) {
+    double v[PART_C] = {sphig, bad};
+    double tot[PART_C];
+    __syncthreads();
+    block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+    if (tid == 0)
+      for (int q = 0; q < PART_C; ++q) S.partC[plane * PART_C + q] = tot[q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1577,9 +1810,12 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
       hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
                          (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
                          b.twbank);
-    else
+    else if (b.has_small)
       hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                          b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
+    if (b.has_big)
+      hipLaunchKernelGGL((k_passA_big<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), BIG_LDS, s,
+                         b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
   }
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
     hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_EVAL>), dim3(b.gridB), dim3(256),
@@ -1592,7 +1828,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  } else if (b.gridC > 0 && (mask & 4)) {
+  } else if (b.gridC > 0 && (mask & 4) && b.has_small) {
     // In FP32 two 512-thread groups share a CU; when the last round of
     // those would be less than half full (e.g. 576 planes), 256-thread
     // groups spread the planes more evenly over the CUs.
@@ -1612,6 +1848,9 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
                          s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     }
   }
+  if (b.gridC > 0 && (mask & 4) && b.has_big)
+    hipLaunchKernelGGL((k_passC_big<R, 256, MODE_EVAL>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
 
@@ -1623,9 +1862,12 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  else if (b.gridC > 0 && (mask & 1))
+  else if (b.gridC > 0 && (mask & 1) && b.has_small)
     hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+  if (b.gridC > 0 && (mask & 1) && b.has_big)
+    hipLaunchKernelGGL((k_passA_big<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
     hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(b.gridB), dim3(256),
                        (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
@@ -1637,9 +1879,12 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  else if (b.gridC > 0 && (mask & 4))
+  else if (b.gridC > 0 && (mask & 4) && b.has_small)
     hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+  if (b.gridC > 0 && (mask & 4) && b.has_big)
+    hipLaunchKernelGGL((k_passC_big<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
 

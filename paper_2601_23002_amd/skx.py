@@ -112,6 +112,7 @@ _sig("skx_profile_enable", C.c_int, [C.c_int])
 _sig("skx_set_graphs", C.c_int, [C.c_int])
 _sig("skx_set_autotune", C.c_int, [C.c_int])
 _sig("skx_set_shape_kernels", C.c_int, [C.c_int])
+_sig("skx_set_plane_chunking", C.c_int, [C.c_int])
 _sig("skx_get_radix_order", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int])
 _sig("skx_profile_reset", C.c_int, [])
 _sig("skx_profile_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int])
@@ -320,6 +321,12 @@ def set_shape_kernels(mask=7):
     elif mask is False:
         mask = 0
     return _lib.skx_set_shape_kernels(int(mask))
+
+
+def set_plane_chunking(force=True):
+    """Run passes A and C of every plane in row-pair / column chunks (force)
+    or only of planes beyond LDS (default); returns the previous setting."""
+    return bool(_lib.skx_set_plane_chunking(1 if force else 0))
 
 
 def radix_order(n, precision=FP64):
