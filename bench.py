@@ -199,7 +199,7 @@ def run_serve(args):
     from paper_2601_23002_amd import skx
     from paper_2601_23002_amd import workloads as W
     count = args.count or 200
-    reqs = W.config_stream(count=count, rate=args.rate, nmax=128, nions_max=1024)
+    reqs = W.config_stream(count=count, rate=args.rate, nmax=192, nions_max=1024)
 
     def replay(rate_scale, label):
         eng = skx.Engine(0, hbm_budget=96 << 30, max_slots=64)
@@ -253,7 +253,7 @@ def run_serve(args):
            "warmup": 0, "ms_per_step": first["wall_s"] / count * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": f"serve: {count} Poisson requests at {args.rate:g}/s, 16-1024 "
-                                  "ions, rs 1-4, T 0.5-10 Ha, grids 32^3-128^3, mixed precision",
+                                  "ions, rs 1-4, T 0.5-10 Ha, grids 32^3-192^3, mixed precision",
                       "parallelism": "continuous batching"},
            "offered": first, "sustainable": sus}
     print(json.dumps(out))

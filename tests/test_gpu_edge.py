@@ -1,6 +1,7 @@
 """Edge cases and error paths of the C ABI on the GPU: uneven and smallest
 grids, a single ion, beta = 0 (three fields), a = 1, warm starts, and the
 documented error codes."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -108,8 +109,10 @@ def test_error_codes():
     with pytest.raises(skx.SkxError) as ex:
         c2.set_ions(np.zeros((1, 3)), [1.0], [-0.3])
     assert ex.value.code == skx.E_INVALID
-    # FP64 planes above 128 do not fit the fused kernels; FP32 ones do
-    s = W.uniform_system(4, 1.0, 0.4, 2.0, 1.0, 160, seed=9)
+    # pass B's x tile of an FP64 320-point x axis (4 fields x 320 x 9
+    # complex) does not fit in LDS: large y-z planes are chunked, x pencils
+    # are not
+    s = dataclasses.replace(W.uniform_system(4, 1.0, 0.4, 2.0, 1.0, 8, seed=9), n=(320, 8, 8))
     c3 = skx.Context(0).setup(s, precision=skx.FP64)
     with pytest.raises(skx.SkxError) as ex:
         c3.evaluate(torch.ones(s.n, dtype=torch.float64, device="cuda"))
