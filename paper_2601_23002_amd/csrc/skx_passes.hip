@@ -927,6 +927,26 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 // workgroup reads back only what it wrote itself, after a barrier (the plane
 // stays in L2 meanwhile).
 // ---------------------------------------------------------------------------
+// Loop over the elements e = tid, tid + NT, ... < tot with U iterations' loads
+// in flight: load(e) for U elements first, then use(e, loaded) for each.
+template <int U, int NT, typename T, typename FL, typename FU>
+__device__ __forceinline__ void batched(int tot, int tid, FL load, FU use) {
+  for (int e0 = tid; e0 < tot; e0 += U * NT) {
+    T t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT;
+      if (e < tot) t[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT;
+      if (e < tot) use(e, t[u]);
+    }
+  }
+}
+template <typename R> struct Quad { R a, b, c, d; };
+
 template <typename V>
 __device__ __forceinline__ int big_cap(int n2, int n3) {
   return (int)(BIG_LDS / sizeof(V)) - n2 - n3;     // complex values of LDS work space
@@ -941,10 +961,16 @@ __device__ void big_columns(V *buf, SKX_G V *spec, const SolveDev &S, const V *t
   for (int k0 = 0; k0 < nh; k0 += cc) {
     const int kc = min(cc, nh - k0);
     const UDiv dkc = make_udiv((unsigned)kc);
-    for (int e = tid; e < n2 * kc; e += NT) {
-      const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
-      buf[y * ccp + kk] = ldg(spec + (size_t)y * pitch + k0 + kk);
-    }
+    batched<8, NT, V>(
+        n2 * kc, tid,
+        [&](int e) {
+          const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+          return ldg(spec + (size_t)y * pitch + k0 + kk);
+        },
+        [&](int e, const V &v) {
+          const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+          buf[y * ccp + kk] = v;
+        });
     __syncthreads();
     fft_lds<V, MAXB_A, INV>(buf, S.p2, kc, ccp, 1, tw2, tid, NT);
     for (int e = tid; e < n2 * kc; e += NT) {
@@ -996,26 +1022,40 @@ __global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *firs
   for (int p0 = 0; p0 < cz; p0 += rc) {
     const int np = min(cz, p0 + rc) - p0;
     // rows 2p and 2p+1 of the pair as one complex row
-    for (int e = tid; e < np * n3; e += NT) {
-      const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-      const int o = 2 * (p0 + q) * n3 + z;
-      R x[2];
+    // (a, b): phi_t or g of the two rows, (c, d): n^a or phi_t
+    batched<8, NT, Quad<R>>(
+        np * n3, tid,
+        [&](int e) {
+          const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+          const int o = 2 * (p0 + q) * n3 + z;
+          Quad<R> w{(R)0, (R)0, (R)0, (R)0};
+          if (MODE == MODE_EVAL) {
+            if (fb != 2) { w.a = pt[o]; w.b = pt[o + n3]; }
+            if (fb >= 2) { w.c = fa[o]; w.d = fa[o + n3]; }
+          } else {
+            w.a = gr[o]; w.b = gr[o + n3]; w.c = pt[o]; w.d = pt[o + n3];
+          }
+          return w;
+        },
+        [&](int e, const Quad<R> &w) {
+          const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+          const int o = 2 * (p0 + q) * n3 + z;
+          R x[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (MODE == MODE_EVAL) {
-          const R p = fb != 2 ? pt[o + h * n3] : (R)0;
-          const R f = fb >= 2 ? fa[o + h * n3] : (R)0;
-          x[h] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
-        } else {
-          x[h] = gr[o + h * n3] - mu2 * pt[o + h * n3];
-          rt[o + h * n3] = x[h];
-        }
-      }
-      V v;
-      v.x = x[0] * invM;
-      v.y = x[1] * invM;
-      buf[q * 2 * pl + z] = v;
-    }
+          for (int h = 0; h < 2; ++h) {
+            const R u = h ? w.b : w.a, f = h ? w.d : w.c;
+            if (MODE == MODE_EVAL)
+              x[h] = fb == 0 ? u : fb == 1 ? u * u : fb == 2 ? f : (f - n0a) * (u * u - n0);
+            else {
+              x[h] = u - mu2 * f;
+              rt[o + h * n3] = x[h];
+            }
+          }
+          V v;
+          v.x = x[0] * invM;
+          v.y = x[1] * invM;
+          buf[q * 2 * pl + z] = v;
+        });
     __syncthreads();
     fft_lds<V, MAXB_A, false>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
     // split into the two rows' half spectra, straight to HBM
@@ -1076,67 +1116,87 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
   for (int p0 = 0; p0 < cz; p0 += rc) {
     const int np = min(cz, p0 + rc) - p0;
     if (MODE == MODE_EVAL) {
-      for (int e = tid; e < np * n3; e += NT) {
-        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-        const int o = 2 * (p0 + q) * n3 + z;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) out[o + h * n3] = (R)2 * phit[o + h * n3] * v0[o + h * n3];
-      }
+      batched<8, NT, Quad<R>>(
+          np * n3, tid,
+          [&](int e) {
+            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+            const int o = 2 * (p0 + q) * n3 + z;
+            return Quad<R>{phit[o], phit[o + n3], v0[o], v0[o + n3]};
+          },
+          [&](int e, const Quad<R> &w) {
+            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+            const int o = 2 * (p0 + q) * n3 + z;
+            out[o] = (R)2 * w.a * w.c;
+            out[o + n3] = (R)2 * w.b * w.d;
+          });
     }
     for (int fb = 0; fb < nfl; ++fb) {
       const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
       if (sl < 0) continue;
       const SKX_G V *spec = spec0 + (size_t)sl * S.H;
       // x_{2p} + i x_{2p+1} over the full row from the two half spectra
-      for (int e = tid; e < np * n3; e += NT) {
-        const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
-        const int y = 2 * (p0 + q);
-        V Av, Bv;
-        if (2 * k <= n3) {
-          Av = ldg(spec + (size_t)y * pitch + k);
-          Bv = ldg(spec + (size_t)(y + 1) * pitch + k);
-          if (k == 0 || 2 * k == n3) { Av.y = 0; Bv.y = 0; }
-        } else {
-          Av = ldg(spec + (size_t)y * pitch + n3 - k);
-          Bv = ldg(spec + (size_t)(y + 1) * pitch + n3 - k);
-          Av.y = -Av.y; Bv.y = -Bv.y;
-        }
-        V X;
-        X.x = Av.x - Bv.y;
-        X.y = Av.y + Bv.x;
-        buf[q * 2 * pl + k] = X;
-      }
+      batched<8, NT, Quad<R>>(
+          np * n3, tid,
+          [&](int e) {
+            const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
+            const int y = 2 * (p0 + q), kk = 2 * k <= n3 ? k : n3 - k;
+            const V Av = ldg(spec + (size_t)y * pitch + kk);
+            const V Bv = ldg(spec + (size_t)(y + 1) * pitch + kk);
+            return Quad<R>{Av.x, Av.y, Bv.x, Bv.y};
+          },
+          [&](int e, const Quad<R> &w) {
+            const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
+            R ay = w.b, by = w.d;
+            if (k == 0 || 2 * k == n3) { ay = 0; by = 0; }
+            else if (2 * k > n3) { ay = -ay; by = -by; }
+            V X;
+            X.x = w.a - by;
+            X.y = ay + w.c;
+            buf[q * 2 * pl + k] = X;
+          });
       __syncthreads();
       fft_lds<V, MAXB_C, true>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
-      for (int e = tid; e < np * n3; e += NT) {
-        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-        const int o = 2 * (p0 + q) * n3 + z;
-        const V X = buf[q * 2 * pl + z];
-        if (MODE == MODE_PREC) {
-          out[o] = X.x;
-          out[o + n3] = X.y;
-        } else {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const R val = h ? X.y : X.x;
-            const R coef = fb == 0 ? (R)1 : fb == 1 ? (R)2 * cfp[1][o + h * n3] : cfp[fb][o + h * n3];
-            out[o + h * n3] += coef * val;
-          }
-        }
-      }
+      batched<8, NT, Quad<R>>(
+          np * n3, tid,
+          [&](int e) {
+            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+            const int o = 2 * (p0 + q) * n3 + z;
+            Quad<R> w{(R)1, (R)1, (R)0, (R)0};
+            if (MODE == MODE_EVAL) {
+              if (fb > 0) { w.a = cfp[fb][o]; w.b = cfp[fb][o + n3]; }
+              w.c = out[o];
+              w.d = out[o + n3];
+            }
+            return w;
+          },
+          [&](int e, const Quad<R> &w) {
+            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+            const int o = 2 * (p0 + q) * n3 + z;
+            const V X = buf[q * 2 * pl + z];
+            if (MODE == MODE_PREC) {
+              out[o] = X.x;
+              out[o + n3] = X.y;
+            } else {
+              const R s = fb == 1 ? (R)2 : (R)1;
+              out[o] = w.c + s * w.a * X.x;
+              out[o + n3] = w.d + s * w.b * X.y;
+            }
+          });
       __syncthreads();
     }
     if (MODE == MODE_EVAL) {
-      for (int e = tid; e < np * n3; e += NT) {
-        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-        const int o = 2 * (p0 + q) * n3 + z;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const R g = out[o + h * n3];
-          sphig += (double)phit[o + h * n3] * (double)g;
-          if (!(g == g)) bad += 1.0;
-        }
-      }
+      batched<8, NT, Quad<R>>(
+          np * n3, tid,
+          [&](int e) {
+            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+            const int o = 2 * (p0 + q) * n3 + z;
+            return Quad<R>{out[o], out[o + n3], phit[o], phit[o + n3]};
+          },
+          [&](int, const Quad<R> &w) {
+            sphig += (double)w.c * (double)w.a + (double)w.d * (double)w.b;
+            if (!(w.a == w.a)) bad += 1.0;
+            if (!(w.b == w.b)) bad += 1.0;
+          });
     }
   }
   if (MODE == MODE_EVAL) {
@@ -1814,7 +1874,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
       hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                          b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
     if (b.has_big)
-      hipLaunchKernelGGL((k_passA_big<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), BIG_LDS, s,
+      hipLaunchKernelGGL((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
                          b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
   }
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
@@ -1849,7 +1909,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
     }
   }
   if (b.gridC > 0 && (mask & 4) && b.has_big)
-    hipLaunchKernelGGL((k_passC_big<R, 256, MODE_EVAL>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+    hipLaunchKernelGGL((k_passC_big<R, 512, MODE_EVAL>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
@@ -1866,7 +1926,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   if (b.gridC > 0 && (mask & 1) && b.has_big)
-    hipLaunchKernelGGL((k_passA_big<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+    hipLaunchKernelGGL((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
     hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(b.gridB), dim3(256),
@@ -1883,7 +1943,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   if (b.gridC > 0 && (mask & 4) && b.has_big)
-    hipLaunchKernelGGL((k_passC_big<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), BIG_LDS, s,
+    hipLaunchKernelGGL((k_passC_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
