@@ -322,13 +322,20 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
 int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s) {
   const int n = (int)hs_in.size();
-  // planes beyond LDS (or every plane, when chunking is forced) take the
-  // chunked pass A and C kernels
+  // Passes A and C of planes beyond LDS take the chunked kernels, and so do
+  // those where the chunked kernel was measured faster on MI355X: FP32
+  // pass C from 24 KB planes (80^2) on, FP32 pass A from 80 KB (144^2);
+  // in FP64 the in-LDS kernels are faster wherever they fit.
   std::vector<SolveDev> hs(hs_in);
   for (SolveDev &h : hs) {
     size_t a, b, cc;
     lds_sizes(h, prec, a, b, cc);
-    h.big = (a > LDS_MAX || (g_chunk_planes && !h.debug)) ? 1 : 0;
+    const size_t plane = (prec == 0 ? 16 : 8) * (size_t)h.n2 * h.nh;
+    const bool forced = g_chunk_planes && !h.debug;
+    const bool bigA = forced || a > LDS_MAX || (prec == 1 && plane > 80 * 1024);
+    const bool bigC = forced || cc > LDS_MAX || (prec == 1 && plane > 24 * 1024);
+    h.big = (bigA ? 1 : 0) | (bigC ? 2 : 0);
+    if (h.debug) h.big = 0;
   }
   std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1), fu(n + 1);
   fa[0] = fb[0] = fc[0] = fv[0] = fu[0] = 0;
@@ -343,7 +350,8 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     size_t a, b, cc;
     lds_sizes(h, prec, a, b, cc);
     lb = std::max(lb, b);
-    if (!h.big) { la = std::max(la, a); lc = std::max(lc, cc); }
+    if (!(h.big & 1)) la = std::max(la, a);
+    if (!(h.big & 2)) lc = std::max(lc, cc);
   }
   if (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX)
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
@@ -374,7 +382,7 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
   size_t lc_acc = 0;
   // (FP64: the dE/dphi plane; FP32: that plane and a copy of phi_t)
   for (const SolveDev &h : hs)
-    if (!h.big)
+    if (!(h.big & 2))
       lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
                                     8 * (size_t)h.n2 * h.n3);
   bl.accC_lds = lc_acc <= LDS_MAX ? 1 : 0;
@@ -382,8 +390,11 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
   bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
   bl.mh = 1;
   for (const SolveDev &h : hs) bl.mh = std::max(bl.mh, std::min(h.mh, MMAX));
-  bl.has_big = bl.has_small = 0;
-  for (const SolveDev &h : hs) (h.big ? bl.has_big : bl.has_small) = 1;
+  bl.bigA = bl.smallA = bl.bigC = bl.smallC = 0;
+  for (const SolveDev &h : hs) {
+    ((h.big & 1) ? bl.bigA : bl.smallA) = 1;
+    ((h.big & 2) ? bl.bigC : bl.smallC) = 1;
+  }
   bl.shape = g_shape_kernels;
   for (const SolveDev &h : hs)
     if (h.n1 != 64 || h.n2 != 64 || h.n3 != 64 || h.debug || h.big) bl.shape = 0;

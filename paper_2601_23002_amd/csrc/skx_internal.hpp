@@ -73,7 +73,7 @@ struct SolveDev {
   int nwg_upd, uchunk;             // workgroups of the optimiser update and their points
   int mh;                          // history slots allocated (>= the solve's m)
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
-  int big;                         // plane too large for LDS: chunked passes A and C
+  int big;                         // passes on the chunked plane kernels: 1 A, 2 C
   unsigned terms;
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
   double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
@@ -124,7 +124,7 @@ struct BatchLaunch {
   size_t ldsA, ldsB, ldsC;
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int mh;                          // largest history length of the batch (1..MMAX)
-  int has_big, has_small;          // solves on the chunked / the in-LDS plane kernels
+  int bigA, smallA, bigC, smallC;  // solves on the chunked / in-LDS kernels of passes A, C
   int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
                                    // 64 x 64 x 64 grids (every solve has that grid)
 };

@@ -470,7 +470,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  if (S.big) return;
+  if (S.big & 1) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -784,7 +784,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  if (S.big) return;
+  if (S.big & 2) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -990,7 +990,7 @@ __global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *firs
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  if (!S.big) return;
+  if (!(S.big & 1)) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
   if (item >= grid) return;
   const int s = find_solve(first, nsolve, item);
   const SolveDev &S = dev[s];
-  if (!S.big) return;
+  if (!(S.big & 2)) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
@@ -1870,10 +1870,10 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
       hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
                          (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
                          b.twbank);
-    else if (b.has_small)
+    else if (b.smallA)
       hipLaunchKernelGGL((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                          b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
-    if (b.has_big)
+    if (b.bigA)
       hipLaunchKernelGGL((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
                          b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
   }
@@ -1888,7 +1888,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  } else if (b.gridC > 0 && (mask & 4) && b.has_small) {
+  } else if (b.gridC > 0 && (mask & 4) && b.smallC) {
     // In FP32 two 512-thread groups share a CU; when the last round of
     // those would be less than half full (e.g. 576 planes), 256-thread
     // groups spread the planes more evenly over the CUs.
@@ -1908,7 +1908,7 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
                          s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     }
   }
-  if (b.gridC > 0 && (mask & 4) && b.has_big)
+  if (b.gridC > 0 && (mask & 4) && b.bigC)
     hipLaunchKernelGGL((k_passC_big<R, 512, MODE_EVAL>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
@@ -1922,10 +1922,10 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  else if (b.gridC > 0 && (mask & 1) && b.has_small)
+  else if (b.gridC > 0 && (mask & 1) && b.smallA)
     hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  if (b.gridC > 0 && (mask & 1) && b.has_big)
+  if (b.gridC > 0 && (mask & 1) && b.bigA)
     hipLaunchKernelGGL((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
@@ -1939,10 +1939,10 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
-  else if (b.gridC > 0 && (mask & 4) && b.has_small)
-    hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s,
+  else if (b.gridC > 0 && (mask & 4) && b.smallC)
+    hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsC, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  if (b.gridC > 0 && (mask & 4) && b.has_big)
+  if (b.gridC > 0 && (mask & 4) && b.bigC)
     hipLaunchKernelGGL((k_passC_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
