@@ -78,7 +78,8 @@ struct Group {
 
 struct skx_engine {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;          // set-up, results, the FP64 group
+  hipStream_t stream32 = nullptr;        // the FP32 group, overlapping the FP64 group's steps
   size_t budget = 0, used = 0;
   int max_slots = 0;
   uint64_t next_ticket = 1;
@@ -94,6 +95,10 @@ struct skx_engine {
 };
 
 namespace {
+
+hipStream_t group_stream(skx_engine *e, const Group &g) {
+  return &g == &e->group[1] ? e->stream32 : e->stream;
+}
 
 int eng_fail(skx_engine *e, int code, const std::string &m) {
   e->err = m;
@@ -174,21 +179,23 @@ int admit(skx_engine *e, Queued &q, Resident *&out) {
 }
 
 hipError_t group_step(skx_engine *e, Group &g) {
-  hipError_t he = launch_normalize(g.bl, e->stream);
-  for (int k = 0; k < ENGINE_CHUNK && he == hipSuccess; ++k) he = step_sequence(g.bl, e->stream);
-  if (he == hipSuccess) he = gather_phases(g.ddev, (int)g.members.size(), g.dphase, e->stream);
+  hipStream_t s = group_stream(e, g);
+  hipError_t he = launch_normalize(g.bl, s);
+  for (int k = 0; k < ENGINE_CHUNK && he == hipSuccess; ++k) he = step_sequence(g.bl, s);
+  if (he == hipSuccess) he = gather_phases(g.ddev, (int)g.members.size(), g.dphase, s);
   return he;
 }
 
 // Capture group_step into a graph (left without one if capture is refused).
 void capture_group(skx_engine *e, Group &g) {
   if (!graphs_enabled() || g.members.empty()) return;
-  if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+  hipStream_t s = group_stream(e, g);
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
     (void)hipGetLastError();
     return;
   }
   const hipError_t ec = group_step(e, g);
-  hipError_t ee = hipStreamEndCapture(e->stream, &g.graph);
+  hipError_t ee = hipStreamEndCapture(s, &g.graph);
   if (ec == hipSuccess && ee == hipSuccess) ee = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
   if (ec != hipSuccess || ee != hipSuccess) {
     g.drop_graph();
@@ -201,8 +208,10 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   g.dirty = false;
   g.drop_graph();
   if (n == 0) return SKX_OK;
+  // set-up work of newly admitted or promoted members is on e->stream
+  hipStreamSynchronize(e->stream);
+  hipStreamSynchronize(group_stream(e, g));
   if (n > g.cap) {
-    hipStreamSynchronize(e->stream);
     if (g.ddev) hipFree(g.ddev);
     if (g.dfirst) hipFree(g.dfirst);
     if (g.dphase) hipFree(g.dphase);
@@ -220,6 +229,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   int rc = build_batch(g.members[0]->ctx, hs, prec, g.ddev, g.dfirst, g.bl, e->stream);
   if (rc) return eng_fail(e, rc, g.members[0]->ctx->err);
   // build_batch reads hs from pageable memory: finish before hs goes away
+  // (and before the group's own stream uses the descriptors)
   hipStreamSynchronize(e->stream);
   capture_group(e, g);
   return SKX_OK;
@@ -273,6 +283,11 @@ int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int
   e->budget = hbm_budget_bytes;
   e->max_slots = max_slots;
   if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete e;
+    return SKX_E_DEVICE;
+  }
+  if (hipStreamCreateWithFlags(&e->stream32, hipStreamNonBlocking) != hipSuccess) {
+    hipStreamDestroy(e->stream);
     delete e;
     return SKX_E_DEVICE;
   }
@@ -354,7 +369,7 @@ int skx_engine_step(skx_engine *e) {
     // replay the captured step while the membership and the graph switch
     // hold; launch eagerly otherwise
     if (g.exec && !graphs_enabled()) g.drop_graph();
-    hipError_t he = g.exec ? hipGraphLaunch(g.exec, e->stream) : group_step(e, g);
+    hipError_t he = g.exec ? hipGraphLaunch(g.exec, group_stream(e, g)) : group_step(e, g);
     if (he != hipSuccess) return eng_fail(e, SKX_E_DEVICE, std::string("step kernels: ") + hipGetErrorString(he));
   }
   // collect phases, retire or promote finished solves
@@ -363,8 +378,9 @@ int skx_engine_step(skx_engine *e) {
     const int n = (int)g.members.size();
     if (n == 0) continue;
     std::vector<int> ph(n);
-    hipError_t he = hipMemcpyAsync(ph.data(), g.dphase, sizeof(int) * n, hipMemcpyDeviceToHost, e->stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+    hipStream_t gs = group_stream(e, g);
+    hipError_t he = hipMemcpyAsync(ph.data(), g.dphase, sizeof(int) * n, hipMemcpyDeviceToHost, gs);
+    if (he == hipSuccess) he = hipStreamSynchronize(gs);
     if (he != hipSuccess) return eng_fail(e, SKX_E_DEVICE, std::string("step execution: ") + hipGetErrorString(he));
     std::vector<Resident *> keep;
     for (int i = 0; i < n; ++i) {
@@ -427,6 +443,7 @@ int skx_engine_pending(const skx_engine *e) {
 void skx_engine_destroy(skx_engine *e) {
   if (!e) return;
   hipSetDevice(e->device);
+  hipStreamSynchronize(e->stream32);
   hipStreamSynchronize(e->stream);
   for (Resident *r : e->resident) {
     skx_destroy(r->ctx);
@@ -440,6 +457,7 @@ void skx_engine_destroy(skx_engine *e) {
     if (g.dfirst) hipFree(g.dfirst);
     if (g.dphase) hipFree(g.dphase);
   }
+  hipStreamDestroy(e->stream32);
   hipStreamDestroy(e->stream);
   delete e;
 }
