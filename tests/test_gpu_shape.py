@@ -62,6 +62,26 @@ def test_shape64_evaluation_matches_oracle(precision):
         assert np.max(np.abs(g - g_ref)) <= tol * np.max(np.abs(g_ref)) * 10, shape
 
 
+@pytest.mark.parametrize("beta,terms", [(0.0, W.TERM_ALL),
+                                        (1.3, W.TERM_ALL & ~W.TERM_VW),
+                                        (1.3, W.TERM_TF | W.TERM_HARTREE | W.TERM_LOCPP)])
+def test_shape64_field_subsets_match_oracle(beta, terms):
+    """Absent fields (no h with beta = 0, no phi without vW, neither f nor h
+    without the nonlocal terms) leave spectrum slots unused; every pass of
+    the shape kernels must skip them consistently (FP64, 1e-10)."""
+    skx, torch = _lib()
+    from oracle.functional import Problem
+    s = W.uniform_system(64, 1.0, 0.3, 2.0, 2.0, 64, seed=27, beta=beta, terms=terms)
+    phi = W.random_phi(s, 28, amp=0.4)
+    _say(f"case: 64^3 shape kernels, beta={beta}, terms={terms}")
+    e_ref, g_ref = Problem(s).evaluate(phi)
+    scale = sum(abs(e_ref[k]) for k in TERMS)
+    e, g = _eval(skx, torch, s, phi, skx.FP64, 7)
+    for k in TERMS:
+        assert abs(e[k] - e_ref[k]) <= 1e-10 * max(abs(e_ref[k]), 1e-3 * scale), (k, e[k], e_ref[k])
+    assert np.max(np.abs(g - g_ref)) <= 1e-9 * np.max(np.abs(g_ref))
+
+
 def test_shape64_sampled_gradient_points():
     """Every point class of the register-resident assembly (each lane's two
     rows and R1 z offsets, every wavefront's row pairs) on one plane: the
