@@ -68,7 +68,9 @@ def test_shape64_evaluation_matches_oracle(precision):
 def test_shape64_field_subsets_match_oracle(beta, terms):
     """Absent fields (no h with beta = 0, no phi without vW, neither f nor h
     without the nonlocal terms) leave spectrum slots unused; every pass of
-    the shape kernels must skip them consistently (FP64, 1e-10)."""
+    the shape kernels must skip them consistently (FP64 1e-10, FP32 2e-5;
+    FP32 pass C streams the next present field's plane while transforming
+    the current one)."""
     skx, torch = _lib()
     from oracle.functional import Problem
     s = W.uniform_system(64, 1.0, 0.3, 2.0, 2.0, 64, seed=27, beta=beta, terms=terms)
@@ -76,10 +78,11 @@ def test_shape64_field_subsets_match_oracle(beta, terms):
     _say(f"case: 64^3 shape kernels, beta={beta}, terms={terms}")
     e_ref, g_ref = Problem(s).evaluate(phi)
     scale = sum(abs(e_ref[k]) for k in TERMS)
-    e, g = _eval(skx, torch, s, phi, skx.FP64, 7)
-    for k in TERMS:
-        assert abs(e[k] - e_ref[k]) <= 1e-10 * max(abs(e_ref[k]), 1e-3 * scale), (k, e[k], e_ref[k])
-    assert np.max(np.abs(g - g_ref)) <= 1e-9 * np.max(np.abs(g_ref))
+    for prec, tol in ((skx.FP64, 1e-10), (skx.FP32, 2e-5)):
+        e, g = _eval(skx, torch, s, phi, prec, 7)
+        for k in TERMS:
+            assert abs(e[k] - e_ref[k]) <= tol * max(abs(e_ref[k]), 1e-3 * scale), (prec, k, e[k], e_ref[k])
+        assert np.max(np.abs(g - g_ref)) <= tol * 10 * np.max(np.abs(g_ref)), prec
 
 
 def test_shape64_sampled_gradient_points():
