@@ -61,21 +61,24 @@ def parse():
 
 
 def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
-    """Algorithmic HBM bytes of one evaluation of passes A, B, C for one solve."""
+    """Algorithmic HBM bytes of one evaluation of one solve, per kernel: the
+    pointwise kernel, pass A's transform, pass B, pass C."""
     n1, n2, n3 = sys_.n
     M = n1 * n2 * n3
     Hh = n1 * n2 * (n3 // 2 + 1)          # half-spectrum complex entries
     b = prec_bytes
     spec = 2 * b * Hh                     # one half spectrum
-    # per-point arrays pass A hands to pass C: phi_t, the local potential,
-    # and the coefficients c_P (with the f field) and c_Q (with the h field)
-    handed = 2 + (1 if nf >= 3 else 0) + (1 if nf >= 4 else 0)
-    # A: phi (+ d) in; the handed arrays and nf half spectra out
-    a = (2 if phase_trial else 1) * b * M + handed * b * M + nf * spec
+    has_f, has_h = nf >= 3, nf >= 4
+    # pointwise kernel: phi (+ d) in; phi_t, the local potential, and with
+    # the f field n^a and c_P, with the h field c_Q out
+    point = (2 if phase_trial else 1) * b * M + (2 + (2 if has_f else 0) + (1 if has_h else 0)) * b * M
+    # pass A transform: phi_t (and n^a) in, nf half spectra out
+    a = (2 if has_f else 1) * b * M + nf * spec
     bb = 2 * nf * spec + (spec if with_loc else 0)
-    # C: nf half spectra and the handed arrays in; dE/dphi out
+    # C: nf half spectra and the handed arrays (phi_t, v0, c_P, c_Q) in; dE/dphi out
+    handed = 2 + (1 if has_f else 0) + (1 if has_h else 0)
     c = nf * spec + handed * b * M + b * M
-    return a, bb, c
+    return point, a, bb, c
 
 
 PASS_SOURCES = ("paper_2601_23002_amd/csrc/skx_passes.hip", "paper_2601_23002_amd/csrc/skx_device.hpp",
@@ -325,7 +328,7 @@ def main():
     skx.profile_enable(True)
     total_work = 0
     evals = {"fp32": 0, "fp64": 0}
-    bytes_pass = {"passA": 0.0, "passB": 0.0, "passC": 0.0}
+    bytes_pass = {"point": 0.0, "passA": 0.0, "passB": 0.0, "passC": 0.0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = None
@@ -341,8 +344,9 @@ def main():
             for (ne, b) in ((e32, 4), (e64, 8)):
                 if ne <= 0:
                     continue
-                a1, b1, c1 = pass_bytes(s, b, nf, True, False)    # first evaluation
-                aT, bT, cT = pass_bytes(s, b, nf, True, True)     # trial evaluations
+                p1, a1, b1, c1 = pass_bytes(s, b, nf, True, False)    # first evaluation
+                pT, aT, bT, cT = pass_bytes(s, b, nf, True, True)     # trial evaluations
+                bytes_pass["point"] += p1 + (ne - 1) * pT
                 bytes_pass["passA"] += a1 + (ne - 1) * aT
                 bytes_pass["passB"] += b1 + (ne - 1) * bT
                 bytes_pass["passC"] += c1 + (ne - 1) * cT
@@ -363,7 +367,7 @@ def main():
     print(f"graph steps: {wall_graph:.3f} s", file=sys.stderr, flush=True)
 
     # roofline of the dominant evaluation kernel
-    dom = max(("passA", "passB", "passC"), key=lambda k: prof[k][0])
+    dom = max(("point", "passA", "passB", "passC"), key=lambda k: prof[k][0])
     ms, launches = prof[dom]
     avg_s = ms / 1e3 / max(1, launches)
     achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9

@@ -183,10 +183,12 @@ int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double 
 
 /* ---- instrumentation ---- */
 /* Process-wide per-pass timing with HIP events recorded on the launch stream
- * around every launch of: 0 pass A, 1 pass B, 2 pass C, 3 evaluation
- * reductions, 4 optimiser update pass (+ its reduction), 5 direction pass
- * (+ its reduction), 6 preconditioner passes. skx_profile_read fills up to n entries of total
- * milliseconds and launch counts and returns the number of passes. */
+ * around every launch of: 0 pass A's transform kernel, 1 pass B, 2 pass C,
+ * 3 evaluation reductions, 4 optimiser update pass (+ its reduction),
+ * 5 direction pass (+ its reduction), 6 preconditioner passes, 7 the
+ * pointwise kernel that precedes pass A's transform. skx_profile_read fills
+ * up to n entries of total milliseconds and launch counts and returns the
+ * number of passes. */
 int skx_profile_enable(int on);
 int skx_profile_reset(void);
 int skx_profile_read(double *ms, long long *launches, int n);

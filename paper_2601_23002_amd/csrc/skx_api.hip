@@ -643,13 +643,16 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
 // ---------------------------------------------------------------------------
 // Optional per-pass timing with HIP events on the launch stream.
 // ---------------------------------------------------------------------------
-enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_N };
+enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_POINT, PP_N };
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  struct Pair { int which, launches; hipEvent_t a, b; };
+  std::vector<Pair> pending;
   double ms[PP_N] = {0};
   long long count[PP_N] = {0};
+  int kernel_tag = -1;               // pass whose kernels take their own events
+  int kernel_pairs = 0;              // pairs taken by the current pass launch
   std::mutex mu;
 } g_prof;
 
@@ -670,16 +673,43 @@ hipEvent_t prof_event() {
   return e;
 }
 
+}  // namespace host
+
+// Events for the next kernel launch of the pass being timed per kernel: the
+// kernel is launched with them as its start and stop events, so the time
+// covers the kernel's execution only (not the dispatch of an event between
+// launches).
+bool kernel_events(hipEvent_t *start, hipEvent_t *stop) {
+  using namespace host;
+  if (!g_prof.on || g_prof.kernel_tag < 0) return false;
+  *start = prof_event();
+  *stop = prof_event();
+  g_prof.pending.push_back({g_prof.kernel_tag, g_prof.kernel_pairs == 0 ? 1 : 0, *start, *stop});
+  ++g_prof.kernel_pairs;
+  return true;
+}
+
+namespace host {
+
 // Launch `fn` between two recorded events when profiling is on (the driver
-// launches eagerly then, so every launch has its own pair).
+// launches eagerly then, so every launch has its own pair). The evaluation
+// passes (pointwise kernel, A, B, C) are timed per kernel instead, from
+// events attached to their kernel launches.
 template <typename F>
 hipError_t timed(int which, hipStream_t s, F fn) {
   if (!g_prof.on) return fn();
+  if (which == PP_POINT || which == PP_A || which == PP_B || which == PP_C) {
+    g_prof.kernel_tag = which;
+    g_prof.kernel_pairs = 0;
+    hipError_t e = fn();
+    g_prof.kernel_tag = -1;
+    return e;
+  }
   hipEvent_t a = prof_event(), b = prof_event();
   hipEventRecord(a, s);
   hipError_t e = fn();
   hipEventRecord(b, s);
-  g_prof.pending.push_back({which, {a, b}});
+  g_prof.pending.push_back({which, 1, a, b});
   return e;
 }
 
@@ -687,12 +717,12 @@ hipError_t timed(int which, hipStream_t s, F fn) {
 void prof_fold() {
   for (auto &p : g_prof.pending) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
-      g_prof.ms[p.first] += t;
-      g_prof.count[p.first] += 1;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      g_prof.ms[p.which] += t;
+      g_prof.count[p.which] += p.launches;
     }
-    g_prof.pool.push_back(p.second.first);
-    g_prof.pool.push_back(p.second.second);
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
   }
   g_prof.pending.clear();
 }
@@ -700,7 +730,8 @@ void prof_fold() {
 // The fixed step sequence: direction, trial evaluation, update.
 hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
   hipError_t e = timed(PP_DIR, s, [&] { return launch_opt_dir(bl, s); });
-  if (e == hipSuccess) e = timed(PP_A, s, [&] { return launch_eval(bl, s, 1); });
+  if (e == hipSuccess) e = timed(PP_POINT, s, [&] { return launch_eval(bl, s, 8); });
+  if (e == hipSuccess) e = timed(PP_A, s, [&] { return launch_eval(bl, s, 16); });
   if (e == hipSuccess) e = timed(PP_B, s, [&] { return launch_eval(bl, s, 2); });
   if (e == hipSuccess) e = timed(PP_C, s, [&] { return launch_eval(bl, s, 4); });
   if (e == hipSuccess) e = timed(PP_FIN, s, [&] { return launch_finalize_eval(bl, s); });
@@ -1022,7 +1053,8 @@ int skx_evaluate_energy_potential(skx_ctx *c, const void *in_dev, int in_kind, v
   {
     hipStream_t s = c->stream;
     const BatchLaunch &bl = I.bl;
-    he = timed(PP_A, s, [&] { return launch_eval(bl, s, 1); });
+    he = timed(PP_POINT, s, [&] { return launch_eval(bl, s, 8); });
+    if (he == hipSuccess) he = timed(PP_A, s, [&] { return launch_eval(bl, s, 16); });
     if (he == hipSuccess) he = timed(PP_B, s, [&] { return launch_eval(bl, s, 2); });
     if (he == hipSuccess) he = timed(PP_C, s, [&] { return launch_eval(bl, s, 4); });
     if (he == hipSuccess) he = timed(PP_FIN, s, [&] { return launch_finalize_eval(bl, s); });

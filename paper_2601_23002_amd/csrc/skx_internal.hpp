@@ -128,7 +128,12 @@ struct BatchLaunch {
   int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
                                    // 64 x 64 x 64 grids (every solve has that grid)
 };
-hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);  // passes A|B|C
+// Start/stop events for the next evaluation kernel launch while its pass is
+// timed per kernel (defined with the profiler), else false.
+bool kernel_events(hipEvent_t *start, hipEvent_t *stop);
+// mask: 1 pass A (pointwise kernel + transform), 2 pass B, 4 pass C,
+// 8 pointwise kernel only, 16 pass A transform only
+hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);
 hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_prec(const BatchLaunch &b, hipStream_t s, int mask = 7);  // P r_t, passes A|B|C
 hipError_t launch_opt_update(const BatchLaunch &b, hipStream_t s);

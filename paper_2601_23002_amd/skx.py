@@ -293,7 +293,7 @@ def run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, 
     return [r.as_dict() for r in res]
 
 
-PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond")
+PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond", "point")
 
 
 def profile_enable(on=True):
