@@ -1398,6 +1398,133 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   }
 }
 
+// The Nyquist column (k3 = n3/2) of pass B for batches on k_passBf, one
+// wavefront per y index: the x transform of that column of every field (a
+// radix-8 butterfly per lane per stage), the multipliers and energy terms of
+// its G points, and the energy row k_passB's last column block would write.
+// tile holds NFIELD (N1 + 1) values of this wavefront.
+template <typename R, int N1, int MODE>
+__device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typename Vec2<R>::T *tile,
+                                              const typename Vec2<R>::T *tw1, int lane) {
+  typedef typename Vec2<R>::T V;
+  constexpr int X0 = CRad<N1>::R0, X1 = CRad<N1>::R1;
+  constexpr int TP = N1 + 1;                          // LDS pitch between fields
+  const int kc = S.nh - 1;                            // the Nyquist column
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const size_t rowstride = (size_t)S.n2 * S.pitch;
+  SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + kc;
+  typedef CMap<N1, X0, NFIELD, false> M;              // lane -> (field slot, butterfly)
+  static_assert(M::MB == 1, "one butterfly per lane");
+  {
+    const int b = lane;
+    if (M::ok(b)) {
+      const int t = M::t(b), jj = M::j(b);
+      V v[X0];
+#pragma unroll
+      for (int r = 0; r < X0; ++r) {
+        if (t < nf) v[r] = ldg(spec + (size_t)t * S.H + (size_t)(jj + M::NB * r) * rowstride);
+        else { v[r].x = 0; v[r].y = 0; }
+      }
+      Bfly<X0, false, V>::run(v);
+#pragma unroll
+      for (int r = 0; r < X0; ++r) tile[t * TP + jj * X0 + r] = v[r];
+    }
+  }
+  SKX_WAVE_SYNC();
+  cstage<V, N1, X1, X0, 1, TP, NFIELD, false, false>(tile, tw1, lane);
+  // G points kx = lane of the column
+  const int kx = lane;
+  const int k3 = kc, g1 = gidx(kx, N1), g2 = gidx(jy, S.n2);
+  const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+  const double G2 = S.kscale * (double)sidx;
+  double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
+  if (MODE == MODE_PREC) {
+    const R pg = (R)(1.0 / (G2 + S.kappa));
+    V x = tile[kx];
+    x.x *= pg; x.y *= pg;
+    tile[kx] = x;
+  } else {
+    const unsigned terms = S.terms;
+    const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
+    const bool do_h = terms & 16u, do_loc = terms & 32u;
+    const int sphi = S.slot[0], sn = S.slot[1], sfl = S.slot[2], sh = S.slot[3];
+    const R b3 = (R)(S.beta / 3.0);
+    const double FOURPI = 12.566370614359172954;
+    V vl;
+    vl.x = 0; vl.y = 0;
+    if (do_loc) vl = ldg(gptr<V>(S.vloc) + ((size_t)kx * S.n2 + jy) * S.pitch + k3);
+    double wv = 0.0, wpv = 0.0;
+    if (sfl >= 0) { wv = gptr<double>(S.w)[sidx]; wpv = gptr<double>(S.wp)[sidx]; }
+    // the Nyquist column has weight 1 in the Hermitian sums
+    if (sphi >= 0) {
+      V x = tile[sphi * TP + kx];
+      if (do_vw) evw += G2 * ((double)x.x * x.x + (double)x.y * x.y);
+      const R g2r = (R)G2;
+      x.x *= g2r; x.y *= g2r;
+      tile[sphi * TP + kx] = x;
+    }
+    {
+      const V x = tile[sn * TP + kx];
+      double bx = 0.0, by = 0.0;
+      if (do_h && sidx > 0) {
+        eh += ((double)x.x * x.x + (double)x.y * x.y) / G2;
+        bx = FOURPI * x.x / G2;
+        by = FOURPI * x.y / G2;
+      }
+      if (do_loc) {
+        eloc += (double)x.x * vl.x + (double)x.y * vl.y;
+        bx += vl.x;
+        by += vl.y;
+      }
+      if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
+      V o; o.x = (R)bx; o.y = (R)by;
+      tile[sn * TP + kx] = o;
+    }
+    if (sfl >= 0) {
+      const V f = tile[sfl * TP + kx];
+      const R w = (R)wv, wp = (R)wpv;
+      V P; P.x = 0; P.y = 0;
+      if (do_nl0) {
+        ef0 += (double)w * ((double)f.x * f.x + (double)f.y * f.y);
+        P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
+      }
+      if (sh >= 0) {
+        const V h = tile[sh * TP + kx];
+        ef1 += (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
+        P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
+        V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
+        tile[sh * TP + kx] = Q;
+      }
+      tile[sfl * TP + kx] = P;
+    }
+  }
+  SKX_WAVE_SYNC();
+  cstage<V, N1, X0, 1, 1, TP, NFIELD, false, true>(tile, tw1, lane);
+  {
+    typedef CMap<N1, X1, NFIELD, false> ML;
+    const int b = lane;
+    if (ML::ok(b)) {
+      const int t = ML::t(b), jj = ML::j(b);
+      V v[X1];
+#pragma unroll
+      for (int r = 0; r < X1; ++r) v[r] = tile[t * TP + jj + ML::NB * r];
+      cbfly<V, N1, X1, X0, true>(v, jj, tw1);
+      if (t < nf) {
+#pragma unroll
+        for (int r = 0; r < X1; ++r) stg(spec + (size_t)t * S.H + (size_t)(jj + X0 * r) * rowstride, v[r]);
+      }
+    }
+  }
+  if (MODE == MODE_EVAL) {
+    double vals[PART_B] = {evw, eh, ef0, ef1, eloc, bad};
+#pragma unroll
+    for (int q = 0; q < PART_B; ++q)
+      for (int off = 32; off > 0; off >>= 1) vals[q] += __shfl_down(vals[q], off, 64);
+    if (lane == 0)
+      for (int q = 0; q < PART_B; ++q) S.partB[(jy * S.nkb + S.nkb - 1) * PART_B + q] = vals[q];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass B for x-transforms of a length fixed at compile time (N1), one
 // workgroup of four wavefronts per (y index, block of TK z columns). In
@@ -1417,17 +1544,33 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   constexpr int TP = TK + 1;                       // LDS row pitch of a field tile
   constexpr int SL = MODE == MODE_EVAL ? TK : TK / NW;   // columns per wavefront
   extern __shared__ __align__(16) unsigned char smem[];
+  // every solve of the batch has the same grid: NB blocks of TK columns per
+  // y index
+  // below the Nyquist column, then N1 / NW workgroups whose wavefronts take
+  // the Nyquist column of one y index each
+  constexpr int NB = (N1 / 2) / TK;
+  static_assert((N1 / 2) % TK == 0, "whole column blocks below the Nyquist column");
+  constexpr int PER = N1 * NB + N1 / NW;           // workgroups per solve
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
-  const int s = find_solve(first, nsolve, item);
+  const int s = __builtin_amdgcn_readfirstlane(item / PER);
   const SolveDev &S = dev[s];
   const SKX_C OptState *st = cptr<OptState>(S.st);
   if (!active_phase<MODE>(st->phase)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int local = item - first_of(first, s);
-  const int jy = local / S.nkb, kb = local % S.nkb;
+  const int rem = item - s * PER;
+  if (rem >= N1 * NB) {
+    V *tw = reinterpret_cast<V *>(smem) + NFIELD * N1 * TP;
+    load_twiddles(tw, twbank, S.p1.tw, N1, tid, NT);
+    __syncthreads();
+    passB_nyquist<R, N1, MODE>(S, (rem - N1 * NB) * NW + wave,
+                               reinterpret_cast<V *>(smem) + wave * NFIELD * (N1 + 1), tw, lane);
+    return;
+  }
+  const int jy = rem / NB, kb = rem - (rem / NB) * NB;
+  const int local = jy * S.nkb + kb;                 // energy row, as in k_passB
   const int k0 = kb * TK;
-  const int tkv = min(TK, S.nh - k0);
+  const int tkv = TK;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N1][TP]
   V *tw1 = tile + NFIELD * N1 * TP;
@@ -1899,10 +2042,12 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
       SKX_EVAL_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
                          b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
   }
-  if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
-    SKX_EVAL_LAUNCH((k_passBf<R, 64, TK, MODE_EVAL>), dim3(b.gridB), dim3(256),
+  if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
+    const int gb = b.nsolve * (64 * (32 / TK) + 16);
+    SKX_EVAL_LAUNCH((k_passBf<R, 64, TK, MODE_EVAL>), dim3(gb), dim3(256),
                        (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
-                       b.nsolve, b.gridB, b.twbank);
+                       b.nsolve, gb, b.twbank);
+  }
   else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
     SKX_EVAL_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(b.gridB), dim3(512), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
@@ -1953,10 +2098,12 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   if (b.gridC > 0 && (mask & 1) && b.bigA)
     hipLaunchKernelGGL((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
-  if (b.gridB > 0 && (mask & 2) && (b.shape & 2))
-    hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(b.gridB), dim3(256),
+  if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
+    const int gb = b.nsolve * (64 * (32 / TK) + 16);
+    hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(gb), dim3(256),
                        (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
-                       b.nsolve, b.gridB, b.twbank);
+                       b.nsolve, gb, b.twbank);
+  }
   else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
     hipLaunchKernelGGL((k_passB<R, 512, TK, MODE_PREC>), dim3(b.gridB), dim3(512), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
