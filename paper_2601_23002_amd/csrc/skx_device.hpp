@@ -522,11 +522,11 @@ __device__ __forceinline__ void pz_dense(T rs, T lr, T irs, T &e, T &de) {
   de = PZ<T>::A * irs + PZ<T>::C * lr + PZ<T>::C + PZ<T>::D;
 }
 
-__device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
+// (e3 = n^(1/3) = exp(x/3), computed by the caller)
+__device__ __forceinline__ void pz81_ln_e3(double x, double e3, double &eps, double &v) {
   const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
   const double LNRS1 = -0.47747065276706024;  // ln RS1
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
-  const double e3 = exp(x * (1.0 / 3.0));
   const double rs = RS1 / e3;
   const double ex = -CX / RS1 * e3;
   double ec, dec;
@@ -548,6 +548,10 @@ __device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
   }
   eps = ex + ec;
   v = (4.0 / 3.0) * ex + ec - rs * (1.0 / 3.0) * dec;
+}
+
+__device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
+  pz81_ln_e3(x, exp(x * (1.0 / 3.0)), eps, v);
 }
 
 // Single-precision PZ81 for the FP32 evaluations (the exchange-correlation

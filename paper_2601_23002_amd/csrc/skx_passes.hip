@@ -389,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
   SKX_G R *qps = gptr<R>(S.qpt) + g0;
   SKX_G R *nas = gptr<R>(S.npa) + g0;
   const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
+  const bool a56 = S.a == 5.0 / 6.0;
   const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
   const bool need_f = (S.fields & F_F) != 0, need_h = (S.fields & F_H) != 0;
   constexpr int PER = CHUNK / NT;
@@ -416,11 +417,13 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     phit[e] = ph;
     const R n = ph * ph;
     const double nd = (double)n;
-    double v = 0.0, lx = 0.0;
+    double v = 0.0, lx = 0.0, e3 = 0.0;
     if (!(nd == nd) || nd > 1e300) bad += 1.0;
     if (nd > 0.0) {
       nel += nd;
       lx = log(nd);
+      // FP64: n^(1/3), shared by PZ81 and, for a = 5/6, by n^a
+      if (sizeof(R) == 8 && (do_xc || a56)) e3 = exp(lx * (1.0 / 3.0));
       if (do_tf) {
         double eta, psi;
         bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
@@ -435,7 +438,7 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
           eps = ef;
           vx = vf;
         } else {
-          pz81_ln(lx, eps, vx);
+          pz81_ln_e3(lx, e3, eps, vx);
         }
         e_xc += nd * eps;
         v += vx;
@@ -443,11 +446,18 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     }
     v0s[e] = (R)v;
     if (need_f) {
-      // FP64: n^a = exp(a ln n) with the logarithm taken above
-      const R f = sizeof(R) == 8 ? (nd > 0.0 ? (R)exp((double)a * lx) : (R)0) : rpow(n, a);
+      // FP64: n^a = exp(a ln n) with the logarithm taken above; for a = 5/6,
+      // n^a = |phi| n^(1/3) and c_P = 2 a sign(phi) n^(1/3)
+      R f, cP;
+      if (sizeof(R) == 8 && a56) {
+        f = (R)(fabs((double)ph) * e3);
+        cP = (ph != (R)0) ? (R)copysign((double)a2 * e3, (double)ph) : (R)0;
+      } else {
+        f = sizeof(R) == 8 ? (nd > 0.0 ? (R)exp((double)a * lx) : (R)0) : rpow(n, a);
+        // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
+        cP = (ph != (R)0) ? a2 * f / ph : (R)0;
+      }
       nas[e] = f;
-      // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
-      const R cP = (ph != (R)0) ? a2 * f / ph : (R)0;
       fps[e] = cP;
       if (need_h) qps[e] = cP * (n - n0) + (R)2 * ph * (f - n0a);
     }
