@@ -691,25 +691,16 @@ bool kernel_events(hipEvent_t *start, hipEvent_t *stop) {
 
 namespace host {
 
-// Launch `fn` between two recorded events when profiling is on (the driver
-// launches eagerly then, so every launch has its own pair). The evaluation
-// passes (pointwise kernel, A, B, C) are timed per kernel instead, from
-// events attached to their kernel launches.
+// Time the kernels `fn` launches when profiling is on (the driver launches
+// eagerly then): every kernel launch of the pass carries its own start/stop
+// events (SKX_TIMED_LAUNCH), so no event packet sits between launches.
 template <typename F>
-hipError_t timed(int which, hipStream_t s, F fn) {
+hipError_t timed(int which, hipStream_t, F fn) {
   if (!g_prof.on) return fn();
-  if (which == PP_POINT || which == PP_A || which == PP_B || which == PP_C) {
-    g_prof.kernel_tag = which;
-    g_prof.kernel_pairs = 0;
-    hipError_t e = fn();
-    g_prof.kernel_tag = -1;
-    return e;
-  }
-  hipEvent_t a = prof_event(), b = prof_event();
-  hipEventRecord(a, s);
+  g_prof.kernel_tag = which;
+  g_prof.kernel_pairs = 0;
   hipError_t e = fn();
-  hipEventRecord(b, s);
-  g_prof.pending.push_back({which, 1, a, b});
+  g_prof.kernel_tag = -1;
   return e;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 #include <cstddef>
 
@@ -128,9 +129,19 @@ struct BatchLaunch {
   int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
                                    // 64 x 64 x 64 grids (every solve has that grid)
 };
-// Start/stop events for the next evaluation kernel launch while its pass is
-// timed per kernel (defined with the profiler), else false.
+// Start/stop events for the next kernel launch while its pass is being timed
+// (defined with the profiler), else false.
 bool kernel_events(hipEvent_t *start, hipEvent_t *stop);
+// A kernel launch that carries start/stop events of its own while its pass
+// is being timed, so the time covers the kernel's execution only.
+#define SKX_TIMED_LAUNCH(K, G, B, SH, S, ...)                             \
+  do {                                                                  \
+    hipEvent_t e0_, e1_;                                                \
+    if (::skx::kernel_events(&e0_, &e1_))                               \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, e0_, e1_, 0, __VA_ARGS__);  \
+    else                                                                \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                  \
+  } while (0)
 // mask: 1 pass A (pointwise kernel + transform), 2 pass B, 4 pass C,
 // 8 pointwise kernel only, 16 pass A transform only
 hipError_t launch_eval(const BatchLaunch &b, hipStream_t s, int mask = 7);

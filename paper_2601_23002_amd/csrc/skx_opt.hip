@@ -603,9 +603,9 @@ static hipError_t launch_update_t(const BatchLaunch &b, hipStream_t s) {
   switch (b.mh) {
 #define SKX_UPD(MM)                                                                         \
   case MM:                                                                                  \
-    hipLaunchKernelGGL((k_update<R, 256, MM>), dim3(b.gridU), dim3(256), 0, s, b.dev,         \
+    SKX_TIMED_LAUNCH((k_update<R, 256, MM>), dim3(b.gridU), dim3(256), 0, s, b.dev,        \
                        b.firstU, b.nsolve, b.gridU);                                        \
-    hipLaunchKernelGGL(k_finalize_update<MM>, dim3(b.nsolve), dim3(256), 0, s, b.dev,        \
+    SKX_TIMED_LAUNCH((k_finalize_update<MM>), dim3(b.nsolve), dim3(256), 0, s, b.dev,       \
                        b.nsolve);                                                           \
     break;
     SKX_UPD(1) SKX_UPD(2) SKX_UPD(3) SKX_UPD(4) SKX_UPD(5) SKX_UPD(6) SKX_UPD(7)
@@ -620,14 +620,14 @@ static hipError_t launch_dir_t(const BatchLaunch &b, hipStream_t s) {
   switch (b.mh) {
 #define SKX_DIR(MM)                                                                         \
   case MM:                                                                                  \
-    hipLaunchKernelGGL((k_dir<R, 256, MM>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV,  \
+    SKX_TIMED_LAUNCH((k_dir<R, 256, MM>), dim3(b.gridV), dim3(256), 0, s, b.dev, b.firstV, \
                        b.nsolve, b.gridV);                                                  \
     break;
     SKX_DIR(1) SKX_DIR(2) SKX_DIR(3) SKX_DIR(4) SKX_DIR(5) SKX_DIR(6) SKX_DIR(7)
     default: SKX_DIR(8)
 #undef SKX_DIR
   }
-  hipLaunchKernelGGL(k_finalize_dir, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  SKX_TIMED_LAUNCH(k_finalize_dir, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
   return hipGetLastError();
 }
 
@@ -640,7 +640,7 @@ static hipError_t launch_norm_t(const BatchLaunch &b, hipStream_t s) {
 }
 
 hipError_t launch_finalize_eval(const BatchLaunch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_eval, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
+  SKX_TIMED_LAUNCH(k_finalize_eval, dim3(b.nsolve), dim3(256), 0, s, b.dev, b.nsolve);
   return hipGetLastError();
 }
 

@@ -31,7 +31,6 @@
 //   pass B  multiplied by 1 / (G^2 + kappa);
 //   pass C  transformed back into P r_t.
 #include "skx_device.hpp"
-#include <hip/hip_ext.h>
 #include <math.h>
 
 namespace skx {
@@ -2013,16 +2012,6 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 // ---------------------------------------------------------------------------
 // Launch
 // ---------------------------------------------------------------------------
-// An evaluation kernel launch, with start/stop events attached to the kernel
-// itself while its pass is being timed.
-#define SKX_EVAL_LAUNCH(K, G, B, SH, S, ...)                 \
-  do {                                                      \
-    hipEvent_t e0_, e1_;                                    \
-    if (kernel_events(&e0_, &e1_))                          \
-      hipExtLaunchKernelGGL(K, G, B, SH, S, e0_, e1_, 0, __VA_ARGS__); \
-    else                                                    \
-      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);      \
-  } while (0)
 
 // Runtime-shaped pass B with 512 threads: measured faster in FP32 at every
 // size, and in FP64 once the x tile takes more than half of a CU's LDS (one
@@ -2038,34 +2027,34 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
   // mask: 1 pass A (pointwise kernel and transform), 2 pass B, 4 pass C,
   // 8 the pointwise kernel alone, 16 pass A's transform alone
   if (b.gridA > 0 && (mask & (1 | 8)))
-    SKX_EVAL_LAUNCH((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
+    SKX_TIMED_LAUNCH((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
                        b.firstV, b.nsolve, b.gridV, b.fd);
   if (b.gridA > 0 && (mask & (1 | 16))) {
     if (b.shape & 1)
-      SKX_EVAL_LAUNCH((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
+      SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
                          (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
                          b.twbank);
     else if (b.smallA)
-      SKX_EVAL_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
+      SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                          b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
     if (b.bigA)
-      SKX_EVAL_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
+      SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
                          b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
   }
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
     const int gb = b.nsolve * (64 * (32 / TK) + 16);
-    SKX_EVAL_LAUNCH((k_passBf<R, 64, TK, MODE_EVAL>), dim3(gb), dim3(256),
+    SKX_TIMED_LAUNCH((k_passBf<R, 64, TK, MODE_EVAL>), dim3(gb), dim3(256),
                        (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
                        b.nsolve, gb, b.twbank);
   }
   else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
-    SKX_EVAL_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(b.gridB), dim3(512), b.ldsB, s,
+    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(b.gridB), dim3(512), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   else if (b.gridB > 0 && (mask & 2))
-    SKX_EVAL_LAUNCH((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
+    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4) && (b.shape & 4)) {
-    SKX_EVAL_LAUNCH((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
+    SKX_TIMED_LAUNCH((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   } else if (b.gridC > 0 && (mask & 4) && b.smallC) {
@@ -2075,21 +2064,21 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
     const int fill = b.gridC % (2 * 256);
     if (sizeof(R) == 4 && fill > 0 && fill <= 256) {
       if (b.accC_lds)
-        SKX_EVAL_LAUNCH((k_passC<R, 256, true, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
+        SKX_TIMED_LAUNCH((k_passC<R, 256, true, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
                            s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
       else
-        SKX_EVAL_LAUNCH((k_passC<R, 256, false, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
+        SKX_TIMED_LAUNCH((k_passC<R, 256, false, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
                            s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     } else if (b.accC_lds) {
-      SKX_EVAL_LAUNCH((k_passC<R, NTC, true, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC, s,
+      SKX_TIMED_LAUNCH((k_passC<R, NTC, true, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC, s,
                          b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     } else {
-      SKX_EVAL_LAUNCH((k_passC<R, NTC, false, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC,
+      SKX_TIMED_LAUNCH((k_passC<R, NTC, false, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC,
                          s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
     }
   }
   if (b.gridC > 0 && (mask & 4) && b.bigC)
-    SKX_EVAL_LAUNCH((k_passC_big<R, 512, MODE_EVAL>), dim3(b.gridC), dim3(512), BIG_LDS, s,
+    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_EVAL>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
@@ -2099,36 +2088,36 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   // one field per solve: pass A has one workgroup per plane, like pass C
   if (b.gridC > 0 && (mask & 1) && (b.shape & 1))
-    hipLaunchKernelGGL((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
+    SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   else if (b.gridC > 0 && (mask & 1) && b.smallA)
-    hipLaunchKernelGGL((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
+    SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   if (b.gridC > 0 && (mask & 1) && b.bigA)
-    hipLaunchKernelGGL((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
+    SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
     const int gb = b.nsolve * (64 * (32 / TK) + 16);
-    hipLaunchKernelGGL((k_passBf<R, 64, TK, MODE_PREC>), dim3(gb), dim3(256),
+    SKX_TIMED_LAUNCH((k_passBf<R, 64, TK, MODE_PREC>), dim3(gb), dim3(256),
                        (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
                        b.nsolve, gb, b.twbank);
   }
   else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
-    hipLaunchKernelGGL((k_passB<R, 512, TK, MODE_PREC>), dim3(b.gridB), dim3(512), b.ldsB, s,
+    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_PREC>), dim3(b.gridB), dim3(512), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   else if (b.gridB > 0 && (mask & 2))
-    hipLaunchKernelGGL((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
+    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
                        b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
   if (b.gridC > 0 && (mask & 4) && (b.shape & 4))
-    hipLaunchKernelGGL((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
+    SKX_TIMED_LAUNCH((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
   else if (b.gridC > 0 && (mask & 4) && b.smallC)
-    hipLaunchKernelGGL((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsC, s,
+    SKX_TIMED_LAUNCH((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsC, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   if (b.gridC > 0 && (mask & 4) && b.bigC)
-    hipLaunchKernelGGL((k_passC_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
+    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
                        b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
