@@ -385,7 +385,10 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     if (!(h.big & 2))
       lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
                                     8 * (size_t)h.n2 * h.n3);
-  bl.accC_lds = lc_acc <= LDS_MAX ? 1 : 0;
+  // (only while that leaves room for two workgroups per CU: beyond 80 KB the
+  // accumulation in the output buffer was measured faster, e.g. FP64 96^3
+  // pass C 216 -> 167 us)
+  bl.accC_lds = lc_acc <= 80 * 1024 ? 1 : 0;
   if (bl.accC_lds) lc = std::max(lc, lc_acc);
   bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
   bl.mh = 1;
