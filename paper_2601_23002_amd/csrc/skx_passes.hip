@@ -2019,6 +2019,10 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 template <typename R> static bool wide_b(const BatchLaunch &b) {
   return sizeof(R) == 4 || b.ldsB > 80 * 1024;
 }
+// Runtime-shaped pass A with 512 threads once its plane takes more than
+// 45 KB of LDS (measured: FP64 96^3 177 -> 161 us, 128^3 540 -> 442 us;
+// FP32 108^3 157 -> 144 us; smaller planes are faster with 256).
+static bool wide_a(const BatchLaunch &b) { return b.ldsA > 45 * 1024; }
 
 template <typename R>
 static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
@@ -2034,6 +2038,9 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
       SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
                          (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
                          b.twbank);
+    else if (b.smallA && wide_a(b))
+      SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), b.ldsA, s, b.dev,
+                         b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
     else if (b.smallA)
       SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
                          b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
@@ -2091,6 +2098,9 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
     SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
                        (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
                        b.twbank);
+  else if (b.gridC > 0 && (mask & 1) && b.smallA && wide_a(b))
+    SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s, b.dev,
+                       b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
   else if (b.gridC > 0 && (mask & 1) && b.smallA)
     SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
                        b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
