@@ -720,9 +720,10 @@ __global__ __launch_bounds__(NT) void k_passB(SolveDev *dev, const int *first, i
         double bx = 0.0, by = 0.0;
         if (do_h && sidx > 0) {
           const double m2 = (double)x.x * x.x + (double)x.y * x.y;
-          eh += wgt * m2 / G2;
-          bx = FOURPI * x.x / G2;
-          by = FOURPI * x.y / G2;
+          const double ig = 1.0 / G2;
+          eh += wgt * m2 * ig;
+          bx = FOURPI * ig * x.x;
+          by = FOURPI * ig * x.y;
         }
         if (do_loc) {
           const V vl = vlb[u];
@@ -1255,9 +1256,13 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   V *buf = reinterpret_cast<V *>(smem);
   V *tw2 = buf + N2 * PL;
   V *tw3 = tw2 + N2;
-  load_twiddles(tw2, twbank, S.p2.tw, N2, tid, NT);
-  load_twiddles(tw3, twbank, S.p3.tw, N3, tid, NT);
-  __syncthreads();
+  // both twiddle tables (tw3 follows tw2) are fetched into registers here
+  // and written to LDS after the first z stage, so their latency overlaps
+  // that of the stage's HBM loads
+  static_assert(N2 + N3 <= NT, "one twiddle per thread");
+  const bool has_tw = tid < N2 + N3;
+  double2 twv = make_double2(0.0, 0.0);
+  if (has_tw) twv = ldg(gptr<double2>(twbank) + (tid < N2 ? S.p2.tw + tid : S.p3.tw + tid - N2));
   const R invM = (R)(1.0 / (double)S.M);
   const size_t pbase = (size_t)plane * N2 * N3;
   V *zb = buf + wave * ZP * 2 * PL;
@@ -1324,7 +1329,8 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
         for (int r = 0; r < R0; ++r) out[r] = v[i][r];
       }
     }
-    SKX_WAVE_SYNC();
+    if (has_tw) { V t; t.x = twv.x; t.y = twv.y; tw2[tid] = t; }
+    __syncthreads();
   }
   cstage<V, N3, R1, R0, 1, 2 * PL, ZP, false, false>(zb, tw3, lane);
   {
@@ -1583,8 +1589,6 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N1][TP]
   V *tw1 = tile + NFIELD * N1 * TP;
-  load_twiddles(tw1, twbank, S.p1.tw, N1, tid, NT);
-  __syncthreads();
   SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + k0;
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   const int cc = MODE == MODE_EVAL ? wave : 0;       // field slot of this wavefront
@@ -1593,9 +1597,10 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   V *tf = tile + cc * N1 * TP + c0;
   SKX_G V *sf = spec + (size_t)cc * S.H + c0;
   const int cv = tkv - c0;                           // valid columns from c0
+  typedef CMap<N1, X0, SL, true> M0;
+  V v[M0::MB][X0];
   if (active) {
-    typedef CMap<N1, X0, SL, true> M;
-    V v[M::MB][X0];
+    typedef M0 M;
 #pragma unroll
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
@@ -1608,6 +1613,12 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
         }
       }
     }
+  }
+  // the twiddle table is loaded while the spectrum loads are in flight
+  load_twiddles(tw1, twbank, S.p1.tw, N1, tid, NT);
+  __syncthreads();
+  if (active) {
+    typedef M0 M;
 #pragma unroll
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
@@ -1685,9 +1696,10 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
         double bx = 0.0, by = 0.0;
         if (do_h && sidx > 0) {
           const double m2 = (double)x.x * x.x + (double)x.y * x.y;
-          eh += wgt * m2 / G2;
-          bx = FOURPI * x.x / G2;
-          by = FOURPI * x.y / G2;
+          const double ig = 1.0 / G2;
+          eh += wgt * m2 * ig;
+          bx = FOURPI * ig * x.x;
+          by = FOURPI * ig * x.y;
         }
         if (do_loc) {
           const V vl = vlb[u];
