@@ -20,6 +20,7 @@ Modules:
   ions       local pseudopotential via the structure factor, Ewald sum
   functional energy terms and dE/dphi on the periodic grid
   optimize   L-BFGS on sqrt(n) with the electron-count constraint
+  forces     forces on the ions: local pseudopotential and Ewald
 
 Parity status per function is stated in each module header. The only
 functions without an independent pin ("parity unpinned") are the PZ81
