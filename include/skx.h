@@ -164,6 +164,25 @@ int skx_optimize_density(skx_ctx *ctx, void *rho_dev, const skx_opt_params *p,
 int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_params *p,
                   skx_opt_result *res);
 
+/* Forces on the ions for molecular dynamics (Methods, molecular dynamics in
+ * the NVT ensemble; the paper gives no force formula). At the minimising
+ * density the energy is stationary in n at fixed N_e, so the force on ion I
+ * is f_loc[I] + f_ii[I] (Hellmann-Feynman), in Hartree/bohr:
+ *   f_loc: the local pseudopotential's force -dE_loc/dR_I from the density,
+ *     sum over the grid's G of G v_I(G) Im[exp(i G.R_I) n~(G)];
+ *   f_ii:  the Ewald ion-ion force -dE_ii/dR_I (same split as the energy).
+ * in_dev: FP64 device field on the cell's grid, n (SKX_RHO) or phi = sqrt(n)
+ *   (SKX_SQRT_RHO); read only; may be NULL when f_loc is NULL.
+ * f_loc, f_ii: host arrays [nions][3] (ion order of skx_set_ions), either
+ *   may be NULL, not both. Works in FP64 whatever the functional's precision.
+ * Needs set_cell and set_ions (not set_functional). Allocates and frees a
+ * scratch buffer of about 24 nions (n1 n2 / 256 + n1 + n2 + n3) bytes on
+ * the ctx stream; synchronises it.
+ * Errors: SKX_E_STATE (no cell or ions), SKX_E_INVALID (no output, missing
+ * field, bad in_kind, a grid the FP64 plane kernels cannot take),
+ * SKX_E_NOMEM / SKX_E_DEVICE. */
+int skx_ion_forces(skx_ctx *ctx, const void *in_dev, int in_kind, double *f_loc, double *f_ii);
+
 /* ---- introspection (tests and tools) ---- */
 
 /* Copy the shell tables w[s], w'[s], s = g1^2+g2^2+g3^2 = 0..len-1, to host. */
@@ -178,7 +197,8 @@ int skx_fd_eval(int device, const double *u_host, double *eta_host, double *psi_
 /* Forward then inverse transform of a host real field through the GPU FFT
  * passes (spectral multipliers off); returns the round trip in out_host and
  * the half spectrum [n1][n2][n3/2+1] complex (FP64 pairs, normalised 1/M)
- * in spec_host (may be NULL). Cell must be set. */
+ * in spec_host (may be NULL). Cell must be set; SKX_E_INVALID for grids
+ * whose FP64 planes exceed LDS. */
 int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double *spec_host);
 
 /* ---- instrumentation ---- */

@@ -335,7 +335,9 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     const bool bigA = forced || a > LDS_MAX || (prec == 1 && plane > 80 * 1024);
     const bool bigC = forced || cc > LDS_MAX || (prec == 1 && plane > 24 * 1024);
     h.big = (bigA ? 1 : 0) | (bigC ? 2 : 0);
-    if (h.debug) h.big = 0;
+    // the forward-only check (debug 1) keeps the chunked pass A; the
+    // chunked pass C has no check mode
+    if (h.debug) h.big &= h.debug == 1 ? 1 : 0;
   }
   std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1), fu(n + 1);
   fa[0] = fb[0] = fc[0] = fv[0] = fu[0] = 0;
@@ -351,7 +353,8 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     lds_sizes(h, prec, a, b, cc);
     lb = std::max(lb, b);
     if (!(h.big & 1)) la = std::max(la, a);
-    if (!(h.big & 2)) lc = std::max(lc, cc);
+    // the forward-only check (debug 1) launches no pass C
+    if (!(h.big & 2) && h.debug != 1) lc = std::max(lc, cc);
   }
   if (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX)
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
@@ -1204,6 +1207,12 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
   if (rc) return rc;
   Instance &I = c->inst[0];
   SolveDev h = I.h;
+  {
+    // the inverse check runs the in-LDS pass C
+    size_t a, b, cc;
+    lds_sizes(h, 0, a, b, cc);
+    if (cc > LDS_MAX) return fail(c, SKX_E_INVALID, "the FFT check needs FP64 planes that fit LDS");
+  }
   h.fields = F_PHI | F_N;
   h.nf = 2;
   h.slot[0] = 0; h.slot[1] = 1; h.slot[2] = -1; h.slot[3] = -1;
@@ -1236,6 +1245,89 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
     e = hipMemcpyAsync(out_host, h.grad, sizeof(double) * M, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(c, e, "inverse passes");
+  return SKX_OK;
+}
+
+int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, double *f_ii) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!f_loc && !f_ii) return fail(c, SKX_E_INVALID, "no force output requested");
+  if (f_loc && !in_dev) return fail(c, SKX_E_INVALID, "the local force needs the density");
+  if (f_loc && in_kind != SKX_RHO && in_kind != SKX_SQRT_RHO) return fail(c, SKX_E_INVALID, "bad in_kind");
+  if (!c->has_cell || !c->has_ions) return fail(c, SKX_E_STATE, "set_cell and set_ions must precede this call");
+  hipSetDevice(c->device);
+  hipStream_t s = c->stream;
+  const int nions = (int)c->species.size();
+  const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
+  const int nblk = force_row_blocks(n1, n2);
+  const int ng = ewald_force_terms(c->L);
+  // one scratch allocation: [f_loc | f_ii] (2 nions x 3), ordered sums,
+  // phase tables, structure factor, species order
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t n_out = 6 * (size_t)nions, n_part = (size_t)nions * nblk * 3;
+  const size_t n_ph = (size_t)nions * (n1 + n2 + nh);
+  const size_t o_part = al(sizeof(double) * n_out), o_ph = o_part + al(sizeof(double) * n_part);
+  const size_t o_sf = o_ph + al(sizeof(double2) * n_ph), o_ord = o_sf + al(sizeof(double2) * ng);
+  const size_t bytes = o_ord + al(sizeof(int) * nions);
+  char *scr = nullptr;
+  hipError_t e = hipMallocAsync((void **)&scr, bytes, s);
+  if (e != hipSuccess) return hip_fail(c, e, "force scratch allocation");
+  double *out = reinterpret_cast<double *>(scr);
+  double *part = reinterpret_cast<double *>(scr + o_part);
+  double2 *ph = reinterpret_cast<double2 *>(scr + o_ph);
+  double2 *sf = reinterpret_cast<double2 *>(scr + o_sf);
+  int *order = reinterpret_cast<int *>(scr + o_ord);
+  int rc = SKX_OK;
+  if (f_loc) {
+    // the density's half spectrum: pass A and pass B's forward x transform
+    // of the fields (phi, n) in the FP64 instance, as in the FFT check
+    rc = check_grid(c, 0);
+    if (rc == SKX_OK) rc = ensure_instance(c, 0, 1);
+    if (rc != SKX_OK) { hipFreeAsync(scr, s); return rc; }
+    Instance &I = c->inst[0];
+    SolveDev h = I.h;
+    h.fields = F_PHI | F_N;
+    h.nf = 2;
+    h.slot[0] = 0; h.slot[1] = 1; h.slot[2] = -1; h.slot[3] = -1;
+    h.terms = 0;
+    h.L = c->L; h.V = c->L * c->L * c->L; h.dV = h.V / (double)h.M;
+    h.ne = 1.0; h.n0 = 1.0; h.a = 1.0; h.n0a = 1.0; h.T = 1.0; h.beta = 0.0;
+    h.debug = 1;
+    if (in_kind == SKX_SQRT_RHO)
+      h.phi2[0] = const_cast<void *>(in_dev);
+    else
+      hipLaunchKernelGGL(k_sqrt_field, dim3(blocks(h.M, 256)), dim3(256), 0, s,
+                         (const double *)in_dev, (double *)h.phi2[0], h.M);
+    OptState st{};
+    st.phase = PH_EVAL_ONLY;
+    e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+    std::vector<SolveDev> hs(1, h);
+    if (e == hipSuccess) rc = build_batch(c, hs, 0, I.dptr, I.first, I.bl, s);
+    if (e == hipSuccess && rc == SKX_OK) e = launch_eval(I.bl, s, 3);
+    // ions sorted by species: the form factor is computed once per run
+    std::vector<int> ord(nions);
+    for (int i = 0; i < nions; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int x, int y) { return c->species[x] < c->species[y]; });
+    if (e == hipSuccess && rc == SKX_OK)
+      e = hipMemcpyAsync(order, ord.data(), sizeof(int) * nions, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && rc == SKX_OK) e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
+    if (e == hipSuccess && rc == SKX_OK)
+      e = local_forces(reinterpret_cast<const double2 *>(h.spec) + h.H, n1, n2, n3, h.pitch, c->L, ph,
+                       order, nions, c->ion_sp, c->sp_z, c->sp_rc, part, out, s);
+    if (e == hipSuccess && rc == SKX_OK) e = hipStreamSynchronize(s);
+  }
+  if (e == hipSuccess && rc == SKX_OK && f_ii)
+    e = ewald_forces(c->L, nions, c->ion_pos, c->ion_z, sf, out + 3 * (size_t)nions, s);
+  if (e == hipSuccess && rc == SKX_OK && f_loc)
+    e = hipMemcpyAsync(f_loc, out, sizeof(double) * 3 * nions, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && rc == SKX_OK && f_ii)
+    e = hipMemcpyAsync(f_ii, out + 3 * (size_t)nions, sizeof(double) * 3 * nions,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFreeAsync(scr, s);
+  if (rc != SKX_OK) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "force kernels");
   return SKX_OK;
 }
 

@@ -401,6 +401,16 @@ __global__ void k_vloc(void *vloc_v, int n1, int n2, int n3, int nh, int pitch, 
   vloc[((size_t)k1 * n2 + k2) * pitch + k3] = out;
 }
 
+hipError_t ion_phase_tables(double2 *ph, int nions, const double *pos_dev, int n1, int n2, int n3,
+                            double L, hipStream_t s) {
+  const int nh = n3 / 2 + 1;
+  const long long ntab = (long long)nions * (n1 + n2 + nh);
+  if (ntab > 0)
+    hipLaunchKernelGGL(k_phase_tables, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0, s, ph,
+                       nions, pos_dev, n1, n2, nh, n3, L);
+  return hipGetLastError();
+}
+
 hipError_t build_vloc(void *vloc, int prec, int n1, int n2, int n3, int pitch, double L,
                       int nions, const double *pos_dev, const int *species_dev, int nspecies,
                       const double *zval_dev, const double *rc_dev, double2 *phase_scratch,

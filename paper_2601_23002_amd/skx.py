@@ -101,6 +101,7 @@ _sig("skx_evaluate_energy_potential", C.c_int, [_VP, _VP, C.c_int, _VP, C.POINTE
 _sig("skx_optimize_density", C.c_int, [_VP, _VP, C.POINTER(OptParams), C.POINTER(OptResult)])
 _sig("skx_run_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(OptParams),
                                 C.POINTER(OptResult)])
+_sig("skx_ion_forces", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -208,6 +209,7 @@ class Context:
         self._check(_lib.skx_set_ions(self._h, len(pos), _dptr(pos),
                                       species.ctypes.data_as(C.POINTER(C.c_int)), len(zsp),
                                       _dptr(zsp), _dptr(rsp)))
+        self.nions = len(pos)
 
     def set_functional(self, T, beta=1.0, alpha=5.0 / 6.0, terms=TERM_ALL, xc=XC_PZ81,
                        precision=FP64):
@@ -248,6 +250,21 @@ class Context:
         rc = _lib.skx_optimize_density(self._h, _VP(rho.data_ptr()), C.byref(p), C.byref(r))
         self._check(rc)
         return rho, r.as_dict()
+
+    def ion_forces(self, field=None, kind=SQRT_RHO, local=True, ewald=True):
+        """Forces on the ions (Hartree/bohr): (f_loc, f_ii), each [nions][3]
+        or None when not asked for. field: contiguous FP64 CUDA tensor on
+        the cell's grid, the density (RHO) or its square root (SQRT_RHO)."""
+        torch = _torch()
+        if local and (field is None or field.dtype != torch.float64 or not field.is_cuda
+                      or not field.is_contiguous()):
+            raise ValueError("field must be a contiguous float64 CUDA tensor")
+        fl = np.zeros((self.nions, 3)) if local else None
+        fi = np.zeros((self.nions, 3)) if ewald else None
+        self._check(_lib.skx_ion_forces(
+            self._h, _VP(field.data_ptr()) if local else None, kind,
+            _dptr(fl) if local else None, _dptr(fi) if ewald else None))
+        return fl, fi
 
     def kernel_tables(self):
         ns = _lib.skx_num_shells(self._h)

@@ -1,0 +1,152 @@
+"""Forces on the ions through the C ABI (skx_ion_forces) against the oracle.
+
+The local pseudopotential force is compared on the same FP64 density (a
+seeded random one, and the GPU's own minimising density of the 64-ion 64^3
+case), the Ewald force on the same ions. Tolerance 1e-10 of the largest
+force component, the FP64 target of the path. The last case checks the
+Hellmann-Feynman reading itself on the GPU: at the minimum, f_loc + f_ii
+equals minus the finite-difference derivative of the minimised total energy.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_23002_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2601_23002_amd import skx
+    return skx, torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_system(n, nions=6, seed=21):
+    rng = np.random.default_rng(seed)
+    zval = rng.choice([1.0, 4.0], nions)
+    rc = np.where(zval > 1.0, 0.5, 0.3)
+    L = W.cell_side(float(np.sum(zval)), 1.7)
+    pos = rng.uniform(0.0, L, size=(nions, 3))
+    return L, pos, zval, rc
+
+
+def _ctx(skx, L, n, pos, zval, rc):
+    c = skx.Context(0)
+    c.set_cell(L, n)
+    c.set_ions(pos, zval, rc)
+    return c
+
+
+@pytest.mark.parametrize("n", [(16, 24, 20), (24, 24, 24), (16, 160, 160)])
+def test_local_and_ewald_forces_match_oracle(n):
+    """Random positive density; (16, 160, 160) has FP64 planes beyond LDS,
+    so pass A runs its chunked kernel."""
+    skx, torch = _lib()
+    from oracle import forces
+    _say(f"case: forces grid {n}")
+    L, pos, zval, rc = _mixed_system(n)
+    rng = np.random.default_rng(22)
+    dens = 0.02 + 0.2 * rng.random(n)
+    c = _ctx(skx, L, n, pos, zval, rc)
+    rho = torch.tensor(dens, dtype=torch.float64, device="cuda:0")
+    f_loc, f_ii = c.ion_forces(rho, kind=skx.RHO)
+    ref_loc = forces.local_forces(L, n, dens, pos, zval, rc)
+    ref_ii = forces.ewald_forces(L, pos, zval)
+    assert np.max(np.abs(f_loc - ref_loc)) < 1e-10 * np.max(np.abs(ref_loc))
+    assert np.max(np.abs(f_ii - ref_ii)) < 1e-10 * np.max(np.abs(ref_ii))
+    # the same density handed over as its square root
+    g_loc, g_ii = c.ion_forces(torch.sqrt(rho), kind=skx.SQRT_RHO, ewald=False)
+    assert g_ii is None
+    assert np.max(np.abs(g_loc - f_loc)) < 1e-12 * np.max(np.abs(ref_loc))
+
+
+def test_forces_at_the_minimum_of_the_64_ion_scan_case():
+    skx, torch = _lib()
+    from oracle import forces
+    _say("case: forces 64 ions 64^3 at the GPU minimum")
+    s = W.uniform_system(64, 1.0, 0.3, 2.0, 2.0, 64, seed=2)
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-8, max_iter=500)
+    assert r["status"] == skx.OK
+    f_loc, f_ii = c.ion_forces(rho, kind=skx.RHO)
+    dens = rho.cpu().numpy()
+    ref_loc = forces.local_forces(s.L, s.n, dens, s.pos, s.zval, s.rc)
+    ref_ii = forces.ewald_forces(s.L, s.pos, s.zval)
+    assert np.max(np.abs(f_loc - ref_loc)) < 1e-10 * np.max(np.abs(ref_loc))
+    assert np.max(np.abs(f_ii - ref_ii)) < 1e-10 * np.max(np.abs(ref_ii))
+    # the Ewald forces sum to zero (Newton's third law)
+    assert np.max(np.abs(f_ii.sum(axis=0))) < 1e-9 * np.max(np.abs(f_ii))
+
+
+def test_ewald_force_of_one_ion_and_of_a_lattice_vanish():
+    skx, _ = _lib()
+    _say("case: forces one ion, bcc lattice")
+    c = _ctx(skx, 7.0, (16, 16, 16), np.array([[1.0, 2.0, 3.0]]), [4.0], [0.5])
+    _, f_ii = c.ion_forces(local=False)
+    assert np.max(np.abs(f_ii)) < 1e-12
+    g = np.arange(2) * 4.0
+    sc = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    bcc = np.concatenate([sc, sc + 2.0])
+    c = _ctx(skx, 8.0, (16, 16, 16), bcc, [1.0] * 16, [0.3] * 16)
+    _, f_ii = c.ion_forces(local=False)
+    assert np.max(np.abs(f_ii)) < 1e-10
+
+
+def test_forces_are_minus_the_gradient_of_the_minimised_energy():
+    """Hellmann-Feynman on the GPU: f_loc + f_ii at the minimum against a
+    central difference of the minimised total energy (warm-started solves
+    with ion 0 moved by +-h along each axis)."""
+    skx, torch = _lib()
+    _say("case: forces vs energy difference, 8 ions 32^3")
+    s = W.uniform_system(8, 1.0, 0.4, 2.0, 1.0, 32, seed=23)
+    gtol = 1e-9
+
+    def solve(pos, rho0=None):
+        c = skx.Context(0)
+        c.set_cell(s.L, s.n)
+        c.set_ions(pos, s.zval, s.rc)
+        c.set_functional(s.T, s.beta, s.alpha, s.terms, skx.XC_PZ81, skx.FP64)
+        rho, r = c.optimize(gtol=gtol, max_iter=2000, rho0=rho0)
+        assert r["status"] == skx.OK
+        return c, rho, r["energy"]["total"]
+
+    c0, rho0, _ = solve(s.pos)
+    f_loc, f_ii = c0.ion_forces(rho0, kind=skx.RHO)
+    F = f_loc[0] + f_ii[0]
+    h = 2e-3
+    fd = np.zeros(3)
+    for a in range(3):
+        p = s.pos.copy(); p[0, a] += h
+        m = s.pos.copy(); m[0, a] -= h
+        fd[a] = -(solve(p, rho0)[2] - solve(m, rho0)[2]) / (2 * h)
+    assert np.max(np.abs(F - fd)) < 1e-4 * np.max(np.abs(F)) + 1e-7
+
+
+def test_force_call_errors():
+    skx, torch = _lib()
+    _say("case: force errors")
+    c = skx.Context(0)
+    c.set_cell(7.0, (16, 16, 16))
+    with pytest.raises(skx.SkxError) as e:
+        c.nions = 1
+        c.ion_forces(local=False)
+    assert e.value.code == skx.E_STATE
+    c.set_ions(np.array([[1.0, 2.0, 3.0]]), [1.0], [0.3])
+    rho = torch.full((16, 16, 16), 0.1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(skx.SkxError) as e:
+        c.ion_forces(rho, local=False, ewald=False)
+    assert e.value.code == skx.E_INVALID
+    with pytest.raises(skx.SkxError) as e:
+        c.ion_forces(rho, kind=7)
+    assert e.value.code == skx.E_INVALID
+    with pytest.raises(ValueError):
+        c.ion_forces(rho.float())
