@@ -183,6 +183,24 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
  * SKX_E_NOMEM / SKX_E_DEVICE. */
 int skx_ion_forces(skx_ctx *ctx, const void *in_dev, int in_kind, double *f_loc, double *f_ii);
 
+/* One velocity-Verlet step of the ions on the free-energy surface of the
+ * functional (the paper's molecular dynamics, Methods; NVE here, no
+ * thermostat), the density warm-started from the previous minimum:
+ *   v += (dt/2) F/m;  R += dt v (wrapped into the cell);  minimise the
+ *   density from rho_dev (skx_optimize_density, warm_start forced);
+ *   F = f_loc + f_ii at the new minimum (skx_ion_forces);  v += (dt/2) F/m.
+ * pos, vel, force: host [nions][3] in bohr, bohr per atomic time unit and
+ *   Hartree/bohr, updated in place; force must hold the forces at pos on
+ *   entry (skx_ion_forces at the current minimum).
+ * mass: host [nspecies], electron masses. dt in atomic time units.
+ * rho_dev: FP64 device density, the current minimum on entry, the new one
+ *   on exit. p, res: as skx_optimize_density.
+ * Returns SKX_OK or SKX_NOT_CONVERGED (the step is completed with the best
+ * density) or an error of the calls above; SKX_E_INVALID for null
+ * arguments, dt <= 0 or a non-positive mass. */
+int skx_md_step(skx_ctx *ctx, void *rho_dev, double *pos, double *vel, double *force,
+                const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res);
+
 /* ---- introspection (tests and tools) ---- */
 
 /* Copy the shell tables w[s], w'[s], s = g1^2+g2^2+g3^2 = 0..len-1, to host. */

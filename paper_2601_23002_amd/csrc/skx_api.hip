@@ -947,6 +947,7 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
   c->zsp.assign(zval, zval + nspecies);
   c->rcsp.assign(rc, rc + nspecies);
   c->nspecies = nspecies;
+  const double ne_old = c->ne;
   c->ne = ne;
   std::vector<double> zi(nions);
   for (int i = 0; i < nions; ++i) zi[i] = zval[species[i]];
@@ -991,8 +992,9 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
     const double V = L * L * L;
     c->e_ii = parts[0] + parts[1] - alpha / std::sqrt(M_PI) * z2 - M_PI * ne * ne / (2.0 * V * alpha * alpha);
   }
+  // the kernel tables depend on n0 = N_e / V only
+  if (!c->has_ions || ne != ne_old) c->tables_ok = false;
   c->has_ions = true;
-  c->tables_ok = false;            // n0 changed
   for (auto &I : c->inst) I.vloc_ok = false;
   return SKX_OK;
 }
@@ -1329,6 +1331,49 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   if (rc != SKX_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "force kernels");
   return SKX_OK;
+}
+
+int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
+                const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!rho_dev || !pos || !vel || !force || !mass || !p || !res)
+    return fail(c, SKX_E_INVALID, "null argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, SKX_E_INVALID, "dt must be positive");
+  if (!c->has_cell || !c->has_ions || !c->has_fn)
+    return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
+  const int nions = (int)c->species.size();
+  for (int k = 0; k < c->nspecies; ++k)
+    if (!(mass[k] > 0) || !std::isfinite(mass[k])) return fail(c, SKX_E_INVALID, "masses must be positive");
+  // half kick and drift (positions are wrapped into the cell by set_ions)
+  for (int i = 0; i < nions; ++i) {
+    const double m = mass[c->species[i]];
+    for (int a = 0; a < 3; ++a) {
+      vel[3 * i + a] += 0.5 * dt * force[3 * i + a] / m;
+      pos[3 * i + a] += dt * vel[3 * i + a];
+    }
+  }
+  const std::vector<int> sp(c->species);
+  const std::vector<double> z(c->zsp), r(c->rcsp);
+  int rc = skx_set_ions(c, nions, pos, sp.data(), (int)z.size(), z.data(), r.data());
+  if (rc != SKX_OK) return rc;
+  for (int i = 0; i < 3 * nions; ++i) pos[i] = c->pos[i];
+  skx_opt_params q = *p;
+  q.warm_start = 1;
+  rc = skx_optimize_density(c, rho_dev, &q, res);
+  if (rc < 0) return rc;
+  const int status = rc;
+  std::vector<double> fl(3 * (size_t)nions), fi(3 * (size_t)nions);
+  rc = skx_ion_forces(c, rho_dev, SKX_RHO, fl.data(), fi.data());
+  if (rc != SKX_OK) return rc;
+  for (int i = 0; i < nions; ++i) {
+    const double m = mass[c->species[i]];
+    for (int a = 0; a < 3; ++a) {
+      force[3 * i + a] = fl[3 * i + a] + fi[3 * i + a];
+      vel[3 * i + a] += 0.5 * dt * force[3 * i + a] / m;
+    }
+  }
+  return status;
 }
 
 int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_params *p,

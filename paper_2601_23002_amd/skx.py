@@ -102,6 +102,9 @@ _sig("skx_optimize_density", C.c_int, [_VP, _VP, C.POINTER(OptParams), C.POINTER
 _sig("skx_run_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(OptParams),
                                 C.POINTER(OptResult)])
 _sig("skx_ion_forces", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)])
+_sig("skx_md_step", C.c_int, [_VP, _VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                              C.POINTER(OptParams), C.POINTER(OptResult)])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -210,6 +213,8 @@ class Context:
                                       species.ctypes.data_as(C.POINTER(C.c_int)), len(zsp),
                                       _dptr(zsp), _dptr(rsp)))
         self.nions = len(pos)
+        self.nspecies = len(zsp)
+        self.species_zrc = list(zip(zsp.tolist(), rsp.tolist()))   # (Z, rc) per species index
 
     def set_functional(self, T, beta=1.0, alpha=5.0 / 6.0, terms=TERM_ALL, xc=XC_PZ81,
                        precision=FP64):
@@ -265,6 +270,25 @@ class Context:
             self._h, _VP(field.data_ptr()) if local else None, kind,
             _dptr(fl) if local else None, _dptr(fi) if ewald else None))
         return fl, fi
+
+    def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
+                fp32_switch_gtol=1e-5):
+        """One velocity-Verlet step; pos, vel, force (float64 [nions][3]
+        arrays) are updated in place, rho (FP64 CUDA density) too. mass per
+        species in electron masses. Returns the solve's result dict."""
+        for a in (pos, vel, force):
+            if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+                    and a.shape == (self.nions, 3)):
+                raise ValueError("pos, vel and force must be C-contiguous float64 [nions][3] arrays")
+        mass = np.ascontiguousarray(mass, dtype=np.float64).reshape(-1)
+        if mass.size != self.nspecies:
+            raise ValueError("one mass per species")
+        p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1)
+        r = OptResult()
+        rc = _lib.skx_md_step(self._h, _VP(rho.data_ptr()), _dptr(pos), _dptr(vel), _dptr(force),
+                              _dptr(mass), dt, C.byref(p), C.byref(r))
+        self._check(rc)
+        return r.as_dict()
 
     def kernel_tables(self):
         ns = _lib.skx_num_shells(self._h)

@@ -150,3 +150,71 @@ def test_force_call_errors():
     assert e.value.code == skx.E_INVALID
     with pytest.raises(ValueError):
         c.ion_forces(rho.float())
+
+
+M_PROTON = 1836.15267343      # proton mass in electron masses
+
+
+def _md_start(skx, torch, seed=31, nions=8, n=32):
+    s = W.uniform_system(nions, 1.0, 0.4, 2.0, 1.0, n, seed=seed)
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-9, max_iter=2000)
+    assert r["status"] == skx.OK
+    f_loc, f_ii = c.ion_forces(rho, kind=skx.RHO)
+    rng = np.random.default_rng(seed + 1)
+    vel = rng.normal(0.0, np.sqrt(0.1 / M_PROTON), size=(nions, 3))
+    vel -= vel.mean(axis=0)
+    return s, c, rho, np.ascontiguousarray(s.pos.copy()), vel, f_loc + f_ii, r["energy"]["total"]
+
+
+def test_md_step_equals_its_pieces():
+    """skx_md_step against the same velocity-Verlet step written out here
+    from the separately tested calls (set_ions, warm-started optimize,
+    ion_forces) on a second context."""
+    skx, torch = _lib()
+    _say("case: md step vs pieces, 8 H 32^3")
+    s, c, rho, pos, vel, F, _ = _md_start(skx, torch)
+    dt = 4.0
+    rho2 = rho.clone()
+    pos2, vel2, F2 = pos.copy(), vel.copy(), F.copy()
+    r = c.md_step(rho, pos, vel, F, [M_PROTON], dt, gtol=1e-9, max_iter=2000)
+    assert r["status"] == skx.OK
+    # the same step from the pieces
+    vel2 += 0.5 * dt * F2 / M_PROTON
+    pos2 += dt * vel2
+    pos2 -= s.L * np.floor(pos2 / s.L)
+    c2 = skx.Context(0)
+    c2.set_cell(s.L, s.n)
+    c2.set_ions(pos2, s.zval, s.rc)
+    c2.set_functional(s.T, s.beta, s.alpha, s.terms, skx.XC_PZ81, skx.FP64)
+    rho2, r2 = c2.optimize(gtol=1e-9, max_iter=2000, rho0=rho2)
+    fl, fi = c2.ion_forces(rho2, kind=skx.RHO)
+    F2 = fl + fi
+    vel2 += 0.5 * dt * F2 / M_PROTON
+    assert np.max(np.abs(pos - pos2)) < 1e-12 * s.L
+    assert np.max(np.abs(F - F2)) < 1e-10 * np.max(np.abs(F2))
+    assert np.max(np.abs(vel - vel2)) < 1e-10 * np.max(np.abs(vel2))
+    assert r["iters"] == r2["iters"]
+    assert abs(r["energy"]["total"] - r2["energy"]["total"]) < 1e-12 * abs(r2["energy"]["total"])
+
+
+def test_md_conserves_free_energy_plus_kinetic_energy():
+    """Born-Oppenheimer NVE dynamics conserves F[n_min(R)] + sum m v^2 / 2;
+    a wrong force (sign, factor, missing term) breaks this within a few
+    steps while the kinetic energy itself changes by much more."""
+    skx, torch = _lib()
+    _say("case: md energy conservation, 8 H 32^3, 30 steps")
+    s, c, rho, pos, vel, F, E = _md_start(skx, torch, seed=41)
+    dt = 4.0
+    ke = [0.5 * M_PROTON * float(np.sum(vel * vel))]
+    etot = [E + ke[0]]
+    for _ in range(30):
+        r = c.md_step(rho, pos, vel, F, [M_PROTON], dt, gtol=1e-9, max_iter=2000)
+        assert r["status"] == skx.OK
+        ke.append(0.5 * M_PROTON * float(np.sum(vel * vel)))
+        etot.append(r["energy"]["total"] + ke[-1])
+    swing = max(ke) - min(ke)
+    drift = max(abs(e - etot[0]) for e in etot)
+    _say(f"  kinetic swing {swing:.3e} Ha, conserved-energy drift {drift:.3e} Ha")
+    assert swing > 1e-3
+    assert drift < 0.02 * swing
