@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests per second")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default FFT radix orders instead of timing the candidates")
+    ap.add_argument("--no-forces", action="store_true",
+                    help="skip the forces / MD-step measurement after the headline steps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
@@ -131,6 +133,77 @@ def cpu_baseline(sys_, seed=5):
     return dict(value=sys_.M / dt, unit="grid-pt evals/s", cores=1, kind="oracle",
                 sample=f"one FP64 evaluation (all terms, energy + dE/dphi) of one {sys_.n[0]}^3 "
                        f"scan system, single thread, {dt:.1f} s")
+
+
+FP64_VEC_PEAK_TFLOPS = 78.6
+FORCE_FLOPS_PER_PAIR = 17        # per (ion, half-spectrum G): phase product 6, Im 3, weights 2, G 6
+M_PROTON = 1836.15267343
+
+
+def forces_leg(args, skx, systems, ctxs, rhos):
+    """The forces and MD-step row on the scan solutions: skx_ion_forces on
+    every solved density (per-kernel HIP events), the local force kernel
+    against the FP64 vector roofline, three warm-started MD steps, and the
+    oracle's forces timed on the first system (one thread)."""
+    import numpy as np
+    import torch
+    skx.profile_reset()
+    skx.profile_enable(True)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for c, r in zip(ctxs, rhos):
+            c.ion_forces(r, kind=skx.RHO)
+    wall = (time.perf_counter() - t0) / (reps * len(ctxs))
+    skx.profile_enable(False)
+    prof = skx.profile_read()
+    ms_loc, n_loc = prof["force_loc"]
+    ms_ii, n_ii = prof["force_ewald"]
+    s0 = systems[0]
+    nh = s0.n[2] // 2 + 1
+    pairs = len(s0.zval) * s0.n[0] * s0.n[1] * nh
+    avg_s = ms_loc / 1e3 / max(1, n_loc)
+    tflops = FORCE_FLOPS_PER_PAIR * pairs / avg_s / 1e12
+    out = {"workload": f"forces on the {len(ctxs)} scan minima ({len(s0.zval)} ions, "
+                       f"{s0.n[0]}^3, FP64)",
+           "ms_per_call": round(wall * 1e3, 3),
+           "force_loc_us": round(avg_s * 1e6, 2), "force_ewald_us": round(ms_ii / max(1, n_ii) * 1e3, 2),
+           "roofline": {"bound": "alu", "kernel": "k_force_loc", "achieved": round(tflops, 3),
+                        "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / FP64_VEC_PEAK_TFLOPS, 4), "traffic": None,
+                        "flops_per_launch": FORCE_FLOPS_PER_PAIR * pairs}}
+    # MD: velocity-Verlet steps with warm-started mixed-precision solves
+    c = skx.Context(0).setup(s0, precision=skx.MIXED)
+    rho = rhos[0].clone()
+    f_loc, f_ii = c.ion_forces(rho, kind=skx.RHO)
+    F = f_loc + f_ii
+    pos = np.ascontiguousarray(s0.pos.copy())
+    rng = np.random.default_rng(7)
+    vel = rng.normal(0.0, math.sqrt(s0.T / M_PROTON), size=pos.shape)
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        r = c.md_step(rho, pos, vel, F, [M_PROTON], 4.0, gtol=args.gtol,
+                      fp32_switch_gtol=args.switch_gtol)
+        iters.append(r["iters"])
+    torch.cuda.synchronize()
+    out["md_step_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 2)
+    out["md_step_iters"] = iters
+    c.close()
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+        from oracle import forces
+        dens = rhos[0].cpu().numpy()
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            forces.local_forces(s0.L, s0.n, dens, s0.pos, s0.zval, s0.rc)
+            forces.ewald_forces(s0.L, s0.pos, s0.zval)
+            dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(dt * 1e3, 1), "unit": "ms per force call", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "local + Ewald forces of the first scan system, single thread"}
+    return out
 
 
 def run_ensemble(args):
@@ -365,6 +438,7 @@ def main():
     torch.cuda.synchronize()
     wall_graph = time.perf_counter() - t0
     print(f"graph steps: {wall_graph:.3f} s", file=sys.stderr, flush=True)
+    forces_out = None if args.no_forces else forces_leg(args, skx, systems, ctxs, rhos)
 
     # roofline of the dominant evaluation kernel
     dom = max(("point", "passA", "passB", "passC"), key=lambda k: prof[k][0])
@@ -419,6 +493,8 @@ def main():
     out["status"] = [r["status"] for r in results]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems[0])
+    if forces_out is not None:
+        out["forces"] = forces_out
     print(json.dumps(out))
 
 

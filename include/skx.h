@@ -176,8 +176,8 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
  * f_loc, f_ii: host arrays [nions][3] (ion order of skx_set_ions), either
  *   may be NULL, not both. Works in FP64 whatever the functional's precision.
  * Needs set_cell and set_ions (not set_functional). Allocates and frees a
- * scratch buffer of about 24 nions (n1 n2 / 256 + n1 + n2 + n3) bytes on
- * the ctx stream; synchronises it.
+ * scratch buffer of about nions (24 max(n1 n2 n3 / 4096, 16) + 16 (n1 + n2
+ * + n3 / 2)) bytes on the ctx stream; synchronises it.
  * Errors: SKX_E_STATE (no cell or ions), SKX_E_INVALID (no output, missing
  * field, bad in_kind, a grid the FP64 plane kernels cannot take),
  * SKX_E_NOMEM / SKX_E_DEVICE. */
@@ -224,7 +224,8 @@ int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double 
  * around every launch of: 0 pass A's transform kernel, 1 pass B, 2 pass C,
  * 3 evaluation reductions, 4 optimiser update pass (+ its reduction),
  * 5 direction pass (+ its reduction), 6 preconditioner passes, 7 the
- * pointwise kernel that precedes pass A's transform. skx_profile_read fills
+ * pointwise kernel that precedes pass A's transform, 8 the local force
+ * kernel and 9 the Ewald force kernels of skx_ion_forces. skx_profile_read fills
  * up to n entries of total milliseconds and launch counts and returns the
  * number of passes. */
 int skx_profile_enable(int on);

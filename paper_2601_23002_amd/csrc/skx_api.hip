@@ -649,7 +649,7 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
 // ---------------------------------------------------------------------------
 // Optional per-pass timing with HIP events on the launch stream.
 // ---------------------------------------------------------------------------
-enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_POINT, PP_N };
+enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_POINT, PP_FLOC, PP_FII, PP_N };
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -1261,7 +1261,7 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   hipStream_t s = c->stream;
   const int nions = (int)c->species.size();
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
-  const int nblk = force_row_blocks(n1, n2);
+  const int nblk = force_row_blocks(n1, n2, n3);
   const int ng = ewald_force_terms(c->L);
   // one scratch allocation: [f_loc | f_ii] (2 nions x 3), ordered sums,
   // phase tables, structure factor, species order
@@ -1315,12 +1315,16 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
       e = hipMemcpyAsync(order, ord.data(), sizeof(int) * nions, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && rc == SKX_OK) e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
     if (e == hipSuccess && rc == SKX_OK)
-      e = local_forces(reinterpret_cast<const double2 *>(h.spec) + h.H, n1, n2, n3, h.pitch, c->L, ph,
-                       order, nions, c->ion_sp, c->sp_z, c->sp_rc, part, out, s);
+      e = timed(PP_FLOC, s, [&] {
+        return local_forces(reinterpret_cast<const double2 *>(h.spec) + h.H, n1, n2, n3, h.pitch,
+                            c->L, ph, order, nions, c->ion_sp, c->sp_z, c->sp_rc, part, out, s);
+      });
     if (e == hipSuccess && rc == SKX_OK) e = hipStreamSynchronize(s);
   }
   if (e == hipSuccess && rc == SKX_OK && f_ii)
-    e = ewald_forces(c->L, nions, c->ion_pos, c->ion_z, sf, out + 3 * (size_t)nions, s);
+    e = timed(PP_FII, s, [&] {
+      return ewald_forces(c->L, nions, c->ion_pos, c->ion_z, sf, part, out + 3 * (size_t)nions, s);
+    });
   if (e == hipSuccess && rc == SKX_OK && f_loc)
     e = hipMemcpyAsync(f_loc, out, sizeof(double) * 3 * nions, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && rc == SKX_OK && f_ii)
@@ -1330,6 +1334,7 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   hipFreeAsync(scr, s);
   if (rc != SKX_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "force kernels");
+  prof_fold();
   return SKX_OK;
 }
 

@@ -24,6 +24,8 @@
 // ordered sum per ion), so results are deterministic.
 #include "skx_internal.hpp"
 
+#include <algorithm>
+
 namespace skx {
 
 namespace {
@@ -52,20 +54,24 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
-// One thread per (k1, k2) row of the half spectrum, one workgroup row per
-// tile of IT ions (ions sorted by species, so the form factor is computed
-// once per G point and species run). part[(I * nrowblk + blockIdx.x) * 3 + c]
-// receives this workgroup's share of F_I.
-template <int IT>
+// One thread per segment of KS consecutive k3 of a (k1, k2) row of the half
+// spectrum, one workgroup row per tile of IT ions (ions sorted by species,
+// so the form factor is computed once per G point and species run).
+// part[(I * gridDim.x + blockIdx.x) * 3 + c] receives this workgroup's share
+// of F_I.
+template <int IT, int KS>
 __global__ __launch_bounds__(256) void k_force_loc(const double2 *spec, int n1, int n2, int n3,
                                                    int nh, int pitch, double L, const double2 *ph,
                                                    const int *order, int nions, const int *species,
                                                    const double *zval, const double *rc,
                                                    double *part) {
   __shared__ double red[4 * 3];
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  const bool live = row < n1 * n2;
-  const int k1 = live ? row / n2 : 0, k2 = live ? row - (row / n2) * n2 : 0;
+  const int nseg = (nh + KS - 1) / KS;
+  const long long item = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool live = item < (long long)n1 * n2 * nseg;
+  const int row = live ? (int)(item / nseg) : 0;
+  const int seg = live ? (int)(item - (long long)row * nseg) : 0;
+  const int k1 = row / n2, k2 = row - (row / n2) * n2;
   const int g1 = 2 * k1 < n1 ? k1 : k1 - n1, g2 = 2 * k2 < n2 ? k2 : k2 - n2;
   // partner row and its G components (differ from -g only on Nyquist rows)
   const int q1 = (n1 - k1) % n1, q2 = (n2 - k2) % n2;
@@ -74,24 +80,24 @@ __global__ __launch_bounds__(256) void k_force_loc(const double2 *spec, int n1, 
   const int stride = n1 + n2 + nh;
   const double kk = 2.0 * PI_D / L;
   int ion[IT];
-  double2 pxy[IT], qxy[IT];
+  double2 pxy[IT];
   double f[IT][3];
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int idx = blockIdx.y * IT + i;
     ion[i] = idx < nions ? order[idx] : -1;
     f[i][0] = f[i][1] = f[i][2] = 0.0;
-    pxy[i] = qxy[i] = make_double2(0.0, 0.0);
+    pxy[i] = make_double2(0.0, 0.0);
     if (ion[i] >= 0) {
       const double2 *p = ph + (size_t)ion[i] * stride;
       // the tables hold exp(-2 pi i g x); conjugate for exp(+i G.R)
       pxy[i] = conjd(cmul(p[k1], p[n1 + k2]));
-      qxy[i] = conjd(cmul(p[q1], p[n1 + q2]));
     }
   }
   if (live) {
     const double2 *srow = spec + (size_t)row * pitch;
-    for (int k3 = 0; k3 < nh; ++k3) {
+    const int kend = min(nh, (seg + 1) * KS);
+    for (int k3 = seg * KS; k3 < kend; ++k3) {
       const int g3 = 2 * k3 < n3 ? k3 : k3 - n3;
       const double G2 = kk * kk * (double)(g1 * g1 + g2 * g2 + g3 * g3);
       if (G2 == 0.0) continue;
@@ -116,7 +122,9 @@ __global__ __launch_bounds__(256) void k_force_loc(const double2 *spec, int n1, 
         f[i][1] += t * g2;
         f[i][2] += t * g3;
         if (pair && nyq) {
-          const double2 ep = cmul(qxy[i], pz);                           // partner phase
+          const double2 *p = ph + (size_t)ion[i] * stride;
+          const double2 qxy = conjd(cmul(p[q1], p[n1 + q2]));
+          const double2 ep = cmul(qxy, pz);                              // partner phase
           const double tp = vf * (ep.y * nt.x - ep.x * nt.y);            // v Im[e' conj(n~)]
           f[i][0] += tp * h1;
           f[i][1] += tp * h2;
@@ -144,10 +152,11 @@ __global__ void k_force_sum(const double *part, int nblk, int nions, double *out
   out[idx] = acc;
 }
 
-// Real-space Ewald force on ion i (one workgroup per ion): lanes run over
-// (J, image) pairs, d = R_i - R_J + L t, r = |d| in (0, rcut):
-//   F_i += Z_i Z_J [erfc(a r)/r^2 + 2a/sqrt(pi) exp(-a^2 r^2)/r] d/r.
-__global__ __launch_bounds__(256) void k_ewald_force_real(double *out, int nions, const double *pos,
+// Real-space Ewald force on ion i, split over gridDim.y workgroups: lanes
+// run over (J, image) pairs, d = R_i - R_J + L t, r = |d| in (0, rcut):
+//   F_i += Z_i Z_J [erfc(a r)/r^2 + 2a/sqrt(pi) exp(-a^2 r^2)/r] d/r;
+// part[(i * gridDim.y + blockIdx.y) * 3 + c] receives each share.
+__global__ __launch_bounds__(256) void k_ewald_force_real(double *part, int nions, const double *pos,
                                                           const double *Z, double L, double alpha,
                                                           int nimg, double rcut) {
   __shared__ double red[4 * 3];
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256) void k_ewald_force_real(double *out, int nions
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
   const double c2 = 2.0 * alpha / sqrt(PI_D);
   double v[3] = {0.0, 0.0, 0.0};
-  for (long long m = threadIdx.x; m < tot; m += 256) {
+  for (long long m = (long long)blockIdx.y * 256 + threadIdx.x; m < tot; m += 256LL * gridDim.y) {
     const int j = (int)(m / nimgs), t = (int)(m - (long long)j * nimgs);
     const int a = t / (side * side) - nimg, b = (t / side) % side - nimg, c = t % side - nimg;
     const double x = xi - pos[3 * j] + a * L, y = yi - pos[3 * j + 1] + b * L,
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(256) void k_ewald_force_real(double *out, int nions
   }
   double sum[3];
   group_sum<3>(v, red, sum);
-  if (threadIdx.x < 3) out[3 * i + threadIdx.x] = Z[i] * sum[threadIdx.x];
+  if (threadIdx.x < 3) part[((size_t)i * gridDim.y + blockIdx.y) * 3 + threadIdx.x] = Z[i] * sum[threadIdx.x];
 }
 
 // S(G) = sum_J Z_J exp(i G.R_J) on the cube of integer vectors |m_c| <= mmax;
@@ -236,17 +245,23 @@ __global__ __launch_bounds__(256) void k_ewald_force_recip(double *out, const do
 
 }  // namespace
 
-int force_row_blocks(int n1, int n2) { return (n1 * n2 + 255) / 256; }
+constexpr int FORCE_IT = 4, FORCE_KS = 16, EWALD_SPLIT = 16;
+
+int force_row_blocks(int n1, int n2, int n3) {
+  const long long items = (long long)n1 * n2 * ((n3 / 2 + 1 + FORCE_KS - 1) / FORCE_KS);
+  return std::max((int)((items + 255) / 256), EWALD_SPLIT);
+}
 
 hipError_t local_forces(const double2 *spec, int n1, int n2, int n3, int pitch, double L,
                         const double2 *ph, const int *order_dev, int nions, const int *species_dev,
                         const double *zval_dev, const double *rc_dev, double *part_dev,
                         double *out_dev, hipStream_t s) {
-  constexpr int IT = 8;
-  const int nblk = force_row_blocks(n1, n2);
-  hipLaunchKernelGGL(k_force_loc<IT>, dim3(nblk, (nions + IT - 1) / IT), dim3(256), 0, s, spec,
-                     n1, n2, n3, n3 / 2 + 1, pitch, L, ph, order_dev, nions, species_dev, zval_dev,
-                     rc_dev, part_dev);
+  constexpr int IT = FORCE_IT;
+  const long long items = (long long)n1 * n2 * ((n3 / 2 + 1 + FORCE_KS - 1) / FORCE_KS);
+  const int nblk = (int)((items + 255) / 256);
+  SKX_TIMED_LAUNCH((k_force_loc<IT, FORCE_KS>), dim3(nblk, (nions + IT - 1) / IT), dim3(256), 0, s, spec,
+                   n1, n2, n3, n3 / 2 + 1, pitch, L, ph, order_dev, nions, species_dev, zval_dev,
+                   rc_dev, part_dev);
   hipLaunchKernelGGL(k_force_sum, dim3((3 * nions + 255) / 256), dim3(256), 0, s, part_dev, nblk,
                      nions, out_dev);
   return hipGetLastError();
@@ -259,18 +274,20 @@ int ewald_force_terms(double L) {
 }
 
 hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double *charge_dev,
-                        double2 *sf_dev, double *out_dev, hipStream_t s) {
+                        double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s) {
   const double alpha = 3.2 / L;
   const double rcut = 6.5 / alpha;
   const int nimg = (int)ceil(rcut / L) + 1;
   const double gcut = 2.0 * alpha * sqrt(44.0);
   const int mmax = (int)ceil(gcut * L / (2.0 * PI_D));
   const int ng = (2 * mmax + 1) * (2 * mmax + 1) * (2 * mmax + 1);
-  hipLaunchKernelGGL(k_ewald_force_real, dim3(nions), dim3(256), 0, s, out_dev, nions, pos_dev,
-                     charge_dev, L, alpha, nimg, rcut);
-  hipLaunchKernelGGL(k_ewald_sf, dim3((ng + 255) / 256), dim3(256), 0, s, sf_dev, nions, pos_dev,
+  SKX_TIMED_LAUNCH(k_ewald_force_real, dim3(nions, EWALD_SPLIT), dim3(256), 0, s, part_dev, nions,
+                   pos_dev, charge_dev, L, alpha, nimg, rcut);
+  hipLaunchKernelGGL(k_force_sum, dim3((3 * nions + 255) / 256), dim3(256), 0, s, part_dev,
+                     EWALD_SPLIT, nions, out_dev);
+  SKX_TIMED_LAUNCH(k_ewald_sf, dim3((ng + 255) / 256), dim3(256), 0, s, sf_dev, nions, pos_dev,
                      charge_dev, L, mmax, gcut * gcut);
-  hipLaunchKernelGGL(k_ewald_force_recip, dim3(nions), dim3(256), 0, s, out_dev, sf_dev, pos_dev,
+  SKX_TIMED_LAUNCH(k_ewald_force_recip, dim3(nions), dim3(256), 0, s, out_dev, sf_dev, pos_dev,
                      charge_dev, L, alpha, mmax);
   return hipGetLastError();
 }

@@ -115,14 +115,14 @@ hipError_t debug_fd_eval(const double *u_dev, double *eta_dev, double *psi_dev, 
 hipError_t ion_phase_tables(double2 *ph, int nions, const double *pos_dev, int n1, int n2, int n3,
                             double L, hipStream_t s);
 // forces on the ions (skx_forces.hip)
-int force_row_blocks(int n1, int n2);
+int force_row_blocks(int n1, int n2, int n3);   // partial sums per ion of the force kernels
 hipError_t local_forces(const double2 *spec, int n1, int n2, int n3, int pitch, double L,
                         const double2 *ph, const int *order_dev, int nions, const int *species_dev,
                         const double *zval_dev, const double *rc_dev, double *part_dev,
                         double *out_dev, hipStream_t s);
 int ewald_force_terms(double L);
 hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double *charge_dev,
-                        double2 *sf_dev, double *out_dev, hipStream_t s);
+                        double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
 struct BatchLaunch {

@@ -334,7 +334,8 @@ def run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, 
     return [r.as_dict() for r in res]
 
 
-PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond", "point")
+PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond", "point",
+              "force_loc", "force_ewald")
 
 
 def profile_enable(on=True):
@@ -384,9 +385,10 @@ def profile_reset():
 
 def profile_read():
     """{pass name: (total ms, launches)} from the library's HIP-event timers."""
-    ms = (C.c_double * 8)()
-    cnt = (C.c_longlong * 8)()
-    n = _lib.skx_profile_read(ms, cnt, 8)
+    k = len(PASS_NAMES)
+    ms = (C.c_double * k)()
+    cnt = (C.c_longlong * k)()
+    n = _lib.skx_profile_read(ms, cnt, k)
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(min(n, len(PASS_NAMES)))}
 
 
