@@ -21,6 +21,7 @@ Modules:
   functional energy terms and dE/dphi on the periodic grid
   optimize   L-BFGS on sqrt(n) with the electron-count constraint
   forces     forces on the ions: local pseudopotential and Ewald
+  structure  static structure factors S_ei, S_ee, S_ii of one snapshot
 
 Parity status per function is stated in each module header. The only
 functions without an independent pin ("parity unpinned") are the PZ81
