@@ -183,6 +183,26 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
  * SKX_E_NOMEM / SKX_E_DEVICE. */
 int skx_ion_forces(skx_ctx *ctx, const void *in_dev, int in_kind, double *f_loc, double *f_ii);
 
+/* Static structure factors of one snapshot (Methods, static structure
+ * factors): S_ab(q) = <n_a(q) n_b*(q)> / sqrt(N_a N_b) averaged over the
+ * grid's wave vectors of equal |q|; the average over MD steps is the
+ * caller's mean of these per-snapshot values. Readings:
+ *   n_e(q) = integral n(r) exp(-i q.r) dr (N_e = sum of the ionic charges),
+ *   n_i(q) = sum_I exp(-i q.R_I) over all ions as one species (N_i ions);
+ *   shell s = g1^2 + g2^2 + g3^2 (|q| = 2 pi sqrt(s) / L), every grid index
+ *   (index map, Nyquist -> -n/2) counted once; real parts of the products.
+ * in_dev: FP64 device field, n (SKX_RHO) or sqrt(n) (SKX_SQRT_RHO).
+ * s_ei, s_ee, s_ii: host arrays of len >= skx_num_shells(ctx) receiving the
+ *   shell averages (0 for shells without grid vectors); count: host ints,
+ *   grid wave vectors per shell. Any may be NULL, not all.
+ * Needs set_cell and set_ions. Allocates and frees about
+ * 20 n1 n2 (n3/2+1) + 16 nions (n1 + n2 + n3/2) bytes of device scratch;
+ * synchronises the ctx stream.
+ * Errors: SKX_E_STATE, SKX_E_INVALID (null field, bad in_kind, short len,
+ * no output, a grid the FP64 plane kernels cannot take), SKX_E_DEVICE. */
+int skx_structure_factors(skx_ctx *ctx, const void *in_dev, int in_kind, double *s_ei,
+                          double *s_ee, double *s_ii, int *count, int len);
+
 /* One velocity-Verlet step of the ions on the free-energy surface of the
  * functional (the paper's molecular dynamics, Methods; NVE here, no
  * thermostat), the density warm-started from the previous minimum:
@@ -225,7 +245,8 @@ int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double 
  * 3 evaluation reductions, 4 optimiser update pass (+ its reduction),
  * 5 direction pass (+ its reduction), 6 preconditioner passes, 7 the
  * pointwise kernel that precedes pass A's transform, 8 the local force
- * kernel and 9 the Ewald force kernels of skx_ion_forces. skx_profile_read fills
+ * kernel and 9 the Ewald force kernels of skx_ion_forces, 10 the structure
+ * factor kernel of skx_structure_factors. skx_profile_read fills
  * up to n entries of total milliseconds and launch counts and returns the
  * number of passes. */
 int skx_profile_enable(int on);

@@ -649,7 +649,7 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
 // ---------------------------------------------------------------------------
 // Optional per-pass timing with HIP events on the launch stream.
 // ---------------------------------------------------------------------------
-enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_POINT, PP_FLOC, PP_FII, PP_N };
+enum { PP_A = 0, PP_B, PP_C, PP_FIN, PP_UPD, PP_DIR, PP_PREC, PP_POINT, PP_FLOC, PP_FII, PP_SF, PP_N };
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -1250,6 +1250,44 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
   return SKX_OK;
 }
 
+// The density's half spectrum (1/M normalised, FP64, [n1][n2][pitch] in
+// slot 1 of the FP64 instance's spectrum buffer): pass A and pass B's
+// forward x transform of the fields (phi, n), as in the FFT check. Enqueued
+// on the ctx stream; *spec_out receives the slot's address.
+static int density_spectrum(skx_ctx *c, const void *in_dev, int in_kind, const double2 **spec_out,
+                            int *pitch_out) {
+  int rc = check_grid(c, 0);
+  if (rc == SKX_OK) rc = ensure_instance(c, 0, 1);
+  if (rc != SKX_OK) return rc;
+  hipStream_t s = c->stream;
+  Instance &I = c->inst[0];
+  SolveDev h = I.h;
+  h.fields = F_PHI | F_N;
+  h.nf = 2;
+  h.slot[0] = 0; h.slot[1] = 1; h.slot[2] = -1; h.slot[3] = -1;
+  h.terms = 0;
+  h.L = c->L; h.V = c->L * c->L * c->L; h.dV = h.V / (double)h.M;
+  h.ne = 1.0; h.n0 = 1.0; h.a = 1.0; h.n0a = 1.0; h.T = 1.0; h.beta = 0.0;
+  h.debug = 1;
+  if (in_kind == SKX_SQRT_RHO)
+    h.phi2[0] = const_cast<void *>(in_dev);
+  else
+    hipLaunchKernelGGL(k_sqrt_field, dim3(blocks(h.M, 256)), dim3(256), 0, s,
+                       (const double *)in_dev, (double *)h.phi2[0], h.M);
+  OptState st{};
+  st.phase = PH_EVAL_ONLY;
+  hipError_t e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "state upload");
+  std::vector<SolveDev> hs(1, h);
+  rc = build_batch(c, hs, 0, I.dptr, I.first, I.bl, s);
+  if (rc != SKX_OK) return rc;
+  e = launch_eval(I.bl, s, 3);
+  if (e != hipSuccess) return hip_fail(c, e, "forward transform");
+  *spec_out = reinterpret_cast<const double2 *>(h.spec) + h.H;
+  *pitch_out = h.pitch;
+  return SKX_OK;
+}
+
 int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, double *f_ii) {
   if (!c) return SKX_E_INVALID;
   c->err.clear();
@@ -1281,31 +1319,10 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   int *order = reinterpret_cast<int *>(scr + o_ord);
   int rc = SKX_OK;
   if (f_loc) {
-    // the density's half spectrum: pass A and pass B's forward x transform
-    // of the fields (phi, n) in the FP64 instance, as in the FFT check
-    rc = check_grid(c, 0);
-    if (rc == SKX_OK) rc = ensure_instance(c, 0, 1);
-    if (rc != SKX_OK) { hipFreeAsync(scr, s); return rc; }
-    Instance &I = c->inst[0];
-    SolveDev h = I.h;
-    h.fields = F_PHI | F_N;
-    h.nf = 2;
-    h.slot[0] = 0; h.slot[1] = 1; h.slot[2] = -1; h.slot[3] = -1;
-    h.terms = 0;
-    h.L = c->L; h.V = c->L * c->L * c->L; h.dV = h.V / (double)h.M;
-    h.ne = 1.0; h.n0 = 1.0; h.a = 1.0; h.n0a = 1.0; h.T = 1.0; h.beta = 0.0;
-    h.debug = 1;
-    if (in_kind == SKX_SQRT_RHO)
-      h.phi2[0] = const_cast<void *>(in_dev);
-    else
-      hipLaunchKernelGGL(k_sqrt_field, dim3(blocks(h.M, 256)), dim3(256), 0, s,
-                         (const double *)in_dev, (double *)h.phi2[0], h.M);
-    OptState st{};
-    st.phase = PH_EVAL_ONLY;
-    e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
-    std::vector<SolveDev> hs(1, h);
-    if (e == hipSuccess) rc = build_batch(c, hs, 0, I.dptr, I.first, I.bl, s);
-    if (e == hipSuccess && rc == SKX_OK) e = launch_eval(I.bl, s, 3);
+    const double2 *spec = nullptr;
+    int pitch = 0;
+    rc = density_spectrum(c, in_dev, in_kind, &spec, &pitch);
+    if (rc != SKX_OK) { hipStreamSynchronize(s); hipFreeAsync(scr, s); return rc; }
     // ions sorted by species: the form factor is computed once per run
     std::vector<int> ord(nions);
     for (int i = 0; i < nions; ++i) ord[i] = i;
@@ -1316,8 +1333,8 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
     if (e == hipSuccess && rc == SKX_OK) e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
     if (e == hipSuccess && rc == SKX_OK)
       e = timed(PP_FLOC, s, [&] {
-        return local_forces(reinterpret_cast<const double2 *>(h.spec) + h.H, n1, n2, n3, h.pitch,
-                            c->L, ph, order, nions, c->ion_sp, c->sp_z, c->sp_rc, part, out, s);
+        return local_forces(spec, n1, n2, n3, pitch, c->L, ph, order, nions, c->ion_sp, c->sp_z,
+                            c->sp_rc, part, out, s);
       });
     if (e == hipSuccess && rc == SKX_OK) e = hipStreamSynchronize(s);
   }
@@ -1335,6 +1352,80 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   if (rc != SKX_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "force kernels");
   prof_fold();
+  return SKX_OK;
+}
+
+int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s_ei,
+                          double *s_ee, double *s_ii, int *count, int len) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!in_dev) return fail(c, SKX_E_INVALID, "the density is required");
+  if (in_kind != SKX_RHO && in_kind != SKX_SQRT_RHO) return fail(c, SKX_E_INVALID, "bad in_kind");
+  if (!c->has_cell || !c->has_ions) return fail(c, SKX_E_STATE, "set_cell and set_ions must precede this call");
+  const int nshell = skx_num_shells(c);
+  if (len < nshell) return fail(c, SKX_E_INVALID, "len must be at least skx_num_shells(ctx)");
+  if (!s_ei && !s_ee && !s_ii && !count) return fail(c, SKX_E_INVALID, "no output requested");
+  hipSetDevice(c->device);
+  hipStream_t s = c->stream;
+  const int nions = (int)c->species.size();
+  const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
+  const long long items = (long long)n1 * n2 * nh;
+  // items of the half spectrum listed by shell (counting sort), fixed order
+  std::vector<int> off(nshell + 1, 0), idx(items);
+  auto shell = [&](long long it) {
+    const int k3 = (int)(it % nh), row = (int)(it / nh);
+    const int k1 = row / n2, k2 = row % n2;
+    const int g1 = 2 * k1 < n1 ? k1 : k1 - n1, g2 = 2 * k2 < n2 ? k2 : k2 - n2;
+    return g1 * g1 + g2 * g2 + k3 * k3;
+  };
+  for (long long it = 0; it < items; ++it) ++off[shell(it) + 1];
+  for (int k = 0; k < nshell; ++k) off[k + 1] += off[k];
+  {
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (long long it = 0; it < items; ++it) idx[fill[shell(it)]++] = (int)it;
+  }
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t n_ph = (size_t)nions * (n1 + n2 + nh);
+  const size_t o_val = al(sizeof(double2) * n_ph), o_out = o_val + al(sizeof(double) * 3 * items);
+  const size_t o_off = o_out + al(sizeof(double) * 4 * nshell), o_idx = o_off + al(sizeof(int) * (nshell + 1));
+  const size_t bytes = o_idx + al(sizeof(int) * items);
+  char *scr = nullptr;
+  hipError_t e = hipMallocAsync((void **)&scr, bytes, s);
+  if (e != hipSuccess) return hip_fail(c, e, "structure factor scratch allocation");
+  double2 *ph = reinterpret_cast<double2 *>(scr);
+  double *val = reinterpret_cast<double *>(scr + o_val);
+  double *out = reinterpret_cast<double *>(scr + o_out);
+  int *doff = reinterpret_cast<int *>(scr + o_off);
+  int *didx = reinterpret_cast<int *>(scr + o_idx);
+  const double2 *spec = nullptr;
+  int pitch = 0;
+  int rc = density_spectrum(c, in_dev, in_kind, &spec, &pitch);
+  if (rc == SKX_OK) {
+    const double V = c->L * c->L * c->L;
+    e = hipMemcpyAsync(doff, off.data(), sizeof(int) * (nshell + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(didx, idx.data(), sizeof(int) * items, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
+    if (e == hipSuccess)
+      e = timed(PP_SF, s, [&] { return structure_items(spec, n1, n2, n3, pitch, V, ph, nions, val, s); });
+    if (e == hipSuccess)
+      e = structure_shells(val, doff, didx, nshell, n3, 1.0 / std::sqrt(c->ne * nions), 1.0 / c->ne,
+                           1.0 / nions, out, s);
+  }
+  std::vector<double> host(4 * (size_t)nshell);
+  if (rc == SKX_OK && e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), out, sizeof(double) * 4 * nshell, hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
+  hipFreeAsync(scr, s);
+  if (rc != SKX_OK) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "structure factor kernels");
+  prof_fold();
+  for (int k = 0; k < nshell; ++k) {
+    if (s_ei) s_ei[k] = host[4 * k];
+    if (s_ee) s_ee[k] = host[4 * k + 1];
+    if (s_ii) s_ii[k] = host[4 * k + 2];
+    if (count) count[k] = (int)host[4 * k + 3];
+  }
   return SKX_OK;
 }
 

@@ -121,6 +121,12 @@ hipError_t local_forces(const double2 *spec, int n1, int n2, int n3, int pitch, 
                         const double *zval_dev, const double *rc_dev, double *part_dev,
                         double *out_dev, hipStream_t s);
 int ewald_force_terms(double L);
+// static structure factors (skx_structure.hip)
+hipError_t structure_items(const double2 *spec, int n1, int n2, int n3, int pitch, double V,
+                           const double2 *ph, int nions, double *val, hipStream_t s);
+hipError_t structure_shells(const double *val, const int *off, const int *idx, int nshell, int n3,
+                            double norm_ei, double norm_ee, double norm_ii, double *out,
+                            hipStream_t s);
 hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double *charge_dev,
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 

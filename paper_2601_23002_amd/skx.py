@@ -105,6 +105,9 @@ _sig("skx_ion_forces", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double), C.POI
 _sig("skx_md_step", C.c_int, [_VP, _VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                               C.POINTER(OptParams), C.POINTER(OptResult)])
+_sig("skx_structure_factors", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int), C.c_int])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -271,6 +274,21 @@ class Context:
             _dptr(fl) if local else None, _dptr(fi) if ewald else None))
         return fl, fi
 
+    def structure_factors(self, field, kind=RHO):
+        """Shell-averaged S_ei, S_ee, S_ii (numpy arrays over shells
+        s = g1^2 + g2^2 + g3^2) and the number of grid wave vectors per shell,
+        for one density snapshot (contiguous FP64 CUDA tensor)."""
+        torch = _torch()
+        if field.dtype != torch.float64 or not field.is_cuda or not field.is_contiguous():
+            raise ValueError("field must be a contiguous float64 CUDA tensor")
+        ns = _lib.skx_num_shells(self._h)
+        ei, ee, ii = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+        cnt = np.zeros(ns, dtype=np.int32)
+        self._check(_lib.skx_structure_factors(self._h, _VP(field.data_ptr()), kind, _dptr(ei),
+                                               _dptr(ee), _dptr(ii),
+                                               cnt.ctypes.data_as(C.POINTER(C.c_int)), ns))
+        return ei, ee, ii, cnt
+
     def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
                 fp32_switch_gtol=1e-5):
         """One velocity-Verlet step; pos, vel, force (float64 [nions][3]
@@ -335,7 +353,7 @@ def run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5, 
 
 
 PASS_NAMES = ("passA", "passB", "passC", "reduce", "update", "direction", "precond", "point",
-              "force_loc", "force_ewald")
+              "force_loc", "force_ewald", "structure")
 
 
 def profile_enable(on=True):
