@@ -137,14 +137,16 @@ def cpu_baseline(sys_, seed=5):
 
 FP64_VEC_PEAK_TFLOPS = 78.6
 FORCE_FLOPS_PER_PAIR = 17        # per (ion, half-spectrum G): phase product 6, Im 3, weights 2, G 6
+SF_FLOPS_PER_PAIR = 14           # per (ion, half-spectrum G): two complex products 12, sum 2
 M_PROTON = 1836.15267343
 
 
 def forces_leg(args, skx, systems, ctxs, rhos):
-    """The forces and MD-step row on the scan solutions: skx_ion_forces on
-    every solved density (per-kernel HIP events), the local force kernel
-    against the FP64 vector roofline, three warm-started MD steps, and the
-    oracle's forces timed on the first system (one thread)."""
+    """The next rows on the scan solutions: skx_ion_forces and
+    skx_structure_factors on every solved density (per-kernel HIP events),
+    their main kernels against the FP64 vector roofline, three warm-started
+    MD steps, and the oracle's forces and structure factors timed on the
+    first system (one thread)."""
     import numpy as np
     import torch
     skx.profile_reset()
@@ -172,6 +174,24 @@ def forces_leg(args, skx, systems, ctxs, rhos):
                         "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tflops / FP64_VEC_PEAK_TFLOPS, 4), "traffic": None,
                         "flops_per_launch": FORCE_FLOPS_PER_PAIR * pairs}}
+    # static structure factors of the same minima
+    skx.profile_reset()
+    skx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for c, r in zip(ctxs, rhos):
+            c.structure_factors(r, kind=skx.RHO)
+    wall_sf = (time.perf_counter() - t0) / (reps * len(ctxs))
+    skx.profile_enable(False)
+    ms_sf, n_sf = skx.profile_read()["structure"]
+    avg_sf = ms_sf / 1e3 / max(1, n_sf)
+    tf_sf = SF_FLOPS_PER_PAIR * pairs / avg_sf / 1e12
+    out["structure"] = {
+        "ms_per_call": round(wall_sf * 1e3, 3), "kernel_us": round(avg_sf * 1e6, 2),
+        "roofline": {"bound": "alu", "kernel": "k_sf_items", "achieved": round(tf_sf, 3),
+                     "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf_sf / FP64_VEC_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": SF_FLOPS_PER_PAIR * pairs}}
     # MD: velocity-Verlet steps with warm-started mixed-precision solves
     c = skx.Context(0).setup(s0, precision=skx.MIXED)
     rho = rhos[0].clone()
@@ -193,16 +213,22 @@ def forces_leg(args, skx, systems, ctxs, rhos):
     c.close()
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
-        from oracle import forces
+        from oracle import forces, structure
         dens = rhos[0].cpu().numpy()
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             forces.local_forces(s0.L, s0.n, dens, s0.pos, s0.zval, s0.rc)
             forces.ewald_forces(s0.L, s0.pos, s0.zval)
             dt = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            structure.structure_factors(s0.L, s0.n, dens, s0.pos, float(sum(s0.zval)))
+            dt_sf = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(dt * 1e3, 1), "unit": "ms per force call", "cores": 1,
                                "kind": "oracle",
                                "sample": "local + Ewald forces of the first scan system, single thread"}
+        out["structure"]["cpu_baseline"] = {
+            "value": round(dt_sf * 1e3, 1), "unit": "ms per snapshot", "cores": 1, "kind": "oracle",
+            "sample": "S_ei, S_ee, S_ii of the first scan system's minimum, single thread"}
     return out
 
 
@@ -494,6 +520,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems[0])
     if forces_out is not None:
+        out["structure"] = forces_out.pop("structure")
         out["forces"] = forces_out
     print(json.dumps(out))
 

@@ -196,8 +196,10 @@ int skx_ion_forces(skx_ctx *ctx, const void *in_dev, int in_kind, double *f_loc,
  *   shell averages (0 for shells without grid vectors); count: host ints,
  *   grid wave vectors per shell. Any may be NULL, not all.
  * Needs set_cell and set_ions. Allocates and frees about
- * 20 n1 n2 (n3/2+1) + 16 nions (n1 + n2 + n3/2) bytes of device scratch;
- * synchronises the ctx stream.
+ * 24 n1 n2 (n3/2+1) + 16 nions (n1 + n2 + n3/2) bytes of device scratch;
+ * the first call on a grid also builds the list of half-spectrum indices by
+ * shell (4 n1 n2 (n3/2+1) bytes), kept by the ctx until the grid changes or
+ * the ctx is destroyed. Synchronises the ctx stream.
  * Errors: SKX_E_STATE, SKX_E_INVALID (null field, bad in_kind, short len,
  * no output, a grid the FP64 plane kernels cannot take), SKX_E_DEVICE. */
 int skx_structure_factors(skx_ctx *ctx, const void *in_dev, int in_kind, double *s_ei,

@@ -894,6 +894,7 @@ void skx_destroy(skx_ctx *c) {
   for (auto &I : c->inst) free_instance(I);
   hipFree(c->w); hipFree(c->wp);
   hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
+  hipFree(c->sf_off); hipFree(c->sf_idx);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1370,41 +1371,50 @@ int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s
   const int nions = (int)c->species.size();
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
   const long long items = (long long)n1 * n2 * nh;
-  // items of the half spectrum listed by shell (counting sort), fixed order
-  std::vector<int> off(nshell + 1, 0), idx(items);
-  auto shell = [&](long long it) {
-    const int k3 = (int)(it % nh), row = (int)(it / nh);
-    const int k1 = row / n2, k2 = row % n2;
-    const int g1 = 2 * k1 < n1 ? k1 : k1 - n1, g2 = 2 * k2 < n2 ? k2 : k2 - n2;
-    return g1 * g1 + g2 * g2 + k3 * k3;
-  };
-  for (long long it = 0; it < items; ++it) ++off[shell(it) + 1];
-  for (int k = 0; k < nshell; ++k) off[k + 1] += off[k];
-  {
-    std::vector<int> fill(off.begin(), off.end() - 1);
-    for (long long it = 0; it < items; ++it) idx[fill[shell(it)]++] = (int)it;
+  hipError_t e = hipSuccess;
+  if (c->sf_n[0] != n1 || c->sf_n[1] != n2 || c->sf_n[2] != n3) {
+    // items of the half spectrum listed by shell (counting sort, fixed
+    // order), kept on the device while the grid stays the same
+    std::vector<int> off(nshell + 1, 0), idx(items);
+    auto shell = [&](long long it) {
+      const int k3 = (int)(it % nh), row = (int)(it / nh);
+      const int k1 = row / n2, k2 = row % n2;
+      const int g1 = 2 * k1 < n1 ? k1 : k1 - n1, g2 = 2 * k2 < n2 ? k2 : k2 - n2;
+      return g1 * g1 + g2 * g2 + k3 * k3;
+    };
+    for (long long it = 0; it < items; ++it) ++off[shell(it) + 1];
+    for (int k = 0; k < nshell; ++k) off[k + 1] += off[k];
+    {
+      std::vector<int> fill(off.begin(), off.end() - 1);
+      for (long long it = 0; it < items; ++it) idx[fill[shell(it)]++] = (int)it;
+    }
+    hipFree(c->sf_off); hipFree(c->sf_idx);
+    c->sf_off = c->sf_idx = nullptr;
+    c->sf_n[0] = c->sf_n[1] = c->sf_n[2] = 0;
+    e = hipMalloc((void **)&c->sf_off, sizeof(int) * (nshell + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->sf_idx, sizeof(int) * items);
+    if (e == hipSuccess) e = hipMemcpy(c->sf_off, off.data(), sizeof(int) * (nshell + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->sf_idx, idx.data(), sizeof(int) * items, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "shell lists");
+    c->sf_n[0] = n1; c->sf_n[1] = n2; c->sf_n[2] = n3;
   }
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t n_ph = (size_t)nions * (n1 + n2 + nh);
   const size_t o_val = al(sizeof(double2) * n_ph), o_out = o_val + al(sizeof(double) * 3 * items);
-  const size_t o_off = o_out + al(sizeof(double) * 4 * nshell), o_idx = o_off + al(sizeof(int) * (nshell + 1));
-  const size_t bytes = o_idx + al(sizeof(int) * items);
+  const size_t bytes = o_out + al(sizeof(double) * 4 * nshell);
   char *scr = nullptr;
-  hipError_t e = hipMallocAsync((void **)&scr, bytes, s);
+  e = hipMallocAsync((void **)&scr, bytes, s);
   if (e != hipSuccess) return hip_fail(c, e, "structure factor scratch allocation");
   double2 *ph = reinterpret_cast<double2 *>(scr);
   double *val = reinterpret_cast<double *>(scr + o_val);
   double *out = reinterpret_cast<double *>(scr + o_out);
-  int *doff = reinterpret_cast<int *>(scr + o_off);
-  int *didx = reinterpret_cast<int *>(scr + o_idx);
+  const int *doff = c->sf_off, *didx = c->sf_idx;
   const double2 *spec = nullptr;
   int pitch = 0;
   int rc = density_spectrum(c, in_dev, in_kind, &spec, &pitch);
   if (rc == SKX_OK) {
     const double V = c->L * c->L * c->L;
-    e = hipMemcpyAsync(doff, off.data(), sizeof(int) * (nshell + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(didx, idx.data(), sizeof(int) * items, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
+    e = ion_phase_tables(ph, nions, c->ion_pos, n1, n2, n3, c->L, s);
     if (e == hipSuccess)
       e = timed(PP_SF, s, [&] { return structure_items(spec, n1, n2, n3, pitch, V, ph, nions, val, s); });
     if (e == hipSuccess)

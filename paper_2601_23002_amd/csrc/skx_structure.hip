@@ -11,8 +11,8 @@
 // 0 < k3 < n3/2 also stands for its conjugate partner, whose products equal
 // its own except on the Nyquist rows of x or y (there the partner's G is not
 // -G and its ion sum is formed separately). k_shell_sum then adds the items
-// of each shell in a fixed order (host-built list sorted by shell), so the
-// result is deterministic.
+// of each shell in a fixed order (host-built list sorted by shell, a fixed
+// lane assignment and shuffle tree), so the result is deterministic.
 #include "skx_internal.hpp"
 
 namespace skx {
@@ -68,25 +68,33 @@ __global__ __launch_bounds__(256) void k_sf_items(const double2 *spec, int n1, i
 }
 
 // out[4 s + (0..3)] = S_ei, S_ee, S_ii, count of shell s, from the items of
-// the shell (list idx[off[s] .. off[s+1])) in list order.
-__global__ void k_shell_sum(const double *val, const int *off, const int *idx, int nshell, int n3,
-                            int nh, double norm_ei, double norm_ee, double norm_ii, double *out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// the shell (list idx[off[s] .. off[s+1])): one wavefront per shell, lane l
+// adding list entries l, l + 64, ... in order, then a fixed shuffle tree.
+__global__ __launch_bounds__(256) void k_shell_sum(const double *val, const int *off,
+                                                   const int *idx, int nshell, int n3, int nh,
+                                                   double norm_ei, double norm_ee,
+                                                   double norm_ii, double *out) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (s >= nshell) return;
-  double a = 0.0, b = 0.0, c = 0.0, cnt = 0.0;
-  for (int j = off[s]; j < off[s + 1]; ++j) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = off[s] + lane; j < off[s + 1]; j += 64) {
     const int it = idx[j];
     const int k3 = it % nh;
-    a += val[3 * (size_t)it];
-    b += val[3 * (size_t)it + 1];
-    c += val[3 * (size_t)it + 2];
-    cnt += (k3 > 0 && 2 * k3 < n3) ? 2.0 : 1.0;
+    v[0] += val[3 * (size_t)it];
+    v[1] += val[3 * (size_t)it + 1];
+    v[2] += val[3 * (size_t)it + 2];
+    v[3] += (k3 > 0 && 2 * k3 < n3) ? 2.0 : 1.0;
   }
-  const double inv = cnt > 0.0 ? 1.0 / cnt : 0.0;
-  out[4 * s] = a * inv * norm_ei;
-  out[4 * s + 1] = b * inv * norm_ee;
-  out[4 * s + 2] = c * inv * norm_ii;
-  out[4 * s + 3] = cnt;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+  if (lane == 0) {
+    const double inv = v[3] > 0.0 ? 1.0 / v[3] : 0.0;
+    out[4 * s] = v[0] * inv * norm_ei;
+    out[4 * s + 1] = v[1] * inv * norm_ee;
+    out[4 * s + 2] = v[2] * inv * norm_ii;
+    out[4 * s + 3] = v[3];
+  }
 }
 
 }  // namespace
@@ -102,7 +110,7 @@ hipError_t structure_items(const double2 *spec, int n1, int n2, int n3, int pitc
 hipError_t structure_shells(const double *val, const int *off, const int *idx, int nshell, int n3,
                             double norm_ei, double norm_ee, double norm_ii, double *out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_shell_sum, dim3((nshell + 255) / 256), dim3(256), 0, s, val, off, idx,
+  hipLaunchKernelGGL(k_shell_sum, dim3((nshell + 3) / 4), dim3(256), 0, s, val, off, idx,
                      nshell, n3, n3 / 2 + 1, norm_ei, norm_ee, norm_ii, out);
   return hipGetLastError();
 }
