@@ -22,6 +22,7 @@ Modules:
   optimize   L-BFGS on sqrt(n) with the electron-count constraint
   forces     forces on the ions: local pseudopotential and Ewald
   structure  static structure factors S_ei, S_ee, S_ii of one snapshot
+  fit        the beta fit of Eq. (3) against a reference density
 
 Parity status per function is stated in each module header. The only
 functions without an independent pin ("parity unpinned") are the PZ81
