@@ -205,6 +205,31 @@ int skx_ion_forces(skx_ctx *ctx, const void *in_dev, int in_kind, double *f_loc,
 int skx_structure_factors(skx_ctx *ctx, const void *in_dev, int in_kind, double *s_ei,
                           double *s_ee, double *s_ii, int *count, int len);
 
+/* The integrated absolute deviation of two FP64 device densities on the
+ * cell's grid, D = integral |a - b| dr = dV sum |a - b| (Eq. (3)), into
+ * *out (host). Fixed-order reduction. Synchronises the ctx stream.
+ * Errors: SKX_E_INVALID (null argument), SKX_E_STATE (no cell). */
+int skx_density_deviation(skx_ctx *ctx, const void *a_dev, const void *b_dev, double *out);
+
+/* Kohn-Sham-assisted fit of beta for one configuration (Eq. (3); Methods,
+ * optimisation of the beta parameter): the beta in [beta_lo, beta_hi]
+ * minimising D(beta) = integral |n[beta] - n_ref| dr, n[beta] the minimising
+ * density of the ctx's functional with beta replaced (skx_optimize_density
+ * with p; warm-started from the previous solve after the first one). The
+ * line minimisation is Brent's method (the one-parameter case of the
+ * paper's Powell search), to an absolute tolerance xtol in beta. The
+ * paper's beta over several configurations is the mean of the results.
+ * rho_ref_dev: FP64 reference density (KSDFT in the paper). rho_dev: FP64
+ *   device work density; a start guess if p->warm_start, on return the
+ *   minimising density at *beta_out.
+ * beta_out, dev_out (may be NULL), nsolves (may be NULL): host results.
+ * The ctx's functional is left as it was. Synchronises the ctx stream.
+ * Errors: SKX_E_INVALID (null arguments, empty interval, xtol <= 0),
+ * SKX_E_STATE, or an error of the solves. */
+int skx_fit_beta(skx_ctx *ctx, const void *rho_ref_dev, void *rho_dev, double beta_lo,
+                 double beta_hi, double xtol, const skx_opt_params *p, double *beta_out,
+                 double *dev_out, int *nsolves);
+
 /* One velocity-Verlet step of the ions on the free-energy surface of the
  * functional (the paper's molecular dynamics, Methods; NVE here, no
  * thermostat), the density warm-started from the previous minimum:

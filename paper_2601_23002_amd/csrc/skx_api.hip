@@ -1439,6 +1439,112 @@ int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s
   return SKX_OK;
 }
 
+int skx_density_deviation(skx_ctx *c, const void *a_dev, const void *b_dev, double *out) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!a_dev || !b_dev || !out) return fail(c, SKX_E_INVALID, "null argument");
+  if (!c->has_cell) return fail(c, SKX_E_STATE, "set_cell first");
+  hipSetDevice(c->device);
+  hipStream_t s = c->stream;
+  const long long M = (long long)c->n1 * c->n2 * c->n3;
+  const int nb = deviation_blocks(M);
+  double *scr = nullptr;
+  hipError_t e = hipMallocAsync((void **)&scr, sizeof(double) * (nb + 1), s);
+  if (e != hipSuccess) return hip_fail(c, e, "deviation scratch");
+  const double dV = c->L * c->L * c->L / (double)M;
+  e = density_deviation((const double *)a_dev, (const double *)b_dev, M, dV, scr, scr + nb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, scr + nb, sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
+  hipFreeAsync(scr, s);
+  if (e != hipSuccess) return hip_fail(c, e, "deviation kernels");
+  return SKX_OK;
+}
+
+int skx_fit_beta(skx_ctx *c, const void *rho_ref_dev, void *rho_dev, double beta_lo,
+                 double beta_hi, double xtol, const skx_opt_params *p, double *beta_out,
+                 double *dev_out, int *nsolves) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!rho_ref_dev || !rho_dev || !p || !beta_out) return fail(c, SKX_E_INVALID, "null argument");
+  if (!(beta_lo < beta_hi) || !std::isfinite(beta_lo) || !std::isfinite(beta_hi))
+    return fail(c, SKX_E_INVALID, "need a finite interval beta_lo < beta_hi");
+  if (!(xtol > 0)) return fail(c, SKX_E_INVALID, "xtol must be positive");
+  if (!c->has_cell || !c->has_ions || !c->has_fn)
+    return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
+  const skx_functional fn0 = c->fn;
+  int solves = 0, err = SKX_OK;
+  double last = 0.0;
+  // D(beta): minimise at beta (warm-started from rho_dev after the first
+  // solve), then the integrated absolute deviation from the reference
+  auto D = [&](double beta) {
+    skx_functional fn = fn0;
+    fn.beta = beta;
+    int rc = skx_set_functional(c, &fn);
+    skx_opt_params q = *p;
+    q.warm_start = (solves > 0 || p->warm_start) ? 1 : 0;
+    skx_opt_result res;
+    if (rc == SKX_OK) rc = skx_optimize_density(c, rho_dev, &q, &res);
+    ++solves;
+    last = beta;
+    double d = 0.0;
+    if (rc >= 0) rc = skx_density_deviation(c, rho_dev, rho_ref_dev, &d);
+    if (rc < 0) { err = rc; return HUGE_VAL; }
+    return d;
+  };
+  // Brent's minimisation on [beta_lo, beta_hi]: golden-section steps with
+  // parabolic interpolation through the three best points when it stays
+  // inside the bracket and shrinks the step (Brent 1973, ch. 5)
+  const double gold = 0.5 * (3.0 - std::sqrt(5.0));
+  double a = beta_lo, b = beta_hi;
+  double x = a + gold * (b - a), w = x, v = x;
+  double fx = D(x), fw = fx, fv = fx;
+  double d = 0.0, e = 0.0;
+  for (int it = 0; it < 200 && err == SKX_OK; ++it) {
+    const double m = 0.5 * (a + b);
+    const double tol1 = 1e-10 * std::fabs(x) + xtol / 3.0, tol2 = 2.0 * tol1;
+    if (std::fabs(x - m) <= tol2 - 0.5 * (b - a)) break;
+    bool golden = true;
+    if (std::fabs(e) > tol1) {
+      double r = (x - w) * (fx - fv), q = (x - v) * (fx - fw);
+      double pp = (x - v) * q - (x - w) * r;
+      q = 2.0 * (q - r);
+      if (q > 0.0) pp = -pp; else q = -q;
+      const double e_prev = e;
+      e = d;
+      if (std::fabs(pp) < std::fabs(0.5 * q * e_prev) && pp > q * (a - x) && pp < q * (b - x)) {
+        d = pp / q;
+        const double u = x + d;
+        if (u - a < tol2 || b - u < tol2) d = x < m ? tol1 : -tol1;
+        golden = false;
+      }
+    }
+    if (golden) {
+      e = (x < m ? b : a) - x;
+      d = gold * e;
+    }
+    const double u = std::fabs(d) >= tol1 ? x + d : x + (d > 0.0 ? tol1 : -tol1);
+    const double fu = D(u);
+    if (err != SKX_OK) break;
+    if (fu <= fx) {
+      if (u < x) b = x; else a = x;
+      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
+    } else {
+      if (u < x) a = u; else b = u;
+      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
+      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
+    }
+  }
+  // leave rho_dev at the minimum of the returned beta
+  if (err == SKX_OK && last != x) fx = D(x);
+  skx_set_functional(c, &fn0);
+  if (err != SKX_OK) return err;
+  *beta_out = x;
+  if (dev_out) *dev_out = fx;
+  if (nsolves) *nsolves = solves;
+  return SKX_OK;
+}
+
 int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
                 const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res) {
   if (!c) return SKX_E_INVALID;

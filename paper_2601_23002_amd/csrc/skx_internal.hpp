@@ -121,6 +121,11 @@ hipError_t local_forces(const double2 *spec, int n1, int n2, int n3, int pitch, 
                         const double *zval_dev, const double *rc_dev, double *part_dev,
                         double *out_dev, hipStream_t s);
 int ewald_force_terms(double L);
+// integrated absolute density deviation of the beta fit (skx_fit.hip);
+// part_dev holds deviation_blocks(n) doubles
+int deviation_blocks(long long n);
+hipError_t density_deviation(const double *a, const double *b, long long n, double dV,
+                             double *part_dev, double *out_dev, hipStream_t s);
 // static structure factors (skx_structure.hip)
 hipError_t structure_items(const double2 *spec, int n1, int n2, int n3, int pitch, double V,
                            const double2 *ph, int nions, double *val, hipStream_t s);

@@ -108,6 +108,10 @@ _sig("skx_md_step", C.c_int, [_VP, _VP, C.POINTER(C.c_double), C.POINTER(C.c_dou
 _sig("skx_structure_factors", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_int), C.c_int])
+_sig("skx_density_deviation", C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_double)])
+_sig("skx_fit_beta", C.c_int, [_VP, _VP, _VP, C.c_double, C.c_double, C.c_double,
+                               C.POINTER(OptParams), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.POINTER(C.c_int)])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -289,6 +293,35 @@ class Context:
                                                cnt.ctypes.data_as(C.POINTER(C.c_int)), ns))
         return ei, ee, ii, cnt
 
+    def density_deviation(self, a, b):
+        """integral |a - b| dr of two contiguous FP64 CUDA densities."""
+        torch = _torch()
+        for t in (a, b):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("densities must be contiguous float64 CUDA tensors")
+        out = C.c_double()
+        self._check(_lib.skx_density_deviation(self._h, _VP(a.data_ptr()), _VP(b.data_ptr()),
+                                               C.byref(out)))
+        return out.value
+
+    def fit_beta(self, rho_ref, lo=0.0, hi=2.0, xtol=1e-4, gtol=1e-8, max_iter=1000, m=5,
+                 fp32_switch_gtol=1e-5, rho0=None):
+        """beta minimising integral |n[beta] - rho_ref| (Eq. (3)) for this
+        configuration; returns (beta, deviation, solves, density at beta)."""
+        torch = _torch()
+        if rho_ref.dtype != torch.float64 or not rho_ref.is_cuda or not rho_ref.is_contiguous():
+            raise ValueError("rho_ref must be a contiguous float64 CUDA tensor")
+        if rho0 is not None:
+            rho = rho0.to(dtype=torch.float64).contiguous().clone()
+        else:
+            rho = torch.empty_like(rho_ref)
+        p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1 if rho0 is not None else 0)
+        beta, dev, ns = C.c_double(), C.c_double(), C.c_int()
+        self._check(_lib.skx_fit_beta(self._h, _VP(rho_ref.data_ptr()), _VP(rho.data_ptr()),
+                                      lo, hi, xtol, C.byref(p), C.byref(beta), C.byref(dev),
+                                      C.byref(ns)))
+        return beta.value, dev.value, ns.value, rho
+
     def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
                 fp32_switch_gtol=1e-5):
         """One velocity-Verlet step; pos, vel, force (float64 [nions][3]
@@ -408,6 +441,13 @@ def profile_read():
     cnt = (C.c_longlong * k)()
     n = _lib.skx_profile_read(ms, cnt, k)
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(min(n, len(PASS_NAMES)))}
+
+
+def fit_beta_mean(ctxs, refs, **kw):
+    """The functional's beta as the mean of per-configuration fits (Methods,
+    optimisation of the beta parameter); returns (mean, [beta_i])."""
+    betas = [c.fit_beta(r, **kw)[0] for c, r in zip(ctxs, refs)]
+    return sum(betas) / len(betas), betas
 
 
 def bench_eval(ctxs, reps=20):
