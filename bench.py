@@ -192,6 +192,23 @@ def forces_leg(args, skx, systems, ctxs, rhos):
                      "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf_sf / FP64_VEC_PEAK_TFLOPS, 4), "traffic": None,
                      "flops_per_launch": SF_FLOPS_PER_PAIR * pairs}}
+    # beta fit (Eq. (3)) of the first system against its own beta = 0.6
+    # minimum as the reference density
+    import dataclasses
+    cref = skx.Context(0).setup(dataclasses.replace(s0, beta=0.6), precision=skx.MIXED)
+    nref, _ = cref.optimize(gtol=args.gtol, fp32_switch_gtol=args.switch_gtol)
+    cref.close()
+    cfit = skx.Context(0).setup(s0, precision=skx.MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    beta, dev, nsolve, _ = cfit.fit_beta(nref, 0.0, 2.0, xtol=1e-3, gtol=args.gtol,
+                                         fp32_switch_gtol=args.switch_gtol)
+    torch.cuda.synchronize()
+    out["beta_fit"] = {"workload": "beta in [0, 2] for the first scan system against its "
+                                   "beta = 0.6 minimum, xtol 1e-3, mixed solves",
+                       "seconds": round(time.perf_counter() - t0, 3), "solves": nsolve,
+                       "beta": round(beta, 6), "deviation": dev}
+    cfit.close()
     # MD: velocity-Verlet steps with warm-started mixed-precision solves
     c = skx.Context(0).setup(s0, precision=skx.MIXED)
     rho = rhos[0].clone()
@@ -521,6 +538,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(systems[0])
     if forces_out is not None:
         out["structure"] = forces_out.pop("structure")
+        out["beta_fit"] = forces_out.pop("beta_fit")
         out["forces"] = forces_out
     print(json.dumps(out))
 
