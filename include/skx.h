@@ -231,8 +231,9 @@ int skx_fit_beta(skx_ctx *ctx, const void *rho_ref_dev, void *rho_dev, double be
                  double *dev_out, int *nsolves);
 
 /* One velocity-Verlet step of the ions on the free-energy surface of the
- * functional (the paper's molecular dynamics, Methods; NVE here, no
- * thermostat), the density warm-started from the previous minimum:
+ * functional (the paper's molecular dynamics, Methods; NVE here,
+ * skx_md_step_nvt adds the thermostat), the density warm-started from the
+ * previous minimum:
  *   v += (dt/2) F/m;  R += dt v (wrapped into the cell);  minimise the
  *   density from rho_dev (skx_optimize_density, warm_start forced);
  *   F = f_loc + f_ii at the new minimum (skx_ion_forces);  v += (dt/2) F/m.
@@ -247,6 +248,26 @@ int skx_fit_beta(skx_ctx *ctx, const void *rho_ref_dev, void *rho_dev, double be
  * arguments, dt <= 0 or a non-positive mass. */
 int skx_md_step(skx_ctx *ctx, void *rho_dev, double *pos, double *vel, double *force,
                 const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res);
+
+/* Nose-Hoover thermostat state for skx_md_step_nvt (the paper's MD runs in
+ * the NVT ensemble with a Nose-Hoover thermostat, Methods). */
+typedef struct {
+  double T_ion;   /* target ionic temperature, Ha */
+  double Q;       /* thermostat mass, Ha (atomic time)^2, > 0 */
+  double xi;      /* thermostat velocity, 1 / atomic time; in/out */
+  double eta;     /* thermostat position (for the conserved quantity); in/out */
+} skx_nose_hoover;
+
+/* skx_md_step in the NVT ensemble: the velocity-Verlet step wrapped in two
+ * half steps of a single Nose-Hoover thermostat, each symmetric:
+ *   xi += (h/2) G;  v *= exp(-xi h);  eta += xi h;  xi += (h/2) G,
+ * h = dt/2, G = (2 K - g T_ion) / Q, K the ionic kinetic energy, g = 3 N_ion.
+ * F[n_min(R)] + K + Q xi^2 / 2 + g T_ion eta is conserved. Arguments and
+ * errors as skx_md_step; SKX_E_INVALID also for a NULL nh, Q <= 0,
+ * T_ion < 0 or a non-finite xi. */
+int skx_md_step_nvt(skx_ctx *ctx, void *rho_dev, double *pos, double *vel, double *force,
+                    const double *mass, double dt, skx_nose_hoover *nh, const skx_opt_params *p,
+                    skx_opt_result *res);
 
 /* ---- introspection (tests and tools) ---- */
 

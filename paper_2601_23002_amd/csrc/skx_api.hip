@@ -1545,27 +1545,56 @@ int skx_fit_beta(skx_ctx *c, const void *rho_ref_dev, void *rho_dev, double beta
   return SKX_OK;
 }
 
-int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
-                const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res) {
+}  // extern "C"
+
+namespace {
+
+// Half a step (h = dt/2) of the Nose-Hoover thermostat, symmetric in
+// itself: xi += (h/2) G, v *= exp(-xi h), eta += xi h, xi += (h/2) G with
+// G = (2 K - g T_ion) / Q, K the ionic kinetic energy, g = 3 N_ion.
+void nose_hoover_half(skx_nose_hoover *nh, double h, double *vel, const double *mass,
+                      const std::vector<int> &species, int nions) {
+  auto kinetic = [&] {
+    double k = 0.0;
+    for (int i = 0; i < nions; ++i)
+      for (int a = 0; a < 3; ++a) k += 0.5 * mass[species[i]] * vel[3 * i + a] * vel[3 * i + a];
+    return k;
+  };
+  const double g = 3.0 * nions;
+  nh->xi += 0.5 * h * (2.0 * kinetic() - g * nh->T_ion) / nh->Q;
+  const double sc = std::exp(-nh->xi * h);
+  for (int i = 0; i < 3 * nions; ++i) vel[i] *= sc;
+  nh->eta += nh->xi * h;
+  nh->xi += 0.5 * h * (2.0 * kinetic() - g * nh->T_ion) / nh->Q;
+}
+
+// Velocity Verlet with a warm-started density minimisation and forces at
+// the new positions; with nh, wrapped in two Nose-Hoover half steps.
+int md_step_impl(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
+                 const double *mass, double dt, skx_nose_hoover *nh, const skx_opt_params *p,
+                 skx_opt_result *res) {
   if (!c) return SKX_E_INVALID;
   c->err.clear();
   if (!rho_dev || !pos || !vel || !force || !mass || !p || !res)
     return fail(c, SKX_E_INVALID, "null argument");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(c, SKX_E_INVALID, "dt must be positive");
+  if (nh && (!(nh->Q > 0) || !std::isfinite(nh->Q) || !(nh->T_ion >= 0) || !std::isfinite(nh->xi)))
+    return fail(c, SKX_E_INVALID, "thermostat needs Q > 0, T_ion >= 0 and a finite xi");
   if (!c->has_cell || !c->has_ions || !c->has_fn)
     return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
   const int nions = (int)c->species.size();
   for (int k = 0; k < c->nspecies; ++k)
     if (!(mass[k] > 0) || !std::isfinite(mass[k])) return fail(c, SKX_E_INVALID, "masses must be positive");
+  const std::vector<int> sp(c->species);
+  if (nh) nose_hoover_half(nh, 0.5 * dt, vel, mass, sp, nions);
   // half kick and drift (positions are wrapped into the cell by set_ions)
   for (int i = 0; i < nions; ++i) {
-    const double m = mass[c->species[i]];
+    const double m = mass[sp[i]];
     for (int a = 0; a < 3; ++a) {
       vel[3 * i + a] += 0.5 * dt * force[3 * i + a] / m;
       pos[3 * i + a] += dt * vel[3 * i + a];
     }
   }
-  const std::vector<int> sp(c->species);
   const std::vector<double> z(c->zsp), r(c->rcsp);
   int rc = skx_set_ions(c, nions, pos, sp.data(), (int)z.size(), z.data(), r.data());
   if (rc != SKX_OK) return rc;
@@ -1579,13 +1608,30 @@ int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *for
   rc = skx_ion_forces(c, rho_dev, SKX_RHO, fl.data(), fi.data());
   if (rc != SKX_OK) return rc;
   for (int i = 0; i < nions; ++i) {
-    const double m = mass[c->species[i]];
+    const double m = mass[sp[i]];
     for (int a = 0; a < 3; ++a) {
       force[3 * i + a] = fl[3 * i + a] + fi[3 * i + a];
       vel[3 * i + a] += 0.5 * dt * force[3 * i + a] / m;
     }
   }
+  if (nh) nose_hoover_half(nh, 0.5 * dt, vel, mass, sp, nions);
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
+                const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res) {
+  return md_step_impl(c, rho_dev, pos, vel, force, mass, dt, nullptr, p, res);
+}
+
+int skx_md_step_nvt(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
+                    const double *mass, double dt, skx_nose_hoover *nh, const skx_opt_params *p,
+                    skx_opt_result *res) {
+  if (!nh) return c ? fail(c, SKX_E_INVALID, "thermostat state is NULL") : SKX_E_INVALID;
+  return md_step_impl(c, rho_dev, pos, vel, force, mass, dt, nh, p, res);
 }
 
 int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_params *p,

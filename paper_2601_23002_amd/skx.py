@@ -69,6 +69,11 @@ class OptResult(C.Structure):
         return d
 
 
+class NoseHoover(C.Structure):
+    """Thermostat state of md_step_nvt (xi and eta are updated in place)."""
+    _fields_ = [("T_ion", C.c_double), ("Q", C.c_double), ("xi", C.c_double), ("eta", C.c_double)]
+
+
 class Request(C.Structure):
     _fields_ = [("lattice", C.c_double * 9), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
                 ("nions", C.c_int), ("pos", C.POINTER(C.c_double)),
@@ -112,6 +117,10 @@ _sig("skx_density_deviation", C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_double)])
 _sig("skx_fit_beta", C.c_int, [_VP, _VP, _VP, C.c_double, C.c_double, C.c_double,
                                C.POINTER(OptParams), C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_int)])
+_sig("skx_md_step_nvt", C.c_int, [_VP, _VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                  C.POINTER(NoseHoover), C.POINTER(OptParams),
+                                  C.POINTER(OptResult)])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -323,10 +332,12 @@ class Context:
         return beta.value, dev.value, ns.value, rho
 
     def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
-                fp32_switch_gtol=1e-5):
+                fp32_switch_gtol=1e-5, thermostat=None):
         """One velocity-Verlet step; pos, vel, force (float64 [nions][3]
         arrays) are updated in place, rho (FP64 CUDA density) too. mass per
-        species in electron masses. Returns the solve's result dict."""
+        species in electron masses. thermostat: a NoseHoover state for an NVT
+        step (updated in place), None for NVE. Returns the solve's result
+        dict."""
         for a in (pos, vel, force):
             if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
                     and a.shape == (self.nions, 3)):
@@ -336,8 +347,13 @@ class Context:
             raise ValueError("one mass per species")
         p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1)
         r = OptResult()
-        rc = _lib.skx_md_step(self._h, _VP(rho.data_ptr()), _dptr(pos), _dptr(vel), _dptr(force),
-                              _dptr(mass), dt, C.byref(p), C.byref(r))
+        if thermostat is None:
+            rc = _lib.skx_md_step(self._h, _VP(rho.data_ptr()), _dptr(pos), _dptr(vel),
+                                  _dptr(force), _dptr(mass), dt, C.byref(p), C.byref(r))
+        else:
+            rc = _lib.skx_md_step_nvt(self._h, _VP(rho.data_ptr()), _dptr(pos), _dptr(vel),
+                                      _dptr(force), _dptr(mass), dt, C.byref(thermostat),
+                                      C.byref(p), C.byref(r))
         self._check(rc)
         return r.as_dict()
 

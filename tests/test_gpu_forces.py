@@ -218,3 +218,44 @@ def test_md_conserves_free_energy_plus_kinetic_energy():
     _say(f"  kinetic swing {swing:.3e} Ha, conserved-energy drift {drift:.3e} Ha")
     assert swing > 1e-3
     assert drift < 0.02 * swing
+
+
+def test_nvt_step_without_coupling_is_the_nve_step():
+    """A thermostat of infinite mass and zero velocity leaves the NVE step."""
+    skx, torch = _lib()
+    _say("case: nvt with Q -> inf equals nve, 8 H 32^3")
+    s, c, rho, pos, vel, F, _ = _md_start(skx, torch, seed=43)
+    rho2, pos2, vel2, F2 = rho.clone(), pos.copy(), vel.copy(), F.copy()
+    c.md_step(rho, pos, vel, F, [M_PROTON], 4.0, gtol=1e-9, max_iter=2000)
+    c2 = skx.Context(0).setup(s, precision=skx.FP64)
+    nh = skx.NoseHoover(0.1, 1e300, 0.0, 0.0)
+    c2.md_step(rho2, pos2, vel2, F2, [M_PROTON], 4.0, gtol=1e-9, max_iter=2000, thermostat=nh)
+    assert abs(nh.xi) < 1e-290
+    assert np.max(np.abs(pos - pos2)) < 1e-12 * s.L
+    assert np.max(np.abs(vel - vel2)) < 1e-10 * np.max(np.abs(vel))
+
+
+def test_nvt_conserves_the_extended_energy_and_heats_a_cold_start():
+    """Nose-Hoover: F + K + Q xi^2/2 + g T eta is conserved; started below
+    the target, the ions gain kinetic energy that NVE would not give."""
+    skx, torch = _lib()
+    _say("case: nvt extended energy, 8 H 32^3, 30 steps")
+    s, c, rho, pos, vel, F, E = _md_start(skx, torch, seed=44)
+    vel *= 0.3
+    T_ion = 0.2
+    g = 3 * len(pos)
+    nh = skx.NoseHoover(T_ion, g * T_ion * 200.0 ** 2, 0.0, 0.0)
+    ke0 = 0.5 * M_PROTON * float(np.sum(vel * vel))
+    ext = [E + ke0]
+    kes = [ke0]
+    for _ in range(30):
+        r = c.md_step(rho, pos, vel, F, [M_PROTON], 4.0, gtol=1e-9, max_iter=2000, thermostat=nh)
+        assert r["status"] == skx.OK
+        ke = 0.5 * M_PROTON * float(np.sum(vel * vel))
+        kes.append(ke)
+        ext.append(r["energy"]["total"] + ke + 0.5 * nh.Q * nh.xi ** 2 + g * T_ion * nh.eta)
+    drift = max(abs(e - ext[0]) for e in ext)
+    swing = max(kes) - min(kes)
+    _say(f"  kinetic {kes[0]:.3e} -> {kes[-1]:.3e} Ha, xi {nh.xi:.3e}, extended-energy drift {drift:.3e} Ha")
+    assert nh.xi < 0.0                       # heating: the thermostat pushes energy in
+    assert drift < 0.02 * swing
