@@ -23,6 +23,7 @@ Modules:
   forces     forces on the ions: local pseudopotential and Ewald
   structure  static structure factors S_ei, S_ee, S_ii of one snapshot
   fit        the beta fit of Eq. (3) against a reference density
+  pressure   closed-form pressures (uniform gas, Ewald) for the equation of state
 
 Parity status per function is stated in each module header. The only
 functions without an independent pin ("parity unpinned") are the PZ81
