@@ -269,6 +269,20 @@ int skx_md_step_nvt(skx_ctx *ctx, void *rho_dev, double *pos, double *vel, doubl
                     const double *mass, double dt, skx_nose_hoover *nh, const skx_opt_params *p,
                     skx_opt_result *res);
 
+/* Pressure of the configuration for the equation of state (Table 1,
+ * Fig. 3; the paper prints no stress formula): P = -dF/dV of the minimised
+ * total free energy (electronic free energy + Ewald energy) at fixed ion
+ * fractional positions, as the central difference between cells of volume
+ * V (1 -+ eps) on the same grid, each minimised warm-started from rho_dev.
+ * The ionic ideal-gas term N_i T_i / V is the caller's. Hartree/bohr^3.
+ * rho_dev: FP64 density at the current minimum (read only). eps in (0, 0.1);
+ * 1e-4 .. 1e-3 keeps the O(eps^2) error below 1e-6 of P. P (host) receives
+ * the pressure, F_lo / F_hi (may be NULL) the two free energies. The ctx's
+ * cell and ions are restored (V_loc and tables are rebuilt on next use).
+ * Returns SKX_OK or SKX_NOT_CONVERGED (a solve hit max_iter) or an error. */
+int skx_pressure(skx_ctx *ctx, const void *rho_dev, double eps, const skx_opt_params *p, double *P,
+                 double *F_lo, double *F_hi);
+
 /* ---- introspection (tests and tools) ---- */
 
 /* Copy the shell tables w[s], w'[s], s = g1^2+g2^2+g3^2 = 0..len-1, to host. */

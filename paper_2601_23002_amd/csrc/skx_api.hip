@@ -1622,6 +1622,61 @@ int md_step_impl(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *fo
 
 extern "C" {
 
+int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_params *p, double *P,
+                 double *F_lo, double *F_hi) {
+  if (!c) return SKX_E_INVALID;
+  c->err.clear();
+  if (!rho_dev || !p || !P) return fail(c, SKX_E_INVALID, "null argument");
+  if (!(eps > 0.0 && eps < 0.1)) return fail(c, SKX_E_INVALID, "eps must be in (0, 0.1)");
+  if (!c->has_cell || !c->has_ions || !c->has_fn)
+    return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
+  hipSetDevice(c->device);
+  hipStream_t s = c->stream;
+  const double L0 = c->L, V0 = L0 * L0 * L0;
+  const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
+  const int nions = (int)c->species.size();
+  const std::vector<double> pos0(c->pos), z(c->zsp), r(c->rcsp);
+  const std::vector<int> sp(c->species);
+  const size_t M = (size_t)n1 * n2 * n3;
+  void *work = nullptr;
+  hipError_t e = hipMalloc(&work, sizeof(double) * M);
+  if (e != hipSuccess) return hip_fail(c, e, "pressure work density");
+  double F[2] = {0.0, 0.0}, V[2] = {0.0, 0.0};
+  int rc = SKX_OK;
+  for (int k = 0; k < 2 && rc >= 0; ++k) {
+    // the cell scaled to V0 (1 -+ eps), ions at fixed fractional positions
+    V[k] = V0 * (k == 0 ? 1.0 - eps : 1.0 + eps);
+    const double L = std::cbrt(V[k]);
+    const double lat[9] = {L, 0, 0, 0, L, 0, 0, 0, L};
+    std::vector<double> pos(pos0);
+    for (double &x : pos) x *= L / L0;
+    rc = skx_set_cell(c, lat, n1, n2, n3);
+    if (rc == SKX_OK) rc = skx_set_ions(c, nions, pos.data(), sp.data(), (int)z.size(), z.data(), r.data());
+    if (rc == SKX_OK) {
+      e = hipMemcpyAsync(work, rho_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) rc = hip_fail(c, e, "density copy");
+    }
+    skx_opt_params q = *p;
+    q.warm_start = 1;
+    skx_opt_result res;
+    if (rc == SKX_OK) rc = skx_optimize_density(c, work, &q, &res);
+    if (rc >= 0) F[k] = res.e.total;
+  }
+  hipStreamSynchronize(s);
+  hipFree(work);
+  // restore the configuration (the error text of a failed solve is kept)
+  const std::string err = c->err;
+  const double lat0[9] = {L0, 0, 0, 0, L0, 0, 0, 0, L0};
+  int rc2 = skx_set_cell(c, lat0, n1, n2, n3);
+  if (rc2 == SKX_OK) rc2 = skx_set_ions(c, nions, pos0.data(), sp.data(), (int)z.size(), z.data(), r.data());
+  if (rc < 0) { c->err = err; return rc; }
+  if (rc2 != SKX_OK) return rc2;
+  *P = -(F[1] - F[0]) / (V[1] - V[0]);
+  if (F_lo) *F_lo = F[0];
+  if (F_hi) *F_hi = F[1];
+  return rc;
+}
+
 int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
                 const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res) {
   return md_step_impl(c, rho_dev, pos, vel, force, mass, dt, nullptr, p, res);

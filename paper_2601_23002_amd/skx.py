@@ -121,6 +121,8 @@ _sig("skx_md_step_nvt", C.c_int, [_VP, _VP, C.POINTER(C.c_double), C.POINTER(C.c
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                                   C.POINTER(NoseHoover), C.POINTER(OptParams),
                                   C.POINTER(OptResult)])
+_sig("skx_pressure", C.c_int, [_VP, _VP, C.c_double, C.POINTER(OptParams), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)])
 _sig("skx_get_kernel_tables", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int])
 _sig("skx_get_vloc", C.c_int, [_VP, C.POINTER(C.c_double)])
 _sig("skx_num_shells", C.c_int, [_VP])
@@ -330,6 +332,19 @@ class Context:
                                       lo, hi, xtol, C.byref(p), C.byref(beta), C.byref(dev),
                                       C.byref(ns)))
         return beta.value, dev.value, ns.value, rho
+
+    def pressure(self, rho, eps=1e-4, gtol=1e-9, max_iter=2000, m=5, fp32_switch_gtol=1e-5):
+        """-dF/dV (Hartree/bohr^3) at fixed fractional ion positions by a
+        central difference of minimised free energies; returns
+        (P, F(V(1-eps)), F(V(1+eps)))."""
+        torch = _torch()
+        if rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous():
+            raise ValueError("rho must be a contiguous float64 CUDA tensor")
+        p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1)
+        P, Flo, Fhi = C.c_double(), C.c_double(), C.c_double()
+        self._check(_lib.skx_pressure(self._h, _VP(rho.data_ptr()), eps, C.byref(p), C.byref(P),
+                                      C.byref(Flo), C.byref(Fhi)))
+        return P.value, Flo.value, Fhi.value
 
     def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
                 fp32_switch_gtol=1e-5, thermostat=None):
