@@ -420,7 +420,10 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     if (!(nd == nd) || nd > 1e300) bad += 1.0;
     if (nd > 0.0) {
       nel += nd;
-      lx = log(nd);
+      // FP32 evaluations take the logarithm in FP32 (its error is below
+      // the FP32 rounding of the potential it feeds)
+      lx = sizeof(R) == 4 ? (double)(0.69314718055994531f * __builtin_amdgcn_logf((float)n))
+                          : log(nd);
       // FP64: n^(1/3), shared by PZ81 and, for a = 5/6, by n^a
       if (sizeof(R) == 8 && (do_xc || a56)) e3 = exp(lx * (1.0 / 3.0));
       if (do_tf) {
