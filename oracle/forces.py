@@ -72,8 +72,9 @@ def local_energy(L: float, n, dens, pos, zval, rc) -> float:
     return float(L ** 3 * np.sum(np.real(nt * np.conj(vl))))
 
 
-def ewald_forces(L: float, pos, zval, alpha: float | None = None) -> np.ndarray:
-    """Minus the gradient of `ions.ewald` with respect to every position."""
+def ewald_forces(L: float, pos, zval, alpha: float | None = None, idx=None) -> np.ndarray:
+    """Minus the gradient of `ions.ewald` with respect to every position
+    (only the rows idx when given, the others left zero)."""
     pos = np.asarray(pos, dtype=np.float64)
     Z = np.asarray(zval, dtype=np.float64)
     V = L ** 3
@@ -85,7 +86,8 @@ def ewald_forces(L: float, pos, zval, alpha: float | None = None) -> np.ndarray:
     T = np.stack(np.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3) * L
     out = np.zeros((len(Z), 3))
     c = 2.0 * alpha / math.sqrt(math.pi)
-    for i in range(len(Z)):
+    rows = range(len(Z)) if idx is None else idx
+    for i in rows:
         d = (pos[i][None, :] - pos)[:, None, :] + T[None, :, :]      # (N, nT, 3)
         r = np.linalg.norm(d, axis=-1)
         mask = (r > 0) & (r < rcut)
@@ -105,5 +107,8 @@ def ewald_forces(L: float, pos, zval, alpha: float | None = None) -> np.ndarray:
     S = ph @ Z
     wG = np.exp(-G2 / (4.0 * alpha ** 2)) / G2
     im = np.imag(ph * np.conj(S)[:, None])                            # (nG, N)
-    out += (4.0 * math.pi / V) * Z[:, None] * ((wG[:, None] * im).T @ G)
+    rec = (4.0 * math.pi / V) * Z[:, None] * ((wG[:, None] * im).T @ G)
+    if idx is None:
+        return out + rec
+    out[list(idx)] += rec[list(idx)]
     return out

@@ -59,3 +59,26 @@ def structure_factors(L: float, n, dens, pos, nelec: float):
     s_ee = shell_mean(np.abs(ne) ** 2) / nelec
     s_ii = shell_mean(np.abs(ni) ** 2) / nI
     return s_ei, s_ee, s_ii, cnt
+
+
+def structure_factors_at(L: float, n, dens, pos, nelec: float, shells):
+    """The same shell averages for the listed shells only (every grid index
+    of those shells summed directly): S_ei, S_ee, S_ii and counts."""
+    V = L ** 3
+    ne = V * fft.fft3(np.asarray(dens, dtype=np.float64))
+    (g1, g2, g3), _ = ions.gvectors(L, n)
+    s = g1 * g1 + g2 * g2 + g3 * g3
+    k = 2.0 * math.pi / L
+    pos = np.asarray(pos)
+    nI = len(pos)
+    out = []
+    for sh in shells:
+        sel = s == sh
+        G = np.stack([g1[sel], g2[sel], g3[sel]], -1) * k             # (count, 3)
+        ni = np.exp(-1j * (G @ pos.T)).sum(axis=1)
+        e = ne[sel]
+        c = int(np.count_nonzero(sel))
+        out.append((float(np.sum(np.real(e * np.conj(ni)))) / c / math.sqrt(nelec * nI),
+                    float(np.sum(np.abs(e) ** 2)) / c / nelec,
+                    float(np.sum(np.abs(ni) ** 2)) / c / nI, c))
+    return out

@@ -259,3 +259,28 @@ def test_nvt_conserves_the_extended_energy_and_heats_a_cold_start():
     _say(f"  kinetic {kes[0]:.3e} -> {kes[-1]:.3e} Ha, xi {nh.xi:.3e}, extended-energy drift {drift:.3e} Ha")
     assert nh.xi < 0.0                       # heating: the thermostat pushes energy in
     assert drift < 0.02 * swing
+
+
+def test_forces_at_the_largest_serving_size_on_sampled_ions():
+    """192^3 with 1024 ions (the largest grid and ion count of the serving
+    mix): every force from the GPU, four sampled ions from the oracle."""
+    skx, torch = _lib()
+    from oracle import forces
+    _say("case: forces 1024 ions 192^3, sampled ions")
+    n = (192, 192, 192)
+    rng = np.random.default_rng(95)
+    nions = 1024
+    zval = np.where(rng.random(nions) < 0.5, 1.0, 4.0)
+    rc = np.where(zval > 1.0, 0.5, 0.3)
+    L = W.cell_side(float(np.sum(zval)), 2.5)
+    pos = rng.uniform(0.0, L, size=(nions, 3))
+    dens = 0.01 + 0.05 * rng.random(n)
+    c = _ctx(skx, L, n, pos, zval, rc)
+    rho = torch.tensor(dens, dtype=torch.float64, device="cuda:0")
+    f_loc, f_ii = c.ion_forces(rho, kind=skx.RHO)
+    pick = [0, 311, 640, 1023]
+    ref_loc = forces.local_forces(L, n, dens, pos[pick], zval[pick], rc[pick])
+    ref_ii = forces.ewald_forces(L, pos, zval, idx=pick)[pick]
+    assert np.max(np.abs(f_loc[pick] - ref_loc)) < 1e-10 * np.max(np.abs(ref_loc))
+    assert np.max(np.abs(f_ii[pick] - ref_ii)) < 1e-10 * np.max(np.abs(ref_ii))
+    assert np.max(np.abs(f_ii.sum(axis=0))) < 1e-9 * np.max(np.abs(f_ii))

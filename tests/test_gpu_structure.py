@@ -92,3 +92,30 @@ def test_structure_factor_errors():
     assert lib.skx_structure_factors(c._h, _VP(rho.data_ptr()), skx.RHO, None, None, None, None,
                                      ns) == skx.E_INVALID
     assert lib.skx_structure_factors(c._h, None, skx.RHO, p, None, None, None, ns) == skx.E_INVALID
+
+
+def test_structure_factors_at_the_largest_serving_size_on_sampled_shells():
+    """192^3 with 1024 ions: every shell from the GPU, a sample of shells
+    (small and large |q|) from the oracle's direct sums."""
+    skx, torch = _lib()
+    from oracle import structure
+    _say("case: structure factors 1024 ions 192^3, sampled shells")
+    n = (192, 192, 192)
+    rng = np.random.default_rng(96)
+    zval = np.where(rng.random(1024) < 0.5, 1.0, 4.0)
+    rc = np.where(zval > 1.0, 0.5, 0.3)
+    L = W.cell_side(float(np.sum(zval)), 2.5)
+    pos = rng.uniform(0.0, L, size=(1024, 3))
+    dens = 0.01 + 0.05 * rng.random(n)
+    c = skx.Context(0)
+    c.set_cell(L, n)
+    c.set_ions(pos, zval, rc)
+    rho = torch.tensor(dens, dtype=torch.float64, device="cuda:0")
+    ei, ee, ii, cnt = c.structure_factors(rho)
+    shells = (1, 2, 3, 14, 200, 9216, 27648)
+    for sh, (rei, ree, rii, rc_) in zip(shells, structure.structure_factors_at(
+            L, n, dens, pos, float(np.sum(zval)), shells)):
+        assert cnt[sh] == rc_
+        assert abs(ei[sh] - rei) < 1e-10 * max(abs(rei), 1e-3 * np.max(np.abs(ei[1:])))
+        assert abs(ee[sh] - ree) < 1e-10 * max(abs(ree), 1e-3 * np.max(np.abs(ee[1:])))
+        assert abs(ii[sh] - rii) < 1e-10 * abs(rii)

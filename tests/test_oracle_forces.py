@@ -116,3 +116,14 @@ def test_ewald_force_of_a_close_pair_is_coulomb():
     F = forces.ewald_forces(L, pos, [1.0, 2.0])
     assert abs(F[0, 0] + 2.0) < 2e-3 and abs(F[1, 0] - 2.0) < 2e-3
     assert np.max(np.abs(F[:, 1:])) < 1e-12
+
+
+def test_ewald_force_rows_equal_the_full_computation():
+    L = 7.0
+    rng = np.random.default_rng(9)
+    pos = rng.random((6, 3)) * L
+    Z = rng.choice([1.0, 4.0], 6)
+    full = forces.ewald_forces(L, pos, Z)
+    part = forces.ewald_forces(L, pos, Z, idx=[1, 4])
+    assert np.array_equal(part[[1, 4]], full[[1, 4]])
+    assert np.all(part[[0, 2, 3, 5]] == 0.0)

@@ -99,3 +99,17 @@ def test_shell_sums_by_brute_force():
         assert abs(s_ei[s] - ei / c / math.sqrt(ne * 3)) < 1e-12 * max(1.0, abs(s_ei[s]))
         assert abs(s_ee[s] - ee / c / ne) < 1e-12 * max(1.0, abs(s_ee[s]))
         assert abs(s_ii[s] - ii / c / 3) < 1e-12 * max(1.0, abs(s_ii[s]))
+
+
+def test_selected_shells_equal_the_full_computation():
+    L, n = 6.0, (10, 12, 8)
+    rng = np.random.default_rng(12)
+    dens = 0.1 + rng.random(n)
+    pos = rng.random((4, 3)) * L
+    full = structure.structure_factors(L, n, dens, pos, 3.0)
+    for sh, (ei, ee, ii, c) in zip((1, 2, 9, 41), structure.structure_factors_at(
+            L, n, dens, pos, 3.0, (1, 2, 9, 41))):
+        assert c == full[3][sh]
+        assert abs(ei - full[0][sh]) < 1e-12 * max(1.0, abs(ei))
+        assert abs(ee - full[1][sh]) < 1e-12 * max(1.0, abs(ee))
+        assert abs(ii - full[2][sh]) < 1e-12 * max(1.0, abs(ii))
