@@ -245,7 +245,9 @@ int skx_fit_beta(skx_ctx *ctx, const void *rho_ref_dev, void *rho_dev, double be
  *   on exit. p, res: as skx_optimize_density.
  * Returns SKX_OK or SKX_NOT_CONVERGED (the step is completed with the best
  * density) or an error of the calls above; SKX_E_INVALID for null
- * arguments, dt <= 0 or a non-positive mass. */
+ * arguments, dt <= 0 or a non-positive mass (checked before anything
+ * moves). After an error of the solve or the forces, pos and vel hold the
+ * drifted values and force the old forces. */
 int skx_md_step(skx_ctx *ctx, void *rho_dev, double *pos, double *vel, double *force,
                 const double *mass, double dt, const skx_opt_params *p, skx_opt_result *res);
 
