@@ -14,10 +14,12 @@ sum over solves of (evaluations x grid points) / wall time of the step.
 The plain FP64 GPU path is timed on the same workload for the speedup,
 and the mixed results are checked against it per solve (Ha/atom).
 
-The headline timed region records a HIP-event pair around every pass launch
-(the library then launches eagerly); the per-pass times and the roofline come
-from those events. The same steps are then timed again replayed from captured
-HIP graphs without events (value_graphs).
+One untimed step first carries HIP events on every pass launch (per-pass
+times, and which evaluation kernel dominates). In the timed steps only the
+dominant kernel's launches carry start/stop events (the library launches
+eagerly, its default); the roofline comes from those events. The same steps
+are then timed without any events (value_no_events) and replayed from
+captured HIP graphs (value_graphs).
 """
 from __future__ import annotations
 
@@ -54,6 +56,9 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests per second")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default FFT radix orders instead of timing the candidates")
+    ap.add_argument("--graphs", choices=("default", "on", "off"), default="default",
+                    help="replay the batched step sequences from HIP graphs or launch them "
+                         "eagerly (default: the library's setting)")
     ap.add_argument("--no-forces", action="store_true",
                     help="skip the forces / MD-step measurement after the headline steps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -251,7 +256,7 @@ def forces_leg(args, skx, systems, ctxs, rhos):
 
 def run_ensemble(args):
     """Uneven thermal-like snapshots solved together: one launch per kernel
-    over every resident solve, step sequences replayed from a HIP graph."""
+    over every resident solve."""
     import numpy as np
     import torch
     from paper_2601_23002_amd import skx
@@ -266,7 +271,7 @@ def run_ensemble(args):
         rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
         kw = dict(gtol=args.gtol, max_iter=args.fp64_max_iter if prec == skx.FP64 else 3000,
                   m=5, fp32_switch_gtol=1e-5)
-        skx.run_batch(ctxs[:8], rhos[:8], **kw)          # warm-up (kernels, graph path)
+        skx.run_batch(ctxs[:8], rhos[:8], **kw)          # warm-up (kernels, tables)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = skx.run_batch(ctxs, rhos, **kw)
@@ -291,7 +296,7 @@ def run_ensemble(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": f"ensemble: {count} thermal-like snapshots, 16-256 Z=1/Z=4 ions, "
-                                  f"grids {sizes[0]}^3-{sizes[-1]}^3, one batch, HIP-graph steps",
+                                  f"grids {sizes[0]}^3-{sizes[-1]}^3, one batch",
                       "global_batch": count, "parallelism": "batch"},
            "fp64_value": res["fp64"]["value"],
            "speedup_vs_fp64": res["mixed"]["value"] / res["fp64"]["value"],
@@ -397,6 +402,8 @@ def main():
     from paper_2601_23002_amd import skx
     from paper_2601_23002_amd import workloads as W
     skx.set_autotune(not args.no_autotune)
+    if args.graphs != "default":
+        skx.set_graphs(args.graphs == "on")
     if args.workload == "ensemble":
         return run_ensemble(args)
     if args.workload == "serve":
@@ -439,8 +446,21 @@ def main():
     ctxs, rhos = make(skx.MIXED)
     for _ in range(args.warmup):
         step(ctxs, rhos)
+    # one untimed step with every pass carrying HIP events: per-pass times
+    # and the dominant evaluation kernel
     torch.cuda.synchronize()
     skx.profile_reset()
+    skx.profile_mask(None)
+    skx.profile_enable(True)
+    step(ctxs, rhos)
+    torch.cuda.synchronize()
+    skx.profile_enable(False)
+    prof_all = skx.profile_read()
+    dom = max(("point", "passA", "passB", "passC"), key=lambda k: prof_all[k][0])
+    # the timed steps: only the dominant kernel's launches carry events
+    torch.cuda.synchronize()
+    skx.profile_reset()
+    skx.profile_mask([dom])
     skx.profile_enable(True)
     total_work = 0
     evals = {"fp32": 0, "fp64": 0}
@@ -469,22 +489,28 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     skx.profile_enable(False)
+    skx.profile_mask(None)
     prof = skx.profile_read()
     value = total_work / wall
 
-    # the same steps replayed from captured HIP graphs (no per-launch events)
-    graph_work = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for it in range(args.steps):
-        graph_work += work(step(ctxs, rhos))
-    torch.cuda.synchronize()
-    wall_graph = time.perf_counter() - t0
-    print(f"graph steps: {wall_graph:.3f} s", file=sys.stderr, flush=True)
+    # the same steps without any events, and replayed from captured HIP graphs
+    def timed_steps():
+        w = 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for it in range(args.steps):
+            w += work(step(ctxs, rhos))
+        torch.cuda.synchronize()
+        return w, time.perf_counter() - t
+    plain_work, wall_plain = timed_steps()
+    old_graphs = skx.set_graphs(True)
+    graph_work, wall_graph = timed_steps()
+    skx.set_graphs(old_graphs)
+    print(f"plain steps: {wall_plain:.3f} s, graph steps: {wall_graph:.3f} s", file=sys.stderr,
+          flush=True)
     forces_out = None if args.no_forces else forces_leg(args, skx, systems, ctxs, rhos)
 
-    # roofline of the dominant evaluation kernel
-    dom = max(("point", "passA", "passB", "passC"), key=lambda k: prof[k][0])
+    # roofline of the dominant evaluation kernel (its events in the timed steps)
     ms, launches = prof[dom]
     avg_s = ms / 1e3 / max(1, launches)
     achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9
@@ -512,7 +538,9 @@ def main():
                                "64^3, batched, FP32 to |r|<%g then FP64 to |r|<%g" % (args.switch_gtol, args.gtol),
                    "global_batch": len(systems), "grid": 64, "parallelism": "batch"},
         "roofline": roof,
-        "passes_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "passes_ms_profiled_step": {k: round(v[0], 3) for k, v in prof_all.items() if v[1] > 0},
+        "value_no_events": plain_work / wall_plain,
+        "ms_per_step_no_events": wall_plain / args.steps * 1e3,
         "value_graphs": graph_work / wall_graph,
         "ms_per_step_graphs": wall_graph / args.steps * 1e3,
         "evals": evals,
@@ -527,7 +555,7 @@ def main():
             rerr.append(float(np.sum(np.abs(n_m - fp64["rho"][i])) / np.sum(fp64["rho"][i])))
         out["fp64_value"] = fp64["value"]
         out["speedup_vs_fp64"] = value / fp64["value"]
-        out["time_speedup_vs_fp64"] = fp64["seconds"] / (wall_graph / args.steps)
+        out["time_speedup_vs_fp64"] = fp64["seconds"] / (wall_plain / args.steps)
         out["max_err_ha_per_atom"] = max(err)
         out["max_rel_density_err"] = max(rerr)
         out["iters_fp64"] = fp64["iters"]

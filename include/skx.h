@@ -314,14 +314,19 @@ int skx_fft_check(skx_ctx *ctx, const double *in_host, double *out_host, double 
  * up to n entries of total milliseconds and launch counts and returns the
  * number of passes. */
 int skx_profile_enable(int on);
+/* Passes timed while profiling is on: bit i for pass i of the list above
+ * (all by default); the other passes launch without events. Returns the
+ * previous mask. */
+unsigned skx_profile_mask(unsigned mask);
 int skx_profile_reset(void);
 int skx_profile_read(double *ms, long long *launches, int n);
 
 /* Process-wide: capture the optimisation driver's fixed chunk of step
- * sequences once per batch into a HIP graph and replay it (on = 1, the
- * default), or launch every kernel eagerly (on = 0). Results are identical
- * either way. While per-pass profiling is enabled the driver launches
- * eagerly. Returns the previous setting. */
+ * sequences once per batch into a HIP graph and replay it (on = 1), or
+ * launch every kernel eagerly (on = 0, the default: faster on the 64^3
+ * scan, equal on larger grids). Results are identical either way. While
+ * per-pass profiling is enabled the driver launches eagerly. Returns the
+ * previous setting. */
 int skx_set_graphs(int on);
 
 /* Process-wide FFT autotuner (off by default). When on, the first set-up of

@@ -132,6 +132,7 @@ _sig("skx_fft_check", C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double
                                 C.POINTER(C.c_double)])
 _sig("skx_profile_enable", C.c_int, [C.c_int])
 _sig("skx_set_graphs", C.c_int, [C.c_int])
+_sig("skx_profile_mask", C.c_uint, [C.c_uint])
 _sig("skx_set_autotune", C.c_int, [C.c_int])
 _sig("skx_set_shape_kernels", C.c_int, [C.c_int])
 _sig("skx_set_plane_chunking", C.c_int, [C.c_int])
@@ -424,9 +425,16 @@ def profile_enable(on=True):
     _lib.skx_profile_enable(1 if on else 0)
 
 
+def profile_mask(passes=None):
+    """Time only the named passes (PASS_NAMES) while profiling; None: all.
+    Returns the previous mask."""
+    mask = 0xFFFFFFFF if passes is None else sum(1 << PASS_NAMES.index(p) for p in passes)
+    return _lib.skx_profile_mask(mask)
+
+
 def set_graphs(on=True):
-    """Replay the driver's step sequences from a captured HIP graph (default)
-    or launch them eagerly; returns the previous setting."""
+    """Replay the driver's step sequences from a captured HIP graph, or
+    launch them eagerly (the default); returns the previous setting."""
     return bool(_lib.skx_set_graphs(1 if on else 0))
 
 

@@ -143,6 +143,7 @@ def test_graph_replay_equals_eager():
     systems = _systems()
     kw = dict(gtol=1e-9, max_iter=400, m=5, fp32_switch_gtol=1e-5)
     out = {}
+    old = skx.set_graphs(False)
     for graphs in (False, True, True):
         _say(f"case: run_batch mixed, graphs={graphs}")
         skx.set_graphs(graphs)
@@ -157,7 +158,7 @@ def test_graph_replay_equals_eager():
             assert key == out["eager"][0]
             for a, b in zip(dens, out["eager"][1]):
                 assert np.array_equal(a, b)
-    skx.set_graphs(True)
+    skx.set_graphs(old)
 
 
 def test_mixed_precision_96cubed_beryllium_like():
