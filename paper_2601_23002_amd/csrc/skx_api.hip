@@ -742,9 +742,10 @@ hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
 
 // Drive a batch until every solve is DONE or FAILED. States are polled
 // every `chunk` steps; the step sequence itself makes every decision, so a
-// chunk is the same work every time and is captured once into a HIP graph
-// (eager launches when graphs are off, while per-pass events are on, or when
-// capture is refused). When half of the solves have finished, the batch is
+// chunk is the same work every time: launched eagerly (the default), or,
+// with graphs on, captured once into a HIP graph and replayed (eager again
+// while per-pass events are on or when capture is refused). When half of
+// the solves have finished, the batch is
 // rebuilt from the unfinished ones (into the same descriptor buffers) so that
 // the launches stop covering finished solves; a solve's arithmetic does not
 // depend on the batch it is in.
