@@ -606,6 +606,23 @@ __global__ void k_gather_phases(const SolveDev *dev, int n, int *out) {
   if (i < n) out[i] = dev[i].st->phase;
 }
 
+// Optimiser states between one packed array and the per-solve state
+// buffers (their addresses in a device array): one workgroup per state,
+// 4-byte words.
+__global__ void k_put_states(const OptState *src, OptState *const *dst, int n) {
+  constexpr int W = (int)(sizeof(OptState) / 4);
+  const int *a = reinterpret_cast<const int *>(src + blockIdx.x);
+  int *b = reinterpret_cast<int *>(dst[blockIdx.x]);
+  for (int w = threadIdx.x; w < W; w += blockDim.x) b[w] = a[w];
+}
+
+__global__ void k_get_states(OptState *const *src, OptState *dst, int n) {
+  constexpr int W = (int)(sizeof(OptState) / 4);
+  const int *a = reinterpret_cast<const int *>(src[blockIdx.x]);
+  int *b = reinterpret_cast<int *>(dst + blockIdx.x);
+  for (int w = threadIdx.x; w < W; w += blockDim.x) b[w] = a[w];
+}
+
 hipError_t gather_phases(const SolveDev *dev, int n, int *out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_phases, dim3(blocks(n, 256)), dim3(256), 0, s, dev, n, out);
@@ -761,7 +778,18 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
   int *dph = nullptr;
   e = hipMallocAsync((void **)&dph, sizeof(int) * n, s);
   if (e != hipSuccess) return hip_fail(c, e, "phase buffer");
-  std::vector<int> ph(n);
+  // the phases are read back into pinned host memory (kept per thread for
+  // the life of the process), which avoids a staged copy at every poll
+  static thread_local int *ph = nullptr;
+  static thread_local int ph_cap = 0;
+  if (ph_cap < n) {
+    if (ph) hipHostFree(ph);
+    ph = nullptr;
+    ph_cap = 0;
+    e = hipHostMalloc((void **)&ph, sizeof(int) * n, hipHostMallocDefault);
+    if (e != hipSuccess) { hipFreeAsync(dph, s); return hip_fail(c, e, "pinned phase buffer"); }
+    ph_cap = n;
+  }
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto drop_graph = [&]() {
@@ -796,7 +824,7 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
       if (e != hipSuccess) { rc = hip_fail(c, e, "step kernels"); break; }
     }
     steps += chunk;
-    e = hipMemcpyAsync(ph.data(), dph, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(ph, dph, sizeof(int) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { rc = hip_fail(c, e, "step execution"); break; }
     prof_fold();
@@ -1724,8 +1752,12 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   hipStream_t s = c0->stream;
   SolveDev *ddev = nullptr;
   int *dfirst = nullptr;
+  OptState *dstage = nullptr;           // packed states (upload and readback)
+  OptState **dsptr = nullptr;           // each solve's state buffer
   hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * NPREFIX * (nctx + 1), s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dstage, sizeof(OptState) * nctx, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dsptr, sizeof(OptState *) * nctx, s);
   if (e != hipSuccess) return hip_fail(c0, e, "batch descriptors");
   std::vector<OptState> outs(nctx), o32(nctx);
   int rc = SKX_OK;
@@ -1736,6 +1768,7 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
                              : std::max(p->gtol, p->fp32_switch_gtol > 0 ? p->fp32_switch_gtol : 1e-5);
     std::vector<SolveDev> hs;
     std::vector<OptState *> states;
+    std::vector<OptState> init(nctx);
     for (int i = 0; i < nctx; ++i) {
       Instance &I = ctxs[i]->inst[pr];
       const long long M = I.h.M;
@@ -1762,22 +1795,27 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
           hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
                              (float *)I.h.phi2[0], (float)v, M);
       }
-      OptState st;
-      init_state(st, *p, gtol, start == 1 ? 1 : 0, pr);
-      e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
-      if (e != hipSuccess) { rc = hip_fail(c0, e, "state upload"); break; }
+      init_state(init[i], *p, gtol, start == 1 ? 1 : 0, pr);
       hs.push_back(I.h);
       states.push_back(I.st);
     }
-    if (rc) break;
+    // every state in one copy, scattered to the solves' buffers on the device
+    e = hipMemcpyAsync(dstage, init.data(), sizeof(OptState) * nctx, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dsptr, states.data(), sizeof(OptState *) * nctx, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_put_states, dim3(nctx), dim3(64), 0, s, dstage, dsptr, nctx);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) { rc = hip_fail(c0, e, "state upload"); break; }
     rc = drive(c0, hs, pr, ddev, dfirst, (p->max_iter + 2) * 24 + 64, s);
     if (rc) break;
-    for (int i = 0; i < nctx; ++i) {
-      OptState *dst = last ? &outs[i] : &o32[i];
-      e = hipMemcpyAsync(dst, states[i], sizeof(OptState), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) { rc = hip_fail(c0, e, "state readback"); break; }
-    }
-    if (rc) break;
+    hipLaunchKernelGGL(k_get_states, dim3(nctx), dim3(64), 0, s, dsptr, dstage, nctx);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(last ? outs.data() : o32.data(), dstage, sizeof(OptState) * nctx,
+                         hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) { rc = hip_fail(c0, e, "state readback"); break; }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) { rc = hip_fail(c0, e, "batch"); break; }
   }
@@ -1813,6 +1851,8 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   }
   hipFreeAsync(ddev, s);
   hipFreeAsync(dfirst, s);
+  hipFreeAsync(dstage, s);
+  hipFreeAsync(dsptr, s);
   hipStreamSynchronize(s);
   if (rc) return rc;
   int worst = SKX_OK;
