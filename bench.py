@@ -124,20 +124,36 @@ def fields_count(sys_):
     return nf
 
 
-def cpu_baseline(sys_, seed=5):
-    """The oracle as it stands, one FP64 evaluation of one 64^3 system."""
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def cpu_baseline(sys_, seed=5, reps=3):
+    """The oracle as it stands: the median of `reps` FP64 evaluations of one
+    64^3 system on one thread."""
     from threadpoolctl import threadpool_limits
     from paper_2601_23002_amd import workloads as W
     from oracle.functional import Problem
+    times = []
     with threadpool_limits(limits=1):
         p = Problem(sys_)
         phi = W.random_phi(sys_, seed)
-        t0 = time.perf_counter()
-        p.evaluate(phi)
-        dt = time.perf_counter() - t0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            p.evaluate(phi)
+            times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
     return dict(value=sys_.M / dt, unit="grid-pt evals/s", cores=1, kind="oracle",
-                sample=f"one FP64 evaluation (all terms, energy + dE/dphi) of one {sys_.n[0]}^3 "
-                       f"scan system, single thread, {dt:.1f} s")
+                sample=f"median of {reps} FP64 evaluations (all terms, energy + dE/dphi) of one "
+                       f"{sys_.n[0]}^3 scan system, single thread, {dt:.1f} s each; host "
+                       f"{_host_cpu()}, {os.cpu_count()} logical CPUs")
 
 
 FP64_VEC_PEAK_TFLOPS = 78.6
