@@ -87,6 +87,12 @@ struct skx_engine {
   std::vector<Resident *> resident;
   Group group[2];                        // by precision: 0 FP64, 1 FP32
   std::deque<Finished> done;
+  // contexts of finished solves kept for reuse by a request of the same grid
+  // (their device arenas stay allocated: no allocation or free, and so no
+  // device-wide synchronisation, per request)
+  struct Pooled { skx_ctx *ctx; int n1, n2, n3, mode, m; size_t bytes; };
+  std::vector<Pooled> pool;
+  size_t pooled = 0;                     // bytes held by pooled contexts
   std::chrono::steady_clock::time_point t0;
   std::string err;
   double now() const {
@@ -142,11 +148,18 @@ double phase_gtol(const Resident &r) {
 
 // Set up one queued request as a resident solve (context, tables, V_loc,
 // uniform start) on the engine stream.
-int admit(skx_engine *e, Queued &q, Resident *&out) {
+int admit(skx_engine *e, Queued &q, int pooled_idx, Resident *&out) {
   const skx_request &r = q.req;
   skx_ctx *c = nullptr;
-  int rc = skx_create(&c, e->device, (void *)e->stream);
-  if (rc) return eng_fail(e, rc, "context creation failed");
+  int rc = SKX_OK;
+  if (pooled_idx >= 0) {
+    c = e->pool[pooled_idx].ctx;
+    e->pooled -= e->pool[pooled_idx].bytes;
+    e->pool.erase(e->pool.begin() + pooled_idx);
+  } else {
+    rc = skx_create(&c, e->device, (void *)e->stream);
+    if (rc) return eng_fail(e, rc, "context creation failed");
+  }
   auto bad = [&](int code) {
     std::string m = "request " + std::to_string(q.ticket) + ": " + c->err;
     skx_destroy(c);
@@ -257,13 +270,19 @@ void finish(skx_engine *e, Resident *r, const OptState &o) {
   else f.res.r.status = (o.phase == PH_DONE && o.status == 0) ? SKX_OK : SKX_NOT_CONVERGED;
   f.res.npoints = I.h.M;
   f.res.t_admit = r->t_admit;
-  if (hipMalloc((void **)&f.rho_dev, sizeof(double) * I.h.M) == hipSuccess)
+  if (hipMallocAsync((void **)&f.rho_dev, sizeof(double) * I.h.M, e->stream) == hipSuccess)
     square_out(I, o.par, f.rho_dev, e->stream);
   else
     f.rho_dev = nullptr;
   hipStreamSynchronize(e->stream);
   f.res.t_done = e->now();
-  skx_destroy(c);
+  if ((int)e->pool.size() < e->max_slots) {
+    const int m = std::min(std::max(r->opt.lbfgs_m, 1), MMAX);
+    e->pool.push_back({c, c->n1, c->n2, c->n3, r->mode, m, r->bytes});
+    e->pooled += r->bytes;
+  } else {
+    skx_destroy(c);
+  }
   e->used -= std::min(e->used, r->bytes);
   e->done.push_back(f);
   delete r;
@@ -333,9 +352,31 @@ int skx_engine_submit(skx_engine *e, const skx_request *req, uint64_t *ticket) {
 int skx_engine_step(skx_engine *e) {
   if (!e) return SKX_E_INVALID;
   hipSetDevice(e->device);
-  // admission in arrival order
-  while (!e->queue.empty() && (int)e->resident.size() < e->max_slots &&
-         e->used + e->queue.front().bytes <= e->budget) {
+  // admission in arrival order; a pooled context of the same grid, mode
+  // and history length is reused, others are freed when the budget needs
+  // their memory
+  while (!e->queue.empty() && (int)e->resident.size() < e->max_slots) {
+    const Queued &qf = e->queue.front();
+    const int m = std::min(std::max(qf.req.opt.lbfgs_m, 1), MMAX);
+    int mi = -1;
+    for (size_t i = 0; i < e->pool.size() && mi < 0; ++i) {
+      const skx_engine::Pooled &p = e->pool[i];
+      if (p.n1 == qf.req.n1 && p.n2 == qf.req.n2 && p.n3 == qf.req.n3 &&
+          p.mode == qf.req.fn.precision && p.m >= m)
+        mi = (int)i;
+    }
+    const size_t reuse = mi >= 0 ? e->pool[mi].bytes : 0;
+    while (e->used + e->pooled - reuse + qf.bytes > e->budget) {
+      int victim = -1;
+      for (size_t i = 0; i < e->pool.size() && victim < 0; ++i)
+        if ((int)i != mi) victim = (int)i;
+      if (victim < 0) break;
+      skx_destroy(e->pool[victim].ctx);
+      e->pooled -= e->pool[victim].bytes;
+      e->pool.erase(e->pool.begin() + victim);
+      if (mi > victim) --mi;
+    }
+    if (e->used + e->pooled - reuse + qf.bytes > e->budget) break;
     Queued q = std::move(e->queue.front());
     e->queue.pop_front();
     q.req.pos = q.pos.data();
@@ -343,7 +384,7 @@ int skx_engine_step(skx_engine *e) {
     q.req.zval = q.zval.data();
     q.req.rc = q.rc.data();
     Resident *r = nullptr;
-    int rc = admit(e, q, r);
+    int rc = admit(e, q, mi, r);
     if (rc) {
       // the request fails alone: report it as a finished result
       Finished f{};
@@ -427,7 +468,7 @@ int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, 
     if (f.rho_dev) {
       if (rho_host && rho_host[k])
         hipMemcpy(rho_host[k], f.rho_dev, sizeof(double) * f.res.npoints, hipMemcpyDeviceToHost);
-      hipFree(f.rho_dev);
+      hipFreeAsync(f.rho_dev, e->stream);
     }
     ++k;
   }
@@ -450,7 +491,10 @@ void skx_engine_destroy(skx_engine *e) {
     delete r;
   }
   for (Finished &f : e->done)
-    if (f.rho_dev) hipFree(f.rho_dev);
+    if (f.rho_dev) hipFreeAsync(f.rho_dev, e->stream);
+  for (skx_engine::Pooled &p : e->pool) skx_destroy(p.ctx);
+  e->pool.clear();
+  hipStreamSynchronize(e->stream);
   for (Group &g : e->group) {
     g.drop_graph();
     if (g.ddev) hipFree(g.ddev);
