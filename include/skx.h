@@ -389,7 +389,11 @@ typedef struct {
 
 typedef struct skx_engine skx_engine;
 /* hbm_budget_bytes bounds the device memory of resident solves;
- * max_slots bounds how many solves are resident at once. */
+ * max_slots bounds how many solves are resident at once. The contexts of
+ * up to max_slots finished solves are kept (their memory counted against
+ * the budget) and reused by requests of the same grid, precision mode and
+ * history length; they are freed when an admission needs the memory and at
+ * skx_engine_destroy. */
 int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int max_slots);
 /* Copies the request; SKX_E_INVALID if it can never fit the budget. */
 int skx_engine_submit(skx_engine *eng, const skx_request *req, uint64_t *ticket);
