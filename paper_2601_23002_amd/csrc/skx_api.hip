@@ -984,15 +984,23 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
   c->ne = ne;
   std::vector<double> zi(nions);
   for (int i = 0; i < nions; ++i) zi[i] = zval[species[i]];
-  hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
-  c->ion_pos = c->ion_z = c->sp_z = c->sp_rc = nullptr;
-  c->ion_sp = nullptr;
-  hipError_t e = hipMalloc((void **)&c->ion_pos, sizeof(double) * 3 * nions);
-  if (e == hipSuccess) e = hipMalloc((void **)&c->ion_z, sizeof(double) * nions);
-  if (e == hipSuccess) e = hipMalloc((void **)&c->sp_z, sizeof(double) * nspecies);
-  if (e == hipSuccess) e = hipMalloc((void **)&c->sp_rc, sizeof(double) * nspecies);
-  if (e == hipSuccess) e = hipMalloc((void **)&c->ion_sp, sizeof(int) * nions);
-  if (e != hipSuccess) return hip_fail(c, e, "ion arrays");
+  // the device ion arrays are reallocated only when they must grow (a free
+  // synchronises the whole device; MD steps and engine reuse call this often)
+  hipError_t e = hipSuccess;
+  if (nions > c->ion_cap || nspecies > c->sp_cap || !c->ion_pos) {
+    hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
+    c->ion_pos = c->ion_z = c->sp_z = c->sp_rc = nullptr;
+    c->ion_sp = nullptr;
+    c->ion_cap = c->sp_cap = 0;
+    e = hipMalloc((void **)&c->ion_pos, sizeof(double) * 3 * nions);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->ion_z, sizeof(double) * nions);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->sp_z, sizeof(double) * nspecies);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->sp_rc, sizeof(double) * nspecies);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->ion_sp, sizeof(int) * nions);
+    if (e != hipSuccess) return hip_fail(c, e, "ion arrays");
+    c->ion_cap = nions;
+    c->sp_cap = nspecies;
+  }
   hipStream_t s = c->stream;
   hipMemcpyAsync(c->ion_pos, c->pos.data(), sizeof(double) * 3 * nions, hipMemcpyHostToDevice, s);
   hipMemcpyAsync(c->ion_z, zi.data(), sizeof(double) * nions, hipMemcpyHostToDevice, s);

@@ -49,6 +49,7 @@ struct skx_ctx {
   skx::host::Instance inst[2];
   double *ion_pos = nullptr, *ion_z = nullptr, *sp_z = nullptr, *sp_rc = nullptr;
   int *ion_sp = nullptr;
+  int ion_cap = 0, sp_cap = 0;     // capacities of the device ion arrays
   // half-spectrum indices listed by shell (structure factors), for grid sf_n
   int *sf_off = nullptr, *sf_idx = nullptr;
   int sf_n[3] = {0, 0, 0};
