@@ -235,7 +235,9 @@ int skx_fit_beta(skx_ctx *ctx, const void *rho_ref_dev, void *rho_dev, double be
  * skx_md_step_nvt adds the thermostat), the density warm-started from the
  * previous minimum:
  *   v += (dt/2) F/m;  R += dt v (wrapped into the cell);  minimise the
- *   density from rho_dev (skx_optimize_density, warm_start forced);
+ *   density (skx_optimize_density, warm_start forced) from rho_dev, or from
+ *   max(2 n(t) - n(t - dt), n(t) / 10) once the ctx holds the density of the
+ *   step before (kept by the ctx, an M-double buffer; only a start guess);
  *   F = f_loc + f_ii at the new minimum (skx_ion_forces);  v += (dt/2) F/m.
  * pos, vel, force: host [nions][3] in bohr, bohr per atomic time unit and
  *   Hartree/bohr, updated in place; force must hold the forces at pos on

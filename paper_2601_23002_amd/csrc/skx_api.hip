@@ -547,6 +547,16 @@ __global__ void k_sqrt_field(const double *in, double *out, long long n) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < n) { double v = in[i]; out[i] = v > 0 ? sqrt(v) : 0.0; }
 }
+// MD start density: n <- max(2 n - n_prev, n / 10) (second-order extrapolation
+// in time, kept positive), n_prev <- the old n.
+__global__ void k_md_extrapolate(double *n, double *n_prev, long long m) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < m) {
+    const double v = n[i];
+    n[i] = fmax(2.0 * v - n_prev[i], 0.1 * v);
+    n_prev[i] = v;
+  }
+}
 __global__ void k_sqrt_field_f(const float *in, float *out, long long n) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < n) { float v = in[i]; out[i] = v > 0 ? sqrtf(v) : 0.0f; }
@@ -927,6 +937,7 @@ void skx_destroy(skx_ctx *c) {
   hipFree(c->w); hipFree(c->wp);
   hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
   hipFree(c->sf_off); hipFree(c->sf_idx);
+  hipFree(c->md_prev);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1639,6 +1650,26 @@ int md_step_impl(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *fo
   int rc = skx_set_ions(c, nions, pos, sp.data(), (int)z.size(), z.data(), r.data());
   if (rc != SKX_OK) return rc;
   for (int i = 0; i < 3 * nions; ++i) pos[i] = c->pos[i];
+  // start density: extrapolated from this and the previous step's minimum
+  // (the ctx keeps the previous one; the first step starts from rho_dev)
+  {
+    const long long M = (long long)c->n1 * c->n2 * c->n3;
+    hipError_t e = hipSuccess;
+    if (c->md_prev && c->md_prev_n == M) {
+      hipLaunchKernelGGL(k_md_extrapolate, dim3(blocks(M, 256)), dim3(256), 0, c->stream,
+                         (double *)rho_dev, c->md_prev, M);
+      e = hipGetLastError();
+    } else {
+      hipFree(c->md_prev);
+      c->md_prev = nullptr;
+      c->md_prev_n = 0;
+      e = hipMalloc((void **)&c->md_prev, sizeof(double) * M);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->md_prev, rho_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) c->md_prev_n = M;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "MD start density");
+  }
   skx_opt_params q = *p;
   q.warm_start = 1;
   rc = skx_optimize_density(c, rho_dev, &q, res);

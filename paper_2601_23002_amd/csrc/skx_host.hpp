@@ -50,6 +50,8 @@ struct skx_ctx {
   double *ion_pos = nullptr, *ion_z = nullptr, *sp_z = nullptr, *sp_rc = nullptr;
   int *ion_sp = nullptr;
   int ion_cap = 0, sp_cap = 0;     // capacities of the device ion arrays
+  double *md_prev = nullptr;       // density before the last MD step
+  long long md_prev_n = 0;
   // half-spectrum indices listed by shell (structure factors), for grid sf_n
   int *sf_off = nullptr, *sf_idx = nullptr;
   int sf_n[3] = {0, 0, 0};

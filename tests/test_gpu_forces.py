@@ -208,14 +208,17 @@ def test_md_conserves_free_energy_plus_kinetic_energy():
     dt = 4.0
     ke = [0.5 * M_PROTON * float(np.sum(vel * vel))]
     etot = [E + ke[0]]
+    iters = []
     for _ in range(30):
         r = c.md_step(rho, pos, vel, F, [M_PROTON], dt, gtol=1e-9, max_iter=2000)
         assert r["status"] == skx.OK
+        iters.append(r["iters"])
         ke.append(0.5 * M_PROTON * float(np.sum(vel * vel)))
         etot.append(r["energy"]["total"] + ke[-1])
     swing = max(ke) - min(ke)
     drift = max(abs(e - etot[0]) for e in etot)
-    _say(f"  kinetic swing {swing:.3e} Ha, conserved-energy drift {drift:.3e} Ha")
+    _say(f"  kinetic swing {swing:.3e} Ha, conserved-energy drift {drift:.3e} Ha, "
+         f"iterations per step {iters}")
     assert swing > 1e-3
     assert drift < 0.02 * swing
 
