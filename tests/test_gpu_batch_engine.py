@@ -213,3 +213,37 @@ def test_thermal_ensemble_batch():
         assert res[i]["energy"]["free_energy"] == r_a["energy"]["free_energy"]
         assert np.array_equal(rhos[i].cpu().numpy(), n_a)
     assert all(r["status"] == skx.OK for r in res)
+
+
+def test_engine_reused_contexts_equal_alone():
+    """Requests of one grid through 2 slots: later requests run on the
+    contexts of finished ones (kept by the engine); every result must still
+    be bitwise the result of solving alone, including a request with a longer
+    history (no reusable context) and one in FP64."""
+    skx, _ = _lib()
+    kw = dict(gtol=1e-9, max_iter=400, fp32_switch_gtol=1e-5)
+    reqs = [(W.uniform_system(4, 1.0, 0.4, 2.0, T, 16, seed=70 + i), skx.MIXED, 5)
+            for i, T in enumerate((0.5, 1.0, 2.0, 4.0))]
+    reqs.append((W.uniform_system(4, 1.0, 0.4, 2.0, 1.5, 16, seed=75), skx.MIXED, 7))
+    reqs.append((W.uniform_system(4, 1.0, 0.4, 2.0, 1.5, 16, seed=76), skx.FP64, 5))
+    _say(f"case: engine context reuse, {len(reqs)} requests on 16^3, 2 slots")
+    eng = skx.Engine(0, hbm_budget=1 << 30, max_slots=2)
+    tickets = {}
+    for s, prec, m in reqs:
+        tickets[eng.submit(s, precision=prec, m=m, **kw)] = (s, prec, m)
+    done = []
+    steps = 0
+    while eng.pending() > 0 and steps < 5000:
+        eng.step()
+        done += eng.poll(want_density=True)
+        steps += 1
+    assert len(done) == len(reqs)
+    for d in done:
+        s, prec, m = tickets[d["ticket"]]
+        n_a, r_a = _alone(skx, s, prec, m=m, **kw)
+        r = d["result"]
+        assert r["status"] == skx.OK, r
+        assert r["iters"] == r_a["iters"] and r["evals"] == r_a["evals"]
+        assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(d["rho"], n_a)
+    eng.close()
