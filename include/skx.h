@@ -63,7 +63,8 @@ enum {
   SKX_E_STATE = -2,        /* call out of order */
   SKX_E_NOMEM = -3,        /* device allocation failed */
   SKX_E_DEVICE = -4,       /* HIP runtime error */
-  SKX_E_NUMERIC = -5       /* non-finite input or numerical blow-up */
+  SKX_E_NUMERIC = -5,      /* non-finite input or numerical blow-up */
+  SKX_CANCELLED = 2        /* engine request cancelled before it finished (no density) */
 };
 
 /* term mask bits of skx_functional.terms */
@@ -412,6 +413,12 @@ int skx_engine_step(skx_engine *eng);
 /* Collect finished results (up to max); the density of each is copied to
  * rho_host[i] when rho_host is non-NULL and rho_host[i] is non-NULL. */
 int skx_engine_poll(skx_engine *eng, skx_result *out, double **rho_host, int max, int *n_out);
+/* Cancel a queued or resident request: it leaves the engine at once (a
+ * resident one frees its slot and budget share) and poll reports it with
+ * status SKX_CANCELLED, no density (npoints 0). Other solves are unaffected: their
+ * results stay those of solving alone. SKX_E_INVALID for an unknown ticket
+ * or one already finished. */
+int skx_engine_cancel(skx_engine *eng, uint64_t ticket);
 /* Queued + resident + finished-but-unpolled requests. */
 int skx_engine_pending(const skx_engine *eng);
 /* Seconds since engine creation (the clock of t_admit / t_done). */

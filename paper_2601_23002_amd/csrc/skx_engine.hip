@@ -476,6 +476,45 @@ int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, 
   return SKX_OK;
 }
 
+int skx_engine_cancel(skx_engine *e, uint64_t ticket) {
+  if (!e) return SKX_E_INVALID;
+  hipSetDevice(e->device);
+  Finished f{};
+  f.res.ticket = ticket;
+  f.res.r.status = SKX_CANCELLED;
+  for (auto it = e->queue.begin(); it != e->queue.end(); ++it) {
+    if (it->ticket != ticket) continue;
+    f.res.t_admit = f.res.t_done = e->now();
+    e->queue.erase(it);
+    e->done.push_back(f);
+    return SKX_OK;
+  }
+  for (auto it = e->resident.begin(); it != e->resident.end(); ++it) {
+    Resident *r = *it;
+    if (r->ticket != ticket) continue;
+    // the steps end with both streams synchronised; set-up work of the
+    // request may still be queued on the engine stream
+    hipStreamSynchronize(e->stream);
+    hipStreamSynchronize(e->stream32);
+    for (Group &g : e->group) {
+      auto m = std::find(g.members.begin(), g.members.end(), r);
+      if (m != g.members.end()) {
+        g.members.erase(m);
+        g.dirty = true;
+      }
+    }
+    e->resident.erase(it);
+    f.res.t_admit = r->t_admit;
+    f.res.t_done = e->now();
+    skx_destroy(r->ctx);
+    e->used -= std::min(e->used, r->bytes);
+    delete r;
+    e->done.push_back(f);
+    return SKX_OK;
+  }
+  return eng_fail(e, SKX_E_INVALID, "no queued or resident request has this ticket");
+}
+
 int skx_engine_pending(const skx_engine *e) {
   if (!e) return 0;
   return (int)(e->queue.size() + e->resident.size() + e->done.size());

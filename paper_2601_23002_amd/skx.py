@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"libskx.so not built ({LIB_PATH}); run paper_2601_23002_amd/build.py")
 _lib = C.CDLL(LIB_PATH)
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, CANCELLED = 0, 1, 2
 E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC = -1, -2, -3, -4, -5
 TERM_TF, TERM_VW, TERM_NL0, TERM_NL1, TERM_HARTREE, TERM_LOCPP, TERM_XC = 1, 2, 4, 8, 16, 32, 64
 TERM_ALL = 127
@@ -146,6 +146,7 @@ _sig("skx_engine_step", C.c_int, [_VP])
 _sig("skx_engine_poll", C.c_int, [_VP, C.POINTER(Result), C.POINTER(C.POINTER(C.c_double)),
                                   C.c_int, C.POINTER(C.c_int)])
 _sig("skx_engine_pending", C.c_int, [_VP])
+_sig("skx_engine_cancel", C.c_int, [_VP, C.c_uint64])
 _sig("skx_engine_destroy", None, [_VP])
 _sig("skx_engine_clock", C.c_double, [_VP])
 _sig("skx_engine_last_error", C.c_char_p, [_VP])
@@ -557,6 +558,12 @@ class Engine:
 
     def pending(self) -> int:
         return _lib.skx_engine_pending(self._h)
+
+    def cancel(self, ticket: int):
+        """Cancel a queued or resident request (reported by poll as CANCELLED)."""
+        rc = _lib.skx_engine_cancel(self._h, ticket)
+        if rc != OK:
+            raise SkxError(rc, _lib.skx_engine_last_error(self._h).decode())
 
     def poll(self, want_density=False, max_results=256):
         """Finished results: dicts with ticket, result, t_admit, t_done (engine clock)

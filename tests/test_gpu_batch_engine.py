@@ -247,3 +247,36 @@ def test_engine_reused_contexts_equal_alone():
         assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
         assert np.array_equal(d["rho"], n_a)
     eng.close()
+
+
+def test_engine_cancel_frees_the_slot_and_leaves_others_alone():
+    skx, _ = _lib()
+    kw = dict(gtol=1e-9, max_iter=400, fp32_switch_gtol=1e-5)
+    reqs = [W.uniform_system(4, 1.0, 0.4, 2.0, T, 16, seed=80 + i)
+            for i, T in enumerate((0.5, 1.0, 2.0, 4.0))]
+    _say("case: engine cancel, 4 requests on 16^3, 2 slots")
+    eng = skx.Engine(0, hbm_budget=1 << 30, max_slots=2)
+    t = [eng.submit(s, precision=skx.MIXED, **kw) for s in reqs]
+    assert eng.step() == 2                  # two resident, two queued
+    eng.cancel(t[0])                        # resident
+    eng.cancel(t[3])                        # queued
+    with pytest.raises(skx.SkxError) as e:
+        eng.cancel(t[0])                    # no longer queued or resident
+    assert e.value.code == skx.E_INVALID
+    done = []
+    steps = 0
+    while eng.pending() > 0 and steps < 5000:
+        eng.step()
+        done += eng.poll(want_density=True)
+        steps += 1
+    by = {d["ticket"]: d for d in done}
+    assert sorted(by) == sorted(t)
+    for k in (0, 3):
+        assert by[t[k]]["result"]["status"] == skx.CANCELLED and "rho" not in by[t[k]]
+    for k in (1, 2):
+        n_a, r_a = _alone(skx, reqs[k], skx.MIXED, **kw)
+        r = by[t[k]]["result"]
+        assert r["status"] == skx.OK
+        assert r["iters"] == r_a["iters"] and r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(by[t[k]]["rho"], n_a)
+    eng.close()
