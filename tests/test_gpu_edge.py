@@ -121,3 +121,22 @@ def test_error_codes():
     with pytest.raises(skx.SkxError) as ex:
         c4.optimize(m=9)
     assert ex.value.code == skx.E_INVALID
+
+
+def test_max_iter_returns_the_best_state_and_non_cubic_cells_are_refused():
+    skx, torch = _lib()
+    _say("case: max_iter reached, non-cubic lattice")
+    s = W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 16, seed=12)
+    for prec in (skx.FP64, skx.MIXED):
+        c = skx.Context(0).setup(s, precision=prec)
+        rho, r = c.optimize(gtol=1e-12, max_iter=3)
+        assert r["status"] == skx.NOT_CONVERGED
+        assert np.isfinite(r["energy"]["free_energy"]) and r["gnorm"] > 1e-12
+        dV = s.L ** 3 / np.prod(s.n)
+        assert abs(float(rho.sum()) * dV - s.nelec) < 1e-9 * s.nelec
+    import ctypes as C
+    from paper_2601_23002_amd.skx import _lib as lib
+    c = skx.Context(0)
+    for lat in ((8.0, 0, 0, 0, 8.0, 0, 0, 0, 9.0), (8.0, 0.5, 0, 0, 8.0, 0, 0, 0, 8.0)):
+        arr = (C.c_double * 9)(*lat)
+        assert lib.skx_set_cell(c._h, arr, 16, 16, 16) == skx.E_INVALID
