@@ -66,14 +66,14 @@ hipError_t init_device(int dev, std::string &err) {
   e = hipMalloc((void **)&r.twbank, sizeof(double) * 2 * off);
   if (e != hipSuccess) { err = "twiddle bank allocation failed"; return e; }
   int *dsz = nullptr, *doff = nullptr;
-  hipMalloc((void **)&dsz, sizeof(int) * sizes.size());
-  hipMalloc((void **)&doff, sizeof(int) * offs.size());
-  hipMemcpy(dsz, sizes.data(), sizeof(int) * sizes.size(), hipMemcpyHostToDevice);
-  hipMemcpy(doff, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice);
-  e = build_twiddles(r.twbank, dsz, doff, (int)sizes.size(), 0);
+  e = hipMalloc((void **)&dsz, sizeof(int) * sizes.size());
+  if (e == hipSuccess) e = hipMalloc((void **)&doff, sizeof(int) * offs.size());
+  if (e == hipSuccess) e = hipMemcpy(dsz, sizes.data(), sizeof(int) * sizes.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(doff, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = build_twiddles(r.twbank, dsz, doff, (int)sizes.size(), 0);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  hipFree(dsz);
-  hipFree(doff);
+  (void)hipFree(dsz);
+  (void)hipFree(doff);
   if (e != hipSuccess) { err = "twiddle kernel failed"; return e; }
   e = hipMalloc((void **)&r.fdcoef, sizeof(double) * 4 * (FD_N + 1));
   if (e != hipSuccess) { err = "FD table allocation failed"; return e; }
@@ -246,7 +246,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   if (I.mem && I.prec == prec && I.m_alloc >= m && I.h.n1 == n1 && I.h.n2 == n2 && I.h.n3 == n3)
     return SKX_OK;
   free_instance(I);
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   const ArenaLayout A = arena_layout(n1, n2, n3, prec, m);
   const size_t off = A.total;
   const size_t o_phi = A.o_phi, o_phit = A.o_phit, o_grad = A.o_grad, o_r = A.o_r, o_rt = A.o_rt;
@@ -426,8 +426,8 @@ int check_grid(skx_ctx *c, int prec) {
 int ensure_tables(skx_ctx *c) {
   if (c->tables_ok) return SKX_OK;
   const int smax = (c->n1 / 2) * (c->n1 / 2) + (c->n2 / 2) * (c->n2 / 2) + (c->n3 / 2) * (c->n3 / 2);
-  if (c->w) { hipFree(c->w); c->w = nullptr; }
-  if (c->wp) { hipFree(c->wp); c->wp = nullptr; }
+  if (c->w) { (void)hipFree(c->w); c->w = nullptr; }
+  if (c->wp) { (void)hipFree(c->wp); c->wp = nullptr; }
   hipError_t e = hipMalloc((void **)&c->w, sizeof(double) * (smax + 1));
   if (e == hipSuccess) e = hipMalloc((void **)&c->wp, sizeof(double) * (smax + 1));
   if (e != hipSuccess) return hip_fail(c, e, "kernel table allocation");
@@ -455,7 +455,7 @@ int ensure_vloc(skx_ctx *c, Instance &I) {
   if (e != hipSuccess) return hip_fail(c, e, "phase table allocation");
   e = build_vloc(I.h.vloc, I.prec, c->n1, c->n2, c->n3, I.h.pitch, c->L, nions, c->ion_pos,
                  c->ion_sp, c->nspecies, c->sp_z, c->sp_rc, scr, c->stream);
-  hipFreeAsync(scr, c->stream);
+  (void)hipFreeAsync(scr, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "structure factor kernel");
   I.vloc_ok = true;
   return SKX_OK;
@@ -473,23 +473,23 @@ double time_eval(skx_ctx *c, Instance &I, int reps) {
   std::vector<SolveDev> hs(1, I.h);
   if (build_batch(c, hs, I.prec, I.dptr, I.first, bl, s)) return -1.0;
   hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
   double best = -1.0;
   hipError_t e = hipSuccess;
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {
     e = hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     if (e == hipSuccess) e = launch_eval(bl, s, 7);
-    hipEventRecord(b, s);
-    hipEventSynchronize(b);
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
     float t = 0.f;
-    hipEventElapsedTime(&t, a, b);
+    (void)hipEventElapsedTime(&t, a, b);
     if (r > 0 && (best < 0 || t < best)) best = t;
   }
   hipEventDestroy(a);
-  hipEventDestroy(b);
-  hipStreamSynchronize(s);
+  (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(s);
   return e == hipSuccess ? best : -1.0;
 }
 
@@ -705,7 +705,7 @@ hipEvent_t prof_event() {
     return e;
   }
   hipEvent_t e;
-  hipEventCreate(&e);
+  (void)hipEventCreate(&e);
   return e;
 }
 
@@ -797,7 +797,7 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
     ph = nullptr;
     ph_cap = 0;
     e = hipHostMalloc((void **)&ph, sizeof(int) * n, hipHostMallocDefault);
-    if (e != hipSuccess) { hipFreeAsync(dph, s); return hip_fail(c, e, "pinned phase buffer"); }
+    if (e != hipSuccess) { (void)hipFreeAsync(dph, s); return hip_fail(c, e, "pinned phase buffer"); }
     ph_cap = n;
   }
   hipGraph_t graph = nullptr;
@@ -857,7 +857,7 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
     }
   }
   drop_graph();
-  hipFreeAsync(dph, s);
+  (void)hipFreeAsync(dph, s);
   return rc;
 }
 
@@ -931,13 +931,13 @@ int skx_create(skx_ctx **out, int device, void *hip_stream) {
 
 void skx_destroy(skx_ctx *c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
   for (auto &I : c->inst) free_instance(I);
-  hipFree(c->w); hipFree(c->wp);
-  hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
-  hipFree(c->sf_off); hipFree(c->sf_idx);
-  hipFree(c->md_prev);
+  (void)hipFree(c->w); (void)hipFree(c->wp);
+  (void)hipFree(c->ion_pos); (void)hipFree(c->ion_z); (void)hipFree(c->sp_z); (void)hipFree(c->sp_rc); (void)hipFree(c->ion_sp);
+  (void)hipFree(c->sf_off); (void)hipFree(c->sf_idx);
+  (void)hipFree(c->md_prev);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -983,7 +983,7 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
   }
   for (int s = 0; s < nspecies; ++s)
     if (!(zval[s] > 0) || !(rc[s] > 0)) return fail(c, SKX_E_INVALID, "zval and rc must be > 0");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   c->pos.assign(pos, pos + 3 * nions);
   // wrap positions into the cell
   for (auto &x : c->pos) x -= c->L * std::floor(x / c->L);
@@ -999,7 +999,7 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
   // synchronises the whole device; MD steps and engine reuse call this often)
   hipError_t e = hipSuccess;
   if (nions > c->ion_cap || nspecies > c->sp_cap || !c->ion_pos) {
-    hipFree(c->ion_pos); hipFree(c->ion_z); hipFree(c->sp_z); hipFree(c->sp_rc); hipFree(c->ion_sp);
+    (void)hipFree(c->ion_pos); (void)hipFree(c->ion_z); (void)hipFree(c->sp_z); (void)hipFree(c->sp_rc); (void)hipFree(c->ion_sp);
     c->ion_pos = c->ion_z = c->sp_z = c->sp_rc = nullptr;
     c->ion_sp = nullptr;
     c->ion_cap = c->sp_cap = 0;
@@ -1013,11 +1013,12 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
     c->sp_cap = nspecies;
   }
   hipStream_t s = c->stream;
-  hipMemcpyAsync(c->ion_pos, c->pos.data(), sizeof(double) * 3 * nions, hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(c->ion_z, zi.data(), sizeof(double) * nions, hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(c->sp_z, zval, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(c->sp_rc, rc, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(c->ion_sp, species, sizeof(int) * nions, hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(c->ion_pos, c->pos.data(), sizeof(double) * 3 * nions, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ion_z, zi.data(), sizeof(double) * nions, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->sp_z, zval, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->sp_rc, rc, sizeof(double) * nspecies, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ion_sp, species, sizeof(int) * nions, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "ion upload");
   // Ewald energy on the device
   {
     const double L = c->L;
@@ -1036,8 +1037,8 @@ int skx_set_ions(skx_ctx *c, int nions, const double *pos, const int *species, i
     double parts[2] = {0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(parts, out, sizeof(parts), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFreeAsync(scr, s);
-    hipFreeAsync(out, s);
+    (void)hipFreeAsync(scr, s);
+    (void)hipFreeAsync(out, s);
     if (e != hipSuccess) return hip_fail(c, e, "Ewald kernels");
     double z2 = 0;
     for (double z : zi) z2 += z * z;
@@ -1076,7 +1077,7 @@ int skx_evaluate_energy_potential(skx_ctx *c, const void *in_dev, int in_kind, v
   c->err.clear();
   if (!in_dev || !e) return fail(c, SKX_E_INVALID, "input field and energy struct are required");
   if (in_kind != SKX_RHO && in_kind != SKX_SQRT_RHO) return fail(c, SKX_E_INVALID, "bad in_kind");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   const int prec = c->has_fn && c->fn.precision == SKX_FP32 ? 1 : 0;
   int rc = prepare(c, prec, 1);
   if (rc) return rc;
@@ -1128,7 +1129,7 @@ int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx
   if (!rho_dev || !p || !res) return fail(c, SKX_E_INVALID, "rho_dev, params and result are required");
   if (p->lbfgs_m < 1 || p->lbfgs_m > MMAX) return fail(c, SKX_E_INVALID, "lbfgs_m must be in 1..8");
   if (!(p->gtol > 0) || p->max_iter < 1) return fail(c, SKX_E_INVALID, "gtol > 0 and max_iter >= 1 required");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   std::memset(res, 0, sizeof(*res));
   const int mode = c->has_fn ? c->fn.precision : SKX_FP64;
   int rc;
@@ -1189,7 +1190,7 @@ int skx_get_kernel_tables(skx_ctx *c, double *w_host, double *wp_host, int len) 
   if (!c) return SKX_E_INVALID;
   c->err.clear();
   if (!c->has_cell || !c->has_ions || !c->has_fn) return fail(c, SKX_E_STATE, "incomplete setup");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   int rc = ensure_tables(c);
   if (rc) return rc;
   if (len > c->smax + 1 || len < 0) return fail(c, SKX_E_INVALID, "len exceeds the shell count");
@@ -1211,7 +1212,7 @@ int skx_get_vloc(skx_ctx *c, double *host) {
   if (!c) return SKX_E_INVALID;
   c->err.clear();
   if (!host) return fail(c, SKX_E_INVALID, "host buffer is NULL");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   int rc = prepare(c, 0, 1);
   if (rc) return rc;
   Instance &I = c->inst[0];
@@ -1230,15 +1231,15 @@ int skx_fd_eval(int device, const double *u_host, double *eta_host, double *psi_
     if (!(u_host[i] > 0) || !std::isfinite(u_host[i])) return SKX_E_INVALID;
   std::string err;
   if (init_device(device, err) != hipSuccess) return SKX_E_DEVICE;
-  hipSetDevice(device);
+  (void)hipSetDevice(device);
   if (n == 0) return SKX_OK;
   double *d = nullptr;
   if (hipMalloc((void **)&d, sizeof(double) * 3 * n) != hipSuccess) return SKX_E_NOMEM;
-  hipMemcpy(d, u_host, sizeof(double) * n, hipMemcpyHostToDevice);
-  hipError_t e = debug_fd_eval(d, d + n, d + 2 * n, n, g_res[device].fd, 0);
+  hipError_t e = hipMemcpy(d, u_host, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = debug_fd_eval(d, d + n, d + 2 * n, n, g_res[device].fd, 0);
   if (e == hipSuccess) e = hipMemcpy(eta_host, d + n, sizeof(double) * n, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(psi_host, d + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
-  hipFree(d);
+  (void)hipFree(d);
   return e == hipSuccess ? SKX_OK : SKX_E_DEVICE;
 }
 
@@ -1254,7 +1255,7 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
   c->err.clear();
   if (!c->has_cell) return fail(c, SKX_E_STATE, "set_cell first");
   if (!in_host || !out_host) return fail(c, SKX_E_INVALID, "host buffers are required");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   int rc = check_grid(c, 0);
   if (rc) return rc;
   rc = ensure_instance(c, 0, 1);
@@ -1347,7 +1348,7 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
   if (f_loc && !in_dev) return fail(c, SKX_E_INVALID, "the local force needs the density");
   if (f_loc && in_kind != SKX_RHO && in_kind != SKX_SQRT_RHO) return fail(c, SKX_E_INVALID, "bad in_kind");
   if (!c->has_cell || !c->has_ions) return fail(c, SKX_E_STATE, "set_cell and set_ions must precede this call");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   hipStream_t s = c->stream;
   const int nions = (int)c->species.size();
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
@@ -1374,7 +1375,7 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
     const double2 *spec = nullptr;
     int pitch = 0;
     rc = density_spectrum(c, in_dev, in_kind, &spec, &pitch);
-    if (rc != SKX_OK) { hipStreamSynchronize(s); hipFreeAsync(scr, s); return rc; }
+    if (rc != SKX_OK) { (void)hipStreamSynchronize(s); (void)hipFreeAsync(scr, s); return rc; }
     // ions sorted by species: the form factor is computed once per run
     std::vector<int> ord(nions);
     for (int i = 0; i < nions; ++i) ord[i] = i;
@@ -1400,7 +1401,7 @@ int skx_ion_forces(skx_ctx *c, const void *in_dev, int in_kind, double *f_loc, d
     e = hipMemcpyAsync(f_ii, out + 3 * (size_t)nions, sizeof(double) * 3 * nions,
                        hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFreeAsync(scr, s);
+  (void)hipFreeAsync(scr, s);
   if (rc != SKX_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "force kernels");
   prof_fold();
@@ -1417,7 +1418,7 @@ int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s
   const int nshell = skx_num_shells(c);
   if (len < nshell) return fail(c, SKX_E_INVALID, "len must be at least skx_num_shells(ctx)");
   if (!s_ei && !s_ee && !s_ii && !count) return fail(c, SKX_E_INVALID, "no output requested");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   hipStream_t s = c->stream;
   const int nions = (int)c->species.size();
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3, nh = n3 / 2 + 1;
@@ -1439,7 +1440,7 @@ int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s
       std::vector<int> fill(off.begin(), off.end() - 1);
       for (long long it = 0; it < items; ++it) idx[fill[shell(it)]++] = (int)it;
     }
-    hipFree(c->sf_off); hipFree(c->sf_idx);
+    hipFree(c->sf_off); (void)hipFree(c->sf_idx);
     c->sf_off = c->sf_idx = nullptr;
     c->sf_n[0] = c->sf_n[1] = c->sf_n[2] = 0;
     e = hipMalloc((void **)&c->sf_off, sizeof(int) * (nshell + 1));
@@ -1477,7 +1478,7 @@ int skx_structure_factors(skx_ctx *c, const void *in_dev, int in_kind, double *s
     e = hipMemcpyAsync(host.data(), out, sizeof(double) * 4 * nshell, hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipStreamSynchronize(s);
   if (e == hipSuccess) e = e2;
-  hipFreeAsync(scr, s);
+  (void)hipFreeAsync(scr, s);
   if (rc != SKX_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "structure factor kernels");
   prof_fold();
@@ -1495,7 +1496,7 @@ int skx_density_deviation(skx_ctx *c, const void *a_dev, const void *b_dev, doub
   c->err.clear();
   if (!a_dev || !b_dev || !out) return fail(c, SKX_E_INVALID, "null argument");
   if (!c->has_cell) return fail(c, SKX_E_STATE, "set_cell first");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   hipStream_t s = c->stream;
   const long long M = (long long)c->n1 * c->n2 * c->n3;
   const int nb = deviation_blocks(M);
@@ -1507,7 +1508,7 @@ int skx_density_deviation(skx_ctx *c, const void *a_dev, const void *b_dev, doub
   if (e == hipSuccess) e = hipMemcpyAsync(out, scr + nb, sizeof(double), hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipStreamSynchronize(s);
   if (e == hipSuccess) e = e2;
-  hipFreeAsync(scr, s);
+  (void)hipFreeAsync(scr, s);
   if (e != hipSuccess) return hip_fail(c, e, "deviation kernels");
   return SKX_OK;
 }
@@ -1660,7 +1661,7 @@ int md_step_impl(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *fo
                          (double *)rho_dev, c->md_prev, M);
       e = hipGetLastError();
     } else {
-      hipFree(c->md_prev);
+      (void)hipFree(c->md_prev);
       c->md_prev = nullptr;
       c->md_prev_n = 0;
       e = hipMalloc((void **)&c->md_prev, sizeof(double) * M);
@@ -1701,7 +1702,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
   if (!(eps > 0.0 && eps < 0.1)) return fail(c, SKX_E_INVALID, "eps must be in (0, 0.1)");
   if (!c->has_cell || !c->has_ions || !c->has_fn)
     return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   hipStream_t s = c->stream;
   const double L0 = c->L, V0 = L0 * L0 * L0;
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
@@ -1734,7 +1735,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
     if (rc >= 0) F[k] = res.e.total;
   }
   hipStreamSynchronize(s);
-  hipFree(work);
+  (void)hipFree(work);
   // restore the configuration (the error text of a failed solve is kept)
   const std::string err = c->err;
   const double lat0[9] = {L0, 0, 0, 0, L0, 0, 0, 0, L0};
@@ -1889,10 +1890,10 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
     if (e != hipSuccess) rc = hip_fail(c0, e, "batch output");
   }
   hipFreeAsync(ddev, s);
-  hipFreeAsync(dfirst, s);
-  hipFreeAsync(dstage, s);
-  hipFreeAsync(dsptr, s);
-  hipStreamSynchronize(s);
+  (void)hipFreeAsync(dfirst, s);
+  (void)hipFreeAsync(dstage, s);
+  (void)hipFreeAsync(dsptr, s);
+  (void)hipStreamSynchronize(s);
   if (rc) return rc;
   int worst = SKX_OK;
   for (int i = 0; i < nctx; ++i)
@@ -1979,7 +1980,7 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
   if (!ctxs || nctx < 1 || reps < 1 || !ms_out) return SKX_E_INVALID;
   skx_ctx *c0 = ctxs[0];
   c0->err.clear();
-  hipSetDevice(c0->device);
+  (void)hipSetDevice(c0->device);
   const int prec = c0->fn.precision == SKX_FP32 ? 1 : 0;
   for (int i = 0; i < nctx; ++i) {
     if (!ctxs[i] || ctxs[i]->device != c0->device) return fail(c0, SKX_E_INVALID, "bad context");
@@ -2000,7 +2001,7 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
                          (float *)I.h.phi2[0], (float)v, I.h.M);
     OptState st{};
     st.phase = PH_EVAL_ONLY;
-    hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(I.st, &st, sizeof(OptState), hipMemcpyHostToDevice, s);
     hs.push_back(I.h);
   }
   SolveDev *ddev = nullptr;
@@ -2015,18 +2016,18 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
     for (auto &x : ev) hipEventCreate(&x);
     double tot[3] = {0, 0, 0};
     for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
-      hipEventRecord(ev[0], s);
+      (void)hipEventRecord(ev[0], s);
       e = launch_eval(bl, s, 1);
-      hipEventRecord(ev[1], s);
+      (void)hipEventRecord(ev[1], s);
       if (e == hipSuccess) e = launch_eval(bl, s, 2);
-      hipEventRecord(ev[2], s);
+      (void)hipEventRecord(ev[2], s);
       if (e == hipSuccess) e = launch_eval(bl, s, 4);
-      hipEventRecord(ev[3], s);
-      hipEventSynchronize(ev[3]);
+      (void)hipEventRecord(ev[3], s);
+      (void)hipEventSynchronize(ev[3]);
       if (r == 0) continue;            // first repetition warms caches
       for (int q = 0; q < 3; ++q) {
         float t = 0.f;
-        hipEventElapsedTime(&t, ev[q], ev[q + 1]);
+        (void)hipEventElapsedTime(&t, ev[q], ev[q + 1]);
         tot[q] += t;
       }
     }
@@ -2035,7 +2036,7 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
     if (e != hipSuccess) rc = hip_fail(c0, e, "bench passes");
   }
   hipFreeAsync(ddev, s);
-  hipFreeAsync(dfirst, s);
-  hipStreamSynchronize(s);
+  (void)hipFreeAsync(dfirst, s);
+  (void)hipStreamSynchronize(s);
   return rc;
 }

@@ -223,7 +223,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   if (n == 0) return SKX_OK;
   // set-up work of newly admitted or promoted members is on e->stream
   hipStreamSynchronize(e->stream);
-  hipStreamSynchronize(group_stream(e, g));
+  (void)hipStreamSynchronize(group_stream(e, g));
   if (n > g.cap) {
     if (g.ddev) hipFree(g.ddev);
     if (g.dfirst) hipFree(g.dfirst);
@@ -274,7 +274,7 @@ void finish(skx_engine *e, Resident *r, const OptState &o) {
     square_out(I, o.par, f.rho_dev, e->stream);
   else
     f.rho_dev = nullptr;
-  hipStreamSynchronize(e->stream);
+  (void)hipStreamSynchronize(e->stream);
   f.res.t_done = e->now();
   if ((int)e->pool.size() < e->max_slots) {
     const int m = std::min(std::max(r->opt.lbfgs_m, 1), MMAX);
@@ -306,7 +306,7 @@ int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int
     return SKX_E_DEVICE;
   }
   if (hipStreamCreateWithFlags(&e->stream32, hipStreamNonBlocking) != hipSuccess) {
-    hipStreamDestroy(e->stream);
+    (void)hipStreamDestroy(e->stream);
     delete e;
     return SKX_E_DEVICE;
   }
@@ -351,7 +351,7 @@ int skx_engine_submit(skx_engine *e, const skx_request *req, uint64_t *ticket) {
 
 int skx_engine_step(skx_engine *e) {
   if (!e) return SKX_E_INVALID;
-  hipSetDevice(e->device);
+  (void)hipSetDevice(e->device);
   // admission in arrival order; a pooled context of the same grid, mode
   // and history length is reused, others are freed when the budget needs
   // their memory
@@ -430,8 +430,8 @@ int skx_engine_step(skx_engine *e) {
       g.dirty = true;
       OptState o;
       Instance &I = r->ctx->inst[r->prec];
-      hipMemcpyAsync(&o, I.st, sizeof(OptState), hipMemcpyDeviceToHost, e->stream);
-      hipStreamSynchronize(e->stream);
+      (void)hipMemcpyAsync(&o, I.st, sizeof(OptState), hipMemcpyDeviceToHost, e->stream);
+      (void)hipStreamSynchronize(e->stream);
       const bool promote = r->mode == SKX_MIXED && r->prec == 1 &&
                            !(o.phase == PH_FAILED && o.status < 0);
       if (promote) {
@@ -459,7 +459,7 @@ int skx_engine_step(skx_engine *e) {
 
 int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, int *n_out) {
   if (!e || !n_out || (max > 0 && !out)) return SKX_E_INVALID;
-  hipSetDevice(e->device);
+  (void)hipSetDevice(e->device);
   int k = 0;
   while (k < max && !e->done.empty()) {
     Finished f = e->done.front();
@@ -468,7 +468,7 @@ int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, 
     if (f.rho_dev) {
       if (rho_host && rho_host[k])
         hipMemcpy(rho_host[k], f.rho_dev, sizeof(double) * f.res.npoints, hipMemcpyDeviceToHost);
-      hipFreeAsync(f.rho_dev, e->stream);
+      (void)hipFreeAsync(f.rho_dev, e->stream);
     }
     ++k;
   }
@@ -478,7 +478,7 @@ int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, 
 
 int skx_engine_cancel(skx_engine *e, uint64_t ticket) {
   if (!e) return SKX_E_INVALID;
-  hipSetDevice(e->device);
+  (void)hipSetDevice(e->device);
   Finished f{};
   f.res.ticket = ticket;
   f.res.r.status = SKX_CANCELLED;
@@ -495,7 +495,7 @@ int skx_engine_cancel(skx_engine *e, uint64_t ticket) {
     // the steps end with both streams synchronised; set-up work of the
     // request may still be queued on the engine stream
     hipStreamSynchronize(e->stream);
-    hipStreamSynchronize(e->stream32);
+    (void)hipStreamSynchronize(e->stream32);
     for (Group &g : e->group) {
       auto m = std::find(g.members.begin(), g.members.end(), r);
       if (m != g.members.end()) {
@@ -522,9 +522,9 @@ int skx_engine_pending(const skx_engine *e) {
 
 void skx_engine_destroy(skx_engine *e) {
   if (!e) return;
-  hipSetDevice(e->device);
-  hipStreamSynchronize(e->stream32);
-  hipStreamSynchronize(e->stream);
+  (void)hipSetDevice(e->device);
+  (void)hipStreamSynchronize(e->stream32);
+  (void)hipStreamSynchronize(e->stream);
   for (Resident *r : e->resident) {
     skx_destroy(r->ctx);
     delete r;
@@ -533,7 +533,7 @@ void skx_engine_destroy(skx_engine *e) {
     if (f.rho_dev) hipFreeAsync(f.rho_dev, e->stream);
   for (skx_engine::Pooled &p : e->pool) skx_destroy(p.ctx);
   e->pool.clear();
-  hipStreamSynchronize(e->stream);
+  (void)hipStreamSynchronize(e->stream);
   for (Group &g : e->group) {
     g.drop_graph();
     if (g.ddev) hipFree(g.ddev);
@@ -541,7 +541,7 @@ void skx_engine_destroy(skx_engine *e) {
     if (g.dphase) hipFree(g.dphase);
   }
   hipStreamDestroy(e->stream32);
-  hipStreamDestroy(e->stream);
+  (void)hipStreamDestroy(e->stream);
   delete e;
 }
 
