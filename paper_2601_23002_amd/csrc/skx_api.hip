@@ -793,7 +793,7 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
   static thread_local int *ph = nullptr;
   static thread_local int ph_cap = 0;
   if (ph_cap < n) {
-    if (ph) hipHostFree(ph);
+    if (ph) (void)hipHostFree(ph);
     ph = nullptr;
     ph_cap = 0;
     e = hipHostMalloc((void **)&ph, sizeof(int) * n, hipHostMallocDefault);
@@ -803,8 +803,8 @@ int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *d
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto drop_graph = [&]() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
   };
@@ -1734,7 +1734,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
     if (rc == SKX_OK) rc = skx_optimize_density(c, work, &q, &res);
     if (rc >= 0) F[k] = res.e.total;
   }
-  hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
   (void)hipFree(work);
   // restore the configuration (the error text of a failed solve is kept)
   const std::string err = c->err;
@@ -1787,7 +1787,7 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
       int rc = prepare(ctxs[i], pr, p->lbfgs_m);
       if (rc) { c0->err = "solve " + std::to_string(i) + ": " + ctxs[i]->err; return rc; }
     }
-    hipStreamSynchronize(ctxs[i]->stream);
+    (void)hipStreamSynchronize(ctxs[i]->stream);
   }
   hipStream_t s = c0->stream;
   SolveDev *ddev = nullptr;
@@ -1986,7 +1986,7 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
     if (!ctxs[i] || ctxs[i]->device != c0->device) return fail(c0, SKX_E_INVALID, "bad context");
     int rc = prepare(ctxs[i], prec, 1);
     if (rc) { c0->err = ctxs[i]->err; return rc; }
-    hipStreamSynchronize(ctxs[i]->stream);
+    (void)hipStreamSynchronize(ctxs[i]->stream);
   }
   hipStream_t s = c0->stream;
   std::vector<SolveDev> hs;

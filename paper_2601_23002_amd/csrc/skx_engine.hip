@@ -222,7 +222,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   g.drop_graph();
   if (n == 0) return SKX_OK;
   // set-up work of newly admitted or promoted members is on e->stream
-  hipStreamSynchronize(e->stream);
+  (void)hipStreamSynchronize(e->stream);
   (void)hipStreamSynchronize(group_stream(e, g));
   if (n > g.cap) {
     if (g.ddev) hipFree(g.ddev);
@@ -243,7 +243,7 @@ int rebuild(skx_engine *e, Group &g, int prec) {
   if (rc) return eng_fail(e, rc, g.members[0]->ctx->err);
   // build_batch reads hs from pageable memory: finish before hs goes away
   // (and before the group's own stream uses the descriptors)
-  hipStreamSynchronize(e->stream);
+  (void)hipStreamSynchronize(e->stream);
   capture_group(e, g);
   return SKX_OK;
 }
@@ -494,7 +494,7 @@ int skx_engine_cancel(skx_engine *e, uint64_t ticket) {
     if (r->ticket != ticket) continue;
     // the steps end with both streams synchronised; set-up work of the
     // request may still be queued on the engine stream
-    hipStreamSynchronize(e->stream);
+    (void)hipStreamSynchronize(e->stream);
     (void)hipStreamSynchronize(e->stream32);
     for (Group &g : e->group) {
       auto m = std::find(g.members.begin(), g.members.end(), r);
