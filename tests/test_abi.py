@@ -4,6 +4,8 @@ import os
 import re
 import ctypes
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -46,3 +48,29 @@ def test_default_radix_orders_factor_the_length():
         assert prod == n, (n, r)
     assert skx.radix_order(64) == [8, 8]
     assert skx.radix_order(96) == [8, 4, 3]
+
+
+def test_binding_refuses_to_load_without_the_library(tmp_path):
+    """No CPU fallback: a copy of the binding with no libskx.so beside it
+    fails at import, naming the missing library."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "skx_nolib"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2601_23002_amd", "skx.py"), pkg / "skx.py")
+    r = subprocess.run([sys.executable, "-c", "import skx_nolib.skx"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libskx.so not built" in r.stderr
+
+
+def test_contexts_need_a_gpu():
+    """Without a visible GPU the binding raises instead of computing on the
+    host."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2601_23002_amd import skx
+    with pytest.raises(RuntimeError, match="needs a GPU"):
+        skx.Context(0)
