@@ -27,7 +27,9 @@
  *   V_loc erf-smeared Coulomb -Z erf(r/rc)/r per ion through the structure
  *        factor, with its G = 0 (non-Coulomb) term; the real part of the
  *        plane-wave sum on even grids
- *   E_xc Perdew-Zunger 1981, unpolarised, temperature independent
+ *   E_xc Perdew-Zunger 1981, unpolarised, temperature independent; the
+ *        published fit (SKX_XC_PZ81) or the same branches joined C1 over
+ *        0.99 <= rs <= 1.01 (SKX_XC_PZ81_C1, see the enum)
  *
  * Units: Hartree atomic units. Energies are totals over the cell.
  *
@@ -73,7 +75,18 @@ enum {
   SKX_TERM_HARTREE = 16, SKX_TERM_LOCPP = 32, SKX_TERM_XC = 64, SKX_TERM_ALL = 127
 };
 
-enum { SKX_XC_NONE = 0, SKX_XC_PZ81 = 1 };
+/* Exchange-correlation (Methods: Perdew-Zunger LDA, adiabatic approximation).
+ *   SKX_XC_PZ81     the published 1981 fit: correlation from the dilute
+ *                   branch gamma / (1 + beta1 sqrt(rs) + beta2 rs) for rs >= 1,
+ *                   the dense branch A ln rs + B + C rs ln rs + D rs below.
+ *                   With the printed constants the branches jump by ~3e-5 Ha
+ *                   in e_c and v_c at rs = 1, which floors a minimisation's
+ *                   ||r|| (about 1e-5..1e-4) when the density straddles rs = 1.
+ *   SKX_XC_PZ81_C1  the same branches joined over 0.99 <= rs <= 1.01 with the
+ *                   weight w = 3t^2 - 2t^3, t = (rs - 0.99) / 0.02,
+ *                   e_c = (1 - w) e_dense + w e_dilute, v_c the exact potential
+ *                   of that e_c; equal to SKX_XC_PZ81 outside the window. */
+enum { SKX_XC_NONE = 0, SKX_XC_PZ81 = 1, SKX_XC_PZ81_C1 = 2 };
 enum { SKX_FP64 = 0, SKX_FP32 = 1, SKX_MIXED = 2 };
 enum { SKX_RHO = 0, SKX_SQRT_RHO = 1 };
 
@@ -86,17 +99,30 @@ void skx_destroy(skx_ctx *ctx);
 /* Text of the last error on ctx (valid until the next call on ctx). */
 const char *skx_last_error(const skx_ctx *ctx);
 
-/* Periodic cell and grid. lattice: 9 doubles, rows a1, a2, a3 in bohr; this
- * version accepts cubic cells only (a1 = L x, a2 = L y, a3 = L z). n1, n2, n3:
- * even and 5-smooth, 8..512; the fused FP64 kernels need n <= 128 (FP32:
- * n <= 192). Invalidates ions and tables. Errors: SKX_E_INVALID. */
+/* Periodic cell and grid of the problem (Methods, "Numerical calculations
+ * for OFDFT and KSDFT": the OFDFT fields live on a uniform grid of stated
+ * spacing in the periodic cell; the cell volume fixes the mean density
+ * n0 = N_e / V and so r_s, Results). lattice: 9
+ * doubles, rows a1, a2, a3 in bohr; this version accepts cubic cells only
+ * (a1 = L x, a2 = L y, a3 = L z). n1, n2, n3: even and 5-smooth, 8..512.
+ * The x axis is transformed as whole pencils in LDS: n1 <= 300 for FP64
+ * work and n1 <= 310 for FP32 (the check is made when a solve is prepared,
+ * SKX_E_INVALID); y-z planes beyond LDS run in chunks, so n2 and n3 may
+ * take any allowed size. Invalidates ions and tables. Errors: SKX_E_INVALID. */
 int skx_set_cell(skx_ctx *ctx, const double lattice[9], int n1, int n2, int n3);
 
-/* Ions: nions host positions [nions][3] (cartesian bohr, any image), a
- * species index per ion, and per species the valence zval and erf width rc
- * (bohr, > 0). Builds V_loc(G) through the ionic structure factor on the
- * device and the Ewald ion-ion energy. Errors: SKX_E_INVALID, SKX_E_STATE
- * (no cell), SKX_E_NOMEM. */
+/* Ions and their local pseudopotentials (Methods, "Numerical calculations
+ * for OFDFT and KSDFT": the ion-electron interaction is a local
+ * pseudopotential per species; its parameters are not printed, so here the
+ * erf-smeared Coulomb -Z erf(r/rc)/r stands in, whose Fourier transform
+ * -4 pi Z exp(-G^2 rc^2/4)/G^2 enters through the ionic structure factor).
+ * nions host positions [nions][3] (cartesian bohr, any image, wrapped into
+ * the cell), a species index per ion, and per species the valence zval and
+ * erf width rc (bohr, > 0); N_e = sum of zval over ions. Builds V_loc(G) on
+ * the device and the Ewald ion-ion energy. The arrays are copied; the
+ * caller keeps ownership. Errors: SKX_E_INVALID (no ion, bad species
+ * index, non-finite position, zval or rc <= 0), SKX_E_STATE (no cell),
+ * SKX_E_NOMEM / SKX_E_DEVICE. */
 int skx_set_ions(skx_ctx *ctx, int nions, const double *pos, const int *species, int nspecies,
                  const double *zval, const double *rc);
 
@@ -105,7 +131,7 @@ typedef struct {
   double beta;       /* weight of F1 (Eq. (2)); 1 reproduces XWMF */
   double alpha;      /* exponent a of f = n^a in F0/F1, in (0.5, 1.5]; default 5/6 */
   unsigned terms;    /* SKX_TERM_* mask */
-  int xc;            /* SKX_XC_PZ81 or SKX_XC_NONE (clears SKX_TERM_XC) */
+  int xc;            /* SKX_XC_PZ81, SKX_XC_PZ81_C1 or SKX_XC_NONE (clears SKX_TERM_XC) */
   int precision;     /* SKX_FP64, SKX_FP32 or SKX_MIXED */
 } skx_functional;
 
@@ -122,7 +148,9 @@ typedef struct {
   double nelec;                     /* int n */
 } skx_energy;
 
-/* One evaluation of every energy term and of dE/dphi.
+/* One evaluation of the free energy F[n;T] = F_TF + F_vW + F0 + beta F1
+ * + E_H + E_loc + E_xc (Eq. (1), Eq. (2) and the Methods' XC and
+ * pseudopotential) and of its potential, as dE/dphi with phi = sqrt(n).
  * in_dev: device field, n (SKX_RHO, phi = sqrt(n) is formed internally) or
  *   phi = sqrt(n) (SKX_SQRT_RHO). FP64 for SKX_FP64/SKX_MIXED, FP32 for SKX_FP32.
  * out_dev: NULL, or a device field of the same type receiving dE/dphi

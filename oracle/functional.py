@@ -63,6 +63,10 @@ class Problem:
         self.beta = float(sys.beta)
         self.a = float(sys.alpha)
         self.terms = int(sys.terms)
+        # XC_PZ81 (published fit) unless the system names the C1-joined variant
+        self.xc = int(getattr(sys, "xc", xc.XC_PZ81))
+        if self.xc == xc.XC_NONE:
+            self.terms &= ~TERM_XC
         _, self.G2 = ions.gvectors(self.L, self.n)
         self.shell = ions.shells(self.n)
         nl = self.terms & (TERM_NL0 | TERM_NL1)
@@ -99,7 +103,7 @@ class Problem:
             e["f_tf"] = dV * np.sum(ftf)
             vmult += np.where(n > 0, vtf, 0.0)
         if self.terms & TERM_XC:
-            eps, vxc = xc.pz81(n)
+            eps, vxc = xc.pz81(n, self.xc)
             e["e_xc"] = dV * np.sum(n * eps)
             vmult += vxc
         nt = fft3(n)

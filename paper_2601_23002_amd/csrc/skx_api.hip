@@ -309,6 +309,7 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
   h.sqrt_ne = std::sqrt(c->ne);
   h.inv_sqrt_ne = 1.0 / h.sqrt_ne;
   h.terms = c->fn.terms;
+  h.xc = c->fn.xc;
   h.fields = fields_mask(h.terms, h.beta);
   int nf = 0;
   for (int b = 0; b < NFIELD; ++b) h.slot[b] = (h.fields & (1 << b)) ? nf++ : -1;
@@ -426,11 +427,18 @@ int check_grid(skx_ctx *c, int prec) {
 int ensure_tables(skx_ctx *c) {
   if (c->tables_ok) return SKX_OK;
   const int smax = (c->n1 / 2) * (c->n1 / 2) + (c->n2 / 2) * (c->n2 / 2) + (c->n3 / 2) * (c->n3 / 2);
-  if (c->w) { (void)hipFree(c->w); c->w = nullptr; }
-  if (c->wp) { (void)hipFree(c->wp); c->wp = nullptr; }
-  hipError_t e = hipMalloc((void **)&c->w, sizeof(double) * (smax + 1));
-  if (e == hipSuccess) e = hipMalloc((void **)&c->wp, sizeof(double) * (smax + 1));
-  if (e != hipSuccess) return hip_fail(c, e, "kernel table allocation");
+  // the buffers are kept while the shell count does not grow (a free
+  // synchronises the whole device; engine admissions reuse contexts)
+  hipError_t e = hipSuccess;
+  if (!c->w || !c->wp || smax + 1 > c->w_cap) {
+    if (c->w) { (void)hipFree(c->w); c->w = nullptr; }
+    if (c->wp) { (void)hipFree(c->wp); c->wp = nullptr; }
+    c->w_cap = 0;
+    e = hipMalloc((void **)&c->w, sizeof(double) * (smax + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->wp, sizeof(double) * (smax + 1));
+    if (e != hipSuccess) return hip_fail(c, e, "kernel table allocation");
+    c->w_cap = smax + 1;
+  }
   c->smax = smax;
   const double V = c->L * c->L * c->L;
   double gas[3] = {0, 1, 0};
@@ -1061,7 +1069,8 @@ int skx_set_functional(skx_ctx *c, const skx_functional *fn) {
   if (!std::isfinite(fn->beta)) return fail(c, SKX_E_INVALID, "beta must be finite");
   if (fn->precision < SKX_FP64 || fn->precision > SKX_MIXED)
     return fail(c, SKX_E_INVALID, "unknown precision");
-  if (fn->xc != SKX_XC_NONE && fn->xc != SKX_XC_PZ81) return fail(c, SKX_E_INVALID, "unknown xc");
+  if (fn->xc != SKX_XC_NONE && fn->xc != SKX_XC_PZ81 && fn->xc != SKX_XC_PZ81_C1)
+    return fail(c, SKX_E_INVALID, "unknown xc");
   if (fn->terms & ~127u) return fail(c, SKX_E_INVALID, "unknown term bits");
   const bool tables_change = !c->has_fn || fn->T != c->fn.T || fn->alpha != c->fn.alpha;
   c->fn = *fn;
@@ -1162,16 +1171,27 @@ int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx
     OptState o32{};
     rc = run_optimize(c, I32, rho_dev, *p, std::max(sw, p->gtol), p->warm_start ? 1 : 0, o32);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_f2d, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
-                       (const float *)I32.h.phi2[o32.par], (double *)I64.h.phi2[0], I64.h.M);
-    rc = run_optimize(c, I64, rho_dev, *p, p->gtol, 2, out);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
-                       (const double *)I64.h.phi2[out.par], (double *)rho_dev, I64.h.M);
     res->fp32_iters = o32.iters;
     res->fp32_evals = o32.evals;
-    res->iters = o32.iters + out.iters;
-    res->evals = o32.evals + out.evals;
+    if (o32.phase == PH_FAILED && o32.status < 0) {
+      // a numerical failure of the FP32 phase ends the solve (the same rule
+      // as skx_run_batch and the serving engine): no refinement from it
+      out = o32;
+      res->iters = o32.iters;
+      res->evals = o32.evals;
+      hipLaunchKernelGGL(k_square_out<float>, dim3(blocks(I32.h.M, 256)), dim3(256), 0, c->stream,
+                         (const float *)I32.h.phi2[o32.par], (double *)rho_dev, I32.h.M);
+    } else {
+      hipLaunchKernelGGL(k_f2d, dim3(blocks(I64.h.M, 256)), dim3(256), 0, c->stream,
+                         (const float *)I32.h.phi2[o32.par], (double *)I64.h.phi2[0], I64.h.M);
+      rc = run_optimize(c, I64, rho_dev, *p, p->gtol, 2, out);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_square_out<double>, dim3(blocks(I64.h.M, 256)), dim3(256), 0,
+                         c->stream, (const double *)I64.h.phi2[out.par], (double *)rho_dev,
+                         I64.h.M);
+      res->iters = o32.iters + out.iters;
+      res->evals = o32.evals + out.evals;
+    }
   }
   hipError_t he = hipStreamSynchronize(c->stream);
   if (he != hipSuccess) return hip_fail(c, he, "optimisation");
@@ -1715,6 +1735,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
   if (e != hipSuccess) return hip_fail(c, e, "pressure work density");
   double F[2] = {0.0, 0.0}, V[2] = {0.0, 0.0};
   int rc = SKX_OK;
+  int worst = SKX_OK;                // SKX_NOT_CONVERGED of either solve is kept
   for (int k = 0; k < 2 && rc >= 0; ++k) {
     // the cell scaled to V0 (1 -+ eps), ions at fixed fractional positions
     V[k] = V0 * (k == 0 ? 1.0 - eps : 1.0 + eps);
@@ -1733,6 +1754,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
     skx_opt_result res;
     if (rc == SKX_OK) rc = skx_optimize_density(c, work, &q, &res);
     if (rc >= 0) F[k] = res.e.total;
+    if (rc > worst) worst = rc;
   }
   (void)hipStreamSynchronize(s);
   (void)hipFree(work);
@@ -1746,7 +1768,7 @@ int skx_pressure(skx_ctx *c, const void *rho_dev, double eps, const skx_opt_para
   *P = -(F[1] - F[0]) / (V[1] - V[0]);
   if (F_lo) *F_lo = F[0];
   if (F_hi) *F_hi = F[1];
-  return rc;
+  return worst;
 }
 
 int skx_md_step(skx_ctx *c, void *rho_dev, double *pos, double *vel, double *force,
@@ -1808,8 +1830,12 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
                              : std::max(p->gtol, p->fp32_switch_gtol > 0 ? p->fp32_switch_gtol : 1e-5);
     std::vector<SolveDev> hs;
     std::vector<OptState *> states;
-    std::vector<OptState> init(nctx);
+    std::vector<OptState> init;
+    std::vector<int> members;                 // solves of this phase
     for (int i = 0; i < nctx; ++i) {
+      // a numerical failure of the FP32 phase ends that solve (no refinement)
+      if (ph > 0 && o32[i].phase == PH_FAILED && o32[i].status < 0) continue;
+      members.push_back(i);
       Instance &I = ctxs[i]->inst[pr];
       const long long M = I.h.M;
       int start = 0;
@@ -1835,33 +1861,40 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
           hipLaunchKernelGGL(k_fill<float>, dim3(blocks(M, 256)), dim3(256), 0, s,
                              (float *)I.h.phi2[0], (float)v, M);
       }
-      init_state(init[i], *p, gtol, start == 1 ? 1 : 0, pr);
+      init.emplace_back();
+      init_state(init.back(), *p, gtol, start == 1 ? 1 : 0, pr);
       hs.push_back(I.h);
       states.push_back(I.st);
     }
+    const int nm = (int)members.size();
+    if (nm == 0) continue;
     // every state in one copy, scattered to the solves' buffers on the device
-    e = hipMemcpyAsync(dstage, init.data(), sizeof(OptState) * nctx, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(dstage, init.data(), sizeof(OptState) * nm, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(dsptr, states.data(), sizeof(OptState *) * nctx, hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(dsptr, states.data(), sizeof(OptState *) * nm, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_put_states, dim3(nctx), dim3(64), 0, s, dstage, dsptr, nctx);
+      hipLaunchKernelGGL(k_put_states, dim3(nm), dim3(64), 0, s, dstage, dsptr, nm);
       e = hipGetLastError();
     }
     if (e != hipSuccess) { rc = hip_fail(c0, e, "state upload"); break; }
     rc = drive(c0, hs, pr, ddev, dfirst, (p->max_iter + 2) * 24 + 64, s);
     if (rc) break;
-    hipLaunchKernelGGL(k_get_states, dim3(nctx), dim3(64), 0, s, dsptr, dstage, nctx);
+    hipLaunchKernelGGL(k_get_states, dim3(nm), dim3(64), 0, s, dsptr, dstage, nm);
     e = hipGetLastError();
+    std::vector<OptState> got(nm);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(last ? outs.data() : o32.data(), dstage, sizeof(OptState) * nctx,
-                         hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(got.data(), dstage, sizeof(OptState) * nm, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) { rc = hip_fail(c0, e, "state readback"); break; }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) { rc = hip_fail(c0, e, "batch"); break; }
+    for (int k = 0; k < nm; ++k) (last ? outs : o32)[members[k]] = got[k];
   }
   if (rc == SKX_OK) {
-    const int pr = precs.back();
     for (int i = 0; i < nctx; ++i) {
+      // a solve whose FP32 phase failed numerically reports that phase
+      const bool failed32 = precs.size() > 1 && o32[i].phase == PH_FAILED && o32[i].status < 0;
+      if (failed32) outs[i] = o32[i];
+      const int pr = failed32 ? 1 : precs.back();
       Instance &I = ctxs[i]->inst[pr];
       const OptState &o = outs[i];
       if (pr == 0)
@@ -1873,7 +1906,10 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
       energy_from(o.e_acc, ctxs[i]->e_ii, &res[i].e);
       res[i].gnorm = o.rnorm;
       res[i].resets = o.resets;
-      if (precs.size() > 1) {
+      if (failed32) {
+        res[i].fp32_iters = res[i].iters = o32[i].iters;
+        res[i].fp32_evals = res[i].evals = o32[i].evals;
+      } else if (precs.size() > 1) {
         res[i].fp32_iters = o32[i].iters;
         res[i].fp32_evals = o32[i].evals;
         res[i].iters = o.iters + o32[i].iters;

@@ -498,11 +498,13 @@ __device__ __forceinline__ int fd_lookup(double y, const FDTable &fd, double &et
 
 // Perdew-Zunger 1981 LDA (spin-unpolarised): energy per electron and
 // potential, from x = ln n (rs = (3/(4 pi))^(1/3) exp(-x/3)). The paper uses
-// PZ LDA in the adiabatic approximation. The two correlation branches of the
-// fit (dense rs < 1, dilute rs >= 1) jump by ~3e-5 Ha at rs = 1; they are
-// joined C1 over 0.99 <= rs <= 1.01 with w = 3t^2 - 2t^3,
-// t = (rs - 0.99)/0.02, e_c = (1 - w) e_dense + w e_dilute, and v_c is the
-// exact potential of that e_c: v_c = e_c - (rs/3) de_c/drs.
+// PZ LDA in the adiabatic approximation. Two variants (uniform per solve):
+//   join = false  the published fit: dilute branch for rs >= 1, dense branch
+//                 below; the branches jump by ~3e-5 Ha at rs = 1;
+//   join = true   the branches joined C1 over 0.99 <= rs <= 1.01 with
+//                 w = 3t^2 - 2t^3, t = (rs - 0.99)/0.02,
+//                 e_c = (1 - w) e_dense + w e_dilute, v_c the exact potential
+//                 of that e_c: v_c = e_c - (rs/3) de_c/drs.
 template <typename T> struct PZ {
   static constexpr T G = (T)-0.1423, B1 = (T)1.0529, B2 = (T)0.3334;
   static constexpr T A = (T)0.0311, B = (T)-0.048, C = (T)0.0020, D = (T)-0.0116;
@@ -523,17 +525,20 @@ __device__ __forceinline__ void pz_dense(T rs, T lr, T irs, T &e, T &de) {
 }
 
 // (e3 = n^(1/3) = exp(x/3), computed by the caller)
-__device__ __forceinline__ void pz81_ln_e3(double x, double e3, double &eps, double &v) {
+__device__ __forceinline__ void pz81_ln_e3(double x, double e3, bool join, double &eps,
+                                           double &v) {
   const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
   const double LNRS1 = -0.47747065276706024;  // ln RS1
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
   const double rs = RS1 / e3;
   const double ex = -CX / RS1 * e3;
+  const double hi = join ? PZ<double>::HI : 1.0;
+  const double lo = join ? PZ<double>::LO : 1.0;
   double ec, dec;
-  if (rs >= PZ<double>::HI) {
+  if (rs >= hi) {
     const double sq = sqrt(rs);
     pz_dilute(rs, sq, 1.0 / (1.0 + PZ<double>::B1 * sq + PZ<double>::B2 * rs), ec, dec);
-  } else if (rs <= PZ<double>::LO) {
+  } else if (rs <= lo) {
     pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 / RS1, ec, dec);
   } else {
     double e1, d1, e2, d2;
@@ -550,14 +555,14 @@ __device__ __forceinline__ void pz81_ln_e3(double x, double e3, double &eps, dou
   v = (4.0 / 3.0) * ex + ec - rs * (1.0 / 3.0) * dec;
 }
 
-__device__ __forceinline__ void pz81_ln(double x, double &eps, double &v) {
-  pz81_ln_e3(x, exp(x * (1.0 / 3.0)), eps, v);
+__device__ __forceinline__ void pz81_ln(double x, bool join, double &eps, double &v) {
+  pz81_ln_e3(x, exp(x * (1.0 / 3.0)), join, eps, v);
 }
 
 // Single-precision PZ81 for the FP32 evaluations (the exchange-correlation
 // potential then carries FP32 rounding like every other FP32 field; the
 // FP64 refinement uses pz81_ln). Hardware exp2 / reciprocal / square root.
-__device__ __forceinline__ void pz81_lnf(float x, float &eps, float &v) {
+__device__ __forceinline__ void pz81_lnf(float x, bool join, float &eps, float &v) {
   const float RS1 = 0.62035049089940001667f;   // (3/(4 pi))^(1/3)
   const float LNRS1 = -0.47747065276706024f;  // ln RS1
   const float CX = 0.45816529328314287f;       // (3/(4 pi)) (9 pi / 4)^(1/3)
@@ -565,12 +570,14 @@ __device__ __forceinline__ void pz81_lnf(float x, float &eps, float &v) {
   const float e3 = __builtin_amdgcn_exp2f(x * L2E3);
   const float rs = RS1 * __builtin_amdgcn_rcpf(e3);
   const float ex = -(CX / RS1) * e3;
+  const float hi = join ? PZ<float>::HI : 1.0f;
+  const float lo = join ? PZ<float>::LO : 1.0f;
   float ec, dec;
-  if (rs >= PZ<float>::HI) {
+  if (rs >= hi) {
     const float sq = __builtin_amdgcn_sqrtf(rs);
     pz_dilute(rs, sq, __builtin_amdgcn_rcpf(1.0f + PZ<float>::B1 * sq + PZ<float>::B2 * rs), ec,
               dec);
-  } else if (rs <= PZ<float>::LO) {
+  } else if (rs <= lo) {
     pz_dense(rs, LNRS1 - x * (1.0f / 3.0f), e3 * (1.0f / RS1), ec, dec);
   } else {
     float e1, d1, e2, d2;

@@ -81,6 +81,7 @@ struct skx_engine {
   hipStream_t stream = nullptr;          // set-up, results, the FP64 group
   hipStream_t stream32 = nullptr;        // the FP32 group, overlapping the FP64 group's steps
   size_t budget = 0, used = 0;
+  size_t held = 0;                       // finished densities waiting to be polled
   int max_slots = 0;
   uint64_t next_ticket = 1;
   std::deque<Queued> queue;
@@ -90,6 +91,8 @@ struct skx_engine {
   // contexts of finished solves kept for reuse by a request of the same grid
   // (their device arenas stay allocated: no allocation or free, and so no
   // device-wide synchronisation, per request)
+  // (bytes: the footprint of the context's arenas as allocated, i.e. for
+  // the largest history length it has held)
   struct Pooled { skx_ctx *ctx; int n1, n2, n3, mode, m; size_t bytes; };
   std::vector<Pooled> pool;
   size_t pooled = 0;                     // bytes held by pooled contexts
@@ -152,8 +155,12 @@ int admit(skx_engine *e, Queued &q, int pooled_idx, Resident *&out) {
   const skx_request &r = q.req;
   skx_ctx *c = nullptr;
   int rc = SKX_OK;
+  size_t bytes = q.bytes;
   if (pooled_idx >= 0) {
+    // a reused context keeps its arenas, which may be larger than this
+    // request needs (a longer history): charge what is allocated
     c = e->pool[pooled_idx].ctx;
+    bytes = std::max(bytes, e->pool[pooled_idx].bytes + 8 * (size_t)r.n1 * r.n2 * r.n3);
     e->pooled -= e->pool[pooled_idx].bytes;
     e->pool.erase(e->pool.begin() + pooled_idx);
   } else {
@@ -181,7 +188,7 @@ int admit(skx_engine *e, Queued &q, int pooled_idx, Resident *&out) {
   s->opt = r.opt;
   s->t_arrival = r.t_arrival;
   s->t_admit = e->now();
-  s->bytes = q.bytes;
+  s->bytes = bytes;
   Instance &I = c->inst[s->prec];
   hipError_t he = start_uniform(c, I, e->stream);
   if (he != hipSuccess) { delete s; return bad(SKX_E_DEVICE); }
@@ -270,16 +277,24 @@ void finish(skx_engine *e, Resident *r, const OptState &o) {
   else f.res.r.status = (o.phase == PH_DONE && o.status == 0) ? SKX_OK : SKX_NOT_CONVERGED;
   f.res.npoints = I.h.M;
   f.res.t_admit = r->t_admit;
-  if (hipMallocAsync((void **)&f.rho_dev, sizeof(double) * I.h.M, e->stream) == hipSuccess)
+  if (hipMallocAsync((void **)&f.rho_dev, sizeof(double) * I.h.M, e->stream) == hipSuccess) {
     square_out(I, o.par, f.rho_dev, e->stream);
-  else
+    e->held += sizeof(double) * (size_t)I.h.M;
+  } else {
     f.rho_dev = nullptr;
+  }
   (void)hipStreamSynchronize(e->stream);
   f.res.t_done = e->now();
+  // the resident's bytes include its finished density, now counted in held
+  const size_t arena = r->bytes - std::min(r->bytes, sizeof(double) * (size_t)I.h.M);
   if ((int)e->pool.size() < e->max_slots) {
-    const int m = std::min(std::max(r->opt.lbfgs_m, 1), MMAX);
+    // the history length the arenas were allocated for
+    int m = 1;
+    for (const Instance &J : c->inst)
+      if (J.mem) m = std::max(m, J.m_alloc);
     e->pool.push_back({c, c->n1, c->n2, c->n3, r->mode, m, r->bytes});
-    e->pooled += r->bytes;
+    e->pooled += arena;
+    e->pool.back().bytes = arena;
   } else {
     skx_destroy(c);
   }
@@ -365,8 +380,11 @@ int skx_engine_step(skx_engine *e) {
           p.mode == qf.req.fn.precision && p.m >= m)
         mi = (int)i;
     }
+    // a reused context brings its arenas (counted in pooled) and needs only
+    // the result density beyond them
     const size_t reuse = mi >= 0 ? e->pool[mi].bytes : 0;
-    while (e->used + e->pooled - reuse + qf.bytes > e->budget) {
+    const size_t need = std::max(qf.bytes, reuse + 8 * (size_t)qf.req.n1 * qf.req.n2 * qf.req.n3);
+    while (e->used + e->held + e->pooled - reuse + need > e->budget) {
       int victim = -1;
       for (size_t i = 0; i < e->pool.size() && victim < 0; ++i)
         if ((int)i != mi) victim = (int)i;
@@ -376,7 +394,7 @@ int skx_engine_step(skx_engine *e) {
       e->pool.erase(e->pool.begin() + victim);
       if (mi > victim) --mi;
     }
-    if (e->used + e->pooled - reuse + qf.bytes > e->budget) break;
+    if (e->used + e->held + e->pooled - reuse + need > e->budget) break;
     Queued q = std::move(e->queue.front());
     e->queue.pop_front();
     q.req.pos = q.pos.data();
@@ -469,6 +487,7 @@ int skx_engine_poll(skx_engine *e, skx_result *out, double **rho_host, int max, 
       if (rho_host && rho_host[k])
         hipMemcpy(rho_host[k], f.rho_dev, sizeof(double) * f.res.npoints, hipMemcpyDeviceToHost);
       (void)hipFreeAsync(f.rho_dev, e->stream);
+      e->held -= std::min(e->held, sizeof(double) * (size_t)f.res.npoints);
     }
     ++k;
   }

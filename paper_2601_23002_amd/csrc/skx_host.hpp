@@ -43,6 +43,7 @@ struct skx_ctx {
   skx_functional fn{};
   double *w = nullptr, *wp = nullptr;
   int smax = 0;
+  int w_cap = 0;                   // shells the w / wp buffers hold
   bool tables_ok = false;
   double kappa = 1.0;              // preconditioner shift (uniform-gas TF curvature)
   double e_ii = 0;

@@ -76,6 +76,7 @@ struct SolveDev {
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
   int big;                         // passes on the chunked plane kernels: 1 A, 2 C
   unsigned terms;
+  int xc;                          // 1 published PZ81 fit, 2 its C1-joined branches
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
   double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
   Plan p1, p2, p3;

@@ -390,6 +390,7 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
   const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
   const bool a56 = S.a == 5.0 / 6.0;
   const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
+  const bool xcj = S.xc == 2;       // C1-joined PZ81 branches
   const bool need_f = (S.fields & F_F) != 0, need_h = (S.fields & F_H) != 0;
   constexpr int PER = CHUNK / NT;
   R pv[PER], dv[PER];
@@ -436,11 +437,11 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
         double eps, vx;
         if (sizeof(R) == 4) {
           float ef, vf;
-          pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), ef, vf);
+          pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), xcj, ef, vf);
           eps = ef;
           vx = vf;
         } else {
-          pz81_ln_e3(lx, e3, eps, vx);
+          pz81_ln_e3(lx, e3, xcj, eps, vx);
         }
         e_xc += nd * eps;
         v += vx;

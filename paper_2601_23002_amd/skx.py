@@ -28,7 +28,7 @@ OK, NOT_CONVERGED, CANCELLED = 0, 1, 2
 E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC = -1, -2, -3, -4, -5
 TERM_TF, TERM_VW, TERM_NL0, TERM_NL1, TERM_HARTREE, TERM_LOCPP, TERM_XC = 1, 2, 4, 8, 16, 32, 64
 TERM_ALL = 127
-XC_NONE, XC_PZ81 = 0, 1
+XC_NONE, XC_PZ81, XC_PZ81_C1 = 0, 1, 2
 FP64, FP32, MIXED = 0, 1, 2
 RHO, SQRT_RHO = 0, 1
 
@@ -246,7 +246,8 @@ class Context:
         """Configure from a workloads.System."""
         self.set_cell(sys.L, sys.n)
         self.set_ions(sys.pos, sys.zval, sys.rc)
-        self.set_functional(sys.T, sys.beta, sys.alpha, sys.terms, XC_PZ81, precision)
+        self.set_functional(sys.T, sys.beta, sys.alpha, sys.terms, getattr(sys, "xc", XC_PZ81),
+                            precision)
         return self
 
     def evaluate(self, field, kind=SQRT_RHO, want_grad=True):
@@ -338,14 +339,16 @@ class Context:
     def pressure(self, rho, eps=1e-4, gtol=1e-9, max_iter=2000, m=5, fp32_switch_gtol=1e-5):
         """-dF/dV (Hartree/bohr^3) at fixed fractional ion positions by a
         central difference of minimised free energies; returns
-        (P, F(V(1-eps)), F(V(1+eps)))."""
+        (P, F(V(1-eps)), F(V(1+eps))). self.last_status holds the call's
+        status: OK, or NOT_CONVERGED when either solve stopped short."""
         torch = _torch()
         if rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous():
             raise ValueError("rho must be a contiguous float64 CUDA tensor")
         p = OptParams(gtol, max_iter, m, fp32_switch_gtol, 1)
         P, Flo, Fhi = C.c_double(), C.c_double(), C.c_double()
-        self._check(_lib.skx_pressure(self._h, _VP(rho.data_ptr()), eps, C.byref(p), C.byref(P),
-                                      C.byref(Flo), C.byref(Fhi)))
+        rc = self._check(_lib.skx_pressure(self._h, _VP(rho.data_ptr()), eps, C.byref(p),
+                                           C.byref(P), C.byref(Flo), C.byref(Fhi)))
+        self.last_status = rc
         return P.value, Flo.value, Fhi.value
 
     def md_step(self, rho, pos, vel, force, mass, dt, gtol=1e-8, max_iter=1000, m=5,
@@ -483,13 +486,6 @@ def profile_read():
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(min(n, len(PASS_NAMES)))}
 
 
-def fit_beta_mean(ctxs, refs, **kw):
-    """The functional's beta as the mean of per-configuration fits (Methods,
-    optimisation of the beta parameter); returns (mean, [beta_i])."""
-    betas = [c.fit_beta(r, **kw)[0] for c, r in zip(ctxs, refs)]
-    return sum(betas) / len(betas), betas
-
-
 def bench_eval(ctxs, reps=20):
     """Mean per-launch milliseconds of passes A, B, C over a batch."""
     n = len(ctxs)
@@ -540,7 +536,8 @@ class Engine:
         req.nspecies = len(zsp)
         req.zval = _dptr(zsp)
         req.rc = _dptr(rsp)
-        req.fn = Functional(sys.T, sys.beta, sys.alpha, sys.terms, XC_PZ81, precision)
+        req.fn = Functional(sys.T, sys.beta, sys.alpha, sys.terms, getattr(sys, "xc", XC_PZ81),
+                            precision)
         req.opt = OptParams(gtol, max_iter, m, fp32_switch_gtol, 0)
         req.t_arrival = self.clock() if t_arrival is None else t_arrival
         t = C.c_uint64()

@@ -57,6 +57,7 @@ class System:
     beta: float = 1.0              # weight of the first-order kernel correction
     alpha: float = 5.0 / 6.0       # exponent a of f = n**a in the nonlocal term
     terms: int = 0x7F              # bitmask, see TERM_* below
+    xc: int = 1                    # XC_PZ81 (published fit) or XC_PZ81_C1 (joined), see below
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -76,6 +77,8 @@ class System:
 TERM_TF, TERM_VW, TERM_NL0, TERM_NL1, TERM_HARTREE, TERM_LOCPP, TERM_XC = (
     1, 2, 4, 8, 16, 32, 64)
 TERM_ALL = 0x7F
+# exchange-correlation variant codes (the same numbers as the library's)
+XC_NONE, XC_PZ81, XC_PZ81_C1 = 0, 1, 2
 
 
 def cell_side(nelec: float, rs: float) -> float:

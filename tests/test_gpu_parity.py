@@ -167,17 +167,38 @@ def test_evaluate_fp32_within_single_precision():
     _compare_eval(_system(24, seed=5), seed=6, tol=2e-5, prec=skx.FP32)
 
 
+@pytest.mark.parametrize("variant", ["published", "joined"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_evaluate_across_the_pz81_join(precision):
-    """Mean density at rs = 1: a good share of the points falls inside the
-    0.99 <= rs <= 1.01 join of the two PZ81 correlation branches."""
+def test_evaluate_across_rs_1(precision, variant):
+    """Mean density at rs = 1: a good share of the points falls on both
+    sides of the PZ81 branch point and inside the 0.99 <= rs <= 1.01 join.
+    Both exchange-correlation variants against the oracle's."""
     skx, _ = _lib()
     s = _system(24, seed=9, rs=1.0, T=2.0)
-    _say(f"case: evaluate across the PZ81 join, {precision}")
+    s.xc = W.XC_PZ81 if variant == "published" else W.XC_PZ81_C1
+    _say(f"case: evaluate across rs = 1, {precision}, PZ81 {variant}")
     if precision == "fp64":
         _compare_eval(s, seed=10)
     else:
         _compare_eval(s, seed=10, tol=2e-5, prec=skx.FP32)
+
+
+def test_pz81_variants_differ_only_inside_the_window():
+    """The two variants give the same E_xc where no density falls inside
+    0.99 <= rs <= 1.01, and different ones where some does."""
+    skx, torch = _lib()
+    out = {}
+    for rs in (1.0, 3.0):
+        s = _system(16, seed=19, rs=rs, T=1.0)
+        phi = torch.tensor(W.random_phi(s, 20, amp=0.2), dtype=torch.float64, device="cuda")
+        for v in (W.XC_PZ81, W.XC_PZ81_C1):
+            s.xc = v
+            c = skx.Context(0).setup(s)
+            out[(rs, v)] = c.evaluate(phi, skx.SQRT_RHO, False)[0]["e_xc"]
+    _say(f"  E_xc published/joined: rs 1 {out[(1.0, 1)]:.12f} {out[(1.0, 2)]:.12f}; "
+         f"rs 3 {out[(3.0, 1)]:.12f} {out[(3.0, 2)]:.12f}")
+    assert out[(3.0, 1)] == out[(3.0, 2)]
+    assert out[(1.0, 1)] != out[(1.0, 2)]
 
 
 def test_evaluate_rejects_nonfinite():

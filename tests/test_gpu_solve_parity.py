@@ -1,0 +1,204 @@
+"""Whole solves through the C ABI against converged oracle minima, the
+pressure against the oracle's, and results in large batches and the serving
+engine against the same solves alone.
+
+Stored minima (tests/golden/minima_*.npz) are written by
+tests/golden/make_minima.py, which calls only the CPU oracle. Tolerances
+(FP64): free energy 1e-10 relative, integrated density deviation
+int |n - n_ref| / N_e <= 1e-6 (the bound is about ||r|| over the smallest
+Hessian eigenvalue, so it cannot be 1e-10). Mixed precision: 1e-6 Ha per
+atom and 1e-5 relative density.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_23002_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2601_23002_amd import skx
+    return skx, torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _golden(case):
+    z = np.load(os.path.join(GOLDEN, f"minima_{case}.npz"))
+    keys = [str(k) for k in z["keys"]]
+    energy = dict(zip(keys, z["energy"].tolist()))
+    info = z["info"]
+    if case == "c1":
+        s = W.config_single_small(32)
+    else:
+        s = W.config_scan(64)[int(case[4:]) - 2]
+    s.xc = int(info[4])
+    assert int(info[3]) == 0, "the stored oracle solve did not converge"
+    return s, z["n"].astype(np.float64), energy
+
+
+CASES = ["c1", "scan2", "scan5", "scan8"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fp64_solve_matches_the_oracle_minimum(case):
+    skx, torch = _lib()
+    s, n_ref, e_ref = _golden(case)
+    _say(f"case: fp64 solve vs oracle minimum {case} ({s.name}, xc {s.xc})")
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-8, max_iter=1000)
+    assert r["status"] == skx.OK, r
+    E, Er = r["energy"]["free_energy"], e_ref["free_energy"]
+    dn = (s.volume / s.M) * np.sum(np.abs(rho.cpu().numpy() - n_ref)) / s.nelec
+    _say(f"  F {E:.14f} vs {Er:.14f} (rel {abs(E - Er) / abs(Er):.2e}); "
+         f"int|dn|/N_e {dn:.2e}; {r['iters']} iterations")
+    assert abs(E - Er) <= 1e-10 * abs(Er)
+    assert dn <= 1e-6
+    for k in ("f_tf", "e_vw", "f_nl0", "f_nl1", "e_h", "e_loc", "e_xc"):
+        assert abs(r["energy"][k] - e_ref[k]) <= 1e-8 * abs(Er), k
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_mixed_solve_matches_the_oracle_minimum(case):
+    skx, torch = _lib()
+    s, n_ref, e_ref = _golden(case)
+    _say(f"case: mixed solve vs oracle minimum {case}")
+    c = skx.Context(0).setup(s, precision=skx.MIXED)
+    rho, r = c.optimize(gtol=1e-8, max_iter=1000, fp32_switch_gtol=1e-5)
+    assert r["status"] == skx.OK, r
+    assert r["fp32_iters"] > 0
+    per_atom = abs(r["energy"]["free_energy"] - e_ref["free_energy"]) / len(s.zval)
+    n = rho.cpu().numpy()
+    rel = np.sum(np.abs(n - n_ref)) / np.sum(n_ref)
+    _say(f"  {per_atom:.2e} Ha/atom, density {rel:.2e}; "
+         f"{r['fp32_iters']} FP32 + {r['iters'] - r['fp32_iters']} FP64 iterations")
+    assert per_atom <= 1e-6
+    assert rel <= 1e-5
+
+
+def test_published_pz81_fit_at_rs_1_floors_the_residual():
+    """The 64-ion rs = 1 scan system with the published PZ81 fit: the jump
+    of the correlation potential at rs = 1 keeps ||r|| from reaching 1e-8.
+    The solve stops with its best state; its energy is reported against the
+    C1-joined variant's oracle minimum."""
+    skx, torch = _lib()
+    s, n_ref, e_ref = _golden("scan2")
+    assert s.xc == W.XC_PZ81_C1
+    s.xc = W.XC_PZ81
+    _say("case: fp64 solve at rs = 1 with the published PZ81 fit")
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-8, max_iter=1000)
+    d = (r["energy"]["free_energy"] - e_ref["free_energy"]) / len(s.zval)
+    dn = (s.volume / s.M) * np.sum(np.abs(rho.cpu().numpy() - n_ref)) / s.nelec
+    _say(f"  status {r['status']}, |r| {r['gnorm']:.3e} after {r['iters']} iterations; "
+         f"F - F(joined minimum) = {d:.3e} Ha/atom, int|dn|/N_e {dn:.2e}")
+    assert r["status"] in (skx.OK, skx.NOT_CONVERGED)
+    assert abs(d) < 1e-4 and dn < 1e-2
+
+
+def test_pressure_matches_the_oracle_pressure():
+    """Full functional (beta = 0.7, every term, 5 H on 12^3): skx_pressure
+    against the oracle's two minimisations at V0 (1 -+ eps)."""
+    skx, torch = _lib()
+    from oracle import pressure
+    from oracle.functional import Problem
+    from oracle.optimize import optimize
+    s = W.uniform_system(5, 1.0, 0.4, 2.0, 1.0, 12, seed=93, beta=0.7)
+    _say("case: pressure vs oracle, 5 H 12^3 full functional")
+    ref_min = optimize(Problem(s), gtol=1e-11, max_iter=2000)
+    P_ref, lo_ref, hi_ref = pressure.minimised_pressure(s, eps=1e-4, gtol=1e-11,
+                                                        phi0=np.sqrt(ref_min["n"]))
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-11, max_iter=2000)
+    assert r["status"] == skx.OK
+    P, lo, hi = c.pressure(rho, eps=1e-4, gtol=1e-11)
+    assert c.last_status == skx.OK
+    _say(f"  P {P:.12e} vs oracle {P_ref:.12e}")
+    assert abs(P - P_ref) <= 1e-6 * abs(P_ref)
+    assert abs(lo - lo_ref) <= 1e-10 * abs(lo_ref) and abs(hi - hi_ref) <= 1e-10 * abs(hi_ref)
+
+
+def test_pressure_reports_an_unconverged_solve():
+    skx, torch = _lib()
+    s = W.uniform_system(5, 1.0, 0.4, 2.0, 1.0, 12, seed=93, beta=0.7)
+    _say("case: pressure with max_iter 1")
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+    rho, r = c.optimize(gtol=1e-9, max_iter=2000)
+    P, lo, hi = c.pressure(rho, eps=1e-4, gtol=1e-14, max_iter=1)
+    assert c.last_status == skx.NOT_CONVERGED
+    assert np.isfinite(P)
+
+
+def _alone(skx, s, precision, **kw):
+    c = skx.Context(0).setup(s, precision=precision)
+    rho, r = c.optimize(**kw)
+    return rho.cpu().numpy(), r
+
+
+def test_80cubed_snapshot_in_an_uneven_batch_equals_alone():
+    """One 80^3 ensemble snapshot (116 Z = 4 ions) batched with 48^3 and 36^3
+    snapshots, mixed precision: every result bitwise equal to its solve
+    alone."""
+    skx, torch = _lib()
+    ens = W.config_ensemble()
+    pick = [10] + [i for i, x in enumerate(ens) if x.n[0] in (36, 48)][:2]
+    systems = [ens[i] for i in pick]
+    for x in systems:
+        x.xc = W.XC_PZ81_C1
+    _say(f"case: batch with an 80^3 snapshot, grids {[x.n[0] for x in systems]}")
+    assert systems[0].n[0] == 80
+    kw = dict(gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5)
+    ctxs = [skx.Context(0).setup(x, precision=skx.MIXED) for x in systems]
+    rhos = [torch.empty(x.n, dtype=torch.float64, device="cuda") for x in systems]
+    res = skx.run_batch(ctxs, rhos, **kw)
+    for x, r, rho in zip(systems, res, rhos):
+        n_a, r_a = _alone(skx, x, skx.MIXED, **kw)
+        assert r["status"] == skx.OK, r
+        assert r["iters"] == r_a["iters"] and r["evals"] == r_a["evals"]
+        assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(rho.cpu().numpy(), n_a)
+
+
+def test_engine_large_requests_equal_alone():
+    """Serving requests of 144^3 (FP64 planes beyond LDS: chunked passes) and
+    128^3 next to a small one, two slots: each result bitwise equal to its
+    solve alone."""
+    skx, _ = _lib()
+    stream = W.config_stream(count=60)
+    systems = [stream[34][1], stream[52][1], W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 16, seed=47)]
+    for x in systems:
+        x.xc = W.XC_PZ81_C1
+    assert systems[0].n[0] == 144 and systems[1].n[0] == 128
+    kw = dict(gtol=1e-8, max_iter=1000, m=5, fp32_switch_gtol=1e-5)
+    _say(f"case: engine with large requests, grids {[x.n[0] for x in systems]}")
+    eng = skx.Engine(0, hbm_budget=8 << 30, max_slots=2)
+    tickets = {eng.submit(x, precision=skx.MIXED, **kw): x for x in systems}
+    done = []
+    steps = 0
+    while eng.pending() > 0 and steps < 20000:
+        eng.step()
+        done += eng.poll(want_density=True)
+        steps += 1
+    assert len(done) == len(systems)
+    for d in done:
+        x = tickets[d["ticket"]]
+        n_a, r_a = _alone(skx, x, skx.MIXED, **kw)
+        r = d["result"]
+        _say(f"  {x.name} {x.n[0]}^3: {r['iters']} iterations, status {r['status']}")
+        assert r["status"] == skx.OK, r
+        assert r["iters"] == r_a["iters"] and r["evals"] == r_a["evals"]
+        assert r["energy"]["free_energy"] == r_a["energy"]["free_energy"]
+        assert np.array_equal(d["rho"], n_a)
+    eng.close()

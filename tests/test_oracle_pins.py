@@ -380,27 +380,61 @@ def test_exchange_closed_form_and_potential():
     assert np.all(eps < eps_x_ref)          # correlation energy is negative
 
 
+def _n_of(rs):
+    return 3.0 / (4.0 * math.pi * rs ** 3)
+
+
+def test_pz81_published_fit_takes_its_branches_on_both_sides_of_rs_1():
+    """XC_PZ81 is the published two-branch fit: the dilute branch for
+    rs >= 1 (rs = 1 included), the dense branch below, exchange added; and
+    v = d(n eps)/dn on each side. The printed constants leave a jump at
+    rs = 1 whose size is that of rounding C and D to four decimals."""
+    for rs in (0.3, 0.7, 0.99, 1.0 - 1e-9):
+        e, v = xc.pz81(np.array([_n_of(rs)]), xc.XC_PZ81)
+        ec = (xc.PZ_A * math.log(rs) + xc.PZ_B + xc.PZ_C * rs * math.log(rs) + xc.PZ_D * rs)
+        assert abs(e[0] - (-xc.CX / rs + ec)) < 1e-14, rs
+    for rs in (1.0, 1.0 + 1e-9, 1.5, 4.0, 20.0):
+        e, v = xc.pz81(np.array([_n_of(rs)]), xc.XC_PZ81)
+        ec = xc.PZ_GAMMA / (1.0 + xc.PZ_BETA1 * math.sqrt(rs) + xc.PZ_BETA2 * rs)
+        assert abs(e[0] - (-xc.CX / rs + ec)) < 1e-14, rs
+    for rs in (0.5, 0.98, 1.02, 3.0):
+        n = _n_of(rs)
+        h = 1e-6 * n
+        e, v = xc.pz81(np.array([n - h, n, n + h]), xc.XC_PZ81)
+        assert abs(((n + h) * e[2] - (n - h) * e[0]) / (2 * h) - v[1]) < 1e-8, rs
+    e, v = xc.pz81(np.array([_n_of(1.0 - 1e-12), _n_of(1.0)]), xc.XC_PZ81)
+    assert 1e-6 < abs(e[0] - e[1]) < 1e-4 and 1e-6 < abs(v[0] - v[1]) < 1e-4
+    # the dense branch's log coefficient is the Gell-Mann-Brueckner value
+    # (1 - ln 2)/pi^2 to the four printed decimals
+    assert abs(xc.PZ_A - (1.0 - math.log(2.0)) / math.pi ** 2) < 5e-5
+
+
 def test_pz81_join_is_continuous_and_consistent():
-    """The two branches of the fit are joined C1 over 0.99 <= rs <= 1.01:
-    eps_xc and v_xc are continuous across the window edges and rs = 1, and
-    v_xc = d(n eps_xc)/dn holds inside the window (central differences)."""
-    def n_of(rs):
-        return 3.0 / (4.0 * math.pi * rs ** 3)
+    """XC_PZ81_C1 joins the two branches C1 over 0.99 <= rs <= 1.01:
+    eps_xc and v_xc are continuous across the window edges and rs = 1,
+    v_xc = d(n eps_xc)/dn holds inside the window (central differences),
+    and outside the window the values are those of the published fit."""
     for rs in (xc.RS_JOIN_LO, 1.0, xc.RS_JOIN_HI):
-        e, v = xc.pz81(np.array([n_of(rs * (1 - 1e-10)), n_of(rs * (1 + 1e-10))]))
-        # (without the join both would jump by ~3e-5 Ha at rs = 1)
+        e, v = xc.pz81(np.array([_n_of(rs * (1 - 1e-10)), _n_of(rs * (1 + 1e-10))]),
+                       xc.XC_PZ81_C1)
+        # (the published fit jumps by ~3e-5 Ha at rs = 1)
         assert abs(e[0] - e[1]) < 1e-8 and abs(v[0] - v[1]) < 1e-8, rs
     for rs in (0.985, 0.992, 0.999, 1.0, 1.004, 1.009, 1.015):
-        n = n_of(rs)
+        n = _n_of(rs)
         h = 1e-6 * n
-        e, v = xc.pz81(np.array([n - h, n, n + h]))
+        e, v = xc.pz81(np.array([n - h, n, n + h]), xc.XC_PZ81_C1)
         dnde = ((n + h) * e[2] - (n - h) * e[0]) / (2 * h)
         assert abs(dnde - v[1]) < 1e-8, rs
-    # the join stays within the branch gap of the published fit
-    e_j, _ = xc.pz81(np.array([n_of(1.0)]))
-    e_d, _ = xc.pz81(np.array([n_of(0.98)]))
-    e_l, _ = xc.pz81(np.array([n_of(1.02)]))
-    assert min(e_d[0], e_l[0]) - 1e-2 < e_j[0] < max(e_d[0], e_l[0]) + 1e-2
+    rs = np.concatenate([np.linspace(0.2, 0.9899, 50), np.linspace(1.0101, 8.0, 50)])
+    e1, v1 = xc.pz81(_n_of(rs), xc.XC_PZ81)
+    e2, v2 = xc.pz81(_n_of(rs), xc.XC_PZ81_C1)
+    assert np.array_equal(e1, e2) and np.array_equal(v1, v2)
+    # inside the window the join stays between the two branches
+    rs = np.linspace(0.9901, 1.0099, 41)
+    e, _ = xc.pz81(_n_of(rs), xc.XC_PZ81_C1)
+    ed = -xc.CX / rs + xc.PZ_A * np.log(rs) + xc.PZ_B + xc.PZ_C * rs * np.log(rs) + xc.PZ_D * rs
+    el = -xc.CX / rs + xc.PZ_GAMMA / (1 + xc.PZ_BETA1 * np.sqrt(rs) + xc.PZ_BETA2 * rs)
+    assert np.all(e >= np.minimum(ed, el) - 1e-15) and np.all(e <= np.maximum(ed, el) + 1e-15)
 
 
 # ----------------------------------------------------------------------------

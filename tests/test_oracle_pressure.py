@@ -36,3 +36,38 @@ def test_ewald_pressure_is_minus_dE_dV():
     fd = -(ions.ewald(Lp, frac * Lp, Z) - ions.ewald(Lm, frac * Lm, Z)) / (2 * h)
     p = pressure.ewald_pressure(L, frac * L, Z)
     assert abs(p - fd) < 1e-7 * abs(p)
+
+
+def _system(nions, n, seed, terms, beta=0.7, rs=2.0, T=1.0):
+    from paper_2601_23002_amd import workloads as W
+    return W.uniform_system(nions, 1.0, 0.4, rs, T, n, seed=seed, beta=beta, terms=terms)
+
+
+def test_minimised_pressure_of_the_uniform_gas_is_the_closed_form():
+    """With no spatial terms the minimum is the uniform density, so the
+    minimised-energy pressure is the closed-form TF + XC + Ewald value."""
+    from paper_2601_23002_amd import workloads as W
+    s = _system(4, 12, 91, W.TERM_TF | W.TERM_XC)
+    P, lo, hi = pressure.minimised_pressure(s, eps=1e-4, gtol=1e-11)
+    ref = pressure.uniform_pressure(s.nelec / s.L ** 3, s.T, True) + pressure.ewald_pressure(
+        s.L, s.pos, s.zval)
+    assert abs(P - ref) < 1e-7 * abs(ref)
+    assert (lo > hi) == (P > 0)
+
+
+def test_minimised_pressure_equals_the_scaled_density_route():
+    """Full functional (beta != 0, every term): two minimisations at
+    V0 (1 -+ eps) against two evaluations of the V0 minimum carried with the
+    cell. F is stationary in n at the minimum, so the two routes agree to
+    O(eps^2); a wrong sign, scaling or volume in either fails."""
+    from paper_2601_23002_amd import workloads as W
+    from oracle.functional import Problem
+    from oracle.optimize import optimize
+    s = _system(5, 12, 93, W.TERM_ALL, beta=0.7)
+    res = optimize(Problem(s), gtol=1e-11, max_iter=2000)
+    assert res["status"] == 0
+    P_min, _, _ = pressure.minimised_pressure(s, eps=1e-4, gtol=1e-11, phi0=np.sqrt(res["n"]))
+    P_sc = pressure.scaled_density_pressure(s, res["n"], eps=1e-4)
+    assert abs(P_min - P_sc) < 1e-8 * abs(P_min), (P_min, P_sc)
+    # and the pressure is not dominated by one term: the Ewald part alone differs
+    assert abs(P_min - pressure.ewald_pressure(s.L, s.pos, s.zval)) > 1e-3 * abs(P_min)
