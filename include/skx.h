@@ -240,6 +240,21 @@ int skx_structure_factors(skx_ctx *ctx, const void *in_dev, int in_kind, double 
  * Errors: SKX_E_INVALID (null argument), SKX_E_STATE (no cell). */
 int skx_density_deviation(skx_ctx *ctx, const void *a_dev, const void *b_dev, double *out);
 
+/* skx_density_deviation for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same value, bit for bit, with the
+ * partial sums and the result in a fixed device array of the library
+ * (1025 doubles, 8200 bytes per device, held until the process ends), so
+ * the call allocates and frees nothing. Every call on a device shares that
+ * device's array: calls that overlap on one device (other contexts or
+ * streams) race and must be serialised by the caller. Nothing needs
+ * clearing between calls (each call writes every value it reads). Arguments
+ * and errors as skx_density_deviation; SKX_E_INVALID also if the grid would
+ * need more partial sums than the array holds (no grid of the accepted
+ * sizes does: the partial sums are capped at 1024). */
+int skx_density_deviation_noalloc(skx_ctx *ctx, const void *a_dev, const void *b_dev,
+                                  double *out);
+
 /* Kohn-Sham-assisted fit of beta for one configuration (Eq. (3); Methods,
  * optimisation of the beta parameter): the beta in [beta_lo, beta_hi]
  * minimising D(beta) = integral |n[beta] - n_ref| dr, n[beta] the minimising

@@ -85,6 +85,8 @@ hipError_t init_device(int dev, std::string &err) {
   r.fd.inv_h = 1.0 / FD_H;
   r.fd.n = FD_N;
   r.fd.node = r.fdcoef;
+  e = init_noalloc_scratch(dev);
+  if (e != hipSuccess) { err = "fixed scratch symbol lookup failed"; return e; }
   r.ready = true;
   return hipSuccess;
 }

@@ -125,6 +125,9 @@ int ewald_force_terms(double L);
 // integrated absolute density deviation of the beta fit (skx_fit.hip);
 // part_dev holds deviation_blocks(n) doubles
 int deviation_blocks(long long n);
+// Per-device set-up of the fixed scratch of skx_density_deviation_noalloc
+// (call with `dev` current).
+hipError_t init_noalloc_scratch(int dev);
 hipError_t density_deviation(const double *a, const double *b, long long n, double dV,
                              double *part_dev, double *out_dev, hipStream_t s);
 // static structure factors (skx_structure.hip)

@@ -114,6 +114,7 @@ _sig("skx_structure_factors", C.c_int, [_VP, _VP, C.c_int, C.POINTER(C.c_double)
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_int), C.c_int])
 _sig("skx_density_deviation", C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_double)])
+_sig("skx_density_deviation_noalloc", C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_double)])
 _sig("skx_fit_beta", C.c_int, [_VP, _VP, _VP, C.c_double, C.c_double, C.c_double,
                                C.POINTER(OptParams), C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_int)])
@@ -316,6 +317,18 @@ class Context:
         out = C.c_double()
         self._check(_lib.skx_density_deviation(self._h, _VP(a.data_ptr()), _VP(b.data_ptr()),
                                                C.byref(out)))
+        return out.value
+
+    def density_deviation_noalloc(self, a, b):
+        """density_deviation with the library's fixed device scratch (the call
+        allocates nothing; calls on one device must not overlap)."""
+        torch = _torch()
+        for t in (a, b):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("densities must be contiguous float64 CUDA tensors")
+        out = C.c_double()
+        self._check(_lib.skx_density_deviation_noalloc(self._h, _VP(a.data_ptr()),
+                                                       _VP(b.data_ptr()), C.byref(out)))
         return out.value
 
     def fit_beta(self, rho_ref, lo=0.0, hi=2.0, xtol=1e-4, gtol=1e-8, max_iter=1000, m=5,
