@@ -1,25 +1,51 @@
 #!/usr/bin/env python3
-"""Throughput of the batched mixed-precision OFDFT solve on one MI355X.
+"""Throughput of batched mixed-precision OFDFT solves on one MI355X.
 
-One step = one batched solve, through the C-ABI library, of the scan
-workload: 9 independent systems of 64 Z=1 ions (erf pseudopotential,
-rc = 0.3 bohr) at rs in {1,2,4} bohr x T in {0.5,2,8} Ha on 64^3 grids,
-uniform random positions (seeds 2..10). Every step runs every hot-path row:
-structure factor and kernel tables (set-up of each solve), then the
-optimiser with its fused FFT/functional evaluations, FP32 until
-||r|| < 1e-5 and FP64 refinement to ||r|| < 1e-8.
+Headline (value): the uneven thermal-like ensemble, 256 snapshots of 16-256
+Z=1 / Z=4 ions (erf pseudopotentials rc 0.3 / 0.5 bohr) on grids of
+32^3-80^3 (h = 0.25 bohr), seed 12. One step = one batched solve of all
+256 through the C-ABI library (skx_run_batch): one launch per kernel over
+every resident solve, FP32 evaluations until ||r|| < 1e-5, then FP64
+refinement to ||r|| < 1e-8. The structure factor and kernel tables are
+built at set-up and cached per context, so a step is the optimisation
+itself: every evaluation (passes A, B, C), the optimiser's vector kernels
+and its preconditioner.
 
 Metric: grid-point functional evaluations per second,
-sum over solves of (evaluations x grid points) / wall time of the step.
-The plain FP64 GPU path is timed on the same workload for the speedup,
-and the mixed results are checked against it per solve (Ha/atom).
+sum over solves of (evaluations x grid points) / wall time of the step. The
+same snapshots solved in plain FP64 give the speedup and the per-result
+error of the mixed path (Ha/atom, relative density).
 
-One untimed step first carries HIP events on every pass launch (per-pass
-times, and which evaluation kernel dominates). In the timed steps only the
-dominant kernel's launches carry start/stop events (the library launches
-eagerly, its default); the roofline comes from those events. The same steps
-are then timed without any events (value_no_events) and replayed from
-captured HIP graphs (value_graphs).
+Sub-objects:
+  scan   the 9 solves of 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha on
+         64^3 (the only grid with compile-time-shaped kernels), mixed and
+         FP64, with the error against the stored oracle minima of seeds 2,
+         5 and 8 (tests/golden);
+  serve  a Poisson request stream (200/s offered, 16-1024 ions, 32^3-192^3)
+         through the serving engine: served rate, p50/p99 latency, and the
+         same at a sustainable rate when the offered one saturates;
+  forces, structure, beta_fit  the next rows on the scan minima.
+
+Timing: one untimed step carries HIP events on every pass launch (per-pass
+times, and which pass dominates). In the timed steps only the dominant
+pass's launches carry start/stop events attached to the kernel launches
+(the library launches eagerly, its default); the roofline comes from those
+events, with the algorithmic bytes of the three-pass schedule per grid
+point and evaluation (b = 8 FP64, 4 FP32; H = n1 n2 (n3/2 + 1) half-spectrum
+entries, nf transformed fields):
+  pass A  b M (phi) [+ b M (the trial direction d)] + nf 2b H
+  pass B  2 nf 2b H + 2b H (V_loc(G))
+  pass C  nf 2b H + b M (phi_t) + b M (dE/dphi)
+(160 B FP64 / 80 B FP32 per point for four fields, as the survey's model,
+plus the Nyquist column and d). The same steps are then timed without any
+events (value_no_events) and replayed from captured HIP graphs
+(value_graphs).
+
+Exchange-correlation: PZ81 with its two correlation branches joined C1 over
+0.99 <= rs <= 1.01 (SKX_XC_PZ81_C1) for every solve that reaches rs < 1.01
+somewhere (the Z = 4 snapshots, the rs = 1 scan systems, the served
+requests): with the published fit's jump at rs = 1 those solves cannot
+reach ||r|| < 1e-8. The rs = 2 and 4 scan systems use the published fit.
 """
 from __future__ import annotations
 
@@ -34,80 +60,77 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LEGS = ("ensemble", "scan", "serve", "forces")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparisons")
     ap.add_argument("--gtol", type=float, default=1e-8)
     ap.add_argument("--switch-gtol", type=float, default=1e-5,
                     help="||r|| at which the mixed solves leave FP32 for the FP64 refinement")
-    ap.add_argument("--fp64-max-iter", type=int, default=500,
+    ap.add_argument("--fp64-max-iter", type=int, default=3000,
                     help="iteration cap of the plain FP64 comparison solves")
-    ap.add_argument("--workload", choices=("scan", "ensemble", "serve"), default="scan",
-                    help="scan: the headline line; ensemble: 256 uneven thermal snapshots in "
-                         "one batch; serve: Poisson request stream through the serving engine")
-    ap.add_argument("--count", type=int, default=0,
-                    help="ensemble snapshots / served requests (0: the workload's default)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma list of ensemble (the headline), scan, serve, forces")
+    ap.add_argument("--count", type=int, default=256, help="ensemble snapshots")
+    ap.add_argument("--serve-count", type=int, default=200, help="served requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests per second")
+    ap.add_argument("--extra-steps", type=int, default=3,
+                    help="steps of the no-event and graph-replay timings")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default FFT radix orders instead of timing the candidates")
     ap.add_argument("--graphs", choices=("default", "on", "off"), default="default",
                     help="replay the batched step sequences from HIP graphs or launch them "
                          "eagerly (default: the library's setting)")
-    ap.add_argument("--no-forces", action="store_true",
-                    help="skip the forces / MD-step measurement after the headline steps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
     return ap.parse_args()
 
 
-def pass_bytes(sys_, prec_bytes, nf, with_loc, phase_trial):
-    """Algorithmic HBM bytes of one evaluation of one solve, per kernel: the
-    pointwise kernel, pass A's transform, pass B, pass C."""
+def pass_bytes(sys_, b, nf, with_loc, trial):
+    """Algorithmic HBM bytes of one evaluation of one solve per pass (A, B,
+    C): each of the nf half spectra crosses HBM once per direction between
+    the plane and pencil phases; phi (and d for a trial point) in, dE/dphi
+    out (b bytes per real value)."""
     n1, n2, n3 = sys_.n
     M = n1 * n2 * n3
-    Hh = n1 * n2 * (n3 // 2 + 1)          # half-spectrum complex entries
-    b = prec_bytes
-    spec = 2 * b * Hh                     # one half spectrum
-    has_f, has_h = nf >= 3, nf >= 4
-    # pointwise kernel: phi (+ d) in; phi_t, the local potential, and with
-    # the f field n^a and c_P, with the h field c_Q out
-    point = (2 if phase_trial else 1) * b * M + (2 + (2 if has_f else 0) + (1 if has_h else 0)) * b * M
-    # pass A transform: phi_t (and n^a) in, nf half spectra out
-    a = (2 if has_f else 1) * b * M + nf * spec
+    spec = 2 * b * n1 * n2 * (n3 // 2 + 1)        # one half spectrum
+    a = (2 if trial else 1) * b * M + nf * spec
     bb = 2 * nf * spec + (spec if with_loc else 0)
-    # C: nf half spectra and the handed arrays (phi_t, v0, c_P, c_Q) in; dE/dphi out
-    handed = 2 + (1 if has_f else 0) + (1 if has_h else 0)
-    c = nf * spec + handed * b * M + b * M
-    return point, a, bb, c
+    c = nf * spec + 2 * b * M
+    return a, bb, c
 
 
 PASS_SOURCES = ("paper_2601_23002_amd/csrc/skx_passes.hip", "paper_2601_23002_amd/csrc/skx_device.hpp",
-                 "paper_2601_23002_amd/csrc/skx_internal.hpp")
-TRAFFIC_FILE = "profiles/traffic_scan64_mixed.md"
+                "paper_2601_23002_amd/csrc/skx_internal.hpp")
+TRAFFIC_FILE = "profiles/traffic_ensemble256_mixed.md"
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of an evaluation pass from the committed
-    FETCH_SIZE/WRITE_SIZE summary, or None when the pass sources changed since
-    those counters were taken."""
+def pass_sources_hash():
     import hashlib
     h = hashlib.sha256()
     for f in PASS_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of an evaluation pass from the committed
+    FETCH_SIZE/WRITE_SIZE summary of the ensemble workload, or None when the
+    pass sources changed since those counters were taken."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
             kv = dict(l.strip().split(": ", 1) for l in fh if l.startswith("    pass"))
     except OSError:
         return None
-    if kv.get("pass_sources_sha256_16") != h.hexdigest()[:16]:
+    if kv.get("pass_sources_sha256_16") != pass_sources_hash():
         return None
     v = kv.get(f"{kernel}_traffic_bytes_per_launch")
     return None if v is None else float(v)
@@ -135,9 +158,9 @@ def _host_cpu():
     return "unknown CPU"
 
 
-def cpu_baseline(sys_, seed=5, reps=3):
+def cpu_baseline(sys_, label, seed=5, reps=3):
     """The oracle as it stands: the median of `reps` FP64 evaluations of one
-    64^3 system on one thread."""
+    system on one thread."""
     from threadpoolctl import threadpool_limits
     from paper_2601_23002_amd import workloads as W
     from oracle.functional import Problem
@@ -151,9 +174,9 @@ def cpu_baseline(sys_, seed=5, reps=3):
             times.append(time.perf_counter() - t0)
     dt = sorted(times)[len(times) // 2]
     return dict(value=sys_.M / dt, unit="grid-pt evals/s", cores=1, kind="oracle",
-                sample=f"median of {reps} FP64 evaluations (all terms, energy + dE/dphi) of one "
-                       f"{sys_.n[0]}^3 scan system, single thread, {dt:.1f} s each; host "
-                       f"{_host_cpu()}, {os.cpu_count()} logical CPUs")
+                sample=f"median of {reps} FP64 evaluations (all terms, energy + dE/dphi) of "
+                       f"{label} ({sys_.n[0]}^3, {len(sys_.zval)} ions), single thread, "
+                       f"{dt:.1f} s each; host {_host_cpu()}, {os.cpu_count()} logical CPUs")
 
 
 FP64_VEC_PEAK_TFLOPS = 78.6
@@ -270,87 +293,243 @@ def forces_leg(args, skx, systems, ctxs, rhos):
     return out
 
 
-def run_ensemble(args):
-    """Uneven thermal-like snapshots solved together: one launch per kernel
-    over every resident solve."""
+
+
+def xc_for(W, s):
+    """The published PZ81 fit unless some density of the solve reaches
+    rs < 1.01 (dense systems: Z = 4 ions, mean rs below 2), where the
+    C1-joined branches let the minimiser converge."""
+    dense = float(s.zval[0]) > 1.0 or float(s.meta.get("rs", 2.0)) < 2.0
+    return W.XC_PZ81_C1 if dense else W.XC_PZ81
+
+
+def solve_errors(res_a, rho_a, res_b, rho_b, systems):
+    """Per-solve |F_a - F_b| / N_ion and int |n_a - n_b| / int n_b."""
     import numpy as np
-    import torch
-    from paper_2601_23002_amd import skx
-    from paper_2601_23002_amd import workloads as W
-    count = args.count or 256
-    systems = W.config_ensemble(count)
+    e, d = [], []
+    for ra, na, rb, nb, s in zip(res_a, rho_a, res_b, rho_b, systems):
+        e.append(abs(ra["energy"]["free_energy"] - rb["energy"]["free_energy"]) / len(s.zval))
+        d.append(float(np.sum(np.abs(na - nb)) / np.sum(nb)))
+    return e, d
+
+
+class PassAccount:
+    """Algorithmic bytes per pass over the evaluations of batched solves."""
+
+    def __init__(self):
+        self.bytes = {"passA": 0.0, "passB": 0.0, "passC": 0.0}
+        self.evals = {"fp32": 0, "fp64": 0}
+
+    def add(self, results, systems):
+        for r, s in zip(results, systems):
+            nf = fields_count(s)
+            e32, e64 = r["fp32_evals"], r["evals"] - r["fp32_evals"]
+            self.evals["fp32"] += e32
+            self.evals["fp64"] += e64
+            for ne, b in ((e32, 4), (e64, 8)):
+                if ne <= 0:
+                    continue
+                first = pass_bytes(s, b, nf, bool(s.terms & 32), False)
+                trial = pass_bytes(s, b, nf, bool(s.terms & 32), True)
+                for k, f, t in zip(("passA", "passB", "passC"), first, trial):
+                    self.bytes[k] += f + (ne - 1) * t
+
+
+# pass A of the library is two kernels (the pointwise kernel and the
+# transform); the roofline takes their summed launch times
+PASS_TIMERS = {"passA": ("point", "passA"), "passB": ("passB",), "passC": ("passC",)}
+
+
+def batched_leg(args, skx, torch, systems, label, timed_steps, want_roofline):
+    """Mixed-precision batched solves of `systems` (the timed steps), the
+    same without events and from graphs, and plain FP64 on the same
+    contexts. Returns a dict with the numbers and the contexts/densities."""
+    import numpy as np
     dev = torch.device("cuda:0")
-    res = {}
-    for name, prec in (("fp64", skx.FP64), ("mixed", skx.MIXED)):
-        print(f"ensemble {name}: set-up of {count} solves", file=sys.stderr, flush=True)
-        ctxs = [skx.Context(0).setup(s, precision=prec) for s in systems]
-        rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
-        kw = dict(gtol=args.gtol, max_iter=args.fp64_max_iter if prec == skx.FP64 else 3000,
-                  m=5, fp32_switch_gtol=1e-5)
-        skx.run_batch(ctxs[:8], rhos[:8], **kw)          # warm-up (kernels, tables)
+    print(f"{label}: set-up of {len(systems)} solves", file=sys.stderr, flush=True)
+    ctxs = [skx.Context(0).setup(s, precision=skx.MIXED) for s in systems]
+    rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
+
+    def step(max_iter=3000):
+        return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=max_iter, m=5,
+                             fp32_switch_gtol=args.switch_gtol)
+
+    def work(res):
+        return sum(r["evals"] * s.M for r, s in zip(res, systems))
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    # one untimed step with every pass timed: per-pass times, dominant pass
+    skx.profile_reset()
+    skx.profile_mask(None)
+    skx.profile_enable(True)
+    step()
+    torch.cuda.synchronize()
+    skx.profile_enable(False)
+    prof_all = skx.profile_read()
+    pass_ms = {k: sum(prof_all[t][0] for t in v) for k, v in PASS_TIMERS.items()}
+    dom = max(pass_ms, key=pass_ms.get)
+    # timed steps: only the dominant pass's kernels carry events
+    acct = PassAccount()
+    skx.profile_reset()
+    skx.profile_mask(list(PASS_TIMERS[dom]))
+    skx.profile_enable(True)
+    total = 0
+    results = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(timed_steps):
+        results = step()
+        total += work(results)
+        acct.add(results, systems)
+        print(f"{label} step {it}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    skx.profile_enable(False)
+    skx.profile_mask(None)
+    prof = skx.profile_read()
+    out = {"value": total / wall, "ms_per_step": wall / timed_steps * 1e3, "steps": timed_steps,
+           "evals": acct.evals,
+           "passes_ms_profiled_step": {k: round(v[0], 3) for k, v in prof_all.items() if v[1] > 0},
+           "iters_mixed_p50_max": [float(np.median([r["iters"] for r in results])),
+                                   max(r["iters"] for r in results)],
+           "status_mixed": sorted(set(r["status"] for r in results))}
+    if want_roofline:
+        ms = sum(prof[t][0] for t in PASS_TIMERS[dom])
+        launches = max(prof[t][1] for t in PASS_TIMERS[dom])
+        avg_s = ms / 1e3 / max(1, launches)
+        bpl = acct.bytes[dom] / max(1, launches)
+        achieved = bpl / avg_s / 1e9
+        traffic = measured_traffic(dom)
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None if traffic is None else round(traffic),
+                           "kernel": dom, "kernels": list(PASS_TIMERS[dom]),
+                           "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                           "bytes_per_launch": round(bpl)}
+        # every pass of the evaluation against the same byte model (its
+        # launches of the profiled step, all passes timed)
+        per = {}
+        for k, v in PASS_TIMERS.items():
+            msk = sum(prof_all[t][0] for t in v)
+            nl = max(prof_all[t][1] for t in v)
+            if nl > 0 and msk > 0:
+                per[k] = round(acct.bytes[k] / timed_steps / nl / (msk / 1e3 / nl) / 1e9 / HBM_PEAK_GBS, 4)
+        out["frac_by_pass_profiled_step"] = per
+
+    def extra(graphs):
+        old = skx.set_graphs(graphs)
+        w = 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.extra_steps):
+            w += work(step())
+        torch.cuda.synchronize()
+        skx.set_graphs(old)
+        return w / (time.perf_counter() - t), (time.perf_counter() - t) / args.extra_steps * 1e3
+    if args.extra_steps > 0:
+        out["value_no_events"], out["ms_per_step_no_events"] = extra(False)
+        out["value_graphs"], out["ms_per_step_graphs"] = extra(True)
+    mixed_res = results
+    mixed_rho = [r.cpu().numpy() for r in rhos]
+    if not args.no_fp64:
+        print(f"{label}: plain FP64", file=sys.stderr, flush=True)
+        for c, s in zip(ctxs, systems):
+            c.set_functional(s.T, s.beta, s.alpha, s.terms, s.xc, skx.FP64)
+        step(args.fp64_max_iter)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = skx.run_batch(ctxs, rhos, **kw)
+        res64 = step(args.fp64_max_iter)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        work = sum(x["evals"] * s.M for x, s in zip(r, systems))
-        res[name] = dict(value=work / dt, seconds=dt, r=r,
-                         rho=[x.cpu().numpy() for x in rhos])
-        print(f"ensemble {name}: {dt:.3f} s", file=sys.stderr, flush=True)
-        for c in ctxs:
-            c.close()
-        del ctxs, rhos
-        torch.cuda.empty_cache()
-    err = [abs(a["energy"]["free_energy"] - b["energy"]["free_energy"]) / len(s.zval)
-           for a, b, s in zip(res["mixed"]["r"], res["fp64"]["r"], systems)]
-    derr = [float(np.sum(np.abs(a - b)) / np.sum(b))
-            for a, b in zip(res["mixed"]["rho"], res["fp64"]["rho"])]
+        t64 = time.perf_counter() - t0
+        rho64 = [r.cpu().numpy() for r in rhos]
+        err, derr = solve_errors(mixed_res, mixed_rho, res64, rho64, systems)
+        out["fp64_value"] = work(res64) / t64
+        out["fp64_ms_per_step"] = t64 * 1e3
+        out["speedup_vs_fp64"] = out["value"] / out["fp64_value"]
+        ms_mixed = out.get("ms_per_step_no_events", out["ms_per_step"])
+        out["time_speedup_vs_fp64"] = t64 * 1e3 / ms_mixed
+        out["max_err_vs_fp64_gpu_ha_per_atom"] = max(err)
+        out["max_rel_density_err_vs_fp64_gpu"] = max(derr)
+        out["status_fp64"] = sorted(set(r["status"] for r in res64))
+        # back to the mixed solution in the densities handed on
+        for c, s in zip(ctxs, systems):
+            c.set_functional(s.T, s.beta, s.alpha, s.terms, s.xc, skx.MIXED)
+        for r, n in zip(rhos, mixed_rho):
+            r.copy_(torch.from_numpy(n))
+    return out, ctxs, rhos, mixed_res
+
+
+def ensemble_leg(args, skx, W, torch):
+    systems = W.config_ensemble(args.count)
+    for s in systems:
+        s.xc = xc_for(W, s)
+    out, ctxs, rhos, _ = batched_leg(args, skx, torch, systems, "ensemble", args.steps, True)
     sizes = sorted({s.n[0] for s in systems})
-    out = {"metric": "grid-pt functional evals/s, batched+mixed vs plain FP64 @1e-6 Ha/atom",
-           "value": res["mixed"]["value"], "unit": "grid-pt evals/s", "n_gpus": 1,
-           "steps": 1, "warmup": 1, "ms_per_step": res["mixed"]["seconds"] * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": f"ensemble: {count} thermal-like snapshots, 16-256 Z=1/Z=4 ions, "
-                                  f"grids {sizes[0]}^3-{sizes[-1]}^3, one batch",
-                      "global_batch": count, "parallelism": "batch"},
-           "fp64_value": res["fp64"]["value"],
-           "speedup_vs_fp64": res["mixed"]["value"] / res["fp64"]["value"],
-           "time_speedup_vs_fp64": res["fp64"]["seconds"] / res["mixed"]["seconds"],
-           "max_err_ha_per_atom": max(err), "max_rel_density_err": max(derr),
-           "status_mixed": sorted(set(x["status"] for x in res["mixed"]["r"])),
-           "status_fp64": sorted(set(x["status"] for x in res["fp64"]["r"])),
-           "iters_mixed_p50_max": [float(np.median([x["iters"] for x in res["mixed"]["r"]])),
-                                   max(x["iters"] for x in res["mixed"]["r"])],
-           "not_converged_mixed": [dict(i=i, N=len(s.zval), Z=float(s.zval[0]), n=s.n[0],
-                                        iters=x["iters"], fp32_iters=x["fp32_iters"],
-                                        gnorm=x["gnorm"], resets=x["resets"])
-                                   for i, (x, s) in enumerate(zip(res["mixed"]["r"], systems))
-                                   if x["status"] != 0][:12],
-           "not_converged_fp64": [dict(i=i, iters=x["iters"], gnorm=x["gnorm"])
-                                  for i, x in enumerate(res["fp64"]["r"]) if x["status"] != 0][:12]}
-    print(json.dumps(out))
+    out["config"] = {
+        "workload": f"ensemble: {len(systems)} thermal-like snapshots, 16-256 Z=1 (rs 2, T 1 Ha) / "
+                    f"Z=4 (rs 1.5, T 4 Ha) ions, grids {sizes[0]}^3-{sizes[-1]}^3, one batch, "
+                    f"FP32 to |r|<{args.switch_gtol:g} then FP64 to |r|<{args.gtol:g}; PZ81 C1-joined "
+                    "for the Z=4 snapshots, published fit for Z=1",
+        "global_batch": len(systems), "grids": f"{sizes[0]}-{sizes[-1]}", "parallelism": "batch"}
+    for c in ctxs:
+        c.close()
+    del ctxs, rhos
+    torch.cuda.empty_cache()
+    return out, systems
 
 
-def run_serve(args):
+def scan_leg(args, skx, W, torch):
+    import numpy as np
+    systems = W.config_scan(64)
+    for s in systems:
+        s.xc = xc_for(W, s)
+    out, ctxs, rhos, res = batched_leg(args, skx, torch, systems, "scan", args.steps, True)
+    out["config"] = {"workload": "scan: 9 solves, 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha, "
+                                 "64^3, batched; PZ81 C1-joined at rs 1, published fit at rs 2, 4",
+                     "global_batch": len(systems), "grid": 64}
+    out["radix_order_64"] = {"fp32": skx.radix_order(64, skx.FP32),
+                             "fp64": skx.radix_order(64, skx.FP64)}
+    out["iters_mixed"] = [r["iters"] for r in res]
+    out["status"] = [r["status"] for r in res]
+    # the mixed results against the oracle's converged minima (tests/golden)
+    errs = {}
+    for seed in (2, 5, 8):
+        path = os.path.join(ROOT, "tests", "golden", f"minima_scan{seed}.npz")
+        if not os.path.exists(path):
+            continue
+        z = np.load(path)
+        keys = [str(k) for k in z["keys"]]
+        F_ref = float(z["energy"][keys.index("free_energy")])
+        i = seed - 2
+        s = systems[i]
+        if int(z["info"][4]) != s.xc:
+            continue
+        n = rhos[i].cpu().numpy()
+        n_ref = z["n"].astype(np.float64)
+        errs[s.name] = {"ha_per_atom": abs(res[i]["energy"]["free_energy"] - F_ref) / len(s.zval),
+                        "rel_density": float(np.sum(np.abs(n - n_ref)) / np.sum(n_ref))}
+    out["err_vs_oracle_minimum"] = errs
+    return out, systems, ctxs, rhos
+
+
+def serve_leg(args, skx, W):
     """Poisson request stream through the continuous-batching engine, replayed
     in real time on the engine clock; latency = completion - arrival."""
     import numpy as np
-    from paper_2601_23002_amd import skx
-    from paper_2601_23002_amd import workloads as W
-    count = args.count or 200
+    count = args.serve_count
     reqs = W.config_stream(count=count, rate=args.rate, nmax=192, nions_max=1024)
+    for _, s in reqs:
+        s.xc = W.XC_PZ81_C1
 
     def replay(rate_scale, label):
         eng = skx.Engine(0, hbm_budget=96 << 30, max_slots=64)
         t0 = eng.clock()
-        arrive = {}
-        sizes = {}
+        arrive, sizes = {}, {}
         lat, work = [], 0
-        i = 0
+        i = done = shown = 0
         busy = 0.0
-        done = 0
-        shown = 0
         while done < len(reqs):
             now = eng.clock() - t0
             while i < len(reqs) and reqs[i][0] * rate_scale <= now:
@@ -373,7 +552,7 @@ def run_serve(args):
                 done += 1
             if done // 50 > shown:
                 shown = done // 50
-                print(f"{label}: {done}/{len(reqs)} done", file=sys.stderr, flush=True)
+                print(f"serve {label}: {done}/{len(reqs)} done", file=sys.stderr, flush=True)
         wall = eng.clock() - t0
         eng.close()
         p50, p99 = np.percentile(lat, [50, 99])
@@ -382,21 +561,14 @@ def run_serve(args):
                     utilisation=busy / wall)
 
     first = replay(1.0, "offered")
-    # if the offered rate exceeds what the device serves, replay at 70% of the
-    # served rate to report latency at a sustainable load
     sus = None
     if first["served_rate"] < 0.95 * args.rate:
-        scale = args.rate / (0.7 * first["served_rate"])
-        sus = replay(scale, "sustainable")
-    out = {"metric": "grid-pt functional evals/s, batched+mixed vs plain FP64 @1e-6 Ha/atom; p99 lat",
-           "value": first["value"], "unit": "grid-pt evals/s", "n_gpus": 1, "steps": count,
-           "warmup": 0, "ms_per_step": first["wall_s"] / count * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": f"serve: {count} Poisson requests at {args.rate:g}/s, 16-1024 "
-                                  "ions, rs 1-4, T 0.5-10 Ha, grids 32^3-192^3, mixed precision",
-                      "parallelism": "continuous batching"},
-           "offered": first, "sustainable": sus}
-    print(json.dumps(out))
+        # the offered rate saturates the device: replay at 70% of the served rate
+        sus = replay(args.rate / (0.7 * first["served_rate"]), "sustainable")
+    return {"config": {"workload": f"serve: {count} Poisson requests at {args.rate:g}/s, 16-1024 "
+                                   "ions, rs 1-4, T 0.5-10 Ha, grids 32^3-192^3, mixed precision, "
+                                   "PZ81 C1-joined", "parallelism": "continuous batching"},
+            "offered": first, "sustainable": sus}
 
 
 def main():
@@ -404,7 +576,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEGS:
+            print(json.dumps({"error": f"unknown leg {x}"}))
+            sys.exit(2)
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -420,170 +596,47 @@ def main():
     skx.set_autotune(not args.no_autotune)
     if args.graphs != "default":
         skx.set_graphs(args.graphs == "on")
-    if args.workload == "ensemble":
-        return run_ensemble(args)
-    if args.workload == "serve":
-        return run_serve(args)
 
-    systems = W.config_scan(64)
-    dev = torch.device("cuda:0")
-
-    def make(prec):
-        ctxs = [skx.Context(0).setup(s, precision=prec) for s in systems]
-        rhos = [torch.empty(s.n, dtype=torch.float64, device=dev) for s in systems]
-        return ctxs, rhos
-
-    def step(ctxs, rhos, max_iter=3000):
-        return skx.run_batch(ctxs, rhos, gtol=args.gtol, max_iter=max_iter, m=5,
-                             fp32_switch_gtol=args.switch_gtol)
-
-    def work(res):
-        return sum(r["evals"] * s.M for r, s in zip(res, systems))
-
-    # ---- plain FP64 GPU path (speedup denominator and accuracy reference)
-    fp64 = None
-    if not args.no_fp64:
-        print("fp64 reference solves", file=sys.stderr, flush=True)
-        c64, r64 = make(skx.FP64)
-        step(c64, r64, args.fp64_max_iter)        # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res64 = step(c64, r64, args.fp64_max_iter)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        fp64 = dict(value=work(res64) / t64, seconds=t64,
-                    E=[r["energy"]["free_energy"] for r in res64],
-                    rho=[r.cpu().numpy() for r in r64],
-                    iters=[r["iters"] for r in res64])
-        for c in c64:
+    out = {"metric": "grid-pt functional evals/s, batched+mixed vs plain FP64 @1e-6 Ha/atom; p99 lat",
+           "value": None, "unit": "grid-pt evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic"}
+    ens_systems = None
+    if "ensemble" in legs:
+        ens, ens_systems = ensemble_leg(args, skx, W, torch)
+        out["value"] = ens.pop("value")
+        out["ms_per_step"] = ens.pop("ms_per_step")
+        out["config"] = ens.pop("config")
+        out["roofline"] = ens.pop("roofline")
+        out.update(ens)
+    scan_ctx = None
+    if "scan" in legs:
+        scan, scan_systems, sctx, srho = scan_leg(args, skx, W, torch)
+        scan_ctx = (scan_systems, sctx, srho)
+        if out["value"] is None:             # scan alone: its line is the headline
+            out["value"] = scan.pop("value")
+            out["ms_per_step"] = scan.pop("ms_per_step")
+            out["config"] = scan.pop("config")
+            out["roofline"] = scan.pop("roofline")
+            out.update(scan)
+        else:
+            out["scan"] = scan
+    if "forces" in legs and scan_ctx is not None:
+        f = forces_leg(args, skx, *scan_ctx)
+        out["structure"] = f.pop("structure")
+        out["beta_fit"] = f.pop("beta_fit")
+        out["forces"] = f
+    if scan_ctx is not None:
+        for c in scan_ctx[1]:
             c.close()
-
-    # ---- batched mixed precision (the headline)
-    ctxs, rhos = make(skx.MIXED)
-    for _ in range(args.warmup):
-        step(ctxs, rhos)
-    # one untimed step with every pass carrying HIP events: per-pass times
-    # and the dominant evaluation kernel
-    torch.cuda.synchronize()
-    skx.profile_reset()
-    skx.profile_mask(None)
-    skx.profile_enable(True)
-    step(ctxs, rhos)
-    torch.cuda.synchronize()
-    skx.profile_enable(False)
-    prof_all = skx.profile_read()
-    dom = max(("point", "passA", "passB", "passC"), key=lambda k: prof_all[k][0])
-    # the timed steps: only the dominant kernel's launches carry events
-    torch.cuda.synchronize()
-    skx.profile_reset()
-    skx.profile_mask([dom])
-    skx.profile_enable(True)
-    total_work = 0
-    evals = {"fp32": 0, "fp64": 0}
-    bytes_pass = {"point": 0.0, "passA": 0.0, "passB": 0.0, "passC": 0.0}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = None
-    for it in range(args.steps):
-        results = step(ctxs, rhos)
-        print(f"step {it}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
-        total_work += work(results)
-        for r, s in zip(results, systems):
-            nf = fields_count(s)
-            e32, e64 = r["fp32_evals"], r["evals"] - r["fp32_evals"]
-            evals["fp32"] += e32
-            evals["fp64"] += e64
-            for (ne, b) in ((e32, 4), (e64, 8)):
-                if ne <= 0:
-                    continue
-                p1, a1, b1, c1 = pass_bytes(s, b, nf, True, False)    # first evaluation
-                pT, aT, bT, cT = pass_bytes(s, b, nf, True, True)     # trial evaluations
-                bytes_pass["point"] += p1 + (ne - 1) * pT
-                bytes_pass["passA"] += a1 + (ne - 1) * aT
-                bytes_pass["passB"] += b1 + (ne - 1) * bT
-                bytes_pass["passC"] += c1 + (ne - 1) * cT
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    skx.profile_enable(False)
-    skx.profile_mask(None)
-    prof = skx.profile_read()
-    value = total_work / wall
-
-    # the same steps without any events, and replayed from captured HIP graphs
-    def timed_steps():
-        w = 0
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for it in range(args.steps):
-            w += work(step(ctxs, rhos))
-        torch.cuda.synchronize()
-        return w, time.perf_counter() - t
-    plain_work, wall_plain = timed_steps()
-    old_graphs = skx.set_graphs(True)
-    graph_work, wall_graph = timed_steps()
-    skx.set_graphs(old_graphs)
-    print(f"plain steps: {wall_plain:.3f} s, graph steps: {wall_graph:.3f} s", file=sys.stderr,
-          flush=True)
-    forces_out = None if args.no_forces else forces_leg(args, skx, systems, ctxs, rhos)
-
-    # roofline of the dominant evaluation kernel (its events in the timed steps)
-    ms, launches = prof[dom]
-    avg_s = ms / 1e3 / max(1, launches)
-    achieved = bytes_pass[dom] / max(1, launches) / avg_s / 1e9
-    traffic = measured_traffic(dom)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic),
-            "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-            "bytes_per_launch": round(bytes_pass[dom] / max(1, launches))}
-
-    out = {
-        "metric": "grid-pt functional evals/s, batched+mixed vs plain FP64 @1e-6 Ha/atom; p99 lat",
-        "value": value,
-        "unit": "grid-pt evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "scan: 9 solves, 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha, "
-                               "64^3, batched, FP32 to |r|<%g then FP64 to |r|<%g" % (args.switch_gtol, args.gtol),
-                   "global_batch": len(systems), "grid": 64, "parallelism": "batch"},
-        "roofline": roof,
-        "passes_ms_profiled_step": {k: round(v[0], 3) for k, v in prof_all.items() if v[1] > 0},
-        "value_no_events": plain_work / wall_plain,
-        "ms_per_step_no_events": wall_plain / args.steps * 1e3,
-        "value_graphs": graph_work / wall_graph,
-        "ms_per_step_graphs": wall_graph / args.steps * 1e3,
-        "evals": evals,
-        "radix_order_64": {"fp32": skx.radix_order(64, skx.FP32), "fp64": skx.radix_order(64, skx.FP64)},
-    }
-    if fp64 is not None:
-        err = []
-        rerr = []
-        for i, (r, s) in enumerate(zip(results, systems)):
-            err.append(abs(r["energy"]["free_energy"] - fp64["E"][i]) / len(s.zval))
-            n_m = rhos[i].cpu().numpy()
-            rerr.append(float(np.sum(np.abs(n_m - fp64["rho"][i])) / np.sum(fp64["rho"][i])))
-        out["fp64_value"] = fp64["value"]
-        out["speedup_vs_fp64"] = value / fp64["value"]
-        out["time_speedup_vs_fp64"] = fp64["seconds"] / (wall_plain / args.steps)
-        out["max_err_ha_per_atom"] = max(err)
-        out["max_rel_density_err"] = max(rerr)
-        out["iters_fp64"] = fp64["iters"]
-        out["fp64_max_iter"] = args.fp64_max_iter
-    out["iters_mixed"] = [r["iters"] for r in results]
-    out["status"] = [r["status"] for r in results]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(systems[0])
-    if forces_out is not None:
-        out["structure"] = forces_out.pop("structure")
-        out["beta_fit"] = forces_out.pop("beta_fit")
-        out["forces"] = forces_out
+    if "serve" in legs:
+        out["serve"] = serve_leg(args, skx, W)
+    if not args.no_cpu_baseline and (ens_systems is not None or scan_ctx is not None):
+        if ens_systems is not None:
+            i64 = next(i for i, s in enumerate(ens_systems) if s.n[0] == 64)
+            out["cpu_baseline"] = cpu_baseline(ens_systems[i64], f"ensemble snapshot {i64}")
+        else:
+            out["cpu_baseline"] = cpu_baseline(scan_ctx[0][0], "the first scan system")
     print(json.dumps(out))
 
 

@@ -229,8 +229,9 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
 }
 
 size_t instance_bytes(int n1, int n2, int n3, int prec, int m) {
-  return arena_layout(n1, n2, n3, prec, std::max(m, 1)).total + sizeof(SolveDev) +
-         sizeof(OptState) + 2 * NPREFIX * sizeof(int);
+  return arena_layout(n1, n2, n3, prec, std::max(m, 1)).total +
+         sizeof(SolveDev) * batch_desc_count(1) + sizeof(OptState) +
+         batch_first_count(1) * sizeof(int);
 }
 
 int ensure_instance(skx_ctx *c, int prec, int m) {
@@ -259,9 +260,9 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   hipError_t e = hipMalloc(&I.mem, off);
   if (e != hipSuccess) { I.mem = nullptr; return hip_fail(c, e, "device arena allocation"); }
   hipMemsetAsync(I.mem, 0, off, c->stream);
-  e = hipMalloc((void **)&I.dptr, sizeof(SolveDev));
+  e = hipMalloc((void **)&I.dptr, sizeof(SolveDev) * batch_desc_count(1));
   if (e == hipSuccess) e = hipMalloc((void **)&I.st, sizeof(OptState));
-  if (e == hipSuccess) e = hipMalloc((void **)&I.first, sizeof(int) * 2 * NPREFIX);
+  if (e == hipSuccess) e = hipMalloc((void **)&I.first, sizeof(int) * batch_first_count(1));
   if (e != hipSuccess) { free_instance(I); return hip_fail(c, e, "descriptor allocation"); }
   hipMemsetAsync(I.st, 0, sizeof(OptState), c->stream);
   I.prec = prec;
@@ -321,14 +322,78 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
   h.kappa = c->kappa;
 }
 
-// Prefix sums and grids of a batch; writes `first` (device, 4*(n+1) ints).
+// Length of the compile-time-shaped kernels a solve runs on (0: the
+// runtime-shaped ones): cubic grids of the lengths with such kernels, unless
+// they are switched off, every plane is forced onto the chunked kernels, or
+// the solve is an FFT check.
+int shaped_length(const SolveDev &h) {
+  if (!g_shape_kernels || g_chunk_planes || h.debug) return 0;
+  if (h.n1 != h.n2 || h.n2 != h.n3) return 0;
+  switch (h.n1) {
+    case 48: case 64: case 72: case 80: return h.n1;
+    default: return 0;
+  }
+}
+
+// Pass B's compile-time-shaped kernel needs whole column blocks of the
+// precision's width below the Nyquist column.
+bool shaped_b_ok(int n, int prec) { return (n / 2) % (prec == 0 ? 8 : 16) == 0; }
+
+// Prefix sums of passes A, B, C of one group, its runtime-shaped LDS sizes
+// and kernel choices.
+int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup &g,
+               std::vector<int> &fa, std::vector<int> &fb, std::vector<int> &fc) {
+  const int n = (int)hs.size();
+  fa.assign(n + 1, 0); fb.assign(n + 1, 0); fc.assign(n + 1, 0);
+  size_t la = 0, lb = 0, lc = 0;
+  for (int i = 0; i < n; ++i) {
+    const SolveDev &h = hs[i];
+    fa[i + 1] = fa[i] + h.n1 * h.nf;
+    fb[i + 1] = fb[i] + h.n2 * h.nkb;
+    fc[i + 1] = fc[i] + h.n1;
+    size_t a, b, cc;
+    lds_sizes(h, prec, a, b, cc);
+    lb = std::max(lb, b);
+    if (!(h.big & 1)) la = std::max(la, a);
+    // the forward-only check (debug 1) launches no pass C
+    if (!(h.big & 2) && h.debug != 1) lc = std::max(lc, cc);
+  }
+  if (g.shapeN == 0 && (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX))
+    return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
+  g.nsolve = n;
+  g.gridA = fa[n]; g.gridB = fb[n]; g.gridC = fc[n];
+  // pass C keeps dE/dphi beside the plane in LDS when every solve fits
+  // (FP64: the dE/dphi plane; FP32: that plane and a copy of phi_t), only
+  // while that leaves room for two workgroups per CU: beyond 80 KB the
+  // accumulation in the output buffer was measured faster, e.g. FP64 96^3
+  // pass C 216 -> 167 us
+  size_t lc_acc = 0;
+  for (const SolveDev &h : hs)
+    if (!(h.big & 2))
+      lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
+                                    8 * (size_t)h.n2 * h.n3);
+  g.accC_lds = lc_acc <= 80 * 1024 ? 1 : 0;
+  if (g.accC_lds) lc = std::max(lc, lc_acc);
+  g.ldsA = la; g.ldsB = lb; g.ldsC = lc;
+  g.bigA = g.smallA = g.bigC = g.smallC = 0;
+  for (const SolveDev &h : hs) {
+    ((h.big & 1) ? g.bigA : g.smallA) = 1;
+    ((h.big & 2) ? g.bigC : g.smallC) = 1;
+  }
+  return SKX_OK;
+}
+
+// Descriptors, prefix sums and pass groups of a batch. ddev holds
+// batch_desc_count(n) descriptors (the batch, then the groups' copies),
+// dfirst batch_first_count(n) ints.
 int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s) {
   const int n = (int)hs_in.size();
   // Passes A and C of planes beyond LDS take the chunked kernels, and so do
   // those where the chunked kernel was measured faster on MI355X: FP32
   // pass C from 24 KB planes (80^2) on, FP32 pass A from 80 KB (144^2);
-  // in FP64 the in-LDS kernels are faster wherever they fit.
+  // in FP64 the in-LDS kernels are faster wherever they fit. Solves on the
+  // compile-time-shaped kernels take none.
   std::vector<SolveDev> hs(hs_in);
   for (SolveDev &h : hs) {
     size_t a, b, cc;
@@ -341,72 +406,75 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     // the forward-only check (debug 1) keeps the chunked pass A; the
     // chunked pass C has no check mode
     if (h.debug) h.big &= h.debug == 1 ? 1 : 0;
+    if (shaped_length(h)) h.big = 0;
   }
-  std::vector<int> fa(n + 1), fb(n + 1), fc(n + 1), fv(n + 1), fu(n + 1);
-  fa[0] = fb[0] = fc[0] = fv[0] = fu[0] = 0;
-  size_t la = 0, lb = 0, lc = 0;
+  std::vector<int> fv(n + 1), fu(n + 1);
+  fv[0] = fu[0] = 0;
   for (int i = 0; i < n; ++i) {
-    const SolveDev &h = hs[i];
-    fa[i + 1] = fa[i] + h.n1 * h.nf;
-    fb[i + 1] = fb[i] + h.n2 * h.nkb;
-    fc[i + 1] = fc[i] + h.n1;
-    fv[i + 1] = fv[i] + h.nwg_vec;
-    fu[i + 1] = fu[i] + h.nwg_upd;
-    size_t a, b, cc;
-    lds_sizes(h, prec, a, b, cc);
-    lb = std::max(lb, b);
-    if (!(h.big & 1)) la = std::max(la, a);
-    // the forward-only check (debug 1) launches no pass C
-    if (!(h.big & 2) && h.debug != 1) lc = std::max(lc, cc);
+    fv[i + 1] = fv[i] + hs[i].nwg_vec;
+    fu[i + 1] = fu[i] + hs[i].nwg_upd;
   }
-  if (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX)
-    return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
+  // pass groups: the runtime-shaped solves, then one group per length
+  std::vector<int> keys;
+  for (const SolveDev &h : hs) {
+    const int k = shaped_length(h);
+    if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<SolveDev> part;
   std::vector<int> all;
-  all.insert(all.end(), fa.begin(), fa.end());
-  all.insert(all.end(), fb.begin(), fb.end());
-  all.insert(all.end(), fc.begin(), fc.end());
   all.insert(all.end(), fv.begin(), fv.end());
   all.insert(all.end(), fu.begin(), fu.end());
+  bl.ngroup = (int)keys.size();
+  struct Off { size_t desc, a, b, cc; };
+  std::vector<Off> offs;
+  for (int gi = 0; gi < bl.ngroup; ++gi) {
+    PassGroup &g = bl.grp[gi];
+    g = PassGroup{};
+    g.shapeN = keys[gi];
+    std::vector<SolveDev> sub;
+    for (const SolveDev &h : hs)
+      if (shaped_length(h) == g.shapeN) sub.push_back(h);
+    std::vector<int> fa, fb, fc;
+    int rc = fill_group(c, sub, prec, g, fa, fb, fc);
+    if (rc) return rc;
+    if (g.shapeN)
+      g.shape = (g_shape_kernels & 5) | ((g_shape_kernels & 2) && shaped_b_ok(g.shapeN, prec) ? 2 : 0);
+    Off o;
+    o.desc = part.size();
+    part.insert(part.end(), sub.begin(), sub.end());
+    o.a = all.size(); all.insert(all.end(), fa.begin(), fa.end());
+    o.b = all.size(); all.insert(all.end(), fb.begin(), fb.end());
+    o.cc = all.size(); all.insert(all.end(), fc.begin(), fc.end());
+    offs.push_back(o);
+  }
+  if (all.size() > batch_first_count(n) || part.size() != (size_t)n)
+    return fail(c, SKX_E_DEVICE, "batch layout exceeds its buffers");
   hipError_t e = hipMemcpyAsync(dfirst, all.data(), sizeof(int) * all.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ddev, hs.data(), sizeof(SolveDev) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ddev + n, part.data(), sizeof(SolveDev) * n, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "descriptor upload");
+  for (int gi = 0; gi < bl.ngroup; ++gi) {
+    PassGroup &g = bl.grp[gi];
+    g.dev = ddev + n + offs[gi].desc;
+    g.firstA = dfirst + offs[gi].a;
+    g.firstB = dfirst + offs[gi].b;
+    g.firstC = dfirst + offs[gi].cc;
+  }
   const DeviceRes &R = g_res[c->device];
   bl.dev = ddev;
   bl.nsolve = n;
   bl.prec = prec;
   bl.twbank = R.twbank;
   bl.fd = R.fd;
-  bl.gridA = fa[n]; bl.gridB = fb[n]; bl.gridC = fc[n]; bl.gridV = fv[n]; bl.gridU = fu[n];
-  bl.firstA = dfirst;
-  bl.firstB = dfirst + (n + 1);
-  bl.firstC = dfirst + 2 * (n + 1);
-  bl.firstV = dfirst + 3 * (n + 1);
-  bl.firstU = dfirst + 4 * (n + 1);
-  // pass C keeps dE/dphi beside the plane in LDS when every solve fits
-  size_t lc_acc = 0;
-  // (FP64: the dE/dphi plane; FP32: that plane and a copy of phi_t)
-  for (const SolveDev &h : hs)
-    if (!(h.big & 2))
-      lc_acc = std::max(lc_acc, (prec == 0 ? 16 : 8) * ((size_t)h.n2 * h.nh + h.n2 + h.n3) +
-                                    8 * (size_t)h.n2 * h.n3);
-  // (only while that leaves room for two workgroups per CU: beyond 80 KB the
-  // accumulation in the output buffer was measured faster, e.g. FP64 96^3
-  // pass C 216 -> 167 us)
-  bl.accC_lds = lc_acc <= 80 * 1024 ? 1 : 0;
-  if (bl.accC_lds) lc = std::max(lc, lc_acc);
-  bl.ldsA = la; bl.ldsB = lb; bl.ldsC = lc;
+  bl.gridV = fv[n]; bl.gridU = fu[n];
+  bl.firstV = dfirst;
+  bl.firstU = dfirst + (n + 1);
   bl.mh = 1;
   for (const SolveDev &h : hs) bl.mh = std::max(bl.mh, std::min(h.mh, MMAX));
-  bl.bigA = bl.smallA = bl.bigC = bl.smallC = 0;
-  for (const SolveDev &h : hs) {
-    ((h.big & 1) ? bl.bigA : bl.smallA) = 1;
-    ((h.big & 2) ? bl.bigC : bl.smallC) = 1;
-  }
-  bl.shape = g_shape_kernels;
-  for (const SolveDev &h : hs)
-    if (h.n1 != 64 || h.n2 != 64 || h.n3 != 64 || h.debug || h.big) bl.shape = 0;
   return SKX_OK;
 }
 
@@ -1316,8 +1384,9 @@ int skx_fft_check(skx_ctx *c, const double *in_host, double *out_host, double *s
     if (e != hipSuccess) return hip_fail(c, e, "spectrum copy");
   }
   hs[0].debug = 2;
-  e = hipMemcpyAsync(I.dptr, hs.data(), sizeof(SolveDev), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_eval(I.bl, s, 6);
+  rc = build_batch(c, hs, 0, I.dptr, I.first, I.bl, s);
+  if (rc) return rc;
+  e = launch_eval(I.bl, s, 6);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out_host, h.grad, sizeof(double) * M, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1818,8 +1887,9 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   int *dfirst = nullptr;
   OptState *dstage = nullptr;           // packed states (upload and readback)
   OptState **dsptr = nullptr;           // each solve's state buffer
-  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * NPREFIX * (nctx + 1), s);
+  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * batch_desc_count(nctx), s);
+  if (e == hipSuccess)
+    e = hipMallocAsync((void **)&dfirst, sizeof(int) * batch_first_count(nctx), s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&dstage, sizeof(OptState) * nctx, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&dsptr, sizeof(OptState *) * nctx, s);
   if (e != hipSuccess) return hip_fail(c0, e, "batch descriptors");
@@ -2044,8 +2114,9 @@ extern "C" int skx_bench_eval(skx_ctx **ctxs, int nctx, int reps, double *ms_out
   }
   SolveDev *ddev = nullptr;
   int *dfirst = nullptr;
-  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * nctx, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&dfirst, sizeof(int) * NPREFIX * (nctx + 1), s);
+  hipError_t e = hipMallocAsync((void **)&ddev, sizeof(SolveDev) * batch_desc_count(nctx), s);
+  if (e == hipSuccess)
+    e = hipMallocAsync((void **)&dfirst, sizeof(int) * batch_first_count(nctx), s);
   if (e != hipSuccess) return hip_fail(c0, e, "bench descriptors");
   BatchLaunch bl{};
   int rc = build_batch(c0, hs, prec, ddev, dfirst, bl, s);

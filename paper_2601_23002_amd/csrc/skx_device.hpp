@@ -451,16 +451,72 @@ __device__ __forceinline__ void cstages(V *buf, const V *tw, int lane) {
   cstages<V, N, NS * R0, ES, TS, SLOTS, TFAST, INV, RS...>(buf, tw, lane);
 }
 
-// Radix orders of the compile-time lengths (first radix even: the real
-// transforms fold their Nyquist terms into the first stage).
-template <int N> struct CRad;
-template <> struct CRad<64> {
-  static constexpr int R0 = 8, R1 = 8;
-  // LDS row pitch (complex values) of a 64-column half-spectrum plane: 36
-  // spreads both the column transforms (8 adjacent columns of 8 rows) and
-  // the row-pair transforms (8 adjacent elements of 8 pairs) evenly over
-  // the LDS banks in FP32 and FP64.
-  static constexpr int PL = 36;
+// Compile-time radix lists and the operations the shaped kernels need on
+// them: first, last, all but the first, all but the last, and running the
+// stages of a list from a given span.
+template <int... Rs> struct RList {};
+template <typename L> struct RFirst;
+template <int R0, int... Rs> struct RFirst<RList<R0, Rs...>> { static constexpr int value = R0; };
+template <typename L> struct RLast;
+template <int R0> struct RLast<RList<R0>> { static constexpr int value = R0; };
+template <int R0, int R1, int... Rs>
+struct RLast<RList<R0, R1, Rs...>> { static constexpr int value = RLast<RList<R1, Rs...>>::value; };
+template <typename L> struct RRest;
+template <int R0, int... Rs> struct RRest<RList<R0, Rs...>> { typedef RList<Rs...> T; };
+template <int R, typename L> struct RPrepend;
+template <int R, int... Rs> struct RPrepend<R, RList<Rs...>> { typedef RList<R, Rs...> T; };
+template <typename L> struct RInit;
+template <int R0> struct RInit<RList<R0>> { typedef RList<> T; };
+template <int R0, int R1, int... Rs> struct RInit<RList<R0, R1, Rs...>> {
+  typedef typename RPrepend<R0, typename RInit<RList<R1, Rs...>>::T>::T T;
+};
+template <typename L> struct RProd;
+template <> struct RProd<RList<>> { static constexpr int value = 1; };
+template <int R0, int... Rs> struct RProd<RList<R0, Rs...>> {
+  static constexpr int value = R0 * RProd<RList<Rs...>>::value;
+};
+template <typename L> struct CStages;
+template <int... Rs> struct CStages<RList<Rs...>> {
+  template <typename V, int N, int NS, int ES, int TS, int SLOTS, bool TFAST, bool INV>
+  __device__ __forceinline__ static void run(V *buf, const V *tw, int lane) {
+    cstages<V, N, NS, ES, TS, SLOTS, TFAST, INV, Rs...>(buf, tw, lane);
+  }
+};
+
+// Cubic grids with compile-time-shaped kernels. Per length N:
+//   L   radix order (the same along x, y and z). The first radix is even:
+//       the real transforms fold their Nyquist terms into the first stage.
+//   NW  wavefronts per workgroup of passes A and C; they split the N/2 row
+//       pairs (z transforms) and the N/2 columns (y transforms) evenly.
+//   PL  LDS row pitch (complex values) of a half-spectrum plane,
+//       >= N/2 + 1; N/2 + 4 spreads the column transforms (adjacent
+//       columns of rows one pitch apart) and the row-pair transforms over
+//       the LDS banks.
+// 64 holds the scan workload; 48, 72 and 80 are the grids most of the
+// ensemble's and the serving stream's points fall on.
+template <int N> struct CShape;
+template <> struct CShape<48> { typedef RList<8, 3, 2> L; static constexpr int NW = 4, PL = 28; };
+template <> struct CShape<64> { typedef RList<8, 8> L; static constexpr int NW = 4, PL = 36; };
+template <> struct CShape<72> { typedef RList<8, 3, 3> L; static constexpr int NW = 6, PL = 40; };
+template <> struct CShape<80> { typedef RList<8, 5, 2> L; static constexpr int NW = 8, PL = 44; };
+// derived per-length constants
+template <int N> struct CS {
+  typedef typename CShape<N>::L L;
+  static constexpr int NW = CShape<N>::NW, NT = 64 * NW, PL = CShape<N>::PL, C = N / 2;
+  static constexpr int R0 = RFirst<L>::value;      // first stage
+  static constexpr int RL = RLast<L>::value;       // last stage
+  static constexpr int NSL = N / RL;               // span of the last stage
+  typedef typename RRest<L>::T Rest;               // stages after the first
+  typedef typename RInit<L>::T Init;               // stages before the last
+  typedef typename RInit<Rest>::T Mid;             // stages between first and last
+  static constexpr int ZP = N / 2 / NW;            // row pairs per wavefront
+  static constexpr int YC = C / NW;                // y columns per wavefront
+  static_assert(RProd<L>::value == N, "radix order must multiply to N");
+  static_assert(R0 % 2 == 0, "even first radix");
+  static_assert(ZP * NW * 2 == N && YC * NW == C, "even split over the wavefronts");
+  static_assert(PL >= C + 1 && 2 * PL >= N, "LDS row pitch");
+  // LDS of passes A and C: the plane and both twiddle tables
+  static constexpr size_t lds_plane(size_t v) { return v * (size_t)(N * PL + 2 * N); }
 };
 
 // ---------------------------------------------------------------------------

@@ -237,8 +237,8 @@ int rebuild(skx_engine *e, Group &g, int prec) {
     if (g.dphase) hipFree(g.dphase);
     g.ddev = nullptr; g.dfirst = nullptr; g.dphase = nullptr; g.cap = 0;
     const int cap = std::max(n, 2 * g.cap + 8);
-    hipError_t he = hipMalloc((void **)&g.ddev, sizeof(SolveDev) * cap);
-    if (he == hipSuccess) he = hipMalloc((void **)&g.dfirst, sizeof(int) * NPREFIX * (cap + 1));
+    hipError_t he = hipMalloc((void **)&g.ddev, sizeof(SolveDev) * batch_desc_count(cap));
+    if (he == hipSuccess) he = hipMalloc((void **)&g.dfirst, sizeof(int) * batch_first_count(cap));
     if (he == hipSuccess) he = hipMalloc((void **)&g.dphase, sizeof(int) * cap);
     if (he != hipSuccess) return eng_fail(e, SKX_E_NOMEM, "batch descriptor allocation");
     g.cap = cap;

@@ -140,21 +140,41 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
+constexpr int MAX_GROUPS = 5;      // pass launch groups: runtime-shaped + 4 compile-time lengths
+
+// The solves of a batch whose evaluation passes run on one kernel family:
+// the compile-time-shaped kernels of one cubic length, or the
+// runtime-shaped (and chunked) kernels. Each group has its own copies of
+// its solves' descriptors and prefix sums of its pass work items, so every
+// launch covers only the solves it computes.
+struct PassGroup {
+  SolveDev *dev;                   // device array of the group's descriptors
+  int nsolve;
+  int shapeN;                      // 0: runtime-shaped; else the compile-time length
+  int shape;                       // passes (1 A, 2 B, 4 C) on the compile-time-shaped kernels
+  int gridA, gridB, gridC;         // work items (workgroups) of the runtime-shaped passes
+  const int *firstA, *firstB, *firstC;  // device prefix sums (nsolve+1)
+  size_t ldsA, ldsB, ldsC;
+  int accC_lds;                    // pass C accumulates in LDS (else in the output)
+  int bigA, smallA, bigC, smallC;  // solves on the chunked / in-LDS kernels of passes A, C
+};
+
 struct BatchLaunch {
-  SolveDev *dev;                   // device array of descriptors
+  SolveDev *dev;                   // device array of descriptors (every solve)
   int nsolve;
   int prec;                        // 0 fp64, 1 fp32
   const double *twbank;
   FDTable fd;
-  int gridA, gridB, gridC, gridV, gridU;  // total workgroups per kernel
-  const int *firstA, *firstB, *firstC, *firstV, *firstU;  // device prefix sums (nsolve+1)
-  size_t ldsA, ldsB, ldsC;
-  int accC_lds;                    // pass C accumulates in LDS (else in the output)
+  int gridV, gridU;                // workgroups of the vector and update kernels
+  const int *firstV, *firstU;      // device prefix sums (nsolve+1)
   int mh;                          // largest history length of the batch (1..MMAX)
-  int bigA, smallA, bigC, smallC;  // solves on the chunked / in-LDS kernels of passes A, C
-  int shape;                       // passes (1 A, 2 B, 4 C) that run their kernels for
-                                   // 64 x 64 x 64 grids (every solve has that grid)
+  int ngroup;
+  PassGroup grp[MAX_GROUPS];
 };
+// Device descriptors and prefix-sum ints a batch of n solves needs (the
+// full batch plus the copies of its pass groups).
+inline size_t batch_desc_count(int n) { return 2 * (size_t)n; }
+inline size_t batch_first_count(int n) { return (size_t)(NPREFIX + 3) * (size_t)(n + MAX_GROUPS + 1); }
 // Start/stop events for the next kernel launch while its pass is being timed
 // (defined with the profiler), else false.
 bool kernel_events(hipEvent_t *start, hipEvent_t *stop);

@@ -98,7 +98,15 @@ template <int MODE> __device__ __forceinline__ bool active_phase(int ph) {
 }
 
 // Complex values per lane the wavefront-owned transforms may stage.
-template <typename R> struct WaveV { static constexpr int value = sizeof(R) == 4 ? 16 : 8; };
+#ifndef SKX_WAVEV_F32
+#define SKX_WAVEV_F32 16
+#endif
+#ifndef SKX_WAVEV_F64
+#define SKX_WAVEV_F64 8
+#endif
+template <typename R> struct WaveV {
+  static constexpr int value = sizeof(R) == 4 ? SKX_WAVEV_F32 : SKX_WAVEV_F64;
+};
 
 // Real-to-complex split of the row pairs [lo, hi) after their z transform,
 // by the wavefront that owns them (X_k of the pair 2p + i 2p+1 becomes the
@@ -1225,25 +1233,25 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
 }
 
 // ---------------------------------------------------------------------------
-// Pass A on planes of a shape fixed at compile time (N2 x N3), one workgroup
-// of four wavefronts per (x-plane, field) (MODE_PREC: per x-plane, the
-// residual field). Every wavefront takes N2/8 row pairs: its first z stage
-// reads x_{2p} + i x_{2p+1} straight from the pointwise arrays, the last
-// one leaves the row pair's spectrum in LDS, which is then split into the
-// two half spectra with the real DC and Nyquist values of each row folded
-// into its column 0. After a barrier every wavefront takes N3/8 of the N3/2
-// columns for the y transform, whose outputs go from registers to HBM; the
-// folded column is unfolded into the DC and Nyquist columns on the way.
+// Pass A on cubic grids of a length N fixed at compile time (radix order,
+// wavefront count and LDS pitch from CShape<N>), one workgroup of NW
+// wavefronts per (x-plane, field) (MODE_PREC: per x-plane, the residual
+// field). Every wavefront takes N/(2 NW) row pairs: its first z stage reads
+// x_{2p} + i x_{2p+1} straight from the pointwise arrays, the remaining
+// stages run in LDS and leave the row pair's spectrum there, which is then
+// split into the two half spectra with the real DC and Nyquist values of
+// each row folded into its column 0. After a barrier every wavefront takes
+// N/(2 NW) of the N/2 columns for the y transform, whose last stage goes
+// from registers to HBM; the folded column is unfolded into the DC and
+// Nyquist columns on the way.
 // ---------------------------------------------------------------------------
-template <typename R, int N2, int N3, int MODE>
-__global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first, int nsolve,
-                                                int grid, const double *twbank) {
+template <typename R, int N, int MODE>
+__global__ __launch_bounds__(CS<N>::NT) void k_passAf(SolveDev *dev, const int *first, int nsolve,
+                                                      int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
-  constexpr int NT = 256, NW = 4;
-  constexpr int C = N3 / 2, PL = CRad<N3>::PL, YC = C / NW, ZP = N2 / 2 / NW;
-  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
-  constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
-  static_assert(Y0 * Y1 == N2 && R0 * R1 == N3 && R0 % 2 == 0, "two stages per direction");
+  typedef CS<N> K;
+  constexpr int NT = K::NT, C = K::C, PL = K::PL, YC = K::YC, ZP = K::ZP;
+  constexpr int R0 = K::R0, YL = K::RL, NSL = K::NSL;
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
@@ -1258,21 +1266,21 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   const int plane = local / nf;
   const int fb = MODE == MODE_EVAL ? nth_field(S.fields, local - plane * nf) : 0;
   V *buf = reinterpret_cast<V *>(smem);
-  V *tw2 = buf + N2 * PL;
-  V *tw3 = tw2 + N2;
+  V *tw2 = buf + N * PL;
+  V *tw3 = tw2 + N;
   // both twiddle tables (tw3 follows tw2) are fetched into registers here
   // and written to LDS after the first z stage, so their latency overlaps
   // that of the stage's HBM loads
-  static_assert(N2 + N3 <= NT, "one twiddle per thread");
-  const bool has_tw = tid < N2 + N3;
+  static_assert(2 * N <= NT, "one twiddle per thread");
+  const bool has_tw = tid < 2 * N;
   double2 twv = make_double2(0.0, 0.0);
-  if (has_tw) twv = ldg(gptr<double2>(twbank) + (tid < N2 ? S.p2.tw + tid : S.p3.tw + tid - N2));
+  if (has_tw) twv = ldg(gptr<double2>(twbank) + (tid < N ? S.p2.tw + tid : S.p3.tw + tid - N));
   const R invM = (R)(1.0 / (double)S.M);
-  const size_t pbase = (size_t)plane * N2 * N3;
+  const size_t pbase = (size_t)plane * N * N;
   V *zb = buf + wave * ZP * 2 * PL;
   {
     // first z stage, inputs from HBM: element e = j + NB r of pair p
-    typedef CMap<N3, R0, ZP, false> M;
+    typedef CMap<N, R0, ZP, false> M;
     V v[M::MB][R0];
     const SKX_G R *pt = gptr<R>(S.phi2[1 - par]) + pbase;
     const SKX_G R *fa = gptr<R>(S.npa) + pbase;
@@ -1285,7 +1293,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
       if (M::ok(b)) {
-        const int o = 2 * (wave * ZP + M::t(b)) * N3 + M::j(b);
+        const int o = 2 * (wave * ZP + M::t(b)) * N + M::j(b);
         R x[2][R0];
         if (MODE == MODE_EVAL) {
           R pv[2][R0], fv[2][R0];
@@ -1293,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-              const int q = o + h * N3 + M::NB * r;
+              const int q = o + h * N + M::NB * r;
               if (need_p) pv[h][r] = pt[q];
               if (need_fa) fv[h][r] = fa[q];
             }
@@ -1310,7 +1318,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-              const int q = o + h * N3 + M::NB * r;
+              const int q = o + h * N + M::NB * r;
               gv[h][r] = gr[q];
               pv[h][r] = pt[q];
             }
@@ -1319,7 +1327,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
               x[h][r] = gv[h][r] - mu2 * pv[h][r];
-              rt[o + h * N3 + M::NB * r] = x[h][r];
+              rt[o + h * N + M::NB * r] = x[h][r];
             }
         }
 #pragma unroll
@@ -1336,7 +1344,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
     if (has_tw) { V t; t.x = twv.x; t.y = twv.y; tw2[tid] = t; }
     __syncthreads();
   }
-  cstage<V, N3, R1, R0, 1, 2 * PL, ZP, false, false>(zb, tw3, lane);
+  CStages<typename K::Rest>::template run<V, N, R0, 1, 2 * PL, ZP, false, false>(zb, tw3, lane);
   {
     // split X_k of the pair into the rows' half spectra; column 0 of each
     // row takes (DC, Nyquist), both real
@@ -1349,7 +1357,7 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
         const int p = e / C, k = e % C;
         const V *row = zb + 2 * p * PL;
         const V X = row[k];
-        const V Xm = row[k == 0 ? C : N3 - k];
+        const V Xm = row[k == 0 ? C : N - k];
         if (k == 0) {
           A[u].x = X.x; A[u].y = Xm.x;
           B[u].x = X.y; B[u].y = Xm.y;
@@ -1372,28 +1380,28 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   }
   __syncthreads();
   SKX_G V *spec = gptr<V>(S.spec) + (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H +
-                  (size_t)plane * N2 * S.pitch;
+                  (size_t)plane * N * S.pitch;
   const int pitch = S.pitch;
   V *cb = buf + wave * YC;
-  cstage<V, N2, Y0, 1, PL, 1, YC, true, false>(cb, tw2, lane);
+  CStages<typename K::Init>::template run<V, N, 1, PL, 1, YC, true, false>(cb, tw2, lane);
   {
-    typedef CMap<N2, Y1, YC, true> M;
+    typedef CMap<N, YL, YC, true> M;
 #pragma unroll
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
       if (M::ok(b)) {
         const int t = M::t(b), j = M::j(b);
-        V v[Y1];
+        V v[YL];
 #pragma unroll
-        for (int r = 0; r < Y1; ++r) v[r] = cb[t + (j + M::NB * r) * PL];
-        cbfly<V, N2, Y1, Y0, false>(v, j, tw2);
+        for (int r = 0; r < YL; ++r) v[r] = cb[t + (j + M::NB * r) * PL];
+        cbfly<V, N, YL, NSL, false>(v, j, tw2);
         const int col = wave * YC + t;
         if (col != 0) {
 #pragma unroll
-          for (int r = 0; r < Y1; ++r) stg(spec + (size_t)(j + Y0 * r) * pitch + col, v[r]);
+          for (int r = 0; r < YL; ++r) stg(spec + (size_t)(j + NSL * r) * pitch + col, v[r]);
         } else {
 #pragma unroll
-          for (int r = 0; r < Y1; ++r) buf[(j + Y0 * r) * PL] = v[r];
+          for (int r = 0; r < YL; ++r) buf[(j + NSL * r) * PL] = v[r];
         }
       }
     }
@@ -1401,12 +1409,12 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   if (wave == 0) {
     // unfold column 0: Z = F_DC + i F_Nyq of two real columns
     SKX_WAVE_SYNC();
-    constexpr int NY = (N2 + 63) / 64;
+    constexpr int NY = (N + 63) / 64;
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
       const int y = lane + 64 * u;
-      if (y < N2) {
-        const V Z = buf[y * PL], Zm = buf[((N2 - y) % N2) * PL];
+      if (y < N) {
+        const V Z = buf[y * PL], Zm = buf[((N - y) % N) * PL];
         V F0, Fn;
         F0.x = (R)0.5 * (Z.x + Zm.x); F0.y = (R)0.5 * (Z.y - Zm.y);
         Fn.x = (R)0.5 * (Z.y + Zm.y); Fn.y = (R)-0.5 * (Z.x - Zm.x);
@@ -1417,23 +1425,24 @@ __global__ __launch_bounds__(256) void k_passAf(SolveDev *dev, const int *first,
   }
 }
 
-// The Nyquist column (k3 = n3/2) of pass B for batches on k_passBf, one
-// wavefront per y index: the x transform of that column of every field (a
-// radix-8 butterfly per lane per stage), the multipliers and energy terms of
-// its G points, and the energy row k_passB's last column block would write.
-// tile holds NFIELD (N1 + 1) values of this wavefront.
-template <typename R, int N1, int MODE>
+// The Nyquist column (k3 = N/2) of pass B on k_passBf, one wavefront per y
+// index: the x transform of that column of every field (the first stage
+// one butterfly per lane, from HBM), the multipliers and energy terms of
+// its G points, and the energy row k_passB's last column block would
+// write. tile holds NFIELD (N + 1) values of this wavefront.
+template <typename R, int N, int MODE>
 __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typename Vec2<R>::T *tile,
                                               const typename Vec2<R>::T *tw1, int lane) {
   typedef typename Vec2<R>::T V;
-  constexpr int X0 = CRad<N1>::R0, X1 = CRad<N1>::R1;
-  constexpr int TP = N1 + 1;                          // LDS pitch between fields
+  typedef CS<N> K;
+  constexpr int X0 = K::R0, XL = K::RL, NSL = K::NSL;
+  constexpr int TP = N + 1;                           // LDS pitch between fields
   const int kc = S.nh - 1;                            // the Nyquist column
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + kc;
-  typedef CMap<N1, X0, NFIELD, false> M;              // lane -> (field slot, butterfly)
-  static_assert(M::MB == 1, "one butterfly per lane");
+  typedef CMap<N, X0, NFIELD, false> M;               // lane -> (field slot, butterfly)
+  static_assert(M::MB == 1, "one first-stage butterfly per lane");
   {
     const int b = lane;
     if (M::ok(b)) {
@@ -1450,25 +1459,27 @@ __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typenam
     }
   }
   SKX_WAVE_SYNC();
-  cstage<V, N1, X1, X0, 1, TP, NFIELD, false, false>(tile, tw1, lane);
-  // G points kx = lane of the column
-  const int kx = lane;
-  const int k3 = kc, g1 = gidx(kx, N1), g2 = gidx(jy, S.n2);
-  const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
-  const double G2 = S.kscale * (double)sidx;
+  CStages<typename K::Rest>::template run<V, N, X0, 1, TP, NFIELD, false, false>(tile, tw1, lane);
   double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
-  if (MODE == MODE_PREC) {
-    const R pg = (R)(1.0 / (G2 + S.kappa));
-    V x = tile[kx];
-    x.x *= pg; x.y *= pg;
-    tile[kx] = x;
-  } else {
-    const unsigned terms = S.terms;
-    const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
-    const bool do_h = terms & 16u, do_loc = terms & 32u;
-    const int sphi = S.slot[0], sn = S.slot[1], sfl = S.slot[2], sh = S.slot[3];
-    const R b3 = (R)(S.beta / 3.0);
-    const double FOURPI = 12.566370614359172954;
+  const int k3 = kc, g2 = gidx(jy, S.n2);
+  const unsigned terms = S.terms;
+  const bool do_vw = terms & 2u, do_nl0 = terms & 4u;
+  const bool do_h = terms & 16u, do_loc = terms & 32u;
+  const int sphi = S.slot[0], sn = S.slot[1], sfl = S.slot[2], sh = S.slot[3];
+  const R b3 = (R)(S.beta / 3.0);
+  const double FOURPI = 12.566370614359172954;
+  // G points kx = lane, lane + 64, ... of the column
+  for (int kx = lane; kx < N; kx += 64) {
+    const int g1 = gidx(kx, N);
+    const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
+    const double G2 = S.kscale * (double)sidx;
+    if (MODE == MODE_PREC) {
+      const R pg = (R)(1.0 / (G2 + S.kappa));
+      V x = tile[kx];
+      x.x *= pg; x.y *= pg;
+      tile[kx] = x;
+      continue;
+    }
     V vl;
     vl.x = 0; vl.y = 0;
     if (do_loc) vl = ldg(gptr<V>(S.vloc) + ((size_t)kx * S.n2 + jy) * S.pitch + k3);
@@ -1518,19 +1529,23 @@ __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typenam
     }
   }
   SKX_WAVE_SYNC();
-  cstage<V, N1, X0, 1, 1, TP, NFIELD, false, true>(tile, tw1, lane);
+  CStages<typename K::Init>::template run<V, N, 1, 1, TP, NFIELD, false, true>(tile, tw1, lane);
   {
-    typedef CMap<N1, X1, NFIELD, false> ML;
-    const int b = lane;
-    if (ML::ok(b)) {
-      const int t = ML::t(b), jj = ML::j(b);
-      V v[X1];
+    typedef CMap<N, XL, NFIELD, false> ML;
 #pragma unroll
-      for (int r = 0; r < X1; ++r) v[r] = tile[t * TP + jj + ML::NB * r];
-      cbfly<V, N1, X1, X0, true>(v, jj, tw1);
-      if (t < nf) {
+    for (int i = 0; i < ML::MB; ++i) {
+      const int b = lane + 64 * i;
+      if (ML::ok(b)) {
+        const int t = ML::t(b), jj = ML::j(b);
+        V v[XL];
 #pragma unroll
-        for (int r = 0; r < X1; ++r) stg(spec + (size_t)t * S.H + (size_t)(jj + X0 * r) * rowstride, v[r]);
+        for (int r = 0; r < XL; ++r) v[r] = tile[t * TP + jj + ML::NB * r];
+        cbfly<V, N, XL, NSL, true>(v, jj, tw1);
+        if (t < nf) {
+#pragma unroll
+          for (int r = 0; r < XL; ++r)
+            stg(spec + (size_t)t * S.H + (size_t)(jj + NSL * r) * rowstride, v[r]);
+        }
       }
     }
   }
@@ -1545,31 +1560,31 @@ __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typenam
 }
 
 // ---------------------------------------------------------------------------
-// Pass B for x-transforms of a length fixed at compile time (N1), one
-// workgroup of four wavefronts per (y index, block of TK z columns). In
-// MODE_EVAL wavefront w owns the x transforms of field slot w (all TK
-// columns); in MODE_PREC the one field's columns are split over the four.
-// The first forward stage reads its inputs from HBM, the last inverse stage
-// writes its outputs there from registers; between the two directions the
-// multipliers and energy terms of every G point run over the LDS tiles.
+// Pass B for cubic grids of a length N fixed at compile time, one workgroup
+// of four wavefronts per (y index, block of TK z columns). In MODE_EVAL
+// wavefront w owns the x transforms of field slot w (all TK columns); in
+// MODE_PREC the one field's columns are split over the four. The first
+// forward stage reads its inputs from HBM, the last inverse stage writes its
+// outputs there from registers; between the two directions the multipliers
+// and energy terms of every G point run over the LDS tiles. Needs
+// (N/2) % TK == 0: the column blocks stop below the Nyquist column, which
+// extra workgroups take for four y rows each, one per wavefront.
 // ---------------------------------------------------------------------------
-template <typename R, int N1, int TK, int MODE>
+template <typename R, int N, int TK, int MODE>
 __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first, int nsolve,
                                                 int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
+  typedef CS<N> K;
   constexpr int NT = 256, NW = 4;
-  constexpr int X0 = CRad<N1>::R0, X1 = CRad<N1>::R1;
-  static_assert(X0 * X1 == N1, "two x stages");
+  constexpr int X0 = K::R0, XL = K::RL, NSL = K::NSL;
   constexpr int TP = TK + 1;                       // LDS row pitch of a field tile
   constexpr int SL = MODE == MODE_EVAL ? TK : TK / NW;   // columns per wavefront
+  static_assert(MODE == MODE_EVAL || TK % NW == 0, "preconditioner columns split evenly");
+  static_assert(N % NW == 0, "Nyquist rows split evenly");
   extern __shared__ __align__(16) unsigned char smem[];
-  // every solve of the batch has the same grid: NB blocks of TK columns per
-  // y index
-  // below the Nyquist column, then N1 / NW workgroups whose wavefronts take
-  // the Nyquist column of one y index each
-  constexpr int NB = (N1 / 2) / TK;
-  static_assert((N1 / 2) % TK == 0, "whole column blocks below the Nyquist column");
-  constexpr int PER = N1 * NB + N1 / NW;           // workgroups per solve
+  constexpr int NB = (N / 2) / TK;
+  static_assert((N / 2) % TK == 0, "whole column blocks below the Nyquist column");
+  constexpr int PER = N * NB + N / NW;             // workgroups per solve
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
   const int s = __builtin_amdgcn_readfirstlane(item / PER);
@@ -1578,12 +1593,12 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   if (!active_phase<MODE>(st->phase)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rem = item - s * PER;
-  if (rem >= N1 * NB) {
-    V *tw = reinterpret_cast<V *>(smem) + NFIELD * N1 * TP;
-    load_twiddles(tw, twbank, S.p1.tw, N1, tid, NT);
+  if (rem >= N * NB) {
+    V *tw = reinterpret_cast<V *>(smem) + NFIELD * N * TP;
+    load_twiddles(tw, twbank, S.p1.tw, N, tid, NT);
     __syncthreads();
-    passB_nyquist<R, N1, MODE>(S, (rem - N1 * NB) * NW + wave,
-                               reinterpret_cast<V *>(smem) + wave * NFIELD * (N1 + 1), tw, lane);
+    passB_nyquist<R, N, MODE>(S, (rem - N * NB) * NW + wave,
+                              reinterpret_cast<V *>(smem) + wave * NFIELD * (N + 1), tw, lane);
     return;
   }
   const int jy = rem / NB, kb = rem - (rem / NB) * NB;
@@ -1591,17 +1606,17 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   const int k0 = kb * TK;
   const int tkv = TK;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
-  V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N1][TP]
-  V *tw1 = tile + NFIELD * N1 * TP;
+  V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N][TP]
+  V *tw1 = tile + NFIELD * N * TP;
   SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + k0;
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   const int cc = MODE == MODE_EVAL ? wave : 0;       // field slot of this wavefront
   const int c0 = MODE == MODE_EVAL ? 0 : wave * SL;  // its first column
   const bool active = cc < nf;
-  V *tf = tile + cc * N1 * TP + c0;
+  V *tf = tile + cc * N * TP + c0;
   SKX_G V *sf = spec + (size_t)cc * S.H + c0;
   const int cv = tkv - c0;                           // valid columns from c0
-  typedef CMap<N1, X0, SL, true> M0;
+  typedef CMap<N, X0, SL, true> M0;
   V v[M0::MB][X0];
   if (active) {
     typedef M0 M;
@@ -1619,7 +1634,7 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
     }
   }
   // the twiddle table is loaded while the spectrum loads are in flight
-  load_twiddles(tw1, twbank, S.p1.tw, N1, tid, NT);
+  load_twiddles(tw1, twbank, S.p1.tw, N, tid, NT);
   __syncthreads();
   if (active) {
     typedef M0 M;
@@ -1634,20 +1649,20 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
       }
     }
     SKX_WAVE_SYNC();
-    cstage<V, N1, X1, X0, TP, 1, SL, true, false>(tf, tw1, lane);
+    CStages<typename K::Rest>::template run<V, N, X0, TP, 1, SL, true, false>(tf, tw1, lane);
   }
   __syncthreads();
   const double kscale = S.kscale;
   const int g2 = gidx(jy, S.n2);
   double evw = 0, eh = 0, ef0 = 0, ef1 = 0, eloc = 0, bad = 0;
-  constexpr int NP = (N1 * TK + NT - 1) / NT;
+  constexpr int NP = (N * TK + NT - 1) / NT;
   if (MODE == MODE_PREC) {
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int e = tid + u * NT;
       const int kx = e / TK, col = e % TK;
-      if ((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv) {
-        const int k3 = k0 + col, g1 = gidx(kx, N1);
+      if ((N * TK % NT == 0 || e < N * TK) && col < tkv) {
+        const int k3 = k0 + col, g1 = gidx(kx, N);
         const double G2 = kscale * (double)(g1 * g1 + g2 * g2 + k3 * k3);
         const R pg = (R)(1.0 / (G2 + S.kappa));
         V x = tile[kx * TP + col];
@@ -1671,8 +1686,8 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
     for (int u = 0; u < NP; ++u) {
       const int e = tid + u * NT;
       const int kx = e / TK, col = e % TK;
-      if ((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv) {
-        const int k3 = k0 + col, g1 = gidx(kx, N1);
+      if ((N * TK % NT == 0 || e < N * TK) && col < tkv) {
+        const int k3 = k0 + col, g1 = gidx(kx, N);
         const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
         if (do_loc) vlb[u] = ldg(vloc + ((size_t)kx * S.n2 + jy) * S.pitch + k3);
         if (sfl >= 0) { wb[u] = wt[sidx]; wpb[u] = wpt[sidx]; }
@@ -1682,21 +1697,21 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
     for (int u = 0; u < NP; ++u) {
       const int e = tid + u * NT;
       const int kx = e / TK, col = e % TK;
-      if (!((N1 * TK % NT == 0 || e < N1 * TK) && col < tkv)) continue;
-      const int k3 = k0 + col, g1 = gidx(kx, N1);
+      if (!((N * TK % NT == 0 || e < N * TK) && col < tkv)) continue;
+      const int k3 = k0 + col, g1 = gidx(kx, N);
       const int sidx = g1 * g1 + g2 * g2 + k3 * k3;
       const double G2 = kscale * (double)sidx;
       const double wgt = (k3 == 0 || 2 * k3 == S.n3) ? 1.0 : 2.0;
-      V *pt = tile + kx * TP + col;                  // field slot c at pt[c N1 TP]
+      V *pt = tile + kx * TP + col;                  // field slot c at pt[c N TP]
       if (sphi >= 0) {
-        V x = pt[sphi * N1 * TP];
+        V x = pt[sphi * N * TP];
         if (do_vw) evw += wgt * G2 * ((double)x.x * x.x + (double)x.y * x.y);
         const R g2r = (R)G2;
         x.x *= g2r; x.y *= g2r;
-        pt[sphi * N1 * TP] = x;
+        pt[sphi * N * TP] = x;
       }
       {
-        const V x = pt[sn * N1 * TP];
+        const V x = pt[sn * N * TP];
         double bx = 0.0, by = 0.0;
         if (do_h && sidx > 0) {
           const double m2 = (double)x.x * x.x + (double)x.y * x.y;
@@ -1713,10 +1728,10 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
         }
         if (!(x.x == x.x) || !(x.y == x.y)) bad += 1.0;
         V o; o.x = (R)bx; o.y = (R)by;
-        pt[sn * N1 * TP] = o;
+        pt[sn * N * TP] = o;
       }
       if (sfl >= 0) {
-        const V f = pt[sfl * N1 * TP];
+        const V f = pt[sfl * N * TP];
         const R w = (R)wb[u];
         const R wp = (R)wpb[u];
         V P; P.x = 0; P.y = 0;
@@ -1725,32 +1740,32 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
           P.x = (R)2 * w * f.x; P.y = (R)2 * w * f.y;
         }
         if (sh >= 0) {
-          const V h = pt[sh * N1 * TP];
+          const V h = pt[sh * N * TP];
           ef1 += wgt * (double)wp * ((double)f.x * h.x + (double)f.y * h.y);
           P.x += b3 * wp * h.x; P.y += b3 * wp * h.y;
           V Q; Q.x = b3 * wp * f.x; Q.y = b3 * wp * f.y;
-          pt[sh * N1 * TP] = Q;
+          pt[sh * N * TP] = Q;
         }
-        pt[sfl * N1 * TP] = P;
+        pt[sfl * N * TP] = P;
       }
     }
   }
   __syncthreads();
   if (active) {
-    cstage<V, N1, X0, 1, TP, 1, SL, true, true>(tf, tw1, lane);
-    typedef CMap<N1, X1, SL, true> M;
+    CStages<typename K::Init>::template run<V, N, 1, TP, 1, SL, true, true>(tf, tw1, lane);
+    typedef CMap<N, XL, SL, true> M;
 #pragma unroll
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
       if (M::ok(b)) {
         const int t = M::t(b), jj = M::j(b);
-        V v[X1];
+        V w[XL];
 #pragma unroll
-        for (int r = 0; r < X1; ++r) v[r] = tf[(jj + M::NB * r) * TP + t];
-        cbfly<V, N1, X1, X0, true>(v, jj, tw1);
+        for (int r = 0; r < XL; ++r) w[r] = tf[(jj + M::NB * r) * TP + t];
+        cbfly<V, N, XL, NSL, true>(w, jj, tw1);
         if (t < cv) {
 #pragma unroll
-          for (int r = 0; r < X1; ++r) stg(sf + (size_t)(jj + X0 * r) * rowstride + t, v[r]);
+          for (int r = 0; r < XL; ++r) stg(sf + (size_t)(jj + NSL * r) * rowstride + t, w[r]);
         }
       }
     }
@@ -1766,25 +1781,24 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
 }
 
 // ---------------------------------------------------------------------------
-// Pass C on planes of a shape fixed at compile time (N2 x N3, radix orders
-// from CRad), one workgroup of four wavefronts per x-plane, every index a
-// constant. Per field:
+// Pass C on cubic grids of a length N fixed at compile time, one workgroup
+// of NW wavefronts per x-plane, every index a constant. Per field:
 //  * the half spectrum of the plane is copied into LDS;
 //  * the DC and Nyquist columns, whose inverse y transforms are real, are
 //    each reduced to their Hermitian part (whose inverse is the real part of
-//    the plain inverse) and folded into one complex column, so the N3/2
+//    the plain inverse) and folded into one complex column, so the N/2
 //    columns split evenly over the wavefronts;
-//  * after a barrier every wavefront takes N2/8 row pairs: its first z stage
-//    builds x_{2p} + i x_{2p+1} over the full row from the two half spectra,
-//    its last stage keeps the outputs in registers, where they are assembled
-//    with their pointwise coefficients into dE/dphi of the 2 R1 points per
-//    butterfly the lane owns (the same points for every field).
+//  * after a barrier every wavefront takes N/(2 NW) row pairs: its first z
+//    stage builds x_{2p} + i x_{2p+1} over the full row from the two half
+//    spectra, its last stage keeps the outputs in registers, where they are
+//    assembled with their pointwise coefficients into dE/dphi of the points
+//    of the butterflies the lane owns (the same points for every field).
 // MODE_PREC transforms the one preconditioner field back to real space.
 // ---------------------------------------------------------------------------
-template <typename V, int N3, int RAD, int ZP>
+template <typename V, int N, int RAD, int ZP>
 __device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
-  constexpr int C = N3 / 2, PL = CRad<N3>::PL;
-  typedef CMap<N3, RAD, ZP, false> M;
+  constexpr int C = N / 2, PL = CS<N>::PL;
+  typedef CMap<N, RAD, ZP, false> M;
   static_assert(RAD % 2 == 0, "even first radix");
   V v[M::MB][RAD];
 #pragma unroll
@@ -1800,9 +1814,9 @@ __device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
         if (r < RAD / 2) {                   // 0 <= e < C
           a = ra[e]; c = rb[e];
           if (r == 0 && j == 0) { a.y = 0; c.y = 0; }        // DC: real part of column 0
-        } else {                             // C <= e < N3: Hermitian mirror
+        } else {                             // C <= e < N: Hermitian mirror
           const bool nyq = (r == RAD / 2) && (j == 0);
-          const int m = nyq ? 0 : N3 - e;
+          const int m = nyq ? 0 : N - e;
           a = ra[m]; c = rb[m];
           if (nyq) { a.x = a.y; a.y = 0; c.x = c.y; c.y = 0; }  // Nyquist: imaginary part of column 0
           else { a.y = -a.y; c.y = -c.y; }
@@ -1827,18 +1841,18 @@ __device__ __forceinline__ void zfirst_merge(V *buf, int lane) {
   SKX_WAVE_SYNC();
 }
 
-// Columns 0 and C of the plane (rows [0, N2)) folded into column 0 as
+// Columns 0 and C of the plane (rows [0, N)) folded into column 0 as
 // herm(X_0) + i herm(X_C), by one wavefront.
-template <typename V, int N2, int N3>
+template <typename V, int N>
 __device__ __forceinline__ void fold_dc_nyquist(V *buf, int lane) {
   typedef decltype(buf[0].x) R;
-  constexpr int C = N3 / 2, PL = CRad<N3>::PL, NY = (N2 + 63) / 64;
+  constexpr int C = N / 2, PL = CS<N>::PL, NY = (N + 63) / 64;
   V z[NY];
 #pragma unroll
   for (int u = 0; u < NY; ++u) {
     const int y = lane + 64 * u;
-    if (y < N2) {
-      const int ym = (N2 - y) % N2;
+    if (y < N) {
+      const int ym = (N - y) % N;
       const V a = buf[y * PL], am = buf[ym * PL], b = buf[y * PL + C], bm = buf[ym * PL + C];
       const R h0x = (R)0.5 * (a.x + am.x), h0y = (R)0.5 * (a.y - am.y);
       const R hnx = (R)0.5 * (b.x + bm.x), hny = (R)0.5 * (b.y - bm.y);
@@ -1850,27 +1864,27 @@ __device__ __forceinline__ void fold_dc_nyquist(V *buf, int lane) {
 #pragma unroll
   for (int u = 0; u < NY; ++u) {
     const int y = lane + 64 * u;
-    if (y < N2) buf[y * PL] = z[u];
+    if (y < N) buf[y * PL] = z[u];
   }
   SKX_WAVE_SYNC();
 }
 
-// Inverse y transform and first z stage of the plane in buf; on return the
-// lane's last-stage butterflies are in v (outputs at z = j + R0 r of the row
-// pair p, real parts row 2p, imaginary parts row 2p+1).
-template <typename V, int N2, int N3, int ZP, int MB>
+// Inverse y transform and the z stages but the last of the plane in buf; on
+// return the lane's last-stage butterflies are in v (outputs at
+// z = j + NSL r of the row pair p, real parts row 2p, imaginary parts row
+// 2p+1).
+template <typename V, int N, int MB>
 __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *tw3, int lane,
-                                                int wave, V (&v)[MB][CRad<N3>::R1]) {
-  constexpr int C = N3 / 2, PL = CRad<N3>::PL, NW = 4, YC = C / NW;
-  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
-  constexpr int Y0 = CRad<N2>::R0, Y1 = CRad<N2>::R1;
-  static_assert(Y0 * Y1 == N2 && R0 * R1 == N3, "two stages per direction");
-  if (wave == 0) fold_dc_nyquist<V, N2, N3>(buf, lane);
-  cstages<V, N2, 1, PL, 1, YC, true, true, Y0, Y1>(buf + wave * YC, tw2, lane);
+                                                int wave, V (&v)[MB][CS<N>::RL]) {
+  typedef CS<N> K;
+  constexpr int PL = K::PL, YC = K::YC, ZP = K::ZP, R0 = K::R0, RL = K::RL, NSL = K::NSL;
+  if (wave == 0) fold_dc_nyquist<V, N>(buf, lane);
+  CStages<typename K::L>::template run<V, N, 1, PL, 1, YC, true, true>(buf + wave * YC, tw2, lane);
   __syncthreads();
   V *zb = buf + wave * ZP * 2 * PL;
-  zfirst_merge<V, N3, R0, ZP>(zb, lane);
-  typedef CMap<N3, R1, ZP, false> ZM;
+  zfirst_merge<V, N, R0, ZP>(zb, lane);
+  CStages<typename K::Mid>::template run<V, N, R0, 1, 2 * PL, ZP, false, true>(zb, tw3, lane);
+  typedef CMap<N, RL, ZP, false> ZM;
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int b = lane + 64 * i;
@@ -1878,22 +1892,21 @@ __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *t
       const int p = ZM::t(b), j = ZM::j(b);
       const V *base = zb + 2 * p * PL + j;
 #pragma unroll
-      for (int r = 0; r < R1; ++r) v[i][r] = base[r * ZM::NB];
-      cbfly<V, N3, R1, R0, true>(v[i], j, tw3);
+      for (int r = 0; r < RL; ++r) v[i][r] = base[r * ZM::NB];
+      cbfly<V, N, RL, NSL, true>(v[i], j, tw3);
     }
   }
 }
 
-template <typename R, int N2, int N3, int MODE>
-// (three workgroups per CU: caps FP64 at 168 VGPRs, FP32 needs fewer)
-__global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *first, int nsolve,
-                                                int grid, const double *twbank) {
+// (about three workgroups' worth of waves per CU: FP64 at 64^3 fits 168
+// VGPRs with three 256-thread groups)
+template <typename R, int N, int MODE>
+__global__ __launch_bounds__(CS<N>::NT, (CS<N>::NW == 4 ? 3 : (CS<N>::NW == 6 ? 2 : 1)))
+void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
-  constexpr int NT = 256, NW = 4;
-  constexpr int C = N3 / 2, PL = CRad<N3>::PL;
-  constexpr int R0 = CRad<N3>::R0, R1 = CRad<N3>::R1;
-  constexpr int ZP = N2 / 2 / NW;                 // row pairs per wavefront
-  typedef CMap<N3, R1, ZP, false> ZM;
+  typedef CS<N> K;
+  constexpr int NT = K::NT, C = K::C, PL = K::PL, ZP = K::ZP, RL = K::RL, NSL = K::NSL;
+  typedef CMap<N, RL, ZP, false> ZM;
   constexpr int MB = ZM::MB;
   constexpr bool KEEP_PHI = sizeof(R) == 4;       // phi_t stays in registers (FP32)
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1907,34 +1920,34 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int plane = item - first_of(first, s);
   V *buf = reinterpret_cast<V *>(smem);
-  V *tw2 = buf + N2 * PL;
-  V *tw3 = tw2 + N2;
-  load_twiddles(tw2, twbank, S.p2.tw, N2, tid, NT);
-  load_twiddles(tw3, twbank, S.p3.tw, N3, tid, NT);
-  const size_t pbase = (size_t)plane * N2 * N3;
-  const SKX_G V *spec = gptr<V>(S.spec) + (size_t)plane * N2 * S.pitch;
+  V *tw2 = buf + N * PL;
+  V *tw3 = tw2 + N;
+  load_twiddles(tw2, twbank, S.p2.tw, N, tid, NT);
+  load_twiddles(tw3, twbank, S.p3.tw, N, tid, NT);
+  const size_t pbase = (size_t)plane * N * N;
+  const SKX_G V *spec = gptr<V>(S.spec) + (size_t)plane * N * S.pitch;
   const int pitch = S.pitch;
-  // the lane's points: row 2p + h, z = j + R0 r of butterfly slot i
+  // the lane's points: row 2p + h, z = j + NSL r of butterfly slot i
   int pt[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int b = lane + 64 * i;
-    pt[i] = ZM::ok(b) ? 2 * (wave * ZP + ZM::t(b)) * N3 + ZM::j(b) : -1;
+    pt[i] = ZM::ok(b) ? 2 * (wave * ZP + ZM::t(b)) * N + ZM::j(b) : -1;
   }
-  V v[MB][R1];
+  V v[MB][RL];
 
   if (MODE == MODE_PREC) {
-    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec, pitch, tid);
+    load_plane_f<V, N, C + 1, PL, NT>(buf, spec, pitch, tid);
     __syncthreads();
-    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
+    plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
     SKX_G R *out = gptr<R>(S.pr2[1 - par]) + pbase;
 #pragma unroll
     for (int i = 0; i < MB; ++i)
       if (pt[i] >= 0) {
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
-          out[pt[i] + R0 * r] = v[i][r].x;
-          out[pt[i] + N3 + R0 * r] = v[i][r].y;
+        for (int r = 0; r < RL; ++r) {
+          out[pt[i] + NSL * r] = v[i][r].x;
+          out[pt[i] + N + NSL * r] = v[i][r].y;
         }
       }
     return;
@@ -1942,8 +1955,8 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 
   const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
   const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
-  R acc[MB][2][R1];
-  R ph[KEEP_PHI ? MB : 1][2][R1];
+  R acc[MB][2][RL];
+  R ph[KEEP_PHI ? MB : 1][2][RL];
   {
     const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
 #pragma unroll
@@ -1952,8 +1965,8 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int r = 0; r < R1; ++r) {
-            const int o = pt[i] + h * N3 + R0 * r;
+          for (int r = 0; r < RL; ++r) {
+            const int o = pt[i] + h * N + NSL * r;
             const R p = phit[o];
             acc[i][h][r] = (R)2 * p * v0[o];
             if (KEEP_PHI) ph[KEEP_PHI ? i : 0][h][r] = p;
@@ -1963,11 +1976,11 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0) continue;
-    R cf[MB][2][R1];
+    R cf[MB][2][RL];
     __syncthreads();
-    load_plane_f<V, N2, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    load_plane_f<V, N, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
     __syncthreads();
-    plane_inverse_f<V, N2, N3, ZP, MB>(buf, tw2, tw3, lane, wave, v);
+    plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
     if (fb >= 2 || (fb == 1 && !KEEP_PHI)) {
       const SKX_G R *src = fb == 1 ? phit : (fb == 2 ? cfp[2] : cfp[3]);
 #pragma unroll
@@ -1976,14 +1989,14 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int r = 0; r < R1; ++r) cf[i][h][r] = src[pt[i] + h * N3 + R0 * r];
+            for (int r = 0; r < RL; ++r) cf[i][h][r] = src[pt[i] + h * N + NSL * r];
         }
     }
 #pragma unroll
     for (int i = 0; i < MB; ++i)
       if (pt[i] >= 0) {
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
+        for (int r = 0; r < RL; ++r) {
           const R g0 = v[i][r].x, g1 = v[i][r].y;
           if (fb == 0) {
             acc[i][0][r] += g0;
@@ -2008,8 +2021,8 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
-          const int o = pt[i] + h * N3 + R0 * r;
+        for (int r = 0; r < RL; ++r) {
+          const int o = pt[i] + h * N + NSL * r;
           const R g = acc[i][h][r];
           const R p = KEEP_PHI ? ph[KEEP_PHI ? i : 0][h][r] : phit[o];
           grad[o] = g;
@@ -2032,119 +2045,173 @@ __global__ __launch_bounds__(256, 3) void k_passCf(SolveDev *dev, const int *fir
 // Runtime-shaped pass B with 512 threads: measured faster in FP32 at every
 // size, and in FP64 once the x tile takes more than half of a CU's LDS (one
 // workgroup per CU).
-template <typename R> static bool wide_b(const BatchLaunch &b) {
-  return sizeof(R) == 4 || b.ldsB > 80 * 1024;
+template <typename R> static bool wide_b(const PassGroup &g) {
+  return sizeof(R) == 4 || g.ldsB > 80 * 1024;
 }
 // Runtime-shaped pass A with 512 threads once its plane takes more than
 // 45 KB of LDS (measured: FP64 96^3 177 -> 161 us, 128^3 540 -> 442 us;
 // FP32 108^3 157 -> 144 us; smaller planes are faster with 256).
-static bool wide_a(const BatchLaunch &b) { return b.ldsA > 45 * 1024; }
+static bool wide_a(const PassGroup &g) { return g.ldsA > 45 * 1024; }
+
+// Compile-time-shaped pass kernels of one length N over one group.
+template <typename R, int N>
+static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
+                          int mode) {
+  typedef typename Vec2<R>::T V;
+  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
+  constexpr int NT = CS<N>::NT;
+  const size_t lds_plane = CS<N>::lds_plane(sizeof(V));
+  if (mode == MODE_EVAL) {
+    if (g.gridA > 0 && (mask & 16) && (g.shape & 1))
+      SKX_TIMED_LAUNCH((k_passAf<R, N, MODE_EVAL>), dim3(g.gridA), dim3(NT), lds_plane, s, g.dev,
+                       g.firstA, g.nsolve, g.gridA, twbank);
+  } else if (g.gridC > 0 && (mask & 1) && (g.shape & 1)) {
+    // one field per solve: pass A has one workgroup per plane, like pass C
+    SKX_TIMED_LAUNCH((k_passAf<R, N, MODE_PREC>), dim3(g.gridC), dim3(NT), lds_plane, s, g.dev,
+                     g.firstC, g.nsolve, g.gridC, twbank);
+  }
+  if constexpr ((N / 2) % TK == 0) {
+    if (g.gridB > 0 && (mask & 2) && (g.shape & 2)) {
+      const int gb = g.nsolve * (N * (N / 2 / TK) + N / 4);
+      const size_t lb = (NFIELD * N * (TK + 1) + N) * sizeof(V);
+      if (mode == MODE_EVAL)
+        SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_EVAL>), dim3(gb), dim3(256), lb, s, g.dev,
+                         g.firstB, g.nsolve, gb, twbank);
+      else
+        SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_PREC>), dim3(gb), dim3(256), lb, s, g.dev,
+                         g.firstB, g.nsolve, gb, twbank);
+    }
+  }
+  if (g.gridC > 0 && (mask & 4) && (g.shape & 4)) {
+    if (mode == MODE_EVAL)
+      SKX_TIMED_LAUNCH((k_passCf<R, N, MODE_EVAL>), dim3(g.gridC), dim3(NT), lds_plane, s, g.dev,
+                       g.firstC, g.nsolve, g.gridC, twbank);
+    else
+      SKX_TIMED_LAUNCH((k_passCf<R, N, MODE_PREC>), dim3(g.gridC), dim3(NT), lds_plane, s, g.dev,
+                       g.firstC, g.nsolve, g.gridC, twbank);
+  }
+}
 
 template <typename R>
-static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
+static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
+                            int mode) {
+  switch (g.shapeN) {
+    case 48: launch_shaped<R, 48>(g, twbank, s, mask, mode); break;
+    case 64: launch_shaped<R, 64>(g, twbank, s, mask, mode); break;
+    case 72: launch_shaped<R, 72>(g, twbank, s, mask, mode); break;
+    case 80: launch_shaped<R, 80>(g, twbank, s, mask, mode); break;
+    default: break;
+  }
+}
+
+// Runtime-shaped (and chunked) pass kernels over one group, for the passes
+// in `mask` (1|16 pass A's transform, 2 pass B, 4 pass C) that the group
+// does not run on compile-time-shaped kernels.
+template <typename R>
+static void launch_eval_runtime(const PassGroup &g, const BatchLaunch &b, hipStream_t s, int mask) {
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   constexpr int NTC = 512;
-  // mask: 1 pass A (pointwise kernel and transform), 2 pass B, 4 pass C,
-  // 8 the pointwise kernel alone, 16 pass A's transform alone
-  if (b.gridA > 0 && (mask & (1 | 8)))
-    SKX_TIMED_LAUNCH((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
-                       b.firstV, b.nsolve, b.gridV, b.fd);
-  if (b.gridA > 0 && (mask & (1 | 16))) {
-    if (b.shape & 1)
-      SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_EVAL>), dim3(b.gridA), dim3(256),
-                         (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstA, b.nsolve, b.gridA,
-                         b.twbank);
-    else if (b.smallA && wide_a(b))
-      SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), b.ldsA, s, b.dev,
-                         b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
-    else if (b.smallA)
-      SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(b.gridA), dim3(256), b.ldsA, s, b.dev,
-                         b.firstA, b.nsolve, b.gridA, b.twbank, b.fd);
-    if (b.bigA)
-      SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(b.gridA), dim3(512), BIG_LDS, s,
-                         b.dev, b.firstA, b.nsolve, b.gridA, b.twbank);
+  if (g.gridA > 0 && (mask & 16) && !(g.shape & 1)) {
+    if (g.smallA && wide_a(g))
+      SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_EVAL>), dim3(g.gridA), dim3(512), g.ldsA, s, g.dev,
+                       g.firstA, g.nsolve, g.gridA, b.twbank, b.fd);
+    else if (g.smallA)
+      SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(g.gridA), dim3(256), g.ldsA, s, g.dev,
+                       g.firstA, g.nsolve, g.gridA, b.twbank, b.fd);
+    if (g.bigA)
+      SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(g.gridA), dim3(512), BIG_LDS, s,
+                       g.dev, g.firstA, g.nsolve, g.gridA, b.twbank);
   }
-  if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
-    const int gb = b.nsolve * (64 * (32 / TK) + 16);
-    SKX_TIMED_LAUNCH((k_passBf<R, 64, TK, MODE_EVAL>), dim3(gb), dim3(256),
-                       (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
-                       b.nsolve, gb, b.twbank);
+  if (g.gridB > 0 && (mask & 2) && !(g.shape & 2)) {
+    if (wide_b<R>(g))
+      SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(g.gridB), dim3(512), g.ldsB, s,
+                       g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
+    else
+      SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_EVAL>), dim3(g.gridB), dim3(256), g.ldsB, s,
+                       g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
   }
-  else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
-    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(b.gridB), dim3(512), b.ldsB, s,
-                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  else if (b.gridB > 0 && (mask & 2))
-    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_EVAL>), dim3(b.gridB), dim3(256), b.ldsB, s,
-                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4) && (b.shape & 4)) {
-    SKX_TIMED_LAUNCH((k_passCf<R, 64, 64, MODE_EVAL>), dim3(b.gridC), dim3(256),
-                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
-                       b.twbank);
-  } else if (b.gridC > 0 && (mask & 4) && b.smallC) {
+  if (g.gridC > 0 && (mask & 4) && !(g.shape & 4) && g.smallC) {
     // In FP32 two 512-thread groups share a CU; when the last round of
     // those would be less than half full (e.g. 576 planes), 256-thread
     // groups spread the planes more evenly over the CUs.
-    const int fill = b.gridC % (2 * 256);
+    const int fill = g.gridC % (2 * 256);
     if (sizeof(R) == 4 && fill > 0 && fill <= 256) {
-      if (b.accC_lds)
-        SKX_TIMED_LAUNCH((k_passC<R, 256, true, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
-                           s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+      if (g.accC_lds)
+        SKX_TIMED_LAUNCH((k_passC<R, 256, true, MODE_EVAL>), dim3(g.gridC), dim3(256), g.ldsC,
+                         s, g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
       else
-        SKX_TIMED_LAUNCH((k_passC<R, 256, false, MODE_EVAL>), dim3(b.gridC), dim3(256), b.ldsC,
-                           s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-    } else if (b.accC_lds) {
-      SKX_TIMED_LAUNCH((k_passC<R, NTC, true, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC, s,
-                         b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+        SKX_TIMED_LAUNCH((k_passC<R, 256, false, MODE_EVAL>), dim3(g.gridC), dim3(256), g.ldsC,
+                         s, g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
+    } else if (g.accC_lds) {
+      SKX_TIMED_LAUNCH((k_passC<R, NTC, true, MODE_EVAL>), dim3(g.gridC), dim3(NTC), g.ldsC, s,
+                       g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
     } else {
-      SKX_TIMED_LAUNCH((k_passC<R, NTC, false, MODE_EVAL>), dim3(b.gridC), dim3(NTC), b.ldsC,
-                         s, b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
+      SKX_TIMED_LAUNCH((k_passC<R, NTC, false, MODE_EVAL>), dim3(g.gridC), dim3(NTC), g.ldsC,
+                       s, g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
     }
   }
-  if (b.gridC > 0 && (mask & 4) && b.bigC)
-    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_EVAL>), dim3(b.gridC), dim3(512), BIG_LDS, s,
-                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
+  if (g.gridC > 0 && (mask & 4) && !(g.shape & 4) && g.bigC)
+    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_EVAL>), dim3(g.gridC), dim3(512), BIG_LDS, s,
+                     g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+}
+
+template <typename R>
+static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
+  // mask: 1 pass A (pointwise kernel and transform), 2 pass B, 4 pass C,
+  // 8 the pointwise kernel alone, 16 pass A's transform alone
+  if (mask & 1) mask |= 8 | 16;
+  if (b.gridV > 0 && (mask & 8))
+    SKX_TIMED_LAUNCH((k_point<R, 256>), dim3(b.gridV), dim3(256), 256 * sizeof(double), s, b.dev,
+                     b.firstV, b.nsolve, b.gridV, b.fd);
+  // pass by pass over the groups (each pass of every group before the next
+  // pass starts)
+  for (const int pm : {16, 2, 4}) {
+    if (!(mask & pm)) continue;
+    for (int gi = 0; gi < b.ngroup; ++gi) {
+      const PassGroup &g = b.grp[gi];
+      if (g.shapeN) launch_shaped_n<R>(g, b.twbank, s, pm, MODE_EVAL);
+      launch_eval_runtime<R>(g, b, s, pm);
+    }
+  }
   return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
   constexpr int TK = sizeof(R) == 8 ? 8 : 16;
-  // one field per solve: pass A has one workgroup per plane, like pass C
-  if (b.gridC > 0 && (mask & 1) && (b.shape & 1))
-    SKX_TIMED_LAUNCH((k_passAf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
-                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
-                       b.twbank);
-  else if (b.gridC > 0 && (mask & 1) && b.smallA && wide_a(b))
-    SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsA, s, b.dev,
-                       b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  else if (b.gridC > 0 && (mask & 1) && b.smallA)
-    SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_PREC>), dim3(b.gridC), dim3(256), b.ldsA, s, b.dev,
-                       b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  if (b.gridC > 0 && (mask & 1) && b.bigA)
-    SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
-                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
-  if (b.gridB > 0 && (mask & 2) && (b.shape & 2)) {
-    const int gb = b.nsolve * (64 * (32 / TK) + 16);
-    SKX_TIMED_LAUNCH((k_passBf<R, 64, TK, MODE_PREC>), dim3(gb), dim3(256),
-                       (NFIELD * 64 * (TK + 1) + 64) * sizeof(R) * 2, s, b.dev, b.firstB,
-                       b.nsolve, gb, b.twbank);
+  for (const int pm : {1, 2, 4}) {
+    if (!(mask & pm)) continue;
+    for (int gi = 0; gi < b.ngroup; ++gi) {
+      const PassGroup &g = b.grp[gi];
+      if (g.shapeN) launch_shaped_n<R>(g, b.twbank, s, pm, MODE_PREC);
+      // one field per solve: pass A has one workgroup per plane, like pass C
+      if (g.gridC > 0 && (pm & 1) && !(g.shape & 1)) {
+        if (g.smallA && wide_a(g))
+          SKX_TIMED_LAUNCH((k_passA<R, 512, MODE_PREC>), dim3(g.gridC), dim3(512), g.ldsA, s,
+                           g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
+        else if (g.smallA)
+          SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_PREC>), dim3(g.gridC), dim3(256), g.ldsA, s,
+                           g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
+        if (g.bigA)
+          SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_PREC>), dim3(g.gridC), dim3(512), BIG_LDS, s,
+                           g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+      }
+      if (g.gridB > 0 && (pm & 2) && !(g.shape & 2)) {
+        if (wide_b<R>(g))
+          SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_PREC>), dim3(g.gridB), dim3(512), g.ldsB, s,
+                           g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
+        else
+          SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_PREC>), dim3(g.gridB), dim3(256), g.ldsB, s,
+                           g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
+      }
+      if (g.gridC > 0 && (pm & 4) && !(g.shape & 4) && g.smallC)
+        SKX_TIMED_LAUNCH((k_passC<R, 512, false, MODE_PREC>), dim3(g.gridC), dim3(512), g.ldsC, s,
+                         g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
+      if (g.gridC > 0 && (pm & 4) && !(g.shape & 4) && g.bigC)
+        SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_PREC>), dim3(g.gridC), dim3(512), BIG_LDS, s,
+                         g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+    }
   }
-  else if (b.gridB > 0 && (mask & 2) && wide_b<R>(b))
-    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_PREC>), dim3(b.gridB), dim3(512), b.ldsB, s,
-                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  else if (b.gridB > 0 && (mask & 2))
-    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_PREC>), dim3(b.gridB), dim3(256), b.ldsB, s,
-                       b.dev, b.firstB, b.nsolve, b.gridB, b.twbank);
-  if (b.gridC > 0 && (mask & 4) && (b.shape & 4))
-    SKX_TIMED_LAUNCH((k_passCf<R, 64, 64, MODE_PREC>), dim3(b.gridC), dim3(256),
-                       (64 * CRad<64>::PL + 128) * sizeof(R) * 2, s, b.dev, b.firstC, b.nsolve, b.gridC,
-                       b.twbank);
-  else if (b.gridC > 0 && (mask & 4) && b.smallC)
-    SKX_TIMED_LAUNCH((k_passC<R, 512, false, MODE_PREC>), dim3(b.gridC), dim3(512), b.ldsC, s,
-                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank, b.fd);
-  if (b.gridC > 0 && (mask & 4) && b.bigC)
-    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_PREC>), dim3(b.gridC), dim3(512), BIG_LDS, s,
-                       b.dev, b.firstC, b.nsolve, b.gridC, b.twbank);
   return hipGetLastError();
 }
 

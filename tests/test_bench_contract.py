@@ -17,15 +17,30 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in msg["error"]
 
 
-def test_pass_bytes_of_the_scan_system():
+def test_pass_bytes_follow_the_three_pass_model():
+    """Per grid point of one FP64 evaluation with four fields: pass A
+    8 (phi) + 32 (half spectra), pass B 64 + 8 (V_loc), pass C 32 + 16 --
+    160 B in all, 168 with the trial direction d -- up to the Nyquist
+    column (33 of 64 complex columns per half spectrum); FP32 half."""
     sys.path.insert(0, ROOT)
     import bench
     from paper_2601_23002_amd import workloads as W
     s = W.config_scan(64)[0]
     M, H = 64 ** 3, 64 * 64 * 33
-    point, a, b, c = bench.pass_bytes(s, 8, 4, True, False)
     spec = 2 * 8 * H
-    assert point == 8 * M + 5 * 8 * M            # phi in; phi_t, v0, c_P, n^a, c_Q out
-    assert a == 2 * 8 * M + 4 * spec              # phi_t and n^a in, 4 half spectra out
-    assert b == 2 * 4 * spec + spec               # 4 spectra in and out, V_loc in
-    assert c == 4 * spec + 4 * 8 * M + 8 * M      # spectra, phi_t, v0, c_P, c_Q in; dE/dphi out
+    a, b, c = bench.pass_bytes(s, 8, 4, True, False)
+    assert a == 8 * M + 4 * spec
+    assert b == 2 * 4 * spec + spec
+    assert c == 4 * spec + 2 * 8 * M
+    at, bt, ct = bench.pass_bytes(s, 8, 4, True, True)
+    assert at == a + 8 * M and bt == b and ct == c
+    # 160 B per point plus the Nyquist column of the 17 half-spectrum crossings
+    assert a + b + c == 160 * M + 17 * 16 * 64 * 64
+    a4, b4, c4 = bench.pass_bytes(s, 4, 4, True, False)
+    assert 2 * (a4 + b4 + c4) == a + b + c
+
+
+def test_unknown_leg_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2

@@ -119,3 +119,80 @@ def test_shape64_optimisation_reaches_same_minimum(precision):
     (e1, r1), (e0, r0) = out[True], out[False]
     assert abs(e1 - e0) / 64 <= 1e-9              # far inside 1e-6 Ha/atom
     assert np.max(np.abs(r1 - r0)) <= 1e-5 * np.max(np.abs(r0))
+
+
+# ----------------------------------------------------------------------------
+# The other compile-time lengths (radix orders 8-3-2, 8-3-3, 8-5-2; pass B
+# on the shaped kernel where whole column blocks fit below the Nyquist
+# column: FP64 48 and 80)
+# ----------------------------------------------------------------------------
+_ORACLE = {}
+
+
+def _shaped_case(n):
+    if n not in _ORACLE:
+        from oracle.functional import Problem
+        s = W.uniform_system(max(8, n * n * n // 4096), 1.0, 0.3, 2.0, 2.0, n, seed=30 + n,
+                             beta=1.3)
+        phi = W.random_phi(s, 31 + n, amp=0.4)
+        _ORACLE[n] = (s, phi) + Problem(s).evaluate(phi)
+    return _ORACLE[n]
+
+
+@pytest.mark.parametrize("n", [48, 72, 80])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_shaped_lengths_match_oracle(n, precision):
+    skx, torch = _lib()
+    prec = skx.FP64 if precision == "fp64" else skx.FP32
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    _say(f"case: {n}^3 evaluation, shape kernels, {precision}")
+    s, phi, e_ref, g_ref = _shaped_case(n)
+    scale = sum(abs(e_ref[k]) for k in TERMS)
+    for shape in (7, 5, 0):                       # all, passes A and C, none
+        e, g = _eval(skx, torch, s, phi, prec, shape)
+        for k in TERMS:
+            assert abs(e[k] - e_ref[k]) <= tol * max(abs(e_ref[k]), 1e-3 * scale), (shape, k)
+        assert abs(e["mu"] - e_ref["mu"]) <= tol * max(1.0, abs(e_ref["mu"])) * 10, shape
+        assert np.max(np.abs(g - g_ref)) <= tol * np.max(np.abs(g_ref)) * 10, shape
+
+
+@pytest.mark.parametrize("n", [48, 72, 80])
+def test_shaped_lengths_equal_runtime_kernels_at_every_point(n):
+    """FP64 gradient of the shaped kernels against the runtime-shaped ones on
+    every grid point (1e-12 of the gradient's scale), with beta = 0 and no
+    vW term as well (absent fields skipped consistently)."""
+    skx, torch = _lib()
+    for beta, terms in ((1.3, W.TERM_ALL), (0.0, W.TERM_ALL & ~W.TERM_VW)):
+        s = W.uniform_system(16, 1.0, 0.3, 2.0, 2.0, n, seed=40 + n, beta=beta, terms=terms)
+        phi = W.random_phi(s, 41 + n, amp=0.5)
+        _say(f"case: {n}^3 shape vs runtime kernels, beta {beta}, terms {terms}")
+        e1, g1 = _eval(skx, torch, s, phi, skx.FP64, 7)
+        e0, g0 = _eval(skx, torch, s, phi, skx.FP64, 0)
+        assert np.max(np.abs(g1 - g0)) <= 1e-12 * np.max(np.abs(g0))
+        for k in TERMS:
+            assert abs(e1[k] - e0[k]) <= 1e-12 * max(1.0, abs(e0[k])), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
+    """A batch over every kernel family (48, 72, 80 shaped; 60 runtime):
+    solved with the shaped kernels on and off, each solve reaches the same
+    minimum (far inside 1e-6 Ha/atom)."""
+    skx, torch = _lib()
+    prec = skx.FP64 if precision == "fp64" else skx.MIXED
+    systems = [W.uniform_system(12, 1.0, 0.3, 2.0, 2.0, n, seed=50 + n) for n in (48, 60, 72, 80)]
+    out = {}
+    for shape in (7, 0):
+        _say(f"case: shaped lengths, batched {precision} solves, shape kernels {shape}")
+        old = skx.set_shape_kernels(shape)
+        try:
+            ctxs = [skx.Context(0).setup(x, precision=prec) for x in systems]
+            rhos = [torch.empty(x.n, dtype=torch.float64, device="cuda") for x in systems]
+            res = skx.run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000)
+        finally:
+            skx.set_shape_kernels(old)
+        assert all(r["status"] == skx.OK for r in res), res
+        out[shape] = [(r["energy"]["free_energy"], x.cpu().numpy()) for r, x in zip(res, rhos)]
+    for (e1, r1), (e0, r0), x in zip(out[7], out[0], systems):
+        assert abs(e1 - e0) / len(x.zval) <= 1e-9
+        assert np.max(np.abs(r1 - r0)) <= 1e-5 * np.max(np.abs(r0))
