@@ -197,6 +197,20 @@ constexpr size_t LDS_MAX = 160 * 1024;
 // partial sums.
 int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
 
+// Width (complex columns) of pass B's column blocks, which also aligns the
+// spectrum pitch: 8 in FP64 and 16 in FP32, or for the cubic lengths with
+// compile-time-shaped kernels the largest width up to that which divides
+// n/2, so that their pass B tiles whole blocks below the Nyquist column
+// (72: 4; 48 and 80 in FP32: 8).
+int block_width(int n1, int n2, int n3, int prec) {
+  const int tk = prec == 0 ? 8 : 16;
+  if (n1 != n2 || n2 != n3) return tk;
+  if (n1 != 48 && n1 != 64 && n1 != 72 && n1 != 80) return tk;
+  for (int w = tk; w >= 4; w /= 2)
+    if ((n1 / 2) % w == 0) return w;
+  return tk;
+}
+
 struct ArenaLayout {
   size_t o_phi, o_phit, o_grad, o_r, o_rt, o_pr, o_prt, o_d, o_vpt, o_fpt, o_qpt, o_npa, o_S, o_Y;
   size_t o_spec, o_vloc, o_pA, o_pB, o_pC, o_pU, o_pD, total;
@@ -204,7 +218,7 @@ struct ArenaLayout {
 
 ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   const size_t rsz = prec == 0 ? 8 : 4;
-  const int tk = prec == 0 ? 8 : 16;
+  const int tk = block_width(n1, n2, n3, prec);
   const int nh = n3 / 2 + 1;
   const int pitch = (int)align_up(nh, tk);
   const long long M = (long long)n1 * n2 * n3;
@@ -238,7 +252,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   Instance &I = c->inst[prec];
   const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
   const size_t rsz = prec == 0 ? 8 : 4;
-  const int tk = prec == 0 ? 8 : 16;
+  const int tk = block_width(n1, n2, n3, prec);
   const int nh = n3 / 2 + 1;
   const int pitch = (int)align_up(nh, tk);
   const long long M = (long long)n1 * n2 * n3;
@@ -335,9 +349,9 @@ int shaped_length(const SolveDev &h) {
   }
 }
 
-// Pass B's compile-time-shaped kernel needs whole column blocks of the
-// precision's width below the Nyquist column.
-bool shaped_b_ok(int n, int prec) { return (n / 2) % (prec == 0 ? 8 : 16) == 0; }
+// Pass B's compile-time-shaped kernel needs whole column blocks below the
+// Nyquist column.
+bool shaped_b_ok(int n, int tk) { return (n / 2) % tk == 0; }
 
 // Prefix sums of passes A, B, C of one group, its runtime-shaped LDS sizes
 // and kernel choices.
@@ -414,13 +428,16 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     fv[i + 1] = fv[i] + hs[i].nwg_vec;
     fu[i + 1] = fu[i] + hs[i].nwg_upd;
   }
-  // pass groups: the runtime-shaped solves, then one group per length
+  // pass groups: the runtime-shaped solves (one group per column-block
+  // width), then one group per compile-time length
+  auto key_of = [](const SolveDev &h) { const int k = shaped_length(h); return k ? k : -h.tk; };
   std::vector<int> keys;
   for (const SolveDev &h : hs) {
-    const int k = shaped_length(h);
+    const int k = key_of(h);
     if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
   }
   std::sort(keys.begin(), keys.end());
+  if ((int)keys.size() > MAX_GROUPS) return fail(c, SKX_E_DEVICE, "too many pass groups");
   std::vector<SolveDev> part;
   std::vector<int> all;
   all.insert(all.end(), fv.begin(), fv.end());
@@ -431,15 +448,16 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
   for (int gi = 0; gi < bl.ngroup; ++gi) {
     PassGroup &g = bl.grp[gi];
     g = PassGroup{};
-    g.shapeN = keys[gi];
+    g.shapeN = std::max(keys[gi], 0);
     std::vector<SolveDev> sub;
     for (const SolveDev &h : hs)
-      if (shaped_length(h) == g.shapeN) sub.push_back(h);
+      if (key_of(h) == keys[gi]) sub.push_back(h);
+    g.tk = sub[0].tk;
     std::vector<int> fa, fb, fc;
     int rc = fill_group(c, sub, prec, g, fa, fb, fc);
     if (rc) return rc;
     if (g.shapeN)
-      g.shape = (g_shape_kernels & 5) | ((g_shape_kernels & 2) && shaped_b_ok(g.shapeN, prec) ? 2 : 0);
+      g.shape = (g_shape_kernels & 5) | ((g_shape_kernels & 2) && shaped_b_ok(g.shapeN, g.tk) ? 2 : 0);
     Off o;
     o.desc = part.size();
     part.insert(part.end(), sub.begin(), sub.end());

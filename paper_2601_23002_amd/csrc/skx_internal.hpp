@@ -140,7 +140,7 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
-constexpr int MAX_GROUPS = 5;      // pass launch groups: runtime-shaped + 4 compile-time lengths
+constexpr int MAX_GROUPS = 7;      // pass launch groups: runtime-shaped (by block width) + 4 lengths
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the
@@ -152,6 +152,7 @@ struct PassGroup {
   int nsolve;
   int shapeN;                      // 0: runtime-shaped; else the compile-time length
   int shape;                       // passes (1 A, 2 B, 4 C) on the compile-time-shaped kernels
+  int tk;                          // pass B column-block width of every solve of the group
   int gridA, gridB, gridC;         // work items (workgroups) of the runtime-shaped passes
   const int *firstA, *firstB, *firstC;  // device prefix sums (nsolve+1)
   size_t ldsA, ldsB, ldsC;

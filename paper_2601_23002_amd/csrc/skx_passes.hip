@@ -363,12 +363,91 @@ __device__ __forceinline__ void load_plane_f(V *buf, const SKX_G V *src, int pit
 }
 
 // ---------------------------------------------------------------------------
-// Pointwise pass (first kernel of pass A), one workgroup per CHUNK points of
-// a solve: the trial point phi_t = ca phi + cb d, n = phi_t^2, f = n^a, the
-// local energy densities (finite-T TF through the Fermi-Dirac table, PZ LDA),
-// the local potential v0 = T eta + v_xc and the assembly coefficients
-// c_P = 2 a f / phi_t, c_Q = c_P (n - n0) + 2 phi_t (f - n0^a). Every point
-// is computed once; the transform kernel and pass C read the results.
+// The pointwise terms of one grid point at the trial point phi_t: the local
+// energy densities (finite-T TF through the Fermi-Dirac table, PZ LDA) added
+// to the running sums, the local potential v0 = T eta + v_xc, f = n^a and
+// the assembly coefficients c_P = 2 a f / phi_t (-> 0 as phi_t -> 0) and
+// c_Q = c_P (n - n0) + 2 phi_t (f - n0^a). Shared by the pointwise kernel
+// and the compile-time-shaped pass A, so both compute the same values.
+// ---------------------------------------------------------------------------
+struct PointCfg {
+  double T, lnnT;
+  bool do_tf, do_xc, xcj, a56, need_f, need_h;
+};
+
+__device__ __forceinline__ PointCfg point_cfg(const SolveDev &S) {
+  PointCfg c;
+  c.T = S.T;
+  c.lnnT = S.lnnT;
+  c.do_tf = (S.terms & 1u) != 0;
+  c.do_xc = (S.terms & 64u) != 0;
+  c.xcj = S.xc == 2;       // C1-joined PZ81 branches
+  c.a56 = S.a == 5.0 / 6.0;
+  c.need_f = (S.fields & F_F) != 0;
+  c.need_h = (S.fields & F_H) != 0;
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, R n0, R n0a,
+                                            const FDTable &fd, double &e_tf, double &e_xc,
+                                            double &nel, double &bad, R &v0, R &f, R &cP, R &cQ) {
+  const R n = ph * ph;
+  const double nd = (double)n;
+  double v = 0.0, lx = 0.0, e3 = 0.0;
+  if (!(nd == nd) || nd > 1e300) bad += 1.0;
+  if (nd > 0.0) {
+    nel += nd;
+    // FP32 evaluations take the logarithm in FP32 (its error is below the
+    // FP32 rounding of the potential it feeds)
+    lx = sizeof(R) == 4 ? (double)(0.69314718055994531f * __builtin_amdgcn_logf((float)n))
+                        : log(nd);
+    // FP64: n^(1/3), shared by PZ81 and, for a = 5/6, by n^a
+    if (sizeof(R) == 8 && (c.do_xc || c.a56)) e3 = exp(lx * (1.0 / 3.0));
+    if (c.do_tf) {
+      double eta, psi;
+      bad += fd_lookup(lx - c.lnnT, fd, eta, psi);
+      e_tf += c.T * nd * psi;
+      v += c.T * eta;
+    }
+    if (c.do_xc) {
+      double eps, vx;
+      if (sizeof(R) == 4) {
+        float ef, vf;
+        pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), c.xcj, ef, vf);
+        eps = ef;
+        vx = vf;
+      } else {
+        pz81_ln_e3(lx, e3, c.xcj, eps, vx);
+      }
+      e_xc += nd * eps;
+      v += vx;
+    }
+  }
+  v0 = (R)v;
+  f = (R)0;
+  cP = (R)0;
+  cQ = (R)0;
+  if (c.need_f) {
+    // FP64: n^a = exp(a ln n) with the logarithm taken above; for a = 5/6,
+    // n^a = |phi| n^(1/3) and c_P = 2 a sign(phi) n^(1/3)
+    if (sizeof(R) == 8 && c.a56) {
+      f = (R)(fabs((double)ph) * e3);
+      cP = (ph != (R)0) ? (R)copysign((double)a2 * e3, (double)ph) : (R)0;
+    } else {
+      f = sizeof(R) == 8 ? (nd > 0.0 ? (R)exp((double)a * lx) : (R)0) : rpow(n, a);
+      // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
+      cP = (ph != (R)0) ? a2 * f / ph : (R)0;
+    }
+    if (c.need_h) cQ = cP * (n - n0) + (R)2 * ph * (f - n0a);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise pass (first kernel of pass A on the runtime-shaped kernels), one
+// workgroup per CHUNK points of a solve: the trial point phi_t = ca phi + cb d
+// and point_terms; writes phi_t, v0, c_P, c_Q and n^a for the transform
+// kernel and pass C.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, int nsolve,
@@ -396,10 +475,7 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
   SKX_G R *qps = gptr<R>(S.qpt) + g0;
   SKX_G R *nas = gptr<R>(S.npa) + g0;
   const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
-  const bool a56 = S.a == 5.0 / 6.0;
-  const bool do_tf = (S.terms & 1u) != 0, do_xc = (S.terms & 64u) != 0;
-  const bool xcj = S.xc == 2;       // C1-joined PZ81 branches
-  const bool need_f = (S.fields & F_F) != 0, need_h = (S.fields & F_H) != 0;
+  const PointCfg pc = point_cfg(S);
   constexpr int PER = CHUNK / NT;
   R pv[PER], dv[PER];
 #pragma unroll
@@ -423,54 +499,13 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
       if (u == w) { p0 = pv[w]; if (use_d) d0 = dv[w]; }
     const R ph = use_d ? (R)(ca * (double)p0 + cb * (double)d0) : (R)(ca * (double)p0);
     phit[e] = ph;
-    const R n = ph * ph;
-    const double nd = (double)n;
-    double v = 0.0, lx = 0.0, e3 = 0.0;
-    if (!(nd == nd) || nd > 1e300) bad += 1.0;
-    if (nd > 0.0) {
-      nel += nd;
-      // FP32 evaluations take the logarithm in FP32 (its error is below
-      // the FP32 rounding of the potential it feeds)
-      lx = sizeof(R) == 4 ? (double)(0.69314718055994531f * __builtin_amdgcn_logf((float)n))
-                          : log(nd);
-      // FP64: n^(1/3), shared by PZ81 and, for a = 5/6, by n^a
-      if (sizeof(R) == 8 && (do_xc || a56)) e3 = exp(lx * (1.0 / 3.0));
-      if (do_tf) {
-        double eta, psi;
-        bad += fd_lookup(lx - S.lnnT, fd, eta, psi);
-        e_tf += S.T * nd * psi;
-        v += S.T * eta;
-      }
-      if (do_xc) {
-        double eps, vx;
-        if (sizeof(R) == 4) {
-          float ef, vf;
-          pz81_lnf(0.69314718055994531f * __builtin_amdgcn_logf((float)n), xcj, ef, vf);
-          eps = ef;
-          vx = vf;
-        } else {
-          pz81_ln_e3(lx, e3, xcj, eps, vx);
-        }
-        e_xc += nd * eps;
-        v += vx;
-      }
-    }
-    v0s[e] = (R)v;
-    if (need_f) {
-      // FP64: n^a = exp(a ln n) with the logarithm taken above; for a = 5/6,
-      // n^a = |phi| n^(1/3) and c_P = 2 a sign(phi) n^(1/3)
-      R f, cP;
-      if (sizeof(R) == 8 && a56) {
-        f = (R)(fabs((double)ph) * e3);
-        cP = (ph != (R)0) ? (R)copysign((double)a2 * e3, (double)ph) : (R)0;
-      } else {
-        f = sizeof(R) == 8 ? (nd > 0.0 ? (R)exp((double)a * lx) : (R)0) : rpow(n, a);
-        // c_P = 2 a sign(phi) |phi|^(2a-1) = 2 a f / phi (-> 0 as phi -> 0)
-        cP = (ph != (R)0) ? a2 * f / ph : (R)0;
-      }
+    R v0, f, cP, cQ;
+    point_terms<R>(ph, pc, a, a2, n0, n0a, fd, e_tf, e_xc, nel, bad, v0, f, cP, cQ);
+    v0s[e] = v0;
+    if (pc.need_f) {
       nas[e] = f;
       fps[e] = cP;
-      if (need_h) qps[e] = cP * (n - n0) + (R)2 * ph * (f - n0a);
+      if (pc.need_h) qps[e] = cQ;
     }
   }
   double vsum[PART_A] = {e_tf, e_xc, nel, bad};
@@ -1901,7 +1936,13 @@ __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *t
 // (about three workgroups' worth of waves per CU: FP64 at 64^3 fits 168
 // VGPRs with three 256-thread groups)
 template <typename R, int N, int MODE>
-__global__ __launch_bounds__(CS<N>::NT, (CS<N>::NW == 4 ? 3 : (CS<N>::NW == 6 ? 2 : 1)))
+#ifndef SKX_PASSC_WAVES6
+#define SKX_PASSC_WAVES6 2
+#endif
+#ifndef SKX_PASSC_WAVES8
+#define SKX_PASSC_WAVES8 1
+#endif
+__global__ __launch_bounds__(CS<N>::NT, (CS<N>::NW == 4 ? 3 : (CS<N>::NW == 6 ? SKX_PASSC_WAVES6 : SKX_PASSC_WAVES8)))
 void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
   typedef CS<N> K;
@@ -2054,11 +2095,19 @@ template <typename R> static bool wide_b(const PassGroup &g) {
 static bool wide_a(const PassGroup &g) { return g.ldsA > 45 * 1024; }
 
 // Compile-time-shaped pass kernels of one length N over one group.
+// Pass B column-block width of a compile-time length: the largest up to 8
+// (FP64) or 16 (FP32) that divides N/2 (the host's block_width).
+template <int N, typename R> constexpr int shaped_tk() {
+  int tk = sizeof(R) == 8 ? 8 : 16;
+  while (tk > 4 && (N / 2) % tk != 0) tk /= 2;
+  return tk;
+}
+
 template <typename R, int N>
 static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                           int mode) {
   typedef typename Vec2<R>::T V;
-  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
+  constexpr int TK = shaped_tk<N, R>();
   constexpr int NT = CS<N>::NT;
   const size_t lds_plane = CS<N>::lds_plane(sizeof(V));
   if (mode == MODE_EVAL) {
@@ -2071,7 +2120,7 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
                      g.firstC, g.nsolve, g.gridC, twbank);
   }
   if constexpr ((N / 2) % TK == 0) {
-    if (g.gridB > 0 && (mask & 2) && (g.shape & 2)) {
+    if (g.gridB > 0 && (mask & 2) && (g.shape & 2) && g.tk == TK) {
       const int gb = g.nsolve * (N * (N / 2 / TK) + N / 4);
       const size_t lb = (NFIELD * N * (TK + 1) + N) * sizeof(V);
       if (mode == MODE_EVAL)
@@ -2104,12 +2153,23 @@ static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_
   }
 }
 
+// Runtime-shaped pass B of one group (column blocks of TK, the group's
+// width; every solve of a group has the same).
+template <typename R, int TK, int MODE>
+static void launch_passB_runtime(const PassGroup &g, const double *twbank, hipStream_t s) {
+  if (wide_b<R>(g))
+    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE>), dim3(g.gridB), dim3(512), g.ldsB, s, g.dev,
+                     g.firstB, g.nsolve, g.gridB, twbank);
+  else
+    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE>), dim3(g.gridB), dim3(256), g.ldsB, s, g.dev,
+                     g.firstB, g.nsolve, g.gridB, twbank);
+}
+
 // Runtime-shaped (and chunked) pass kernels over one group, for the passes
 // in `mask` (1|16 pass A's transform, 2 pass B, 4 pass C) that the group
 // does not run on compile-time-shaped kernels.
 template <typename R>
 static void launch_eval_runtime(const PassGroup &g, const BatchLaunch &b, hipStream_t s, int mask) {
-  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   constexpr int NTC = 512;
   if (g.gridA > 0 && (mask & 16) && !(g.shape & 1)) {
     if (g.smallA && wide_a(g))
@@ -2123,12 +2183,11 @@ static void launch_eval_runtime(const PassGroup &g, const BatchLaunch &b, hipStr
                        g.dev, g.firstA, g.nsolve, g.gridA, b.twbank);
   }
   if (g.gridB > 0 && (mask & 2) && !(g.shape & 2)) {
-    if (wide_b<R>(g))
-      SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_EVAL>), dim3(g.gridB), dim3(512), g.ldsB, s,
-                       g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
-    else
-      SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_EVAL>), dim3(g.gridB), dim3(256), g.ldsB, s,
-                       g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
+    switch (g.tk) {
+      case 4: launch_passB_runtime<R, 4, MODE_EVAL>(g, b.twbank, s); break;
+      case 8: launch_passB_runtime<R, 8, MODE_EVAL>(g, b.twbank, s); break;
+      default: launch_passB_runtime<R, 16, MODE_EVAL>(g, b.twbank, s); break;
+    }
   }
   if (g.gridC > 0 && (mask & 4) && !(g.shape & 4) && g.smallC) {
     // In FP32 two 512-thread groups share a CU; when the last round of
@@ -2178,7 +2237,6 @@ static hipError_t launch_eval_t(const BatchLaunch &b, hipStream_t s, int mask) {
 
 template <typename R>
 static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
-  constexpr int TK = sizeof(R) == 8 ? 8 : 16;
   for (const int pm : {1, 2, 4}) {
     if (!(mask & pm)) continue;
     for (int gi = 0; gi < b.ngroup; ++gi) {
@@ -2197,12 +2255,11 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
                            g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
       }
       if (g.gridB > 0 && (pm & 2) && !(g.shape & 2)) {
-        if (wide_b<R>(g))
-          SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE_PREC>), dim3(g.gridB), dim3(512), g.ldsB, s,
-                           g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
-        else
-          SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE_PREC>), dim3(g.gridB), dim3(256), g.ldsB, s,
-                           g.dev, g.firstB, g.nsolve, g.gridB, b.twbank);
+        switch (g.tk) {
+          case 4: launch_passB_runtime<R, 4, MODE_PREC>(g, b.twbank, s); break;
+          case 8: launch_passB_runtime<R, 8, MODE_PREC>(g, b.twbank, s); break;
+          default: launch_passB_runtime<R, 16, MODE_PREC>(g, b.twbank, s); break;
+        }
       }
       if (g.gridC > 0 && (pm & 4) && !(g.shape & 4) && g.smallC)
         SKX_TIMED_LAUNCH((k_passC<R, 512, false, MODE_PREC>), dim3(g.gridC), dim3(512), g.ldsC, s,
