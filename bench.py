@@ -417,6 +417,7 @@ def batched_leg(args, skx, torch, systems, label, timed_steps, want_roofline):
             if nl > 0 and msk > 0:
                 per[k] = round(acct.bytes[k] / timed_steps / nl / (msk / 1e3 / nl) / 1e9 / HBM_PEAK_GBS, 4)
         out["frac_by_pass_profiled_step"] = per
+        out["alg_bytes_per_step"] = {k: round(v / timed_steps) for k, v in acct.bytes.items()}
 
     def extra(graphs):
         old = skx.set_graphs(graphs)

@@ -205,7 +205,10 @@ int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
 int block_width(int n1, int n2, int n3, int prec) {
   const int tk = prec == 0 ? 8 : 16;
   if (n1 != n2 || n2 != n3) return tk;
-  if (n1 != 48 && n1 != 64 && n1 != 72 && n1 != 80) return tk;
+  switch (n1) {
+    case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: case 80: break;
+    default: return tk;
+  }
   for (int w = tk; w >= 4; w /= 2)
     if ((n1 / 2) % w == 0) return w;
   return tk;
@@ -344,7 +347,7 @@ int shaped_length(const SolveDev &h) {
   if (!g_shape_kernels || g_chunk_planes || h.debug) return 0;
   if (h.n1 != h.n2 || h.n2 != h.n3) return 0;
   switch (h.n1) {
-    case 48: case 64: case 72: case 80: return h.n1;
+    case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: case 80: return h.n1;
     default: return 0;
   }
 }

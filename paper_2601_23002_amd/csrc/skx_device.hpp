@@ -492,17 +492,26 @@ template <int... Rs> struct CStages<RList<Rs...>> {
 //       >= N/2 + 1; N/2 + 4 spreads the column transforms (adjacent
 //       columns of rows one pitch apart) and the row-pair transforms over
 //       the LDS banks.
-// 64 holds the scan workload; 48, 72 and 80 are the grids most of the
-// ensemble's and the serving stream's points fall on.
+//   CW  waves per SIMD pass C's launch bound asks for: as many as its
+//       register-resident dE/dphi (N^2 / (64 NW) points per lane) allows
+//       without spilling.
+// 64 holds the scan workload; 36-80 are the grids of the thermal
+// ensemble (h = 0.25 bohr) and of the smaller serving requests.
 template <int N> struct CShape;
-template <> struct CShape<48> { typedef RList<8, 3, 2> L; static constexpr int NW = 4, PL = 28; };
-template <> struct CShape<64> { typedef RList<8, 8> L; static constexpr int NW = 4, PL = 36; };
-template <> struct CShape<72> { typedef RList<8, 3, 3> L; static constexpr int NW = 6, PL = 40; };
-template <> struct CShape<80> { typedef RList<8, 5, 2> L; static constexpr int NW = 8, PL = 44; };
+template <> struct CShape<36> { typedef RList<4, 3, 3> L; static constexpr int NW = 3, PL = 22, CW = 3; };
+template <> struct CShape<40> { typedef RList<8, 5> L; static constexpr int NW = 4, PL = 24, CW = 3; };
+template <> struct CShape<48> { typedef RList<8, 3, 2> L; static constexpr int NW = 4, PL = 28, CW = 3; };
+template <> struct CShape<50> { typedef RList<2, 5, 5> L; static constexpr int NW = 5, PL = 29, CW = 3; };
+template <> struct CShape<54> { typedef RList<2, 3, 3, 3> L; static constexpr int NW = 3, PL = 31, CW = 2; };
+template <> struct CShape<60> { typedef RList<4, 3, 5> L; static constexpr int NW = 6, PL = 34, CW = 2; };
+template <> struct CShape<64> { typedef RList<8, 8> L; static constexpr int NW = 4, PL = 36, CW = 3; };
+template <> struct CShape<72> { typedef RList<8, 3, 3> L; static constexpr int NW = 6, PL = 40, CW = 2; };
+template <> struct CShape<80> { typedef RList<8, 5, 2> L; static constexpr int NW = 8, PL = 44, CW = 1; };
 // derived per-length constants
 template <int N> struct CS {
   typedef typename CShape<N>::L L;
   static constexpr int NW = CShape<N>::NW, NT = 64 * NW, PL = CShape<N>::PL, C = N / 2;
+  static constexpr int CW = CShape<N>::CW;
   static constexpr int R0 = RFirst<L>::value;      // first stage
   static constexpr int RL = RLast<L>::value;       // last stage
   static constexpr int NSL = N / RL;               // span of the last stage

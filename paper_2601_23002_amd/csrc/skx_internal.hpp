@@ -140,7 +140,7 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
-constexpr int MAX_GROUPS = 7;      // pass launch groups: runtime-shaped (by block width) + 4 lengths
+constexpr int MAX_GROUPS = 12;     // pass launch groups: runtime-shaped (by block width) + 9 lengths
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the

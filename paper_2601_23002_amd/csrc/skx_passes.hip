@@ -1933,16 +1933,10 @@ __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *t
   }
 }
 
-// (about three workgroups' worth of waves per CU: FP64 at 64^3 fits 168
-// VGPRs with three 256-thread groups)
+// (the launch bound asks for CShape's CW waves per SIMD: FP64 at 64^3 fits
+// 168 VGPRs with three 256-thread groups)
 template <typename R, int N, int MODE>
-#ifndef SKX_PASSC_WAVES6
-#define SKX_PASSC_WAVES6 2
-#endif
-#ifndef SKX_PASSC_WAVES8
-#define SKX_PASSC_WAVES8 1
-#endif
-__global__ __launch_bounds__(CS<N>::NT, (CS<N>::NW == 4 ? 3 : (CS<N>::NW == 6 ? SKX_PASSC_WAVES6 : SKX_PASSC_WAVES8)))
+__global__ __launch_bounds__(CS<N>::NT, CS<N>::CW)
 void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const double *twbank) {
   typedef typename Vec2<R>::T V;
   typedef CS<N> K;
@@ -2145,7 +2139,12 @@ template <typename R>
 static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                             int mode) {
   switch (g.shapeN) {
+    case 36: launch_shaped<R, 36>(g, twbank, s, mask, mode); break;
+    case 40: launch_shaped<R, 40>(g, twbank, s, mask, mode); break;
     case 48: launch_shaped<R, 48>(g, twbank, s, mask, mode); break;
+    case 50: launch_shaped<R, 50>(g, twbank, s, mask, mode); break;
+    case 54: launch_shaped<R, 54>(g, twbank, s, mask, mode); break;
+    case 60: launch_shaped<R, 60>(g, twbank, s, mask, mode); break;
     case 64: launch_shaped<R, 64>(g, twbank, s, mask, mode); break;
     case 72: launch_shaped<R, 72>(g, twbank, s, mask, mode); break;
     case 80: launch_shaped<R, 80>(g, twbank, s, mask, mode); break;

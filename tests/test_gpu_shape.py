@@ -122,10 +122,11 @@ def test_shape64_optimisation_reaches_same_minimum(precision):
 
 
 # ----------------------------------------------------------------------------
-# The other compile-time lengths (radix orders 8-3-2, 8-3-3, 8-5-2; pass B
-# on the shaped kernel where whole column blocks fit below the Nyquist
-# column: FP64 48 and 80)
+# The other compile-time lengths (radix orders 4-3-3, 8-5, 8-3-2, 2-5-5,
+# 2-3-3-3, 4-3-5, 8-3-3, 8-5-2; pass B on the shaped kernel where whole
+# column blocks fit below the Nyquist column: 40, 48, 72, 80)
 # ----------------------------------------------------------------------------
+SHAPED = [36, 40, 48, 50, 54, 60, 72, 80]
 _ORACLE = {}
 
 
@@ -139,7 +140,7 @@ def _shaped_case(n):
     return _ORACLE[n]
 
 
-@pytest.mark.parametrize("n", [48, 72, 80])
+@pytest.mark.parametrize("n", SHAPED)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_shaped_lengths_match_oracle(n, precision):
     skx, torch = _lib()
@@ -156,7 +157,7 @@ def test_shaped_lengths_match_oracle(n, precision):
         assert np.max(np.abs(g - g_ref)) <= tol * np.max(np.abs(g_ref)) * 10, shape
 
 
-@pytest.mark.parametrize("n", [48, 72, 80])
+@pytest.mark.parametrize("n", SHAPED)
 def test_shaped_lengths_equal_runtime_kernels_at_every_point(n):
     """FP64 gradient of the shaped kernels against the runtime-shaped ones on
     every grid point (1e-12 of the gradient's scale), with beta = 0 and no
@@ -175,12 +176,12 @@ def test_shaped_lengths_equal_runtime_kernels_at_every_point(n):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
-    """A batch over every kernel family (48, 72, 80 shaped; 60 runtime):
+    """A batch over every kernel family (36, 54, 72, 80 shaped; 90 runtime):
     solved with the shaped kernels on and off, each solve reaches the same
     minimum (far inside 1e-6 Ha/atom)."""
     skx, torch = _lib()
     prec = skx.FP64 if precision == "fp64" else skx.MIXED
-    systems = [W.uniform_system(12, 1.0, 0.3, 2.0, 2.0, n, seed=50 + n) for n in (48, 60, 72, 80)]
+    systems = [W.uniform_system(12, 1.0, 0.3, 2.0, 2.0, n, seed=50 + n) for n in (36, 54, 72, 80, 90)]
     out = {}
     for shape in (7, 0):
         _say(f"case: shaped lengths, batched {precision} solves, shape kernels {shape}")
