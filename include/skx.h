@@ -87,6 +87,14 @@ enum {
  *                   e_c = (1 - w) e_dense + w e_dilute, v_c the exact potential
  *                   of that e_c; equal to SKX_XC_PZ81 outside the window. */
 enum { SKX_XC_NONE = 0, SKX_XC_PZ81 = 1, SKX_XC_PZ81_C1 = 2 };
+/* Precision of the fields and transforms (sums and the optimiser's scalar
+ * work are FP64 throughout).
+ *   SKX_FP64   every field FP64.
+ *   SKX_FP32   every field FP32.
+ *   SKX_MIXED  FP32 until ||r|| < fp32_switch_gtol or stalls, then FP64 from
+ *              that point to gtol (the precision policy of the batched path);
+ *              the FP64 phase keeps its L-BFGS pairs (s, P y) in FP32, every
+ *              inner product taken with the stored values. */
 enum { SKX_FP64 = 0, SKX_FP32 = 1, SKX_MIXED = 2 };
 enum { SKX_RHO = 0, SKX_SQRT_RHO = 1 };
 

@@ -219,7 +219,9 @@ struct ArenaLayout {
   size_t o_spec, o_vloc, o_pA, o_pB, o_pC, o_pU, o_pD, total;
 };
 
-ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
+// own_hist false: no history arrays (the FP64 instance of a mixed solve
+// keeps its S, P Y in the FP32 instance's arrays, stored as FP32).
+ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m, bool own_hist) {
   const size_t rsz = prec == 0 ? 8 : 4;
   const int tk = block_width(n1, n2, n3, prec);
   const int nh = n3 / 2 + 1;
@@ -236,7 +238,8 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   L.o_r = take(rsz * M); L.o_rt = take(rsz * M); L.o_pr = take(rsz * M); L.o_prt = take(rsz * M);
   L.o_d = take(rsz * M); L.o_vpt = take(rsz * M); L.o_fpt = take(rsz * M);
   L.o_qpt = take(rsz * M); L.o_npa = take(rsz * M);
-  L.o_S = take(rsz * M * m); L.o_Y = take(rsz * M * m);
+  const size_t hist = own_hist ? rsz * M * m : 0;
+  L.o_S = take(hist); L.o_Y = take(hist);
   L.o_spec = take(2 * rsz * H * NFIELD); L.o_vloc = take(2 * rsz * H);
   L.o_pA = take(8 * (size_t)nwg * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
   L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwu * NDOT);
@@ -245,8 +248,8 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m) {
   return L;
 }
 
-size_t instance_bytes(int n1, int n2, int n3, int prec, int m) {
-  return arena_layout(n1, n2, n3, prec, std::max(m, 1)).total +
+size_t instance_bytes(int n1, int n2, int n3, int prec, int m, bool own_hist) {
+  return arena_layout(n1, n2, n3, prec, std::max(m, 1), own_hist).total +
          sizeof(SolveDev) * batch_desc_count(1) + sizeof(OptState) +
          batch_first_count(1) * sizeof(int);
 }
@@ -263,11 +266,13 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   const int nkb = (nh + tk - 1) / tk;
   const int nwg = (int)((M + CHUNK - 1) / CHUNK);
   if (m < 1) m = 1;
-  if (I.mem && I.prec == prec && I.m_alloc >= m && I.h.n1 == n1 && I.h.n2 == n2 && I.h.n3 == n3)
+  const bool own_hist = !(prec == 0 && c->fn.precision == SKX_MIXED);
+  if (I.mem && I.prec == prec && I.m_alloc >= m && I.h.n1 == n1 && I.h.n2 == n2 &&
+      I.h.n3 == n3 && I.own_hist == own_hist)
     return SKX_OK;
   free_instance(I);
   (void)hipSetDevice(c->device);
-  const ArenaLayout A = arena_layout(n1, n2, n3, prec, m);
+  const ArenaLayout A = arena_layout(n1, n2, n3, prec, m, own_hist);
   const size_t off = A.total;
   const size_t o_phi = A.o_phi, o_phit = A.o_phit, o_grad = A.o_grad, o_r = A.o_r, o_rt = A.o_rt;
   const size_t o_pr = A.o_pr, o_prt = A.o_prt, o_d = A.o_d, o_vpt = A.o_vpt, o_fpt = A.o_fpt;
@@ -286,6 +291,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   I.rsz = rsz;
   I.bytes = off;
   I.m_alloc = m;
+  I.own_hist = own_hist;
   char *base = (char *)I.mem;
   SolveDev &h = I.h;
   h = SolveDev{};
@@ -296,7 +302,9 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.M = M; h.H = H;
   h.phi2[0] = base + o_phi; h.phi2[1] = base + o_phit; h.grad = base + o_grad;
   h.r2[0] = base + o_r; h.r2[1] = base + o_rt; h.pr2[0] = base + o_pr; h.pr2[1] = base + o_prt;
-  h.d = base + o_d; h.S = base + o_S; h.Y = base + o_Y;
+  h.d = base + o_d;
+  h.S = own_hist ? base + o_S : nullptr;
+  h.Y = own_hist ? base + o_Y : nullptr;
   h.vpt = base + o_vpt; h.fpt = base + o_fpt; h.qpt = base + o_qpt;
   h.npa = base + o_npa;
   h.spec = base + o_spec; h.vloc = base + o_vloc;
@@ -624,6 +632,21 @@ int autotune(skx_ctx *c, Instance &I) {
 
 // Prepare instance `prec` of a context for a run: buffers, tables, V_loc,
 // descriptor upload for the batch of one.
+// The FP64 instance of a mixed solve takes the FP32 instance's history
+// arrays (the pairs stay FP32 through the refinement, and the pairs of the
+// FP32 phase are there when it starts).
+void link_history(skx_ctx *c) {
+  Instance &I64 = c->inst[0];
+  if (!I64.mem) return;
+  if (I64.own_hist) { I64.h.hist32 = 0; return; }
+  const Instance &I32 = c->inst[1];
+  const bool ok = I32.mem && I32.h.n1 == I64.h.n1 && I32.h.n2 == I64.h.n2 && I32.h.n3 == I64.h.n3;
+  I64.h.S = ok ? I32.h.S : nullptr;
+  I64.h.Y = ok ? I32.h.Y : nullptr;
+  I64.h.mh = ok ? std::min(I64.m_alloc, I32.m_alloc) : 0;
+  I64.h.hist32 = 1;
+}
+
 int prepare(skx_ctx *c, int prec, int m) {
   if (!c->has_cell || !c->has_ions || !c->has_fn)
     return fail(c, SKX_E_STATE, "set_cell, set_ions and set_functional must precede this call");
@@ -638,6 +661,7 @@ int prepare(skx_ctx *c, int prec, int m) {
   rc = ensure_vloc(c, I);
   if (rc) return rc;
   if (g_autotune) rc = autotune(c, I);
+  link_history(c);
   return rc;
 }
 
@@ -746,6 +770,12 @@ void energy_from(const double *e, double e_ii, skx_energy *out) {
 }
 
 // Initialise the optimiser state of one instance (host -> device).
+#ifndef SKX_FP32_STALL_LIMIT
+#define SKX_FP32_STALL_LIMIT 3
+#endif
+#ifndef SKX_FP32_STALL_FACTOR
+#define SKX_FP32_STALL_FACTOR 0.5
+#endif
 void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho, int prec) {
   st = OptState{};
   st.phase = PH_EVAL_INIT;
@@ -765,8 +795,8 @@ void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho
   // 1e-5..1e-3 (growing with the cell volume), where L-BFGS stops
   // converging fast; the FP32 phase ends (and the FP64 refinement starts)
   // once ||r|| fails to halve within 3 iterations.
-  st.stall_limit = prec == 0 ? 150 : 3;
-  st.stall_factor = prec == 0 ? 0.9 : 0.5;
+  st.stall_limit = prec == 0 ? 150 : SKX_FP32_STALL_LIMIT;
+  st.stall_factor = prec == 0 ? 0.9 : SKX_FP32_STALL_FACTOR;
   st.best_r = 1e300;
   st.par = 0;
   st.reset_pending = from_rho ? 2 : 0;
@@ -877,6 +907,8 @@ hipError_t step_sequence(const BatchLaunch &bl, hipStream_t s) {
 // depend on the batch it is in.
 int drive(skx_ctx *c, std::vector<SolveDev> hs, int prec, SolveDev *ddev, int *dfirst,
           int max_steps, hipStream_t s) {
+  for (const SolveDev &h : hs)
+    if (!h.S || !h.Y) return fail(c, SKX_E_STATE, "history arrays missing (mixed solve without its FP32 instance)");
   BatchLaunch bl{};
   int rc = build_batch(c, hs, prec, ddev, dfirst, bl, s);
   if (rc) return rc;

@@ -125,8 +125,9 @@ size_t footprint(const skx_request &r) {
   const int m = std::min(std::max(r.opt.lbfgs_m, 1), MMAX);
   const long long M = (long long)r.n1 * r.n2 * r.n3;
   size_t b = 8 * (size_t)M;                          // finished density
-  if (r.fn.precision != SKX_FP32) b += instance_bytes(r.n1, r.n2, r.n3, 0, m);
-  if (r.fn.precision != SKX_FP64) b += instance_bytes(r.n1, r.n2, r.n3, 1, m);
+  if (r.fn.precision != SKX_FP32)
+    b += instance_bytes(r.n1, r.n2, r.n3, 0, m, r.fn.precision != SKX_MIXED);
+  if (r.fn.precision != SKX_FP64) b += instance_bytes(r.n1, r.n2, r.n3, 1, m, true);
   const int n = std::max(r.n1, std::max(r.n2, r.n3));
   b += 16 * (size_t)(3 * (n / 2) * (n / 2) + 1);     // kernel tables
   return b;

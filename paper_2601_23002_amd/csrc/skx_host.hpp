@@ -23,6 +23,7 @@ struct Instance {
   BatchLaunch bl{};
   bool vloc_ok = false;
   int m_alloc = 0;
+  bool own_hist = true;          // false: S, P Y live in the FP32 instance (mixed)
 };
 
 }  // namespace host
@@ -66,8 +67,9 @@ void free_instance(Instance &I);
 int hip_fail(skx_ctx *c, hipError_t e, const char *what);
 // Buffers, kernel tables and V_loc of precision instance `prec` (0 FP64, 1 FP32).
 int prepare(skx_ctx *c, int prec, int m);
-// Device bytes of one instance (the arena of ensure_instance plus descriptors).
-size_t instance_bytes(int n1, int n2, int n3, int prec, int m);
+// Device bytes of one instance (the arena of ensure_instance plus
+// descriptors); own_hist false for the FP64 instance of a mixed solve.
+size_t instance_bytes(int n1, int n2, int n3, int prec, int m, bool own_hist);
 void init_state(OptState &st, const skx_opt_params &p, double gtol, int from_rho, int prec);
 int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s);

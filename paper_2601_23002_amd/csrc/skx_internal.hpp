@@ -77,12 +77,13 @@ struct SolveDev {
   int big;                         // passes on the chunked plane kernels: 1 A, 2 C
   unsigned terms;
   int xc;                          // 1 published PZ81 fit, 2 its C1-joined branches
+  int hist32;                      // FP64 fields with the history S, P Y stored in FP32
   long long M, H;                  // H = n1*n2*pitch complex entries per spectrum
   double L, V, dV, ne, n0, n0a, T, beta, a, kscale, lnnT, inv_sqrt_ne, sqrt_ne;
   Plan p1, p2, p3;
   double kappa;                    // preconditioner P(G) = 1 / (G^2 + kappa)
   void *phi2[2], *r2[2], *pr2[2];  // current / trial point pairs (see OptState::par)
-  void *grad, *d, *S, *Y;          // real fields (fp64 or fp32); Y holds P y
+  void *grad, *d, *S, *Y;          // real fields (fp64 or fp32; S, Y fp32 if hist32); Y holds P y
   void *vpt;                       // T eta + v_xc at the trial point (pass A -> C)
   void *fpt, *qpt;                 // coefficients c_P, c_Q of the fields P, Q (pass A -> C)
   void *npa;                       // n^a at the trial point (pointwise kernel -> pass A)

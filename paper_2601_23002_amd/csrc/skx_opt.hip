@@ -155,18 +155,14 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
 // L-BFGS needs, in one sweep over the history. Reads the current point
 // (buffers par) and the accepted trial point (buffers 1 - par).
 // ---------------------------------------------------------------------------
-template <typename R, int NT, int MM>
-__global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
-                                               int grid) {
-  __shared__ double sh[64 * (NT / 64)];
-  __shared__ double tot[NDOT];
-  const int item = blockIdx.x;
-  const int s = find_solve(first, nsolve, item);
-  const SolveDev &S = dev[s];
-  const SKX_C OptState *st = cptr<OptState>(S.st);
-  if (st->phase != PH_UPDATE) return;
-  const int tid = threadIdx.x;
-  const int wl = item - first_of(first, s);
+// H is the storage type of the history S, P Y: the field type, or FP32
+// for FP64 fields of a mixed-precision solve. Every inner product that
+// involves a history vector is taken with the stored (rounded) values, the
+// new pair's included, so the compact matrices describe exactly the pairs
+// the direction pass reads back.
+template <typename R, typename H, int NT, int MM>
+__device__ __forceinline__ void update_body(const SolveDev &S, const SKX_C OptState *st, int wl,
+                                            int tid, double *sh, double *tot) {
   const long long g0 = (long long)wl * S.uchunk;
   const long long g1 = min((long long)S.M, g0 + S.uchunk);
   const int par = st->par;
@@ -176,8 +172,8 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
   const SKX_G R *rt = gptr<R>(S.r2[1 - par]);
   const SKX_G R *pr = gptr<R>(S.pr2[par]);
   const SKX_G R *prt = gptr<R>(S.pr2[1 - par]);
-  SKX_G R *Sv = gptr<R>(S.S);
-  SKX_G R *Yv = gptr<R>(S.Y);
+  SKX_G H *Sv = gptr<H>(S.S);
+  SKX_G H *Yv = gptr<H>(S.Y);
   // MM = largest history length of the batch: at most KO = MM - 1 old pairs
   // take part, so only NA sums are carried (laid out in blocks of KO, then
   // the ten new-pair sums) and scattered to the MMAX layout at the end
@@ -205,13 +201,14 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
     int slot[KO > 0 ? KO : 1];
 #pragma unroll
     for (int i = 0; i < KO; ++i) slot[i] = (i < kold) ? ((head - kold + i + 2 * m) % m) : 0;
-    SKX_G R *Snew = Sv + (size_t)head * S.M;
-    SKX_G R *Ynew = Yv + (size_t)head * S.M;
+    SKX_G H *Snew = Sv + (size_t)head * S.M;
+    SKX_G H *Ynew = Yv + (size_t)head * S.M;
     for (long long g = g0 + tid; g < g1; g += NT) {
       const R pt = phit[g], rtg = rt[g], prtg = prt[g];
-      const R sv = pt - phi[g];
+      const H svh = (H)(pt - phi[g]);
       const R yv = rtg - r[g];
-      const R pyv = prtg - pr[g];
+      const H pyh = (H)(prtg - pr[g]);
+      const double sv = (double)svh, pyv = (double)pyh;
 #pragma unroll
       for (int i = 0; i < KO; ++i) {
         if (i < kold) {
@@ -225,18 +222,18 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
           acc[5 * KO + i] += Yi * pt;
         }
       }
-      acc[B + 0] += (double)sv * yv;
+      acc[B + 0] += sv * yv;
       acc[B + 1] += (double)yv * pyv;
-      acc[B + 2] += (double)sv * rtg;
-      acc[B + 3] += (double)pyv * rtg;
-      acc[B + 4] += (double)sv * pt;
-      acc[B + 5] += (double)pyv * pt;
+      acc[B + 2] += sv * rtg;
+      acc[B + 3] += pyv * rtg;
+      acc[B + 4] += sv * pt;
+      acc[B + 5] += pyv * pt;
       acc[B + 6] += (double)rtg * rtg;
       acc[B + 7] += (double)rtg * prtg;
       acc[B + 8] += (double)pt * prtg;
       acc[B + 9] += (double)rtg * pt;
-      Snew[g] = sv;
-      Ynew[g] = pyv;
+      Snew[g] = svh;
+      Ynew[g] = pyh;
     }
   }
   block_reduce_many<NA>(acc, sh, tid, NT, tot);
@@ -250,6 +247,23 @@ __global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, 
     }
     S.partU[wl * NDOT + tid] = v;
   }
+}
+
+template <typename R, int NT, int MM>
+__global__ __launch_bounds__(NT) void k_update(SolveDev *dev, const int *first, int nsolve,
+                                               int grid) {
+  __shared__ double sh[64 * (NT / 64)];
+  __shared__ double tot[NDOT];
+  const int item = blockIdx.x;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (st->phase != PH_UPDATE) return;
+  const int wl = item - first_of(first, s);
+  if (sizeof(R) == 8 && S.hist32)
+    update_body<R, float, NT, MM>(S, st, wl, threadIdx.x, sh, tot);
+  else
+    update_body<R, R, NT, MM>(S, st, wl, threadIdx.x, sh, tot);
 }
 
 // t holds the NDOT sums of the update pass, already scaled by dV; the
@@ -445,25 +459,17 @@ __global__ __launch_bounds__(256) void k_finalize_update(SolveDev *dev, int nsol
 // Direction pass: d = cr P r + sum cS_i s_i + sum cY_i P y_i + cphi phi,
 // with |d|^2 and r.d.
 // ---------------------------------------------------------------------------
-template <typename R, int NT, int MM>
-__global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int nsolve, int grid) {
-  __shared__ double sh[2 * (NT / 64)];
-  __shared__ double tot[2];
-  const int item = blockIdx.x;
-  const int s = find_solve(first, nsolve, item);
-  const SolveDev &S = dev[s];
-  const SKX_C OptState *st = cptr<OptState>(S.st);
-  if (st->phase != PH_NEED_DIR) return;
-  const int tid = threadIdx.x;
-  const int wl = item - first_of(first, s);
+template <typename R, typename H, int NT, int MM>
+__device__ __forceinline__ void dir_body(const SolveDev &S, const SKX_C OptState *st, int wl,
+                                         int tid, double *sh, double *tot) {
   const long long g0 = (long long)wl * CHUNK;
   const long long g1 = min((long long)S.M, g0 + CHUNK);
   const int par = st->par;
   const SKX_G R *phi = gptr<R>(S.phi2[par]);
   const SKX_G R *r = gptr<R>(S.r2[par]);
   const SKX_G R *pr = gptr<R>(S.pr2[par]);
-  const SKX_G R *Sv = gptr<R>(S.S);
-  const SKX_G R *Yv = gptr<R>(S.Y);
+  const SKX_G H *Sv = gptr<H>(S.S);
+  const SKX_G H *Yv = gptr<H>(S.Y);
   SKX_G R *d = gptr<R>(S.d);
   const int m = st->m, k = st->k, head = st->head;
   int slot[MM];
@@ -480,7 +486,8 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
     R v = cr * pr[g] + cphi * phi[g];
 #pragma unroll
     for (int i = 0; i < MM; ++i) {
-      if (i < k) v += cS[i] * Sv[(size_t)slot[i] * S.M + g] + cY[i] * Yv[(size_t)slot[i] * S.M + g];
+      if (i < k)
+        v += cS[i] * (R)Sv[(size_t)slot[i] * S.M + g] + cY[i] * (R)Yv[(size_t)slot[i] * S.M + g];
     }
     d[g] = v;
     dd += (double)v * v;
@@ -489,6 +496,22 @@ __global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int
   double acc[2] = {dd, rd};
   block_reduce<2>(acc, sh, tid, NT, tot);
   if (tid == 0) { S.partD[wl * 2] = tot[0]; S.partD[wl * 2 + 1] = tot[1]; }
+}
+
+template <typename R, int NT, int MM>
+__global__ __launch_bounds__(NT) void k_dir(SolveDev *dev, const int *first, int nsolve, int grid) {
+  __shared__ double sh[2 * (NT / 64)];
+  __shared__ double tot[2];
+  const int item = blockIdx.x;
+  const int s = find_solve(first, nsolve, item);
+  const SolveDev &S = dev[s];
+  const SKX_C OptState *st = cptr<OptState>(S.st);
+  if (st->phase != PH_NEED_DIR) return;
+  const int wl = item - first_of(first, s);
+  if (sizeof(R) == 8 && S.hist32)
+    dir_body<R, float, NT, MM>(S, st, wl, threadIdx.x, sh, tot);
+  else
+    dir_body<R, R, NT, MM>(S, st, wl, threadIdx.x, sh, tot);
 }
 
 __device__ void finalize_dir_body(OptState *st, const SKX_C SolveDev &S, const double *t) {
