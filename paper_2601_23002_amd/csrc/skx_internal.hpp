@@ -84,7 +84,7 @@ struct SolveDev {
   double kappa;                    // preconditioner P(G) = 1 / (G^2 + kappa)
   void *phi2[2], *r2[2], *pr2[2];  // current / trial point pairs (see OptState::par)
   void *grad, *d, *S, *Y;          // real fields (fp64 or fp32; S, Y fp32 if hist32); Y holds P y
-  void *vpt;                       // T eta + v_xc at the trial point (pass A -> C)
+  void *vpt;                       // w0 = 2 phi_t (T eta + v_xc) at the trial point (pass A -> C)
   void *fpt, *qpt;                 // coefficients c_P, c_Q of the fields P, Q (pass A -> C)
   void *npa;                       // n^a at the trial point (pointwise kernel -> pass A)
   void *spec, *vloc;                         // complex spectra

@@ -444,10 +444,10 @@ __device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, 
 }
 
 // ---------------------------------------------------------------------------
-// Pointwise pass (first kernel of pass A on the runtime-shaped kernels), one
-// workgroup per CHUNK points of a solve: the trial point phi_t = ca phi + cb d
-// and point_terms; writes phi_t, v0, c_P, c_Q and n^a for the transform
-// kernel and pass C.
+// Pointwise pass (first kernel of pass A), one workgroup per CHUNK points of
+// a solve: the trial point phi_t = ca phi + cb d and point_terms; writes
+// phi_t and n^a for the transform kernel, and w0 = 2 phi_t v0, c_P, c_Q for
+// pass C.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, int nsolve,
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     phit[e] = ph;
     R v0, f, cP, cQ;
     point_terms<R>(ph, pc, a, a2, n0, n0a, fd, e_tf, e_xc, nel, bad, v0, f, cP, cQ);
-    v0s[e] = v0;
+    v0s[e] = (R)2 * ph * v0;
     if (pc.need_f) {
       nas[e] = f;
       fps[e] = cP;
@@ -874,10 +874,11 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
     return;
   }
 
-  // Per element the fields enter with the coefficients 1 (phi), 2 phi_t
-  // (n), c_P (f) and c_Q (h), stored by pass A; read as pairs along z, LU_C
-  // pairs per thread in flight. In FP32 phi_t is also kept in LDS beside
-  // dE/dphi, so that every array is read from HBM once.
+  // dE/dphi starts from w0 = 2 phi_t v0; the fields enter with the
+  // coefficients 1 (phi), 2 phi_t (n), c_P (f) and c_Q (h), stored by the
+  // pointwise pass; read as pairs along z, LU_C pairs per thread in flight.
+  // In FP32 phi_t is also kept in LDS beside dE/dphi, so that every array
+  // is read from HBM once.
   constexpr bool PCACHE = ACC_LDS && sizeof(R) == 4;
   const size_t qbase = pbase >> 1;
   const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
@@ -893,14 +894,17 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 #pragma unroll
     for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
-      if (q < npair) { pv[u] = ldg(phit + q); vv[u] = ldg(v0 + q); }
+      if (q < npair) {
+        if (PCACHE) pv[u] = ldg(phit + q);
+        vv[u] = ldg(v0 + q);
+      }
     }
 #pragma unroll
     for (int u = 0; u < LU_C; ++u) {
       const int q = q0 + u * NT;
       if (q < npair) {
-        acc[2 * q] = S.debug ? (R)0 : (R)2 * pv[u].x * vv[u].x;
-        acc[2 * q + 1] = S.debug ? (R)0 : (R)2 * pv[u].y * vv[u].y;
+        acc[2 * q] = S.debug ? (R)0 : vv[u].x;
+        acc[2 * q + 1] = S.debug ? (R)0 : vv[u].y;
         if (PCACHE) pc[q] = pv[u];
       }
     }
@@ -1179,13 +1183,13 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
           [&](int e) {
             const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
             const int o = 2 * (p0 + q) * n3 + z;
-            return Quad<R>{phit[o], phit[o + n3], v0[o], v0[o + n3]};
+            return Quad<R>{v0[o], v0[o + n3], (R)0, (R)0};
           },
           [&](int e, const Quad<R> &w) {
             const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
             const int o = 2 * (p0 + q) * n3 + z;
-            out[o] = (R)2 * w.a * w.c;
-            out[o + n3] = (R)2 * w.b * w.d;
+            out[o] = w.a;                   // w0 = 2 phi_t v0
+            out[o + n3] = w.b;
           });
     }
     for (int fb = 0; fb < nfl; ++fb) {
@@ -1943,7 +1947,6 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
   constexpr int NT = K::NT, C = K::C, PL = K::PL, ZP = K::ZP, RL = K::RL, NSL = K::NSL;
   typedef CMap<N, RL, ZP, false> ZM;
   constexpr int MB = ZM::MB;
-  constexpr bool KEEP_PHI = sizeof(R) == 4;       // phi_t stays in registers (FP32)
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
@@ -1988,12 +1991,17 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
     return;
   }
 
+  // dE/dphi = w0 + A + 2 phi_t B + c_P P + c_Q Q with w0 = 2 phi_t v0 from
+  // the pointwise pass, the fields in slot order; phi_t is kept in
+  // registers in FP32, and read again for B and the closing sums in FP64.
+  constexpr bool KEEP_PHI = sizeof(R) == 4;
   const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
   const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
+  SKX_G R *grad = gptr<R>(S.grad) + pbase;
   R acc[MB][2][RL];
   R ph[KEEP_PHI ? MB : 1][2][RL];
   {
-    const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
+    const SKX_G R *w0 = gptr<R>(S.vpt) + pbase;
 #pragma unroll
     for (int i = 0; i < MB; ++i)
       if (pt[i] >= 0) {
@@ -2002,22 +2010,22 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
 #pragma unroll
           for (int r = 0; r < RL; ++r) {
             const int o = pt[i] + h * N + NSL * r;
-            const R p = phit[o];
-            acc[i][h][r] = (R)2 * p * v0[o];
-            if (KEEP_PHI) ph[KEEP_PHI ? i : 0][h][r] = p;
+            acc[i][h][r] = w0[o];
+            if (KEEP_PHI) ph[KEEP_PHI ? i : 0][h][r] = phit[o];
           }
       }
   }
+  double sphig = 0.0, bad = 0.0;
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0) continue;
-    R cf[MB][2][RL];
     __syncthreads();
     load_plane_f<V, N, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
     __syncthreads();
     plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
+    R cf[MB][2][RL];
     if (fb >= 2 || (fb == 1 && !KEEP_PHI)) {
-      const SKX_G R *src = fb == 1 ? phit : (fb == 2 ? cfp[2] : cfp[3]);
+      const SKX_G R *src = cfp[fb];
 #pragma unroll
       for (int i = 0; i < MB; ++i)
         if (pt[i] >= 0) {
@@ -2048,8 +2056,6 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
         }
       }
   }
-  double sphig = 0.0, bad = 0.0;
-  SKX_G R *grad = gptr<R>(S.grad) + pbase;
 #pragma unroll
   for (int i = 0; i < MB; ++i)
     if (pt[i] >= 0) {
