@@ -201,7 +201,8 @@ int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
 // spectrum pitch: 8 in FP64 and 16 in FP32, or for the cubic lengths with
 // compile-time-shaped kernels the largest width up to that which divides
 // n/2, so that their pass B tiles whole blocks below the Nyquist column
-// (72: 4; 48 and 80 in FP32: 8).
+// (72: 4; 48 and 80 in FP32: 8), and 8 where none of 16, 8, 4 divides n/2
+// (36, 50, 54, 60: ragged blocks over all n/2 + 1 columns).
 int block_width(int n1, int n2, int n3, int prec) {
   const int tk = prec == 0 ? 8 : 16;
   if (n1 != n2 || n2 != n3) return tk;
@@ -211,7 +212,7 @@ int block_width(int n1, int n2, int n3, int prec) {
   }
   for (int w = tk; w >= 4; w /= 2)
     if ((n1 / 2) % w == 0) return w;
-  return tk;
+  return 8;                       // ragged blocks, the last one holding the Nyquist column
 }
 
 struct ArenaLayout {
@@ -362,7 +363,6 @@ int shaped_length(const SolveDev &h) {
 
 // Pass B's compile-time-shaped kernel needs whole column blocks below the
 // Nyquist column.
-bool shaped_b_ok(int n, int tk) { return (n / 2) % tk == 0; }
 
 // Prefix sums of passes A, B, C of one group, its runtime-shaped LDS sizes
 // and kernel choices.
@@ -468,7 +468,7 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     int rc = fill_group(c, sub, prec, g, fa, fb, fc);
     if (rc) return rc;
     if (g.shapeN)
-      g.shape = (g_shape_kernels & 5) | ((g_shape_kernels & 2) && shaped_b_ok(g.shapeN, g.tk) ? 2 : 0);
+      g.shape = g_shape_kernels & 7;
     Off o;
     o.desc = part.size();
     part.insert(part.end(), sub.begin(), sub.end());

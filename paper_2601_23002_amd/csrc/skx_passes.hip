@@ -1619,11 +1619,14 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   constexpr int TP = TK + 1;                       // LDS row pitch of a field tile
   constexpr int SL = MODE == MODE_EVAL ? TK : TK / NW;   // columns per wavefront
   static_assert(MODE == MODE_EVAL || TK % NW == 0, "preconditioner columns split evenly");
-  static_assert(N % NW == 0, "Nyquist rows split evenly");
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NB = (N / 2) / TK;
-  static_assert((N / 2) % TK == 0, "whole column blocks below the Nyquist column");
-  constexpr int PER = N * NB + N / NW;             // workgroups per solve
+  // Whole blocks below the Nyquist column when TK divides N/2, the Nyquist
+  // column then on passB_nyquist; otherwise (ragged) blocks over all N/2 + 1
+  // columns, the last one partial and holding the Nyquist column.
+  constexpr bool RAG = (N / 2) % TK != 0;
+  constexpr int NB = RAG ? (N / 2 + TK) / TK : (N / 2) / TK;
+  constexpr int PER = N * NB + (RAG ? 0 : N / NW);  // workgroups per solve
+  static_assert(RAG || N % NW == 0, "Nyquist rows split evenly");
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
   const int s = __builtin_amdgcn_readfirstlane(item / PER);
@@ -1632,18 +1635,20 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   if (!active_phase<MODE>(st->phase)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rem = item - s * PER;
-  if (rem >= N * NB) {
-    V *tw = reinterpret_cast<V *>(smem) + NFIELD * N * TP;
-    load_twiddles(tw, twbank, S.p1.tw, N, tid, NT);
-    __syncthreads();
-    passB_nyquist<R, N, MODE>(S, (rem - N * NB) * NW + wave,
-                              reinterpret_cast<V *>(smem) + wave * NFIELD * (N + 1), tw, lane);
-    return;
+  if constexpr (!RAG) {
+    if (rem >= N * NB) {
+      V *tw = reinterpret_cast<V *>(smem) + NFIELD * N * TP;
+      load_twiddles(tw, twbank, S.p1.tw, N, tid, NT);
+      __syncthreads();
+      passB_nyquist<R, N, MODE>(S, (rem - N * NB) * NW + wave,
+                                reinterpret_cast<V *>(smem) + wave * NFIELD * (N + 1), tw, lane);
+      return;
+    }
   }
   const int jy = rem / NB, kb = rem - (rem / NB) * NB;
   const int local = jy * S.nkb + kb;                 // energy row, as in k_passB
   const int k0 = kb * TK;
-  const int tkv = TK;
+  const int tkv = RAG ? min(TK, N / 2 + 1 - k0) : TK;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N][TP]
   V *tw1 = tile + NFIELD * N * TP;
@@ -2095,12 +2100,13 @@ template <typename R> static bool wide_b(const PassGroup &g) {
 static bool wide_a(const PassGroup &g) { return g.ldsA > 45 * 1024; }
 
 // Compile-time-shaped pass kernels of one length N over one group.
-// Pass B column-block width of a compile-time length: the largest up to 8
-// (FP64) or 16 (FP32) that divides N/2 (the host's block_width).
+// Pass B column-block width of a compile-time length: the largest of 8
+// (FP64) or 16 (FP32), halved down to 4, that divides N/2; 8 (ragged
+// blocks) when none does (the host's block_width).
 template <int N, typename R> constexpr int shaped_tk() {
   int tk = sizeof(R) == 8 ? 8 : 16;
   while (tk > 4 && (N / 2) % tk != 0) tk /= 2;
-  return tk;
+  return (N / 2) % tk == 0 ? tk : 8;
 }
 
 template <typename R, int N>
@@ -2119,9 +2125,10 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
     SKX_TIMED_LAUNCH((k_passAf<R, N, MODE_PREC>), dim3(g.gridC), dim3(NT), lds_plane, s, g.dev,
                      g.firstC, g.nsolve, g.gridC, twbank);
   }
-  if constexpr ((N / 2) % TK == 0) {
+  {
     if (g.gridB > 0 && (mask & 2) && (g.shape & 2) && g.tk == TK) {
-      const int gb = g.nsolve * (N * (N / 2 / TK) + N / 4);
+      constexpr bool RAG = (N / 2) % TK != 0;
+      const int gb = g.nsolve * (RAG ? N * ((N / 2 + TK) / TK) : N * (N / 2 / TK) + N / 4);
       const size_t lb = (NFIELD * N * (TK + 1) + N) * sizeof(V);
       if (mode == MODE_EVAL)
         SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_EVAL>), dim3(gb), dim3(256), lb, s, g.dev,
