@@ -198,11 +198,10 @@ constexpr size_t LDS_MAX = 160 * 1024;
 int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
 
 // Width (complex columns) of pass B's column blocks, which also aligns the
-// spectrum pitch: 8 in FP64 and 16 in FP32, or for the cubic lengths with
-// compile-time-shaped kernels the largest width up to that which divides
-// n/2, so that their pass B tiles whole blocks below the Nyquist column
-// (72: 4; 48 and 80 in FP32: 8), and 8 where none of 16, 8, 4 divides n/2
-// (36, 50, 54, 60: ragged blocks over all n/2 + 1 columns).
+// spectrum pitch: 8 in FP64 and 16 in FP32; for the cubic lengths with
+// compile-time-shaped kernels 16 in FP32 only where it divides n/2, else 8.
+// Where 8 does not divide n/2 either (36, 40, 50, 54, 60, 72) the shaped
+// pass B takes ragged blocks over all n/2 + 1 columns.
 int block_width(int n1, int n2, int n3, int prec) {
   const int tk = prec == 0 ? 8 : 16;
   if (n1 != n2 || n2 != n3) return tk;
@@ -210,9 +209,7 @@ int block_width(int n1, int n2, int n3, int prec) {
     case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: case 80: break;
     default: return tk;
   }
-  for (int w = tk; w >= 4; w /= 2)
-    if ((n1 / 2) % w == 0) return w;
-  return 8;                       // ragged blocks, the last one holding the Nyquist column
+  return (prec == 1 && (n1 / 2) % 16 == 0) ? 16 : 8;
 }
 
 struct ArenaLayout {

@@ -2100,13 +2100,12 @@ template <typename R> static bool wide_b(const PassGroup &g) {
 static bool wide_a(const PassGroup &g) { return g.ldsA > 45 * 1024; }
 
 // Compile-time-shaped pass kernels of one length N over one group.
-// Pass B column-block width of a compile-time length: the largest of 8
-// (FP64) or 16 (FP32), halved down to 4, that divides N/2; 8 (ragged
-// blocks) when none does (the host's block_width).
+// Pass B column-block width of a compile-time length (the host's
+// block_width): 16 in FP32 where it divides N/2, else 8, in ragged blocks
+// where 8 does not divide N/2 (measured: ragged blocks of 8 beat whole
+// blocks of 4 at 40 and 72).
 template <int N, typename R> constexpr int shaped_tk() {
-  int tk = sizeof(R) == 8 ? 8 : 16;
-  while (tk > 4 && (N / 2) % tk != 0) tk /= 2;
-  return (N / 2) % tk == 0 ? tk : 8;
+  return (sizeof(R) == 4 && (N / 2) % 16 == 0) ? 16 : 8;
 }
 
 template <typename R, int N>

@@ -124,8 +124,8 @@ def test_shape64_optimisation_reaches_same_minimum(precision):
 # ----------------------------------------------------------------------------
 # The other compile-time lengths (radix orders 4-3-3, 8-5, 8-3-2, 2-5-5,
 # 2-3-3-3, 4-3-5, 8-3-3, 8-5-2; pass B on the shaped kernel with whole column
-# blocks below the Nyquist column at 40, 48, 72, 80, and ragged blocks whose
-# last one holds the Nyquist column at 36, 50, 54, 60)
+# blocks below the Nyquist column at 48 and 80, and ragged blocks whose last
+# one holds the Nyquist column at 36, 40, 50, 54, 60, 72)
 # ----------------------------------------------------------------------------
 SHAPED = [36, 40, 48, 50, 54, 60, 72, 80]
 _ORACLE = {}
