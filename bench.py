@@ -18,7 +18,7 @@ error of the mixed path (Ha/atom, relative density).
 
 Sub-objects:
   scan   the 9 solves of 64 Z=1 ions, rs in {1,2,4} x T in {0.5,2,8} Ha on
-         64^3 (the only grid with compile-time-shaped kernels), mixed and
+         64^3 (one of the compile-time-shaped lengths), mixed and
          FP64, with the error against the stored oracle minima of seeds 2,
          5 and 8 (tests/golden);
   serve  a Poisson request stream (200/s offered, 16-1024 ions, 32^3-192^3)
@@ -36,8 +36,8 @@ entries, nf transformed fields):
   pass A  b M (phi) [+ b M (the trial direction d)] + nf 2b H
   pass B  2 nf 2b H + 2b H (V_loc(G))
   pass C  nf 2b H + b M (phi_t) + b M (dE/dphi)
-(160 B FP64 / 80 B FP32 per point for four fields, as the survey's model,
-plus the Nyquist column and d). The same steps are then timed without any
+(160 B FP64 / 80 B FP32 per point for four fields, plus the Nyquist
+column and d). The same steps are then timed without any
 events (value_no_events) and replayed from captured HIP graphs
 (value_graphs).
 
