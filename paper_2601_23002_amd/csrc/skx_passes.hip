@@ -57,6 +57,26 @@ template <> __device__ __forceinline__ float rpow(float x, float a) {
   return x > 1e-30f ? __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(x)) : 0.0f;
 }
 
+// FP32 evaluations hand only phi_t and w0 from the pointwise kernel to the
+// passes: n^a (pass A) and the assembly coefficients c_P, c_Q (pass C) are
+// derived again from phi_t with the pointwise kernel's own arithmetic
+// (hardware log2/exp2, a few instructions), which saves their round trips
+// through HBM. FP64 evaluations hand them over (an FP64 logarithm and
+// exponential per point cost more than the bytes).
+// (Deriving only n^a and handing c_P, c_Q to pass C measured 1 ms slower
+// per batched solve of the 256-snapshot ensemble.)
+template <typename R> constexpr bool derive_na() { return sizeof(R) == 4; }
+template <typename R> constexpr bool derive_coefs() { return sizeof(R) == 4; }
+template <typename R> __device__ __forceinline__ R derived_na(R p, R a) { return rpow(p * p, a); }
+// c_P (fb = 2) or c_Q (fb = 3) of one point
+template <typename R>
+__device__ __forceinline__ R derived_coef(R p, int fb, R a, R a2, R n0, R n0a) {
+  const R n = p * p;
+  const R f = rpow(n, a);
+  const R cP = (p != (R)0) ? a2 * f / p : (R)0;
+  return fb == 2 ? cP : cP * (n - n0) + (R)2 * p * (f - n0a);
+}
+
 __device__ __forceinline__ int nth_field(int mask, int c) {
   // bit index of the c-th set bit of mask (slot order phi, n, f, h)
   for (int b = 0; b < NFIELD; ++b)
@@ -446,8 +466,8 @@ __device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, 
 // ---------------------------------------------------------------------------
 // Pointwise pass (first kernel of pass A), one workgroup per CHUNK points of
 // a solve: the trial point phi_t = ca phi + cb d and point_terms; writes
-// phi_t and n^a for the transform kernel, and w0 = 2 phi_t v0, c_P, c_Q for
-// pass C.
+// phi_t and w0 = 2 phi_t v0, and in FP64 also n^a for the transform kernel
+// and c_P, c_Q for pass C.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, int nsolve,
@@ -503,9 +523,11 @@ __global__ __launch_bounds__(NT) void k_point(SolveDev *dev, const int *first, i
     point_terms<R>(ph, pc, a, a2, n0, n0a, fd, e_tf, e_xc, nel, bad, v0, f, cP, cQ);
     v0s[e] = (R)2 * ph * v0;
     if (pc.need_f) {
-      nas[e] = f;
-      fps[e] = cP;
-      if (pc.need_h) qps[e] = cQ;
+      if (!derive_na<R>()) nas[e] = f;
+      if (!derive_coefs<R>()) {
+        fps[e] = cP;
+        if (pc.need_h) qps[e] = cQ;
+      }
     }
   }
   double vsum[PART_A] = {e_tf, e_xc, nel, bad};
@@ -554,8 +576,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
     const size_t qbase = pbase >> 1;
     const SKX_G V *pt = gptr<V>(S.phi2[1 - par]) + qbase;
     const SKX_G V *fa = gptr<V>(S.npa) + qbase;
-    const bool need_p = fb != 2, need_fa = fb >= 2;
-    const R n0 = (R)S.n0, n0a = (R)S.n0a;
+    constexpr bool DER = derive_na<R>();
+    const bool need_p = fb != 2 || DER, need_fa = fb >= 2 && !DER;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a, aa = (R)S.a;
     const int npair = np >> 1, h3 = n3 >> 1;
     const UDiv dh3 = make_udiv((unsigned)h3);
     for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
@@ -577,7 +600,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const R p = need_p ? (h ? pv[u].y : pv[u].x) : (R)0;
-            const R f = need_fa ? (h ? fv[u].y : fv[u].x) : (R)0;
+            const R f = DER ? (fb >= 2 ? derived_na(p, aa) : (R)0)
+                            : (need_fa ? (h ? fv[u].y : fv[u].x) : (R)0);
             xv[h] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
           }
           R *slot = reinterpret_cast<R *>(&buf[(j >> 1) * 2 * pl + k]);
@@ -880,6 +904,8 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
   // In FP32 phi_t is also kept in LDS beside dE/dphi, so that every array
   // is read from HBM once.
   constexpr bool PCACHE = ACC_LDS && sizeof(R) == 4;
+  constexpr bool DER = derive_coefs<R>();         // c_P, c_Q from phi_t
+  const R ca = (R)S.a, ca2 = (R)(2.0 * S.a), cn0 = (R)S.n0, cn0a = (R)S.n0a;
   const size_t qbase = pbase >> 1;
   const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
   const SKX_G V *v0 = gptr<V>(S.vpt) + qbase;
@@ -926,7 +952,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
       for (int u = 0; u < LU_C; ++u) {
         const int q = q0 + u * NT;
         if (q < npair) {
-          if (fb == 1) cv2[u] = PCACHE ? pc[q] : ldg(phit + q);
+          if (fb == 1 || (fb >= 2 && DER)) cv2[u] = PCACHE ? pc[q] : ldg(phit + q);
           else if (fb == 2) cv2[u] = ldg(cpw + q);
           else if (fb == 3) cv2[u] = ldg(cqw + q);
         }
@@ -941,7 +967,9 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
           for (int h = 0; h < 2; ++h) {
             const R val = cv[2 * h + (j & 1)];
             const R c = h ? cv2[u].y : cv2[u].x;
-            const R coef = fb == 0 ? (R)1 : (fb == 1 ? (R)2 * c : c);
+            const R coef = fb == 0 ? (R)1
+                         : fb == 1 ? (R)2 * c
+                                   : (DER ? derived_coef(c, fb, ca, ca2, cn0, cn0a) : c);
             acc[2 * q + h] += coef * val;
           }
         }
@@ -1092,8 +1120,8 @@ __global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *firs
           const int o = 2 * (p0 + q) * n3 + z;
           Quad<R> w{(R)0, (R)0, (R)0, (R)0};
           if (MODE == MODE_EVAL) {
-            if (fb != 2) { w.a = pt[o]; w.b = pt[o + n3]; }
-            if (fb >= 2) { w.c = fa[o]; w.d = fa[o + n3]; }
+            if (fb != 2 || derive_na<R>()) { w.a = pt[o]; w.b = pt[o + n3]; }
+            if (fb >= 2 && !derive_na<R>()) { w.c = fa[o]; w.d = fa[o + n3]; }
           } else {
             w.a = gr[o]; w.b = gr[o + n3]; w.c = pt[o]; w.d = pt[o + n3];
           }
@@ -1105,7 +1133,9 @@ __global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *firs
           R x[2];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const R u = h ? w.b : w.a, f = h ? w.d : w.c;
+            const R u = h ? w.b : w.a;
+            const R f = (MODE == MODE_EVAL && derive_na<R>() && fb >= 2) ? derived_na(u, (R)S.a)
+                                                                           : (h ? w.d : w.c);
             if (MODE == MODE_EVAL)
               x[h] = fb == 0 ? u : fb == 1 ? u * u : fb == 2 ? f : (f - n0a) * (u * u - n0);
             else {
@@ -1225,7 +1255,14 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
             const int o = 2 * (p0 + q) * n3 + z;
             Quad<R> w{(R)1, (R)1, (R)0, (R)0};
             if (MODE == MODE_EVAL) {
-              if (fb > 0) { w.a = cfp[fb][o]; w.b = cfp[fb][o + n3]; }
+              if (fb >= 2 && derive_coefs<R>()) {
+                const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
+                w.a = derived_coef(phit[o], fb, a, a2, n0, n0a);
+                w.b = derived_coef(phit[o + n3], fb, a, a2, n0, n0a);
+              } else if (fb > 0) {
+                w.a = cfp[fb][o];
+                w.b = cfp[fb][o + n3];
+              }
               w.c = out[o];
               w.d = out[o + n3];
             }
@@ -1325,9 +1362,10 @@ __global__ __launch_bounds__(CS<N>::NT) void k_passAf(SolveDev *dev, const int *
     const SKX_G R *fa = gptr<R>(S.npa) + pbase;
     const SKX_G R *gr = gptr<R>(S.grad) + pbase;
     SKX_G R *rt = gptr<R>(S.r2[1 - par]) + pbase;
-    const R n0 = (R)S.n0, n0a = (R)S.n0a;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a, aa = (R)S.a;
     const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
-    const bool need_p = fb != 2, need_fa = fb >= 2;
+    constexpr bool DER = derive_na<R>();
+    const bool need_p = fb != 2 || DER, need_fa = fb >= 2 && !DER;
 #pragma unroll
     for (int i = 0; i < M::MB; ++i) {
       const int b = lane + 64 * i;
@@ -1348,7 +1386,8 @@ __global__ __launch_bounds__(CS<N>::NT) void k_passAf(SolveDev *dev, const int *
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-              const R p = need_p ? pv[h][r] : (R)0, f = need_fa ? fv[h][r] : (R)0;
+              const R p = need_p ? pv[h][r] : (R)0;
+              const R f = DER ? (fb >= 2 ? derived_na(p, aa) : (R)0) : (need_fa ? fv[h][r] : (R)0);
               x[h][r] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
             }
         } else {
@@ -2000,6 +2039,9 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
   // the pointwise pass, the fields in slot order; phi_t is kept in
   // registers in FP32, and read again for B and the closing sums in FP64.
   constexpr bool KEEP_PHI = sizeof(R) == 4;
+  constexpr bool DER = derive_coefs<R>();         // c_P, c_Q from the phi_t registers
+  static_assert(!DER || KEEP_PHI, "derived coefficients need phi_t in registers");
+  const R ca = (R)S.a, ca2 = (R)(2.0 * S.a), cn0 = (R)S.n0, cn0a = (R)S.n0a;
   const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
   const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
   SKX_G R *grad = gptr<R>(S.grad) + pbase;
@@ -2029,7 +2071,7 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
     __syncthreads();
     plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
     R cf[MB][2][RL];
-    if (fb >= 2 || (fb == 1 && !KEEP_PHI)) {
+    if ((fb >= 2 && !DER) || (fb == 1 && !KEEP_PHI)) {
       const SKX_G R *src = cfp[fb];
 #pragma unroll
       for (int i = 0; i < MB; ++i)
@@ -2054,6 +2096,10 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
             const R p1 = KEEP_PHI ? ph[KEEP_PHI ? i : 0][1][r] : cf[i][1][r];
             acc[i][0][r] += (R)2 * p0 * g0;
             acc[i][1][r] += (R)2 * p1 * g1;
+          } else if (DER) {
+            const R p0 = ph[KEEP_PHI ? i : 0][0][r], p1 = ph[KEEP_PHI ? i : 0][1][r];
+            acc[i][0][r] += derived_coef(p0, fb, ca, ca2, cn0, cn0a) * g0;
+            acc[i][1][r] += derived_coef(p1, fb, ca, ca2, cn0, cn0a) * g1;
           } else {
             acc[i][0][r] += cf[i][0][r] * g0;
             acc[i][1][r] += cf[i][1][r] * g1;
