@@ -57,24 +57,71 @@ template <> __device__ __forceinline__ float rpow(float x, float a) {
   return x > 1e-30f ? __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(x)) : 0.0f;
 }
 
-// FP32 evaluations hand only phi_t and w0 from the pointwise kernel to the
-// passes: n^a (pass A) and the assembly coefficients c_P, c_Q (pass C) are
-// derived again from phi_t with the pointwise kernel's own arithmetic
-// (hardware log2/exp2, a few instructions), which saves their round trips
-// through HBM. FP64 evaluations hand them over (an FP64 logarithm and
-// exponential per point cost more than the bytes).
-// (Deriving only n^a and handing c_P, c_Q to pass C measured 1 ms slower
-// per batched solve of the 256-snapshot ensemble.)
-template <typename R> constexpr bool derive_na() { return sizeof(R) == 4; }
+// n^a for pass A is derived again from phi_t instead of being handed over
+// by the pointwise kernel, and in FP32 so are pass C's assembly coefficients
+// c_P, c_Q, which saves their round trips through HBM. FP32 takes n^a
+// through the hardware log2/exp2; FP64 with a = 5/6 takes n^a = |phi|
+// n^(1/3) with the cube root from an FP32 estimate and two Newton steps on
+// n^(-1/3) (about 15 FP64 operations instead of a logarithm and an
+// exponential), other a through exp(a ln n). FP64 pass C keeps the handed
+// c_P, c_Q: deriving them there pushed it past its register budget.
+template <typename R> constexpr bool derive_na() { return true; }
 template <typename R> constexpr bool derive_coefs() { return sizeof(R) == 4; }
-template <typename R> __device__ __forceinline__ R derived_na(R p, R a) { return rpow(p * p, a); }
+
+template <typename R> struct NaCfg {
+  R a, a2, n0, n0a;
+  bool a56;
+};
+template <typename R> __device__ __forceinline__ NaCfg<R> na_cfg(const SolveDev &S) {
+  NaCfg<R> c;
+  c.a = (R)S.a;
+  c.a2 = (R)(2.0 * S.a);
+  c.n0 = (R)S.n0;
+  c.n0a = (R)S.n0a;
+  c.a56 = S.a == 5.0 / 6.0;
+  return c;
+}
+
+// x^(1/3) for x > 0 in FP64
+__device__ __forceinline__ double cbrt_pos(double x) {
+  if (x < 1e-30) return exp(log(x) * (1.0 / 3.0));
+  double z = (double)__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf((float)x));
+  z = fma(z * (1.0 / 3.0), fma(-x * z, z * z, 1.0), z);
+  z = fma(z * (1.0 / 3.0), fma(-x * z, z * z, 1.0), z);
+  return x * z * z;
+}
+
+template <typename R> __device__ __forceinline__ R derived_na(R p, const NaCfg<R> &c);
+template <> __device__ __forceinline__ float derived_na(float p, const NaCfg<float> &c) {
+  return rpow(p * p, c.a);
+}
+template <> __device__ __forceinline__ double derived_na(double p, const NaCfg<double> &c) {
+  const double n = p * p;
+  if (!(n > 0.0)) return 0.0;
+  return c.a56 ? fabs(p) * cbrt_pos(n) : exp(c.a * log(n));
+}
 // c_P (fb = 2) or c_Q (fb = 3) of one point
-template <typename R>
-__device__ __forceinline__ R derived_coef(R p, int fb, R a, R a2, R n0, R n0a) {
-  const R n = p * p;
-  const R f = rpow(n, a);
-  const R cP = (p != (R)0) ? a2 * f / p : (R)0;
-  return fb == 2 ? cP : cP * (n - n0) + (R)2 * p * (f - n0a);
+template <typename R> __device__ __forceinline__ R derived_coef(R p, int fb, const NaCfg<R> &c);
+template <> __device__ __forceinline__ float derived_coef(float p, int fb, const NaCfg<float> &c) {
+  const float n = p * p;
+  const float f = rpow(n, c.a);
+  const float cP = (p != 0.0f) ? c.a2 * f / p : 0.0f;
+  return fb == 2 ? cP : cP * (n - c.n0) + 2.0f * p * (f - c.n0a);
+}
+template <> __device__ __forceinline__ double derived_coef(double p, int fb, const NaCfg<double> &c) {
+  const double n = p * p;
+  double f = 0.0, cP = 0.0;
+  if (n > 0.0) {
+    if (c.a56) {
+      const double e3 = cbrt_pos(n);
+      f = fabs(p) * e3;
+      cP = copysign(c.a2 * e3, p);
+    } else {
+      f = exp(c.a * log(n));
+      cP = c.a2 * f / p;
+    }
+  }
+  return fb == 2 ? cP : cP * (n - c.n0) + 2.0 * p * (f - c.n0a);
 }
 
 __device__ __forceinline__ int nth_field(int mask, int c) {
@@ -578,7 +625,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
     const SKX_G V *fa = gptr<V>(S.npa) + qbase;
     constexpr bool DER = derive_na<R>();
     const bool need_p = fb != 2 || DER, need_fa = fb >= 2 && !DER;
-    const R n0 = (R)S.n0, n0a = (R)S.n0a, aa = (R)S.a;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a;
+    const NaCfg<R> nc = na_cfg<R>(S);
     const int npair = np >> 1, h3 = n3 >> 1;
     const UDiv dh3 = make_udiv((unsigned)h3);
     for (int q0 = tid; q0 < npair; q0 += LU_A * NT) {
@@ -600,7 +648,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 5 : 4) void k_passA(SolveDev *
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const R p = need_p ? (h ? pv[u].y : pv[u].x) : (R)0;
-            const R f = DER ? (fb >= 2 ? derived_na(p, aa) : (R)0)
+            const R f = DER ? (fb >= 2 ? derived_na(p, nc) : (R)0)
                             : (need_fa ? (h ? fv[u].y : fv[u].x) : (R)0);
             xv[h] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
           }
@@ -905,7 +953,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
   // is read from HBM once.
   constexpr bool PCACHE = ACC_LDS && sizeof(R) == 4;
   constexpr bool DER = derive_coefs<R>();         // c_P, c_Q from phi_t
-  const R ca = (R)S.a, ca2 = (R)(2.0 * S.a), cn0 = (R)S.n0, cn0a = (R)S.n0a;
+  const NaCfg<R> nc = na_cfg<R>(S);
   const size_t qbase = pbase >> 1;
   const SKX_G V *phit = gptr<V>(S.phi2[1 - par]) + qbase;
   const SKX_G V *v0 = gptr<V>(S.vpt) + qbase;
@@ -969,7 +1017,7 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
             const R c = h ? cv2[u].y : cv2[u].x;
             const R coef = fb == 0 ? (R)1
                          : fb == 1 ? (R)2 * c
-                                   : (DER ? derived_coef(c, fb, ca, ca2, cn0, cn0a) : c);
+                                   : (DER ? derived_coef(c, fb, nc) : c);
             acc[2 * q + h] += coef * val;
           }
         }
@@ -1134,7 +1182,7 @@ __global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *firs
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const R u = h ? w.b : w.a;
-            const R f = (MODE == MODE_EVAL && derive_na<R>() && fb >= 2) ? derived_na(u, (R)S.a)
+            const R f = (MODE == MODE_EVAL && derive_na<R>() && fb >= 2) ? derived_na(u, na_cfg<R>(S))
                                                                            : (h ? w.d : w.c);
             if (MODE == MODE_EVAL)
               x[h] = fb == 0 ? u : fb == 1 ? u * u : fb == 2 ? f : (f - n0a) * (u * u - n0);
@@ -1256,9 +1304,9 @@ __global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *firs
             Quad<R> w{(R)1, (R)1, (R)0, (R)0};
             if (MODE == MODE_EVAL) {
               if (fb >= 2 && derive_coefs<R>()) {
-                const R a = (R)S.a, a2 = (R)(2.0 * S.a), n0 = (R)S.n0, n0a = (R)S.n0a;
-                w.a = derived_coef(phit[o], fb, a, a2, n0, n0a);
-                w.b = derived_coef(phit[o + n3], fb, a, a2, n0, n0a);
+                const NaCfg<R> nc = na_cfg<R>(S);
+                w.a = derived_coef(phit[o], fb, nc);
+                w.b = derived_coef(phit[o + n3], fb, nc);
               } else if (fb > 0) {
                 w.a = cfp[fb][o];
                 w.b = cfp[fb][o + n3];
@@ -1362,7 +1410,8 @@ __global__ __launch_bounds__(CS<N>::NT) void k_passAf(SolveDev *dev, const int *
     const SKX_G R *fa = gptr<R>(S.npa) + pbase;
     const SKX_G R *gr = gptr<R>(S.grad) + pbase;
     SKX_G R *rt = gptr<R>(S.r2[1 - par]) + pbase;
-    const R n0 = (R)S.n0, n0a = (R)S.n0a, aa = (R)S.a;
+    const R n0 = (R)S.n0, n0a = (R)S.n0a;
+    const NaCfg<R> nc = na_cfg<R>(S);
     const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
     constexpr bool DER = derive_na<R>();
     const bool need_p = fb != 2 || DER, need_fa = fb >= 2 && !DER;
@@ -1387,7 +1436,7 @@ __global__ __launch_bounds__(CS<N>::NT) void k_passAf(SolveDev *dev, const int *
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
               const R p = need_p ? pv[h][r] : (R)0;
-              const R f = DER ? (fb >= 2 ? derived_na(p, aa) : (R)0) : (need_fa ? fv[h][r] : (R)0);
+              const R f = DER ? (fb >= 2 ? derived_na(p, nc) : (R)0) : (need_fa ? fv[h][r] : (R)0);
               x[h][r] = fb == 0 ? p : fb == 1 ? p * p : fb == 2 ? f : (f - n0a) * (p * p - n0);
             }
         } else {
@@ -2039,9 +2088,8 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
   // the pointwise pass, the fields in slot order; phi_t is kept in
   // registers in FP32, and read again for B and the closing sums in FP64.
   constexpr bool KEEP_PHI = sizeof(R) == 4;
-  constexpr bool DER = derive_coefs<R>();         // c_P, c_Q from the phi_t registers
-  static_assert(!DER || KEEP_PHI, "derived coefficients need phi_t in registers");
-  const R ca = (R)S.a, ca2 = (R)(2.0 * S.a), cn0 = (R)S.n0, cn0a = (R)S.n0a;
+  constexpr bool DER = derive_coefs<R>();         // c_P, c_Q from phi_t
+  const NaCfg<R> nc = na_cfg<R>(S);
   const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
   const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
   SKX_G R *grad = gptr<R>(S.grad) + pbase;
@@ -2071,8 +2119,8 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
     __syncthreads();
     plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
     R cf[MB][2][RL];
-    if ((fb >= 2 && !DER) || (fb == 1 && !KEEP_PHI)) {
-      const SKX_G R *src = cfp[fb];
+    if (fb >= 2 ? !(DER && KEEP_PHI) : (fb == 1 && !KEEP_PHI)) {
+      const SKX_G R *src = (fb >= 2 && DER) ? phit : cfp[fb];
 #pragma unroll
       for (int i = 0; i < MB; ++i)
         if (pt[i] >= 0) {
@@ -2097,9 +2145,10 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
             acc[i][0][r] += (R)2 * p0 * g0;
             acc[i][1][r] += (R)2 * p1 * g1;
           } else if (DER) {
-            const R p0 = ph[KEEP_PHI ? i : 0][0][r], p1 = ph[KEEP_PHI ? i : 0][1][r];
-            acc[i][0][r] += derived_coef(p0, fb, ca, ca2, cn0, cn0a) * g0;
-            acc[i][1][r] += derived_coef(p1, fb, ca, ca2, cn0, cn0a) * g1;
+            const R p0 = KEEP_PHI ? ph[KEEP_PHI ? i : 0][0][r] : cf[i][0][r];
+            const R p1 = KEEP_PHI ? ph[KEEP_PHI ? i : 0][1][r] : cf[i][1][r];
+            acc[i][0][r] += derived_coef(p0, fb, nc) * g0;
+            acc[i][1][r] += derived_coef(p1, fb, nc) * g1;
           } else {
             acc[i][0][r] += cf[i][0][r] * g0;
             acc[i][1][r] += cf[i][1][r] * g1;
