@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--count", type=int, default=256, help="ensemble snapshots")
     ap.add_argument("--serve-count", type=int, default=200, help="served requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests per second")
+    ap.add_argument("--serve-budget-gb", type=int, default=192, help="serve: engine HBM budget (GiB)")
+    ap.add_argument("--serve-slots", type=int, default=128, help="serve: resident solves at most")
     ap.add_argument("--extra-steps", type=int, default=3,
                     help="steps of the no-event and graph-replay timings")
     ap.add_argument("--no-autotune", action="store_true",
@@ -525,7 +527,7 @@ def serve_leg(args, skx, W):
         s.xc = W.XC_PZ81_C1
 
     def replay(rate_scale, label):
-        eng = skx.Engine(0, hbm_budget=96 << 30, max_slots=64)
+        eng = skx.Engine(0, hbm_budget=args.serve_budget_gb << 30, max_slots=args.serve_slots)
         t0 = eng.clock()
         arrive, sizes = {}, {}
         lat, work = [], 0

@@ -549,8 +549,33 @@ int ensure_tables(skx_ctx *c) {
   return SKX_OK;
 }
 
+// FP32 V_loc(G) from the FP64 instance's: k_vloc computes every entry in
+// FP64 and rounds it to the field type, so the rounded copy is the same
+// array (the two instances may differ in spectrum pitch).
+__global__ void k_vloc_d2f(const double2 *src, int spitch, float2 *dst, int dpitch, int rows,
+                           int nh) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= (long long)rows * nh) return;
+  const long long row = idx / nh;
+  const int k = (int)(idx - row * nh);
+  const double2 v = src[row * spitch + k];
+  dst[row * dpitch + k] = make_float2((float)v.x, (float)v.y);
+}
+
 int ensure_vloc(skx_ctx *c, Instance &I) {
   if (I.vloc_ok) return SKX_OK;
+  const Instance &I64 = c->inst[0];
+  if (I.prec == 1 && I64.mem && I64.vloc_ok && I64.h.n1 == I.h.n1 && I64.h.n2 == I.h.n2 &&
+      I64.h.n3 == I.h.n3) {
+    const int rows = I.h.n1 * I.h.n2, nh = I.h.nh;
+    hipLaunchKernelGGL(k_vloc_d2f, dim3((unsigned)(((long long)rows * nh + 255) / 256)), dim3(256), 0,
+                       c->stream, (const double2 *)I64.h.vloc, I64.h.pitch, (float2 *)I.h.vloc,
+                       I.h.pitch, rows, nh);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "V_loc conversion");
+    I.vloc_ok = true;
+    return SKX_OK;
+  }
   const int nions = (int)c->species.size();
   const int nh = c->n3 / 2 + 1;
   double2 *scr = nullptr;
@@ -1281,9 +1306,10 @@ int skx_optimize_density(skx_ctx *c, void *rho_dev, const skx_opt_params *p, skx
     if (prec == 1) { res->fp32_iters = out.iters; res->fp32_evals = out.evals; }
   } else {
     // mixed: FP32 phase to fp32_switch_gtol, then FP64 refinement from there
-    rc = prepare(c, 1, p->lbfgs_m);
-    if (rc) return rc;
+    // FP64 first: the FP32 instance then copies its V_loc(G) (ensure_vloc)
     rc = prepare(c, 0, p->lbfgs_m);
+    if (rc) return rc;
+    rc = prepare(c, 1, p->lbfgs_m);
     if (rc) return rc;
     Instance &I32 = c->inst[1];
     Instance &I64 = c->inst[0];
@@ -1926,7 +1952,9 @@ int skx_run_batch(skx_ctx **ctxs, int nctx, void **rho_devs, const skx_opt_param
   else precs = {1, 0};
   for (int i = 0; i < nctx; ++i) {
     std::memset(&res[i], 0, sizeof(skx_opt_result));
-    for (int pr : precs) {
+    // FP64 first: the FP32 instance then copies its V_loc(G) (ensure_vloc)
+    for (int pr : {0, 1}) {
+      if (std::find(precs.begin(), precs.end(), pr) == precs.end()) continue;
       int rc = prepare(ctxs[i], pr, p->lbfgs_m);
       if (rc) { c0->err = "solve " + std::to_string(i) + ": " + ctxs[i]->err; return rc; }
     }
