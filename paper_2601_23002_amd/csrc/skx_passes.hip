@@ -92,8 +92,11 @@ __device__ __forceinline__ double cbrt_pos(double x) {
 }
 
 template <typename R> __device__ __forceinline__ R derived_na(R p, const NaCfg<R> &c);
+// FP32: with L = log2 |phi|, n^a = 2^(2a L) and c_P = 2a sign(phi) 2^((2a-1) L)
+// (no division); |phi| below 1e-15 gives 0 for both.
 template <> __device__ __forceinline__ float derived_na(float p, const NaCfg<float> &c) {
-  return rpow(p * p, c.a);
+  const float ap = fabsf(p);
+  return ap > 1e-15f ? __builtin_amdgcn_exp2f(2.0f * c.a * __builtin_amdgcn_logf(ap)) : 0.0f;
 }
 template <> __device__ __forceinline__ double derived_na(double p, const NaCfg<double> &c) {
   const double n = p * p;
@@ -103,9 +106,13 @@ template <> __device__ __forceinline__ double derived_na(double p, const NaCfg<d
 // c_P (fb = 2) or c_Q (fb = 3) of one point
 template <typename R> __device__ __forceinline__ R derived_coef(R p, int fb, const NaCfg<R> &c);
 template <> __device__ __forceinline__ float derived_coef(float p, int fb, const NaCfg<float> &c) {
-  const float n = p * p;
-  const float f = rpow(n, c.a);
-  const float cP = (p != 0.0f) ? c.a2 * f / p : 0.0f;
+  const float n = p * p, ap = fabsf(p);
+  float f = 0.0f, cP = 0.0f;
+  if (ap > 1e-15f) {
+    const float L = __builtin_amdgcn_logf(ap);
+    f = __builtin_amdgcn_exp2f(2.0f * c.a * L);
+    cP = copysignf(c.a2 * __builtin_amdgcn_exp2f((2.0f * c.a - 1.0f) * L), p);
+  }
   return fb == 2 ? cP : cP * (n - c.n0) + 2.0f * p * (f - c.n0a);
 }
 template <> __device__ __forceinline__ double derived_coef(double p, int fb, const NaCfg<double> &c) {
