@@ -2039,6 +2039,11 @@ __device__ __forceinline__ void plane_inverse_f(V *buf, const V *tw2, const V *t
 
 // (the launch bound asks for CShape's CW waves per SIMD: FP64 at 64^3 fits
 // 168 VGPRs with three 256-thread groups)
+// Pass C prefetches the next field's plane at the lengths where it measured
+// faster (60, 72, 80: 5-7% per launch); at 48 and 64 the extra registers
+// spill.
+template <typename R, int N> constexpr bool passc_prefetch() { return N == 60 || N >= 72; }
+
 template <typename R, int N, int MODE>
 __global__ __launch_bounds__(CS<N>::NT, CS<N>::CW)
 void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const double *twbank) {
@@ -2118,12 +2123,47 @@ void k_passCf(SolveDev *dev, const int *first, int nsolve, int grid, const doubl
       }
   }
   double sphig = 0.0, bad = 0.0;
+  // With PF the next field's plane is loaded into registers while the
+  // current one is transformed (the lengths whose pass C holds one
+  // workgroup per CU, where nothing else would hide the load latency).
+  constexpr bool PF = passc_prefetch<R, N>();
+  constexpr int TOTP = N * (C + 1), NUP = (TOTP + NT - 1) / NT;
+  V pre[PF ? NUP : 1];
+  auto fetch = [&](int f) {
+    const SKX_G V *src = spec + (size_t)S.slot[f] * S.H;
+#pragma unroll
+    for (int u = 0; u < NUP; ++u) {
+      const int e = tid + u * NT;
+      if (TOTP % NT == 0 || e < TOTP) pre[PF ? u : 0] = ldg(src + (size_t)(e / (C + 1)) * pitch + e % (C + 1));
+    }
+  };
+  auto next_field = [&](int f) {
+    for (int q = f + 1; q < NFIELD; ++q)
+      if (S.slot[q] >= 0) return q;
+    return NFIELD;
+  };
+  if (PF) {
+    const int f0 = next_field(-1);
+    if (f0 < NFIELD) fetch(f0);
+  }
   for (int fb = 0; fb < NFIELD; ++fb) {
     const int sl = S.slot[fb];
     if (sl < 0) continue;
     __syncthreads();
-    load_plane_f<V, N, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    if (PF) {
+#pragma unroll
+      for (int u = 0; u < NUP; ++u) {
+        const int e = tid + u * NT;
+        if (TOTP % NT == 0 || e < TOTP) buf[(e / (C + 1)) * PL + e % (C + 1)] = pre[PF ? u : 0];
+      }
+    } else {
+      load_plane_f<V, N, C + 1, PL, NT>(buf, spec + (size_t)sl * S.H, pitch, tid);
+    }
     __syncthreads();
+    if (PF) {
+      const int fn = next_field(fb);
+      if (fn < NFIELD) fetch(fn);
+    }
     plane_inverse_f<V, N, MB>(buf, tw2, tw3, lane, wave, v);
     R cf[MB][2][RL];
     if (fb >= 2 ? !(DER && KEEP_PHI) : (fb == 1 && !KEEP_PHI)) {
