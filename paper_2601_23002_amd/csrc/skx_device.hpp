@@ -589,13 +589,13 @@ __device__ __forceinline__ void pz_dense(T rs, T lr, T irs, T &e, T &de) {
   de = PZ<T>::A * irs + PZ<T>::C * lr + PZ<T>::C + PZ<T>::D;
 }
 
-// (e3 = n^(1/3) = exp(x/3), computed by the caller)
-__device__ __forceinline__ void pz81_ln_e3(double x, double e3, bool join, double &eps,
-                                           double &v) {
+// (e3 = n^(1/3) = exp(x/3) and ie3 = 1/e3, computed by the caller)
+__device__ __forceinline__ void pz81_ln_e3(double x, double e3, double ie3, bool join,
+                                           double &eps, double &v) {
   const double RS1 = 0.62035049089940001667;   // (3/(4 pi))^(1/3)
   const double LNRS1 = -0.47747065276706024;  // ln RS1
   const double CX = 0.45816529328314287;      // (3/(4 pi)) (9 pi / 4)^(1/3)
-  const double rs = RS1 / e3;
+  const double rs = RS1 * ie3;
   const double ex = -CX / RS1 * e3;
   const double hi = join ? PZ<double>::HI : 1.0;
   const double lo = join ? PZ<double>::LO : 1.0;
@@ -604,10 +604,10 @@ __device__ __forceinline__ void pz81_ln_e3(double x, double e3, bool join, doubl
     const double sq = sqrt(rs);
     pz_dilute(rs, sq, 1.0 / (1.0 + PZ<double>::B1 * sq + PZ<double>::B2 * rs), ec, dec);
   } else if (rs <= lo) {
-    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 / RS1, ec, dec);
+    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 * (1.0 / RS1), ec, dec);
   } else {
     double e1, d1, e2, d2;
-    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 / RS1, e1, d1);
+    pz_dense(rs, LNRS1 - x * (1.0 / 3.0), e3 * (1.0 / RS1), e1, d1);
     const double sq = sqrt(rs);
     pz_dilute(rs, sq, 1.0 / (1.0 + PZ<double>::B1 * sq + PZ<double>::B2 * rs), e2, d2);
     const double t = (rs - PZ<double>::LO) / (PZ<double>::HI - PZ<double>::LO);
@@ -621,7 +621,8 @@ __device__ __forceinline__ void pz81_ln_e3(double x, double e3, bool join, doubl
 }
 
 __device__ __forceinline__ void pz81_ln(double x, bool join, double &eps, double &v) {
-  pz81_ln_e3(x, exp(x * (1.0 / 3.0)), join, eps, v);
+  const double e3 = exp(x * (1.0 / 3.0));
+  pz81_ln_e3(x, e3, 1.0 / e3, join, eps, v);
 }
 
 // Single-precision PZ81 for the FP32 evaluations (the exchange-correlation

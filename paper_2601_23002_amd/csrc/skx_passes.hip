@@ -82,12 +82,18 @@ template <typename R> __device__ __forceinline__ NaCfg<R> na_cfg(const SolveDev 
   return c;
 }
 
-// x^(1/3) for x > 0 in FP64
-__device__ __forceinline__ double cbrt_pos(double x) {
-  if (x < 1e-30) return exp(log(x) * (1.0 / 3.0));
+// x^(-1/3) for x > 0 in FP64: an FP32 estimate and two Newton steps on
+// z^-3 = x (quadratic convergence from ~1e-7 to the FP64 rounding)
+__device__ __forceinline__ double rcbrt_pos(double x) {
+  if (x < 1e-30 || x > 1e30) return exp(log(x) * (-1.0 / 3.0));
   double z = (double)__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf((float)x));
   z = fma(z * (1.0 / 3.0), fma(-x * z, z * z, 1.0), z);
   z = fma(z * (1.0 / 3.0), fma(-x * z, z * z, 1.0), z);
+  return z;
+}
+// x^(1/3) for x > 0 in FP64
+__device__ __forceinline__ double cbrt_pos(double x) {
+  const double z = rcbrt_pos(x);
   return x * z * z;
 }
 
@@ -468,7 +474,7 @@ __device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, 
                                             double &nel, double &bad, R &v0, R &f, R &cP, R &cQ) {
   const R n = ph * ph;
   const double nd = (double)n;
-  double v = 0.0, lx = 0.0, e3 = 0.0;
+  double v = 0.0, lx = 0.0, e3 = 0.0, ie3 = 0.0;
   if (!(nd == nd) || nd > 1e300) bad += 1.0;
   if (nd > 0.0) {
     nel += nd;
@@ -477,7 +483,10 @@ __device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, 
     lx = sizeof(R) == 4 ? (double)(0.69314718055994531f * __builtin_amdgcn_logf((float)n))
                         : log(nd);
     // FP64: n^(1/3), shared by PZ81 and, for a = 5/6, by n^a
-    if (sizeof(R) == 8 && (c.do_xc || c.a56)) e3 = exp(lx * (1.0 / 3.0));
+    if (sizeof(R) == 8 && (c.do_xc || c.a56)) {
+      ie3 = rcbrt_pos(nd);
+      e3 = nd * ie3 * ie3;
+    }
     if (c.do_tf) {
       double eta, psi;
       bad += fd_lookup(lx - c.lnnT, fd, eta, psi);
@@ -492,7 +501,7 @@ __device__ __forceinline__ void point_terms(R ph, const PointCfg &c, R a, R a2, 
         eps = ef;
         vx = vf;
       } else {
-        pz81_ln_e3(lx, e3, c.xcj, eps, vx);
+        pz81_ln_e3(lx, e3, ie3, c.xcj, eps, vx);
       }
       e_xc += nd * eps;
       v += vx;
