@@ -189,7 +189,10 @@ typedef struct {
  * limited-memory BFGS on phi (the minimisation the paper calls its SCF
  * iterations). rho_dev: FP64 device field; input guess if warm_start,
  * output density always. Returns SKX_OK, SKX_NOT_CONVERGED (best state
- * returned) or an error. Synchronises the stream. */
+ * returned) or an error. SKX_MIXED: a numerical failure of the FP32 phase
+ * ends the solve with that phase's status (no FP64 refinement from it);
+ * skx_run_batch and the serving engine apply the same rule. Synchronises
+ * the stream. */
 int skx_optimize_density(skx_ctx *ctx, void *rho_dev, const skx_opt_params *p,
                          skx_opt_result *res);
 
