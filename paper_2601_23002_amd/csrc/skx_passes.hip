@@ -1713,6 +1713,18 @@ __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typenam
 // (N/2) % TK == 0: the column blocks stop below the Nyquist column, which
 // extra workgroups take for four y rows each, one per wavefront.
 // ---------------------------------------------------------------------------
+// LDS of the shaped pass B in complex elements before its twiddle table:
+// the four field tiles in MODE_EVAL; in MODE_PREC (one field) one tile, or
+// the Nyquist workgroups' per-wavefront tiles where those exist, so the
+// preconditioner's launches take a quarter of the LDS and fit more
+// workgroups per CU.
+template <int N, int TK, int MODE> constexpr int passb_tw_off() {
+  constexpr int TP = TK + 1;
+  constexpr bool RAG = (N / 2) % TK != 0;
+  constexpr int NY = RAG ? 0 : 4 * NFIELD * (N + 1);
+  return MODE == MODE_EVAL ? NFIELD * N * TP : (N * TP > NY ? N * TP : NY);
+}
+
 template <typename R, int N, int TK, int MODE>
 __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first, int nsolve,
                                                 int grid, const double *twbank) {
@@ -1741,7 +1753,7 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   const int rem = item - s * PER;
   if constexpr (!RAG) {
     if (rem >= N * NB) {
-      V *tw = reinterpret_cast<V *>(smem) + NFIELD * N * TP;
+      V *tw = reinterpret_cast<V *>(smem) + passb_tw_off<N, TK, MODE>();
       load_twiddles(tw, twbank, S.p1.tw, N, tid, NT);
       __syncthreads();
       passB_nyquist<R, N, MODE>(S, (rem - N * NB) * NW + wave,
@@ -1754,8 +1766,8 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   const int k0 = kb * TK;
   const int tkv = RAG ? min(TK, N / 2 + 1 - k0) : TK;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
-  V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N][TP]
-  V *tw1 = tile + NFIELD * N * TP;
+  V *tile = reinterpret_cast<V *>(smem);             // [NFIELD][N][TP] (MODE_PREC: [1][N][TP])
+  V *tw1 = tile + passb_tw_off<N, TK, MODE>();
   SKX_G V *spec = gptr<V>(S.spec) + (size_t)jy * S.pitch + k0;
   const size_t rowstride = (size_t)S.n2 * S.pitch;
   const int cc = MODE == MODE_EVAL ? wave : 0;       // field slot of this wavefront
@@ -2279,13 +2291,15 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
     if (g.gridB > 0 && (mask & 2) && (g.shape & 2) && g.tk == TK) {
       constexpr bool RAG = (N / 2) % TK != 0;
       const int gb = g.nsolve * (RAG ? N * ((N / 2 + TK) / TK) : N * (N / 2 / TK) + N / 4);
-      const size_t lb = (NFIELD * N * (TK + 1) + N) * sizeof(V);
-      if (mode == MODE_EVAL)
+      if (mode == MODE_EVAL) {
+        const size_t lb = (passb_tw_off<N, TK, MODE_EVAL>() + N) * sizeof(V);
         SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_EVAL>), dim3(gb), dim3(256), lb, s, g.dev,
                          g.firstB, g.nsolve, gb, twbank);
-      else
+      } else {
+        const size_t lb = (passb_tw_off<N, TK, MODE_PREC>() + N) * sizeof(V);
         SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_PREC>), dim3(gb), dim3(256), lb, s, g.dev,
                          g.firstB, g.nsolve, gb, twbank);
+      }
     }
   }
   if (g.gridC > 0 && (mask & 4) && (g.shape & 4)) {
