@@ -367,7 +367,7 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
                std::vector<int> &fa, std::vector<int> &fb, std::vector<int> &fc) {
   const int n = (int)hs.size();
   fa.assign(n + 1, 0); fb.assign(n + 1, 0); fc.assign(n + 1, 0);
-  size_t la = 0, lb = 0, lc = 0;
+  size_t la = 0, lb = 0, lc = 0, lbp = 1024;
   for (int i = 0; i < n; ++i) {
     const SolveDev &h = hs[i];
     fa[i + 1] = fa[i] + h.n1 * h.nf;
@@ -376,6 +376,8 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
     size_t a, b, cc;
     lds_sizes(h, prec, a, b, cc);
     lb = std::max(lb, b);
+    // the preconditioner's pass B holds one field's tile
+    lbp = std::max(lbp, (size_t)(prec == 0 ? 16 : 8) * ((size_t)h.n1 * (h.tk + 1) + h.n1));
     if (!(h.big & 1)) la = std::max(la, a);
     // the forward-only check (debug 1) launches no pass C
     if (!(h.big & 2) && h.debug != 1) lc = std::max(lc, cc);
@@ -396,7 +398,7 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
                                     8 * (size_t)h.n2 * h.n3);
   g.accC_lds = lc_acc <= 80 * 1024 ? 1 : 0;
   if (g.accC_lds) lc = std::max(lc, lc_acc);
-  g.ldsA = la; g.ldsB = lb; g.ldsC = lc;
+  g.ldsA = la; g.ldsB = lb; g.ldsC = lc; g.ldsBp = std::min(lbp, lb);
   g.bigA = g.smallA = g.bigC = g.smallC = 0;
   for (const SolveDev &h : hs) {
     ((h.big & 1) ? g.bigA : g.smallA) = 1;

@@ -157,6 +157,7 @@ struct PassGroup {
   int gridA, gridB, gridC;         // work items (workgroups) of the runtime-shaped passes
   const int *firstA, *firstB, *firstC;  // device prefix sums (nsolve+1)
   size_t ldsA, ldsB, ldsC;
+  size_t ldsBp;                    // pass B of the preconditioner (one field)
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int bigA, smallA, bigC, smallC;  // solves on the chunked / in-LDS kernels of passes A, C
 };

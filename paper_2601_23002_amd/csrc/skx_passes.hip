@@ -2333,11 +2333,12 @@ static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_
 // width; every solve of a group has the same).
 template <typename R, int TK, int MODE>
 static void launch_passB_runtime(const PassGroup &g, const double *twbank, hipStream_t s) {
+  const size_t lds = MODE == MODE_EVAL ? g.ldsB : g.ldsBp;
   if (wide_b<R>(g))
-    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE>), dim3(g.gridB), dim3(512), g.ldsB, s, g.dev,
+    SKX_TIMED_LAUNCH((k_passB<R, 512, TK, MODE>), dim3(g.gridB), dim3(512), lds, s, g.dev,
                      g.firstB, g.nsolve, g.gridB, twbank);
   else
-    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE>), dim3(g.gridB), dim3(256), g.ldsB, s, g.dev,
+    SKX_TIMED_LAUNCH((k_passB<R, 256, TK, MODE>), dim3(g.gridB), dim3(256), lds, s, g.dev,
                      g.firstB, g.nsolve, g.gridB, twbank);
 }
 
