@@ -190,6 +190,16 @@ void lds_sizes(const SolveDev &h, int prec, size_t &a, size_t &b, size_t &c) {
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
+// LDS bytes of the split plane kernels for one solve: a row-pair chunk
+// (rows of pitch 2 nh, z twiddles) and a column chunk (pitch split_cc + 1,
+// y twiddles)
+void split_lds(const SolveDev &h, int prec, size_t &row, size_t &col) {
+  const size_t v = prec == 0 ? 16 : 8;
+  row = v * ((size_t)h.rp * 2 * h.nh + h.n3);
+  col = v * ((size_t)h.n2 * (split_cc(prec) + 1) + h.n2);
+  row = std::max(row, (size_t)1024);
+}
+
 // Allocate (or reuse) the buffers of one precision instance and fill the
 // descriptor's grid and buffer fields.
 // Points per workgroup of the optimiser update: larger on large grids,
@@ -198,12 +208,21 @@ constexpr size_t LDS_MAX = 160 * 1024;
 int update_chunk(long long M) { return M >= (1LL << 20) ? UCHUNK : CHUNK; }
 
 // Width (complex columns) of pass B's column blocks, which also aligns the
-// spectrum pitch: 8 in FP64 and 16 in FP32; for the cubic lengths with
+// spectrum pitch: 8 in FP64 and 16 in FP32, narrower on long x axes; for
+// the cubic lengths with
 // compile-time-shaped kernels 16 in FP32 only where it divides n/2, else 8.
 // Where 8 does not divide n/2 either (36, 40, 50, 54, 60, 72) the shaped
 // pass B takes ragged blocks over all n/2 + 1 columns.
 int block_width(int n1, int n2, int n3, int prec) {
-  const int tk = prec == 0 ? 8 : 16;
+  // Pass B's workgroup holds an x tile of n1 x (NFIELD tk) complex values;
+  // on long x axes narrower blocks keep it small enough for several
+  // workgroups per CU (measured on MI355X, runtime-shaped pass B: FP64
+  // blocks of 4 from 78 points on, 128^3 179 -> 138 us and 192^3 667 ->
+  // 589 us for two solves, neutral at 96^3; FP32 blocks of 8 from 158 points
+  // on, 192^3 444 -> 315 us, while at 96^3-144^3 blocks of 16 stay faster).
+  int tk = prec == 0 ? 8 : 16;
+  const size_t lim = prec == 0 ? 40 * 1024 : 80 * 1024;
+  while (tk > 4 && (size_t)(prec == 0 ? 16 : 8) * n1 * (NFIELD * tk + 1) > lim) tk /= 2;
   if (n1 != n2 || n2 != n3) return tk;
   switch (n1) {
     case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: case 80: break;
@@ -240,7 +259,8 @@ ArenaLayout arena_layout(int n1, int n2, int n3, int prec, int m, bool own_hist)
   L.o_S = take(hist); L.o_Y = take(hist);
   L.o_spec = take(2 * rsz * H * NFIELD); L.o_vloc = take(2 * rsz * H);
   L.o_pA = take(8 * (size_t)nwg * PART_A); L.o_pB = take(8 * (size_t)n2 * nkb * PART_B);
-  L.o_pC = take(8 * (size_t)n1 * PART_C); L.o_pU = take(8 * (size_t)nwu * NDOT);
+  const int nrc = (n2 / 2 + split_rp(n3) - 1) / split_rp(n3);
+  L.o_pC = take(8 * (size_t)n1 * nrc * PART_C); L.o_pU = take(8 * (size_t)nwu * NDOT);
   L.o_pD = take(8 * (size_t)nwg * 2);
   L.total = off;
   return L;
@@ -295,6 +315,9 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h = SolveDev{};
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = nh; h.pitch = pitch;
   h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg; h.mh = m;
+  h.rp = split_rp(n3);
+  h.nrc = (n2 / 2 + h.rp - 1) / h.rp;
+  h.rowsC = n1;
   h.uchunk = update_chunk(M);
   h.nwg_upd = (int)((M + h.uchunk - 1) / h.uchunk);
   h.M = M; h.H = H;
@@ -347,7 +370,7 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
 
 // Length of the compile-time-shaped kernels a solve runs on (0: the
 // runtime-shaped ones): cubic grids of the lengths with such kernels, unless
-// they are switched off, every plane is forced onto the chunked kernels, or
+// they are switched off, every plane is forced onto the split kernels, or
 // the solve is an FFT check.
 int shaped_length(const SolveDev &h) {
   if (!g_shape_kernels || g_chunk_planes || h.debug) return 0;
@@ -357,9 +380,6 @@ int shaped_length(const SolveDev &h) {
     default: return 0;
   }
 }
-
-// Pass B's compile-time-shaped kernel needs whole column blocks below the
-// Nyquist column.
 
 // Prefix sums of passes A, B, C of one group, its runtime-shaped LDS sizes
 // and kernel choices.
@@ -400,10 +420,22 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
   if (g.accC_lds) lc = std::max(lc, lc_acc);
   g.ldsA = la; g.ldsB = lb; g.ldsC = lc; g.ldsBp = std::min(lbp, lb);
   g.bigA = g.smallA = g.bigC = g.smallC = 0;
+  g.krow = g.kcol = 0;
+  g.ldsRow = g.ldsCol = 0;
   for (const SolveDev &h : hs) {
     ((h.big & 1) ? g.bigA : g.smallA) = 1;
     ((h.big & 2) ? g.bigC : g.smallC) = 1;
+    if (h.big) {
+      size_t lr, lcol;
+      split_lds(h, prec, lr, lcol);
+      g.krow = std::max(g.krow, h.nrc);
+      g.kcol = std::max(g.kcol, (h.nh + split_cc(prec) - 1) / split_cc(prec));
+      g.ldsRow = std::max(g.ldsRow, lr);
+      g.ldsCol = std::max(g.ldsCol, lcol);
+    }
   }
+  if (g.ldsRow > LDS_MAX || g.ldsCol > LDS_MAX)
+    return fail(c, SKX_E_INVALID, "grid too large for the split plane kernels at this precision");
   return SKX_OK;
 }
 
@@ -413,11 +445,12 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
 int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveDev *ddev,
                 int *dfirst, BatchLaunch &bl, hipStream_t s) {
   const int n = (int)hs_in.size();
-  // Passes A and C of planes beyond LDS take the chunked kernels, and so do
-  // those where the chunked kernel was measured faster on MI355X: FP32
-  // pass C from 24 KB planes (80^2) on, FP32 pass A from 80 KB (144^2);
-  // in FP64 the in-LDS kernels are faster wherever they fit. Solves on the
-  // compile-time-shaped kernels take none.
+  // Passes A and C of planes beyond LDS take the split kernels, and so do
+  // those where the split kernels were measured faster on MI355X: pass C
+  // from 24 KB planes (80^2) on in FP32 and from 80 KB (108^2) in FP64
+  // (108^3 FP64 275 -> 188 us for three solves, 128^3 200 -> 177 us), FP32
+  // pass A from 80 KB (144^2); FP64 pass A is faster in LDS wherever it
+  // fits. Solves on the compile-time-shaped kernels take none.
   std::vector<SolveDev> hs(hs_in);
   for (SolveDev &h : hs) {
     size_t a, b, cc;
@@ -425,12 +458,13 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
     const size_t plane = (prec == 0 ? 16 : 8) * (size_t)h.n2 * h.nh;
     const bool forced = g_chunk_planes && !h.debug;
     const bool bigA = forced || a > LDS_MAX || (prec == 1 && plane > 80 * 1024);
-    const bool bigC = forced || cc > LDS_MAX || (prec == 1 && plane > 24 * 1024);
+    const bool bigC = forced || cc > LDS_MAX || plane > (size_t)(prec == 1 ? 24 : 80) * 1024;
     h.big = (bigA ? 1 : 0) | (bigC ? 2 : 0);
-    // the forward-only check (debug 1) keeps the chunked pass A; the
-    // chunked pass C has no check mode
+    // the forward-only check (debug 1) keeps the split pass A; the split
+    // pass C has no check mode
     if (h.debug) h.big &= h.debug == 1 ? 1 : 0;
     if (shaped_length(h)) h.big = 0;
+    h.rowsC = (h.big & 2) ? h.n1 * h.nrc : h.n1;
   }
   std::vector<int> fv(n + 1), fu(n + 1);
   fv[0] = fu[0] = 0;
@@ -512,11 +546,12 @@ int check_grid(skx_ctx *c, int prec) {
   h.n1 = n1; h.n2 = n2; h.n3 = n3; h.nh = n3 / 2 + 1; h.nf = NFIELD; h.tk = prec == 0 ? 8 : 16;
   size_t a, b, cc;
   lds_sizes(h, prec, a, b, cc);
-  // planes beyond LDS run the chunked kernels, which need room for one row
-  // pair and two columns; pass B's x tile must fit as it is
-  const size_t v = prec == 0 ? 16 : 8;
-  const size_t cap = BIG_LDS / v - n2 - n3;
-  if (b > LDS_MAX || cap < 2 * (size_t)h.nh || cap < 2 * (size_t)n2)
+  // planes beyond LDS run the split kernels (a chunk of row pairs, a chunk
+  // of columns); pass B's x tile must fit as it is
+  h.rp = split_rp(n3);
+  size_t lr, lcol;
+  split_lds(h, prec, lr, lcol);
+  if (b > LDS_MAX || lr > LDS_MAX || lcol > LDS_MAX)
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
   (void)a;
   return SKX_OK;

@@ -17,7 +17,18 @@ constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinit
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
 constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
 constexpr int CHUNK = 1024;        // grid points per workgroup in the vector passes
-constexpr size_t BIG_LDS = 96 * 1024;   // LDS of the chunked plane kernels (bytes)
+constexpr int SPLIT_NT = 256;      // threads of the split plane kernels (planes beyond LDS)
+constexpr int SPLIT_EPT = 8;       // complex elements per thread of their row-pair chunks
+constexpr int SPLIT_RPMAX = 16;    // row pairs per chunk at most (measured: 8 -> 16 cuts
+                                   // passes A and C 2-5% at 144^3 and 192^3; 4 is 10-20% slower)
+// Row pairs per chunk of the split plane kernels (the chunk's rp * n3
+// complex elements are at most SPLIT_EPT per thread), and columns per
+// column chunk (128-byte row segments in both precisions).
+__host__ __device__ constexpr int split_rp(int n3) {
+  return SPLIT_EPT * SPLIT_NT / n3 < 1 ? 1
+         : (SPLIT_EPT * SPLIT_NT / n3 > SPLIT_RPMAX ? SPLIT_RPMAX : SPLIT_EPT * SPLIT_NT / n3);
+}
+__host__ __device__ constexpr int split_cc(int prec) { return prec == 0 ? 8 : 16; }
 constexpr int UCHUNK = 4096;       // grid points per workgroup of the optimiser update on
                                    // large grids (fewer rows of its 58 partial sums)
 constexpr int NPREFIX = 5;         // batch prefix-sum arrays: A, B, C, vector, update
@@ -74,7 +85,9 @@ struct SolveDev {
   int nwg_upd, uchunk;             // workgroups of the optimiser update and their points
   int mh;                          // history slots allocated (>= the solve's m)
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
-  int big;                         // passes on the chunked plane kernels: 1 A, 2 C
+  int big;                         // passes on the split plane kernels: 1 A, 2 C
+  int rp, nrc;                     // split plane kernels: row pairs per chunk, chunks per plane
+  int rowsC;                       // rows of pass C partial sums (n1, n1 * nrc when split)
   unsigned terms;
   int xc;                          // 1 published PZ81 fit, 2 its C1-joined branches
   int hist32;                      // FP64 fields with the history S, P Y stored in FP32
@@ -145,7 +158,7 @@ constexpr int MAX_GROUPS = 12;     // pass launch groups: runtime-shaped (by blo
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the
-// runtime-shaped (and chunked) kernels. Each group has its own copies of
+// runtime-shaped (and split) kernels. Each group has its own copies of
 // its solves' descriptors and prefix sums of its pass work items, so every
 // launch covers only the solves it computes.
 struct PassGroup {
@@ -159,7 +172,9 @@ struct PassGroup {
   size_t ldsA, ldsB, ldsC;
   size_t ldsBp;                    // pass B of the preconditioner (one field)
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
-  int bigA, smallA, bigC, smallC;  // solves on the chunked / in-LDS kernels of passes A, C
+  int bigA, smallA, bigC, smallC;  // solves on the split / in-LDS kernels of passes A, C
+  int krow, kcol;                  // split kernels: most row-pair and column chunks per plane
+  size_t ldsRow, ldsCol;           // and their LDS
 };
 
 struct BatchLaunch {

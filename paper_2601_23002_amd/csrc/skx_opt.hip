@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_finalize_eval(SolveDev *dev, int nsolve
   double v[NP];
   row_sums<PART_A, 0>(S.partA, S.nwg_vec, tid, v);
   row_sums<PART_B, PART_A>(S.partB, S.n2 * S.nkb, tid, v);
-  row_sums<PART_C, PART_A + PART_B>(S.partC, S.n1, tid, v);
+  row_sums<PART_C, PART_A + PART_B>(S.partC, S.rowsC, tid, v);
   put_slice(&lst, tid, sv);
   block_reduce<NP>(v, sh, tid, 256, t);
   if (tid == 0) finalize_eval_body(&lst, S, t, t + PART_A, t + PART_A + PART_B, ph);

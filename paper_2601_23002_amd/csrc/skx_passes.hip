@@ -1074,12 +1074,15 @@ __global__ __launch_bounds__(NT, 4) void k_passC(SolveDev *dev, const int *first
 
 // ---------------------------------------------------------------------------
 // Passes A and C for planes whose half spectrum does not fit in LDS (FP64
-// beyond 128 x 128, FP32 beyond 192 x 192): one workgroup per plane (and
-// field, in pass A's evaluation) works through the plane in chunks of row
-// pairs for the z transforms and chunks of columns for the y transforms,
-// the half spectrum staying in the plane's HBM slot in between. The
-// workgroup reads back only what it wrote itself, after a barrier (the plane
-// stays in L2 meanwhile).
+// beyond 128 x 128, FP32 beyond 192 x 192, and FP32 pass C from 80 x 80):
+// each pass runs as two launches over many small workgroups, so that many of
+// them share a CU and hide each other's load latency. Pass A: z transforms
+// over chunks of rp row pairs (one workgroup per chunk takes every field,
+// reading phi_t once), then y transforms over chunks of split_cc columns of
+// one field. Pass C: the inverse y transforms over column chunks, then the
+// inverse z transforms over row-pair chunks, accumulating dE/dphi in
+// registers over the fields. The half spectrum sits in its HBM slot between
+// the two launches of a pass.
 // ---------------------------------------------------------------------------
 // Loop over the elements e = tid, tid + NT, ... < tot with U iterations' loads
 // in flight: load(e) for U elements first, then use(e, loaded) for each.
@@ -1099,276 +1102,289 @@ __device__ __forceinline__ void batched(int tot, int tid, FL load, FU use) {
     }
   }
 }
+
 template <typename R> struct Quad { R a, b, c, d; };
 
-template <typename V>
-__device__ __forceinline__ int big_cap(int n2, int n3) {
-  return (int)(BIG_LDS / sizeof(V)) - n2 - n3;     // complex values of LDS work space
+// Row-pair chunk `j` of an x-plane: work item -> (solve, plane, chunk), or
+// false for items past the solve's chunks or phase.
+struct SplitItem { int s, plane, j; };
+template <int MODE>
+__device__ __forceinline__ bool split_item(const SolveDev *dev, const int *first, int nsolve,
+                                           int item, int per, int bigbit, SplitItem &it) {
+  const int pi = item / per;
+  it.j = item - pi * per;
+  it.s = find_solve(first, nsolve, pi);
+  const SolveDev &S = dev[it.s];
+  if (!(S.big & bigbit)) return false;
+  if (!active_phase<MODE>(cptr<OptState>(S.st)->phase)) return false;
+  it.plane = pi - first_of(first, it.s);
+  return true;
 }
 
-// y transforms of every column of the plane's half spectrum, in place in HBM.
-template <typename V, bool INV, int NT>
-__device__ void big_columns(V *buf, SKX_G V *spec, const SolveDev &S, const V *tw2, int tid) {
-  const int n2 = S.n2, nh = S.nh, pitch = S.pitch;
-  const int cap = big_cap<V>(n2, S.n3);
-  const int cc = max(1, min(nh, cap / n2 - 1)), ccp = cc + 1;
-  for (int k0 = 0; k0 < nh; k0 += cc) {
-    const int kc = min(cc, nh - k0);
-    const UDiv dkc = make_udiv((unsigned)kc);
-    batched<8, NT, V>(
-        n2 * kc, tid,
-        [&](int e) {
-          const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
-          return ldg(spec + (size_t)y * pitch + k0 + kk);
-        },
-        [&](int e, const V &v) {
-          const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
-          buf[y * ccp + kk] = v;
-        });
-    __syncthreads();
-    fft_lds<V, MAXB_A, INV>(buf, S.p2, kc, ccp, 1, tw2, tid, NT);
-    for (int e = tid; e < n2 * kc; e += NT) {
-      const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
-      stg(spec + (size_t)y * pitch + k0 + kk, buf[y * ccp + kk]);
-    }
-    __syncthreads();
-  }
-}
-
-template <typename R, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_passA_big(SolveDev *dev, const int *first, int nsolve,
-                                                  int grid, const double *twbank) {
+// Pass A, z transforms of one chunk of row pairs: every field built from
+// phi_t held in registers (MODE_PREC: r_t = dE/dphi - 2 mu_t phi_t, also
+// stored), rows 2p and 2p+1 packed as one complex row, then split into the
+// two rows' half spectra straight to HBM.
+template <typename R, int MODE>
+__global__ __launch_bounds__(SPLIT_NT, 4) void k_passA_rows(SolveDev *dev, const int *first,
+                                                         int nsolve, int grid, int krow,
+                                                         const double *twbank) {
   typedef typename Vec2<R>::T V;
+  static_assert(derive_na<R>(), "the split kernels derive n^a from phi_t");
+  constexpr int NT = SPLIT_NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
-  const int s = find_solve(first, nsolve, item);
-  const SolveDev &S = dev[s];
-  if (!(S.big & 1)) return;
+  SplitItem it;
+  if (!split_item<MODE>(dev, first, nsolve, item, krow, 1, it)) return;
+  const SolveDev &S = dev[it.s];
+  if (it.j >= S.nrc) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
-  if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
   const int tid = threadIdx.x;
-  const int local = item - first_of(first, s);
-  const int nf = MODE == MODE_EVAL ? S.nf : 1;
-  const int plane = local / nf;
-  const int fb = MODE == MODE_EVAL ? nth_field(S.fields, local - plane * nf) : 0;
-  const int n2 = S.n2, n3 = S.n3, nh = S.nh, pl = nh, pitch = S.pitch;
-  V *tw2 = reinterpret_cast<V *>(smem);
-  V *tw3 = tw2 + n2;
+  const int n2 = S.n2, n3 = S.n3, nh = S.nh, pitch = S.pitch, pl2 = 2 * nh;
+  const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  V *tw3 = reinterpret_cast<V *>(smem);
   V *buf = tw3 + n3;
-  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
-  __syncthreads();
-  const R invM = (R)(1.0 / (double)S.M);
-  const size_t pbase = (size_t)plane * n2 * n3;
-  SKX_G V *spec = gptr<V>(S.spec) + (size_t)(MODE == MODE_EVAL ? S.slot[fb] : 0) * S.H +
-                  (size_t)plane * n2 * pitch;
+  const size_t pbase = (size_t)it.plane * n2 * n3 + (size_t)2 * p0 * n3;
+  const UDiv dn3 = make_udiv((unsigned)n3);
   const SKX_G R *pt = gptr<R>(S.phi2[1 - par]) + pbase;
-  const SKX_G R *fa = gptr<R>(S.npa) + pbase;
   const SKX_G R *gr = gptr<R>(S.grad) + pbase;
   SKX_G R *rt = gptr<R>(S.r2[1 - par]) + pbase;
-  const R n0 = (R)S.n0, n0a = (R)S.n0a;
   const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
-  const int cz = n2 / 2, nk = n3 / 2 + 1;
-  const int rc = max(1, min(cz, big_cap<V>(n2, n3) / (2 * pl)));
-  const UDiv dn3 = make_udiv((unsigned)n3), dnk = make_udiv((unsigned)nk);
-  for (int p0 = 0; p0 < cz; p0 += rc) {
-    const int np = min(cz, p0 + rc) - p0;
-    // rows 2p and 2p+1 of the pair as one complex row
-    // (a, b): phi_t or g of the two rows, (c, d): n^a or phi_t
-    batched<8, NT, Quad<R>>(
-        np * n3, tid,
+  const R invM = (R)(1.0 / (double)S.M);
+  const R n0 = (R)S.n0, n0a = (R)S.n0a;
+  const int nk = n3 / 2 + 1;
+  const UDiv dnk = make_udiv((unsigned)nk);
+  const int nfl = MODE == MODE_EVAL ? S.nf : 1;
+#pragma unroll 1
+  for (int c = 0; c < nfl; ++c) {
+    const int fb = MODE == MODE_EVAL ? nth_field(S.fields, c) : 0;
+    // rows 2q and 2q+1 as one complex row; phi_t is read again per field
+    // (from cache after the first)
+    batched<4, NT, Quad<R>>(
+        tot, tid,
         [&](int e) {
-          const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-          const int o = 2 * (p0 + q) * n3 + z;
-          Quad<R> w{(R)0, (R)0, (R)0, (R)0};
-          if (MODE == MODE_EVAL) {
-            if (fb != 2 || derive_na<R>()) { w.a = pt[o]; w.b = pt[o + n3]; }
-            if (fb >= 2 && !derive_na<R>()) { w.c = fa[o]; w.d = fa[o + n3]; }
-          } else {
-            w.a = gr[o]; w.b = gr[o + n3]; w.c = pt[o]; w.d = pt[o + n3];
-          }
+          const int q = (int)udiv((unsigned)e, dn3), o = 2 * q * n3 + (e - q * n3);
+          Quad<R> w{pt[o], pt[o + n3], (R)0, (R)0};
+          if (MODE == MODE_PREC) { w.c = gr[o]; w.d = gr[o + n3]; }
           return w;
         },
         [&](int e, const Quad<R> &w) {
           const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-          const int o = 2 * (p0 + q) * n3 + z;
           R x[2];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const R u = h ? w.b : w.a;
-            const R f = (MODE == MODE_EVAL && derive_na<R>() && fb >= 2) ? derived_na(u, na_cfg<R>(S))
-                                                                           : (h ? w.d : w.c);
-            if (MODE == MODE_EVAL)
+            if (MODE == MODE_EVAL) {
+              const R f = fb >= 2 ? derived_na(u, na_cfg<R>(S)) : (R)0;
               x[h] = fb == 0 ? u : fb == 1 ? u * u : fb == 2 ? f : (f - n0a) * (u * u - n0);
-            else {
-              x[h] = u - mu2 * f;
-              rt[o + h * n3] = x[h];
+            } else {
+              x[h] = (h ? w.d : w.c) - mu2 * u;        // r_t
+              rt[2 * q * n3 + z + h * n3] = x[h];
             }
           }
           V v;
           v.x = x[0] * invM;
           v.y = x[1] * invM;
-          buf[q * 2 * pl + z] = v;
+          buf[q * pl2 + z] = v;
         });
     __syncthreads();
-    fft_lds<V, MAXB_A, false>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
-    // split into the two rows' half spectra, straight to HBM
+    fft_lds<V, MAXB_A, false>(buf, S.p3, np, 1, pl2, tw3, tid, NT);
+    SKX_G V *spec = gptr<V>(S.spec) + (size_t)c * S.H + ((size_t)it.plane * n2 + 2 * p0) * pitch;
     for (int e = tid; e < np * nk; e += NT) {
       const int q = (int)udiv((unsigned)e, dnk), k = e - q * nk;
-      const V X = buf[q * 2 * pl + k];
-      const V Xm = buf[q * 2 * pl + (k == 0 ? 0 : n3 - k)];
+      const V X = buf[q * pl2 + k];
+      const V Xm = buf[q * pl2 + (k == 0 ? 0 : n3 - k)];
       V A, B;
       A.x = (R)0.5 * (X.x + Xm.x); A.y = (R)0.5 * (X.y - Xm.y);
       B.x = (R)0.5 * (X.y + Xm.y); B.y = (R)-0.5 * (X.x - Xm.x);
-      const int y = 2 * (p0 + q);
-      stg(spec + (size_t)y * pitch + k, A);
-      stg(spec + (size_t)(y + 1) * pitch + k, B);
+      stg(spec + (size_t)(2 * q) * pitch + k, A);
+      stg(spec + (size_t)(2 * q + 1) * pitch + k, B);
     }
     __syncthreads();
   }
-  big_columns<V, false, NT>(buf, spec, S, tw2, tid);
 }
 
-template <typename R, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_passC_big(SolveDev *dev, const int *first, int nsolve,
-                                                  int grid, const double *twbank) {
+// y transforms (forward in pass A, inverse in pass C) of one chunk of
+// split_cc columns of one field's half-spectrum plane, in place in HBM.
+template <typename R, int MODE, bool INV>
+__global__ __launch_bounds__(SPLIT_NT, 4) void k_plane_cols(SolveDev *dev, const int *first,
+                                                         int nsolve, int grid, int kcol,
+                                                         const double *twbank) {
   typedef typename Vec2<R>::T V;
+  constexpr int NT = SPLIT_NT, NFC = MODE == MODE_EVAL ? NFIELD : 1;
+  constexpr int CC = split_cc(sizeof(R) == 8 ? 0 : 1), CCP = CC + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
-  const int s = find_solve(first, nsolve, item);
-  const SolveDev &S = dev[s];
-  if (!(S.big & 2)) return;
+  SplitItem it;
+  if (!split_item<MODE>(dev, first, nsolve, item, NFC * kcol, INV ? 2 : 1, it)) return;
+  const SolveDev &S = dev[it.s];
+  const int c = it.j / kcol, k0 = (it.j - c * kcol) * CC;
+  if (MODE == MODE_EVAL && c >= S.nf) return;
+  if (k0 >= S.nh) return;
+  const int tid = threadIdx.x;
+  const int n2 = S.n2, pitch = S.pitch, kc = min(CC, S.nh - k0);
+  V *tw2 = reinterpret_cast<V *>(smem);
+  V *buf = tw2 + n2;
+  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
+  SKX_G V *spec = gptr<V>(S.spec) + (size_t)c * S.H + (size_t)it.plane * n2 * pitch + k0;
+  const UDiv dkc = make_udiv((unsigned)kc);
+  batched<8, NT, V>(
+      n2 * kc, tid,
+      [&](int e) {
+        const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+        return ldg(spec + (size_t)y * pitch + kk);
+      },
+      [&](int e, const V &v) {
+        const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+        buf[y * CCP + kk] = v;
+      });
+  __syncthreads();
+  fft_lds<V, MAXB_A, INV>(buf, S.p2, kc, CCP, 1, tw2, tid, NT);
+  for (int e = tid; e < n2 * kc; e += NT) {
+    const int y = (int)udiv((unsigned)e, dkc), kk = e - y * kc;
+    stg(spec + (size_t)y * pitch + kk, buf[y * CCP + kk]);
+  }
+}
+
+// Pass C, inverse z transforms of one chunk of row pairs: for every field
+// the two rows' half spectra as one complex row, the C2R transform in LDS,
+// and dE/dphi = w0 + A + 2 phi_t B + c_P P + c_Q Q accumulated in
+// registers (MODE_PREC: the single field is P r_t); then the chunk's
+// partials of int phi_t dE/dphi.
+template <typename R, int MODE>
+__global__ __launch_bounds__(SPLIT_NT, 3) void k_passC_rows(SolveDev *dev, const int *first,
+                                                         int nsolve, int grid, int krow,
+                                                         const double *twbank) {
+  typedef typename Vec2<R>::T V;
+  constexpr int NT = SPLIT_NT, EPT = SPLIT_EPT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, grid);
+  if (item >= grid) return;
+  SplitItem it;
+  if (!split_item<MODE>(dev, first, nsolve, item, krow, 2, it)) return;
+  const SolveDev &S = dev[it.s];
+  if (it.j >= S.nrc) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
-  if (!active_phase<MODE>(st->phase)) return;
   const int par = st->par;
   const int tid = threadIdx.x;
-  const int plane = item - first_of(first, s);
-  const int n2 = S.n2, n3 = S.n3, pl = S.nh, pitch = S.pitch;
-  V *tw2 = reinterpret_cast<V *>(smem);
-  V *tw3 = tw2 + n2;
+  const int n2 = S.n2, n3 = S.n3, pitch = S.pitch, pl2 = 2 * S.nh;
+  const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  V *tw3 = reinterpret_cast<V *>(smem);
   V *buf = tw3 + n3;
-  load_twiddles(tw2, twbank, S.p2.tw, n2, tid, NT);
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
-  __syncthreads();
-  const size_t pbase = (size_t)plane * n2 * n3;
-  SKX_G V *spec0 = gptr<V>(S.spec) + (size_t)plane * n2 * pitch;
+  const size_t pbase = (size_t)it.plane * n2 * n3 + (size_t)2 * p0 * n3;
+  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
+  const SKX_G R *cfP = gptr<R>(S.fpt) + pbase, *cfQ = gptr<R>(S.qpt) + pbase;
+  SKX_G R *out = MODE == MODE_EVAL ? gptr<R>(S.grad) + pbase : gptr<R>(S.pr2[1 - par]) + pbase;
+  const UDiv dn3 = make_udiv((unsigned)n3);
+  // element i of this thread: row pair q, column z; og = its offset in the
+  // chunk's rows, q * pl2 + z its place in LDS
+  auto elem = [&](int i, int &q, int &z) {
+    const int e = tid + i * NT;
+    q = (int)udiv((unsigned)e, dn3);
+    z = e - q * n3;
+  };
+  R a0[EPT], a1[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    a0[i] = a1[i] = (R)0;
+    if (MODE == MODE_EVAL && tid + i * NT < tot) {
+      const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
+      int q, z;
+      elem(i, q, z);
+      a0[i] = v0[2 * q * n3 + z];              // w0 = 2 phi_t v0
+      a1[i] = v0[2 * q * n3 + z + n3];
+    }
+  }
   const int nfl = MODE == MODE_EVAL ? NFIELD : 1;
+#pragma unroll 1
   for (int fb = 0; fb < nfl; ++fb) {
     const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
     if (sl < 0) continue;
-    big_columns<V, true, NT>(buf, spec0 + (size_t)sl * S.H, S, tw2, tid);
+    const SKX_G V *spec = gptr<V>(S.spec) + (size_t)sl * S.H + ((size_t)it.plane * n2 + 2 * p0) * pitch;
+    // x_{2p} + i x_{2p+1} over the full row from the two half spectra
+    batched<4, NT, Quad<R>>(
+        tot, tid,
+        [&](int e) {
+          const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
+          const int kk = 2 * k <= n3 ? k : n3 - k;
+          const V Av = ldg(spec + (size_t)(2 * q) * pitch + kk);
+          const V Bv = ldg(spec + (size_t)(2 * q + 1) * pitch + kk);
+          return Quad<R>{Av.x, Av.y, Bv.x, Bv.y};
+        },
+        [&](int e, const Quad<R> &w) {
+          const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
+          R ay = w.b, by = w.d;
+          if (k == 0 || 2 * k == n3) { ay = 0; by = 0; }
+          else if (2 * k > n3) { ay = -ay; by = -by; }
+          V X;
+          X.x = w.a - by;
+          X.y = ay + w.c;
+          buf[q * pl2 + k] = X;
+        });
+    __syncthreads();
+    fft_lds<V, MAXB_C, true>(buf, S.p3, np, 1, pl2, tw3, tid, NT);
+    // this field's coefficients
+    // (phi_t for the 2 phi_t B term and the FP32 derivation of c_P, c_Q;
+    // the FP64 c_P, c_Q arrays)
+    R c0[EPT], c1[EPT];
+    const SKX_G R *cf = (fb == 1 || derive_coefs<R>()) ? phit : fb == 2 ? cfP : cfQ;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      c0[i] = c1[i] = (R)1;
+      if (MODE == MODE_EVAL && fb > 0 && tid + i * NT < tot) {
+        int q, z;
+        elem(i, q, z);
+        c0[i] = cf[2 * q * n3 + z];
+        c1[i] = cf[2 * q * n3 + z + n3];
+      }
+    }
+    const NaCfg<R> nc = na_cfg<R>(S);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      if (tid + i * NT < tot) {
+        int q, z;
+        elem(i, q, z);
+        const V X = buf[q * pl2 + z];
+        R k0 = c0[i], k1 = c1[i];
+        if (MODE == MODE_EVAL && fb == 1) { k0 *= (R)2; k1 *= (R)2; }
+        if (MODE == MODE_EVAL && fb >= 2 && derive_coefs<R>()) {
+          k0 = derived_coef(k0, fb, nc);
+          k1 = derived_coef(k1, fb, nc);
+        }
+        a0[i] += k0 * X.x;
+        a1[i] += k1 * X.y;
+      }
+    }
+    __syncthreads();
   }
-  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
-  const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
-  const SKX_G R *cfp[NFIELD] = {nullptr, phit, gptr<R>(S.fpt) + pbase, gptr<R>(S.qpt) + pbase};
-  SKX_G R *out = MODE == MODE_EVAL ? gptr<R>(S.grad) + pbase : gptr<R>(S.pr2[1 - par]) + pbase;
-  const int cz = n2 / 2;
-  const int rc = max(1, min(cz, big_cap<V>(n2, n3) / (2 * pl)));
-  const UDiv dn3 = make_udiv((unsigned)n3);
   double sphig = 0.0, bad = 0.0;
-  for (int p0 = 0; p0 < cz; p0 += rc) {
-    const int np = min(cz, p0 + rc) - p0;
-    if (MODE == MODE_EVAL) {
-      batched<8, NT, Quad<R>>(
-          np * n3, tid,
-          [&](int e) {
-            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-            const int o = 2 * (p0 + q) * n3 + z;
-            return Quad<R>{v0[o], v0[o + n3], (R)0, (R)0};
-          },
-          [&](int e, const Quad<R> &w) {
-            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-            const int o = 2 * (p0 + q) * n3 + z;
-            out[o] = w.a;                   // w0 = 2 phi_t v0
-            out[o + n3] = w.b;
-          });
-    }
-    for (int fb = 0; fb < nfl; ++fb) {
-      const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
-      if (sl < 0) continue;
-      const SKX_G V *spec = spec0 + (size_t)sl * S.H;
-      // x_{2p} + i x_{2p+1} over the full row from the two half spectra
-      batched<8, NT, Quad<R>>(
-          np * n3, tid,
-          [&](int e) {
-            const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
-            const int y = 2 * (p0 + q), kk = 2 * k <= n3 ? k : n3 - k;
-            const V Av = ldg(spec + (size_t)y * pitch + kk);
-            const V Bv = ldg(spec + (size_t)(y + 1) * pitch + kk);
-            return Quad<R>{Av.x, Av.y, Bv.x, Bv.y};
-          },
-          [&](int e, const Quad<R> &w) {
-            const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
-            R ay = w.b, by = w.d;
-            if (k == 0 || 2 * k == n3) { ay = 0; by = 0; }
-            else if (2 * k > n3) { ay = -ay; by = -by; }
-            V X;
-            X.x = w.a - by;
-            X.y = ay + w.c;
-            buf[q * 2 * pl + k] = X;
-          });
-      __syncthreads();
-      fft_lds<V, MAXB_C, true>(buf, S.p3, np, 1, 2 * pl, tw3, tid, NT);
-      batched<8, NT, Quad<R>>(
-          np * n3, tid,
-          [&](int e) {
-            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-            const int o = 2 * (p0 + q) * n3 + z;
-            Quad<R> w{(R)1, (R)1, (R)0, (R)0};
-            if (MODE == MODE_EVAL) {
-              if (fb >= 2 && derive_coefs<R>()) {
-                const NaCfg<R> nc = na_cfg<R>(S);
-                w.a = derived_coef(phit[o], fb, nc);
-                w.b = derived_coef(phit[o + n3], fb, nc);
-              } else if (fb > 0) {
-                w.a = cfp[fb][o];
-                w.b = cfp[fb][o + n3];
-              }
-              w.c = out[o];
-              w.d = out[o + n3];
-            }
-            return w;
-          },
-          [&](int e, const Quad<R> &w) {
-            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-            const int o = 2 * (p0 + q) * n3 + z;
-            const V X = buf[q * 2 * pl + z];
-            if (MODE == MODE_PREC) {
-              out[o] = X.x;
-              out[o + n3] = X.y;
-            } else {
-              const R s = fb == 1 ? (R)2 : (R)1;
-              out[o] = w.c + s * w.a * X.x;
-              out[o + n3] = w.d + s * w.b * X.y;
-            }
-          });
-      __syncthreads();
-    }
-    if (MODE == MODE_EVAL) {
-      batched<8, NT, Quad<R>>(
-          np * n3, tid,
-          [&](int e) {
-            const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-            const int o = 2 * (p0 + q) * n3 + z;
-            return Quad<R>{out[o], out[o + n3], phit[o], phit[o + n3]};
-          },
-          [&](int, const Quad<R> &w) {
-            sphig += (double)w.c * (double)w.a + (double)w.d * (double)w.b;
-            if (!(w.a == w.a)) bad += 1.0;
-            if (!(w.b == w.b)) bad += 1.0;
-          });
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    if (tid + i * NT < tot) {
+      int q, z;
+      elem(i, q, z);
+      const int o = 2 * q * n3 + z;
+      out[o] = a0[i];
+      out[o + n3] = a1[i];
+      if (MODE == MODE_EVAL) {
+        sphig += (double)phit[o] * (double)a0[i] + (double)phit[o + n3] * (double)a1[i];
+        if (!(a0[i] == a0[i])) bad += 1.0;
+        if (!(a1[i] == a1[i])) bad += 1.0;
+      }
     }
   }
   if (MODE == MODE_EVAL) {
     double v[PART_C] = {sphig, bad};
-    double tot[PART_C];
-    __syncthreads();
-    block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot);
+    double tot2[PART_C];
+    block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot2);
     if (tid == 0)
-      for (int q = 0; q < PART_C; ++q) S.partC[plane * PART_C + q] = tot[q];
+      for (int q = 0; q < PART_C; ++q)
+        S.partC[((size_t)it.plane * S.nrc + it.j) * PART_C + q] = tot2[q];
   }
 }
 
@@ -2342,7 +2358,29 @@ static void launch_passB_runtime(const PassGroup &g, const double *twbank, hipSt
                      g.firstB, g.nsolve, g.gridB, twbank);
 }
 
-// Runtime-shaped (and chunked) pass kernels over one group, for the passes
+// The split plane kernels of one group: pass A's z transforms over row-pair
+// chunks then its y transforms over column chunks; pass C in the opposite
+// order. Both launches of a pass are timed as that pass.
+template <typename R, int MODE>
+static void launch_split_a(const PassGroup &g, const double *twbank, hipStream_t s) {
+  const int gr = g.gridC * g.krow;
+  const int gc = g.gridC * (MODE == MODE_EVAL ? NFIELD : 1) * g.kcol;
+  SKX_TIMED_LAUNCH((k_passA_rows<R, MODE>), dim3(gr), dim3(SPLIT_NT), g.ldsRow, s, g.dev,
+                   g.firstC, g.nsolve, gr, g.krow, twbank);
+  SKX_TIMED_LAUNCH((k_plane_cols<R, MODE, false>), dim3(gc), dim3(SPLIT_NT), g.ldsCol, s, g.dev,
+                   g.firstC, g.nsolve, gc, g.kcol, twbank);
+}
+template <typename R, int MODE>
+static void launch_split_c(const PassGroup &g, const double *twbank, hipStream_t s) {
+  const int gr = g.gridC * g.krow;
+  const int gc = g.gridC * (MODE == MODE_EVAL ? NFIELD : 1) * g.kcol;
+  SKX_TIMED_LAUNCH((k_plane_cols<R, MODE, true>), dim3(gc), dim3(SPLIT_NT), g.ldsCol, s, g.dev,
+                   g.firstC, g.nsolve, gc, g.kcol, twbank);
+  SKX_TIMED_LAUNCH((k_passC_rows<R, MODE>), dim3(gr), dim3(SPLIT_NT), g.ldsRow, s, g.dev,
+                   g.firstC, g.nsolve, gr, g.krow, twbank);
+}
+
+// Runtime-shaped (and split) pass kernels over one group, for the passes
 // in `mask` (1|16 pass A's transform, 2 pass B, 4 pass C) that the group
 // does not run on compile-time-shaped kernels.
 template <typename R>
@@ -2355,9 +2393,7 @@ static void launch_eval_runtime(const PassGroup &g, const BatchLaunch &b, hipStr
     else if (g.smallA)
       SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_EVAL>), dim3(g.gridA), dim3(256), g.ldsA, s, g.dev,
                        g.firstA, g.nsolve, g.gridA, b.twbank, b.fd);
-    if (g.bigA)
-      SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_EVAL>), dim3(g.gridA), dim3(512), BIG_LDS, s,
-                       g.dev, g.firstA, g.nsolve, g.gridA, b.twbank);
+    if (g.bigA) launch_split_a<R, MODE_EVAL>(g, b.twbank, s);
   }
   if (g.gridB > 0 && (mask & 2) && !(g.shape & 2)) {
     switch (g.tk) {
@@ -2387,8 +2423,7 @@ static void launch_eval_runtime(const PassGroup &g, const BatchLaunch &b, hipStr
     }
   }
   if (g.gridC > 0 && (mask & 4) && !(g.shape & 4) && g.bigC)
-    SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_EVAL>), dim3(g.gridC), dim3(512), BIG_LDS, s,
-                     g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+    launch_split_c<R, MODE_EVAL>(g, b.twbank, s);
 }
 
 template <typename R>
@@ -2427,9 +2462,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
         else if (g.smallA)
           SKX_TIMED_LAUNCH((k_passA<R, 256, MODE_PREC>), dim3(g.gridC), dim3(256), g.ldsA, s,
                            g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
-        if (g.bigA)
-          SKX_TIMED_LAUNCH((k_passA_big<R, 512, MODE_PREC>), dim3(g.gridC), dim3(512), BIG_LDS, s,
-                           g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+        if (g.bigA) launch_split_a<R, MODE_PREC>(g, b.twbank, s);
       }
       if (g.gridB > 0 && (pm & 2) && !(g.shape & 2)) {
         switch (g.tk) {
@@ -2442,8 +2475,7 @@ static hipError_t launch_prec_t(const BatchLaunch &b, hipStream_t s, int mask) {
         SKX_TIMED_LAUNCH((k_passC<R, 512, false, MODE_PREC>), dim3(g.gridC), dim3(512), g.ldsC, s,
                          g.dev, g.firstC, g.nsolve, g.gridC, b.twbank, b.fd);
       if (g.gridC > 0 && (pm & 4) && !(g.shape & 4) && g.bigC)
-        SKX_TIMED_LAUNCH((k_passC_big<R, 512, MODE_PREC>), dim3(g.gridC), dim3(512), BIG_LDS, s,
-                         g.dev, g.firstC, g.nsolve, g.gridC, b.twbank);
+        launch_split_c<R, MODE_PREC>(g, b.twbank, s);
     }
   }
   return hipGetLastError();

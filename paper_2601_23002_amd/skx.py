@@ -473,8 +473,10 @@ def set_shape_kernels(mask=7):
 
 
 def set_plane_chunking(force=True):
-    """Run passes A and C of every plane in row-pair / column chunks (force)
-    or only of planes beyond LDS (default); returns the previous setting."""
+    """Run passes A and C of every plane on the split kernels (row-pair and
+    column chunks in separate launches; force) or only where they are chosen
+    (planes beyond LDS and the sizes measured faster; default); returns the
+    previous setting."""
     return bool(_lib.skx_set_plane_chunking(1 if force else 0))
 
 

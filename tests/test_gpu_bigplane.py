@@ -1,11 +1,14 @@
-"""Passes A and C in row-pair / column chunks, for planes whose half spectrum
-does not fit in LDS (FP64 beyond 128 x 128, FP32 beyond 192 x 192).
+"""Passes A and C on the split kernels (z transforms over row-pair chunks and
+y transforms over column chunks, in separate launches), for planes whose
+half spectrum does not fit in LDS (FP64 beyond 128 x 128, FP32 beyond
+192 x 192) and the sizes where they were measured faster.
 
-The chunked kernels are checked against the oracle on small grids with
-chunking forced, on planes that need it (FP64 8 x 144 x 144, FP32
+The split kernels are checked against the oracle on small grids with the
+split forced (one and several row-pair chunks per plane, ragged last column
+chunks, absent fields), on planes that need it (FP64 8 x 144 x 144, FP32
 8 x 216 x 216: large planes at an oracle cost of seconds), and through whole
 optimisations (forced against natural on 32^3; mixed against FP64 on
-8 x 144 x 144, which exercises the chunked preconditioner passes too).
+8 x 144 x 144, which exercises the split preconditioner passes too).
 """
 import dataclasses
 import sys
@@ -60,7 +63,29 @@ def test_forced_chunking_matches_oracle(precision):
     for n in (24, 30):
         s = W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, n, seed=n, beta=1.3)
         phi = W.random_phi(s, n + 1, amp=0.4)
-        _say(f"case: chunked planes forced, {precision}, {n}^3")
+        _say(f"case: split planes forced, {precision}, {n}^3")
+        old = skx.set_plane_chunking(True)
+        try:
+            _check(skx, torch, s, phi, prec, tol)
+        finally:
+            skx.set_plane_chunking(old)
+
+
+@pytest.mark.parametrize("beta,terms", [(0.0, W.TERM_ALL & ~W.TERM_VW),
+                                        (1.3, W.TERM_TF | W.TERM_HARTREE | W.TERM_LOCPP)])
+def test_forced_split_field_subsets_match_oracle(beta, terms):
+    """Absent fields (no h with beta = 0, no phi without vW, neither f nor h
+    without the nonlocal terms) leave spectrum slots unused; the split
+    kernels' field loops and column-chunk items must skip them consistently.
+    A 40-point z axis gives two row-pair chunks per plane (16 and 4 row pairs)
+    and a ragged last column chunk (21 columns: 8 + 8 + 5 in FP64, 16 + 5 in
+    FP32)."""
+    skx, torch = _lib()
+    for n1, prec, tol in ((40, skx.FP64, 1e-10), (16, skx.FP32, 2e-5)):
+        s = dataclasses.replace(W.uniform_system(8, 1.0, 0.4, 2.0, 1.0, 40, seed=51, beta=beta,
+                                                 terms=terms), n=(n1, 40, 40))
+        phi = W.random_phi(s, 52, amp=0.4)
+        _say(f"case: split planes forced, {n1}x40x40, beta={beta}, terms={terms}, prec {prec}")
         old = skx.set_plane_chunking(True)
         try:
             _check(skx, torch, s, phi, prec, tol)
@@ -73,7 +98,7 @@ def test_forced_chunking_optimisation_same_minimum():
     s = W.uniform_system(16, 1.0, 0.3, 2.0, 1.0, 32, seed=31)
     out = {}
     for force in (True, False):
-        _say(f"case: 32^3 FP64 optimise, chunking forced {force}")
+        _say(f"case: 32^3 FP64 optimise, split forced {force}")
         old = skx.set_plane_chunking(force)
         try:
             c = skx.Context(0).setup(s, precision=skx.FP64)
