@@ -220,9 +220,7 @@ int block_width(int n1, int n2, int n3, int prec) {
   // blocks of 4 from 78 points on, 128^3 179 -> 138 us and 192^3 667 ->
   // 589 us for two solves, neutral at 96^3; FP32 blocks of 8 from 158 points
   // on, 192^3 444 -> 315 us, while at 96^3-144^3 blocks of 16 stay faster).
-  int tk = prec == 0 ? 8 : 16;
-  const size_t lim = prec == 0 ? 40 * 1024 : 80 * 1024;
-  while (tk > 4 && (size_t)(prec == 0 ? 16 : 8) * n1 * (NFIELD * tk + 1) > lim) tk /= 2;
+  const int tk = passb_width(n1, prec);
   if (n1 != n2 || n2 != n3) return tk;
   switch (n1) {
     case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: case 80: break;
@@ -372,6 +370,15 @@ void fill_physics(skx_ctx *c, SolveDev &h) {
 // runtime-shaped ones): cubic grids of the lengths with such kernels, unless
 // they are switched off, every plane is forced onto the split kernels, or
 // the solve is an FFT check.
+// Large cubic length whose pass B alone runs on the compile-time-shaped
+// kernel (0: none), unless shaped pass B is switched off or the solve is an
+// FFT check.
+int shaped_b_length(const SolveDev &h) {
+  if (!(g_shape_kernels & 2) || h.debug) return 0;
+  if (h.n1 != h.n2 || h.n2 != h.n3 || !shaped_b_only(h.n1)) return 0;
+  return h.n1;
+}
+
 int shaped_length(const SolveDev &h) {
   if (!g_shape_kernels || g_chunk_planes || h.debug) return 0;
   if (h.n1 != h.n2 || h.n2 != h.n3) return 0;
@@ -402,7 +409,8 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
     // the forward-only check (debug 1) launches no pass C
     if (!(h.big & 2) && h.debug != 1) lc = std::max(lc, cc);
   }
-  if (g.shapeN == 0 && (la > LDS_MAX || lb > LDS_MAX || lc > LDS_MAX))
+  if ((!(g.shape & 1) && la > LDS_MAX) || (!(g.shape & 2) && lb > LDS_MAX) ||
+      (!(g.shape & 4) && lc > LDS_MAX))
     return fail(c, SKX_E_INVALID, "grid too large for the fused plane kernels at this precision");
   g.nsolve = n;
   g.gridA = fa[n]; g.gridB = fb[n]; g.gridC = fc[n];
@@ -474,7 +482,10 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
   }
   // pass groups: the runtime-shaped solves (one group per column-block
   // width), then one group per compile-time length
-  auto key_of = [](const SolveDev &h) { const int k = shaped_length(h); return k ? k : -h.tk; };
+  auto key_of = [](const SolveDev &h) {
+    const int k = shaped_length(h) ? shaped_length(h) : shaped_b_length(h);
+    return k ? k : -h.tk;
+  };
   std::vector<int> keys;
   for (const SolveDev &h : hs) {
     const int k = key_of(h);
@@ -498,10 +509,15 @@ int build_batch(skx_ctx *c, const std::vector<SolveDev> &hs_in, int prec, SolveD
       if (key_of(h) == keys[gi]) sub.push_back(h);
     g.tk = sub[0].tk;
     std::vector<int> fa, fb, fc;
+    // passes on compile-time-shaped kernels: all three for the lengths that
+    // have them, pass B alone for the large lengths (at the width the
+    // kernel is built for)
+    if (g.shapeN && shaped_b_only(g.shapeN))
+      g.shape = (g.tk == passb_width(g.shapeN, prec)) ? (g_shape_kernels & 2) : 0;
+    else if (g.shapeN)
+      g.shape = g_shape_kernels & 7;
     int rc = fill_group(c, sub, prec, g, fa, fb, fc);
     if (rc) return rc;
-    if (g.shapeN)
-      g.shape = g_shape_kernels & 7;
     Off o;
     o.desc = part.size();
     part.insert(part.end(), sub.begin(), sub.end());

@@ -17,6 +17,23 @@ constexpr int PART_B = 6;          // pass B: e_vw, e_h, f0, f1, e_loc, nonfinit
 constexpr int PART_C = 2;          // pass C: int phi dE/dphi, nonfinite
 constexpr int NDOT = 6 * MMAX + 10; // update-pass dot products
 constexpr int CHUNK = 1024;        // grid points per workgroup in the vector passes
+// Pass B column-block width on the runtime-shaped path and for the large
+// cubic lengths whose pass B alone is compile-time shaped: 8 in FP64 and 16
+// in FP32, halved (to 4 at least) while the x tile of n1 x (NFIELD tk)
+// complex values exceeds 40 KB in FP64 or 80 KB in FP32, so that several
+// workgroups share a CU.
+__host__ __device__ constexpr int passb_width(int n1, int prec) {
+  return prec == 0 ? (16 * n1 * (NFIELD * 8 + 1) > 40 * 1024 ? 4 : 8)
+                   : (8 * n1 * (NFIELD * 16 + 1) <= 80 * 1024 ? 16
+                      : (8 * n1 * (NFIELD * 8 + 1) <= 80 * 1024 ? 8 : 4));
+}
+// Large cubic lengths of the serving mix whose pass B runs on the
+// compile-time-shaped kernel (passes A and C on the split kernels: their
+// planes exceed LDS).
+__host__ __device__ constexpr bool shaped_b_only(int n) {
+  return n == 144 || n == 160 || n == 180 || n == 192;
+}
+
 constexpr int SPLIT_NT = 256;      // threads of the split plane kernels (planes beyond LDS)
 constexpr int SPLIT_EPT = 8;       // complex elements per thread of their row-pair chunks
 constexpr int SPLIT_RPMAX = 16;    // row pairs per chunk at most (measured: 8 -> 16 cuts
@@ -154,7 +171,7 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
-constexpr int MAX_GROUPS = 12;     // pass launch groups: runtime-shaped (by block width) + 9 lengths
+constexpr int MAX_GROUPS = 16;     // pass launch groups: runtime-shaped (by block width) + 13 lengths
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the

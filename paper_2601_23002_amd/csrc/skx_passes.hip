@@ -1734,9 +1734,15 @@ __device__ __forceinline__ void passB_nyquist(const SolveDev &S, int jy, typenam
 // the Nyquist workgroups' per-wavefront tiles where those exist, so the
 // preconditioner's launches take a quarter of the LDS and fit more
 // workgroups per CU.
+// Ragged column blocks over all N/2 + 1 columns (the last one holding the
+// Nyquist column) where TK does not divide N/2, or where the Nyquist
+// column's first transform stage would not fit one butterfly per lane.
+template <int N, int TK> constexpr bool passb_ragged() {
+  return (N / 2) % TK != 0 || NFIELD * N / CS<N>::R0 > 64;
+}
 template <int N, int TK, int MODE> constexpr int passb_tw_off() {
   constexpr int TP = TK + 1;
-  constexpr bool RAG = (N / 2) % TK != 0;
+  constexpr bool RAG = passb_ragged<N, TK>();
   constexpr int NY = RAG ? 0 : 4 * NFIELD * (N + 1);
   return MODE == MODE_EVAL ? NFIELD * N * TP : (N * TP > NY ? N * TP : NY);
 }
@@ -1755,7 +1761,7 @@ __global__ __launch_bounds__(256) void k_passBf(SolveDev *dev, const int *first,
   // Whole blocks below the Nyquist column when TK divides N/2, the Nyquist
   // column then on passB_nyquist; otherwise (ragged) blocks over all N/2 + 1
   // columns, the last one partial and holding the Nyquist column.
-  constexpr bool RAG = (N / 2) % TK != 0;
+  constexpr bool RAG = passb_ragged<N, TK>();
   constexpr int NB = RAG ? (N / 2 + TK) / TK : (N / 2) / TK;
   constexpr int PER = N * NB + (RAG ? 0 : N / NW);  // workgroups per solve
   static_assert(RAG || N % NW == 0, "Nyquist rows split evenly");
@@ -2305,7 +2311,7 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
   }
   {
     if (g.gridB > 0 && (mask & 2) && (g.shape & 2) && g.tk == TK) {
-      constexpr bool RAG = (N / 2) % TK != 0;
+      constexpr bool RAG = passb_ragged<N, TK>();
       const int gb = g.nsolve * (RAG ? N * ((N / 2 + TK) / TK) : N * (N / 2 / TK) + N / 4);
       if (mode == MODE_EVAL) {
         const size_t lb = (passb_tw_off<N, TK, MODE_EVAL>() + N) * sizeof(V);
@@ -2328,10 +2334,35 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
   }
 }
 
+// Pass B alone on the compile-time-shaped kernel, for the large lengths
+// (the group's width equals passb_width, which the host checks).
+template <typename R, int N>
+static void launch_shaped_b(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
+                            int mode) {
+  typedef typename Vec2<R>::T V;
+  constexpr int TK = passb_width(N, sizeof(R) == 8 ? 0 : 1);
+  static_assert(passb_ragged<N, TK>(), "large lengths take ragged blocks");
+  if (g.gridB <= 0 || !(mask & 2) || !(g.shape & 2) || g.tk != TK) return;
+  const int gb = g.nsolve * N * ((N / 2 + TK) / TK);
+  if (mode == MODE_EVAL) {
+    const size_t lb = (passb_tw_off<N, TK, MODE_EVAL>() + N) * sizeof(V);
+    SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_EVAL>), dim3(gb), dim3(256), lb, s, g.dev,
+                     g.firstB, g.nsolve, gb, twbank);
+  } else {
+    const size_t lb = (passb_tw_off<N, TK, MODE_PREC>() + N) * sizeof(V);
+    SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_PREC>), dim3(gb), dim3(256), lb, s, g.dev,
+                     g.firstB, g.nsolve, gb, twbank);
+  }
+}
+
 template <typename R>
 static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                             int mode) {
   switch (g.shapeN) {
+    case 144: launch_shaped_b<R, 144>(g, twbank, s, mask, mode); break;
+    case 160: launch_shaped_b<R, 160>(g, twbank, s, mask, mode); break;
+    case 180: launch_shaped_b<R, 180>(g, twbank, s, mask, mode); break;
+    case 192: launch_shaped_b<R, 192>(g, twbank, s, mask, mode); break;
     case 36: launch_shaped<R, 36>(g, twbank, s, mask, mode); break;
     case 40: launch_shaped<R, 40>(g, twbank, s, mask, mode); break;
     case 48: launch_shaped<R, 48>(g, twbank, s, mask, mode); break;

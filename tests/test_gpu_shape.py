@@ -1,5 +1,6 @@
-"""The compile-time-shaped pass kernels (64^3 grids) against the oracle and
-against the runtime-shaped kernels.
+"""The compile-time-shaped pass kernels (36^3-80^3 grids, and pass B alone at
+the large serving lengths 144^3-192^3) against the oracle and against the
+runtime-shaped kernels.
 
 Passes A and C fold the real DC and Nyquist columns of each plane into one
 complex y transform, so they round differently from the runtime-shaped
@@ -189,6 +190,65 @@ def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
         old = skx.set_shape_kernels(shape)
         try:
             ctxs = [skx.Context(0).setup(x, precision=prec) for x in systems]
+            rhos = [torch.empty(x.n, dtype=torch.float64, device="cuda") for x in systems]
+            res = skx.run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000)
+        finally:
+            skx.set_shape_kernels(old)
+        assert all(r["status"] == skx.OK for r in res), res
+        out[shape] = [(r["energy"]["free_energy"], x.cpu().numpy()) for r, x in zip(res, rhos)]
+    for (e1, r1), (e0, r0), x in zip(out[7], out[0], systems):
+        assert abs(e1 - e0) / len(x.zval) <= 1e-9
+        assert np.max(np.abs(r1 - r0)) <= 1e-5 * np.max(np.abs(r0))
+
+
+# ----------------------------------------------------------------------------
+# Large serving lengths (144, 160, 180, 192): pass B alone on the
+# compile-time-shaped kernel (ragged column blocks, the last one holding the
+# Nyquist column; FP64 blocks of 4, FP32 of 16 at 144 and 8 beyond), passes
+# A and C on the split kernels. The oracle takes minutes per evaluation at
+# these sizes, so the shaped pass B is held to the runtime-shaped one, which
+# the oracle pins on large planes (test_gpu_bigplane.py), at every grid point.
+# ----------------------------------------------------------------------------
+LARGE_B = [144, 160, 180, 192]
+
+
+@pytest.mark.parametrize("n", LARGE_B)
+def test_large_shaped_pass_b_equals_runtime_kernel_at_every_point(n):
+    """FP64: gradient within 1e-12 of its scale, every energy term within
+    1e-12 relative; FP32: within 2e-5 of the FP64 runtime result (both
+    precisions' shaped pass B against the runtime one), with beta = 0 and no
+    vW term as well."""
+    skx, torch = _lib()
+    for beta, terms in ((1.3, W.TERM_ALL), (0.0, W.TERM_ALL & ~W.TERM_VW)):
+        s = W.uniform_system(16, 1.0, 0.3, 2.0, 2.0, n, seed=60 + n, beta=beta, terms=terms)
+        phi = W.random_phi(s, 61 + n, amp=0.4)
+        _say(f"case: {n}^3 shaped pass B vs runtime, beta {beta}, terms {terms}")
+        e1, g1 = _eval(skx, torch, s, phi, skx.FP64, 7)
+        e0, g0 = _eval(skx, torch, s, phi, skx.FP64, 0)
+        scale = np.max(np.abs(g0))
+        assert np.max(np.abs(g1 - g0)) <= 1e-12 * scale
+        for k in TERMS:
+            assert abs(e1[k] - e0[k]) <= 1e-12 * max(1.0, abs(e0[k])), k
+        escale = sum(abs(e0[k]) for k in TERMS)
+        for shape in (7, 0):
+            e, g = _eval(skx, torch, s, phi, skx.FP32, shape)
+            for k in TERMS:
+                assert abs(e[k] - e0[k]) <= 2e-5 * max(abs(e0[k]), 1e-3 * escale), (shape, k)
+            assert np.max(np.abs(g - g0)) <= 2e-4 * scale, shape
+
+
+def test_large_shaped_pass_b_optimisation_reaches_same_minimum():
+    """A mixed-precision batch of a 144^3 and a 160^3 solve with the shaped
+    pass B on and off reaches the same minimum (far inside 1e-6 Ha/atom);
+    the preconditioner's pass B runs on the shaped kernel too."""
+    skx, torch = _lib()
+    systems = [W.uniform_system(16, 1.0, 0.3, 2.0, 2.0, n, seed=70 + n) for n in (144, 160)]
+    out = {}
+    for shape in (7, 0):
+        _say(f"case: 144^3 + 160^3 mixed batch, shape kernels {shape}")
+        old = skx.set_shape_kernels(shape)
+        try:
+            ctxs = [skx.Context(0).setup(x, precision=skx.MIXED) for x in systems]
             rhos = [torch.empty(x.n, dtype=torch.float64, device="cuda") for x in systems]
             res = skx.run_batch(ctxs, rhos, gtol=1e-8, max_iter=1000)
         finally:
