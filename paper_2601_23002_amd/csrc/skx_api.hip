@@ -190,12 +190,12 @@ void lds_sizes(const SolveDev &h, int prec, size_t &a, size_t &b, size_t &c) {
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
-// LDS bytes of the split plane kernels for one solve: a row-pair chunk
-// (rows of pitch 2 nh, z twiddles) and a column chunk (pitch split_cc + 1,
+// LDS bytes of the split plane kernels for one solve: a row-pair chunk of
+// every field (rows of pitch 2 nh, z twiddles) and a column chunk (pitch split_cc + 1,
 // y twiddles)
 void split_lds(const SolveDev &h, int prec, size_t &row, size_t &col) {
   const size_t v = prec == 0 ? 16 : 8;
-  row = v * ((size_t)h.rp * 2 * h.nh + h.n3);
+  row = v * ((size_t)NFIELD * h.rp * 2 * h.nh + h.n3);
   col = v * ((size_t)h.n2 * (split_cc(prec) + 1) + h.n2);
   row = std::max(row, (size_t)1024);
 }

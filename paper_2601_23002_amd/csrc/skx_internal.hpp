@@ -35,15 +35,15 @@ __host__ __device__ constexpr bool shaped_b_only(int n) {
 }
 
 constexpr int SPLIT_NT = 256;      // threads of the split plane kernels (planes beyond LDS)
-constexpr int SPLIT_EPT = 8;       // complex elements per thread of their row-pair chunks
-constexpr int SPLIT_RPMAX = 16;    // row pairs per chunk at most (measured: 8 -> 16 cuts
-                                   // passes A and C 2-5% at 144^3 and 192^3; 4 is 10-20% slower)
-// Row pairs per chunk of the split plane kernels (the chunk's rp * n3
-// complex elements are at most SPLIT_EPT per thread), and columns per
-// column chunk (128-byte row segments in both precisions).
+constexpr int SPLIT_RPMAX = 16;    // row pairs per chunk at most
+// Row pairs per chunk of the split plane kernels: every field's rows of the
+// chunk (pitch n3 + 2) take at most 52 KB of LDS in FP64 and 26 KB in FP32
+// (measured on MI355X against 36 KB and 26 KB in FP64, 52 KB in FP32:
+// 192^3 FP64 passes A + C 1138 us against 1154 and 1154 for two solves,
+// FP32 584 us against 630); and columns per column chunk (128-byte row
+// segments in both precisions).
 __host__ __device__ constexpr int split_rp(int n3) {
-  return SPLIT_EPT * SPLIT_NT / n3 < 1 ? 1
-         : (SPLIT_EPT * SPLIT_NT / n3 > SPLIT_RPMAX ? SPLIT_RPMAX : SPLIT_EPT * SPLIT_NT / n3);
+  return 832 / (n3 + 2) < 1 ? 1 : (832 / (n3 + 2) > SPLIT_RPMAX ? SPLIT_RPMAX : 832 / (n3 + 2));
 }
 __host__ __device__ constexpr int split_cc(int prec) { return prec == 0 ? 8 : 16; }
 constexpr int UCHUNK = 4096;       // grid points per workgroup of the optimiser update on

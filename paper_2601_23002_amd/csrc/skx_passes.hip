@@ -1121,12 +1121,12 @@ __device__ __forceinline__ bool split_item(const SolveDev *dev, const int *first
   return true;
 }
 
-// Pass A, z transforms of one chunk of row pairs: every field built from
-// phi_t held in registers (MODE_PREC: r_t = dE/dphi - 2 mu_t phi_t, also
-// stored), rows 2p and 2p+1 packed as one complex row, then split into the
-// two rows' half spectra straight to HBM.
+// Pass A, z transforms of one chunk of row pairs: every field of the chunk
+// built from phi_t (MODE_PREC: r_t = dE/dphi - 2 mu_t phi_t, also stored),
+// rows 2p and 2p+1 packed as one complex row, all fields' rows transformed
+// together, then split into the two rows' half spectra straight to HBM.
 template <typename R, int MODE>
-__global__ __launch_bounds__(SPLIT_NT, 4) void k_passA_rows(SolveDev *dev, const int *first,
+__global__ __launch_bounds__(SPLIT_NT) void k_passA_rows(SolveDev *dev, const int *first,
                                                          int nsolve, int grid, int krow,
                                                          const double *twbank) {
   typedef typename Vec2<R>::T V;
@@ -1144,6 +1144,8 @@ __global__ __launch_bounds__(SPLIT_NT, 4) void k_passA_rows(SolveDev *dev, const
   const int tid = threadIdx.x;
   const int n2 = S.n2, n3 = S.n3, nh = S.nh, pitch = S.pitch, pl2 = 2 * nh;
   const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const int fs = np * pl2;                      // LDS stride between the fields' rows
   V *tw3 = reinterpret_cast<V *>(smem);
   V *buf = tw3 + n3;
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
@@ -1155,55 +1157,67 @@ __global__ __launch_bounds__(SPLIT_NT, 4) void k_passA_rows(SolveDev *dev, const
   const R mu2 = MODE == MODE_PREC ? (R)(2.0 * st->mut) : (R)0;
   const R invM = (R)(1.0 / (double)S.M);
   const R n0 = (R)S.n0, n0a = (R)S.n0a;
-  const int nk = n3 / 2 + 1;
-  const UDiv dnk = make_udiv((unsigned)nk);
-  const int nfl = MODE == MODE_EVAL ? S.nf : 1;
-#pragma unroll 1
-  for (int c = 0; c < nfl; ++c) {
-    const int fb = MODE == MODE_EVAL ? nth_field(S.fields, c) : 0;
-    // rows 2q and 2q+1 as one complex row; phi_t is read again per field
-    // (from cache after the first)
-    batched<4, NT, Quad<R>>(
-        tot, tid,
-        [&](int e) {
-          const int q = (int)udiv((unsigned)e, dn3), o = 2 * q * n3 + (e - q * n3);
-          Quad<R> w{pt[o], pt[o + n3], (R)0, (R)0};
-          if (MODE == MODE_PREC) { w.c = gr[o]; w.d = gr[o + n3]; }
-          return w;
-        },
-        [&](int e, const Quad<R> &w) {
-          const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
-          R x[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const R u = h ? w.b : w.a;
-            if (MODE == MODE_EVAL) {
-              const R f = fb >= 2 ? derived_na(u, na_cfg<R>(S)) : (R)0;
-              x[h] = fb == 0 ? u : fb == 1 ? u * u : fb == 2 ? f : (f - n0a) * (u * u - n0);
-            } else {
-              x[h] = (h ? w.d : w.c) - mu2 * u;        // r_t
-              rt[2 * q * n3 + z + h * n3] = x[h];
-            }
-          }
+  const int fields = S.fields;
+  batched<4, NT, Quad<R>>(
+      tot, tid,
+      [&](int e) {
+        const int q = (int)udiv((unsigned)e, dn3), o = 2 * q * n3 + (e - q * n3);
+        Quad<R> w{pt[o], pt[o + n3], (R)0, (R)0};
+        if (MODE == MODE_PREC) { w.c = gr[o]; w.d = gr[o + n3]; }
+        return w;
+      },
+      [&](int e, const Quad<R> &w) {
+        const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+        V *dst = buf + q * pl2 + z;
+        if (MODE == MODE_PREC) {
+          const R x0 = w.c - mu2 * w.a, x1 = w.d - mu2 * w.b;    // r_t
+          rt[2 * q * n3 + z] = x0;
+          rt[2 * q * n3 + z + n3] = x1;
           V v;
-          v.x = x[0] * invM;
-          v.y = x[1] * invM;
-          buf[q * pl2 + z] = v;
-        });
-    __syncthreads();
-    fft_lds<V, MAXB_A, false>(buf, S.p3, np, 1, pl2, tw3, tid, NT);
-    SKX_G V *spec = gptr<V>(S.spec) + (size_t)c * S.H + ((size_t)it.plane * n2 + 2 * p0) * pitch;
-    for (int e = tid; e < np * nk; e += NT) {
-      const int q = (int)udiv((unsigned)e, dnk), k = e - q * nk;
-      const V X = buf[q * pl2 + k];
-      const V Xm = buf[q * pl2 + (k == 0 ? 0 : n3 - k)];
-      V A, B;
-      A.x = (R)0.5 * (X.x + Xm.x); A.y = (R)0.5 * (X.y - Xm.y);
-      B.x = (R)0.5 * (X.y + Xm.y); B.y = (R)-0.5 * (X.x - Xm.x);
-      stg(spec + (size_t)(2 * q) * pitch + k, A);
-      stg(spec + (size_t)(2 * q + 1) * pitch + k, B);
-    }
-    __syncthreads();
+          v.x = x0 * invM;
+          v.y = x1 * invM;
+          dst[0] = v;
+        } else {
+          // n^a of both rows once for the f and h fields
+          R f0 = (R)0, f1 = (R)0;
+          if (fields & (F_F | F_H)) {
+            f0 = derived_na(w.a, na_cfg<R>(S));
+            f1 = derived_na(w.b, na_cfg<R>(S));
+          }
+          int c = 0;
+#pragma unroll
+          for (int fb = 0; fb < NFIELD; ++fb) {
+            if (!(fields & (1 << fb))) continue;
+            R x0, x1;
+            if (fb == 0) { x0 = w.a; x1 = w.b; }
+            else if (fb == 1) { x0 = w.a * w.a; x1 = w.b * w.b; }
+            else if (fb == 2) { x0 = f0; x1 = f1; }
+            else { x0 = (f0 - n0a) * (w.a * w.a - n0); x1 = (f1 - n0a) * (w.b * w.b - n0); }
+            V v;
+            v.x = x0 * invM;
+            v.y = x1 * invM;
+            dst[c * fs] = v;
+            ++c;
+          }
+        }
+      });
+  __syncthreads();
+  fft_lds<V, MAXB_A, false>(buf, S.p3, nf * np, 1, pl2, tw3, tid, NT);
+  const int nk = n3 / 2 + 1, per = np * nk;
+  const UDiv dnk = make_udiv((unsigned)nk), dper = make_udiv((unsigned)per);
+  SKX_G V *spec0 = gptr<V>(S.spec) + ((size_t)it.plane * n2 + 2 * p0) * pitch;
+  for (int e = tid; e < nf * per; e += NT) {
+    const int c = (int)udiv((unsigned)e, dper), r = e - c * per;
+    const int q = (int)udiv((unsigned)r, dnk), k = r - q * nk;
+    const V *row = buf + c * fs + q * pl2;
+    const V X = row[k];
+    const V Xm = row[k == 0 ? 0 : n3 - k];
+    V A, B;
+    A.x = (R)0.5 * (X.x + Xm.x); A.y = (R)0.5 * (X.y - Xm.y);
+    B.x = (R)0.5 * (X.y + Xm.y); B.y = (R)-0.5 * (X.x - Xm.x);
+    SKX_G V *spec = spec0 + (size_t)c * S.H;
+    stg(spec + (size_t)(2 * q) * pitch + k, A);
+    stg(spec + (size_t)(2 * q + 1) * pitch + k, B);
   }
 }
 
@@ -1250,17 +1264,17 @@ __global__ __launch_bounds__(SPLIT_NT, 4) void k_plane_cols(SolveDev *dev, const
   }
 }
 
-// Pass C, inverse z transforms of one chunk of row pairs: for every field
-// the two rows' half spectra as one complex row, the C2R transform in LDS,
-// and dE/dphi = w0 + A + 2 phi_t B + c_P P + c_Q Q accumulated in
-// registers (MODE_PREC: the single field is P r_t); then the chunk's
-// partials of int phi_t dE/dphi.
+// Pass C, inverse z transforms of one chunk of row pairs: every field's two
+// half-spectrum rows as one complex row, all fields' rows transformed
+// together in LDS, then dE/dphi = w0 + A + 2 phi_t B + c_P P + c_Q Q
+// (MODE_PREC: the single field is P r_t) and the chunk's partials of
+// int phi_t dE/dphi.
 template <typename R, int MODE>
-__global__ __launch_bounds__(SPLIT_NT, 3) void k_passC_rows(SolveDev *dev, const int *first,
+__global__ __launch_bounds__(SPLIT_NT) void k_passC_rows(SolveDev *dev, const int *first,
                                                          int nsolve, int grid, int krow,
                                                          const double *twbank) {
   typedef typename Vec2<R>::T V;
-  constexpr int NT = SPLIT_NT, EPT = SPLIT_EPT;
+  constexpr int NT = SPLIT_NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = xcd_item(blockIdx.x, grid);
   if (item >= grid) return;
@@ -1273,114 +1287,97 @@ __global__ __launch_bounds__(SPLIT_NT, 3) void k_passC_rows(SolveDev *dev, const
   const int tid = threadIdx.x;
   const int n2 = S.n2, n3 = S.n3, pitch = S.pitch, pl2 = 2 * S.nh;
   const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  const int nf = MODE == MODE_EVAL ? S.nf : 1;
+  const int fs = np * pl2;
   V *tw3 = reinterpret_cast<V *>(smem);
   V *buf = tw3 + n3;
   load_twiddles(tw3, twbank, S.p3.tw, n3, tid, NT);
+  const UDiv dn3 = make_udiv((unsigned)n3), dtot = make_udiv((unsigned)tot);
+  const SKX_G V *spec0 = gptr<V>(S.spec) + ((size_t)it.plane * n2 + 2 * p0) * pitch;
+  // x_{2p} + i x_{2p+1} over the full row from the two half spectra, every
+  // field (spectrum slot c)
+  batched<4, NT, Quad<R>>(
+      nf * tot, tid,
+      [&](int e) {
+        const int c = (int)udiv((unsigned)e, dtot), r = e - c * tot;
+        const int q = (int)udiv((unsigned)r, dn3), k = r - q * n3;
+        const int kk = 2 * k <= n3 ? k : n3 - k;
+        const SKX_G V *spec = spec0 + (size_t)c * S.H;
+        const V Av = ldg(spec + (size_t)(2 * q) * pitch + kk);
+        const V Bv = ldg(spec + (size_t)(2 * q + 1) * pitch + kk);
+        return Quad<R>{Av.x, Av.y, Bv.x, Bv.y};
+      },
+      [&](int e, const Quad<R> &w) {
+        const int c = (int)udiv((unsigned)e, dtot), r = e - c * tot;
+        const int q = (int)udiv((unsigned)r, dn3), k = r - q * n3;
+        R ay = w.b, by = w.d;
+        if (k == 0 || 2 * k == n3) { ay = 0; by = 0; }
+        else if (2 * k > n3) { ay = -ay; by = -by; }
+        V X;
+        X.x = w.a - by;
+        X.y = ay + w.c;
+        buf[c * fs + q * pl2 + k] = X;
+      });
+  __syncthreads();
+  fft_lds<V, MAXB_C, true>(buf, S.p3, nf * np, 1, pl2, tw3, tid, NT);
   const size_t pbase = (size_t)it.plane * n2 * n3 + (size_t)2 * p0 * n3;
-  const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
-  const SKX_G R *cfP = gptr<R>(S.fpt) + pbase, *cfQ = gptr<R>(S.qpt) + pbase;
   SKX_G R *out = MODE == MODE_EVAL ? gptr<R>(S.grad) + pbase : gptr<R>(S.pr2[1 - par]) + pbase;
-  const UDiv dn3 = make_udiv((unsigned)n3);
-  // element i of this thread: row pair q, column z; og = its offset in the
-  // chunk's rows, q * pl2 + z its place in LDS
-  auto elem = [&](int i, int &q, int &z) {
-    const int e = tid + i * NT;
-    q = (int)udiv((unsigned)e, dn3);
-    z = e - q * n3;
-  };
-  R a0[EPT], a1[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    a0[i] = a1[i] = (R)0;
-    if (MODE == MODE_EVAL && tid + i * NT < tot) {
-      const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
-      int q, z;
-      elem(i, q, z);
-      a0[i] = v0[2 * q * n3 + z];              // w0 = 2 phi_t v0
-      a1[i] = v0[2 * q * n3 + z + n3];
+  double sphig = 0.0, bad = 0.0;
+  if (MODE == MODE_PREC) {
+    for (int e = tid; e < tot; e += NT) {
+      const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+      const V X = buf[q * pl2 + z];
+      out[2 * q * n3 + z] = X.x;
+      out[2 * q * n3 + z + n3] = X.y;
     }
-  }
-  const int nfl = MODE == MODE_EVAL ? NFIELD : 1;
-#pragma unroll 1
-  for (int fb = 0; fb < nfl; ++fb) {
-    const int sl = MODE == MODE_EVAL ? S.slot[fb] : 0;
-    if (sl < 0) continue;
-    const SKX_G V *spec = gptr<V>(S.spec) + (size_t)sl * S.H + ((size_t)it.plane * n2 + 2 * p0) * pitch;
-    // x_{2p} + i x_{2p+1} over the full row from the two half spectra
-    batched<4, NT, Quad<R>>(
+  } else {
+    // w0 (= 2 phi_t v0) and phi_t of both rows; the FP64 c_P, c_Q arrays
+    struct Pt { R w0a, w0b, pa, pb, fa, fb, qa, qb; };
+    const SKX_G R *v0 = gptr<R>(S.vpt) + pbase;
+    const SKX_G R *phit = gptr<R>(S.phi2[1 - par]) + pbase;
+    const SKX_G R *cfP = gptr<R>(S.fpt) + pbase, *cfQ = gptr<R>(S.qpt) + pbase;
+    const int sphi = S.slot[0], sn = S.slot[1], sf = S.slot[2], sh = S.slot[3];
+    const NaCfg<R> nc = na_cfg<R>(S);
+    batched<2, NT, Pt>(
         tot, tid,
         [&](int e) {
-          const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
-          const int kk = 2 * k <= n3 ? k : n3 - k;
-          const V Av = ldg(spec + (size_t)(2 * q) * pitch + kk);
-          const V Bv = ldg(spec + (size_t)(2 * q + 1) * pitch + kk);
-          return Quad<R>{Av.x, Av.y, Bv.x, Bv.y};
+          const int q = (int)udiv((unsigned)e, dn3), o = 2 * q * n3 + (e - q * n3);
+          Pt p{v0[o], v0[o + n3], phit[o], phit[o + n3], (R)0, (R)0, (R)0, (R)0};
+          if (!derive_coefs<R>()) {
+            if (sf >= 0) { p.fa = cfP[o]; p.fb = cfP[o + n3]; }
+            if (sh >= 0) { p.qa = cfQ[o]; p.qb = cfQ[o + n3]; }
+          }
+          return p;
         },
-        [&](int e, const Quad<R> &w) {
-          const int q = (int)udiv((unsigned)e, dn3), k = e - q * n3;
-          R ay = w.b, by = w.d;
-          if (k == 0 || 2 * k == n3) { ay = 0; by = 0; }
-          else if (2 * k > n3) { ay = -ay; by = -by; }
-          V X;
-          X.x = w.a - by;
-          X.y = ay + w.c;
-          buf[q * pl2 + k] = X;
+        [&](int e, const Pt &p) {
+          const int q = (int)udiv((unsigned)e, dn3), z = e - q * n3;
+          const V *x = buf + q * pl2 + z;
+          R a0 = p.w0a, a1 = p.w0b;
+          if (sphi >= 0) { const V X = x[sphi * fs]; a0 += X.x; a1 += X.y; }
+          { const V X = x[sn * fs]; a0 += (R)2 * p.pa * X.x; a1 += (R)2 * p.pb * X.y; }
+          if (sf >= 0) {
+            const R k0 = derive_coefs<R>() ? derived_coef(p.pa, 2, nc) : p.fa;
+            const R k1 = derive_coefs<R>() ? derived_coef(p.pb, 2, nc) : p.fb;
+            const V X = x[sf * fs];
+            a0 += k0 * X.x;
+            a1 += k1 * X.y;
+          }
+          if (sh >= 0) {
+            const R k0 = derive_coefs<R>() ? derived_coef(p.pa, 3, nc) : p.qa;
+            const R k1 = derive_coefs<R>() ? derived_coef(p.pb, 3, nc) : p.qb;
+            const V X = x[sh * fs];
+            a0 += k0 * X.x;
+            a1 += k1 * X.y;
+          }
+          out[2 * q * n3 + z] = a0;
+          out[2 * q * n3 + z + n3] = a1;
+          sphig += (double)p.pa * (double)a0 + (double)p.pb * (double)a1;
+          if (!(a0 == a0)) bad += 1.0;
+          if (!(a1 == a1)) bad += 1.0;
         });
-    __syncthreads();
-    fft_lds<V, MAXB_C, true>(buf, S.p3, np, 1, pl2, tw3, tid, NT);
-    // this field's coefficients
-    // (phi_t for the 2 phi_t B term and the FP32 derivation of c_P, c_Q;
-    // the FP64 c_P, c_Q arrays)
-    R c0[EPT], c1[EPT];
-    const SKX_G R *cf = (fb == 1 || derive_coefs<R>()) ? phit : fb == 2 ? cfP : cfQ;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      c0[i] = c1[i] = (R)1;
-      if (MODE == MODE_EVAL && fb > 0 && tid + i * NT < tot) {
-        int q, z;
-        elem(i, q, z);
-        c0[i] = cf[2 * q * n3 + z];
-        c1[i] = cf[2 * q * n3 + z + n3];
-      }
-    }
-    const NaCfg<R> nc = na_cfg<R>(S);
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      if (tid + i * NT < tot) {
-        int q, z;
-        elem(i, q, z);
-        const V X = buf[q * pl2 + z];
-        R k0 = c0[i], k1 = c1[i];
-        if (MODE == MODE_EVAL && fb == 1) { k0 *= (R)2; k1 *= (R)2; }
-        if (MODE == MODE_EVAL && fb >= 2 && derive_coefs<R>()) {
-          k0 = derived_coef(k0, fb, nc);
-          k1 = derived_coef(k1, fb, nc);
-        }
-        a0[i] += k0 * X.x;
-        a1[i] += k1 * X.y;
-      }
-    }
-    __syncthreads();
-  }
-  double sphig = 0.0, bad = 0.0;
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    if (tid + i * NT < tot) {
-      int q, z;
-      elem(i, q, z);
-      const int o = 2 * q * n3 + z;
-      out[o] = a0[i];
-      out[o + n3] = a1[i];
-      if (MODE == MODE_EVAL) {
-        sphig += (double)phit[o] * (double)a0[i] + (double)phit[o + n3] * (double)a1[i];
-        if (!(a0[i] == a0[i])) bad += 1.0;
-        if (!(a1[i] == a1[i])) bad += 1.0;
-      }
-    }
-  }
-  if (MODE == MODE_EVAL) {
     double v[PART_C] = {sphig, bad};
     double tot2[PART_C];
+    __syncthreads();
     block_reduce<PART_C>(v, reinterpret_cast<double *>(smem), tid, NT, tot2);
     if (tid == 0)
       for (int q = 0; q < PART_C; ++q)
