@@ -315,6 +315,7 @@ int ensure_instance(skx_ctx *c, int prec, int m) {
   h.nkb = nkb; h.tk = tk; h.nwg_vec = nwg; h.mh = m;
   h.rp = split_rp(n3);
   h.nrc = (n2 / 2 + h.rp - 1) / h.rp;
+  h.nrcp = (n2 / 2 + NFIELD * h.rp - 1) / (NFIELD * h.rp);
   h.rowsC = n1;
   h.uchunk = update_chunk(M);
   h.nwg_upd = (int)((M + h.uchunk - 1) / h.uchunk);
@@ -428,7 +429,7 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
   if (g.accC_lds) lc = std::max(lc, lc_acc);
   g.ldsA = la; g.ldsB = lb; g.ldsC = lc; g.ldsBp = std::min(lbp, lb);
   g.bigA = g.smallA = g.bigC = g.smallC = 0;
-  g.krow = g.kcol = 0;
+  g.krow = g.kcol = g.krowp = 0;
   g.ldsRow = g.ldsCol = 0;
   for (const SolveDev &h : hs) {
     ((h.big & 1) ? g.bigA : g.smallA) = 1;
@@ -437,6 +438,7 @@ int fill_group(skx_ctx *c, const std::vector<SolveDev> &hs, int prec, PassGroup 
       size_t lr, lcol;
       split_lds(h, prec, lr, lcol);
       g.krow = std::max(g.krow, h.nrc);
+      g.krowp = std::max(g.krowp, h.nrcp);
       g.kcol = std::max(g.kcol, (h.nh + split_cc(prec) - 1) / split_cc(prec));
       g.ldsRow = std::max(g.ldsRow, lr);
       g.ldsCol = std::max(g.ldsCol, lcol);

@@ -105,6 +105,7 @@ struct SolveDev {
   int debug;                       // 0 normal; FFT check: 1 forward x only, 2 inverse x only
   int big;                         // passes on the split plane kernels: 1 A, 2 C
   int rp, nrc;                     // split plane kernels: row pairs per chunk, chunks per plane
+  int nrcp;                        // chunks per plane of the preconditioner (NFIELD rp row pairs)
   int rowsC;                       // rows of pass C partial sums (n1, n1 * nrc when split)
   unsigned terms;
   int xc;                          // 1 published PZ81 fit, 2 its C1-joined branches
@@ -191,7 +192,7 @@ struct PassGroup {
   size_t ldsBp;                    // pass B of the preconditioner (one field)
   int accC_lds;                    // pass C accumulates in LDS (else in the output)
   int bigA, smallA, bigC, smallC;  // solves on the split / in-LDS kernels of passes A, C
-  int krow, kcol;                  // split kernels: most row-pair and column chunks per plane
+  int krow, kcol, krowp;           // split kernels: most row-pair and column chunks per plane
   size_t ldsRow, ldsCol;           // and their LDS
 };
 

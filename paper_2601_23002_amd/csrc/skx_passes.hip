@@ -1138,12 +1138,14 @@ __global__ __launch_bounds__(SPLIT_NT) void k_passA_rows(SolveDev *dev, const in
   SplitItem it;
   if (!split_item<MODE>(dev, first, nsolve, item, krow, 1, it)) return;
   const SolveDev &S = dev[it.s];
-  if (it.j >= S.nrc) return;
+  // the preconditioner's single field takes NFIELD times the row pairs
+  const int rpm = MODE == MODE_PREC ? NFIELD * S.rp : S.rp;
+  if (it.j >= (MODE == MODE_PREC ? S.nrcp : S.nrc)) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   const int par = st->par;
   const int tid = threadIdx.x;
   const int n2 = S.n2, n3 = S.n3, nh = S.nh, pitch = S.pitch, pl2 = 2 * nh;
-  const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  const int p0 = it.j * rpm, np = min(rpm, n2 / 2 - p0), tot = np * n3;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   const int fs = np * pl2;                      // LDS stride between the fields' rows
   V *tw3 = reinterpret_cast<V *>(smem);
@@ -1281,12 +1283,14 @@ __global__ __launch_bounds__(SPLIT_NT) void k_passC_rows(SolveDev *dev, const in
   SplitItem it;
   if (!split_item<MODE>(dev, first, nsolve, item, krow, 2, it)) return;
   const SolveDev &S = dev[it.s];
-  if (it.j >= S.nrc) return;
+  // the preconditioner's single field takes NFIELD times the row pairs
+  const int rpm = MODE == MODE_PREC ? NFIELD * S.rp : S.rp;
+  if (it.j >= (MODE == MODE_PREC ? S.nrcp : S.nrc)) return;
   const SKX_C OptState *st = cptr<OptState>(S.st);
   const int par = st->par;
   const int tid = threadIdx.x;
   const int n2 = S.n2, n3 = S.n3, pitch = S.pitch, pl2 = 2 * S.nh;
-  const int p0 = it.j * S.rp, np = min(S.rp, n2 / 2 - p0), tot = np * n3;
+  const int p0 = it.j * rpm, np = min(rpm, n2 / 2 - p0), tot = np * n3;
   const int nf = MODE == MODE_EVAL ? S.nf : 1;
   const int fs = np * pl2;
   V *tw3 = reinterpret_cast<V *>(smem);
@@ -2391,21 +2395,23 @@ static void launch_passB_runtime(const PassGroup &g, const double *twbank, hipSt
 // order. Both launches of a pass are timed as that pass.
 template <typename R, int MODE>
 static void launch_split_a(const PassGroup &g, const double *twbank, hipStream_t s) {
-  const int gr = g.gridC * g.krow;
+  const int kr = MODE == MODE_EVAL ? g.krow : g.krowp;
+  const int gr = g.gridC * kr;
   const int gc = g.gridC * (MODE == MODE_EVAL ? NFIELD : 1) * g.kcol;
   SKX_TIMED_LAUNCH((k_passA_rows<R, MODE>), dim3(gr), dim3(SPLIT_NT), g.ldsRow, s, g.dev,
-                   g.firstC, g.nsolve, gr, g.krow, twbank);
+                   g.firstC, g.nsolve, gr, kr, twbank);
   SKX_TIMED_LAUNCH((k_plane_cols<R, MODE, false>), dim3(gc), dim3(SPLIT_NT), g.ldsCol, s, g.dev,
                    g.firstC, g.nsolve, gc, g.kcol, twbank);
 }
 template <typename R, int MODE>
 static void launch_split_c(const PassGroup &g, const double *twbank, hipStream_t s) {
-  const int gr = g.gridC * g.krow;
+  const int kr = MODE == MODE_EVAL ? g.krow : g.krowp;
+  const int gr = g.gridC * kr;
   const int gc = g.gridC * (MODE == MODE_EVAL ? NFIELD : 1) * g.kcol;
   SKX_TIMED_LAUNCH((k_plane_cols<R, MODE, true>), dim3(gc), dim3(SPLIT_NT), g.ldsCol, s, g.dev,
                    g.firstC, g.nsolve, gc, g.kcol, twbank);
   SKX_TIMED_LAUNCH((k_passC_rows<R, MODE>), dim3(gr), dim3(SPLIT_NT), g.ldsRow, s, g.dev,
-                   g.firstC, g.nsolve, gr, g.krow, twbank);
+                   g.firstC, g.nsolve, gr, kr, twbank);
 }
 
 // Runtime-shaped (and split) pass kernels over one group, for the passes
