@@ -115,8 +115,9 @@ const char *skx_last_error(const skx_ctx *ctx);
  * (a1 = L x, a2 = L y, a3 = L z). n1, n2, n3: even and 5-smooth, 8..512.
  * The x axis is transformed as whole pencils in LDS: n1 <= 300 for FP64
  * work and n1 <= 310 for FP32 (the check is made when a solve is prepared,
- * SKX_E_INVALID); y-z planes beyond LDS run in chunks, so n2 and n3 may
- * take any allowed size. Invalidates ions and tables. Errors: SKX_E_INVALID. */
+ * SKX_E_INVALID); y-z planes beyond LDS run in row-pair and column chunks
+ * (separate launches), so n2 and n3 may take any allowed size. Invalidates
+ * ions and tables. Errors: SKX_E_INVALID. */
 int skx_set_cell(skx_ctx *ctx, const double lattice[9], int n1, int n2, int n3);
 
 /* Ions and their local pseudopotentials (Methods, "Numerical calculations
