@@ -110,7 +110,7 @@ def test_error_codes():
         c2.set_ions(np.zeros((1, 3)), [1.0], [-0.3])
     assert ex.value.code == skx.E_INVALID
     # pass B's x tile of an FP64 320-point x axis (4 fields x 320 x 9
-    # complex) does not fit in LDS: large y-z planes are chunked, x pencils
+    # complex) does not fit in LDS: large y-z planes are split, x pencils
     # are not
     s = dataclasses.replace(W.uniform_system(4, 1.0, 0.4, 2.0, 1.0, 8, seed=9), n=(320, 8, 8))
     c3 = skx.Context(0).setup(s, precision=skx.FP64)

@@ -49,7 +49,7 @@ def _ctx(skx, L, n, pos, zval, rc):
 @pytest.mark.parametrize("n", [(16, 24, 20), (24, 24, 24), (16, 160, 160)])
 def test_local_and_ewald_forces_match_oracle(n):
     """Random positive density; (16, 160, 160) has FP64 planes beyond LDS,
-    so pass A runs its chunked kernel."""
+    so pass A runs its split kernels."""
     skx, torch = _lib()
     from oracle import forces
     _say(f"case: forces grid {n}")

@@ -172,7 +172,7 @@ def test_80cubed_snapshot_in_an_uneven_batch_equals_alone():
 
 
 def test_engine_large_requests_equal_alone():
-    """Serving requests of 144^3 (FP64 planes beyond LDS: chunked passes) and
+    """Serving requests of 144^3 (FP64 planes beyond LDS: split passes) and
     128^3 next to a small one, two slots: each result bitwise equal to its
     solve alone."""
     skx, _ = _lib()
