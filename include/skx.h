@@ -457,7 +457,7 @@ int skx_engine_create(skx_engine **out, int device, size_t hbm_budget_bytes, int
 int skx_engine_submit(skx_engine *eng, const skx_request *req, uint64_t *ticket);
 /* Admit queued requests (in arrival order) into free slots while their
  * device footprint fits the budget, then advance every resident solve by
- * four fused step sequences (one launch per kernel over all resident solves
+ * two fused step sequences (one launch per kernel over all resident solves
  * of a precision; a step sequence is one trial evaluation of the line search
  * plus the history update when the trial is accepted). Mixed-precision
  * solves move from the FP32 to the FP64 group at the switch; finished solves
