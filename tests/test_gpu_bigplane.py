@@ -93,6 +93,25 @@ def test_forced_split_field_subsets_match_oracle(beta, terms):
             skx.set_plane_chunking(old)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_forced_split_uneven_grid_matches_oracle(precision):
+    """Rows, columns and x pencils of three different lengths (10 x 24 x 40:
+    z transforms of 40 points in one row-pair chunk of 12 pairs, y transforms
+    of 24 points over column chunks of 21 columns)."""
+    skx, torch = _lib()
+    prec = skx.FP64 if precision == "fp64" else skx.FP32
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    s = dataclasses.replace(W.uniform_system(6, 1.0, 0.4, 2.0, 1.0, 24, seed=53, beta=1.3),
+                            n=(10, 24, 40))
+    phi = W.random_phi(s, 54, amp=0.4)
+    _say(f"case: split planes forced, 10x24x40, {precision}")
+    old = skx.set_plane_chunking(True)
+    try:
+        _check(skx, torch, s, phi, prec, tol)
+    finally:
+        skx.set_plane_chunking(old)
+
+
 def test_forced_chunking_optimisation_same_minimum():
     skx, torch = _lib()
     s = W.uniform_system(16, 1.0, 0.3, 2.0, 1.0, 32, seed=31)
