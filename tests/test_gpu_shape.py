@@ -258,3 +258,31 @@ def test_large_shaped_pass_b_optimisation_reaches_same_minimum():
     for (e1, r1), (e0, r0), x in zip(out[7], out[0], systems):
         assert abs(e1 - e0) / len(x.zval) <= 1e-9
         assert np.max(np.abs(r1 - r0)) <= 1e-5 * np.max(np.abs(r0))
+
+
+@pytest.mark.parametrize("n", [160, 192])
+def test_large_grid_potential_matches_energy_finite_difference(n):
+    """At the large serving lengths (split passes A and C, shaped pass B)
+    the FP64 potential is the derivative of the FP64 energy: dV sum(dE/dphi d)
+    against a fourth-order central difference of E along a smooth direction
+    d, to 1e-7 of its scale (the difference quotient's rounding is about
+    1e-9 of it here). A property that holds at any size, checked where the
+    oracle would need minutes per evaluation."""
+    skx, torch = _lib()
+    s = W.uniform_system(32, 1.0, 0.3, 2.0, 2.0, n, seed=90 + n, beta=1.3)
+    phi = W.random_phi(s, 91 + n, amp=0.4)
+    d = W.random_phi(s, 92 + n, amp=0.5) - W.random_phi(s, 93 + n, amp=0.5)
+    _say(f"case: {n}^3 FP64 potential against energy differences")
+    c = skx.Context(0).setup(s, precision=skx.FP64)
+
+    def ev(x, grad=True):
+        return c.evaluate(torch.tensor(x, dtype=torch.float64, device="cuda"), skx.SQRT_RHO,
+                          want_grad=grad)
+
+    e, g = ev(phi)
+    an = s.volume / s.M * float(np.sum(g.double().cpu().numpy() * d))
+    eps = 2e-4
+    E = lambda t: ev(phi + t * d, grad=False)[0]["free_energy"]
+    fd = (-E(2 * eps) + 8 * E(eps) - 8 * E(-eps) + E(-2 * eps)) / (12 * eps)
+    scale = max(abs(an), 1e-3 * abs(e["free_energy"]))
+    assert abs(fd - an) <= 1e-7 * scale, (n, fd, an)
