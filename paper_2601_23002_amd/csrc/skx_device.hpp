@@ -507,9 +507,13 @@ template <> struct CShape<60> { typedef RList<4, 3, 5> L; static constexpr int N
 template <> struct CShape<64> { typedef RList<8, 8> L; static constexpr int NW = 4, PL = 36, CW = 3; };
 template <> struct CShape<72> { typedef RList<8, 3, 3> L; static constexpr int NW = 6, PL = 40, CW = 2; };
 template <> struct CShape<80> { typedef RList<8, 5, 2> L; static constexpr int NW = 8, PL = 44, CW = 1; };
-// Large serving lengths: pass B only (their planes exceed LDS, so passes A
-// and C run on the split kernels); NW, PL and CW only satisfy the checks
-// below.
+// Larger serving lengths: pass B only (passes A and C run on the in-LDS
+// runtime-shaped or the split kernels); NW, PL and CW only satisfy the
+// checks below.
+template <> struct CShape<96> { typedef RList<8, 4, 3> L; static constexpr int NW = 4, PL = 52, CW = 1; };
+template <> struct CShape<108> { typedef RList<4, 3, 3, 3> L; static constexpr int NW = 3, PL = 58, CW = 1; };
+template <> struct CShape<120> { typedef RList<8, 5, 3> L; static constexpr int NW = 4, PL = 64, CW = 1; };
+template <> struct CShape<128> { typedef RList<8, 4, 4> L; static constexpr int NW = 4, PL = 68, CW = 1; };
 template <> struct CShape<144> { typedef RList<4, 4, 3, 3> L; static constexpr int NW = 4, PL = 76, CW = 1; };
 template <> struct CShape<160> { typedef RList<8, 4, 5> L; static constexpr int NW = 4, PL = 84, CW = 1; };
 template <> struct CShape<180> { typedef RList<4, 5, 3, 3> L; static constexpr int NW = 6, PL = 94, CW = 1; };

@@ -27,11 +27,12 @@ __host__ __device__ constexpr int passb_width(int n1, int prec) {
                    : (8 * n1 * (NFIELD * 16 + 1) <= 80 * 1024 ? 16
                       : (8 * n1 * (NFIELD * 8 + 1) <= 80 * 1024 ? 8 : 4));
 }
-// Large cubic lengths of the serving mix whose pass B runs on the
-// compile-time-shaped kernel (passes A and C on the split kernels: their
-// planes exceed LDS).
+// Larger cubic lengths of the serving mix whose pass B alone runs on the
+// compile-time-shaped kernel (passes A and C on the runtime-shaped in-LDS
+// or the split kernels).
 __host__ __device__ constexpr bool shaped_b_only(int n) {
-  return n == 144 || n == 160 || n == 180 || n == 192;
+  return n == 96 || n == 108 || n == 120 || n == 128 || n == 144 || n == 160 || n == 180 ||
+         n == 192;
 }
 
 constexpr int SPLIT_NT = 256;      // threads of the split plane kernels (planes beyond LDS)
@@ -173,7 +174,7 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
-constexpr int MAX_GROUPS = 16;     // pass launch groups: runtime-shaped (by block width) + 13 lengths
+constexpr int MAX_GROUPS = 20;     // pass launch groups: runtime-shaped (by block width) + 17 lengths
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the

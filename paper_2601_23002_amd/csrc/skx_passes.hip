@@ -2336,16 +2336,16 @@ static void launch_shaped(const PassGroup &g, const double *twbank, hipStream_t 
   }
 }
 
-// Pass B alone on the compile-time-shaped kernel, for the large lengths
+// Pass B alone on the compile-time-shaped kernel, for the larger lengths
 // (the group's width equals passb_width, which the host checks).
 template <typename R, int N>
 static void launch_shaped_b(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                             int mode) {
   typedef typename Vec2<R>::T V;
   constexpr int TK = passb_width(N, sizeof(R) == 8 ? 0 : 1);
-  static_assert(passb_ragged<N, TK>(), "large lengths take ragged blocks");
   if (g.gridB <= 0 || !(mask & 2) || !(g.shape & 2) || g.tk != TK) return;
-  const int gb = g.nsolve * N * ((N / 2 + TK) / TK);
+  constexpr bool RAG = passb_ragged<N, TK>();
+  const int gb = g.nsolve * (RAG ? N * ((N / 2 + TK) / TK) : N * (N / 2 / TK) + N / 4);
   if (mode == MODE_EVAL) {
     const size_t lb = (passb_tw_off<N, TK, MODE_EVAL>() + N) * sizeof(V);
     SKX_TIMED_LAUNCH((k_passBf<R, N, TK, MODE_EVAL>), dim3(gb), dim3(256), lb, s, g.dev,
@@ -2361,6 +2361,10 @@ template <typename R>
 static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                             int mode) {
   switch (g.shapeN) {
+    case 96: launch_shaped_b<R, 96>(g, twbank, s, mask, mode); break;
+    case 108: launch_shaped_b<R, 108>(g, twbank, s, mask, mode); break;
+    case 120: launch_shaped_b<R, 120>(g, twbank, s, mask, mode); break;
+    case 128: launch_shaped_b<R, 128>(g, twbank, s, mask, mode); break;
     case 144: launch_shaped_b<R, 144>(g, twbank, s, mask, mode); break;
     case 160: launch_shaped_b<R, 160>(g, twbank, s, mask, mode); break;
     case 180: launch_shaped_b<R, 180>(g, twbank, s, mask, mode); break;

@@ -202,14 +202,17 @@ def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
 
 
 # ----------------------------------------------------------------------------
-# Large serving lengths (144, 160, 180, 192): pass B alone on the
-# compile-time-shaped kernel (ragged column blocks, the last one holding the
-# Nyquist column; FP64 blocks of 4, FP32 of 16 at 144 and 8 beyond), passes
-# A and C on the split kernels. The oracle takes minutes per evaluation at
-# these sizes, so the shaped pass B is held to the runtime-shaped one, which
-# the oracle pins on large planes (test_gpu_bigplane.py), at every grid point.
+# Larger serving lengths (96, 108, 120, 128, 144, 160, 180, 192): pass B
+# alone on the compile-time-shaped kernel (FP64 blocks of 4, FP32 of 16 up
+# to 144 and 8 beyond; ragged where the width does not divide N/2 or the
+# Nyquist column's first stage would not fit, else whole blocks and the
+# Nyquist column on its own workgroups), passes A and C on the in-LDS
+# runtime-shaped or the split kernels. The oracle takes minutes per
+# evaluation at the largest sizes, so the shaped pass B is held to the
+# runtime-shaped one, which the oracle pins on large planes
+# (test_gpu_bigplane.py), at every grid point.
 # ----------------------------------------------------------------------------
-LARGE_B = [144, 160, 180, 192]
+LARGE_B = [96, 108, 120, 128, 144, 160, 180, 192]
 
 
 @pytest.mark.parametrize("n", LARGE_B)
