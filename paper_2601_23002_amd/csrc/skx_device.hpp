@@ -510,12 +510,16 @@ template <> struct CShape<80> { typedef RList<8, 5, 2> L; static constexpr int N
 // Larger serving lengths: pass B only (passes A and C run on the in-LDS
 // runtime-shaped or the split kernels); NW, PL and CW only satisfy the
 // checks below.
+template <> struct CShape<90> { typedef RList<2, 5, 3, 3> L; static constexpr int NW = 3, PL = 49, CW = 1; };
 template <> struct CShape<96> { typedef RList<8, 4, 3> L; static constexpr int NW = 4, PL = 52, CW = 1; };
+template <> struct CShape<100> { typedef RList<4, 5, 5> L; static constexpr int NW = 5, PL = 54, CW = 1; };
 template <> struct CShape<108> { typedef RList<4, 3, 3, 3> L; static constexpr int NW = 3, PL = 58, CW = 1; };
 template <> struct CShape<120> { typedef RList<8, 5, 3> L; static constexpr int NW = 4, PL = 64, CW = 1; };
 template <> struct CShape<128> { typedef RList<8, 4, 4> L; static constexpr int NW = 4, PL = 68, CW = 1; };
 template <> struct CShape<144> { typedef RList<4, 4, 3, 3> L; static constexpr int NW = 4, PL = 76, CW = 1; };
+template <> struct CShape<150> { typedef RList<2, 5, 5, 3> L; static constexpr int NW = 5, PL = 79, CW = 1; };
 template <> struct CShape<160> { typedef RList<8, 4, 5> L; static constexpr int NW = 4, PL = 84, CW = 1; };
+template <> struct CShape<162> { typedef RList<2, 3, 3, 3, 3> L; static constexpr int NW = 3, PL = 85, CW = 1; };
 template <> struct CShape<180> { typedef RList<4, 5, 3, 3> L; static constexpr int NW = 6, PL = 94, CW = 1; };
 template <> struct CShape<192> { typedef RList<8, 8, 3> L; static constexpr int NW = 4, PL = 100, CW = 1; };
 // derived per-length constants

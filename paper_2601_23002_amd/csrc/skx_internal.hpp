@@ -31,8 +31,8 @@ __host__ __device__ constexpr int passb_width(int n1, int prec) {
 // compile-time-shaped kernel (passes A and C on the runtime-shaped in-LDS
 // or the split kernels).
 __host__ __device__ constexpr bool shaped_b_only(int n) {
-  return n == 96 || n == 108 || n == 120 || n == 128 || n == 144 || n == 160 || n == 180 ||
-         n == 192;
+  return n == 90 || n == 96 || n == 100 || n == 108 || n == 120 || n == 128 || n == 144 ||
+         n == 150 || n == 160 || n == 162 || n == 180 || n == 192;
 }
 
 constexpr int SPLIT_NT = 256;      // threads of the split plane kernels (planes beyond LDS)
@@ -174,7 +174,7 @@ hipError_t ewald_forces(double L, int nions, const double *pos_dev, const double
                         double2 *sf_dev, double *part_dev, double *out_dev, hipStream_t s);
 
 // The fixed step sequence over a batch of solves (defined in skx_passes.hip)
-constexpr int MAX_GROUPS = 20;     // pass launch groups: runtime-shaped (by block width) + 17 lengths
+constexpr int MAX_GROUPS = 24;     // pass launch groups: runtime-shaped (by block width) + 21 lengths
 
 // The solves of a batch whose evaluation passes run on one kernel family:
 // the compile-time-shaped kernels of one cubic length, or the

@@ -2361,12 +2361,16 @@ template <typename R>
 static void launch_shaped_n(const PassGroup &g, const double *twbank, hipStream_t s, int mask,
                             int mode) {
   switch (g.shapeN) {
+    case 90: launch_shaped_b<R, 90>(g, twbank, s, mask, mode); break;
     case 96: launch_shaped_b<R, 96>(g, twbank, s, mask, mode); break;
+    case 100: launch_shaped_b<R, 100>(g, twbank, s, mask, mode); break;
     case 108: launch_shaped_b<R, 108>(g, twbank, s, mask, mode); break;
     case 120: launch_shaped_b<R, 120>(g, twbank, s, mask, mode); break;
     case 128: launch_shaped_b<R, 128>(g, twbank, s, mask, mode); break;
     case 144: launch_shaped_b<R, 144>(g, twbank, s, mask, mode); break;
+    case 150: launch_shaped_b<R, 150>(g, twbank, s, mask, mode); break;
     case 160: launch_shaped_b<R, 160>(g, twbank, s, mask, mode); break;
+    case 162: launch_shaped_b<R, 162>(g, twbank, s, mask, mode); break;
     case 180: launch_shaped_b<R, 180>(g, twbank, s, mask, mode); break;
     case 192: launch_shaped_b<R, 192>(g, twbank, s, mask, mode); break;
     case 36: launch_shaped<R, 36>(g, twbank, s, mask, mode); break;

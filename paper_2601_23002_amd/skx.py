@@ -464,7 +464,8 @@ def set_autotune(on=True):
 def set_shape_kernels(mask=7):
     """Passes (bit mask: 1 A, 2 B, 4 C; True = all, False = none) that run
     their compile-time-shaped kernels on the cubic lengths that have them
-    (all three passes at 36-80, pass B alone at 96-192; process-wide);
+    (all three passes at 36-80, pass B alone at twelve lengths 90-192;
+    process-wide);
     returns the previous mask."""
     if mask is True:
         mask = 7

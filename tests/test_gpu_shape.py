@@ -202,7 +202,8 @@ def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
 
 
 # ----------------------------------------------------------------------------
-# Larger serving lengths (96, 108, 120, 128, 144, 160, 180, 192): pass B
+# Larger serving lengths (90, 96, 100, 108, 120, 128, 144, 150, 160, 162,
+# 180, 192): pass B
 # alone on the compile-time-shaped kernel (FP64 blocks of 4, FP32 of 16 up
 # to 144 and 8 beyond; ragged where the width does not divide N/2 or the
 # Nyquist column's first stage would not fit, else whole blocks and the
@@ -212,7 +213,7 @@ def test_shaped_lengths_optimisation_reaches_same_minimum(precision):
 # runtime-shaped one, which the oracle pins on large planes
 # (test_gpu_bigplane.py), at every grid point.
 # ----------------------------------------------------------------------------
-LARGE_B = [96, 108, 120, 128, 144, 160, 180, 192]
+LARGE_B = [90, 96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192]
 
 
 @pytest.mark.parametrize("n", LARGE_B)
