@@ -446,11 +446,16 @@ __global__ __launch_bounds__(256) void k_ewald_real(double *part, int nions, con
   const long long idx = blockIdx.x * 4LL + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (idx >= npair) return;
-  // decode (i, j) with i <= j
-  long long rem = idx;
-  int i = 0;
-  while (rem >= nions - i) { rem -= nions - i; ++i; }
-  const int j = i + (int)rem;
+  // decode (i, j) with i <= j: row i starts at S(i) = i n - i (i - 1) / 2;
+  // the root of S(i) = idx, then exact integer fix-ups
+  auto row_start = [&](long long r) { return r * nions - r * (r - 1) / 2; };
+  const double b = 2.0 * nions + 1.0;
+  long long i = (long long)floor(0.5 * (b - sqrt(fmax(0.0, b * b - 8.0 * (double)idx))));
+  if (i < 0) i = 0;
+  if (i > nions - 1) i = nions - 1;
+  while (i > 0 && row_start(i) > idx) --i;
+  while (i < nions - 1 && row_start(i + 1) <= idx) ++i;
+  const int j = (int)(i + (idx - row_start(i)));
   const double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
                dz = pos[3 * i + 2] - pos[3 * j + 2];
   const int side = 2 * nimg + 1, nimgs = side * side * side;
